@@ -1,0 +1,103 @@
+"""Per-pair precompute of the two-body correction (oracle).
+
+For a near-contact pair (i, k) with coarse one-body data ``ob`` (both disks of the
+same class, unit radius), following Sec. 3.2-3.4 (resistance) and Sec. 4.3-4.4
+(mobility):
+
+* X = [[0, Q^(k,i)], [Q^(i,k), 0]]: rows are the fine nodes of body i then body k,
+  columns are lambda_bar^(i) then lambda_bar^(k) (Remark "Symmetrizing pairs").
+  Resistance: Q^(i,k) = S(fine nodes of k, Y^(i)).  Mobility: Q^(i,k) =
+  S(fine nodes of k, Y^(i)) (I - L) (eq. after Sec. 4.4 bullet list).
+* F = S(fine nodes, fine sources) (resistance), or, for mobility,
+  S(fine nodes, fine sources)(I - calL) + blockdiag(calB_i calK_i^T, calB_k calK_k^T)
+  with calL the blockwise rigid projector of the fine sources (eq. chi_mob) and
+  calB the fine-node rigid map (reading Q12: the text defines the fine counterpart).
+* C = S(peanut, Y^(i) u Y^(k)) [(I - L^pair)],  D = S(peanut, fine sources) [(I - calL)]
+  (eq. peanut / eq. peanut_mob).
+* G = F^+ X with truncation 1e-11 (reading Q17), applied as V Sigma^+ (U^T X).
+* A = -C^+ D G with truncation 1e-14 (eq. Amat), right to left (reading Q18).
+* E: force/torque extraction (resistance) E_ft = -blockdiag(calK_i^T, calK_k^T) G,
+  since beta = -F^+ X lambda_bar and f = K^T lambda_bar + calK^T beta (eq. force_syst);
+  velocity extraction (mobility) E_v = +blockdiag(calK^T) G, since
+  [v; omega] = -calK^T beta - K^T lambda_bar (eq. rbm2).  (Reading Q10: eq. force_ext
+  as printed lacks the transpose and the sign.)
+* W: the step-2b field correction of Alg. 3 for this pair, precombined,
+  W = -([[P, S^(ik)], [S^(ki), P]] Pi A + [[0, S^(ik) Pi], [S^(ki) Pi, 0]]) with
+  Pi = I - L for mobility (reading Q9) and Pi = I for resistance, and with the
+  H blocks of step 2b read as the one-body basis of the neighbour evaluated at
+  the coarse nodes (reading Q8): H^(k,i) mu^(k) = S^(ik) Pi lambda_bar^(k).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+from scipy.linalg import block_diag
+
+from .geometry import fine_nodes, fine_sources, peanut_nodes, rigid_map, rigid_projector
+from .kernel import stokeslet_matrix
+from .onebody import apply_pinv, truncated_svd
+
+
+def pair_matrices(ci, ck, ob, prm, keep=False):
+    """Precompute A (4N_c x 4N_c), E (6 x 4N_c) and W (4M_c x 4N_c) for the pair (i, k)."""
+    if abs(ob.radius - 1.0) > 1e-14:
+        raise NotImplementedError("the fine pair discretisation of Sec. 5 is for unit disks")
+    ci = np.asarray(ci, dtype=np.float64)
+    ck = np.asarray(ck, dtype=np.float64)
+    mu = prm.mu
+    mob = ob.problem == "mobility"
+    Yi = ci + ob.Yr
+    Yk = ck + ob.Yr
+    Xi = ci + ob.Xr
+    Xk = ck + ob.Xr
+    Yfi, Yfk = fine_sources(ci, ck, prm)
+    Xfi, Xfk = fine_nodes(ci, ck, prm)
+    z = peanut_nodes(ci, ck, prm.m_p)
+    Yf = np.concatenate([Yfi, Yfk])
+    Xf = np.concatenate([Xfi, Xfk])
+    Kfi = rigid_map(Yfi, ci)
+    Kfk = rigid_map(Yfk, ck)
+    nc2 = 2 * ob.n_src
+    Pi = ob.IL if mob else np.eye(nc2)
+
+    Q_ik = stokeslet_matrix(Xfk, Yi, mu) @ Pi        # body i's basis on body k's fine nodes
+    Q_ki = stokeslet_matrix(Xfi, Yk, mu) @ Pi        # body k's basis on body i's fine nodes
+    mf2 = Q_ik.shape[0]
+    Xmat = np.zeros((2 * mf2, 2 * nc2))
+    Xmat[:mf2, nc2:] = Q_ki
+    Xmat[mf2:, :nc2] = Q_ik
+
+    Sff = stokeslet_matrix(Xf, Yf, mu)
+    Szf = stokeslet_matrix(z, Yf, mu)
+    Szc = stokeslet_matrix(z, np.concatenate([Yi, Yk]), mu)
+    if mob:
+        ILf = block_diag(np.eye(Kfi.shape[0]) - rigid_projector(Kfi), np.eye(Kfk.shape[0]) - rigid_projector(Kfk))
+        Bfi = rigid_map(Xfi, ci)
+        Bfk = rigid_map(Xfk, ck)
+        F = Sff @ ILf + block_diag(Bfi @ Kfi.T, Bfk @ Kfk.T)
+        C = Szc @ block_diag(Pi, Pi)
+        D = Szf @ ILf
+    else:
+        F = Sff
+        C = Szc
+        D = Szf
+
+    UF, sF, VtF = truncated_svd(F, prm.eps_trunc_fine)
+    G = apply_pinv(UF, sF, VtF, Xmat)
+    UC, sC, VtC = truncated_svd(C, prm.eps_trunc)
+    A = -apply_pinv(UC, sC, VtC, D @ G)
+    KfT = block_diag(Kfi.T, Kfk.T)
+    E = KfT @ G if mob else -(KfT @ G)
+
+    P = ob.P
+    Sik = stokeslet_matrix(Xi, Yk, mu)
+    Ski = stokeslet_matrix(Xk, Yi, mu)
+    near = np.block([[P @ Pi, Sik @ Pi], [Ski @ Pi, P @ Pi]])
+    cross = np.block([[np.zeros_like(P), Sik @ Pi], [Ski @ Pi, np.zeros_like(P)]])
+    W = -(near @ A + cross)
+
+    out = dict(A=A, E=E, W=W, n_fine=(Yfi.shape[0], Yfk.shape[0]))
+    if keep:
+        out.update(F=F, C=C, D=D, X=Xmat, G=G, sF=sF, sC=sC, Yf=Yf, Xf=Xf, z=z, Kfi=Kfi, Kfk=Kfk,
+                   Yfi=Yfi, Yfk=Yfk, Xfi=Xfi, Xfk=Xfk)
+    return out
