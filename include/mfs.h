@@ -1,0 +1,183 @@
+/*
+ * mfs.h -- C ABI of the MI355X (gfx950) implementation of the peanut-compressed
+ * two-body method of fundamental solutions for 2D Stokes flow around nearly
+ * touching rigid disks (Broms, Tornberg & Barnett, arXiv 2606.11273).
+ *
+ * The calls follow the paper's problem statement and the phases of Alg. 2:
+ *   mfs_setup             geometry, coarse discretisation, one-body bases, contact list
+ *                         (Sec. 3.1, Sec. 4.1, Sec. 6);
+ *   mfs_precompute_pairs  per-close-pair compressed corrections A, E (Sec. 3.2-3.4, 4.3-4.4, 5;
+ *                         Alg. 2 precompute loop);
+ *   mfs_apply             the preconditioned matrix-vector product T mu (Alg. 3);
+ *   mfs_gmres_solve       RHS -> GMRES -> post-processing (Alg. 2; Sec. 4.4 for mobility).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns mfs_status.  On error nothing is written to the outputs,
+ *    except MFS_ERR_NOCONV from mfs_gmres_solve, which writes the best iterate's
+ *    outputs and info.  mfs_last_error() returns a message for the last failing
+ *    call on that context.
+ *  - "host" pointers are read or written during the call only.  "device" pointers
+ *    must be device memory of the current HIP device, at least the stated size;
+ *    they are accessed on the context's stream and the call returns after that
+ *    work is enqueued (mfs_apply, mfs_kernel_sum) or completed (everything else).
+ *  - Coarse collocation data (mu, u, b) have n = 2 * sum(n_col) entries: per node
+ *    (x, y) interleaved, nodes of body 0 first.  Source strengths have
+ *    2 * sum(n_src) entries, same layout.  Per-body triples are (x, y, rotational).
+ *  - Node q of body i sits at c_i + a_i (cos 2 pi q / n_col_i, sin 2 pi q / n_col_i);
+ *    source j at c_i + r_src_i a_i (cos 2 pi j / n_src_i, sin 2 pi j / n_src_i)
+ *    (equispaced rings, first point at angle 0 in the global frame).
+ *  - Forces are sums of Stokeslet strengths: the force exerted on the fluid.  Torque
+ *    is the (x - c)^perp moment with (x1, x2)^perp = (-x2, x1) (Sec. 1).
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef MFS_H
+#define MFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfs_ctx mfs_ctx;
+
+typedef enum {
+  MFS_OK = 0,
+  MFS_ERR_ARG = 1,       /* invalid argument, size or unsupported configuration */
+  MFS_ERR_GEOMETRY = 2,  /* overlapping or touching disks (gap <= 0) */
+  MFS_ERR_OOM = 3,       /* device allocation failed */
+  MFS_ERR_DEVICE = 4,    /* HIP / rocBLAS / rocSOLVER error */
+  MFS_ERR_STATE = 5,     /* call out of order (e.g. apply before precompute) */
+  MFS_ERR_NOCONV = 6,    /* GMRES stopped at max_iter above tolerance (outputs = best iterate) */
+  MFS_ERR_NUMERIC = 7    /* NaN or Inf in the input or the iteration */
+} mfs_status;
+
+typedef enum { MFS_RESISTANCE = 0, MFS_MOBILITY = 1 } mfs_problem;
+
+/* Arithmetic of the all-pairs Stokeslet sum (step 2a of Alg. 3).  Every other step
+ * is FP64 in both modes.  MFS_MIXED evaluates the kernel in FP32 on body-relative
+ * coordinates with FP64 accumulation; mfs_gmres_solve then refines in FP64
+ * (GMRES-IR: FP64 true residual, inner GMRES on the mixed operator). */
+typedef enum { MFS_FP64 = 0, MFS_MIXED = 1 } mfs_precision;
+
+/* Method parameters; mfs_default_params fills the paper's values (Sec. 5, Sec. 6). */
+typedef struct {
+  double mu;              /* viscosity (1) */
+  double delta_c;         /* contact threshold on the gap: |c_i - c_k| <= a_i + a_k + delta_c (0.2) */
+  double eps_trunc;       /* one-body and peanut pseudoinverse truncation, relative to sigma_1 (1e-14) */
+  double eps_trunc_fine;  /* fine pair pseudoinverse truncation (1e-11) */
+  double eps_ring;        /* ring rule R = 1 - ln(1/eps)/N (1e-12) */
+  int32_t n_fp;           /* fine proxy sources per disk (150) */
+  int32_t n_ell;          /* shielding-ellipse sampling parameter (80) */
+  int32_t m_p;            /* peanut collocation nodes (200) */
+  int32_t a_ell;          /* Moebius fine nodes = a_ell * n_ell (5) */
+  double gamma;           /* ellipse tip parameter (0.3) */
+  double a_f;             /* equispaced fine nodes = ceil(a_f * n_fp) (1.2) */
+  double mobius_r;        /* Moebius clustering parameter (0.6) */
+} mfs_params;
+
+typedef struct {
+  int32_t iters_total;    /* inner GMRES iterations summed over refinement steps */
+  int32_t outer_steps;    /* FP64 refinement steps (1 for MFS_FP64) */
+  double rel_resid;       /* final FP64 true residual |b - T x| / |b| */
+  double* resid_hist;     /* host, optional: relative residual estimate per inner iteration */
+  int32_t hist_cap;       /* capacity of resid_hist */
+  int32_t hist_len;       /* entries written */
+  double ms_rhs, ms_iterate, ms_post;   /* wall-clock phases of the solve */
+  int64_t n_pairs;
+} mfs_solve_info;
+
+/* Fill *prm with the paper's defaults.  prm: host, written. */
+void mfs_default_params(mfs_params* prm);
+
+/* Create a context for P disks.
+ * centers: host, P x 2 row-major; radii: host, P (> 0); n_src, n_col: host, P each
+ * (1 <= n_src < n_col, n_col <= 512, even counts; disks with equal (radius, n_src,
+ * n_col, r_src) share one-body factors); r_src: host, P, source-ring radius as a
+ * fraction of the disk radius in (0, 1), or <= 0 for 1 - ln(1/eps_ring)/n_src (Sec. 6).
+ * prm: host or NULL for defaults.  stream: the hipStream_t every call of this context
+ * runs on (NULL: the null stream).  Builds the coarse rings, the one-body factors of
+ * every disk class by SVD (eq. howG+, eq. SL) and the contact list.
+ * Errors: MFS_ERR_ARG (sizes, parameters), MFS_ERR_GEOMETRY (some gap <= 0),
+ * MFS_ERR_OOM, MFS_ERR_DEVICE.  *ctx is NULL on error. */
+mfs_status mfs_setup(mfs_ctx** ctx, int32_t P, const double* centers, const double* radii,
+                     const int32_t* n_src, const int32_t* n_col, const double* r_src,
+                     const mfs_params* prm, void* stream);
+
+/* Precompute, on the device, the compressed correction A^c (eq. Amat) and the
+ * extraction matrix E^c (velocities for mobility, eq. rbm2; forces/torques for
+ * resistance, eq. force_ext read with a transpose and sign) of every close pair,
+ * for problem prob.  n_pairs_out: host or NULL.  Pairs of disks with different
+ * classes, or with radius != 1, give MFS_ERR_ARG.  Calling it again for the
+ * other problem keeps both sets. */
+mfs_status mfs_precompute_pairs(mfs_ctx* ctx, mfs_problem prob, int64_t* n_pairs_out);
+
+/* Number of close pairs and the list itself.  pairs: host, n_pairs x 2 (i < k),
+ * lexicographic order, or NULL to query only the count. */
+mfs_status mfs_get_pairs(const mfs_ctx* ctx, int64_t* n_pairs, int32_t* pairs);
+
+/* Import (set) or export (get) the pair matrices of problem prob in the pair
+ * order of mfs_get_pairs.  A: host, sum over pairs of (2 n_src_i + 2 n_src_k)^2,
+ * each pair's matrix row-major; E: host, sum of 6 x (2 n_src_i + 2 n_src_k),
+ * row-major.  Setting marks prob as precomputed (used to run the matvec on
+ * matrices computed elsewhere, e.g. at an earlier time step). */
+mfs_status mfs_set_pair_matrices(mfs_ctx* ctx, mfs_problem prob, const double* A, const double* E);
+mfs_status mfs_get_pair_matrices(const mfs_ctx* ctx, mfs_problem prob, double* A, double* E);
+
+/* u_out = T mu_in, the matvec of Alg. 3 for problem prob (steps 1a, 1b, 2a, 2b and
+ * the identity fix), for n_rhs stacked vectors.  mu_in, u_out: device, n_rhs x n
+ * doubles, must not overlap.  The all-pairs sum skips each disk's own sources
+ * and those of its contact partners; the pair step adds, in FP64, each partner's
+ * corrections from its other contacts; the result equals Alg. 3 in exact
+ * arithmetic (the self and near blocks that Alg. 3 adds and then subtracts are
+ * never formed).  Errors: MFS_ERR_STATE before precompute of prob, MFS_ERR_ARG. */
+mfs_status mfs_apply(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t n_rhs,
+                     const double* mu_in, double* u_out);
+
+/* Plain all-pairs Stokeslet sum over the context's coarse sources and nodes
+ * (eq. getall): u[t] = sum_s S(x_t, y_s) sigma[s].  skip = 0: every source;
+ * skip = 1: sources of the target's own disk are left out; skip = 2: also those
+ * of the disk's contact partners (the form step 2a of mfs_apply uses, with the
+ * skipped blocks applied in FP64 by the pair step).  sigma: device,
+ * 2 * sum(n_src); u: device, 2 * sum(n_col).  This is the kernel of step 2a,
+ * exposed for tests and measurement. */
+mfs_status mfs_kernel_sum(mfs_ctx* ctx, mfs_precision prec, const double* sigma, double* u,
+                          int32_t skip);
+
+/* Right-hand side of the preconditioned system.  given: host, P x 3 (forces and
+ * torques for mobility, velocities for resistance); b: device, n.  Mobility:
+ * b = -u_0 with u_0 the completion flow of lambda_0 = K (K^T K)^{-1} [f; t] summed over
+ * all disks (eq. u0_def); resistance: b = B [v; omega] at every node (eq. rigidbc). */
+mfs_status mfs_rhs(mfs_ctx* ctx, mfs_problem prob, const double* given, double* b);
+
+/* Post-processing of a solution mu (device, n): out (host, P x 3) = velocities
+ * [v; omega] = -K^T lambda_bar + sum_c E^c x_c (mobility) or forces/torques
+ * K^T lambda_bar + sum_c E^c x_c (resistance), lambda_bar = one-body pseudoinverse of mu. */
+mfs_status mfs_post(mfs_ctx* ctx, mfs_problem prob, const double* mu, double* out);
+
+/* Full solve (Alg. 2; Sec. 4.4).  rhs: host, n_rhs x P x 3; out: host, n_rhs x P x 3.
+ * x0: device, n_rhs x n initial mu, or NULL for zero.  tol: relative residual of
+ * the square system; max_iter: cap on GMRES iterations per solve (unrestarted).
+ * MFS_FP64 runs GMRES on the FP64 operator; MFS_MIXED runs GMRES-IR (outer FP64
+ * residuals, inner GMRES on the mixed operator).  info: host or NULL. */
+mfs_status mfs_gmres_solve(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t n_rhs,
+                           const double* rhs, double* out, const double* x0, double tol,
+                           int32_t max_iter, mfs_solve_info* info);
+
+/* Sizes: P, total sources N_s, total nodes N_t (n = 2 N_t), pairs.  Any pointer may be NULL. */
+mfs_status mfs_get_sizes(const mfs_ctx* ctx, int32_t* P, int64_t* n_sources, int64_t* n_nodes,
+                         int64_t* n_pairs);
+
+/* Release every device and host resource of ctx (NULL is accepted). */
+mfs_status mfs_destroy(mfs_ctx* ctx);
+
+/* Message of the last failing call on ctx (or of the last failing mfs_setup when
+ * ctx is NULL).  Valid until the next call on that context. */
+const char* mfs_last_error(const mfs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFS_H */

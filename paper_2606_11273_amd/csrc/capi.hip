@@ -1,0 +1,439 @@
+// C ABI of the library (include/mfs.h): setup, precompute, matvec, solve.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <algorithm>
+#include <new>
+
+#include "internal.h"
+
+using namespace mfs;
+
+namespace {
+
+thread_local std::string g_setup_err;
+
+mfs_status fail(mfs_ctx* c, Status st) {
+  if (c)
+    c->last = st;
+  else
+    g_setup_err = st.msg;
+  return st.code;
+}
+
+mfs_status ok(mfs_ctx* c) {
+  if (c) c->last = Status{};
+  return MFS_OK;
+}
+
+template <class T>
+Status dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (hipMalloc((void**)p, sizeof(T) * (n ? n : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    return Status{MFS_ERR_OOM, "device allocation of " + std::to_string(sizeof(T) * n) + " bytes failed"};
+  }
+  return Status{};
+}
+
+template <class T>
+Status upload(T** p, const std::vector<T>& h, hipStream_t s) {
+  Status st = dalloc(p, h.size());
+  if (st.code) return st;
+  if (!h.empty()) MFS_HIP(hipMemcpyAsync(*p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s));
+  return Status{};
+}
+
+void free_all(mfs_ctx* c) {
+  void* ptrs[] = {c->d_nbr_off, c->d_nbr_list, c->d_bdat,
+                  c->d_src_off, c->d_col_off, c->d_cls,   c->d_tgt_body, c->d_pairs,  c->d_bp_off, c->d_bp_list,
+                  c->d_xoff,    c->d_aoff,    c->d_coff,  c->d_centers,  c->d_Y,      c->d_X,      c->d_Xr32,
+                  c->d_lam_bar, c->d_ltil,    c->d_sig64, c->d_u,        c->d_corr,   c->d_upart,  c->d_epair,
+                  c->d_out3,    c->d_given,   c->d_sig32, c->d_src64,    c->ps[0].A,  c->ps[0].E,  c->ps[1].A,
+                  c->ps[1].E,   c->kr.V,      c->kr.w,    c->kr.part,    c->kr.hdev,  c->kr.x,     c->kr.r,
+                  c->kr.b,      c->kr.d,      c->kr.tmp};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->kr.hhost) (void)hipHostFree(c->kr.hhost);
+  for (void* p : c->class_bufs)
+    if (p) (void)hipFree(p);
+  if (c->blas) rocblas_destroy_handle(c->blas);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+// Host-only checks and contact search (no HIP call, so argument and geometry errors
+// are reported without touching the device).
+Status validate_host(mfs_ctx* c, const double* centers, const double* radii, const int32_t* n_src,
+                     const int32_t* n_col, const double* r_src) {
+  const int P = c->P;
+  c->centers.assign(centers, centers + 2 * P);
+  c->radii.assign(radii, radii + P);
+  c->n_src.assign(n_src, n_src + P);
+  c->n_col.assign(n_col, n_col + P);
+  c->r_src.resize(P);
+  for (int i = 0; i < P; ++i) {
+    if (!(radii[i] > 0.0) || !std::isfinite(radii[i]) || !std::isfinite(centers[2 * i]) ||
+        !std::isfinite(centers[2 * i + 1]))
+      return Status{MFS_ERR_ARG, "body " + std::to_string(i) + ": invalid centre or radius"};
+    if (n_src[i] < 1 || n_col[i] <= n_src[i] || n_col[i] > kMaxCol)
+      return Status{MFS_ERR_ARG, "body " + std::to_string(i) + ": need 1 <= n_src < n_col <= 512"};
+    double rs = r_src[i] > 0.0 ? r_src[i] : ring_rule(n_src[i], c->prm.eps_ring);
+    if (!(rs > 0.0 && rs < 1.0)) return Status{MFS_ERR_ARG, "body " + std::to_string(i) + ": source ring radius not in (0, 1)"};
+    c->r_src[i] = rs;
+  }
+  int bi = -1, bk = -1;
+  double bg = 0;
+  if (!find_contacts(P, centers, radii, c->prm.delta_c, c->pairs, &bi, &bk, &bg))
+    return Status{MFS_ERR_GEOMETRY, "disks " + std::to_string(bi) + " and " + std::to_string(bk) +
+                                        " overlap or touch (gap " + std::to_string(bg) + ")"};
+  return Status{};
+}
+
+Status build(mfs_ctx* c, const double* centers, const double* radii, const int32_t* n_src, const int32_t* n_col,
+             const double* r_src) {
+  (void)radii;
+  (void)r_src;
+  const int P = c->P;
+  c->src_off.assign(P + 1, 0);
+  c->col_off.assign(P + 1, 0);
+  for (int i = 0; i < P; ++i) {
+    c->src_off[i + 1] = c->src_off[i] + n_src[i];
+    c->col_off[i + 1] = c->col_off[i] + n_col[i];
+  }
+  c->Ns = c->src_off[P];
+  c->Nt = c->col_off[P];
+  const int C = (int)(c->pairs.size() / 2);
+  c->xoff.assign(C + 1, 0);
+  c->aoff.assign(C + 1, 0);
+  c->coff.assign(C + 1, 0);
+  std::vector<std::vector<int32_t>> bl(P);
+  for (int p = 0; p < C; ++p) {
+    const int i = c->pairs[2 * p], k = c->pairs[2 * p + 1];
+    const int64_t nx = 2 * (int64_t)(n_src[i] + n_src[k]);
+    c->xoff[p + 1] = c->xoff[p] + nx;
+    c->aoff[p + 1] = c->aoff[p] + nx * nx;
+    c->coff[p + 1] = c->coff[p] + 2 * (int64_t)(n_col[i] + n_col[k]);
+    bl[i].push_back(2 * p);
+    bl[k].push_back(2 * p + 1);
+  }
+  c->bp_off.assign(P + 1, 0);
+  c->bp_list.clear();
+  c->nbr_off.assign(P + 1, 0);
+  c->nbr_list.clear();
+  for (int i = 0; i < P; ++i) {
+    c->bp_list.insert(c->bp_list.end(), bl[i].begin(), bl[i].end());
+    c->bp_off[i + 1] = (int32_t)c->bp_list.size();
+    std::vector<int32_t> nb;
+    for (int32_t e : bl[i]) nb.push_back(c->pairs[2 * (e >> 1) + 1 - (e & 1)]);
+    std::sort(nb.begin(), nb.end());
+    c->nbr_list.insert(c->nbr_list.end(), nb.begin(), nb.end());
+    c->nbr_off[i + 1] = (int32_t)c->nbr_list.size();
+  }
+  Status st = onebody_factors(c);
+  if (st.code) return st;
+  // absolute and relative coordinates
+  std::vector<double> Y(2 * c->Ns), X(2 * c->Nt);
+  std::vector<float> Xr32(2 * c->Nt);
+  std::vector<int32_t> tb(c->Nt);
+  for (int i = 0; i < P; ++i) {
+    const int k = c->cls[i];
+    const std::vector<double>& yr = c->h_Yr[k];
+    const std::vector<double>& xr = c->h_Xr[k];
+    for (int j = 0; j < n_src[i]; ++j) {
+      Y[2 * (c->src_off[i] + j)] = centers[2 * i] + yr[2 * j];
+      Y[2 * (c->src_off[i] + j) + 1] = centers[2 * i + 1] + yr[2 * j + 1];
+    }
+    for (int q = 0; q < n_col[i]; ++q) {
+      const int64_t t = c->col_off[i] + q;
+      X[2 * t] = centers[2 * i] + xr[2 * q];
+      X[2 * t + 1] = centers[2 * i + 1] + xr[2 * q + 1];
+      Xr32[2 * t] = (float)xr[2 * q];
+      Xr32[2 * t + 1] = (float)xr[2 * q + 1];
+      tb[t] = i;
+    }
+  }
+  hipStream_t s = c->stream;
+  if ((st = upload(&c->d_src_off, c->src_off, s)).code) return st;
+  if ((st = upload(&c->d_col_off, c->col_off, s)).code) return st;
+  if ((st = upload(&c->d_cls, c->cls, s)).code) return st;
+  if ((st = upload(&c->d_tgt_body, tb, s)).code) return st;
+  if ((st = upload(&c->d_pairs, c->pairs, s)).code) return st;
+  if ((st = upload(&c->d_bp_off, c->bp_off, s)).code) return st;
+  if ((st = upload(&c->d_bp_list, c->bp_list, s)).code) return st;
+  if ((st = upload(&c->d_nbr_off, c->nbr_off, s)).code) return st;
+  if ((st = upload(&c->d_nbr_list, c->nbr_list, s)).code) return st;
+  if ((st = upload(&c->d_xoff, c->xoff, s)).code) return st;
+  if ((st = upload(&c->d_aoff, c->aoff, s)).code) return st;
+  if ((st = upload(&c->d_coff, c->coff, s)).code) return st;
+  if ((st = upload(&c->d_centers, c->centers, s)).code) return st;
+  if ((st = upload(&c->d_Y, Y, s)).code) return st;
+  if ((st = upload(&c->d_X, X, s)).code) return st;
+  if ((st = upload(&c->d_Xr32, Xr32, s)).code) return st;
+  if ((st = dalloc(&c->d_lam_bar, 2 * c->Ns)).code) return st;
+  if ((st = dalloc(&c->d_ltil, c->xoff[C])).code) return st;
+  if ((st = dalloc(&c->d_u, 2 * c->Nt)).code) return st;
+  if ((st = dalloc(&c->d_corr, c->coff[C])).code) return st;
+  if ((st = dalloc(&c->d_epair, 6 * (size_t)C)).code) return st;
+  if ((st = dalloc(&c->d_out3, 3 * (size_t)P)).code) return st;
+  if ((st = dalloc(&c->d_given, 3 * (size_t)P)).code) return st;
+  if ((st = dalloc(&c->d_sig32, c->Ns)).code) return st;
+  if ((st = dalloc(&c->d_bdat, (size_t)P)).code) return st;
+  if ((st = dalloc(&c->d_src64, c->Ns)).code) return st;
+  MFS_HIP(hipStreamSynchronize(s));
+  return Status{};
+}
+
+Status check_kernel_sum(mfs_ctx* c, bool launched) {
+  if (!launched) return Status{MFS_ERR_OOM, "kernel-sum split buffer does not fit"};
+  MFS_HIP(hipGetLastError());
+  return Status{};
+}
+
+}  // namespace
+
+namespace mfs {
+
+Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u) {
+  const bool wp = c->pairs.size() > 0;
+  launch_onebody_apply(c, prob, mu, c->d_lam_bar);
+  if (wp) launch_pair_A(c, prob, c->d_lam_bar, c->d_ltil);
+  launch_gather_project(c, prob, c->d_lam_bar, c->d_ltil, wp, mixed, !mixed);
+  const bool ks = launch_kernel_sum(c, mixed, 2, c->d_u, 1.0 / (4.0 * kPiD * c->prm.mu));
+  if (wp) launch_pair_field(c, prob, c->d_ltil, c->d_corr);
+  launch_finish(c, c->d_u, mu, c->d_corr, u, wp);
+  return check_kernel_sum(c, ks);
+}
+
+}  // namespace mfs
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void mfs_default_params(mfs_params* p) {
+  if (!p) return;
+  p->mu = 1.0;
+  p->delta_c = 0.2;
+  p->eps_trunc = 1e-14;
+  p->eps_trunc_fine = 1e-11;
+  p->eps_ring = 1e-12;
+  p->n_fp = 150;
+  p->n_ell = 80;
+  p->m_p = 200;
+  p->a_ell = 5;
+  p->gamma = 0.3;
+  p->a_f = 1.2;
+  p->mobius_r = 0.6;
+}
+
+mfs_status mfs_setup(mfs_ctx** out, int32_t P, const double* centers, const double* radii, const int32_t* n_src,
+                     const int32_t* n_col, const double* r_src, const mfs_params* prm, void* stream) {
+  if (!out) return fail(nullptr, Status{MFS_ERR_ARG, "ctx pointer is NULL"});
+  *out = nullptr;
+  if (P < 1 || !centers || !radii || !n_src || !n_col || !r_src)
+    return fail(nullptr, Status{MFS_ERR_ARG, "P < 1 or NULL geometry array"});
+  mfs_params p;
+  if (prm)
+    p = *prm;
+  else
+    mfs_default_params(&p);
+  if (!(p.mu > 0) || !(p.delta_c >= 0) || !(p.eps_trunc > 0 && p.eps_trunc < 1) ||
+      !(p.eps_trunc_fine > 0 && p.eps_trunc_fine < 1) || !(p.eps_ring > 0 && p.eps_ring < 1) || p.n_fp < 4 ||
+      p.n_ell < 1 || p.m_p < 8 || p.a_ell < 1 || !(p.gamma > 0 && p.gamma < 1) || !(p.a_f >= 1) ||
+      !(p.mobius_r >= 0 && p.mobius_r < 1) || !(p.delta_c < 2 * (std::sqrt(3.0) - 1.0)) ||
+      ring_rule(p.n_fp, p.eps_ring) <= 0)
+    return fail(nullptr, Status{MFS_ERR_ARG, "invalid method parameters"});
+  mfs_ctx* c = new (std::nothrow) mfs_ctx();
+  if (!c) return fail(nullptr, Status{MFS_ERR_OOM, "host allocation failed"});
+  c->P = P;
+  c->prm = p;
+  {
+    Status st = validate_host(c, centers, radii, n_src, n_col, r_src);
+    if (st.code) {
+      delete c;
+      return fail(nullptr, st);
+    }
+  }
+  c->stream = (hipStream_t)stream;   // NULL: the null (default) stream
+  c->own_stream = false;
+  if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
+      rocblas_set_stream(c->blas, c->stream) != rocblas_status_success) {
+    free_all(c);
+    delete c;
+    return fail(nullptr, Status{MFS_ERR_DEVICE, "rocBLAS handle creation failed"});
+  }
+  Status st = build(c, centers, radii, n_src, n_col, r_src);
+  if (st.code) {
+    free_all(c);
+    delete c;
+    return fail(nullptr, st);
+  }
+  *out = c;
+  return MFS_OK;
+}
+
+mfs_status mfs_precompute_pairs(mfs_ctx* c, mfs_problem prob, int64_t* n_pairs_out) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if (prob != MFS_RESISTANCE && prob != MFS_MOBILITY) return fail(c, Status{MFS_ERR_ARG, "unknown problem"});
+  Status st = precompute_pairs(c, prob);
+  if (st.code) return fail(c, st);
+  if (n_pairs_out) *n_pairs_out = (int64_t)(c->pairs.size() / 2);
+  return ok(c);
+}
+
+mfs_status mfs_get_pairs(const mfs_ctx* c, int64_t* n_pairs, int32_t* pairs) {
+  if (!c || !n_pairs) return MFS_ERR_ARG;
+  *n_pairs = (int64_t)(c->pairs.size() / 2);
+  if (pairs) std::memcpy(pairs, c->pairs.data(), sizeof(int32_t) * c->pairs.size());
+  return MFS_OK;
+}
+
+mfs_status mfs_set_pair_matrices(mfs_ctx* c, mfs_problem prob, const double* A, const double* E) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if ((prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || !A || !E)
+    return fail(c, Status{MFS_ERR_ARG, "unknown problem or NULL matrix"});
+  const int C = (int)(c->pairs.size() / 2);
+  PairSet& ps = c->ps[prob];
+  if (!ps.A) {
+    Status st = dalloc(&ps.A, c->aoff[C]);
+    if (!st.code) st = dalloc(&ps.E, 6 * c->xoff[C]);
+    if (st.code) return fail(c, st);
+  }
+  std::vector<double> Ac(c->aoff[C]), Ec(6 * c->xoff[C]);
+  for (int p = 0; p < C; ++p) {
+    const int64_t n = c->xoff[p + 1] - c->xoff[p];
+    const double* a = A + c->aoff[p];
+    double* ac = Ac.data() + c->aoff[p];
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t q = 0; q < n; ++q) ac[q * n + r] = a[r * n + q];
+    const double* e = E + 6 * c->xoff[p];
+    double* ec = Ec.data() + 6 * c->xoff[p];
+    for (int r = 0; r < 6; ++r)
+      for (int64_t q = 0; q < n; ++q) ec[q * 6 + r] = e[r * n + q];
+  }
+  if (!finite_all(Ac.data(), Ac.size()) || !finite_all(Ec.data(), Ec.size()))
+    return fail(c, Status{MFS_ERR_NUMERIC, "non-finite pair matrix"});
+  if (hipMemcpy(ps.A, Ac.data(), sizeof(double) * Ac.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ps.E, Ec.data(), sizeof(double) * Ec.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, Status{MFS_ERR_DEVICE, "hipMemcpy of pair matrices failed"});
+  ps.ready = true;
+  return ok(c);
+}
+
+mfs_status mfs_get_pair_matrices(const mfs_ctx* cc, mfs_problem prob, double* A, double* E) {
+  mfs_ctx* c = const_cast<mfs_ctx*>(cc);
+  if (!c) return MFS_ERR_ARG;
+  if ((prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || !A || !E) return fail(c, Status{MFS_ERR_ARG, "bad argument"});
+  const PairSet& ps = c->ps[prob];
+  if (!ps.ready) return fail(c, Status{MFS_ERR_STATE, "pair matrices not computed for this problem"});
+  const int C = (int)(c->pairs.size() / 2);
+  std::vector<double> Ac(c->aoff[C]), Ec(6 * c->xoff[C]);
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(Ac.data(), ps.A, sizeof(double) * Ac.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(Ec.data(), ps.E, sizeof(double) * Ec.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, Status{MFS_ERR_DEVICE, "hipMemcpy of pair matrices failed"});
+  for (int p = 0; p < C; ++p) {
+    const int64_t n = c->xoff[p + 1] - c->xoff[p];
+    const double* ac = Ac.data() + c->aoff[p];
+    double* a = A + c->aoff[p];
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t q = 0; q < n; ++q) a[r * n + q] = ac[q * n + r];
+    const double* ec = Ec.data() + 6 * c->xoff[p];
+    double* e = E + 6 * c->xoff[p];
+    for (int r = 0; r < 6; ++r)
+      for (int64_t q = 0; q < n; ++q) e[r * n + q] = ec[q * 6 + r];
+  }
+  return ok(c);
+}
+
+mfs_status mfs_apply(mfs_ctx* c, mfs_problem prob, mfs_precision prec, int32_t n_rhs, const double* mu_in,
+                     double* u_out) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if ((prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || (prec != MFS_FP64 && prec != MFS_MIXED) || n_rhs < 1 ||
+      !mu_in || !u_out)
+    return fail(c, Status{MFS_ERR_ARG, "bad argument"});
+  if (!c->ps[prob].ready && !c->pairs.empty())
+    return fail(c, Status{MFS_ERR_STATE, "mfs_precompute_pairs has not run for this problem"});
+  const int64_t n = 2 * c->Nt;
+  for (int r = 0; r < n_rhs; ++r) {
+    Status st = apply_T(c, prob, prec == MFS_MIXED, mu_in + r * n, u_out + r * n);
+    if (st.code) return fail(c, st);
+  }
+  return ok(c);
+}
+
+mfs_status mfs_kernel_sum(mfs_ctx* c, mfs_precision prec, const double* sigma, double* u, int32_t skip) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if ((prec != MFS_FP64 && prec != MFS_MIXED) || !sigma || !u || skip < 0 || skip > 2)
+    return fail(c, Status{MFS_ERR_ARG, "bad argument"});
+  const bool mixed = prec == MFS_MIXED;
+  launch_gather_project(c, MFS_RESISTANCE, sigma, nullptr, false, mixed, !mixed);
+  const bool ks = launch_kernel_sum(c, mixed, skip, u, 1.0 / (4.0 * kPiD * c->prm.mu));
+  Status st = check_kernel_sum(c, ks);
+  if (st.code) return fail(c, st);
+  return ok(c);
+}
+
+mfs_status mfs_rhs(mfs_ctx* c, mfs_problem prob, const double* given, double* b) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if ((prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || !given || !b) return fail(c, Status{MFS_ERR_ARG, "bad argument"});
+  if (!finite_all(given, 3 * (size_t)c->P)) return fail(c, Status{MFS_ERR_NUMERIC, "non-finite right-hand side"});
+  if (hipMemcpyAsync(c->d_given, given, sizeof(double) * 3 * c->P, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return fail(c, Status{MFS_ERR_DEVICE, "hipMemcpy"});
+  bool ks = true;
+  if (prob == MFS_MOBILITY) {
+    launch_rhs_mobility_sources(c, c->d_given);
+    ks = launch_kernel_sum(c, false, 0, b, -1.0 / (4.0 * kPiD * c->prm.mu));
+  } else {
+    launch_rhs_resistance(c, c->d_given, b);
+  }
+  Status st = check_kernel_sum(c, ks);
+  if (!st.code && hipStreamSynchronize(c->stream) != hipSuccess) st = Status{MFS_ERR_DEVICE, "stream error"};
+  if (st.code) return fail(c, st);
+  return ok(c);
+}
+
+mfs_status mfs_post(mfs_ctx* c, mfs_problem prob, const double* mu, double* out) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if ((prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || !mu || !out) return fail(c, Status{MFS_ERR_ARG, "bad argument"});
+  if (!c->ps[prob].ready && !c->pairs.empty())
+    return fail(c, Status{MFS_ERR_STATE, "mfs_precompute_pairs has not run for this problem"});
+  launch_onebody_apply(c, prob, mu, c->d_lam_bar);
+  launch_post(c, prob, c->d_lam_bar, c->d_out3);
+  if (hipMemcpyAsync(out, c->d_out3, sizeof(double) * 3 * c->P, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(c, Status{MFS_ERR_DEVICE, "post-processing failed"});
+  return ok(c);
+}
+
+mfs_status mfs_get_sizes(const mfs_ctx* c, int32_t* P, int64_t* ns, int64_t* nt, int64_t* np) {
+  if (!c) return MFS_ERR_ARG;
+  if (P) *P = c->P;
+  if (ns) *ns = c->Ns;
+  if (nt) *nt = c->Nt;
+  if (np) *np = (int64_t)(c->pairs.size() / 2);
+  return MFS_OK;
+}
+
+mfs_status mfs_destroy(mfs_ctx* c) {
+  if (!c) return MFS_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return MFS_OK;
+}
+
+const char* mfs_last_error(const mfs_ctx* c) {
+  if (!c) return g_setup_err.c_str();
+  return c->last.msg.c_str();
+}
+
+}  // extern "C"

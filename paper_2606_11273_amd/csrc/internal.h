@@ -1,0 +1,144 @@
+// Internal state and kernel entry points of the MFS library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mfs.h"
+#include "geometry.h"
+
+namespace mfs {
+
+constexpr int kMaxClasses = 4;     // distinct (radius, n_src, n_col, r_src) disk classes
+constexpr int kMaxCol = 512;       // n_col limit per disk
+constexpr double kPiD = 3.14159265358979323846;
+
+struct Status {
+  mfs_status code = MFS_OK;
+  std::string msg;
+};
+
+// Shared one-body factors of a disk class, passed to kernels by value.
+struct ClassTab {
+  int n = 0;
+  int nc[kMaxClasses], mc[kMaxClasses], rank[kMaxClasses];
+  const double* U[kMaxClasses];     // (2 mc x rank) row-major: left singular vectors
+  const double* sinv[kMaxClasses];  // rank: truncated 1/sigma
+  const double* Vt[kMaxClasses];    // (rank x 2 nc) row-major: right singular vectors transposed
+  const double* Yr[kMaxClasses];    // nc x 2: sources relative to the centre
+  const double* Xr[kMaxClasses];    // mc x 2: nodes relative to the centre
+  double KtKi[kMaxClasses][9];      // (K^T K)^{-1}, row-major, of the coarse source ring
+  double radius[kMaxClasses];
+};
+
+struct PairSet {
+  bool ready = false;
+  double* A = nullptr;   // per pair column-major (n x n), n = n_i + n_k, offset aoff[c]
+  double* E = nullptr;   // per pair column-major (6 x n), offset 6 * xoff[c]
+};
+
+// GMRES work space, sized on first use.
+struct Krylov {
+  int64_t n = 0;
+  int cap = 0;           // basis vectors allocated
+  double* V = nullptr;   // n x cap, column j at V + j n
+  double* w = nullptr;
+  double* part = nullptr;    // partial dot products
+  double* hdev = nullptr;    // reduced dots
+  double* hhost = nullptr;   // pinned host mirror
+  double* x = nullptr;
+  double* r = nullptr;
+  double* b = nullptr;
+  double* d = nullptr;
+  double* tmp = nullptr;
+};
+
+}  // namespace mfs
+
+struct mfs_ctx {
+  int P = 0;
+  mfs_params prm{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  rocblas_handle blas = nullptr;
+  mfs::Status last;
+
+  // host geometry
+  std::vector<double> centers, radii, r_src;
+  std::vector<int32_t> n_src, n_col, cls;  // per body
+  std::vector<int32_t> src_off, col_off;   // P + 1
+  std::vector<int32_t> pairs;              // 2 C
+  std::vector<int64_t> xoff, aoff, coff;   // C + 1: pair source-vector, matrix and node-vector offsets
+  std::vector<int32_t> bp_off, bp_list;    // body -> (pair, side) CSR
+  std::vector<int32_t> nbr_off, nbr_list;  // body -> sorted contact partners
+  int64_t Ns = 0, Nt = 0;
+
+  // class data
+  mfs::ClassTab ct[2];                     // [problem]
+  std::vector<void*> class_bufs;
+  std::vector<double> h_Yr[mfs::kMaxClasses], h_Xr[mfs::kMaxClasses];   // host copies (relative rings)
+
+  // device geometry
+  int32_t *d_src_off = nullptr, *d_col_off = nullptr, *d_cls = nullptr, *d_tgt_body = nullptr;
+  int32_t *d_pairs = nullptr, *d_bp_off = nullptr, *d_bp_list = nullptr, *d_nbr_off = nullptr, *d_nbr_list = nullptr;
+  int64_t *d_xoff = nullptr, *d_aoff = nullptr, *d_coff = nullptr;
+  double* d_centers = nullptr;   // P x 2
+  double* d_Y = nullptr;         // Ns x 2 absolute sources
+  double* d_X = nullptr;         // Nt x 2 absolute nodes
+  float* d_Xr32 = nullptr;       // Nt x 2 nodes relative to their centre
+
+  // work vectors
+  double *d_lam_bar = nullptr, *d_ltil = nullptr, *d_sig64 = nullptr, *d_u = nullptr, *d_corr = nullptr;
+  double *d_upart = nullptr, *d_epair = nullptr, *d_out3 = nullptr, *d_given = nullptr;
+  float4* d_sig32 = nullptr;     // per source: (yr_x, yr_y, sigma_x, sigma_y)
+  float4* d_bdat = nullptr;      // per disk: (net strength x, y, ring radius^2, 0) for the FP32 sum
+  double4* d_src64 = nullptr;    // per source: (y_x, y_y, sigma_x, sigma_y)
+  int64_t upart_cap = 0;
+
+  mfs::PairSet ps[2];
+  mfs::Krylov kr;
+};
+
+namespace mfs {
+
+// ---- kernel launchers (kernels.hip) ----
+void launch_onebody_apply(mfs_ctx* c, int prob, const double* mu, double* lam_bar);
+void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil);
+void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
+                           bool pack32, bool pack64);
+// mode 0: all sources; 1: skip the target's own disk; 2: also skip its contact partners.  false: out of memory
+bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale);
+void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr);
+void launch_finish(mfs_ctx* c, const double* u_sum, const double* mu, const double* corr, double* u_out,
+                   bool with_pairs);
+void launch_rhs_mobility_sources(mfs_ctx* c, const double* given);
+void launch_rhs_resistance(mfs_ctx* c, const double* given, double* b);
+void launch_post(mfs_ctx* c, int prob, const double* lam_bar, double* out3);
+// GMRES helpers
+void launch_mdot(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* part,
+                 double* out, int nblk);
+void launch_maxpy(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w);
+void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y);
+void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, double* y);
+void launch_gemv_n(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* y, double* x);
+int mdot_blocks(int64_t n);
+
+// ---- precompute (precompute.hip) ----
+Status onebody_factors(mfs_ctx* c);
+Status precompute_pairs(mfs_ctx* c, int prob);
+
+// ---- matvec pieces (capi.hip) ----
+Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u);
+
+}  // namespace mfs
+
+#define MFS_HIP(call)                                                                             \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return ::mfs::Status{MFS_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)

@@ -1,0 +1,830 @@
+// gfx950 kernels of the matvec T mu (Alg. 3), the right-hand side, the
+// post-processing and the GMRES vector operations.
+//
+// Layout: per-node and per-source 2-vectors are (x, y) interleaved, bodies in
+// order (offsets src_off / col_off).  Every reduction over several producers
+// (pair contributions to a body, source splits of the kernel sum, block partials
+// of a dot product) runs in a fixed order, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mfs {
+
+namespace {
+
+constexpr int kBodyThreads = 128;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum over a block of up to 1024 threads; every thread gets the result.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  static_assert(NT % 64 == 0 && NT <= 1024, "block size");
+  constexpr int NW = NT / 64;
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += red[w];
+  return s;
+}
+
+// In-place (I - L) of a body's source strengths held in LDS: lambda - K (K^T K)^{-1} K^T lambda,
+// with K rows [1, 0, -yr_y; 0, 1, yr_x] (eq. Kmat, Sec. 4.1).
+template <int NT>
+__device__ void project_rigid(double* s_l, int nc, const double* Yr, const double* KtKi, double* red) {
+  double f0 = 0, f1 = 0, f2 = 0;
+  for (int j = threadIdx.x; j < nc; j += NT) {
+    double lx = s_l[2 * j], ly = s_l[2 * j + 1];
+    double yx = Yr[2 * j], yy = Yr[2 * j + 1];
+    f0 += lx;
+    f1 += ly;
+    f2 += -yy * lx + yx * ly;
+  }
+  f0 = block_sum<NT>(f0, red);
+  f1 = block_sum<NT>(f1, red + 16);
+  f2 = block_sum<NT>(f2, red + 32);
+  const double a0 = KtKi[0] * f0 + KtKi[1] * f1 + KtKi[2] * f2;
+  const double a1 = KtKi[3] * f0 + KtKi[4] * f1 + KtKi[5] * f2;
+  const double a2 = KtKi[6] * f0 + KtKi[7] * f1 + KtKi[8] * f2;
+  __syncthreads();
+  for (int j = threadIdx.x; j < nc; j += NT) {
+    double yx = Yr[2 * j], yy = Yr[2 * j + 1];
+    s_l[2 * j] -= a0 - a2 * yy;
+    s_l[2 * j + 1] -= a1 + a2 * yx;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Step 1a: lambda_bar = V Sigma^+ (U^T mu) per body, shared factors per class (eq. howG+, eq. SL).
+__global__ __launch_bounds__(kBodyThreads) void k_onebody(int P, const int* __restrict__ cls,
+                                                          const int* __restrict__ src_off,
+                                                          const int* __restrict__ col_off, ClassTab ct,
+                                                          const double* __restrict__ mu,
+                                                          double* __restrict__ lam) {
+  const int b = blockIdx.x;
+  if (b >= P) return;
+  const int k = cls[b];
+  const int m2 = 2 * ct.mc[k], n2 = 2 * ct.nc[k], r = ct.rank[k];
+  __shared__ double s_mu[2 * kMaxCol];
+  __shared__ double s_t[2 * kMaxCol];
+  const double* mub = mu + 2 * (int64_t)col_off[b];
+  for (int q = threadIdx.x; q < m2; q += kBodyThreads) s_mu[q] = mub[q];
+  __syncthreads();
+  const double* U = ct.U[k];
+  const double* si = ct.sinv[k];
+  for (int j = threadIdx.x; j < r; j += kBodyThreads) {
+    double acc = 0.0;
+    for (int q = 0; q < m2; ++q) acc = fma(U[(int64_t)q * r + j], s_mu[q], acc);
+    s_t[j] = acc * si[j];
+  }
+  __syncthreads();
+  const double* Vt = ct.Vt[k];
+  double* lb = lam + 2 * (int64_t)src_off[b];
+  for (int i = threadIdx.x; i < n2; i += kBodyThreads) {
+    double acc = 0.0;
+    for (int j = 0; j < r; ++j) acc = fma(Vt[(int64_t)j * n2 + i], s_t[j], acc);
+    lb[i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 1b: lambda_tilde^c = A^c [lambda_bar^(i); lambda_bar^(k)] per close pair (eq. correction).
+// A^c column-major: for a fixed column the threads of a block read consecutive rows.
+constexpr int kPairThreads = 256;
+__global__ __launch_bounds__(kPairThreads) void k_pair_A(int C, const int* __restrict__ pairs,
+                                                         const int* __restrict__ src_off,
+                                                         const int64_t* __restrict__ xoff,
+                                                         const int64_t* __restrict__ aoff,
+                                                         const double* __restrict__ A,
+                                                         const double* __restrict__ lam,
+                                                         double* __restrict__ ltil) {
+  const int c = blockIdx.x;
+  if (c >= C) return;
+  const int i = pairs[2 * c], k = pairs[2 * c + 1];
+  const int ni = 2 * (src_off[i + 1] - src_off[i]);
+  const int n = (int)(xoff[c + 1] - xoff[c]);
+  __shared__ double s_x[4 * kMaxCol];
+  for (int q = threadIdx.x; q < n; q += kPairThreads)
+    s_x[q] = q < ni ? lam[2 * (int64_t)src_off[i] + q] : lam[2 * (int64_t)src_off[k] + (q - ni)];
+  __syncthreads();
+  const double* Ac = A + aoff[c];
+  for (int row = threadIdx.x; row < n; row += kPairThreads) {
+    double acc = 0.0;
+    for (int col = 0; col < n; ++col) acc = fma(Ac[(int64_t)col * n + row], s_x[col], acc);
+    ltil[xoff[c] + row] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// eq. total_corr + projection: lambda^(b) = lambda_bar^(b) + sum_{c contains b} lambda_tilde^c_b,
+// sigma = (I - L) lambda (mobility) or lambda (resistance); packed for the kernel sum.
+__global__ __launch_bounds__(kBodyThreads) void k_gather_project(
+    int P, int mobility, const int* __restrict__ cls, const int* __restrict__ src_off, ClassTab ct,
+    const int* __restrict__ bp_off, const int* __restrict__ bp_list, const int* __restrict__ pairs,
+    const int64_t* __restrict__ xoff, const double* __restrict__ ltil, const double* __restrict__ lam_bar,
+    int with_pairs, const double* __restrict__ centers, double* __restrict__ sig64, float4* __restrict__ sig32,
+    double4* __restrict__ src64, float4* __restrict__ bdat) {
+  const int b = blockIdx.x;
+  if (b >= P) return;
+  const int k = cls[b];
+  const int nc = ct.nc[k];
+  const int64_t so = src_off[b];
+  __shared__ double s_l[2 * kMaxCol];
+  __shared__ double red[64];
+  for (int q = threadIdx.x; q < 2 * nc; q += kBodyThreads) {
+    double v = lam_bar[2 * so + q];
+    if (with_pairs) {
+      for (int e = bp_off[b]; e < bp_off[b + 1]; ++e) {
+        const int c = bp_list[e] >> 1, side = bp_list[e] & 1;
+        const int64_t off = xoff[c] + (side ? 2 * (src_off[pairs[2 * c] + 1] - src_off[pairs[2 * c]]) : 0);
+        v += ltil[off + q];
+      }
+    }
+    s_l[q] = v;
+  }
+  __syncthreads();
+  if (mobility) project_rigid<kBodyThreads>(s_l, nc, ct.Yr[k], ct.KtKi[k], red);
+  const double* Yr = ct.Yr[k];
+  const double cx = centers[2 * b], cy = centers[2 * b + 1];
+  if (bdat) {
+    // net strength of the disk (FP64 sum) and its ring radius squared, for the
+    // compensated log of the FP32 kernel sum
+    double s0x = 0, s0y = 0;
+    for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
+      s0x += s_l[2 * j];
+      s0y += s_l[2 * j + 1];
+    }
+    s0x = block_sum<kBodyThreads>(s0x, red);
+    s0y = block_sum<kBodyThreads>(s0y, red + 16);
+    if (threadIdx.x == 0) {
+      const double q = Yr[0] * Yr[0] + Yr[1] * Yr[1];
+      bdat[b] = make_float4((float)s0x, (float)s0y, (float)q, 0.0f);
+    }
+  }
+  for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
+    const double sx = s_l[2 * j], sy = s_l[2 * j + 1];
+    if (sig64) {
+      sig64[2 * (so + j)] = sx;
+      sig64[2 * (so + j) + 1] = sy;
+    }
+    if (sig32) sig32[so + j] = make_float4((float)Yr[2 * j], (float)Yr[2 * j + 1], (float)sx, (float)sy);
+    if (src64) src64[so + j] = make_double4(cx + Yr[2 * j], cy + Yr[2 * j + 1], sx, sy);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 2a: all-pairs Stokeslet sum u_t = sum_s S(x_t, y_s) sigma_s (eq. getall, eq. stokeslet2d).
+//
+// A workgroup owns KS_T * 256 consecutive targets and streams the sources of a
+// range of bodies (one split of blockIdx.y) through LDS in tiles of whole bodies.
+//   u = 1/(4 pi mu) [ sum (d.sigma / r^2) d  -  (ln 2 / 2) sum log2(r^2) sigma ].
+// Mixed form: per (target, source disk) the offset D of the target from the disk
+// centre is formed in FP64 and rounded once; the pair terms are evaluated in FP32
+// on body-relative coordinates (v_rcp_f32 for 1/r^2, v_log_f32 for the log) and
+// summed per source disk in FP32; each disk's partial is added to FP64
+// accumulators.  Compensated log: with y the source offset on the ring (|y|^2 = q),
+//   log2 r^2 = log2 R^2 + log2(1 + (q - 2 D.y) / R^2),   R = |D|,
+// so sum_s log2(r_s^2) sigma_s = log2(R^2) S0 + sum_s log2(u_s) sigma_s with S0 the
+// disk's net strength (from the FP64 strengths).  The FP32 rounding of the second
+// sum scales with |u_s - 1| ~ |y|/R instead of |log2 r^2|, so the far-field error
+// of a disk whose strengths nearly cancel shrinks with distance.
+constexpr int KS_THREADS = 256;
+constexpr int KS_TILE = 1024;   // sources per LDS tile (16 KB of float4)
+constexpr int KS_MAXB = 64;     // bodies per LDS tile
+
+// Skip modes: 0 = every source, 1 = skip the target's own disk, 2 = skip the own disk
+// and its contact partners (nbr_off/nbr_list: sorted partner list per disk).  A
+// thread walks its target's sorted partner list alongside the increasing source
+// body index, so the test costs one compare per (target, source disk).
+struct Skip {
+  int next;   // next partner >= current source body, or INT_MAX
+  int pos, end;
+};
+
+__device__ __forceinline__ void skip_init(Skip& sk, int mode, int body, int kb0, const int* __restrict__ nbr_off,
+                                          const int* __restrict__ nbr_list) {
+  sk.next = 0x7fffffff;
+  sk.pos = sk.end = 0;
+  if (mode != 2) return;
+  sk.pos = nbr_off[body];
+  sk.end = nbr_off[body + 1];
+  while (sk.pos < sk.end && nbr_list[sk.pos] < kb0) ++sk.pos;
+  if (sk.pos < sk.end) sk.next = nbr_list[sk.pos];
+}
+
+// true if source body kb must be skipped for this target; advances the partner cursor
+__device__ __forceinline__ bool skip_test(Skip& sk, int mode, int kb, int body, const int* __restrict__ nbr_list) {
+  if (mode == 0) return false;
+  if (kb == body) return true;
+  if (kb == sk.next) {
+    ++sk.pos;
+    sk.next = sk.pos < sk.end ? nbr_list[sk.pos] : 0x7fffffff;
+    return true;
+  }
+  return false;
+}
+
+template <int T>
+__global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __restrict__ src_off,
+                                                           const double* __restrict__ centers,
+                                                           const float4* __restrict__ src,
+                                                           const float4* __restrict__ bdat, int64_t Nt,
+                                                           const int* __restrict__ tgt_body,
+                                                           const float* __restrict__ xr32, int bodies_per_split,
+                                                           int mode, const int* __restrict__ nbr_off,
+                                                           const int* __restrict__ nbr_list, double scale,
+                                                           double* __restrict__ out) {
+  __shared__ float4 s_src[KS_TILE];
+  __shared__ double s_c[2 * KS_MAXB];
+  __shared__ float4 s_b[KS_MAXB];
+  __shared__ int s_off[KS_MAXB + 1];
+  const int split = blockIdx.y;
+  const int kb0 = split * bodies_per_split;
+  const int kb1 = min(P, kb0 + bodies_per_split);
+  int64_t t[T];
+  int bt[T];
+  double cx[T], cy[T], ax[T], ay[T];
+  float xr[T], yr[T];
+  Skip sk[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + j * KS_THREADS + threadIdx.x;
+    const int64_t tc = t[j] < Nt ? t[j] : Nt - 1;
+    bt[j] = tgt_body[tc];
+    cx[j] = centers[2 * bt[j]];
+    cy[j] = centers[2 * bt[j] + 1];
+    xr[j] = xr32[2 * tc];
+    yr[j] = xr32[2 * tc + 1];
+    ax[j] = 0.0;
+    ay[j] = 0.0;
+    skip_init(sk[j], mode, bt[j], kb0, nbr_off, nbr_list);
+  }
+  const float kHalfLn2 = 0.34657359027997264f;
+  for (int kt = kb0; kt < kb1;) {
+    const int s0 = src_off[kt];
+    int nb = 0;
+    while (kt + nb < kb1 && nb < KS_MAXB && src_off[kt + nb + 1] - s0 <= KS_TILE) ++nb;
+    const int ns = src_off[kt + nb] - s0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < ns; q += KS_THREADS) s_src[q] = src[s0 + q];
+    for (int q = threadIdx.x; q < nb; q += KS_THREADS) {
+      s_c[2 * q] = centers[2 * (kt + q)];
+      s_c[2 * q + 1] = centers[2 * (kt + q) + 1];
+      s_b[q] = bdat[kt + q];
+    }
+    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
+    __syncthreads();
+    for (int kk = 0; kk < nb; ++kk) {
+      const int kbody = kt + kk;
+      const float4 bd = s_b[kk];   // (S0x, S0y, q, -)
+      float dxt[T], dyt[T], r2c[T], ir2c[T], lx[T], ly[T], tx[T], ty[T];
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        dxt[j] = (float)(cx[j] - s_c[2 * kk]) + xr[j];
+        dyt[j] = (float)(cy[j] - s_c[2 * kk + 1]) + yr[j];
+        r2c[j] = fmaf(dxt[j], dxt[j], dyt[j] * dyt[j]);
+        ir2c[j] = __builtin_amdgcn_rcpf(r2c[j]);
+        lx[j] = ly[j] = tx[j] = ty[j] = 0.0f;
+      }
+      const int q1 = s_off[kk + 1];
+      for (int q = s_off[kk]; q < q1; ++q) {
+        const float4 s = s_src[q];
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const float dx = dxt[j] - s.x;
+          const float dy = dyt[j] - s.y;
+          const float dy2 = fmaf(dxt[j], s.x, dyt[j] * s.y);      // D.y
+          const float num = fmaf(-2.0f, dy2, bd.z);                 // q - 2 D.y = r^2 - R^2
+          const float u = fmaf(num, ir2c[j], 1.0f);                 // r^2 / R^2
+          const float r2 = r2c[j] * u;
+          const float lg = __builtin_amdgcn_logf(u);
+          const float inv = __builtin_amdgcn_rcpf(r2);
+          const float dot = fmaf(dx, s.z, dy * s.w) * inv;
+          lx[j] = fmaf(lg, s.z, lx[j]);
+          ly[j] = fmaf(lg, s.w, ly[j]);
+          tx[j] = fmaf(dot, dx, tx[j]);
+          ty[j] = fmaf(dot, dy, ty[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
+          const float lR = __builtin_amdgcn_logf(r2c[j]);
+          ax[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.x, lx[j]), tx[j]);
+          ay[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.y, ly[j]), ty[j]);
+        }
+      }
+    }
+    kt += nb;
+  }
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    if (t[j] < Nt) {
+      out[((int64_t)split * Nt + t[j]) * 2] = ax[j] * scale;
+      out[((int64_t)split * Nt + t[j]) * 2 + 1] = ay[j] * scale;
+    }
+  }
+}
+
+// FP64 form of the same sum, absolute coordinates, OCML log.
+template <int T>
+__global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __restrict__ src_off,
+                                                          const double4* __restrict__ src, int64_t Nt,
+                                                          const int* __restrict__ tgt_body,
+                                                          const double* __restrict__ X, int bodies_per_split,
+                                                          int mode, const int* __restrict__ nbr_off,
+                                                          const int* __restrict__ nbr_list, double scale,
+                                                          double* __restrict__ out) {
+  __shared__ double4 s_src[KS_TILE / 2];
+  __shared__ int s_off[KS_MAXB + 1];
+  const int split = blockIdx.y;
+  const int kb0 = split * bodies_per_split;
+  const int kb1 = min(P, kb0 + bodies_per_split);
+  int64_t t[T];
+  int bt[T];
+  double x[T], y[T], ax[T], ay[T];
+  Skip sk[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + j * KS_THREADS + threadIdx.x;
+    const int64_t tc = t[j] < Nt ? t[j] : Nt - 1;
+    bt[j] = tgt_body[tc];
+    x[j] = X[2 * tc];
+    y[j] = X[2 * tc + 1];
+    ax[j] = 0.0;
+    ay[j] = 0.0;
+    skip_init(sk[j], mode, bt[j], kb0, nbr_off, nbr_list);
+  }
+  for (int kt = kb0; kt < kb1;) {
+    const int s0 = src_off[kt];
+    int nb = 0;
+    while (kt + nb < kb1 && nb < KS_MAXB && src_off[kt + nb + 1] - s0 <= KS_TILE / 2) ++nb;
+    const int ns = src_off[kt + nb] - s0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < ns; q += KS_THREADS) s_src[q] = src[s0 + q];
+    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
+    __syncthreads();
+    for (int kk = 0; kk < nb; ++kk) {
+      const int kbody = kt + kk;
+      double lx[T], ly[T], tx[T], ty[T];
+#pragma unroll
+      for (int j = 0; j < T; ++j) lx[j] = ly[j] = tx[j] = ty[j] = 0.0;
+      const int q1 = s_off[kk + 1];
+      for (int q = s_off[kk]; q < q1; ++q) {
+        const double4 s = s_src[q];
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const double dx = x[j] - s.x;
+          const double dy = y[j] - s.y;
+          const double r2 = fma(dx, dx, dy * dy);
+          const double lg = log(r2);
+          const double dot = fma(dx, s.z, dy * s.w) / r2;
+          lx[j] = fma(lg, s.z, lx[j]);
+          ly[j] = fma(lg, s.w, ly[j]);
+          tx[j] = fma(dot, dx, tx[j]);
+          ty[j] = fma(dot, dy, ty[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
+          ax[j] += fma(-0.5, lx[j], tx[j]);
+          ay[j] += fma(-0.5, ly[j], ty[j]);
+        }
+      }
+    }
+    kt += nb;
+  }
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    if (t[j] < Nt) {
+      out[((int64_t)split * Nt + t[j]) * 2] = ax[j] * scale;
+      out[((int64_t)split * Nt + t[j]) * 2 + 1] = ay[j] * scale;
+    }
+  }
+}
+
+__global__ void k_reduce_splits(int64_t n2, int nsplit, const double* __restrict__ part, double* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2) return;
+  double s = 0.0;
+  for (int p = 0; p < nsplit; ++p) s += part[(int64_t)p * n2 + i];
+  u[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Step 2b, per pair, in source form.  The kernel sum skipped each disk's own
+// sources and those of its contact partners; in exact arithmetic Alg. 3 leaves, on
+// body i of pair c = (i, k), the field of k's corrections from its other pairs:
+//   corr^c_i = S^(ik) Pi sum_{c' contains k, c' != c} lambda_tilde^{c'}_k
+// (the self blocks P Pi (.) of step 2b and the neighbour one-body terms H mu cancel
+// exactly against the skipped terms).  Evaluated directly in FP64, relative to c_k.
+__global__ __launch_bounds__(kPairThreads) void k_pair_field(
+    int C, int mobility, const int* __restrict__ pairs, const int* __restrict__ cls,
+    const int* __restrict__ src_off, const int* __restrict__ col_off, ClassTab ct,
+    const double* __restrict__ centers, const int64_t* __restrict__ xoff, const int64_t* __restrict__ coff,
+    const int* __restrict__ bp_off, const int* __restrict__ bp_list, const double* __restrict__ ltil,
+    double inv4pimu, double* __restrict__ corr) {
+  const int c = blockIdx.x;
+  if (c >= C) return;
+  const int i = pairs[2 * c], k = pairs[2 * c + 1];
+  const int ci = cls[i], ck = cls[k];
+  const int nci = ct.nc[ci], nck = ct.nc[ck], mci = ct.mc[ci], mck = ct.mc[ck];
+  __shared__ double s_vi[2 * kMaxCol];
+  __shared__ double s_vk[2 * kMaxCol];
+  __shared__ double red[64];
+  // sums over the other pairs of i (for the field on k) and of k (for the field on i)
+  const bool other_i = bp_off[i + 1] - bp_off[i] > 1, other_k = bp_off[k + 1] - bp_off[k] > 1;
+  if (!other_i && !other_k) {
+    for (int q = threadIdx.x; q < 2 * (mci + mck); q += kPairThreads) corr[coff[c] + q] = 0.0;
+    return;
+  }
+  for (int side = 0; side < 2; ++side) {
+    const int b = side ? k : i;
+    const int n2 = 2 * (side ? nck : nci);
+    double* s_v = side ? s_vk : s_vi;
+    for (int q = threadIdx.x; q < n2; q += kPairThreads) {
+      double v = 0.0;
+      for (int e = bp_off[b]; e < bp_off[b + 1]; ++e) {
+        const int cc = bp_list[e] >> 1, sd = bp_list[e] & 1;
+        if (cc == c) continue;
+        const int64_t off = xoff[cc] + (sd ? 2 * (src_off[pairs[2 * cc] + 1] - src_off[pairs[2 * cc]]) : 0);
+        v += ltil[off + q];
+      }
+      s_v[q] = v;
+    }
+  }
+  __syncthreads();
+  if (mobility) {
+    project_rigid<kPairThreads>(s_vi, nci, ct.Yr[ci], ct.KtKi[ci], red);
+    project_rigid<kPairThreads>(s_vk, nck, ct.Yr[ck], ct.KtKi[ck], red);
+  }
+  const double dcx = centers[2 * i] - centers[2 * k], dcy = centers[2 * i + 1] - centers[2 * k + 1];
+  for (int q = threadIdx.x; q < mci + mck; q += kPairThreads) {
+    double tx, ty;
+    const double* Ys;
+    const double* vs;
+    int ns;
+    if (q < mci) {  // node q of body i, sources of body k (coordinates relative to c_k)
+      tx = ct.Xr[ci][2 * q] + dcx;
+      ty = ct.Xr[ci][2 * q + 1] + dcy;
+      Ys = ct.Yr[ck];
+      vs = s_vk;
+      ns = other_k ? nck : 0;
+    } else {        // node of body k, sources of body i (relative to c_i)
+      const int qq = q - mci;
+      tx = ct.Xr[ck][2 * qq] - dcx;
+      ty = ct.Xr[ck][2 * qq + 1] - dcy;
+      Ys = ct.Yr[ci];
+      vs = s_vi;
+      ns = other_i ? nci : 0;
+    }
+    double lx = 0, ly = 0, px = 0, py = 0;
+    for (int s = 0; s < ns; ++s) {
+      const double dx = tx - Ys[2 * s], dy = ty - Ys[2 * s + 1];
+      const double r2 = fma(dx, dx, dy * dy);
+      const double lg = log(r2);
+      const double sx = vs[2 * s], sy = vs[2 * s + 1];
+      const double dot = fma(dx, sx, dy * sy) / r2;
+      lx = fma(lg, sx, lx);
+      ly = fma(lg, sy, ly);
+      px = fma(dot, dx, px);
+      py = fma(dot, dy, py);
+    }
+    corr[coff[c] + 2 * q] = fma(-0.5, lx, px) * inv4pimu;
+    corr[coff[c] + 2 * q + 1] = fma(-0.5, ly, py) * inv4pimu;
+  }
+}
+
+// Identity fix and gather of the pair field corrections:
+// u^(b) = u_sum^(b) + mu^(b) + sum_{c contains b} corr^c_b.
+__global__ __launch_bounds__(kBodyThreads) void k_finish(int P, const int* __restrict__ col_off,
+                                                         const int* __restrict__ bp_off,
+                                                         const int* __restrict__ bp_list,
+                                                         const int* __restrict__ pairs,
+                                                         const int64_t* __restrict__ coff,
+                                                         const double* __restrict__ usum,
+                                                         const double* __restrict__ mu,
+                                                         const double* __restrict__ corr, int with_pairs,
+                                                         double* __restrict__ uout) {
+  const int b = blockIdx.x;
+  if (b >= P) return;
+  const int64_t o = 2 * (int64_t)col_off[b];
+  const int m2 = 2 * (col_off[b + 1] - col_off[b]);
+  for (int q = threadIdx.x; q < m2; q += kBodyThreads) {
+    double v = usum[o + q] + mu[o + q];
+    if (with_pairs) {
+      for (int e = bp_off[b]; e < bp_off[b + 1]; ++e) {
+        const int c = bp_list[e] >> 1, side = bp_list[e] & 1;
+        const int i = pairs[2 * c];
+        const int64_t off = coff[c] + (side ? 2 * (col_off[i + 1] - col_off[i]) : 0);
+        v += corr[off + q];
+      }
+    }
+    uout[o + q] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mobility RHS sources: lambda_0^(b) = K (K^T K)^{-1} [f; t]^(b) (Sec. 4.1), packed with absolute coordinates.
+__global__ __launch_bounds__(kBodyThreads) void k_rhs_sources(int P, const int* __restrict__ cls,
+                                                             const int* __restrict__ src_off, ClassTab ct,
+                                                             const double* __restrict__ centers,
+                                                             const double* __restrict__ given,
+                                                             double4* __restrict__ src64) {
+  const int b = blockIdx.x;
+  if (b >= P) return;
+  const int k = cls[b];
+  const double* Q = ct.KtKi[k];
+  const double f0 = given[3 * b], f1 = given[3 * b + 1], f2 = given[3 * b + 2];
+  const double a0 = Q[0] * f0 + Q[1] * f1 + Q[2] * f2;
+  const double a1 = Q[3] * f0 + Q[4] * f1 + Q[5] * f2;
+  const double a2 = Q[6] * f0 + Q[7] * f1 + Q[8] * f2;
+  const double cx = centers[2 * b], cy = centers[2 * b + 1];
+  const double* Yr = ct.Yr[k];
+  for (int j = threadIdx.x; j < ct.nc[k]; j += kBodyThreads) {
+    const double yx = Yr[2 * j], yy = Yr[2 * j + 1];
+    src64[src_off[b] + j] = make_double4(cx + yx, cy + yy, a0 - a2 * yy, a1 + a2 * yx);
+  }
+}
+
+// Resistance RHS: b = v + omega (x - c)^perp at every coarse node (eq. rigidbc).
+__global__ void k_rhs_resistance(int64_t Nt, const int* __restrict__ tgt_body, const double* __restrict__ X,
+                                 const double* __restrict__ centers, const double* __restrict__ given,
+                                 double* __restrict__ b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Nt) return;
+  const int p = tgt_body[t];
+  const double rx = X[2 * t] - centers[2 * p], ry = X[2 * t + 1] - centers[2 * p + 1];
+  b[2 * t] = given[3 * p] - given[3 * p + 2] * ry;
+  b[2 * t + 1] = given[3 * p + 1] + given[3 * p + 2] * rx;
+}
+
+// Post-processing, per pair: e^c = E^c [lambda_bar^(i); lambda_bar^(k)] (6 values).
+__global__ __launch_bounds__(64) void k_post_pairs(int C, const int* __restrict__ pairs,
+                                                   const int* __restrict__ src_off, const int64_t* __restrict__ xoff,
+                                                   const double* __restrict__ E, const double* __restrict__ lam,
+                                                   double* __restrict__ epair) {
+  const int c = blockIdx.x;
+  if (c >= C) return;
+  const int i = pairs[2 * c], k = pairs[2 * c + 1];
+  const int ni = 2 * (src_off[i + 1] - src_off[i]);
+  const int n = (int)(xoff[c + 1] - xoff[c]);
+  const double* Ec = E + 6 * xoff[c];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int q = threadIdx.x; q < n; q += 64) {
+    const double x = q < ni ? lam[2 * (int64_t)src_off[i] + q] : lam[2 * (int64_t)src_off[k] + q - ni];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) acc[r] = fma(Ec[(int64_t)q * 6 + r], x, acc[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    const double s = wave_sum(acc[r]);
+    if (threadIdx.x == 0) epair[6 * c + r] = s;
+  }
+}
+
+// Per body: out = sgn K^T lambda_bar + sum_c e^c_b (mobility: sgn = -1, eq. rbm_ansatz; resistance: +1).
+__global__ __launch_bounds__(64) void k_post_bodies(int P, int mobility, const int* __restrict__ cls,
+                                                    const int* __restrict__ src_off, ClassTab ct,
+                                                    const int* __restrict__ bp_off, const int* __restrict__ bp_list,
+                                                    const double* __restrict__ epair,
+                                                    const double* __restrict__ lam, int with_pairs,
+                                                    double* __restrict__ out3) {
+  const int b = blockIdx.x;
+  if (b >= P) return;
+  const int k = cls[b];
+  const double* Yr = ct.Yr[k];
+  const double* lb = lam + 2 * (int64_t)src_off[b];
+  double f0 = 0, f1 = 0, f2 = 0;
+  for (int j = threadIdx.x; j < ct.nc[k]; j += 64) {
+    const double lx = lb[2 * j], ly = lb[2 * j + 1];
+    f0 += lx;
+    f1 += ly;
+    f2 += -Yr[2 * j + 1] * lx + Yr[2 * j] * ly;
+  }
+  f0 = wave_sum(f0);
+  f1 = wave_sum(f1);
+  f2 = wave_sum(f2);
+  if (threadIdx.x == 0) {
+    const double sg = mobility ? -1.0 : 1.0;
+    double o0 = sg * f0, o1 = sg * f1, o2 = sg * f2;
+    if (with_pairs) {
+      for (int e = bp_off[b]; e < bp_off[b + 1]; ++e) {
+        const int c = bp_list[e] >> 1, side = bp_list[e] & 1;
+        o0 += epair[6 * c + 3 * side];
+        o1 += epair[6 * c + 3 * side + 1];
+        o2 += epair[6 * c + 3 * side + 2];
+      }
+    }
+    out3[3 * b] = o0;
+    out3[3 * b + 1] = o1;
+    out3[3 * b + 2] = o2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GMRES vector kernels.  Dot products: block partials in a fixed order, then a
+// per-vector sum over blocks in a fixed order.
+constexpr int kDotThreads = 256;
+
+__global__ __launch_bounds__(kDotThreads) void k_mdot(int64_t n, int k, const double* __restrict__ V, int64_t ldv,
+                                                      const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[16];
+  const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + kDotThreads - 1) / kDotThreads * kDotThreads;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = min(n, lo + chunk);
+  for (int j = 0; j < k; ++j) {
+    const double* v = V + (int64_t)j * ldv;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kDotThreads) acc = fma(v[i], w[i], acc);
+    acc = block_sum<kDotThreads>(acc, red);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + j] = acc;
+  }
+}
+
+__global__ void k_mdot_reduce(int k, int nblk, const double* __restrict__ part, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * k + j];
+  out[j] = s;
+}
+
+__global__ void k_maxpy(int64_t n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
+                        double* __restrict__ w) {
+  __shared__ double s_h[1024];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) s_h[j] = h[j];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = w[i];
+  for (int j = 0; j < k; ++j) acc = fma(-s_h[j], V[(int64_t)j * ldv + i], acc);
+  w[i] = acc;
+}
+
+__global__ void k_gemv_n(int64_t n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ y,
+                         double* __restrict__ x) {
+  __shared__ double s_y[1024];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) s_y[j] = y[j];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = x[i];
+  for (int j = 0; j < k; ++j) acc = fma(s_y[j], V[(int64_t)j * ldv + i], acc);
+  x[i] = acc;
+}
+
+__global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = fma(a, x[i], b * y[i]);
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+
+void launch_onebody_apply(mfs_ctx* c, int prob, const double* mu, double* lam_bar) {
+  hipLaunchKernelGGL(k_onebody, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
+                     c->d_col_off, c->ct[prob], mu, lam_bar);
+}
+
+void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil) {
+  const int C = (int)(c->pairs.size() / 2);
+  if (C == 0) return;
+  hipLaunchKernelGGL(k_pair_A, dim3(C), dim3(kPairThreads), 0, c->stream, C, c->d_pairs, c->d_src_off, c->d_xoff,
+                     c->d_aoff, c->ps[prob].A, lam_bar, ltil);
+}
+
+void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
+                           bool pack32, bool pack64) {
+  hipLaunchKernelGGL(k_gather_project, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P,
+                     prob == MFS_MOBILITY ? 1 : 0, c->d_cls, c->d_src_off, c->ct[prob], c->d_bp_off, c->d_bp_list,
+                     c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers,
+                     (double*)nullptr, pack32 ? c->d_sig32 : (float4*)nullptr,
+                     pack64 ? c->d_src64 : (double4*)nullptr, pack32 ? c->d_bdat : (float4*)nullptr);
+}
+
+// Choose the source split so that the grid holds enough workgroups to fill the chip.
+static int ksum_splits(int64_t tblocks, int P) {
+  int s = 1;
+  while (tblocks * s < 2048 && s * 2 <= P && s < 64) s *= 2;
+  return s;
+}
+
+bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale) {
+  constexpr int T = 2;
+  const int64_t Nt = c->Nt;
+  const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
+  const int ns = ksum_splits(tblocks, c->P);
+  const int bps = (c->P + ns - 1) / ns;
+  double* out = u;
+  if (ns > 1) {
+    const int64_t need = (int64_t)ns * Nt * 2;
+    if (c->upart_cap < need) {
+      if (c->d_upart) (void)hipFree(c->d_upart);
+      c->d_upart = nullptr;
+      if (hipMalloc(&c->d_upart, need * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->d_upart = nullptr;
+        c->upart_cap = 0;
+        return false;
+      }
+      c->upart_cap = need;
+    }
+    out = c->d_upart;
+  }
+  dim3 grid((unsigned)tblocks, (unsigned)ns);
+  if (mixed)
+    hipLaunchKernelGGL(k_ksum_mixed<T>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_centers,
+                       c->d_sig32, c->d_bdat, Nt, c->d_tgt_body, c->d_Xr32, bps, mode, c->d_nbr_off, c->d_nbr_list, scale,
+                       out);
+  else
+    hipLaunchKernelGGL(k_ksum_fp64<T>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_src64, Nt,
+                       c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out);
+  if (ns > 1)
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns,
+                       c->d_upart, u);
+  return true;
+}
+
+void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr) {
+  const int C = (int)(c->pairs.size() / 2);
+  if (C == 0) return;
+  hipLaunchKernelGGL(k_pair_field, dim3(C), dim3(kPairThreads), 0, c->stream, C, prob == MFS_MOBILITY ? 1 : 0,
+                     c->d_pairs, c->d_cls, c->d_src_off, c->d_col_off, c->ct[prob], c->d_centers, c->d_xoff,
+                     c->d_coff, c->d_bp_off, c->d_bp_list, ltil, 1.0 / (4.0 * kPiD * c->prm.mu), corr);
+}
+
+void launch_finish(mfs_ctx* c, const double* u_sum, const double* mu, const double* corr, double* u_out,
+                   bool with_pairs) {
+  hipLaunchKernelGGL(k_finish, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_col_off, c->d_bp_off,
+                     c->d_bp_list, c->d_pairs, c->d_coff, u_sum, mu, corr, with_pairs ? 1 : 0,
+                     u_out);
+}
+
+void launch_rhs_mobility_sources(mfs_ctx* c, const double* given) {
+  hipLaunchKernelGGL(k_rhs_sources, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
+                     c->ct[MFS_MOBILITY], c->d_centers, given, c->d_src64);
+}
+
+void launch_rhs_resistance(mfs_ctx* c, const double* given, double* b) {
+  hipLaunchKernelGGL(k_rhs_resistance, dim3(nblocks(c->Nt, 256)), dim3(256), 0, c->stream, c->Nt, c->d_tgt_body,
+                     c->d_X, c->d_centers, given, b);
+}
+
+void launch_post(mfs_ctx* c, int prob, const double* lam_bar, double* out3) {
+  const int C = (int)(c->pairs.size() / 2);
+  const bool wp = C > 0 && c->ps[prob].ready;
+  if (wp)
+    hipLaunchKernelGGL(k_post_pairs, dim3(C), dim3(64), 0, c->stream, C, c->d_pairs, c->d_src_off, c->d_xoff,
+                       c->ps[prob].E, lam_bar, c->d_epair);
+  hipLaunchKernelGGL(k_post_bodies, dim3(c->P), dim3(64), 0, c->stream, c->P, prob == MFS_MOBILITY ? 1 : 0, c->d_cls,
+                     c->d_src_off, c->ct[prob], c->d_bp_off, c->d_bp_list, c->d_epair, lam_bar, wp ? 1 : 0, out3);
+}
+
+int mdot_blocks(int64_t n) {
+  int64_t b = (n + 4 * kDotThreads - 1) / (4 * kDotThreads);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+}
+
+void launch_mdot(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* part,
+                 double* out, int nblk) {
+  hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(kDotThreads), 0, s, n, k, V, ldv, w, part);
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(nblocks(k, 64)), dim3(64), 0, s, k, nblk, part, out);
+}
+
+void launch_maxpy(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w) {
+  hipLaunchKernelGGL(k_maxpy, dim3(nblocks(n, 256)), dim3(256), 0, s, n, k, V, ldv, h, w);
+}
+
+void launch_gemv_n(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* y, double* x) {
+  hipLaunchKernelGGL(k_gemv_n, dim3(nblocks(n, 256)), dim3(256), 0, s, n, k, V, ldv, y, x);
+}
+
+void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(nblocks(n, 256)), dim3(256), 0, s, n, a, x, y);
+}
+
+void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, double* y) {
+  hipLaunchKernelGGL(k_axpby, dim3(nblocks(n, 256)), dim3(256), 0, s, n, a, x, b, y);
+}
+
+}  // namespace mfs

@@ -1,0 +1,610 @@
+// Device precompute: one-body factors (Sec. 3.1, Sec. 4.1) and per-pair compressed
+// corrections (Sec. 3.2-3.4, Sec. 4.3-4.4, Sec. 5), FP64 throughout.
+//
+// Per pair (i, k), with fine sources Yf, fine nodes Xf, peanut nodes z, coarse
+// sources Yc = Y^(i) u Y^(k) and Pi = I - L (mobility) or I (resistance):
+//   F  = S(Xf, Yf) Pi_f [+ blockdiag(Bf_i Kf_i^T, Bf_k Kf_k^T) for mobility]
+//   X  = [[0, S(Xf_i, Y^(k)) Pi], [S(Xf_k, Y^(i)) Pi, 0]]
+//   C  = S(z, Yc) Pi,   D = S(z, Yf) Pi_f
+//   G  = F^+ X  (truncated SVD, 1e-11 relative), applied as V (Sigma^+ (U^T X))
+//   A  = -C^+ (D G)  (truncated SVD, 1e-14 relative)
+//   E  = +-blockdiag(Kf_i^T, Kf_k^T) G   (+ mobility velocities, - resistance forces)
+// Matrices are filled by a kernel of this file, factorised by rocSOLVER's batched
+// SVD and multiplied with rocBLAS GEMMs; pairs are processed in batches whose fine
+// source lists are zero-padded to a common length (zero columns do not change the
+// truncated pseudoinverse).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <array>
+#include <cstring>
+
+#include "internal.h"
+
+namespace mfs {
+
+#define MFS_RB(call)                                                                          \
+  do {                                                                                        \
+    rocblas_status s_ = (call);                                                               \
+    if (s_ != rocblas_status_success)                                                         \
+      return Status{MFS_ERR_DEVICE, std::string(#call) + ": rocBLAS status " + std::to_string((int)s_)}; \
+  } while (0)
+
+namespace {
+
+// Stokeslet block at d = x - y, scaled by 1/(4 pi mu): s00, s01(=s10), s11.
+__device__ __forceinline__ void stokeslet(double dx, double dy, double k, double& s00, double& s01, double& s11) {
+  const double r2 = dx * dx + dy * dy;
+  const double lg = 0.5 * log(r2);
+  const double ir2 = 1.0 / r2;
+  s00 = k * (dx * dx * ir2 - lg);
+  s11 = k * (dy * dy * ir2 - lg);
+  s01 = k * (dx * dy * ir2);
+}
+
+// One column block of a projected Stokeslet matrix: the sources of one body.
+struct SrcBlock {
+  const double* y;   // n x 2 absolute positions
+  int n;             // actual count
+  int col0;          // first point column of this block in the matrix
+  double cx, cy;     // body centre
+  const double* KKi; // (K^T K)^{-1} of this block's sources (row-major 3x3)
+};
+
+// Fill rows 2t, 2t+1 of a column-major matrix for target point x on body rb
+// (0 or 1), with source blocks b0, b1:
+//   value = S(x, y_s) - (S K)(x) (K^T K)^{-1} K_s^T   [if project]
+//         + B_x K_s^T                                  [if rigid and block == rb]
+// Blocks with index == rb are left zero when cross_only.
+__device__ void fill_row(double* M, int64_t ld, int64_t row2, double x, double y, int rb, const SrcBlock* blk,
+                         bool project, bool rigid, bool cross_only, double kscale) {
+  for (int b = 0; b < 2; ++b) {
+    const SrcBlock& B = blk[b];
+    if (cross_only && b == rb) continue;
+    double sk[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    if (project) {
+      for (int s = 0; s < B.n; ++s) {
+        double s00, s01, s11;
+        stokeslet(x - B.y[2 * s], y - B.y[2 * s + 1], kscale, s00, s01, s11);
+        const double rx = B.y[2 * s] - B.cx, ry = B.y[2 * s + 1] - B.cy;
+        // S K_s with K_s = [1 0 -ry; 0 1 rx]
+        sk[0][0] += s00;
+        sk[0][1] += s01;
+        sk[0][2] += -s00 * ry + s01 * rx;
+        sk[1][0] += s01;
+        sk[1][1] += s11;
+        sk[1][2] += -s01 * ry + s11 * rx;
+      }
+    }
+    // SK (K^T K)^{-1}
+    double q[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    if (project)
+      for (int a = 0; a < 2; ++a)
+        for (int m = 0; m < 3; ++m) q[a][m] = sk[a][0] * B.KKi[0 * 3 + m] + sk[a][1] * B.KKi[1 * 3 + m] + sk[a][2] * B.KKi[2 * 3 + m];
+    const bool add_rigid = rigid && b == rb;
+    const double bx = x - B.cx, by = y - B.cy;  // B_x = [1 0 -by; 0 1 bx]
+    for (int s = 0; s < B.n; ++s) {
+      double s00, s01, s11;
+      stokeslet(x - B.y[2 * s], y - B.y[2 * s + 1], kscale, s00, s01, s11);
+      const double rx = B.y[2 * s] - B.cx, ry = B.y[2 * s + 1] - B.cy;
+      // K_s^T = [1 0; 0 1; -ry rx]
+      double v00 = s00, v01 = s01, v10 = s01, v11 = s11;
+      if (project) {
+        v00 -= q[0][0] - q[0][2] * ry;
+        v01 -= q[0][1] + q[0][2] * rx;
+        v10 -= q[1][0] - q[1][2] * ry;
+        v11 -= q[1][1] + q[1][2] * rx;
+      }
+      if (add_rigid) {  // B_x K_s^T
+        v00 += 1.0 + by * ry;
+        v01 += -by * rx;
+        v10 += -bx * ry;
+        v11 += 1.0 + bx * rx;
+      }
+      const int64_t col2 = 2 * (int64_t)(B.col0 + s);
+      M[col2 * ld + row2] = v00;
+      M[col2 * ld + row2 + 1] = v10;
+      M[(col2 + 1) * ld + row2] = v01;
+      M[(col2 + 1) * ld + row2 + 1] = v11;
+    }
+  }
+}
+
+struct PairGeo {
+  // per pair in a batch (device pointers into one staging buffer)
+  const double* yf[2];   // fine sources of i and k
+  const double* yc[2];   // coarse sources of i and k
+  const double* xf;      // 2 mf fine nodes (i then k)
+  const double* z;       // mp peanut nodes
+  int nf[2];
+  double c[2][2];
+  double KKf[2][9];      // fine (K^T K)^{-1} per body
+};
+
+struct BatchDims {
+  int mf;      // fine nodes per disk
+  int nfpad;   // padded fine sources per disk
+  int nc;      // coarse sources per disk
+  int mp;      // peanut nodes
+  int64_t ldF, ldD;  // = 4 mf, 2 mp
+  int64_t sF, sX, sD, sC;  // batch strides
+};
+
+// One thread per target point of one matrix; blockIdx.y = pair in batch, blockIdx.z = matrix (0 F, 1 X, 2 D, 3 C).
+__global__ __launch_bounds__(64) void k_fill(const PairGeo* __restrict__ geo, BatchDims d, int mobility, double kscale,
+                                             const double* __restrict__ KKc, double* F, double* X, double* D,
+                                             double* Cm) {
+  const int p = blockIdx.y;
+  const int which = blockIdx.z;
+  const PairGeo& g = geo[p];
+  const int npts = (which <= 1) ? 2 * d.mf : d.mp;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npts) return;
+  SrcBlock blk[2];
+  const bool fine_cols = (which == 0 || which == 2);
+  for (int b = 0; b < 2; ++b) {
+    blk[b].y = fine_cols ? g.yf[b] : g.yc[b];
+    blk[b].n = fine_cols ? g.nf[b] : d.nc;
+    blk[b].col0 = b * (fine_cols ? d.nfpad : d.nc);
+    blk[b].cx = g.c[b][0];
+    blk[b].cy = g.c[b][1];
+    blk[b].KKi = fine_cols ? g.KKf[b] : KKc;
+  }
+  double x, y;
+  int rb = -1;
+  if (which <= 1) {
+    x = g.xf[2 * t];
+    y = g.xf[2 * t + 1];
+    rb = t < d.mf ? 0 : 1;
+  } else {
+    x = g.z[2 * t];
+    y = g.z[2 * t + 1];
+  }
+  const bool proj = mobility != 0;
+  switch (which) {
+    case 0: fill_row(F + p * d.sF, d.ldF, 2 * (int64_t)t, x, y, rb, blk, proj, proj, false, kscale); break;
+    case 1: fill_row(X + p * d.sX, d.ldF, 2 * (int64_t)t, x, y, rb, blk, proj, false, true, kscale); break;
+    case 2: fill_row(D + p * d.sD, d.ldD, 2 * (int64_t)t, x, y, -1, blk, proj, false, false, kscale); break;
+    default: fill_row(Cm + p * d.sC, d.ldD, 2 * (int64_t)t, x, y, -1, blk, proj, false, false, kscale); break;
+  }
+}
+
+// sinv_j = 1/s_j if s_j > eps s_0 else 0, then scale row j of T (column-major, ld, ncol columns).
+__global__ void k_trunc_scale(int nsv, const double* __restrict__ S, int64_t sS, double eps, double* T, int64_t ld,
+                              int ncol, int64_t sT) {
+  const int p = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nsv * ncol) return;
+  const int j = (int)(idx % nsv);
+  const int col = (int)(idx / nsv);
+  const double s0 = S[p * sS];
+  const double sj = S[p * sS + j];
+  const double f = (sj > eps * s0) ? 1.0 / sj : 0.0;
+  T[p * sT + (int64_t)col * ld + j] *= f;
+}
+
+// E = sgn blockdiag(Kf_i^T, Kf_k^T) G for each pair; G column-major (2 * 2 nfpad) x ncols.
+__global__ void k_extract(const PairGeo* __restrict__ geo, BatchDims d, const double* __restrict__ G, int64_t sG,
+                          double sgn, double* __restrict__ E, const int64_t* __restrict__ eoff) {
+  const int p = blockIdx.y;
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ncols = 4 * d.nc;
+  if (col >= ncols) return;
+  const PairGeo& g = geo[p];
+  const double* Gc = G + p * sG + (int64_t)col * (4 * d.nfpad);
+  for (int b = 0; b < 2; ++b) {
+    double f0 = 0, f1 = 0, f2 = 0;
+    for (int s = 0; s < g.nf[b]; ++s) {
+      const int64_t r = 2 * (int64_t)(b * d.nfpad + s);
+      const double gx = Gc[r], gy = Gc[r + 1];
+      const double rx = g.yf[b][2 * s] - g.c[b][0], ry = g.yf[b][2 * s + 1] - g.c[b][1];
+      f0 += gx;
+      f1 += gy;
+      f2 += -ry * gx + rx * gy;
+    }
+    double* Ec = E + eoff[p] + (int64_t)col * 6;
+    Ec[3 * b] = sgn * f0;
+    Ec[3 * b + 1] = sgn * f1;
+    Ec[3 * b + 2] = sgn * f2;
+  }
+}
+
+void inv3(const double* M, double* R) {
+  const double a = M[0], b = M[1], c = M[2], d = M[3], e = M[4], f = M[5], g = M[6], h = M[7], i = M[8];
+  const double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
+  const double det = a * A + b * B + c * C;
+  R[0] = A / det;
+  R[1] = -(b * i - c * h) / det;
+  R[2] = (b * f - c * e) / det;
+  R[3] = B / det;
+  R[4] = (a * i - c * g) / det;
+  R[5] = -(a * f - c * d) / det;
+  R[6] = C / det;
+  R[7] = -(a * h - b * g) / det;
+  R[8] = (a * e - b * d) / det;
+}
+
+// (K^T K)^{-1} for points relative to centre (rows [1 0 -ry; 0 1 rx]).
+void ktk_inv(const std::vector<Pt>& pts, double cx, double cy, double* out) {
+  double M[9] = {0};
+  for (const Pt& p : pts) {
+    const double rx = p.x - cx, ry = p.y - cy;
+    M[0] += 1;
+    M[4] += 1;
+    M[2] += -ry;
+    M[6] += -ry;
+    M[5] += rx;
+    M[7] += rx;
+    M[8] += rx * rx + ry * ry;
+  }
+  inv3(M, out);
+}
+
+struct DevMem {
+  void* p = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+Status onebody_factors(mfs_ctx* c) {
+  // distinct classes
+  std::vector<int> first_of_class;
+  c->cls.assign(c->P, -1);
+  std::vector<std::array<double, 4>> keys;
+  for (int i = 0; i < c->P; ++i) {
+    std::array<double, 4> key{c->radii[i], (double)c->n_src[i], (double)c->n_col[i], c->r_src[i]};
+    int k = -1;
+    for (size_t q = 0; q < keys.size(); ++q)
+      if (keys[q] == key) k = (int)q;
+    if (k < 0) {
+      if ((int)keys.size() == kMaxClasses)
+        return Status{MFS_ERR_ARG, "more than 4 distinct disk classes (radius, n_src, n_col, r_src)"};
+      keys.push_back(key);
+      k = (int)keys.size() - 1;
+    }
+    c->cls[i] = k;
+  }
+  const double kscale = 1.0 / (4.0 * kPiD * c->prm.mu);
+  for (int prob = 0; prob < 2; ++prob) {
+    ClassTab& ct = c->ct[prob];
+    ct.n = (int)keys.size();
+    for (int k = 0; k < ct.n; ++k) {
+      const double a = keys[k][0], rs = keys[k][3];
+      const int nc = (int)keys[k][1], mc = (int)keys[k][2];
+      std::vector<Pt> Y, X;
+      ring_points({0, 0}, rs * a, nc, Y);
+      ring_points({0, 0}, a, mc, X);
+      const int m = 2 * mc, n = 2 * nc;
+      // P = S(X, Y), column-major m x n
+      std::vector<double> M((size_t)m * n);
+      for (int q = 0; q < mc; ++q)
+        for (int j = 0; j < nc; ++j) {
+          const double dx = X[q].x - Y[j].x, dy = X[q].y - Y[j].y;
+          const double r2 = dx * dx + dy * dy, lg = 0.5 * std::log(r2);
+          M[(size_t)(2 * j) * m + 2 * q] = kscale * (dx * dx / r2 - lg);
+          M[(size_t)(2 * j) * m + 2 * q + 1] = kscale * (dx * dy / r2);
+          M[(size_t)(2 * j + 1) * m + 2 * q] = kscale * (dx * dy / r2);
+          M[(size_t)(2 * j + 1) * m + 2 * q + 1] = kscale * (dy * dy / r2 - lg);
+        }
+      double KKi[9];
+      ktk_inv(Y, 0, 0, KKi);
+      if (prob == MFS_MOBILITY) {
+        // S_L = P (I - L) + B K^T, L = K (K^T K)^{-1} K^T  (eq. SL)
+        std::vector<double> K((size_t)n * 3), B((size_t)m * 3);  // row-major
+        for (int j = 0; j < nc; ++j) {
+          K[(2 * j) * 3 + 0] = 1; K[(2 * j) * 3 + 1] = 0; K[(2 * j) * 3 + 2] = -Y[j].y;
+          K[(2 * j + 1) * 3 + 0] = 0; K[(2 * j + 1) * 3 + 1] = 1; K[(2 * j + 1) * 3 + 2] = Y[j].x;
+        }
+        for (int q = 0; q < mc; ++q) {
+          B[(2 * q) * 3 + 0] = 1; B[(2 * q) * 3 + 1] = 0; B[(2 * q) * 3 + 2] = -X[q].y;
+          B[(2 * q + 1) * 3 + 0] = 0; B[(2 * q + 1) * 3 + 1] = 1; B[(2 * q + 1) * 3 + 2] = X[q].x;
+        }
+        // W = (K^T K)^{-1} K^T (3 x n); PK = P K (m x 3)
+        std::vector<double> W((size_t)3 * n), PK((size_t)m * 3, 0.0);
+        for (int r = 0; r < 3; ++r)
+          for (int j = 0; j < n; ++j) W[r * n + j] = KKi[r * 3 + 0] * K[j * 3 + 0] + KKi[r * 3 + 1] * K[j * 3 + 1] + KKi[r * 3 + 2] * K[j * 3 + 2];
+        for (int row = 0; row < m; ++row)
+          for (int r = 0; r < 3; ++r) {
+            double s = 0;
+            for (int j = 0; j < n; ++j) s += M[(size_t)j * m + row] * K[j * 3 + r];
+            PK[row * 3 + r] = s;
+          }
+        for (int row = 0; row < m; ++row)
+          for (int j = 0; j < n; ++j) {
+            double v = M[(size_t)j * m + row];
+            for (int r = 0; r < 3; ++r) v += -PK[row * 3 + r] * W[r * n + j] + B[row * 3 + r] * K[j * 3 + r];
+            M[(size_t)j * m + row] = v;
+          }
+      }
+      // SVD on the device
+      const int mn = std::min(m, n);
+      DevMem dA, dS, dU, dV, dE, dInfo;
+      MFS_HIP(hipMalloc(&dA.p, sizeof(double) * m * n));
+      MFS_HIP(hipMalloc(&dS.p, sizeof(double) * mn));
+      MFS_HIP(hipMalloc(&dU.p, sizeof(double) * m * mn));
+      MFS_HIP(hipMalloc(&dV.p, sizeof(double) * mn * n));
+      MFS_HIP(hipMalloc(&dE.p, sizeof(double) * mn));
+      MFS_HIP(hipMalloc(&dInfo.p, sizeof(int)));
+      MFS_HIP(hipMemcpyAsync(dA.p, M.data(), sizeof(double) * m * n, hipMemcpyHostToDevice, c->stream));
+      MFS_RB(rocsolver_dgesvd(c->blas, rocblas_svect_singular, rocblas_svect_singular, m, n, (double*)dA.p, m,
+                              (double*)dS.p, (double*)dU.p, m, (double*)dV.p, mn, (double*)dE.p,
+                              rocblas_outofplace, (int*)dInfo.p));
+      std::vector<double> S(mn), U((size_t)m * mn), VT((size_t)mn * n);
+      int info = 0;
+      MFS_HIP(hipMemcpyAsync(S.data(), dS.p, sizeof(double) * mn, hipMemcpyDeviceToHost, c->stream));
+      MFS_HIP(hipMemcpyAsync(U.data(), dU.p, sizeof(double) * m * mn, hipMemcpyDeviceToHost, c->stream));
+      MFS_HIP(hipMemcpyAsync(VT.data(), dV.p, sizeof(double) * mn * n, hipMemcpyDeviceToHost, c->stream));
+      MFS_HIP(hipMemcpyAsync(&info, dInfo.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      MFS_HIP(hipStreamSynchronize(c->stream));
+      if (info != 0) return Status{MFS_ERR_NUMERIC, "one-body SVD did not converge"};
+      int rank = 0;
+      while (rank < mn && S[rank] > S[0] * c->prm.eps_trunc) ++rank;
+      std::vector<double> Urm((size_t)m * rank), Vtrm((size_t)rank * n), sinv(rank);
+      for (int q = 0; q < m; ++q)
+        for (int j = 0; j < rank; ++j) Urm[(size_t)q * rank + j] = U[(size_t)j * m + q];
+      for (int j = 0; j < rank; ++j) {
+        sinv[j] = 1.0 / S[j];
+        for (int i = 0; i < n; ++i) Vtrm[(size_t)j * n + i] = VT[(size_t)i * mn + j];
+      }
+      std::vector<double>& Yr = c->h_Yr[k];
+      std::vector<double>& Xr = c->h_Xr[k];
+      Yr.assign(2 * nc, 0.0);
+      Xr.assign(2 * mc, 0.0);
+      for (int j = 0; j < nc; ++j) {
+        Yr[2 * j] = Y[j].x;
+        Yr[2 * j + 1] = Y[j].y;
+      }
+      for (int q = 0; q < mc; ++q) {
+        Xr[2 * q] = X[q].x;
+        Xr[2 * q + 1] = X[q].y;
+      }
+      auto upload = [&](const std::vector<double>& h, const double** dst) -> Status {
+        void* p = nullptr;
+        MFS_HIP(hipMalloc(&p, sizeof(double) * std::max<size_t>(1, h.size())));
+        c->class_bufs.push_back(p);
+        MFS_HIP(hipMemcpy(p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+        *dst = (const double*)p;
+        return Status{};
+      };
+      Status st;
+      if ((st = upload(Urm, &ct.U[k])).code) return st;
+      if ((st = upload(sinv, &ct.sinv[k])).code) return st;
+      if ((st = upload(Vtrm, &ct.Vt[k])).code) return st;
+      if ((st = upload(Yr, &ct.Yr[k])).code) return st;
+      if ((st = upload(Xr, &ct.Xr[k])).code) return st;
+      ct.nc[k] = nc;
+      ct.mc[k] = mc;
+      ct.rank[k] = rank;
+      ct.radius[k] = a;
+      std::memcpy(ct.KtKi[k], KKi, sizeof(KKi));
+    }
+  }
+  return Status{};
+}
+
+// ---------------------------------------------------------------------------
+Status precompute_pairs(mfs_ctx* c, int prob) {
+  const int C = (int)(c->pairs.size() / 2);
+  PairSet& ps = c->ps[prob];
+  const int64_t asz = c->aoff[C], esz = 6 * c->xoff[C];
+  if (!ps.A) {
+    MFS_HIP(hipMalloc(&ps.A, sizeof(double) * std::max<int64_t>(1, asz)));
+    MFS_HIP(hipMalloc(&ps.E, sizeof(double) * std::max<int64_t>(1, esz)));
+  }
+  if (C == 0) {
+    ps.ready = true;
+    return Status{};
+  }
+  FineParams fp{c->prm.n_fp, c->prm.n_ell, c->prm.m_p, c->prm.a_ell, c->prm.gamma, c->prm.a_f, c->prm.mobius_r,
+                c->prm.eps_ring};
+  for (int p = 0; p < C; ++p) {
+    const int i = c->pairs[2 * p], k = c->pairs[2 * p + 1];
+    if (c->cls[i] != c->cls[k]) return Status{MFS_ERR_ARG, "pair of disks of different classes is not supported"};
+    if (std::fabs(c->radii[i] - 1.0) > 1e-14)
+      return Status{MFS_ERR_ARG, "the fine pair discretisation is defined for unit disks"};
+  }
+  const int mf = (int)std::ceil(fp.a_f * fp.n_fp - 1e-12) + fp.a_ell * fp.n_ell;
+  const int mp = fp.m_p;
+  const double kscale = 1.0 / (4.0 * kPiD * c->prm.mu);
+  const int mobility = prob == MFS_MOBILITY ? 1 : 0;
+  const ClassTab& ct = c->ct[prob];
+
+  // order pairs by fine-source count so each batch pads little
+  std::vector<int> order(C), nfe(C);
+  for (int p = 0; p < C; ++p) {
+    const int i = c->pairs[2 * p], k = c->pairs[2 * p + 1];
+    const double dx = c->centers[2 * k] - c->centers[2 * i], dy = c->centers[2 * k + 1] - c->centers[2 * i + 1];
+    nfe[p] = fp.n_fp + ellipse_count(std::sqrt(dx * dx + dy * dy) - 2.0, fp);
+    order[p] = p;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nfe[a] < nfe[b]; });
+
+  const int batch = 32;
+  for (int b0 = 0; b0 < C; b0 += batch) {
+    const int nb = std::min(batch, C - b0);
+    int nfpad = 0;
+    for (int q = 0; q < nb; ++q) nfpad = std::max(nfpad, nfe[order[b0 + q]]);
+    const int nc = ct.nc[c->cls[c->pairs[2 * order[b0]]]];
+    BatchDims d;
+    d.mf = mf;
+    d.nfpad = nfpad;
+    d.nc = nc;
+    d.mp = mp;
+    d.ldF = 4 * mf;
+    d.ldD = 2 * mp;
+    const int64_t m = 4 * mf, n = 4 * nfpad, nx = 4 * nc, mpp = 2 * mp;
+    d.sF = m * n;
+    d.sX = m * nx;
+    d.sD = mpp * n;
+    d.sC = mpp * nx;
+    // host staging: geometry
+    const int64_t per_pair = 2 * (2 * nfpad) + 2 * (2 * nc) + 2 * (2 * mf) + 2 * mp;
+    std::vector<double> stage((size_t)per_pair * nb, 0.0);
+    std::vector<PairGeo> geo(nb);
+    DevMem dstage, dgeo;
+    MFS_HIP(hipMalloc(&dstage.p, sizeof(double) * stage.size()));
+    MFS_HIP(hipMalloc(&dgeo.p, sizeof(PairGeo) * nb));
+    const double* dbase = (const double*)dstage.p;
+    std::vector<int64_t> eoff(nb);
+    for (int q = 0; q < nb; ++q) {
+      const int p = order[b0 + q];
+      const int i = c->pairs[2 * p], k = c->pairs[2 * p + 1];
+      const Pt ci{c->centers[2 * i], c->centers[2 * i + 1]}, ck{c->centers[2 * k], c->centers[2 * k + 1]};
+      std::vector<Pt> yi, yk, xi, xk, z;
+      pair_fine_sources(ci, ck, fp, yi, yk);
+      pair_fine_nodes(ci, ck, fp, xi, xk);
+      peanut(ci, ck, mp, z);
+      double* base = stage.data() + (size_t)q * per_pair;
+      const int64_t o_yf0 = 0, o_yf1 = 2 * nfpad, o_yc0 = 4 * nfpad, o_yc1 = 4 * nfpad + 2 * nc,
+                    o_xf = 4 * nfpad + 4 * nc, o_z = o_xf + 4 * mf;
+      for (size_t s = 0; s < yi.size(); ++s) {
+        base[o_yf0 + 2 * s] = yi[s].x;
+        base[o_yf0 + 2 * s + 1] = yi[s].y;
+        base[o_yf1 + 2 * s] = yk[s].x;
+        base[o_yf1 + 2 * s + 1] = yk[s].y;
+      }
+      const std::vector<double>& yr = c->h_Yr[c->cls[i]];
+      for (int s = 0; s < nc; ++s) {
+        base[o_yc0 + 2 * s] = ci.x + yr[2 * s];
+        base[o_yc0 + 2 * s + 1] = ci.y + yr[2 * s + 1];
+        base[o_yc1 + 2 * s] = ck.x + yr[2 * s];
+        base[o_yc1 + 2 * s + 1] = ck.y + yr[2 * s + 1];
+      }
+      for (int s = 0; s < mf; ++s) {
+        base[o_xf + 2 * s] = xi[s].x;
+        base[o_xf + 2 * s + 1] = xi[s].y;
+        base[o_xf + 2 * mf + 2 * s] = xk[s].x;
+        base[o_xf + 2 * mf + 2 * s + 1] = xk[s].y;
+      }
+      for (int s = 0; s < mp; ++s) {
+        base[o_z + 2 * s] = z[s].x;
+        base[o_z + 2 * s + 1] = z[s].y;
+      }
+      PairGeo& g = geo[q];
+      const double* db = dbase + (size_t)q * per_pair;
+      g.yf[0] = db + o_yf0;
+      g.yf[1] = db + o_yf1;
+      g.yc[0] = db + o_yc0;
+      g.yc[1] = db + o_yc1;
+      g.xf = db + o_xf;
+      g.z = db + o_z;
+      g.nf[0] = (int)yi.size();
+      g.nf[1] = (int)yk.size();
+      g.c[0][0] = ci.x;
+      g.c[0][1] = ci.y;
+      g.c[1][0] = ck.x;
+      g.c[1][1] = ck.y;
+      ktk_inv(yi, ci.x, ci.y, g.KKf[0]);
+      ktk_inv(yk, ck.x, ck.y, g.KKf[1]);
+      eoff[q] = 6 * c->xoff[p];
+    }
+    MFS_HIP(hipMemcpyAsync(dstage.p, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice, c->stream));
+    MFS_HIP(hipMemcpyAsync(dgeo.p, geo.data(), sizeof(PairGeo) * nb, hipMemcpyHostToDevice, c->stream));
+    // coarse (K^T K)^{-1}
+    DevMem dKKc, deoff;
+    MFS_HIP(hipMalloc(&dKKc.p, sizeof(double) * 9));
+    MFS_HIP(hipMemcpyAsync(dKKc.p, ct.KtKi[c->cls[c->pairs[2 * order[b0]]]], sizeof(double) * 9,
+                           hipMemcpyHostToDevice, c->stream));
+    MFS_HIP(hipMalloc(&deoff.p, sizeof(int64_t) * nb));
+    MFS_HIP(hipMemcpyAsync(deoff.p, eoff.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, c->stream));
+
+    const int64_t mn = std::min(m, n);
+    DevMem dF, dX, dD, dC, dSF, dU, dVT, dE, dT1, dG, dDG, dSC, dUC, dVTC, dEC, dT2, dinfo, dinfoC;
+    MFS_HIP(hipMalloc(&dF.p, sizeof(double) * d.sF * nb));
+    MFS_HIP(hipMalloc(&dX.p, sizeof(double) * d.sX * nb));
+    MFS_HIP(hipMalloc(&dD.p, sizeof(double) * d.sD * nb));
+    MFS_HIP(hipMalloc(&dC.p, sizeof(double) * d.sC * nb));
+    MFS_HIP(hipMemsetAsync(dF.p, 0, sizeof(double) * d.sF * nb, c->stream));
+    MFS_HIP(hipMemsetAsync(dX.p, 0, sizeof(double) * d.sX * nb, c->stream));
+    MFS_HIP(hipMemsetAsync(dD.p, 0, sizeof(double) * d.sD * nb, c->stream));
+    {
+      const int maxpts = std::max(2 * mf, mp);
+      dim3 grid((maxpts + 63) / 64, nb, 4);
+      hipLaunchKernelGGL(k_fill, grid, dim3(64), 0, c->stream, (const PairGeo*)dgeo.p, d, mobility, kscale,
+                         (const double*)dKKc.p, (double*)dF.p, (double*)dX.p, (double*)dD.p, (double*)dC.p);
+      MFS_HIP(hipGetLastError());
+    }
+    MFS_HIP(hipMalloc(&dSF.p, sizeof(double) * mn * nb));
+    MFS_HIP(hipMalloc(&dU.p, sizeof(double) * m * mn * nb));
+    MFS_HIP(hipMalloc(&dVT.p, sizeof(double) * mn * n * nb));
+    MFS_HIP(hipMalloc(&dE.p, sizeof(double) * mn * nb));
+    MFS_HIP(hipMalloc(&dinfo.p, sizeof(int) * nb));
+    MFS_HIP(hipMalloc(&dinfoC.p, sizeof(int) * nb));
+    MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m, (int)n,
+                                            (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p, (int)m,
+                                            m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
+                                            rocblas_outofplace, (int*)dinfo.p, nb));
+    // T1 = U^T X  (mn x nx)
+    MFS_HIP(hipMalloc(&dT1.p, sizeof(double) * mn * nx * nb));
+    MFS_HIP(hipMalloc(&dG.p, sizeof(double) * n * nx * nb));
+    const double one = 1.0, zero = 0.0, mone = -1.0;
+    MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mn,
+                                         (int)nx, (int)m, &one, (const double*)dU.p, (int)m, m * mn,
+                                         (const double*)dX.p, (int)m, d.sX, &zero, (double*)dT1.p, (int)mn, mn * nx,
+                                         nb));
+    {
+      dim3 grid((unsigned)((mn * nx + 255) / 256), nb);
+      hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mn, (const double*)dSF.p, mn,
+                         c->prm.eps_trunc_fine, (double*)dT1.p, mn, (int)nx, mn * nx);
+    }
+    // G = V T1 = (V^T)^T T1   (n x nx)
+    MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)n,
+                                         (int)nx, (int)mn, &one, (const double*)dVT.p, (int)mn, mn * n,
+                                         (const double*)dT1.p, (int)mn, mn * nx, &zero, (double*)dG.p, (int)n, n * nx,
+                                         nb));
+    // DG = D G  (2mp x nx)
+    MFS_HIP(hipMalloc(&dDG.p, sizeof(double) * mpp * nx * nb));
+    MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none, (int)mpp, (int)nx,
+                                         (int)n, &one, (const double*)dD.p, (int)mpp, d.sD, (const double*)dG.p,
+                                         (int)n, n * nx, &zero, (double*)dDG.p, (int)mpp, mpp * nx, nb));
+    // SVD of C (2mp x nx), then A = -V_C Sigma_C^+ U_C^T (D G)
+    const int64_t mnc = std::min(mpp, nx);
+    MFS_HIP(hipMalloc(&dSC.p, sizeof(double) * mnc * nb));
+    MFS_HIP(hipMalloc(&dUC.p, sizeof(double) * mpp * mnc * nb));
+    MFS_HIP(hipMalloc(&dVTC.p, sizeof(double) * mnc * nx * nb));
+    MFS_HIP(hipMalloc(&dEC.p, sizeof(double) * mnc * nb));
+    MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
+                                            (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
+                                            (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
+                                            mnc * nx, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nb));
+    MFS_HIP(hipMalloc(&dT2.p, sizeof(double) * mnc * nx * nb));
+    MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnc,
+                                         (int)nx, (int)mpp, &one, (const double*)dUC.p, (int)mpp, mpp * mnc,
+                                         (const double*)dDG.p, (int)mpp, mpp * nx, &zero, (double*)dT2.p, (int)mnc,
+                                         mnc * nx, nb));
+    {
+      dim3 grid((unsigned)((mnc * nx + 255) / 256), nb);
+      hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mnc, (const double*)dSC.p, mnc,
+                         c->prm.eps_trunc, (double*)dT2.p, mnc, (int)nx, mnc * nx);
+    }
+    // A into place; pairs of a batch are not contiguous in the pair order, so one GEMM per pair
+    for (int q = 0; q < nb; ++q) {
+      const int p = order[b0 + q];
+      MFS_RB(rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)nx, (int)nx, (int)mnc,
+                           &mone, (const double*)dVTC.p + q * mnc * nx, (int)mnc,
+                           (const double*)dT2.p + q * mnc * nx, (int)mnc, &zero, ps.A + c->aoff[p], (int)nx));
+    }
+    {
+      dim3 grid((unsigned)((nx + 63) / 64), nb);
+      hipLaunchKernelGGL(k_extract, grid, dim3(64), 0, c->stream, (const PairGeo*)dgeo.p, d, (const double*)dG.p,
+                         n * nx, mobility ? 1.0 : -1.0, ps.E, (const int64_t*)deoff.p);
+    }
+    std::vector<int> info(2 * nb);
+    MFS_HIP(hipMemcpyAsync(info.data(), dinfo.p, sizeof(int) * nb, hipMemcpyDeviceToHost, c->stream));
+    MFS_HIP(hipMemcpyAsync(info.data() + nb, dinfoC.p, sizeof(int) * nb, hipMemcpyDeviceToHost, c->stream));
+    MFS_HIP(hipStreamSynchronize(c->stream));
+    for (int q = 0; q < 2 * nb; ++q)
+      if (info[q] != 0) return Status{MFS_ERR_NUMERIC, "pair SVD did not converge"};
+  }
+  ps.ready = true;
+  return Status{};
+}
+
+}  // namespace mfs

@@ -1,0 +1,226 @@
+"""ctypes binding of libmfs_hip.so (the C ABI declared in include/mfs.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+The functions keep the C names.  Device arrays are torch tensors on the current
+HIP device (float64, contiguous); host arrays are numpy arrays.  torch is
+imported before the library is loaded so that both use one HIP runtime.
+Loading fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (HIP runtime first)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfs_hip.so")
+
+MFS_OK, MFS_ERR_ARG, MFS_ERR_GEOMETRY, MFS_ERR_OOM, MFS_ERR_DEVICE, MFS_ERR_STATE, MFS_ERR_NOCONV, MFS_ERR_NUMERIC = range(8)
+MFS_RESISTANCE, MFS_MOBILITY = 0, 1
+MFS_FP64, MFS_MIXED = 0, 1
+PROBLEMS = {"resistance": MFS_RESISTANCE, "mobility": MFS_MOBILITY}
+PRECISIONS = {"fp64": MFS_FP64, "mixed": MFS_MIXED}
+STATUS_NAMES = {0: "MFS_OK", 1: "MFS_ERR_ARG", 2: "MFS_ERR_GEOMETRY", 3: "MFS_ERR_OOM", 4: "MFS_ERR_DEVICE",
+                5: "MFS_ERR_STATE", 6: "MFS_ERR_NOCONV", 7: "MFS_ERR_NUMERIC"}
+
+# Exported symbols, in the order of include/mfs.h.
+SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_pairs", "mfs_set_pair_matrices",
+           "mfs_get_pair_matrices", "mfs_apply", "mfs_kernel_sum", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
+           "mfs_get_sizes", "mfs_destroy", "mfs_last_error"]
+
+
+class MfsParams(C.Structure):
+    _fields_ = [("mu", C.c_double), ("delta_c", C.c_double), ("eps_trunc", C.c_double),
+                ("eps_trunc_fine", C.c_double), ("eps_ring", C.c_double), ("n_fp", C.c_int32),
+                ("n_ell", C.c_int32), ("m_p", C.c_int32), ("a_ell", C.c_int32), ("gamma", C.c_double),
+                ("a_f", C.c_double), ("mobius_r", C.c_double)]
+
+
+class MfsSolveInfo(C.Structure):
+    _fields_ = [("iters_total", C.c_int32), ("outer_steps", C.c_int32), ("rel_resid", C.c_double),
+                ("resid_hist", C.POINTER(C.c_double)), ("hist_cap", C.c_int32), ("hist_len", C.c_int32),
+                ("ms_rhs", C.c_double), ("ms_iterate", C.c_double), ("ms_post", C.c_double),
+                ("n_pairs", C.c_int64)]
+
+
+class MFSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmfs_hip.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2606_11273_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    L.mfs_default_params.argtypes = [C.POINTER(MfsParams)]
+    L.mfs_default_params.restype = None
+    L.mfs_setup.argtypes = [C.POINTER(vp), C.c_int32, dp, dp, ip, ip, dp, C.POINTER(MfsParams), vp]
+    L.mfs_precompute_pairs.argtypes = [vp, C.c_int, i64p]
+    L.mfs_get_pairs.argtypes = [vp, i64p, ip]
+    L.mfs_set_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
+    L.mfs_get_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
+    L.mfs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int32, vp, vp]
+    L.mfs_kernel_sum.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
+    L.mfs_rhs.argtypes = [vp, C.c_int, dp, vp]
+    L.mfs_post.argtypes = [vp, C.c_int, vp, dp]
+    L.mfs_gmres_solve.argtypes = [vp, C.c_int, C.c_int, C.c_int32, dp, dp, vp, C.c_double, C.c_int32,
+                                  C.POINTER(MfsSolveInfo)]
+    L.mfs_get_sizes.argtypes = [vp, ip, i64p, i64p, i64p]
+    L.mfs_destroy.argtypes = [vp]
+    L.mfs_last_error.argtypes = [vp]
+    L.mfs_last_error.restype = C.c_char_p
+    for name in SYMBOLS:
+        if name not in ("mfs_default_params", "mfs_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _check(code, ctx):
+    if code != MFS_OK:
+        msg = lib().mfs_last_error(ctx).decode()
+        raise MFSError(code, msg)
+
+
+def _dev(t, n=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("device arrays must be contiguous float64 torch tensors on the GPU")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"device array has {t.numel()} entries, need {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def mfs_default_params():
+    p = MfsParams()
+    lib().mfs_default_params(C.byref(p))
+    return p
+
+
+def mfs_setup(centers, radii, n_src, n_col, r_src, params=None, stream=None):
+    """Returns an opaque context handle (c_void_p).  Host inputs: numpy arrays."""
+    centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 2)
+    P = centers.shape[0]
+    radii = np.ascontiguousarray(np.broadcast_to(radii, (P,)), dtype=np.float64)
+    n_src = np.ascontiguousarray(np.broadcast_to(n_src, (P,)), dtype=np.int32)
+    n_col = np.ascontiguousarray(np.broadcast_to(n_col, (P,)), dtype=np.int32)
+    r_src = np.ascontiguousarray(np.broadcast_to(r_src, (P,)), dtype=np.float64)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    ctx = C.c_void_p()
+    code = lib().mfs_setup(C.byref(ctx), P, _dp(centers), _dp(radii), _ip(n_src), _ip(n_col), _dp(r_src),
+                           C.byref(params) if params is not None else None, C.c_void_p(stream))
+    if code != MFS_OK:
+        raise MFSError(code, lib().mfs_last_error(None).decode())
+    return ctx
+
+
+def mfs_precompute_pairs(ctx, problem):
+    n = C.c_int64()
+    _check(lib().mfs_precompute_pairs(ctx, PROBLEMS[problem], C.byref(n)), ctx)
+    return n.value
+
+
+def mfs_get_sizes(ctx):
+    P, ns, nt, npairs = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().mfs_get_sizes(ctx, C.byref(P), C.byref(ns), C.byref(nt), C.byref(npairs)), ctx)
+    return P.value, ns.value, nt.value, npairs.value
+
+
+def mfs_get_pairs(ctx):
+    n = C.c_int64()
+    _check(lib().mfs_get_pairs(ctx, C.byref(n), None), ctx)
+    out = np.zeros((n.value, 2), dtype=np.int32)
+    _check(lib().mfs_get_pairs(ctx, C.byref(n), _ip(out)), ctx)
+    return out
+
+
+def _pair_sizes(ctx, n_src):
+    pr = mfs_get_pairs(ctx)
+    n = 2 * (n_src[pr[:, 0]] + n_src[pr[:, 1]]) if len(pr) else np.zeros(0, dtype=np.int64)
+    return pr, n.astype(np.int64)
+
+
+def mfs_set_pair_matrices(ctx, problem, A_list, E_list):
+    A = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in A_list]) if A_list
+                             else np.zeros(1))
+    E = np.ascontiguousarray(np.concatenate([np.asarray(e, dtype=np.float64).ravel() for e in E_list]) if E_list
+                             else np.zeros(1))
+    _check(lib().mfs_set_pair_matrices(ctx, PROBLEMS[problem], _dp(A), _dp(E)), ctx)
+
+
+def mfs_get_pair_matrices(ctx, problem, n_src):
+    pr, n = _pair_sizes(ctx, np.asarray(n_src))
+    A = np.zeros(max(1, int(np.sum(n * n))))
+    E = np.zeros(max(1, int(np.sum(6 * n))))
+    _check(lib().mfs_get_pair_matrices(ctx, PROBLEMS[problem], _dp(A), _dp(E)), ctx)
+    As, Es, ao, eo = [], [], 0, 0
+    for m in n:
+        As.append(A[ao:ao + m * m].reshape(m, m))
+        Es.append(E[eo:eo + 6 * m].reshape(6, m))
+        ao += m * m
+        eo += 6 * m
+    return As, Es
+
+
+def mfs_apply(ctx, problem, precision, mu, u, n_rhs=1):
+    _check(lib().mfs_apply(ctx, PROBLEMS[problem], PRECISIONS[precision], n_rhs, _dev(mu), _dev(u)), ctx)
+
+
+def mfs_kernel_sum(ctx, precision, sigma, u, skip=1):
+    """skip: 0 all sources, 1 skip the target's own disk, 2 also skip its contact partners."""
+    _check(lib().mfs_kernel_sum(ctx, PRECISIONS[precision], _dev(sigma), _dev(u), int(skip)), ctx)
+
+
+def mfs_rhs(ctx, problem, given, b):
+    given = np.ascontiguousarray(given, dtype=np.float64)
+    _check(lib().mfs_rhs(ctx, PROBLEMS[problem], _dp(given), _dev(b)), ctx)
+
+
+def mfs_post(ctx, problem, mu, P):
+    out = np.zeros((P, 3))
+    _check(lib().mfs_post(ctx, PROBLEMS[problem], _dev(mu), _dp(out)), ctx)
+    return out
+
+
+def mfs_gmres_solve(ctx, problem, precision, rhs, tol, max_iter=500, x0=None, hist_cap=1000, allow_noconv=False):
+    """rhs: (P,3) or (n_rhs,P,3) host array.  Returns (out, info dict)."""
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+    n_rhs = 1 if rhs.ndim == 2 else rhs.shape[0]
+    out = np.zeros_like(rhs)
+    hist = np.zeros(hist_cap)
+    info = MfsSolveInfo()
+    info.resid_hist = _dp(hist)
+    info.hist_cap = hist_cap
+    code = lib().mfs_gmres_solve(ctx, PROBLEMS[problem], PRECISIONS[precision], n_rhs, _dp(rhs), _dp(out),
+                                 _dev(x0) if x0 is not None else None, tol, max_iter, C.byref(info))
+    if not (code == MFS_OK or (allow_noconv and code == MFS_ERR_NOCONV)):
+        _check(code, ctx)
+    d = dict(iters=info.iters_total, outer=info.outer_steps, rel_resid=info.rel_resid,
+             hist=hist[:info.hist_len].copy(), ms_rhs=info.ms_rhs, ms_iterate=info.ms_iterate, ms_post=info.ms_post,
+             n_pairs=info.n_pairs, status=STATUS_NAMES[code])
+    return out, d
+
+
+def mfs_destroy(ctx):
+    if ctx:
+        lib().mfs_destroy(ctx)
