@@ -1,0 +1,222 @@
+"""Benchmark: Stokeslet pair-evals/s and time-to-solve of the P = 10^4 mobility problem.
+
+Workload: P = 10000 unit disks at area fraction 0.65 (seeded perturbed triangular
+lattice relaxed to a minimum gap of 1e-3, about 0.99 P close pairs), 36 coarse
+Stokeslet sources on radius 0.7 and 72 collocation nodes per disk, unit torque on
+every disk, zero forces, GMRES tolerance 1e-7 (the paper's).  One step is one
+full mobility solve through the C ABI: right-hand side, GMRES-IR on the Alg. 3
+operator (FP32 kernel sum with FP64 accumulation and FP64 refinement), and
+post-processing to velocities.  Setup and the pair precompute happen before the
+timed region and are reported separately; the plain-FP64 solve of the same input
+is run once beside it for the mixed-vs-FP64 comparison.
+
+Prints one JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 20          # algorithmic flops of one Stokeslet evaluation applied to a 2-vector
+PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (dense)
+PEAK_FP64_TFLOPS = 78.6
+
+
+def rel_rigid_error(out, ref):
+    """max_i (|v_i - v_ref,i| + |w_i - w_ref,i|) / max_j (|v_ref,j| + |w_ref,j|) (eq. rel_vel_err)."""
+    import numpy as np
+    e = np.linalg.norm(out[:, :2] - ref[:, :2], axis=1) + np.abs(out[:, 2] - ref[:, 2])
+    s = np.linalg.norm(ref[:, :2], axis=1) + np.abs(ref[:, 2])
+    return float(e.max() / s.max())
+
+
+def cpu_baseline(centers, radii, n_src, n_col, r_src, n_targets, sig_seed=1):
+    """The FP64 oracle's direct sum timed on the host cores on a sample of the workload's targets."""
+    import numpy as np
+    from oracle.geometry import ring
+    from oracle.kernel import direct_sum
+    P = centers.shape[0]
+    Y = np.concatenate([ring(centers[i], r_src[i] * radii[i], int(n_src[i])) for i in range(P)])
+    X = np.concatenate([ring(centers[i], radii[i], int(n_col[i])) for i in range(P)])
+    rng = np.random.default_rng(sig_seed)
+    sig = rng.standard_normal((Y.shape[0], 2))
+    tsel = np.sort(rng.choice(X.shape[0], n_targets, replace=False))
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    direct_sum(X[tsel], Y, sig, workers=workers, chunk_elems=2_000_000)
+    dt = time.perf_counter() - t0
+    evals = n_targets * Y.shape[0]
+    return dict(value=evals / dt, unit="pair-evals/s", cores=workers, kind="oracle",
+                sample=f"{n_targets} of {X.shape[0]} targets x {Y.shape[0]} sources of the same packing, "
+                       f"FP64 NumPy direct sum, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--P", type=int, default=10000)
+    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-targets", type=int, default=3000)
+    ap.add_argument("--ksum-reps", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs the hot path on one GPU; multi-GPU runs are not part of it "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    # the library prints precompute progress and stage times to stderr with this set
+    os.environ.setdefault("MFS_PROFILE", "1")
+    import numpy as np
+    import torch
+    from paper_2606_11273_amd import native as nv
+    from workloads import config_geometry, unit_torques
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    g = config_geometry(3, P=args.P)
+    c, a, ns, nc, rs = g["centers"], g["radii"], g["n_src"], g["n_col"], g["r_src"]
+    P = c.shape[0]
+    given = unit_torques(P)
+    prm = nv.mfs_default_params()
+    prm.delta_c = g["delta_c"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = nv.mfs_setup(c, a, ns, nc, rs, prm)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    n_pairs = nv.mfs_precompute_pairs(ctx, "mobility")
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+    _, Ns, Nt, _ = nv.mfs_get_sizes(ctx)
+    log(f"setup {t_setup:.2f}s  precompute {n_pairs} pairs {t_pre:.2f}s  Ns {Ns} Nt {Nt}")
+
+    # dominant kernel: the mixed all-pairs sum in the matvec's launch configuration (skip own disk and partners)
+    sig = torch.randn(2 * Ns, dtype=torch.float64, device="cuda")
+    u = torch.zeros(2 * Nt, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ks = {}
+    for prec, reps in (("mixed", args.ksum_reps), ("fp64", 1)):
+        nv.mfs_kernel_sum(ctx, prec, sig, u, 2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            nv.mfs_kernel_sum(ctx, prec, sig, u, 2)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ks[prec] = e0.elapsed_time(e1) / reps
+    # the launch also packs the strengths (a few microseconds); the kernel-sum kernel itself dominates
+
+    # plain FP64 solve of the same input (comparison)
+    out64 = None
+    info64 = {}
+    t_fp64 = None
+    if not args.no_fp64:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out64, info64 = nv.mfs_gmres_solve(ctx, "mobility", "fp64", given, args.tol, 500)
+        t_fp64 = time.perf_counter() - t0
+        log(f"fp64 solve {t_fp64:.2f}s iters {info64['iters']} resid {info64['rel_resid']:.2e}")
+
+    for _ in range(args.warmup):
+        nv.mfs_gmres_solve(ctx, "mobility", "mixed", given, args.tol, 500)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    evals = 0
+    infos = []
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out32, info32 = nv.mfs_gmres_solve(ctx, "mobility", "mixed", given, args.tol, 500)
+        evals += info32["pair_evals"]
+        infos.append(info32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    log(f"mixed solve {ms:.1f} ms/solve iters {infos[-1]['iters']} outer {infos[-1]['outer']} "
+        f"resid {infos[-1]['rel_resid']:.2e}")
+    evals_skip = infos[-1]["pair_evals"]
+    value = evals / wall
+
+    if args.copy_calibration:
+        buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        out = torch.empty_like(buf)
+        out.copy_(buf)
+        torch.cuda.synchronize()
+
+    # roofline of the dominant kernel (mixed kernel sum; one launch = one matvec's sum without
+    # each disk's own sources and its contact partners'): exact evaluations per launch
+    pr = nv.mfs_get_pairs(ctx)
+    skipped = ns.astype(np.int64).copy()
+    np.add.at(skipped, pr[:, 0], ns[pr[:, 1]])
+    np.add.at(skipped, pr[:, 1], ns[pr[:, 0]])
+    evals_launch = int(np.sum(nc.astype(np.int64) * (Ns - skipped)))
+    achieved = evals_launch * FLOP_PER_PAIR / (ks["mixed"] * 1e-3) / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
+                    kernel="k_ksum_mixed (FP32 compensated Stokeslet sum)",
+                    ms_per_launch=round(ks["mixed"], 3), pair_evals_per_launch=evals_launch,
+                    pair_evals_per_s=round(evals_launch / (ks["mixed"] * 1e-3), 1),
+                    fp64_kernel_ms_per_launch=round(ks["fp64"], 2),
+                    fp64_kernel_tflops=round(evals_launch * FLOP_PER_PAIR / (ks["fp64"] * 1e-3) / 1e12, 2),
+                    fp64_peak=PEAK_FP64_TFLOPS)
+
+    err = rel_rigid_error(out32, out64) if out64 is not None else None
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(c, a, ns, nc, rs, args.cpu_targets)
+        log(f"cpu baseline {cpu['value']:.3e} pair-evals/s on {cpu['cores']} processes")
+
+    line = {
+        "metric": "Stokeslet pair-evals/s + time-to-solve P=10k phi=0.65 at 1e-5 (mixed vs FP64)",
+        "value": round(value, 1),
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"mobility solve, P={P} unit disks, area fraction 0.65, min gap 1e-3, "
+                               f"{n_pairs} close pairs, N_c=36 M_c=72 R_c=0.7, unit torques, GMRES tol {args.tol:g}",
+                   "P": P, "n_pairs": n_pairs, "unknowns": 2 * Nt},
+        "time_to_solve_s": {"mixed": round(ms / 1e3, 3), "fp64": round(t_fp64, 3) if t_fp64 else None},
+        "speedup_mixed_vs_fp64": round(t_fp64 / (ms / 1e3), 2) if t_fp64 else None,
+        "max_rel_velocity_diff_mixed_vs_fp64": err,
+        "iterations": {"mixed_inner": infos[-1]["iters"], "mixed_outer": infos[-1]["outer"],
+                       "fp64": info64.get("iters")},
+        "rel_resid": {"mixed": infos[-1]["rel_resid"], "fp64": info64.get("rel_resid")},
+        "pair_evals_per_solve": evals_skip,
+        "setup_s": round(t_setup, 3),
+        "precompute_s": round(t_pre, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    nv.mfs_destroy(ctx)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,6 +86,9 @@ typedef struct {
   int32_t hist_len;       /* entries written */
   double ms_rhs, ms_iterate, ms_post;   /* wall-clock phases of the solve */
   int64_t n_pairs;
+  int32_t matvecs_fp64;   /* operator applications with the FP64 kernel sum (refinement residuals) */
+  int32_t matvecs_mixed;  /* operator applications with the mixed kernel sum */
+  int64_t pair_evals;     /* Stokeslet (target, source) evaluations in all kernel sums of the solve */
 } mfs_solve_info;
 
 /* Fill *prm with the paper's defaults.  prm: host, written. */

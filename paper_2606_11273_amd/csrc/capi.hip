@@ -140,6 +140,14 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   }
   Status st = onebody_factors(c);
   if (st.code) return st;
+  // exact evaluation counts of one kernel sum: all sources, and without own disk and partners
+  c->evals_all = c->Ns * c->Nt;
+  c->evals_skip = 0;
+  for (int i = 0; i < P; ++i) {
+    int64_t skipped = n_src[i];
+    for (int e = c->nbr_off[i]; e < c->nbr_off[i + 1]; ++e) skipped += n_src[c->nbr_list[e]];
+    c->evals_skip += (int64_t)n_col[i] * (c->Ns - skipped);
+  }
   // absolute and relative coordinates
   std::vector<double> Y(2 * c->Ns), X(2 * c->Nt);
   std::vector<float> Xr32(2 * c->Nt);
@@ -208,6 +216,11 @@ Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u) {
   if (wp) launch_pair_A(c, prob, c->d_lam_bar, c->d_ltil);
   launch_gather_project(c, prob, c->d_lam_bar, c->d_ltil, wp, mixed, !mixed);
   const bool ks = launch_kernel_sum(c, mixed, 2, c->d_u, 1.0 / (4.0 * kPiD * c->prm.mu));
+  c->cnt_pair_evals += c->evals_skip;
+  if (mixed)
+    ++c->cnt_mv32;
+  else
+    ++c->cnt_mv64;
   if (wp) launch_pair_field(c, prob, c->d_ltil, c->d_corr);
   launch_finish(c, c->d_u, mu, c->d_corr, u, wp);
   return check_kernel_sum(c, ks);
@@ -392,6 +405,7 @@ mfs_status mfs_rhs(mfs_ctx* c, mfs_problem prob, const double* given, double* b)
   if (prob == MFS_MOBILITY) {
     launch_rhs_mobility_sources(c, c->d_given);
     ks = launch_kernel_sum(c, false, 0, b, -1.0 / (4.0 * kPiD * c->prm.mu));
+    c->cnt_pair_evals += c->evals_all;
   } else {
     launch_rhs_resistance(c, c->d_given, b);
   }

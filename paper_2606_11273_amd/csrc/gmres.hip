@@ -5,15 +5,24 @@
 // (CGS2): two passes of h = V^T w, w -= V h per iteration, all FP64, with the dot
 // products reduced in a fixed order.  The (k+1) x k Hessenberg least-squares
 // problem is updated by Givens rotations on the host (a few doubles per
-// iteration cross the bus).  MFS_MIXED runs GMRES-IR: FP64 true residual
-// r = b - T_64 x, inner GMRES on the operator whose all-pairs sum is FP32 with
-// FP64 accumulation, x += d, until |r| <= tol |b|.
+// iteration cross the bus).
+//
+// MFS_MIXED: FP64 iterative refinement around a GMRES whose operator applications
+// switch from FP64 to the mixed operator (FP32 all-pairs sum, FP64 accumulation)
+// once the Arnoldi residual estimate has dropped below tol_inner / delta, delta an
+// upper estimate of the mixed operator's relative error.  This is the relaxation
+// of inexact Krylov methods (Simoncini & Szyld 2003; Bouras & Fraysse 2005): the
+// operator error tolerated at step k grows like tol / |r_k|, so only the first
+// iterations need FP64, and one Krylov space serves the whole solve instead of
+// being rebuilt at every refinement step.  Each refinement step computes the
+// true residual r = b - T_64 x in FP64 and stops when |r| <= tol |b|.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "internal.h"
@@ -66,8 +75,9 @@ double dnorm(mfs_ctx* c, const double* v, Status* st) {
 }
 
 // Solve T d = r (starting from d = 0) to |r - T d| <= tol |r| (Givens estimate); d returned in k.d.
-Status gmres_core(mfs_ctx* c, int prob, bool mixed, const double* r, double tol, int maxit, int* iters,
-                  std::vector<double>& hist) {
+// Operator applications use the mixed kernel sum once the estimate is below switch_below.
+Status gmres_core(mfs_ctx* c, int prob, bool mixed, double switch_below, const double* r, double tol, int maxit,
+                  int* iters, std::vector<double>& hist) {
   Krylov& k = c->kr;
   const int64_t n = k.n;
   const int nblk = mdot_blocks(n);
@@ -84,9 +94,13 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, const double* r, double tol,
   g[0] = beta;
   int kdone = 0;
   const int cap = k.cap;
+  const bool prof = std::getenv("MFS_PROFILE") != nullptr;
+  auto t_start = clk::now();
+  double rel_est = 1.0;
   for (int j = 0; j < maxit; ++j) {
     double* vj = k.V + (int64_t)j * n;
-    if ((st = apply_T(c, prob, mixed, vj, k.w)).code) return st;
+    const bool use32 = mixed && rel_est <= switch_below;
+    if ((st = apply_T(c, prob, use32, vj, k.w)).code) return st;
     // CGS2
     launch_mdot(c->stream, n, j + 1, k.V, n, k.w, k.part, k.hdev, nblk);
     launch_maxpy(c->stream, n, j + 1, k.V, n, k.hdev, k.w);
@@ -115,6 +129,10 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, const double* r, double tol,
     g[j] = cs[j] * g[j];
     kdone = j + 1;
     hist.push_back(std::fabs(g[j + 1]) / beta);
+    rel_est = hist.back();
+    if (prof && (kdone % 10 == 0))
+      std::fprintf(stderr, "[mfs gmres] %s it %d resid %.3e  %.1f s\n", use32 ? "fp32-sum" : "fp64", kdone,
+                   hist.back(), ms_since(t_start) * 1e-3);
     if (std::fabs(g[j + 1]) <= tol * beta || hn == 0.0) break;
   }
   std::vector<double> y(kdone);
@@ -128,6 +146,14 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, const double* r, double tol,
   MFS_HIP(hipStreamSynchronize(c->stream));
   *iters = kdone;
   return Status{};
+}
+
+// Upper estimate of the relative error of the mixed operator on Krylov vectors
+// (measured: 1e-5 on smooth data, up to 1e-2 on i.i.d. rough data at P = 16).
+double mixed_delta() {
+  const char* e = std::getenv("MFS_MIXED_DELTA");
+  const double d = e ? std::atof(e) : 1e-4;
+  return d > 0 ? d : 1e-4;
 }
 
 }  // namespace
@@ -158,6 +184,8 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
   double t_rhs = 0, t_it = 0, t_post = 0;
   int iters_total = 0, outer = 0, hist_len = 0;
   double rel = 0;
+  c->cnt_pair_evals = 0;
+  c->cnt_mv64 = c->cnt_mv32 = 0;
   for (int rr = 0; rr < n_rhs; ++rr) {
     auto t0 = clk::now();
     mfs_status s = mfs_rhs(c, prob, rhs + 3 * (size_t)c->P * rr, k.b);
@@ -173,7 +201,7 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
     std::vector<double> hist;
     const bool mixed = prec == MFS_MIXED;
     // outer refinement (a single pass for FP64 with x0 = 0)
-    const int max_outer = mixed ? 30 : 3;
+    const int max_outer = mixed ? 10 : 3;
     int used = 0;
     rel = 1.0;
     for (int o = 0; o < max_outer; ++o) {
@@ -191,11 +219,15 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
       rel = bn > 0 ? rn / bn : 0.0;
       if (rel <= tol || used >= max_iter) break;
       ++outer;
-      // inner tolerance: reach the target in one pass if the operator allows it
-      double tin = tol * bn / rn;
-      if (mixed) tin = std::max(0.5 * tin, 1e-6);
+      // reach the target in one pass if the operator allows it
+      const double tin = tol * bn / rn;
+      const double switch_below = mixed ? std::min(1.0, tin / mixed_delta()) : 0.0;
+      if (std::getenv("MFS_PROFILE"))
+        std::fprintf(stderr, "[mfs gmres] refinement %d: |r|/|b| = %.3e, inner tol %.3e, mixed below %.3e\n", o, rel,
+                     tin, switch_below);
       int it = 0;
-      if ((st = gmres_core(c, prob, mixed, k.r, tin, max_iter - used, &it, hist)).code) return failc(st);
+      if ((st = gmres_core(c, prob, mixed, switch_below, k.r, tin, max_iter - used, &it, hist)).code)
+        return failc(st);
       used += it;
       launch_axpby(c->stream, n, 1.0, k.d, 1.0, k.x);
       if (it == 0) break;
@@ -221,6 +253,9 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
     info->ms_iterate = t_it;
     info->ms_post = t_post;
     info->n_pairs = (int64_t)(c->pairs.size() / 2);
+    info->matvecs_fp64 = c->cnt_mv64;
+    info->matvecs_mixed = c->cnt_mv32;
+    info->pair_evals = c->cnt_pair_evals;
   }
   if (result != MFS_OK) {
     char buf[64];

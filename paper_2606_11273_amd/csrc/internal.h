@@ -101,6 +101,11 @@ struct mfs_ctx {
 
   mfs::PairSet ps[2];
   mfs::Krylov kr;
+
+  // work counters (host side, reset by mfs_gmres_solve)
+  int64_t evals_all = 0, evals_skip = 0;     // pair evaluations of one kernel sum per skip mode
+  int64_t cnt_pair_evals = 0;
+  int32_t cnt_mv64 = 0, cnt_mv32 = 0;
 };
 
 namespace mfs {

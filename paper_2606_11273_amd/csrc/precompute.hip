@@ -18,7 +18,10 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <array>
 #include <cstring>
 
@@ -426,8 +429,32 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
   }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nfe[a] < nfe[b]; });
 
-  const int batch = 32;
+  const bool prof = std::getenv("MFS_PROFILE") != nullptr;
+  double tstage[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  auto tick = [&](int k, std::chrono::steady_clock::time_point& t0) {
+    if (!prof) return;
+    (void)hipStreamSynchronize(c->stream);
+    auto t1 = std::chrono::steady_clock::now();
+    tstage[k] += std::chrono::duration<double>(t1 - t0).count();
+    t0 = t1;
+  };
+  // Batched SVDs are latency-bound at small batch counts: size the batch from free
+  // device memory (about 40 MB of work space per pair at the paper's fine grids).
+  int batch = 32;
+  {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      const int nfmax = fp.n_fp + 2 * fp.n_ell;
+      const double per_pair = 8.0 * (2.0 * (4.0 * mf) * (4.0 * nfmax) + 2.0 * (4.0 * nfmax) * (4.0 * nfmax) +
+                                     6.0 * (4.0 * mf + 2.0 * mp) * 4.0 * kMaxCol / 4.0);
+      const double cap = 0.5 * (double)free_b / per_pair;
+      batch = (int)std::max(1.0, std::min(256.0, cap));
+    }
+    const char* env = std::getenv("MFS_PRECOMPUTE_BATCH");
+    if (env) batch = std::max(1, std::atoi(env));
+  }
   for (int b0 = 0; b0 < C; b0 += batch) {
+    auto t0 = std::chrono::steady_clock::now();
     const int nb = std::min(batch, C - b0);
     int nfpad = 0;
     for (int q = 0; q < nb; ++q) nfpad = std::max(nfpad, nfe[order[b0 + q]]);
@@ -524,6 +551,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_HIP(hipMemsetAsync(dF.p, 0, sizeof(double) * d.sF * nb, c->stream));
     MFS_HIP(hipMemsetAsync(dX.p, 0, sizeof(double) * d.sX * nb, c->stream));
     MFS_HIP(hipMemsetAsync(dD.p, 0, sizeof(double) * d.sD * nb, c->stream));
+    tick(0, t0);
     {
       const int maxpts = std::max(2 * mf, mp);
       dim3 grid((maxpts + 63) / 64, nb, 4);
@@ -531,6 +559,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
                          (const double*)dKKc.p, (double*)dF.p, (double*)dX.p, (double*)dD.p, (double*)dC.p);
       MFS_HIP(hipGetLastError());
     }
+    tick(1, t0);
     MFS_HIP(hipMalloc(&dSF.p, sizeof(double) * mn * nb));
     MFS_HIP(hipMalloc(&dU.p, sizeof(double) * m * mn * nb));
     MFS_HIP(hipMalloc(&dVT.p, sizeof(double) * mn * n * nb));
@@ -541,6 +570,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
                                             (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p, (int)m,
                                             m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
                                             rocblas_outofplace, (int*)dinfo.p, nb));
+    tick(2, t0);
     // T1 = U^T X  (mn x nx)
     MFS_HIP(hipMalloc(&dT1.p, sizeof(double) * mn * nx * nb));
     MFS_HIP(hipMalloc(&dG.p, sizeof(double) * n * nx * nb));
@@ -564,6 +594,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none, (int)mpp, (int)nx,
                                          (int)n, &one, (const double*)dD.p, (int)mpp, d.sD, (const double*)dG.p,
                                          (int)n, n * nx, &zero, (double*)dDG.p, (int)mpp, mpp * nx, nb));
+    tick(3, t0);
     // SVD of C (2mp x nx), then A = -V_C Sigma_C^+ U_C^T (D G)
     const int64_t mnc = std::min(mpp, nx);
     MFS_HIP(hipMalloc(&dSC.p, sizeof(double) * mnc * nb));
@@ -574,6 +605,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
                                             (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
                                             (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
                                             mnc * nx, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nb));
+    tick(4, t0);
     MFS_HIP(hipMalloc(&dT2.p, sizeof(double) * mnc * nx * nb));
     MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnc,
                                          (int)nx, (int)mpp, &one, (const double*)dUC.p, (int)mpp, mpp * mnc,
@@ -602,7 +634,12 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_HIP(hipStreamSynchronize(c->stream));
     for (int q = 0; q < 2 * nb; ++q)
       if (info[q] != 0) return Status{MFS_ERR_NUMERIC, "pair SVD did not converge"};
+    tick(5, t0);
+    if (prof) std::fprintf(stderr, "[mfs precompute] %d / %d pairs (batch %d)\n", b0 + nb, C, batch);
   }
+  if (prof)
+    std::fprintf(stderr, "[mfs precompute] pairs %d: host+upload %.3fs fill %.3fs svdF %.3fs gemm %.3fs svdC %.3fs rest %.3fs\n",
+                 C, tstage[0], tstage[1], tstage[2], tstage[3], tstage[4], tstage[5]);
   ps.ready = true;
   return Status{};
 }

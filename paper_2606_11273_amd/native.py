@@ -43,7 +43,8 @@ class MfsSolveInfo(C.Structure):
     _fields_ = [("iters_total", C.c_int32), ("outer_steps", C.c_int32), ("rel_resid", C.c_double),
                 ("resid_hist", C.POINTER(C.c_double)), ("hist_cap", C.c_int32), ("hist_len", C.c_int32),
                 ("ms_rhs", C.c_double), ("ms_iterate", C.c_double), ("ms_post", C.c_double),
-                ("n_pairs", C.c_int64)]
+                ("n_pairs", C.c_int64), ("matvecs_fp64", C.c_int32), ("matvecs_mixed", C.c_int32),
+                ("pair_evals", C.c_int64)]
 
 
 class MFSError(RuntimeError):
@@ -217,7 +218,8 @@ def mfs_gmres_solve(ctx, problem, precision, rhs, tol, max_iter=500, x0=None, hi
         _check(code, ctx)
     d = dict(iters=info.iters_total, outer=info.outer_steps, rel_resid=info.rel_resid,
              hist=hist[:info.hist_len].copy(), ms_rhs=info.ms_rhs, ms_iterate=info.ms_iterate, ms_post=info.ms_post,
-             n_pairs=info.n_pairs, status=STATUS_NAMES[code])
+             n_pairs=info.n_pairs, matvecs_fp64=info.matvecs_fp64, matvecs_mixed=info.matvecs_mixed,
+             pair_evals=info.pair_evals, status=STATUS_NAMES[code])
     return out, d
 
 

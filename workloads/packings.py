@@ -125,6 +125,32 @@ def _set_closest_gap(c, radii, g_min):
     raise RuntimeError("could not set the closest gap exactly")
 
 
+def _mc_sweeps(c, radii, box, g_min, step, sweeps, rng):
+    """Accept/reject Monte-Carlo sweeps (the packing randomisation of Sec. 6.2): each disk in
+    turn proposes a displacement uniform in a disk of radius ``step``; it is accepted if the
+    disk stays in the box and keeps gap >= g_min to every other disk."""
+    P = c.shape[0]
+    amax = radii.max()
+    for _ in range(sweeps):
+        tree = cKDTree(c)
+        cand = tree.query_ball_point(c, r=2.0 * amax + g_min + 2.0 * step)
+        rr = step * np.sqrt(rng.uniform(size=P))
+        tt = rng.uniform(0.0, 2.0 * math.pi, size=P)
+        disp = np.stack([rr * np.cos(tt), rr * np.sin(tt)], axis=1)
+        for i in rng.permutation(P):
+            p = c[i] + disp[i]
+            if box is not None and (np.any(p < radii[i]) or np.any(p > box - radii[i])):
+                continue
+            nb = [k for k in cand[i] if k != i]
+            if nb:
+                nb = np.asarray(nb)
+                d = np.hypot(c[nb, 0] - p[0], c[nb, 1] - p[1]) - radii[nb] - radii[i]
+                if d.min() < g_min:
+                    continue
+            c[i] = p
+    return c
+
+
 def jittered_grid(seed, n=4, spacing=2.3, jitter=0.12, g_min=1e-3, radius=1.0):
     """n x n square grid with spacing ``spacing``, each centre jittered U[-jitter, jitter]^2.
 
@@ -157,11 +183,12 @@ def _triangular_sites(P, box, rng):
     return sites, lattice_gap_dist
 
 
-def lattice_packing(seed, P, phi, g_min, rho, radius=1.0):
+def lattice_packing(seed, P, phi, g_min, rho, radius=1.0, sweeps=4):
     """Perturbed triangular lattice of P equal disks in a square box at area fraction phi.
 
     Each centre moves uniformly within a disk of radius rho*(s - 2a) (s the lattice
-    distance), the packing is relaxed until every gap >= g_min, and the closest
+    distance), the packing is relaxed until every gap >= g_min, randomised by
+    ``sweeps`` accept/reject Monte-Carlo sweeps (step (s - 2a)/2), and the closest
     pair is set to gap g_min exactly.  Returns (centres, radii, box side).
     """
     rng = _rng(seed)
@@ -174,6 +201,7 @@ def lattice_packing(seed, P, phi, g_min, rho, radius=1.0):
     radii = np.full(P, radius)
     c = np.minimum(np.maximum(c, radius), box - radius)
     c = _relax(c, radii, box, g_min * 1.02)
+    c = _mc_sweeps(c, radii, box, g_min * 1.02, 0.5 * max(s - 2.0 * radius, 0.05), sweeps, rng)
     c = _set_closest_gap(c, radii, g_min)
     return c, radii, box
 
@@ -190,6 +218,7 @@ def bidisperse_packing(seed, P, phi, g_min, rho, radii_pair=(1.0, 1.4)):
     c = sites + np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
     c = np.minimum(np.maximum(c, radii[:, None]), box - radii[:, None])
     c = _relax(c, radii, box, g_min * 1.02)
+    c = _mc_sweeps(c, radii, box, g_min * 1.02, 0.5 * max(s - 2.0 * radii_pair[1], 0.05), 4, rng)
     c = _set_closest_gap(c, radii, g_min)
     return c, radii, box
 
@@ -197,7 +226,7 @@ def bidisperse_packing(seed, P, phi, g_min, rho, radii_pair=(1.0, 1.4)):
 # Perturbation amplitudes: C3's is calibrated so that the number of pairs with
 # gap <= 0.2 is close to 0.99 P, the close-pair density of the paper's
 # P = 10^4, area fraction 0.65 packing (9920 close pairs).
-_RHO = {2: 0.9, 3: 1.55, 5: 0.9}
+_RHO = {2: 0.9, 3: 1.62, 5: 0.9}
 
 
 def config_geometry(cfg, k=0, P=None):
