@@ -3,7 +3,8 @@
 Workload: P = 10000 unit disks at area fraction 0.65 (seeded perturbed triangular
 lattice relaxed to a minimum gap of 1e-3, about 0.99 P close pairs), 36 coarse
 Stokeslet sources on radius 0.7 and 72 collocation nodes per disk, unit torque on
-every disk, zero forces, GMRES tolerance 1e-7 (the paper's).  One step is one
+every disk, zero forces, GMRES relative-residual tolerance 5e-9 (the velocities of
+both forms then agree to 1e-5; the paper's 1e-7 leaves them ~2e-4 apart).  One step is one
 full mobility solve through the C ABI: right-hand side, GMRES-IR on the Alg. 3
 operator (FP32 kernel sum with FP64 accumulation and FP64 refinement), and
 post-processing to velocities.  Setup and the pair precompute happen before the
@@ -62,16 +63,21 @@ def cpu_baseline(centers, radii, n_src, n_col, r_src, n_targets, sig_seed=1):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--P", type=int, default=10000)
-    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--tol", type=float, default=5e-9,
+                    help="relative residual; 5e-9 brings both forms within 1e-5 of each other in the "
+                         "velocities (at the paper's 1e-7 they differ by ~2e-4)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-targets", type=int, default=3000)
     ap.add_argument("--ksum-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="set up the workload and run only the dominant kernel (plus --copy-calibration): "
+                         "the short program the hardware-counter runs profile")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs the hot path on one GPU; multi-GPU runs are not part of it "
@@ -99,6 +105,21 @@ def main():
     t0 = time.perf_counter()
     ctx = nv.mfs_setup(c, a, ns, nc, rs, prm)
     t_setup = time.perf_counter() - t0
+    if args.kernel_only:
+        _, Ns, Nt, _ = nv.mfs_get_sizes(ctx)
+        sig = torch.randn(2 * Ns, dtype=torch.float64, device="cuda")
+        u = torch.zeros(2 * Nt, dtype=torch.float64, device="cuda")
+        for _ in range(args.ksum_reps):
+            nv.mfs_kernel_sum(ctx, "mixed", sig, u, 2)
+        if args.copy_calibration:
+            buf = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+            out = torch.empty_like(buf)
+            out.copy_(buf)
+        torch.cuda.synchronize()
+        nv.mfs_destroy(ctx)
+        print(json.dumps({"kernel_only": True, "launches": args.ksum_reps, "copy_bytes": (1 << 30) if
+                          args.copy_calibration else 0}), flush=True)
+        return
     t0 = time.perf_counter()
     n_pairs = nv.mfs_precompute_pairs(ctx, "mobility")
     torch.cuda.synchronize()

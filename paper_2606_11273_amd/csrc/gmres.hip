@@ -148,12 +148,14 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, double switch_below, const d
   return Status{};
 }
 
-// Upper estimate of the relative error of the mixed operator on Krylov vectors
-// (measured: 1e-5 on smooth data, up to 1e-2 on i.i.d. rough data at P = 16).
+// Upper estimate of the relative error of the mixed operator on Krylov vectors:
+// 1e-5 on smooth data, but Krylov vectors carry rough components whose strengths
+// the one-body pseudoinverse amplifies, and at P = 10^4 the true residual of a
+// relaxed solve showed about 1e-2.  MFS_MIXED_DELTA overrides it.
 double mixed_delta() {
   const char* e = std::getenv("MFS_MIXED_DELTA");
-  const double d = e ? std::atof(e) : 1e-4;
-  return d > 0 ? d : 1e-4;
+  const double d = e ? std::atof(e) : 1e-2;
+  return d > 0 ? d : 1e-2;
 }
 
 }  // namespace

@@ -7,6 +7,9 @@
 // of a dot product) runs in a fixed order, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace mfs {
@@ -274,11 +277,12 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
                                                            const float4* __restrict__ src,
                                                            const float4* __restrict__ bdat, int64_t Nt,
                                                            const int* __restrict__ tgt_body,
-                                                           const float* __restrict__ xr32, int bodies_per_split,
+                                                           const double* __restrict__ X, int bodies_per_split,
                                                            int mode, const int* __restrict__ nbr_off,
                                                            const int* __restrict__ nbr_list, double scale,
                                                            double* __restrict__ out) {
-  __shared__ float4 s_src[KS_TILE];
+  __shared__ float4 s_src[KS_TILE];    // (y_x, y_y, sigma_x, sigma_y), y relative to the disk centre
+  __shared__ float s_w[KS_TILE];       // y . sigma
   __shared__ double s_c[2 * KS_MAXB];
   __shared__ float4 s_b[KS_MAXB];
   __shared__ int s_off[KS_MAXB + 1];
@@ -287,18 +291,15 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
   const int kb1 = min(P, kb0 + bodies_per_split);
   int64_t t[T];
   int bt[T];
-  double cx[T], cy[T], ax[T], ay[T];
-  float xr[T], yr[T];
+  double x[T], y[T], ax[T], ay[T];
   Skip sk[T];
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + j * KS_THREADS + threadIdx.x;
     const int64_t tc = t[j] < Nt ? t[j] : Nt - 1;
     bt[j] = tgt_body[tc];
-    cx[j] = centers[2 * bt[j]];
-    cy[j] = centers[2 * bt[j] + 1];
-    xr[j] = xr32[2 * tc];
-    yr[j] = xr32[2 * tc + 1];
+    x[j] = X[2 * tc];
+    y[j] = X[2 * tc + 1];
     ax[j] = 0.0;
     ay[j] = 0.0;
     skip_init(sk[j], mode, bt[j], kb0, nbr_off, nbr_list);
@@ -310,7 +311,11 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
     while (kt + nb < kb1 && nb < KS_MAXB && src_off[kt + nb + 1] - s0 <= KS_TILE) ++nb;
     const int ns = src_off[kt + nb] - s0;
     __syncthreads();
-    for (int q = threadIdx.x; q < ns; q += KS_THREADS) s_src[q] = src[s0 + q];
+    for (int q = threadIdx.x; q < ns; q += KS_THREADS) {
+      const float4 v = src[s0 + q];
+      s_src[q] = v;
+      s_w[q] = fmaf(v.x, v.z, v.y * v.w);
+    }
     for (int q = threadIdx.x; q < nb; q += KS_THREADS) {
       s_c[2 * q] = centers[2 * (kt + q)];
       s_c[2 * q + 1] = centers[2 * (kt + q) + 1];
@@ -320,42 +325,46 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
     __syncthreads();
     for (int kk = 0; kk < nb; ++kk) {
       const int kbody = kt + kk;
-      const float4 bd = s_b[kk];   // (S0x, S0y, q, -)
-      float dxt[T], dyt[T], r2c[T], ir2c[T], lx[T], ly[T], tx[T], ty[T];
+      const float4 bd = s_b[kk];   // (S0x, S0y, q = |y|^2, -)
+      // per (target, disk): D = x - c_k (FP64, rounded once), R^2, and the scaled
+      // offsets for u = r^2 / R^2 = 1 + (q - 2 D.y) / R^2
+      float Dx[T], Dy[T], ir2[T], Dxs[T], Dys[T], c0[T], lx[T], ly[T], t0[T], tsx[T], tsy[T];
 #pragma unroll
       for (int j = 0; j < T; ++j) {
-        dxt[j] = (float)(cx[j] - s_c[2 * kk]) + xr[j];
-        dyt[j] = (float)(cy[j] - s_c[2 * kk + 1]) + yr[j];
-        r2c[j] = fmaf(dxt[j], dxt[j], dyt[j] * dyt[j]);
-        ir2c[j] = __builtin_amdgcn_rcpf(r2c[j]);
-        lx[j] = ly[j] = tx[j] = ty[j] = 0.0f;
+        Dx[j] = (float)(x[j] - s_c[2 * kk]);
+        Dy[j] = (float)(y[j] - s_c[2 * kk + 1]);
+        ir2[j] = __builtin_amdgcn_rcpf(fmaf(Dx[j], Dx[j], Dy[j] * Dy[j]));
+        Dxs[j] = -2.0f * Dx[j] * ir2[j];
+        Dys[j] = -2.0f * Dy[j] * ir2[j];
+        c0[j] = fmaf(bd.z, ir2[j], 1.0f);
+        lx[j] = ly[j] = t0[j] = tsx[j] = tsy[j] = 0.0f;
       }
       const int q1 = s_off[kk + 1];
       for (int q = s_off[kk]; q < q1; ++q) {
         const float4 s = s_src[q];
+        const float w = s_w[q];
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-          const float dx = dxt[j] - s.x;
-          const float dy = dyt[j] - s.y;
-          const float dy2 = fmaf(dxt[j], s.x, dyt[j] * s.y);      // D.y
-          const float num = fmaf(-2.0f, dy2, bd.z);                 // q - 2 D.y = r^2 - R^2
-          const float u = fmaf(num, ir2c[j], 1.0f);                 // r^2 / R^2
-          const float r2 = r2c[j] * u;
-          const float lg = __builtin_amdgcn_logf(u);
-          const float inv = __builtin_amdgcn_rcpf(r2);
-          const float dot = fmaf(dx, s.z, dy * s.w) * inv;
+          const float u = fmaf(Dxs[j], s.x, fmaf(Dys[j], s.y, c0[j]));   // r^2 / R^2
+          const float lg = __builtin_amdgcn_logf(u);                      // log2(r^2 / R^2)
+          const float iu = __builtin_amdgcn_rcpf(u);
+          const float tt = fmaf(Dx[j], s.z, fmaf(Dy[j], s.w, -w)) * iu;   // R^2 (d.sigma) / r^2
           lx[j] = fmaf(lg, s.z, lx[j]);
           ly[j] = fmaf(lg, s.w, ly[j]);
-          tx[j] = fmaf(dot, dx, tx[j]);
-          ty[j] = fmaf(dot, dy, ty[j]);
+          t0[j] += tt;
+          tsx[j] = fmaf(tt, s.x, tsx[j]);
+          tsy[j] = fmaf(tt, s.y, tsy[j]);
         }
       }
 #pragma unroll
       for (int j = 0; j < T; ++j) {
         if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
-          const float lR = __builtin_amdgcn_logf(r2c[j]);
-          ax[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.x, lx[j]), tx[j]);
-          ay[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.y, ly[j]), ty[j]);
+          // sum_s (d.sigma) d / r^2 = (D sum t - sum t y) / R^2
+          const float tx = ir2[j] * fmaf(Dx[j], t0[j], -tsx[j]);
+          const float ty = ir2[j] * fmaf(Dy[j], t0[j], -tsy[j]);
+          const float lR = __builtin_amdgcn_logf(fmaf(Dx[j], Dx[j], Dy[j] * Dy[j]));
+          ax[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.x, lx[j]), tx);
+          ay[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.y, ly[j]), ty);
         }
       }
     }
@@ -757,15 +766,24 @@ void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const do
                      pack64 ? c->d_src64 : (double4*)nullptr, pack32 ? c->d_bdat : (float4*)nullptr);
 }
 
-// Choose the source split so that the grid holds enough workgroups to fill the chip.
+// Choose the source split so that the grid holds enough workgroups to fill the chip
+// (256 CUs, several resident workgroups each).  MFS_KSUM_SPLITS overrides it.
 static int ksum_splits(int64_t tblocks, int P) {
+  const char* e = std::getenv("MFS_KSUM_SPLITS");
+  if (e) return std::max(1, std::min(P, std::atoi(e)));
   int s = 1;
-  while (tblocks * s < 2048 && s * 2 <= P && s < 64) s *= 2;
+  while (tblocks * s < 16384 && s * 2 <= std::max(1, P / 8) && s < 64) s *= 2;
   return s;
 }
 
+static int ksum_targets_per_thread(bool mixed) {
+  const char* e = std::getenv(mixed ? "MFS_KSUM_T" : "MFS_KSUM_T64");
+  const int t = e ? std::atoi(e) : 2;
+  return t == 1 || t == 2 || t == 4 ? t : 2;
+}
+
 bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale) {
-  constexpr int T = 2;
+  const int T = ksum_targets_per_thread(mixed);
   const int64_t Nt = c->Nt;
   const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
   const int ns = ksum_splits(tblocks, c->P);
@@ -787,13 +805,20 @@ bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale
     out = c->d_upart;
   }
   dim3 grid((unsigned)tblocks, (unsigned)ns);
-  if (mixed)
-    hipLaunchKernelGGL(k_ksum_mixed<T>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_centers,
-                       c->d_sig32, c->d_bdat, Nt, c->d_tgt_body, c->d_Xr32, bps, mode, c->d_nbr_off, c->d_nbr_list, scale,
-                       out);
-  else
-    hipLaunchKernelGGL(k_ksum_fp64<T>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_src64, Nt,
-                       c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out);
+#define MFS_KS_MIXED(TT)                                                                                          \
+  hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_centers,   \
+                     c->d_sig32, c->d_bdat, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, \
+                     scale, out)
+#define MFS_KS_FP64(TT)                                                                                       \
+  hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_src64, Nt, \
+                     c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out)
+  if (mixed) {
+    if (T == 4) MFS_KS_MIXED(4); else if (T == 1) MFS_KS_MIXED(1); else MFS_KS_MIXED(2);
+  } else {
+    if (T == 4) MFS_KS_FP64(4); else if (T == 1) MFS_KS_FP64(1); else MFS_KS_FP64(2);
+  }
+#undef MFS_KS_MIXED
+#undef MFS_KS_FP64
   if (ns > 1)
     hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns,
                        c->d_upart, u);
