@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=3000)
     ap.add_argument("--ksum-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 1 GiB device copy (reference kernel for HBM counters)")
+                    help="also run one 1 GiB-in, 1 GiB-out elementwise kernel (reference for HBM counters)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="set up the workload and run only the dominant kernel (plus --copy-calibration): "
                          "the short program the hardware-counter runs profile")
@@ -112,9 +112,11 @@ def main():
         for _ in range(args.ksum_reps):
             nv.mfs_kernel_sum(ctx, "mixed", sig, u, 2)
         if args.copy_calibration:
+            # an elementwise kernel that reads 1 GiB and writes 1 GiB (a same-dtype copy_ could
+            # go to the DMA engines, which the shader counters do not see)
             buf = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
             out = torch.empty_like(buf)
-            out.copy_(buf)
+            torch.neg(buf, out=out)
         torch.cuda.synchronize()
         nv.mfs_destroy(ctx)
         print(json.dumps({"kernel_only": True, "launches": args.ksum_reps, "copy_bytes": (1 << 30) if
@@ -179,9 +181,9 @@ def main():
     value = evals / wall
 
     if args.copy_calibration:
-        buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        buf = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         out = torch.empty_like(buf)
-        out.copy_(buf)
+        torch.neg(buf, out=out)
         torch.cuda.synchronize()
 
     # roofline of the dominant kernel (mixed kernel sum; one launch = one matvec's sum without

@@ -179,6 +179,77 @@ mfs_status mfs_destroy(mfs_ctx* ctx);
  * ctx is NULL).  Valid until the next call on that context. */
 const char* mfs_last_error(const mfs_ctx* ctx);
 
+/* ---------------------------------------------------------------------------------
+ * Serving: continuous batching of independent suspension solves on one device.
+ *
+ * A server owns max_slots HIP streams, each driven by a host worker thread.  A
+ * submitted request (geometry + given forces/torques or velocities) is queued; a
+ * free slot admits the oldest queued request whose device-memory footprint fits in
+ * what the budget has left (requests that arrive while others run are admitted as
+ * slots and memory free up).  An admitted request runs setup, the pair precompute
+ * and the solve (mfs_setup, mfs_precompute_pairs, mfs_gmres_solve) on its slot's
+ * stream, so the work of different requests overlaps on the device; its context,
+ * pair matrices and Krylov basis stay resident until it completes.  Each request's
+ * arithmetic does not depend on what else runs: the same request gives the same
+ * result alone and in a mix.  The solve follows Alg. 2 (Sec. 4.4 for mobility).
+ * --------------------------------------------------------------------------------- */
+typedef struct mfs_server mfs_server;
+
+typedef struct {
+  int32_t P;                /* number of disks */
+  const double* centers;    /* host, P x 2 */
+  const double* radii;      /* host, P */
+  const int32_t* n_src;     /* host, P */
+  const int32_t* n_col;     /* host, P */
+  const double* r_src;      /* host, P (see mfs_setup) */
+  mfs_problem problem;
+  mfs_precision precision;
+  const double* given;      /* host, P x 3: (fx, fy, t) for mobility, (vx, vy, omega) for resistance */
+  double tol;               /* relative residual tolerance of the solve */
+  int32_t max_iter;         /* inner iteration limit, 1..1000 */
+} mfs_request;
+
+typedef struct {
+  double ms_queue;          /* submit -> admission */
+  double ms_service;        /* admission -> completion (setup, precompute, solve) */
+  double ms_total;          /* submit -> completion: the time to solution */
+  double ms_precompute;     /* pair precompute inside the service time */
+  int64_t footprint_bytes;  /* device memory reserved for the request while it ran */
+  mfs_solve_info solve;     /* as from mfs_gmres_solve (resid_hist not filled) */
+} mfs_ticket_info;
+
+/* Create a server.  hbm_budget_bytes: device memory the admitted requests may hold
+ * together (0: 80% of the memory free on the current device now).  max_slots:
+ * concurrent requests, 1..64.  prm: host or NULL for the defaults; applies to every
+ * request.  Errors: MFS_ERR_ARG, MFS_ERR_DEVICE (stream creation).  *srv is NULL on
+ * error. */
+mfs_status mfs_server_create(mfs_server** srv, size_t hbm_budget_bytes, int32_t max_slots, const mfs_params* prm);
+
+/* Device-memory footprint the server reserves for a request (an upper bound of what
+ * its context, pair matrices, precompute work space and Krylov basis allocate).
+ * The host inputs are read during the call.  Errors: MFS_ERR_ARG, MFS_ERR_GEOMETRY. */
+mfs_status mfs_server_footprint(const mfs_server* srv, const mfs_request* req, int64_t* bytes);
+
+/* Queue a request; returns at once with its ticket (> 0).  The inputs are copied.
+ * Errors: MFS_ERR_ARG (sizes, or a footprint above the whole budget),
+ * MFS_ERR_GEOMETRY (some gap <= 0), MFS_ERR_STATE (server shutting down). */
+mfs_status mfs_server_submit(mfs_server* srv, const mfs_request* req, int64_t* ticket);
+
+/* Wait for a ticket to complete.  out: host, P x 3 ((vx, vy, omega) for mobility,
+ * (fx, fy, t) for resistance); info: host or NULL.  timeout_ms < 0 waits without
+ * limit.  Returns the request's own status (outputs are written for MFS_OK and
+ * MFS_ERR_NOCONV); the ticket is released.  On a timeout returns MFS_ERR_STATE and
+ * keeps the ticket.  An unknown ticket gives MFS_ERR_ARG. */
+mfs_status mfs_server_wait(mfs_server* srv, int64_t ticket, double* out, mfs_ticket_info* info,
+                           int32_t timeout_ms);
+
+/* Message for the last failing server call or request (valid until the next call). */
+const char* mfs_server_last_error(const mfs_server* srv);
+
+/* Stop admitting, finish the running requests, drop the queued ones and release
+ * every resource.  srv may be NULL. */
+mfs_status mfs_server_destroy(mfs_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

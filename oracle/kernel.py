@@ -74,7 +74,8 @@ def direct_sum(x, y, sig, mu=1.0, workers=None, chunk_elems=4_000_000):
     step = max(1, chunk_elems // max(N, 1))
     bounds = [(lo, min(M, lo + step)) for lo in range(0, M, step)]
     if workers is None:
-        workers = min(len(bounds), os.cpu_count() or 1) if M * N > 5e8 else 1
+        # at most 16 processes: hosts that share their cores between jobs give each one that many
+        workers = min(len(bounds), os.cpu_count() or 1, 16) if M * N > 5e8 else 1
     if workers <= 1 or len(bounds) == 1:
         for lo, hi in bounds:
             out[lo:hi] = _sum_chunk(x[lo:hi], y, sig, mu)

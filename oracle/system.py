@@ -124,8 +124,11 @@ class System:
         """T mu by Alg. 3 (FP64, direct O(N_s N_t) sum in step 2a)."""
         mu = np.asarray(mu, dtype=np.float64)
         lam_bar, lam, ltil = self.step1(mu)
-        sig = self.sigma(lam)
-        u = direct_sum(self.X, self.Y, sig.reshape(-1, 2), self.prm.mu, workers=workers).reshape(-1)
+        sig = self.sigma(lam).reshape(-1, 2)
+        # sources of zero strength add nothing to eq. getall: leaving them out changes no
+        # term of the sum (it lets inputs supported on a few disks run at large P)
+        nz = np.any(sig != 0.0, axis=1)
+        u = direct_sum(self.X, self.Y[nz], sig[nz], self.prm.mu, workers=workers).reshape(-1)
         mu_v = self.prm.mu
         for c, (i, k) in enumerate(self.pairs):
             ni = 2 * self.n_src[i]

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libmfs_hip.so")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["kernels.hip", "precompute.hip", "capi.hip", "gmres.hip"]
+HIP_SOURCES = ["kernels.hip", "precompute.hip", "capi.hip", "gmres.hip", "server.hip"]
 CXX_SOURCES = ["geometry.cpp"]
 
 HIPCC_FLAGS = [
@@ -61,7 +61,7 @@ def build(verbose=False):
     objs = [j[-1] for j in jobs]
     tmp = OUT + ".tmp"
     _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, f"-L{ROCM}/lib",
-          "-lrocsolver", "-lrocblas", f"-Wl,-rpath,{ROCM}/lib"])
+          "-lrocsolver", "-lrocblas", "-pthread", f"-Wl,-rpath,{ROCM}/lib"])
     os.replace(tmp, OUT)
     return OUT
 

@@ -66,6 +66,7 @@ struct mfs_ctx {
   bool own_stream = false;
   rocblas_handle blas = nullptr;
   mfs::Status last;
+  int pre_batch = 0;   // pairs per precompute batch; 0: sized from free device memory
 
   // host geometry
   std::vector<double> centers, radii, r_src;

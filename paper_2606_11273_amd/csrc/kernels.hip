@@ -194,18 +194,21 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
   const double* Yr = ct.Yr[k];
   const double cx = centers[2 * b], cy = centers[2 * b + 1];
   if (bdat) {
-    // net strength of the disk (FP64 sum) and its ring radius squared, for the
-    // compensated log of the FP32 kernel sum
-    double s0x = 0, s0y = 0;
+    // moments of the disk's strengths in FP64 for the FP32 kernel sum: the net
+    // strength S0 = sum_j sigma_j, W = sum_j y_j . sigma_j (y relative to the
+    // centre), and the ring radius squared q = |y_j|^2
+    double s0x = 0, s0y = 0, w = 0;
     for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
       s0x += s_l[2 * j];
       s0y += s_l[2 * j + 1];
+      w += Yr[2 * j] * s_l[2 * j] + Yr[2 * j + 1] * s_l[2 * j + 1];
     }
     s0x = block_sum<kBodyThreads>(s0x, red);
     s0y = block_sum<kBodyThreads>(s0y, red + 16);
+    w = block_sum<kBodyThreads>(w, red + 32);
     if (threadIdx.x == 0) {
       const double q = Yr[0] * Yr[0] + Yr[1] * Yr[1];
-      bdat[b] = make_float4((float)s0x, (float)s0y, (float)q, 0.0f);
+      bdat[b] = make_float4((float)s0x, (float)s0y, (float)q, (float)w);
     }
   }
   for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
@@ -229,12 +232,15 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
 // centre is formed in FP64 and rounded once; the pair terms are evaluated in FP32
 // on body-relative coordinates (v_rcp_f32 for 1/r^2, v_log_f32 for the log) and
 // summed per source disk in FP32; each disk's partial is added to FP64
-// accumulators.  Compensated log: with y the source offset on the ring (|y|^2 = q),
-//   log2 r^2 = log2 R^2 + log2(1 + (q - 2 D.y) / R^2),   R = |D|,
-// so sum_s log2(r_s^2) sigma_s = log2(R^2) S0 + sum_s log2(u_s) sigma_s with S0 the
-// disk's net strength (from the FP64 strengths).  The FP32 rounding of the second
-// sum scales with |u_s - 1| ~ |y|/R instead of |log2 r^2|, so the far-field error
-// of a disk whose strengths nearly cancel shrinks with distance.
+// accumulators.  The disk's field is split so that the FP32 loop only sums parts
+// that shrink with the distance R = |D| as the field itself does, the leading parts
+// coming from FP64 moments of the disk's strengths (S0 = sum sigma, W = sum y.sigma):
+//   log2 r^2 = log2 R^2 + log2(1 + w),  w = (q - 2 D.y) / R^2,  |y|^2 = q,
+// with log2(1 + w) rounded relative to w (not to 1), and
+//   sum_s (d.sigma) / (r^2 / R^2) = D.S0 - W - sum_s w_s (d.sigma)_s / (r_s^2 / R^2).
+// Without this a disk whose strengths nearly cancel (zero net force and torque in
+// the mobility problem) leaves an FP32 error of ~eps_32 |sigma| at every distance,
+// and those errors add up over all disks.
 constexpr int KS_THREADS = 256;
 constexpr int KS_TILE = 1024;   // sources per LDS tile (16 KB of float4)
 constexpr int KS_MAXB = 64;     // bodies per LDS tile
@@ -325,10 +331,10 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
     __syncthreads();
     for (int kk = 0; kk < nb; ++kk) {
       const int kbody = kt + kk;
-      const float4 bd = s_b[kk];   // (S0x, S0y, q = |y|^2, -)
-      // per (target, disk): D = x - c_k (FP64, rounded once), R^2, and the scaled
-      // offsets for u = r^2 / R^2 = 1 + (q - 2 D.y) / R^2
-      float Dx[T], Dy[T], ir2[T], Dxs[T], Dys[T], c0[T], lx[T], ly[T], t0[T], tsx[T], tsy[T];
+      const float4 bd = s_b[kk];   // (S0x, S0y, q = |y|^2, W = sum y . sigma)
+      // per (target, disk): D = x - c_k (FP64, rounded once), R^2 = |D|^2, and the
+      // scaled offsets for w = r^2 / R^2 - 1 = (q - 2 D.y) / R^2
+      float Dx[T], Dy[T], ir2[T], Dxs[T], Dys[T], qs[T], lx[T], ly[T], t0[T], tsx[T], tsy[T];
 #pragma unroll
       for (int j = 0; j < T; ++j) {
         Dx[j] = (float)(x[j] - s_c[2 * kk]);
@@ -336,22 +342,29 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
         ir2[j] = __builtin_amdgcn_rcpf(fmaf(Dx[j], Dx[j], Dy[j] * Dy[j]));
         Dxs[j] = -2.0f * Dx[j] * ir2[j];
         Dys[j] = -2.0f * Dy[j] * ir2[j];
-        c0[j] = fmaf(bd.z, ir2[j], 1.0f);
+        qs[j] = bd.z * ir2[j];
         lx[j] = ly[j] = t0[j] = tsx[j] = tsy[j] = 0.0f;
       }
       const int q1 = s_off[kk + 1];
+#pragma unroll 4
       for (int q = s_off[kk]; q < q1; ++q) {
         const float4 s = s_src[q];
-        const float w = s_w[q];
+        const float wq = s_w[q];
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-          const float u = fmaf(Dxs[j], s.x, fmaf(Dys[j], s.y, c0[j]));   // r^2 / R^2
-          const float lg = __builtin_amdgcn_logf(u);                      // log2(r^2 / R^2)
+          // u = 1 + w = r^2 / R^2.  For a far disk w is small and u = fl(1 + w) loses
+          // the low bits of w: e = w - (u - 1) is that rounding error (exact for
+          // |w| <= 1), and log2(1 + w) = log2(u) + e / (u ln 2) + O(e^2), with the
+          // factor 1/u ~ 1 dropped (an error of e w, below the rounding of log2(u))
+          const float w = fmaf(Dxs[j], s.x, fmaf(Dys[j], s.y, qs[j]));
+          const float u = 1.0f + w;
+          const float e = w - (u - 1.0f);
+          const float lg = fmaf(e, 1.44269504088896341f, __builtin_amdgcn_logf(u));
           const float iu = __builtin_amdgcn_rcpf(u);
-          const float tt = fmaf(Dx[j], s.z, fmaf(Dy[j], s.w, -w)) * iu;   // R^2 (d.sigma) / r^2
+          const float tt = fmaf(Dx[j], s.z, fmaf(Dy[j], s.w, -wq)) * iu;   // R^2 (d.sigma) / r^2
           lx[j] = fmaf(lg, s.z, lx[j]);
           ly[j] = fmaf(lg, s.w, ly[j]);
-          t0[j] += tt;
+          t0[j] = fmaf(tt, w, t0[j]);
           tsx[j] = fmaf(tt, s.x, tsx[j]);
           tsy[j] = fmaf(tt, s.y, tsy[j]);
         }
@@ -359,9 +372,15 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
 #pragma unroll
       for (int j = 0; j < T; ++j) {
         if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
-          // sum_s (d.sigma) d / r^2 = (D sum t - sum t y) / R^2
-          const float tx = ir2[j] * fmaf(Dx[j], t0[j], -tsx[j]);
-          const float ty = ir2[j] * fmaf(Dy[j], t0[j], -tsy[j]);
+          // sum_s (d.sigma) d / r^2 = (D sum_s t_s - sum_s t_s y_s) / R^2 with
+          // t_s = R^2 (d_s.sigma_s) / r_s^2 = a_s / u_s, a_s = D.sigma_s - y_s.sigma_s.
+          // sum_s a_s / u_s = sum_s a_s - sum_s a_s w_s / u_s = D.S0 - W - sum_s t_s w_s:
+          // the leading part comes from the disk's FP64 moments and the FP32 loop
+          // only sums the remainder, which shrinks with the distance like the field
+          const float T0 = fmaf(Dx[j], bd.x, fmaf(Dy[j], bd.y, -bd.w)) - t0[j];
+          const float tx = ir2[j] * fmaf(Dx[j], T0, -tsx[j]);
+          const float ty = ir2[j] * fmaf(Dy[j], T0, -tsy[j]);
+          // sum_s sigma_s ln r_s^2 = S0 ln R^2 + sum_s sigma_s ln u_s
           const float lR = __builtin_amdgcn_logf(fmaf(Dx[j], Dx[j], Dy[j] * Dy[j]));
           ax[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.x, lx[j]), tx);
           ay[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.y, ly[j]), ty);

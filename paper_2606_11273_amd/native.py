@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "MFS_OK", 1: "MFS_ERR_ARG", 2: "MFS_ERR_GEOMETRY", 3: "MFS_ER
 # Exported symbols, in the order of include/mfs.h.
 SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_pairs", "mfs_set_pair_matrices",
            "mfs_get_pair_matrices", "mfs_apply", "mfs_kernel_sum", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
-           "mfs_get_sizes", "mfs_destroy", "mfs_last_error"]
+           "mfs_get_sizes", "mfs_destroy", "mfs_last_error", "mfs_server_create", "mfs_server_footprint",
+           "mfs_server_submit", "mfs_server_wait", "mfs_server_last_error", "mfs_server_destroy"]
 
 
 class MfsParams(C.Structure):
@@ -45,6 +46,18 @@ class MfsSolveInfo(C.Structure):
                 ("ms_rhs", C.c_double), ("ms_iterate", C.c_double), ("ms_post", C.c_double),
                 ("n_pairs", C.c_int64), ("matvecs_fp64", C.c_int32), ("matvecs_mixed", C.c_int32),
                 ("pair_evals", C.c_int64)]
+
+
+class MfsRequest(C.Structure):
+    _fields_ = [("P", C.c_int32), ("centers", C.POINTER(C.c_double)), ("radii", C.POINTER(C.c_double)),
+                ("n_src", C.POINTER(C.c_int32)), ("n_col", C.POINTER(C.c_int32)), ("r_src", C.POINTER(C.c_double)),
+                ("problem", C.c_int), ("precision", C.c_int), ("given", C.POINTER(C.c_double)),
+                ("tol", C.c_double), ("max_iter", C.c_int32)]
+
+
+class MfsTicketInfo(C.Structure):
+    _fields_ = [("ms_queue", C.c_double), ("ms_service", C.c_double), ("ms_total", C.c_double),
+                ("ms_precompute", C.c_double), ("footprint_bytes", C.c_int64), ("solve", MfsSolveInfo)]
 
 
 class MFSError(RuntimeError):
@@ -82,8 +95,15 @@ def lib():
     L.mfs_destroy.argtypes = [vp]
     L.mfs_last_error.argtypes = [vp]
     L.mfs_last_error.restype = C.c_char_p
+    L.mfs_server_create.argtypes = [C.POINTER(vp), C.c_size_t, C.c_int32, C.POINTER(MfsParams)]
+    L.mfs_server_footprint.argtypes = [vp, C.POINTER(MfsRequest), i64p]
+    L.mfs_server_submit.argtypes = [vp, C.POINTER(MfsRequest), i64p]
+    L.mfs_server_wait.argtypes = [vp, C.c_int64, dp, C.POINTER(MfsTicketInfo), C.c_int32]
+    L.mfs_server_last_error.argtypes = [vp]
+    L.mfs_server_last_error.restype = C.c_char_p
+    L.mfs_server_destroy.argtypes = [vp]
     for name in SYMBOLS:
-        if name not in ("mfs_default_params", "mfs_last_error"):
+        if name not in ("mfs_default_params", "mfs_last_error", "mfs_server_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -226,3 +246,68 @@ def mfs_gmres_solve(ctx, problem, precision, rhs, tol, max_iter=500, x0=None, hi
 def mfs_destroy(ctx):
     if ctx:
         lib().mfs_destroy(ctx)
+
+
+# -- serving ----------------------------------------------------------------------------
+
+def mfs_server_create(hbm_budget_bytes=0, max_slots=4, params=None):
+    srv = C.c_void_p()
+    code = lib().mfs_server_create(C.byref(srv), int(hbm_budget_bytes), int(max_slots),
+                                   C.byref(params) if params is not None else None)
+    if code != MFS_OK:
+        raise MFSError(code, "server creation failed")
+    return srv
+
+
+def _request(centers, radii, n_src, n_col, r_src, problem, precision, given, tol, max_iter):
+    """Build an MfsRequest; returns (request, keep-alive arrays)."""
+    centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 2)
+    P = centers.shape[0]
+    arrs = dict(centers=centers,
+                radii=np.ascontiguousarray(np.broadcast_to(radii, (P,)), dtype=np.float64),
+                n_src=np.ascontiguousarray(np.broadcast_to(n_src, (P,)), dtype=np.int32),
+                n_col=np.ascontiguousarray(np.broadcast_to(n_col, (P,)), dtype=np.int32),
+                r_src=np.ascontiguousarray(np.broadcast_to(r_src, (P,)), dtype=np.float64),
+                given=np.ascontiguousarray(given, dtype=np.float64).reshape(P, 3))
+    r = MfsRequest(P, _dp(arrs["centers"]), _dp(arrs["radii"]), _ip(arrs["n_src"]), _ip(arrs["n_col"]),
+                   _dp(arrs["r_src"]), PROBLEMS[problem], PRECISIONS[precision], _dp(arrs["given"]), float(tol),
+                   int(max_iter))
+    return r, arrs
+
+
+def _srv_check(code, srv):
+    if code != MFS_OK:
+        raise MFSError(code, lib().mfs_server_last_error(srv).decode())
+
+
+def mfs_server_footprint(srv, centers, radii, n_src, n_col, r_src, problem, precision, given, tol, max_iter=300):
+    r, keep = _request(centers, radii, n_src, n_col, r_src, problem, precision, given, tol, max_iter)
+    b = C.c_int64()
+    _srv_check(lib().mfs_server_footprint(srv, C.byref(r), C.byref(b)), srv)
+    return b.value
+
+
+def mfs_server_submit(srv, centers, radii, n_src, n_col, r_src, problem, precision, given, tol, max_iter=300):
+    """Queue one solve; returns its ticket."""
+    r, keep = _request(centers, radii, n_src, n_col, r_src, problem, precision, given, tol, max_iter)
+    t = C.c_int64()
+    _srv_check(lib().mfs_server_submit(srv, C.byref(r), C.byref(t)), srv)
+    return t.value
+
+
+def mfs_server_wait(srv, ticket, P, timeout_ms=-1, allow_noconv=False):
+    """Wait for a ticket; returns (out (P, 3), dict of timings and solve figures)."""
+    out = np.zeros((P, 3))
+    info = MfsTicketInfo()
+    code = lib().mfs_server_wait(srv, int(ticket), _dp(out), C.byref(info), int(timeout_ms))
+    if code != MFS_OK and not (allow_noconv and code == MFS_ERR_NOCONV):
+        _srv_check(code, srv)
+    s = info.solve
+    return out, dict(ms_queue=info.ms_queue, ms_service=info.ms_service, ms_total=info.ms_total,
+                     ms_precompute=info.ms_precompute, footprint=info.footprint_bytes, iters=s.iters_total,
+                     outer=s.outer_steps, rel_resid=s.rel_resid, n_pairs=s.n_pairs, pair_evals=s.pair_evals,
+                     status=code)
+
+
+def mfs_server_destroy(srv):
+    lib().mfs_server_destroy(srv)

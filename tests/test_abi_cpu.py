@@ -75,3 +75,15 @@ def test_setup_rejects_bad_arguments_and_overlaps_without_touching_the_device():
     assert L.mfs_setup(C.byref(ctx), 2, dp(c), dp(a), ip(ns), ip(nc), dp(rs), C.byref(p), None) == native.MFS_ERR_ARG
     assert not ctx.value
     assert L.mfs_destroy(None) == native.MFS_OK
+
+
+def test_server_rejects_bad_arguments_without_touching_the_device():
+    native, L = _lib()
+    srv = C.c_void_p()
+    assert L.mfs_server_create(C.byref(srv), 0, 0, None) == native.MFS_ERR_ARG
+    assert L.mfs_server_create(C.byref(srv), 0, 65, None) == native.MFS_ERR_ARG
+    assert L.mfs_server_create(None, 0, 1, None) == native.MFS_ERR_ARG
+    assert not srv.value
+    out = np.zeros(3)
+    assert L.mfs_server_wait(None, 1, out.ctypes.data_as(C.POINTER(C.c_double)), None, 0) == native.MFS_ERR_ARG
+    assert L.mfs_server_destroy(None) == native.MFS_OK

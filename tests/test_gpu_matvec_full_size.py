@@ -1,0 +1,124 @@
+"""Parity of the GPU matvec T mu (Alg. 3) with the FP64 oracle at the full benchmark size.
+
+Workload: P = 10^4 unit disks at area fraction 0.65, min gap 1e-3, contact threshold
+0.2 (about 10^4 close pairs), N_c = 36 on radius 0.7, M_c = 72: 3.6e5 sources and
+7.2e5 collocation points, the launch configuration of the benchmark's matvec.
+
+The input mu is smooth (a rigid motion plus two Fourier modes per disk) and supported on
+a few disks: the two disks of the closest pair, a disk with the most contacts, the first
+and last disk, and random others.  Then lambda_bar vanishes off that support, so only
+pairs touching it have nonzero corrections (steps 1b and 2b), and the oracle needs the
+pair matrices of those pairs alone.  The other pairs' A^c are zero on both sides, which
+leaves T mu unchanged.  The output is compared everywhere: every one of the 1.44e6
+entries holds the far field of the supported disks, so every tile of the all-pairs sum
+is checked.  Both sides use the oracle's A^c (mfs_set_pair_matrices), as in the
+small-size matvec tests; the GPU's own precompute is checked against the oracle
+elsewhere.
+
+Tolerances.  FP64: 2e-11 of max |T mu|, as in the small-size smooth case.  Mixed: the
+FP32 sum differs from the FP64 one by at most 2e-6 m_t at each target t, with
+m_t = sum_s (|log r_ts| + 1) |sigma_s| / (4 pi mu) over the sources the step sums (the
+bound of the kernel-sum tests; every other step is FP64 in both forms).  Relative to
+max |T mu| that is not small here: the support holds the closest pair (gap 1e-3),
+whose compressed strengths lambda_tilde are much larger than mu, and their FP32 near
+field at neighbouring disks that are not contact partners carries eps_32 |lambda_tilde|.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.geometry import contacts, perp
+from oracle.pairs import pair_matrices
+from oracle.params import MFSParams
+from oracle.system import System
+from workloads import config_geometry
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _support(c, pairs, rng, n_random=8):
+    P = c.shape[0]
+    gaps = np.linalg.norm(c[pairs[:, 1]] - c[pairs[:, 0]], axis=1) - 2.0
+    close = pairs[np.argmin(gaps)]
+    deg = np.bincount(pairs.ravel(), minlength=P)
+    chosen = {0, P - 1, int(close[0]), int(close[1]), int(np.argmax(deg))}
+    chosen.update(int(i) for i in rng.choice(P, n_random, replace=False))
+    return np.array(sorted(chosen))
+
+
+def _smooth_mu(S, support, rng):
+    mu = np.zeros(S.n)
+    for i in support:
+        X = S.Xb(i) - S.c[i]
+        th = np.arctan2(X[:, 1], X[:, 0])
+        v, w = rng.standard_normal(2), rng.standard_normal()
+        a2, a3 = rng.standard_normal(2), rng.standard_normal(2)
+        val = v + w * perp(X) + np.outer(np.cos(2 * th), a2) + np.outer(np.sin(3 * th), a3)
+        S.mu_of(mu, i)[:] = val.reshape(-1)
+    return mu
+
+
+@pytest.mark.parametrize("problem", ["mobility", "resistance"])
+def test_matvec_full_size_localised_input(problem):
+    from paper_2606_11273_amd import native as nv
+    g = config_geometry(3)
+    c, a = g["centers"], g["radii"]
+    P = c.shape[0]
+    prm = MFSParams(delta_c=g["delta_c"])
+    pairs = contacts(c, a, prm.delta_c)
+    rng = np.random.default_rng(11)
+    sup = _support(c, pairs, rng)
+    touched = np.isin(pairs, sup).any(axis=1)
+    say(f"matvec full size {problem}: P {P}, pairs {len(pairs)}, support {len(sup)} disks, "
+        f"{int(touched.sum())} pairs touch it")
+    S = System(c, a, g["n_src"], g["n_col"], g["r_src"], problem, prm, pair_data=[None] * len(pairs))
+    assert np.array_equal(S.pairs, pairs)
+    m = 4 * int(g["n_src"][0])
+    zero = {"A": np.zeros((m, m)), "E": np.zeros((6, m))}
+    for p in range(len(pairs)):
+        i, k = pairs[p]
+        S.pd[p] = pair_matrices(S.c[i], S.c[k], S.cls[i], prm) if touched[p] else zero
+    mu = _smooth_mu(S, sup, rng)
+    say("  oracle matvec")
+    ref = S.matvec(mu)
+
+    gp = nv.mfs_default_params()
+    gp.delta_c = g["delta_c"]
+    ctx = nv.mfs_setup(c, a, g["n_src"], g["n_col"], g["r_src"], gp)
+    try:
+        assert np.array_equal(nv.mfs_get_pairs(ctx), pairs.astype(np.int32))
+        nv.mfs_set_pair_matrices(ctx, problem, [d["A"] for d in S.pd], [d["E"] for d in S.pd])
+        dmu = torch.tensor(mu, device="cuda")
+        scale = np.abs(ref).max()
+        out = {}
+        for prec in ("fp64", "mixed"):
+            u = torch.zeros_like(dmu)
+            nv.mfs_apply(ctx, problem, prec, dmu, u)
+            torch.cuda.synchronize()
+            out[prec] = u.cpu().numpy()
+    finally:
+        nv.mfs_destroy(ctx)
+    e64 = np.abs(out["fp64"] - ref).max() / scale
+    d32 = np.abs(out["mixed"] - out["fp64"]).reshape(-1, 2).max(1)
+    mag = _magnitude(S, mu)
+    say(f"  fp64: max |T mu - ref| / max |ref| = {e64:.2e}; mixed: {np.abs(out['mixed'] - ref).max() / scale:.2e} "
+        f"of max |ref|, max_t |mixed - fp64| / m_t = {(d32 / mag).max():.2e}")
+    assert e64 <= 2e-11
+    assert np.all(d32 <= 2e-6 * mag)
+
+
+def _magnitude(S, mu):
+    """m_t = sum_s (|log r_ts| + 1) |sigma_s| / (4 pi mu) over the nonzero strengths of step 2a."""
+    _, lam, _ = S.step1(mu)
+    sig = S.sigma(lam).reshape(-1, 2)
+    nz = np.any(sig != 0.0, axis=1)
+    Y, sabs = S.Y[nz], np.abs(sig[nz]).sum(1)
+    mag = np.empty(S.X.shape[0])
+    blk = max(1, 4_000_000 // max(1, Y.shape[0]))
+    for t0 in range(0, S.X.shape[0], blk):
+        d = S.X[t0:t0 + blk, None, :] - Y[None, :, :]
+        r = np.sqrt((d ** 2).sum(-1))
+        mag[t0:t0 + blk] = ((np.abs(np.log(r)) + 1.0) * sabs[None, :]).sum(1)
+    return mag / (4 * np.pi * S.prm.mu)

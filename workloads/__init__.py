@@ -21,3 +21,8 @@ from .rhs import (  # noqa: F401
     resistance_rhs,
     unit_torques,
 )
+from .serving import (  # noqa: F401
+    serving_request,
+    poisson_arrivals,
+    SERVING_SEED_BASE,
+)
