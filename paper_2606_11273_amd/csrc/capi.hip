@@ -54,7 +54,8 @@ void free_all(mfs_ctx* c) {
                   c->d_lam_bar, c->d_ltil,    c->d_sig64, c->d_u,        c->d_corr,   c->d_upart,  c->d_epair,
                   c->d_out3,    c->d_given,   c->d_sig32, c->d_src64,    c->ps[0].A,  c->ps[0].E,  c->ps[1].A,
                   c->ps[1].E,   c->kr.V,      c->kr.w,    c->kr.part,    c->kr.hdev,  c->kr.x,     c->kr.r,
-                  c->kr.b,      c->kr.d,      c->kr.tmp};
+                  c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
+                  c->d_sig32m,  c->d_bdatm,   c->d_src64m};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->kr.hhost) (void)hipHostFree(c->kr.hhost);
@@ -226,6 +227,73 @@ Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u) {
   return check_kernel_sum(c, ks);
 }
 
+// Stacked buffers for R right-hand sides.
+Status ensure_stacked(mfs_ctx* c, int R) {
+  if (c->rhs_cap >= R) return Status{};
+  for (void* p : {(void*)c->d_lam_bar_m, (void*)c->d_ltil_m, (void*)c->d_u_m, (void*)c->d_corr_m,
+                  (void*)c->d_sig32m, (void*)c->d_bdatm, (void*)c->d_src64m})
+    if (p) (void)hipFree(p);
+  c->d_lam_bar_m = c->d_ltil_m = c->d_u_m = c->d_corr_m = nullptr;
+  c->d_sig32m = c->d_bdatm = nullptr;
+  c->d_src64m = nullptr;
+  c->rhs_cap = 0;
+  const int C = (int)(c->pairs.size() / 2);
+  Status st;
+  if ((st = dalloc(&c->d_lam_bar_m, (size_t)R * 2 * c->Ns)).code) return st;
+  if ((st = dalloc(&c->d_ltil_m, (size_t)R * c->xoff[C])).code) return st;
+  if ((st = dalloc(&c->d_u_m, (size_t)R * 2 * c->Nt)).code) return st;
+  if ((st = dalloc(&c->d_corr_m, (size_t)R * c->coff[C])).code) return st;
+  if ((st = dalloc(&c->d_sig32m, (size_t)R * c->Ns)).code) return st;
+  if ((st = dalloc(&c->d_bdatm, (size_t)R * c->P)).code) return st;
+  if ((st = dalloc(&c->d_src64m, (size_t)R * c->Ns)).code) return st;
+  c->rhs_cap = R;
+  return Status{};
+}
+
+Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, double* u) {
+  const int64_t n = 2 * c->Nt;
+  int max_src = 0;
+  for (int i = 0; i < c->P; ++i) max_src = std::max(max_src, c->n_src[i]);
+  // stacked kernels take 8, 4 or 2 vectors; a remainder of one goes through apply_T
+  int r0 = 0;
+  while (r0 < R) {
+    const int left = R - r0;
+    const int Rc = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    if (Rc == 1 || max_src > 256) {
+      Status st = apply_T(c, prob, mixed, mu + r0 * n, u + r0 * n);
+      if (st.code) return st;
+      r0 += 1;
+      continue;
+    }
+    Status st = ensure_stacked(c, 8);
+    if (st.code) return st;
+    const bool wp = c->pairs.size() > 0;
+    const int C = (int)(c->pairs.size() / 2);
+    const int64_t ns2 = 2 * c->Ns, nx = c->xoff[C], nc = c->coff[C];
+    for (int r = 0; r < Rc; ++r) launch_onebody_apply(c, prob, mu + (r0 + r) * n, c->d_lam_bar_m + r * ns2);
+    if (wp && !launch_pair_A_rhs(c, prob, Rc, c->d_lam_bar_m, ns2, c->d_ltil_m, nx))
+      for (int r = 0; r < Rc; ++r) launch_pair_A(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx);
+    for (int r = 0; r < Rc; ++r)
+      launch_gather_project_to(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx, wp,
+                               mixed ? c->d_sig32m + r * c->Ns : nullptr, mixed ? nullptr : c->d_src64m + r * c->Ns,
+                               mixed ? c->d_bdatm + (int64_t)r * c->P : nullptr);
+    const bool ks = launch_kernel_sum_rhs(c, mixed, 2, Rc, c->d_u_m, 1.0 / (4.0 * kPiD * c->prm.mu));
+    if ((st = check_kernel_sum(c, ks)).code) return st;
+    c->cnt_pair_evals += (int64_t)Rc * c->evals_skip;
+    if (mixed)
+      c->cnt_mv32 += Rc;
+    else
+      c->cnt_mv64 += Rc;
+    for (int r = 0; r < Rc; ++r) {
+      if (wp) launch_pair_field(c, prob, c->d_ltil_m + r * nx, c->d_corr_m + r * nc);
+      launch_finish(c, c->d_u_m + r * n, mu + (r0 + r) * n, c->d_corr_m + r * nc, u + (r0 + r) * n, wp);
+    }
+    MFS_HIP(hipGetLastError());
+    r0 += Rc;
+  }
+  return Status{};
+}
+
 }  // namespace mfs
 
 // ---------------------------------------------------------------------------
@@ -375,11 +443,8 @@ mfs_status mfs_apply(mfs_ctx* c, mfs_problem prob, mfs_precision prec, int32_t n
     return fail(c, Status{MFS_ERR_ARG, "bad argument"});
   if (!c->ps[prob].ready && !c->pairs.empty())
     return fail(c, Status{MFS_ERR_STATE, "mfs_precompute_pairs has not run for this problem"});
-  const int64_t n = 2 * c->Nt;
-  for (int r = 0; r < n_rhs; ++r) {
-    Status st = apply_T(c, prob, prec == MFS_MIXED, mu_in + r * n, u_out + r * n);
-    if (st.code) return fail(c, st);
-  }
+  Status st = apply_T_rhs(c, prob, prec == MFS_MIXED, n_rhs, mu_in, u_out);
+  if (st.code) return fail(c, st);
   return ok(c);
 }
 

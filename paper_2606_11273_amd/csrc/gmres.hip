@@ -24,6 +24,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -34,27 +37,28 @@ namespace {
 using clk = std::chrono::steady_clock;
 double ms_since(clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); }
 
-Status ensure_krylov(mfs_ctx* c, int cap) {
+Status ensure_krylov(mfs_ctx* c, int cap, int R) {
   Krylov& k = c->kr;
   const int64_t n = 2 * c->Nt;
-  if (k.V && k.cap >= cap && k.n == n) return Status{};
-  if (k.V) (void)hipFree(k.V);
-  if (k.part) (void)hipFree(k.part);
-  if (k.hdev) (void)hipFree(k.hdev);
+  if (k.V && k.cap >= cap && k.rcap >= R && k.n == n) return Status{};
+  for (double** p : {&k.V, &k.part, &k.hdev, &k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp})
+    if (*p) (void)hipFree(*p);
   if (k.hhost) (void)hipHostFree(k.hhost);
-  k.V = k.part = k.hdev = k.hhost = nullptr;
-  for (double** p : {&k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp})
-    if (!*p) MFS_HIP(hipMalloc((void**)p, sizeof(double) * n));
-  if (hipMalloc((void**)&k.V, sizeof(double) * n * (cap + 1)) != hipSuccess) {
+  k.V = k.part = k.hdev = k.hhost = k.w = k.x = k.r = k.b = k.d = k.tmp = nullptr;
+  k.cap = k.rcap = 0;
+  for (double** p : {&k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp}) MFS_HIP(hipMalloc((void**)p, sizeof(double) * n * R));
+  if (hipMalloc((void**)&k.V, sizeof(double) * n * R * (cap + 1)) != hipSuccess) {
     (void)hipGetLastError();
     k.V = nullptr;
-    return Status{MFS_ERR_OOM, "Krylov basis of " + std::to_string(cap + 1) + " vectors does not fit"};
+    return Status{MFS_ERR_OOM, "Krylov basis of " + std::to_string(cap + 1) + " x " + std::to_string(R) +
+                                   " vectors does not fit"};
   }
   const int nblk = mdot_blocks(n);
   MFS_HIP(hipMalloc((void**)&k.part, sizeof(double) * nblk * (cap + 2)));
-  MFS_HIP(hipMalloc((void**)&k.hdev, sizeof(double) * 3 * (cap + 2)));
-  MFS_HIP(hipHostMalloc((void**)&k.hhost, sizeof(double) * 3 * (cap + 2), hipHostMallocDefault));
+  MFS_HIP(hipMalloc((void**)&k.hdev, sizeof(double) * 3 * (cap + 2) * R));
+  MFS_HIP(hipHostMalloc((void**)&k.hhost, sizeof(double) * 3 * (cap + 2) * R, hipHostMallocDefault));
   k.cap = cap;
+  k.rcap = R;
   k.n = n;
   return Status{};
 }
@@ -148,6 +152,129 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, double switch_below, const d
   return Status{};
 }
 
+// Lockstep GMRES for R right-hand sides (the stacked form of gmres_core): every right-hand
+// side keeps its own Krylov basis, Hessenberg matrix and Givens rotations; each step
+// applies the operator to the R newest basis vectors at once (apply_T_rhs), so the
+// all-pairs sum and the pair matrices are read once for all of them.  A right-hand side
+// whose estimate reaches its tolerance is frozen (its slot is fed zeros).  The mixed
+// kernel sum is used once every active right-hand side is below its switch point.
+// r, d: R x n; tol, switch_below: R; iters: R.
+Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* switch_below, const double* r,
+                      const double* tol, const bool* active_in, int maxit, int* iters,
+                      std::vector<std::vector<double>>& hist) {
+  Krylov& k = c->kr;
+  const int64_t n = k.n;
+  const int64_t ldv = (int64_t)R * n;
+  const int nblk = mdot_blocks(n);
+  const int cap = k.cap;
+  const int64_t hstride = 3 * (int64_t)(cap + 2);
+  Status st;
+  std::vector<double> beta(R, 0.0), rel(R, 1.0);
+  std::vector<char> active(R, 0);
+  std::vector<int> kdone(R, 0);
+  std::vector<std::vector<double>> H(R), cs(R), sn(R), g(R);
+  MFS_HIP(hipMemsetAsync(k.d, 0, sizeof(double) * n * R, c->stream));
+  MFS_HIP(hipMemsetAsync(k.V, 0, sizeof(double) * ldv, c->stream));
+  for (int q = 0; q < R; ++q) {
+    iters[q] = 0;
+    if (!active_in[q]) continue;
+    beta[q] = dnorm(c, r + q * n, &st);
+    if (st.code) return st;
+    if (!std::isfinite(beta[q])) return Status{MFS_ERR_NUMERIC, "non-finite residual"};
+    if (beta[q] == 0.0) continue;
+    active[q] = 1;
+    launch_scale_copy(c->stream, n, 1.0 / beta[q], r + q * n, k.V + q * n);
+    H[q].assign((size_t)(maxit + 1) * maxit, 0.0);
+    cs[q].assign(maxit, 0.0);
+    sn[q].assign(maxit, 0.0);
+    g[q].assign(maxit + 1, 0.0);
+    g[q][0] = beta[q];
+  }
+  const bool prof = std::getenv("MFS_PROFILE") != nullptr;
+  auto t_start = clk::now();
+  for (int j = 0; j < maxit; ++j) {
+    bool any = false, all_low = true;
+    for (int q = 0; q < R; ++q)
+      if (active[q]) {
+        any = true;
+        if (rel[q] > switch_below[q]) all_low = false;
+      }
+    if (!any) break;
+    const bool use32 = mixed && all_low;
+    double* vj = k.V + (int64_t)j * ldv;
+    if ((st = apply_T_rhs(c, prob, use32, R, vj, k.w)).code) return st;
+    for (int q = 0; q < R; ++q) {
+      if (!active[q]) continue;
+      const double* Vq = k.V + q * n;
+      double* wq = k.w + q * n;
+      double* hq = k.hdev + q * hstride;
+      launch_mdot(c->stream, n, j + 1, Vq, ldv, wq, k.part, hq, nblk);
+      launch_maxpy(c->stream, n, j + 1, Vq, ldv, hq, wq);
+      launch_mdot(c->stream, n, j + 1, Vq, ldv, wq, k.part, hq + (cap + 2), nblk);
+      launch_maxpy(c->stream, n, j + 1, Vq, ldv, hq + (cap + 2), wq);
+      launch_mdot(c->stream, n, 1, wq, n, wq, k.part, hq + 2 * (cap + 2), nblk);
+    }
+    MFS_HIP(hipMemcpyAsync(k.hhost, k.hdev, sizeof(double) * hstride * R, hipMemcpyDeviceToHost, c->stream));
+    MFS_HIP(hipStreamSynchronize(c->stream));
+    double* vn = k.V + (int64_t)(j + 1) * ldv;
+    for (int q = 0; q < R; ++q) {
+      if (!active[q]) {
+        MFS_HIP(hipMemsetAsync(vn + q * n, 0, sizeof(double) * n, c->stream));
+        continue;
+      }
+      const double* hh = k.hhost + q * hstride;
+      auto Hc = [&](int row, int col) -> double& { return H[q][(size_t)col * (maxit + 1) + row]; };
+      for (int i = 0; i <= j; ++i) Hc(i, j) = hh[i] + hh[(cap + 2) + i];
+      const double hn = std::sqrt(std::max(0.0, hh[2 * (cap + 2)]));
+      Hc(j + 1, j) = hn;
+      for (int i = 0; i <= j + 1; ++i)
+        if (!std::isfinite(Hc(i, j))) return Status{MFS_ERR_NUMERIC, "non-finite value in the Arnoldi process"};
+      if (hn > 0.0)
+        launch_scale_copy(c->stream, n, 1.0 / hn, k.w + q * n, vn + q * n);
+      else
+        MFS_HIP(hipMemsetAsync(vn + q * n, 0, sizeof(double) * n, c->stream));
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[q][i] * Hc(i, j) + sn[q][i] * Hc(i + 1, j);
+        Hc(i + 1, j) = -sn[q][i] * Hc(i, j) + cs[q][i] * Hc(i + 1, j);
+        Hc(i, j) = t;
+      }
+      const double den = std::hypot(Hc(j, j), Hc(j + 1, j));
+      cs[q][j] = Hc(j, j) / den;
+      sn[q][j] = Hc(j + 1, j) / den;
+      Hc(j, j) = den;
+      Hc(j + 1, j) = 0.0;
+      g[q][j + 1] = -sn[q][j] * g[q][j];
+      g[q][j] = cs[q][j] * g[q][j];
+      kdone[q] = j + 1;
+      rel[q] = std::fabs(g[q][j + 1]) / beta[q];
+      hist[q].push_back(rel[q]);
+      if (std::fabs(g[q][j + 1]) <= tol[q] * beta[q] || hn == 0.0) active[q] = 0;
+    }
+    if (prof && ((j + 1) % 10 == 0)) {
+      double worst = 0;
+      for (int q = 0; q < R; ++q) worst = std::max(worst, active[q] ? rel[q] : 0.0);
+      std::fprintf(stderr, "[mfs gmres x%d] %s it %d worst active resid %.3e  %.1f s\n", R,
+                   use32 ? "fp32-sum" : "fp64", j + 1, worst, ms_since(t_start) * 1e-3);
+    }
+  }
+  for (int q = 0; q < R; ++q) {
+    iters[q] = kdone[q];
+    if (kdone[q] == 0) continue;
+    auto Hc = [&](int row, int col) -> double& { return H[q][(size_t)col * (maxit + 1) + row]; };
+    std::vector<double> y(kdone[q]);
+    for (int i = kdone[q] - 1; i >= 0; --i) {
+      double sum = g[q][i];
+      for (int p = i + 1; p < kdone[q]; ++p) sum -= Hc(i, p) * y[p];
+      y[i] = sum / Hc(i, i);
+    }
+    double* hq = k.hdev + q * hstride;
+    MFS_HIP(hipMemcpyAsync(hq, y.data(), sizeof(double) * kdone[q], hipMemcpyHostToDevice, c->stream));
+    launch_gemv_n(c->stream, n, kdone[q], k.V + q * n, ldv, hq, k.d + q * n);
+    MFS_HIP(hipStreamSynchronize(c->stream));   // y is released at the end of this scope
+  }
+  return Status{};
+}
+
 // Relaxation parameter delta of the inner GMRES: operator applications switch from
 // the FP64 to the mixed kernel sum once the residual estimate is below tol_inner /
 // delta.  In the inexact-Krylov bound (Simoncini & Szyld 2003) delta stands for the
@@ -164,6 +291,163 @@ double mixed_delta() {
 
 }  // namespace
 
+namespace {
+
+struct SolveTotals {
+  int iters = 0, outer = 0, hist_len = 0;
+  double rel = 0, t_rhs = 0, t_it = 0, t_post = 0;
+  bool noconv = false;
+};
+
+// One right-hand side: FP64 refinement around gmres_core (see the file comment).
+Status solve_one(mfs_ctx* c, int prob, bool mixed, const double* given, double* out, const double* x0, double tol,
+                 int max_iter, mfs_solve_info* info, SolveTotals& tot) {
+  Krylov& k = c->kr;
+  const int64_t n = k.n;
+  Status st;
+  auto t0 = clk::now();
+  mfs_status s = mfs_rhs(c, (mfs_problem)prob, given, k.b);
+  if (s != MFS_OK) return c->last;
+  tot.t_rhs += ms_since(t0);
+  t0 = clk::now();
+  const double bn = dnorm(c, k.b, &st);
+  if (st.code) return st;
+  if (x0)
+    MFS_HIP(hipMemcpyAsync(k.x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  else
+    MFS_HIP(hipMemsetAsync(k.x, 0, sizeof(double) * n, c->stream));
+  std::vector<double> hist;
+  const int max_outer = mixed ? 10 : 3;
+  int used = 0;
+  double rel = 1.0;
+  for (int o = 0; o < max_outer; ++o) {
+    // r = b - T64 x
+    if (o == 0 && !x0) {
+      MFS_HIP(hipMemcpyAsync(k.r, k.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      if ((st = apply_T(c, prob, false, k.x, k.tmp)).code) return st;
+      MFS_HIP(hipMemcpyAsync(k.r, k.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+      launch_axpby(c->stream, n, -1.0, k.tmp, 1.0, k.r);
+    }
+    const double rn = dnorm(c, k.r, &st);
+    if (st.code) return st;
+    if (!std::isfinite(rn)) return Status{MFS_ERR_NUMERIC, "non-finite residual"};
+    rel = bn > 0 ? rn / bn : 0.0;
+    if (rel <= tol || used >= max_iter) break;
+    tot.outer = std::max(tot.outer, o + 1);
+    // reach the target in one pass if the operator allows it
+    const double tin = tol * bn / rn;
+    const double switch_below = mixed ? std::min(1.0, tin / mixed_delta()) : 0.0;
+    if (std::getenv("MFS_PROFILE"))
+      std::fprintf(stderr, "[mfs gmres] refinement %d: |r|/|b| = %.3e, inner tol %.3e, mixed below %.3e\n", o, rel,
+                   tin, switch_below);
+    int it = 0;
+    if ((st = gmres_core(c, prob, mixed, switch_below, k.r, tin, max_iter - used, &it, hist)).code) return st;
+    used += it;
+    launch_axpby(c->stream, n, 1.0, k.d, 1.0, k.x);
+    if (it == 0) break;
+  }
+  tot.iters += used;
+  tot.t_it += ms_since(t0);
+  t0 = clk::now();
+  s = mfs_post(c, (mfs_problem)prob, k.x, out);
+  if (s != MFS_OK) return c->last;
+  tot.t_post += ms_since(t0);
+  if (info && info->resid_hist && info->hist_cap > 0)
+    for (double h : hist)
+      if (tot.hist_len < info->hist_cap) info->resid_hist[tot.hist_len++] = h;
+  tot.rel = std::max(tot.rel, rel);
+  if (rel > tol) tot.noconv = true;
+  return Status{};
+}
+
+// R right-hand sides in lockstep (2 <= R <= Krylov rcap): the refinement of solve_one
+// with stacked residuals and gmres_core_rhs; each right-hand side stops on its own.
+Status solve_stacked(mfs_ctx* c, int prob, bool mixed, int R, const double* given, double* out, const double* x0,
+                     double tol, int max_iter, mfs_solve_info* info, SolveTotals& tot) {
+  Krylov& k = c->kr;
+  const int64_t n = k.n;
+  Status st;
+  auto t0 = clk::now();
+  for (int q = 0; q < R; ++q)
+    if (mfs_rhs(c, (mfs_problem)prob, given + 3 * (size_t)c->P * q, k.b + q * n) != MFS_OK) return c->last;
+  tot.t_rhs += ms_since(t0);
+  t0 = clk::now();
+  std::vector<double> bn(R), rel(R, 1.0), tin(R), sw(R);
+  for (int q = 0; q < R; ++q) {
+    bn[q] = dnorm(c, k.b + q * n, &st);
+    if (st.code) return st;
+  }
+  if (x0)
+    MFS_HIP(hipMemcpyAsync(k.x, x0, sizeof(double) * n * R, hipMemcpyDeviceToDevice, c->stream));
+  else
+    MFS_HIP(hipMemsetAsync(k.x, 0, sizeof(double) * n * R, c->stream));
+  std::vector<std::vector<double>> hist(R);
+  std::vector<int> used(R, 0), it(R, 0);
+  std::unique_ptr<bool[]> act(new bool[R]);
+  const int max_outer = mixed ? 10 : 3;
+  for (int o = 0; o < max_outer; ++o) {
+    if (o == 0 && !x0) {
+      MFS_HIP(hipMemcpyAsync(k.r, k.b, sizeof(double) * n * R, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      if ((st = apply_T_rhs(c, prob, false, R, k.x, k.tmp)).code) return st;
+      MFS_HIP(hipMemcpyAsync(k.r, k.b, sizeof(double) * n * R, hipMemcpyDeviceToDevice, c->stream));
+      launch_axpby(c->stream, n * R, -1.0, k.tmp, 1.0, k.r);
+    }
+    bool any = false;
+    for (int q = 0; q < R; ++q) {
+      const double rn = dnorm(c, k.r + q * n, &st);
+      if (st.code) return st;
+      if (!std::isfinite(rn)) return Status{MFS_ERR_NUMERIC, "non-finite residual"};
+      rel[q] = bn[q] > 0 ? rn / bn[q] : 0.0;
+      act[q] = rel[q] > tol && used[q] < max_iter;
+      if (act[q]) {
+        any = true;
+        tin[q] = tol * bn[q] / rn;
+        sw[q] = mixed ? std::min(1.0, tin[q] / mixed_delta()) : 0.0;
+      } else {
+        tin[q] = 1.0;
+        sw[q] = 1.0;
+      }
+    }
+    if (!any) break;
+    tot.outer = std::max(tot.outer, o + 1);
+    if (std::getenv("MFS_PROFILE")) {
+      double worst = 0;
+      for (int q = 0; q < R; ++q) worst = std::max(worst, rel[q]);
+      std::fprintf(stderr, "[mfs gmres x%d] refinement %d: worst |r|/|b| = %.3e\n", R, o, worst);
+    }
+    int room = max_iter;
+    for (int q = 0; q < R; ++q)
+      if (act[q]) room = std::min(room, max_iter - used[q]);
+    if ((st = gmres_core_rhs(c, prob, mixed, R, sw.data(), k.r, tin.data(), act.get(), room, it.data(), hist)).code)
+      return st;
+    int most = 0;
+    for (int q = 0; q < R; ++q) {
+      used[q] += it[q];
+      most = std::max(most, it[q]);
+    }
+    launch_axpby(c->stream, n * R, 1.0, k.d, 1.0, k.x);
+    if (most == 0) break;
+  }
+  for (int q = 0; q < R; ++q) tot.iters += used[q];
+  tot.t_it += ms_since(t0);
+  t0 = clk::now();
+  for (int q = 0; q < R; ++q)
+    if (mfs_post(c, (mfs_problem)prob, k.x + q * n, out + 3 * (size_t)c->P * q) != MFS_OK) return c->last;
+  tot.t_post += ms_since(t0);
+  for (int q = 0; q < R; ++q) {
+    if (info && info->resid_hist && info->hist_cap > 0)
+      for (double h : hist[q])
+        if (tot.hist_len < info->hist_cap) info->resid_hist[tot.hist_len++] = h;
+    tot.rel = std::max(tot.rel, rel[q]);
+    if (rel[q] > tol) tot.noconv = true;
+  }
+  return Status{};
+}
+
+}  // namespace
+
 extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precision prec, int32_t n_rhs,
                                       const double* rhs, double* out, const double* x0, double tol,
                                       int32_t max_iter, mfs_solve_info* info) {
@@ -172,102 +456,48 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
     c->last = st;
     return st.code;
   };
-#define MFS_HIP_CALL_OR(call)                                                        \
-  do {                                                                               \
-    hipError_t e_ = (call);                                                          \
-    if (e_ != hipSuccess) return failc(Status{MFS_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}); \
-  } while (0)
   if ((prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || (prec != MFS_FP64 && prec != MFS_MIXED) || n_rhs < 1 ||
       !rhs || !out || !(tol > 0) || max_iter < 1 || max_iter > 1000)
     return failc(Status{MFS_ERR_ARG, "bad argument (1 <= max_iter <= 1000, tol > 0)"});
   if (!c->ps[prob].ready && !c->pairs.empty())
     return failc(Status{MFS_ERR_STATE, "mfs_precompute_pairs has not run for this problem"});
-  Status st = ensure_krylov(c, max_iter);
+  // right-hand sides run in lockstep groups of up to kLockstep
+  constexpr int kLockstep = 8;
+  const int R = std::min<int>(n_rhs, kLockstep);
+  Status st = ensure_krylov(c, max_iter, R);
   if (st.code) return failc(st);
-  Krylov& k = c->kr;
-  const int64_t n = k.n;
-  mfs_status result = MFS_OK;
-  double t_rhs = 0, t_it = 0, t_post = 0;
-  int iters_total = 0, outer = 0, hist_len = 0;
-  double rel = 0;
+  const int64_t n = c->kr.n;
+  const bool mixed = prec == MFS_MIXED;
   c->cnt_pair_evals = 0;
   c->cnt_mv64 = c->cnt_mv32 = 0;
-  for (int rr = 0; rr < n_rhs; ++rr) {
-    auto t0 = clk::now();
-    mfs_status s = mfs_rhs(c, prob, rhs + 3 * (size_t)c->P * rr, k.b);
-    if (s != MFS_OK) return s;
-    t_rhs += ms_since(t0);
-    t0 = clk::now();
-    const double bn = dnorm(c, k.b, &st);
+  SolveTotals tot;
+  for (int r0 = 0; r0 < n_rhs; r0 += R) {
+    const int Rc = std::min(R, n_rhs - r0);
+    const double* g = rhs + 3 * (size_t)c->P * r0;
+    double* o = out + 3 * (size_t)c->P * r0;
+    const double* x = x0 ? x0 + n * r0 : nullptr;
+    st = Rc == 1 ? solve_one(c, prob, mixed, g, o, x, tol, max_iter, info, tot)
+                 : solve_stacked(c, prob, mixed, Rc, g, o, x, tol, max_iter, info, tot);
     if (st.code) return failc(st);
-    if (x0)
-      MFS_HIP_CALL_OR(hipMemcpyAsync(k.x, x0 + n * rr, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-    else
-      MFS_HIP_CALL_OR(hipMemsetAsync(k.x, 0, sizeof(double) * n, c->stream));
-    std::vector<double> hist;
-    const bool mixed = prec == MFS_MIXED;
-    // outer refinement (a single pass for FP64 with x0 = 0)
-    const int max_outer = mixed ? 10 : 3;
-    int used = 0;
-    rel = 1.0;
-    for (int o = 0; o < max_outer; ++o) {
-      // r = b - T64 x
-      if (o == 0 && !x0) {
-        MFS_HIP_CALL_OR(hipMemcpyAsync(k.r, k.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-      } else {
-        if ((st = apply_T(c, prob, false, k.x, k.tmp)).code) return failc(st);
-        MFS_HIP_CALL_OR(hipMemcpyAsync(k.r, k.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-        launch_axpby(c->stream, n, -1.0, k.tmp, 1.0, k.r);
-      }
-      const double rn = dnorm(c, k.r, &st);
-      if (st.code) return failc(st);
-      if (!std::isfinite(rn)) return failc(Status{MFS_ERR_NUMERIC, "non-finite residual"});
-      rel = bn > 0 ? rn / bn : 0.0;
-      if (rel <= tol || used >= max_iter) break;
-      ++outer;
-      // reach the target in one pass if the operator allows it
-      const double tin = tol * bn / rn;
-      const double switch_below = mixed ? std::min(1.0, tin / mixed_delta()) : 0.0;
-      if (std::getenv("MFS_PROFILE"))
-        std::fprintf(stderr, "[mfs gmres] refinement %d: |r|/|b| = %.3e, inner tol %.3e, mixed below %.3e\n", o, rel,
-                     tin, switch_below);
-      int it = 0;
-      if ((st = gmres_core(c, prob, mixed, switch_below, k.r, tin, max_iter - used, &it, hist)).code)
-        return failc(st);
-      used += it;
-      launch_axpby(c->stream, n, 1.0, k.d, 1.0, k.x);
-      if (it == 0) break;
-    }
-    iters_total += used;
-    t_it += ms_since(t0);
-    t0 = clk::now();
-    s = mfs_post(c, prob, k.x, out + 3 * (size_t)c->P * rr);
-    if (s != MFS_OK) return s;
-    t_post += ms_since(t0);
-    if (info && info->resid_hist && info->hist_cap > 0) {
-      for (double h : hist)
-        if (hist_len < info->hist_cap) info->resid_hist[hist_len++] = h;
-    }
-    if (rel > tol) result = MFS_ERR_NOCONV;
   }
   if (info) {
-    info->iters_total = iters_total;
-    info->outer_steps = outer;
-    info->rel_resid = rel;
-    info->hist_len = hist_len;
-    info->ms_rhs = t_rhs;
-    info->ms_iterate = t_it;
-    info->ms_post = t_post;
+    info->iters_total = tot.iters;
+    info->outer_steps = tot.outer;
+    info->rel_resid = tot.rel;
+    info->hist_len = tot.hist_len;
+    info->ms_rhs = tot.t_rhs;
+    info->ms_iterate = tot.t_it;
+    info->ms_post = tot.t_post;
     info->n_pairs = (int64_t)(c->pairs.size() / 2);
     info->matvecs_fp64 = c->cnt_mv64;
     info->matvecs_mixed = c->cnt_mv32;
     info->pair_evals = c->cnt_pair_evals;
   }
-  if (result != MFS_OK) {
+  if (tot.noconv) {
     char buf[64];
-    std::snprintf(buf, sizeof(buf), "%.3e", rel);
-    c->last = Status{result, std::string("GMRES stopped above tolerance (relative residual ") + buf + ")"};
-    return result;
+    std::snprintf(buf, sizeof(buf), "%.3e", tot.rel);
+    c->last = Status{MFS_ERR_NOCONV, std::string("GMRES stopped above tolerance (relative residual ") + buf + ")"};
+    return MFS_ERR_NOCONV;
   }
   c->last = Status{};
   return MFS_OK;

@@ -41,16 +41,17 @@ struct PairSet {
   double* E = nullptr;   // per pair column-major (6 x n), offset 6 * xoff[c]
 };
 
-// GMRES work space, sized on first use.
+// GMRES work space, sized on first use, for up to rcap right-hand sides in lockstep.
 struct Krylov {
   int64_t n = 0;
-  int cap = 0;           // basis vectors allocated
-  double* V = nullptr;   // n x cap, column j at V + j n
+  int cap = 0;           // basis vectors allocated per right-hand side
+  int rcap = 0;          // right-hand sides
+  double* V = nullptr;   // n x rcap x (cap + 1): vector j of right-hand side r at V + (j rcap + r) n
   double* w = nullptr;
   double* part = nullptr;    // partial dot products
   double* hdev = nullptr;    // reduced dots
   double* hhost = nullptr;   // pinned host mirror
-  double* x = nullptr;
+  double* x = nullptr;    // the vectors below hold rcap x n doubles
   double* r = nullptr;
   double* b = nullptr;
   double* d = nullptr;
@@ -100,6 +101,13 @@ struct mfs_ctx {
   double4* d_src64 = nullptr;    // per source: (y_x, y_y, sigma_x, sigma_y)
   int64_t upart_cap = 0;
 
+  // stacked right-hand sides of the matvec (allocated on first use for rhs_cap vectors)
+  int rhs_cap = 0;
+  double *d_lam_bar_m = nullptr, *d_ltil_m = nullptr, *d_u_m = nullptr, *d_corr_m = nullptr;
+  float4* d_sig32m = nullptr;    // rhs_cap arrays of Ns records
+  float4* d_bdatm = nullptr;     // rhs_cap arrays of P records
+  double4* d_src64m = nullptr;   // rhs_cap arrays of Ns records
+
   mfs::PairSet ps[2];
   mfs::Krylov kr;
 
@@ -116,6 +124,12 @@ void launch_onebody_apply(mfs_ctx* c, int prob, const double* mu, double* lam_ba
 void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil);
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                            bool pack32, bool pack64);
+void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
+                              float4* sig32, double4* src64, float4* bdat);
+// stacked forms for R = 2, 4 or 8 vectors (false: unsupported size or out of memory)
+bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
+                       int64_t ltil_stride);
+bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, double scale);
 // mode 0: all sources; 1: skip the target's own disk; 2: also skip its contact partners.  false: out of memory
 bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale);
 void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr);
@@ -139,6 +153,8 @@ Status precompute_pairs(mfs_ctx* c, int prob);
 
 // ---- matvec pieces (capi.hip) ----
 Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u);
+// T applied to R vectors (mu, u: R x n, vector r at offset r n); stacked kernels for R in {2, 4, 8}
+Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, double* u);
 
 }  // namespace mfs
 

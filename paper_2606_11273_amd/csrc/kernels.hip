@@ -162,6 +162,44 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_A(int C, const int* __res
   }
 }
 
+// Stacked right-hand sides: lambda_tilde^c_r = A^c [lambda_bar_r^(i); lambda_bar_r^(k)] for
+// R vectors at once, so each A^c is read from HBM once for all of them.  Dynamic LDS
+// holds the R gathered inputs (R n doubles).
+template <int R>
+__global__ __launch_bounds__(kPairThreads) void k_pair_A_rhs(int C, const int* __restrict__ pairs,
+                                                             const int* __restrict__ src_off,
+                                                             const int64_t* __restrict__ xoff,
+                                                             const int64_t* __restrict__ aoff,
+                                                             const double* __restrict__ A,
+                                                             const double* __restrict__ lam, int64_t lam_stride,
+                                                             double* __restrict__ ltil, int64_t ltil_stride) {
+  extern __shared__ double s_xr[];   // [r][n]
+  const int c = blockIdx.x;
+  if (c >= C) return;
+  const int i = pairs[2 * c], k = pairs[2 * c + 1];
+  const int ni = 2 * (src_off[i + 1] - src_off[i]);
+  const int n = (int)(xoff[c + 1] - xoff[c]);
+  for (int e = threadIdx.x; e < R * n; e += kPairThreads) {
+    const int r = e / n, q = e - r * n;
+    const double* l = lam + r * lam_stride;
+    s_xr[e] = q < ni ? l[2 * (int64_t)src_off[i] + q] : l[2 * (int64_t)src_off[k] + (q - ni)];
+  }
+  __syncthreads();
+  const double* Ac = A + aoff[c];
+  for (int row = threadIdx.x; row < n; row += kPairThreads) {
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int col = 0; col < n; ++col) {
+      const double a = Ac[(int64_t)col * n + row];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = fma(a, s_xr[r * n + col], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) ltil[r * ltil_stride + xoff[c] + row] = acc[r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // eq. total_corr + projection: lambda^(b) = lambda_bar^(b) + sum_{c contains b} lambda_tilde^c_b,
 // sigma = (I - L) lambda (mobility) or lambda (resistance); packed for the kernel sum.
@@ -485,6 +523,196 @@ __global__ void k_reduce_splits(int64_t n2, int nsplit, const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Step 2a for R stacked strength vectors on the same sources and nodes (one thread per
+// target).  The geometry of each (target, source) pair is evaluated once and applied to
+// the R strengths: in the FP32 form w, log2(1 + w) and 1/(1 + w); in the FP64 form
+// ln r^2 and 1/r^2.  The per-pair arithmetic is otherwise that of k_ksum_mixed and
+// k_ksum_fp64, term for term.  src holds R packed arrays of Ns records, bdat R arrays
+// of P disk records; out is [split][R][Nt][2].  Disks must have at most KR_TILE sources.
+constexpr int KR_TILE = 256;
+constexpr int KR_MAXB = 16;
+
+template <int R>
+__global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed_rhs(
+    int P, const int* __restrict__ src_off, const double* __restrict__ centers, const float4* __restrict__ src,
+    int64_t Ns, const float4* __restrict__ bdat, int64_t Nt, const int* __restrict__ tgt_body,
+    const double* __restrict__ X, int bodies_per_split, int mode, const int* __restrict__ nbr_off,
+    const int* __restrict__ nbr_list, double scale, double* __restrict__ out) {
+  __shared__ float2 s_y[KR_TILE];
+  __shared__ float2 s_s[KR_TILE * R];   // [q][r] strengths
+  __shared__ float s_w[KR_TILE * R];    // [q][r] y . sigma_r
+  __shared__ double s_c[2 * KR_MAXB];
+  __shared__ float4 s_b[KR_MAXB * R];   // [kk][r] (S0x, S0y, q, W)
+  __shared__ int s_off[KR_MAXB + 1];
+  const int split = blockIdx.y;
+  const int kb0 = split * bodies_per_split;
+  const int kb1 = min(P, kb0 + bodies_per_split);
+  const int64_t t = (int64_t)blockIdx.x * KS_THREADS + threadIdx.x;
+  const int64_t tc = t < Nt ? t : Nt - 1;
+  const int bt = tgt_body[tc];
+  const double x = X[2 * tc], y = X[2 * tc + 1];
+  double ax[R], ay[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ax[r] = ay[r] = 0.0;
+  Skip sk;
+  skip_init(sk, mode, bt, kb0, nbr_off, nbr_list);
+  const float kHalfLn2 = 0.34657359027997264f;
+  for (int kt = kb0; kt < kb1;) {
+    const int s0 = src_off[kt];
+    int nb = 0;
+    while (kt + nb < kb1 && nb < KR_MAXB && src_off[kt + nb + 1] - s0 <= KR_TILE) ++nb;
+    const int ns = src_off[kt + nb] - s0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * ns; e += KS_THREADS) {
+      const int r = e / ns, q = e - r * ns;
+      const float4 v = src[r * Ns + s0 + q];
+      if (r == 0) s_y[q] = make_float2(v.x, v.y);
+      s_s[q * R + r] = make_float2(v.z, v.w);
+      s_w[q * R + r] = fmaf(v.x, v.z, v.y * v.w);
+    }
+    for (int e = threadIdx.x; e < R * nb; e += KS_THREADS) {
+      const int kk = e / R, r = e - kk * R;
+      s_b[e] = bdat[(int64_t)r * P + kt + kk];
+    }
+    for (int q = threadIdx.x; q < nb; q += KS_THREADS) {
+      s_c[2 * q] = centers[2 * (kt + q)];
+      s_c[2 * q + 1] = centers[2 * (kt + q) + 1];
+    }
+    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
+    __syncthreads();
+    for (int kk = 0; kk < nb; ++kk) {
+      const int kbody = kt + kk;
+      const float Dx = (float)(x - s_c[2 * kk]);
+      const float Dy = (float)(y - s_c[2 * kk + 1]);
+      const float R2 = fmaf(Dx, Dx, Dy * Dy);
+      const float ir2 = __builtin_amdgcn_rcpf(R2);
+      const float Dxs = -2.0f * Dx * ir2, Dys = -2.0f * Dy * ir2;
+      const float qs = s_b[kk * R].z * ir2;
+      float lx[R], ly[R], t0[R], tsx[R], tsy[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) lx[r] = ly[r] = t0[r] = tsx[r] = tsy[r] = 0.0f;
+      const int q1 = s_off[kk + 1];
+#pragma unroll 2
+      for (int q = s_off[kk]; q < q1; ++q) {
+        const float2 yq = s_y[q];
+        const float w = fmaf(Dxs, yq.x, fmaf(Dys, yq.y, qs));
+        const float u = 1.0f + w;
+        const float e = w - (u - 1.0f);
+        const float lg = fmaf(e, 1.44269504088896341f, __builtin_amdgcn_logf(u));
+        const float iu = __builtin_amdgcn_rcpf(u);
+        const float g0 = iu * w, g1 = iu * yq.x, g2 = iu * yq.y;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float2 sg = s_s[q * R + r];
+          const float a = fmaf(Dx, sg.x, fmaf(Dy, sg.y, -s_w[q * R + r]));   // d . sigma, d = D - y
+          lx[r] = fmaf(lg, sg.x, lx[r]);
+          ly[r] = fmaf(lg, sg.y, ly[r]);
+          t0[r] = fmaf(a, g0, t0[r]);
+          tsx[r] = fmaf(a, g1, tsx[r]);
+          tsy[r] = fmaf(a, g2, tsy[r]);
+        }
+      }
+      if (!skip_test(sk, mode, kbody, bt, nbr_list)) {
+        const float lR = __builtin_amdgcn_logf(R2);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float4 bd = s_b[kk * R + r];
+          const float T0 = fmaf(Dx, bd.x, fmaf(Dy, bd.y, -bd.w)) - t0[r];
+          const float tx = ir2 * fmaf(Dx, T0, -tsx[r]);
+          const float ty = ir2 * fmaf(Dy, T0, -tsy[r]);
+          ax[r] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.x, lx[r]), tx);
+          ay[r] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.y, ly[r]), ty);
+        }
+      }
+    }
+    kt += nb;
+  }
+  if (t < Nt) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      out[(((int64_t)split * R + r) * Nt + t) * 2] = ax[r] * scale;
+      out[(((int64_t)split * R + r) * Nt + t) * 2 + 1] = ay[r] * scale;
+    }
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64_rhs(
+    int P, const int* __restrict__ src_off, const double4* __restrict__ src, int64_t Ns, int64_t Nt,
+    const int* __restrict__ tgt_body, const double* __restrict__ X, int bodies_per_split, int mode,
+    const int* __restrict__ nbr_off, const int* __restrict__ nbr_list, double scale, double* __restrict__ out) {
+  __shared__ double2 s_y[KR_TILE];
+  __shared__ double2 s_s[KR_TILE * R];
+  __shared__ int s_off[KR_MAXB + 1];
+  const int split = blockIdx.y;
+  const int kb0 = split * bodies_per_split;
+  const int kb1 = min(P, kb0 + bodies_per_split);
+  const int64_t t = (int64_t)blockIdx.x * KS_THREADS + threadIdx.x;
+  const int64_t tc = t < Nt ? t : Nt - 1;
+  const int bt = tgt_body[tc];
+  const double x = X[2 * tc], y = X[2 * tc + 1];
+  double ax[R], ay[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ax[r] = ay[r] = 0.0;
+  Skip sk;
+  skip_init(sk, mode, bt, kb0, nbr_off, nbr_list);
+  for (int kt = kb0; kt < kb1;) {
+    const int s0 = src_off[kt];
+    int nb = 0;
+    while (kt + nb < kb1 && nb < KR_MAXB && src_off[kt + nb + 1] - s0 <= KR_TILE) ++nb;
+    const int ns = src_off[kt + nb] - s0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * ns; e += KS_THREADS) {
+      const int r = e / ns, q = e - r * ns;
+      const double4 v = src[r * Ns + s0 + q];
+      if (r == 0) s_y[q] = make_double2(v.x, v.y);
+      s_s[q * R + r] = make_double2(v.z, v.w);
+    }
+    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
+    __syncthreads();
+    for (int kk = 0; kk < nb; ++kk) {
+      const int kbody = kt + kk;
+      double lx[R], ly[R], tx[R], ty[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) lx[r] = ly[r] = tx[r] = ty[r] = 0.0;
+      const int q1 = s_off[kk + 1];
+      for (int q = s_off[kk]; q < q1; ++q) {
+        const double2 yq = s_y[q];
+        const double dx = x - yq.x;
+        const double dy = y - yq.y;
+        const double r2 = fma(dx, dx, dy * dy);
+        const double lg = ln_f64(r2);
+        const double ir = rcp_f64(r2);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double2 sg = s_s[q * R + r];
+          const double dot = fma(dx, sg.x, dy * sg.y) * ir;
+          lx[r] = fma(lg, sg.x, lx[r]);
+          ly[r] = fma(lg, sg.y, ly[r]);
+          tx[r] = fma(dot, dx, tx[r]);
+          ty[r] = fma(dot, dy, ty[r]);
+        }
+      }
+      if (!skip_test(sk, mode, kbody, bt, nbr_list)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ax[r] += fma(-0.5, lx[r], tx[r]);
+          ay[r] += fma(-0.5, ly[r], ty[r]);
+        }
+      }
+    }
+    kt += nb;
+  }
+  if (t < Nt) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      out[(((int64_t)split * R + r) * Nt + t) * 2] = ax[r] * scale;
+      out[(((int64_t)split * R + r) * Nt + t) * 2 + 1] = ay[r] * scale;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Step 2b, per pair, in source form.  The kernel sum skipped each disk's own
 // sources and those of its contact partners; in exact arithmetic Alg. 3 leaves, on
 // body i of pair c = (i, k), the field of k's corrections from its other pairs:
@@ -778,11 +1006,37 @@ void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil) {
 
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                            bool pack32, bool pack64) {
+  launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, pack32 ? c->d_sig32 : nullptr,
+                           pack64 ? c->d_src64 : nullptr, pack32 ? c->d_bdat : nullptr);
+}
+
+void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
+                              float4* sig32, double4* src64, float4* bdat) {
   hipLaunchKernelGGL(k_gather_project, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P,
                      prob == MFS_MOBILITY ? 1 : 0, c->d_cls, c->d_src_off, c->ct[prob], c->d_bp_off, c->d_bp_list,
-                     c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers,
-                     (double*)nullptr, pack32 ? c->d_sig32 : (float4*)nullptr,
-                     pack64 ? c->d_src64 : (double4*)nullptr, pack32 ? c->d_bdat : (float4*)nullptr);
+                     c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers, (double*)nullptr,
+                     sig32, src64, bdat);
+}
+
+bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
+                       int64_t ltil_stride) {
+  const int C = (int)(c->pairs.size() / 2);
+  if (C == 0) return true;
+  int64_t nmax = 0;
+  for (int p = 0; p < C; ++p) nmax = std::max<int64_t>(nmax, c->xoff[p + 1] - c->xoff[p]);
+  const size_t lds = sizeof(double) * (size_t)R * (size_t)nmax;
+  if (lds > 64 * 1024) return false;
+#define MFS_PA(RR)                                                                                                  \
+  hipLaunchKernelGGL(k_pair_A_rhs<RR>, dim3(C), dim3(kPairThreads), lds, c->stream, C, c->d_pairs, c->d_src_off, \
+                     c->d_xoff, c->d_aoff, c->ps[prob].A, lam_bar, lam_stride, ltil, ltil_stride)
+  switch (R) {
+    case 2: MFS_PA(2); break;
+    case 4: MFS_PA(4); break;
+    case 8: MFS_PA(8); break;
+    default: return false;
+  }
+#undef MFS_PA
+  return true;
 }
 
 // Choose the source split so that the grid holds enough workgroups to fill the chip
@@ -799,6 +1053,53 @@ static int ksum_targets_per_thread(bool mixed) {
   const char* e = std::getenv(mixed ? "MFS_KSUM_T" : "MFS_KSUM_T64");
   const int t = e ? std::atoi(e) : 2;
   return t == 1 || t == 2 || t == 4 ? t : 2;
+}
+
+// Stacked form of launch_kernel_sum: R strength vectors packed by launch_gather_project_to
+// into c->d_sig32m / c->d_bdatm (mixed) or c->d_src64m (FP64), R arrays each; u: R x 2 Nt.
+// false: out of memory for the split partials, or R unsupported.
+bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, double scale) {
+  const int64_t Nt = c->Nt;
+  const int64_t tblocks = (Nt + KS_THREADS - 1) / KS_THREADS;
+  const int ns = ksum_splits(tblocks, c->P);
+  const int bps = (c->P + ns - 1) / ns;
+  double* out = u;
+  if (ns > 1) {
+    const int64_t need = (int64_t)ns * R * Nt * 2;
+    if (c->upart_cap < need) {
+      if (c->d_upart) (void)hipFree(c->d_upart);
+      c->d_upart = nullptr;
+      if (hipMalloc(&c->d_upart, need * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->d_upart = nullptr;
+        c->upart_cap = 0;
+        return false;
+      }
+      c->upart_cap = need;
+    }
+    out = c->d_upart;
+  }
+  dim3 grid((unsigned)tblocks, (unsigned)ns);
+#define MFS_KR_MIXED(RR)                                                                                     \
+  hipLaunchKernelGGL(k_ksum_mixed_rhs<RR>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off,        \
+                     c->d_centers, c->d_sig32m, c->Ns, c->d_bdatm, Nt, c->d_tgt_body, c->d_X, bps, mode,    \
+                     c->d_nbr_off, c->d_nbr_list, scale, out)
+#define MFS_KR_FP64(RR)                                                                                    \
+  hipLaunchKernelGGL(k_ksum_fp64_rhs<RR>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off,       \
+                     c->d_src64m, c->Ns, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, \
+                     scale, out)
+  switch (R) {
+    case 2: if (mixed) MFS_KR_MIXED(2); else MFS_KR_FP64(2); break;
+    case 4: if (mixed) MFS_KR_MIXED(4); else MFS_KR_FP64(4); break;
+    case 8: if (mixed) MFS_KR_MIXED(8); else MFS_KR_FP64(8); break;
+    default: return false;
+  }
+#undef MFS_KR_MIXED
+#undef MFS_KR_FP64
+  if (ns > 1)
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt * R, 256)), dim3(256), 0, c->stream, 2 * Nt * R, ns,
+                       c->d_upart, u);
+  return true;
 }
 
 bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale) {
