@@ -11,7 +11,7 @@ on the true residual, and post-processing to velocities.  Setup and the pair pre
 timed region and are reported separately; the plain-FP64 solve of the same input
 is run once beside it for the mixed-vs-FP64 comparison.
 
-Prints one JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 exits: the benchmark runs on one GPU.
 
 --serve runs the serving workload instead: a stream of independent mobility solves
 (P ~ U{50..3000}, area fraction U[0.4, 0.65], min gap 10^U[-4,-2], N(0,1) forces and
@@ -103,17 +103,21 @@ def main():
     ap.add_argument("--ksum-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB-in, 1 GiB-out elementwise kernel (reference for HBM counters)")
+    ap.add_argument("--rhs", type=int, default=1,
+                    help="stacked right-hand sides solved in lockstep: #1 unit torques, the others N(0,1) "
+                         "forces and torques with zero net force")
     ap.add_argument("--serve", action="store_true", help="run the serving workload (see the module doc)")
-    ap.add_argument("--requests", type=int, default=24, help="requests in the Poisson stream (--serve)")
-    ap.add_argument("--saturated", type=int, default=8, help="requests in the saturated pass (--serve)")
+    ap.add_argument("--requests", type=int, default=12, help="requests in the Poisson stream (--serve)")
+    ap.add_argument("--saturated", type=int, default=6, help="requests in the saturated pass (--serve)")
     ap.add_argument("--slots", type=int, default=4, help="server slots (--serve)")
     ap.add_argument("--kernel-only", action="store_true",
-                    help="set up the workload and run only the dominant kernel (plus --copy-calibration): "
-                         "the short program the hardware-counter runs profile")
+                    help="set up the workload and run only the dominant kernel (5 launches), then one mixed "
+                         "and one FP64 matvec with zero pair matrices (plus --copy-calibration): the short "
+                         "program the hardware-counter runs profile")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs the hot path on one GPU; multi-GPU runs are not part of it "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the hot path runs on one GPU; runs on several GPUs are not implemented "
+              "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     if args.serve:
@@ -123,7 +127,7 @@ def main():
     import numpy as np
     import torch
     from paper_2606_11273_amd import native as nv
-    from workloads import config_geometry, unit_torques
+    from workloads import config_geometry, mobility_rhs, unit_torques
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
@@ -133,6 +137,8 @@ def main():
     c, a, ns, nc, rs = g["centers"], g["radii"], g["n_src"], g["n_col"], g["r_src"]
     P = c.shape[0]
     given = unit_torques(P)
+    if args.rhs > 1:
+        given = np.stack([given] + [mobility_rhs(g["seed"] + r, P) for r in range(1, args.rhs)])
     prm = nv.mfs_default_params()
     prm.delta_c = g["delta_c"]
     torch.cuda.synchronize()
@@ -145,6 +151,15 @@ def main():
         u = torch.zeros(2 * Nt, dtype=torch.float64, device="cuda")
         for _ in range(args.ksum_reps):
             nv.mfs_kernel_sum(ctx, "mixed", sig, u, 2)
+        # two whole matvecs (mixed, then FP64) so that counters also cover the pair-correction
+        # kernels; the pair matrices are zeros of the right shapes (same memory traffic)
+        n_pairs = len(nv.mfs_get_pairs(ctx))
+        m = 4 * int(ns[0])
+        nv.mfs_set_pair_matrices(ctx, "mobility", [np.zeros((m, m))] * n_pairs, [np.zeros((6, m))] * n_pairs)
+        mu = torch.randn(2 * Nt, dtype=torch.float64, device="cuda")
+        w = torch.zeros_like(mu)
+        for prec in ("mixed", "fp64"):
+            nv.mfs_apply(ctx, "mobility", prec, mu, w)
         if args.copy_calibration:
             # an elementwise kernel that reads 1 GiB and writes 1 GiB (a same-dtype copy_ could
             # go to the DMA engines, which the shader counters do not see)
@@ -238,7 +253,26 @@ def main():
                     fp64_kernel_tflops=round(evals_launch * FLOP_PER_PAIR / (ks["fp64"] * 1e-3) / 1e12, 2),
                     fp64_peak=PEAK_FP64_TFLOPS)
 
-    err = rel_rigid_error(out32, out64) if out64 is not None else None
+    # stacked matvec: one T mu on args.rhs vectors at once, per vector (HIP events)
+    stacked = None
+    if args.rhs > 1:
+        mu = torch.randn(args.rhs * 2 * Nt, dtype=torch.float64, device="cuda")
+        w = torch.zeros_like(mu)
+        stacked = {}
+        for prec in ("mixed", "fp64"):
+            nv.mfs_apply(ctx, "mobility", prec, mu, w, n_rhs=args.rhs)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            nv.mfs_apply(ctx, "mobility", prec, mu, w, n_rhs=args.rhs)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            stacked[f"{prec}_ms_per_vector"] = round(e0.elapsed_time(e1) / args.rhs, 2)
+
+    err = None
+    if out64 is not None:
+        err = max(rel_rigid_error(a32, a64) for a32, a64 in zip(out32.reshape(-1, P, 3), out64.reshape(-1, P, 3)))
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(c, a, ns, nc, rs, args.cpu_targets)
@@ -258,8 +292,11 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"mobility solve, P={P} unit disks, area fraction 0.65, min gap 1e-3, "
-                               f"{n_pairs} close pairs, N_c=36 M_c=72 R_c=0.7, unit torques, GMRES tol {args.tol:g}",
-                   "P": P, "n_pairs": n_pairs, "unknowns": 2 * Nt},
+                               f"{n_pairs} close pairs, N_c=36 M_c=72 R_c=0.7, "
+                               + ("unit torques" if args.rhs == 1 else
+                                  f"{args.rhs} right-hand sides in lockstep (unit torques + N(0,1))")
+                               + f", GMRES tol {args.tol:g}",
+                   "P": P, "n_pairs": n_pairs, "unknowns": 2 * Nt, "rhs": args.rhs},
         "time_to_solve_s": {"mixed": round(ms / 1e3, 3), "fp64": round(t_fp64, 3) if t_fp64 else None},
         "speedup_mixed_vs_fp64": round(t_fp64 / (ms / 1e3), 2) if t_fp64 else None,
         "max_rel_velocity_diff_mixed_vs_fp64": err,
@@ -269,6 +306,7 @@ def main():
         "pair_evals_per_solve": evals_skip,
         "setup_s": round(t_setup, 3),
         "precompute_s": round(t_pre, 2),
+        "stacked_matvec": stacked,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -300,28 +338,50 @@ def run_serving(args):
         # saturated pass: every request queued at once
         sat = reqs[:args.saturated]
         t0 = time.perf_counter()
-        tk = [submit(r) for r in sat]
-        for t, r in zip(tk, sat):
-            nv.mfs_server_wait(srv, t, r["P"])
-            log(f"saturated: request P={r['P']} done at {time.perf_counter() - t0:.1f} s")
+        pending = {submit(r): r for r in sat}
+        while pending:
+            for t in list(pending):
+                r = pending[t]
+                try:
+                    nv.mfs_server_wait(srv, t, r["P"], timeout_ms=0)
+                except nv.MFSError as e:
+                    if e.code == nv.MFS_ERR_STATE:
+                        continue
+                    raise
+                del pending[t]
+                log(f"saturated: request P={r['P']} done at {time.perf_counter() - t0:.1f} s")
+            time.sleep(0.05)
         sat_rate = len(sat) / (time.perf_counter() - t0)
-        # Poisson stream at 0.8 x the saturated rate
+        # Poisson stream at 0.8 x the saturated rate: submit at the arrival times, collect
+        # completions as they happen
         stream = reqs[args.saturated:]
         rate = 0.8 * sat_rate
         arrive = poisson_arrivals(len(stream), rate)
         t0 = time.perf_counter()
-        tk = []
-        for a, r in zip(arrive, stream):
-            dt = a - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tk.append(submit(r))
+        pending = {}
         res = []
-        for t, r in zip(tk, stream):
-            out, info = nv.mfs_server_wait(srv, t, r["P"])
-            res.append(info)
-            log(f"stream: P={r['P']} total {info['ms_total'] / 1e3:.1f} s (queue {info['ms_queue'] / 1e3:.1f}, "
-                f"precompute {info['ms_precompute'] / 1e3:.1f}, iters {info['iters']})")
+        nxt = 0
+        while nxt < len(stream) or pending:
+            now = time.perf_counter() - t0
+            while nxt < len(stream) and arrive[nxt] <= now:
+                r = stream[nxt]
+                pending[submit(r)] = r
+                log(f"stream: submitted P={r['P']} at {now:.1f} s ({len(pending)} in the server)")
+                nxt += 1
+            for t in list(pending):
+                r = pending[t]
+                try:
+                    out, info = nv.mfs_server_wait(srv, t, r["P"], timeout_ms=0)
+                except nv.MFSError as e:
+                    if e.code == nv.MFS_ERR_STATE:
+                        continue
+                    raise
+                del pending[t]
+                res.append(info)
+                log(f"stream: P={r['P']} done at {time.perf_counter() - t0:.1f} s: total {info['ms_total'] / 1e3:.1f} s "
+                    f"(queue {info['ms_queue'] / 1e3:.1f}, precompute {info['ms_precompute'] / 1e3:.1f}, "
+                    f"iters {info['iters']})")
+            time.sleep(0.05)
         wall = time.perf_counter() - t0
     finally:
         nv.mfs_server_destroy(srv)

@@ -588,9 +588,13 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed_rhs(
       const float ir2 = __builtin_amdgcn_rcpf(R2);
       const float Dxs = -2.0f * Dx * ir2, Dys = -2.0f * Dy * ir2;
       const float qs = s_b[kk * R].z * ir2;
-      float lx[R], ly[R], t0[R], tsx[R], tsy[R];
+      // With a_s = d_s . sigma_s and t_s = a_s / u_s, the dyadic sum of k_ksum_mixed is
+      //   (D sum t - sum t y) R^-2 = (D (D.S0 - W) - sum_s t_s (D w_s + y_s)) R^-2,
+      // so one accumulator per component suffices: h = (D w + y) / u is shared by the R
+      // strength vectors and each of them costs 6 instructions per pair.
+      float lx[R], ly[R], hx[R], hy[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) lx[r] = ly[r] = t0[r] = tsx[r] = tsy[r] = 0.0f;
+      for (int r = 0; r < R; ++r) lx[r] = ly[r] = hx[r] = hy[r] = 0.0f;
       const int q1 = s_off[kk + 1];
 #pragma unroll 2
       for (int q = s_off[kk]; q < q1; ++q) {
@@ -600,16 +604,15 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed_rhs(
         const float e = w - (u - 1.0f);
         const float lg = fmaf(e, 1.44269504088896341f, __builtin_amdgcn_logf(u));
         const float iu = __builtin_amdgcn_rcpf(u);
-        const float g0 = iu * w, g1 = iu * yq.x, g2 = iu * yq.y;
+        const float gx = iu * fmaf(Dx, w, yq.x), gy = iu * fmaf(Dy, w, yq.y);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const float2 sg = s_s[q * R + r];
           const float a = fmaf(Dx, sg.x, fmaf(Dy, sg.y, -s_w[q * R + r]));   // d . sigma, d = D - y
           lx[r] = fmaf(lg, sg.x, lx[r]);
           ly[r] = fmaf(lg, sg.y, ly[r]);
-          t0[r] = fmaf(a, g0, t0[r]);
-          tsx[r] = fmaf(a, g1, tsx[r]);
-          tsy[r] = fmaf(a, g2, tsy[r]);
+          hx[r] = fmaf(a, gx, hx[r]);
+          hy[r] = fmaf(a, gy, hy[r]);
         }
       }
       if (!skip_test(sk, mode, kbody, bt, nbr_list)) {
@@ -617,9 +620,9 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed_rhs(
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const float4 bd = s_b[kk * R + r];
-          const float T0 = fmaf(Dx, bd.x, fmaf(Dy, bd.y, -bd.w)) - t0[r];
-          const float tx = ir2 * fmaf(Dx, T0, -tsx[r]);
-          const float ty = ir2 * fmaf(Dy, T0, -tsy[r]);
+          const float M0 = fmaf(Dx, bd.x, fmaf(Dy, bd.y, -bd.w));   // D.S0 - W
+          const float tx = ir2 * fmaf(Dx, M0, -hx[r]);
+          const float ty = ir2 * fmaf(Dy, M0, -hy[r]);
           ax[r] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.x, lx[r]), tx);
           ay[r] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.y, ly[r]), ty);
         }

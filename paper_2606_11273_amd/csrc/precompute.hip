@@ -177,14 +177,24 @@ __global__ __launch_bounds__(64) void k_fill(const PairGeo* __restrict__ geo, Ba
 }
 
 // sinv_j = 1/s_j if s_j > eps s_0 else 0, then scale row j of T (column-major, ld, ncol columns).
-__global__ void k_trunc_scale(int nsv, const double* __restrict__ S, int64_t sS, double eps, double* T, int64_t ld,
-                              int ncol, int64_t sT) {
+__global__ __launch_bounds__(256) void k_trunc_scale(int nsv, const double* __restrict__ S, int64_t sS, double eps,
+                                                     double* T, int64_t ld, int ncol, int64_t sT) {
   const int p = blockIdx.y;
+  // sigma_1 as the largest entry (no reliance on the order the SVD returns)
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int j = threadIdx.x; j < nsv; j += 256) m = fmax(m, S[p * sS + j]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const double s0 = red[0];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)nsv * ncol) return;
   const int j = (int)(idx % nsv);
   const int col = (int)(idx / nsv);
-  const double s0 = S[p * sS];
   const double sj = S[p * sS + j];
   const double f = (sj > eps * s0) ? 1.0 / sj : 0.0;
   T[p * sT + (int64_t)col * ld + j] *= f;

