@@ -14,6 +14,7 @@ import multiprocessing as mp
 import os
 
 import numpy as np
+from threadpoolctl import threadpool_limits
 
 
 def stokeslet_blocks(x, y, mu=1.0):
@@ -53,7 +54,9 @@ _SHARED = {}
 def _worker(bounds):
     lo, hi = bounds
     s = _SHARED
-    return lo, _sum_chunk(s["x"][lo:hi], s["y"], s["sig"], s["mu"])
+    # one thread per worker process: the pool already uses the cores
+    with threadpool_limits(1):
+        return lo, _sum_chunk(s["x"][lo:hi], s["y"], s["sig"], s["mu"])
 
 
 def direct_sum(x, y, sig, mu=1.0, workers=None, chunk_elems=4_000_000):

@@ -163,8 +163,14 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_A(int C, const int* __res
 }
 
 // Stacked right-hand sides: lambda_tilde^c_r = A^c [lambda_bar_r^(i); lambda_bar_r^(k)] for
-// R vectors at once, so each A^c is read from HBM once for all of them.  Dynamic LDS
-// holds the R gathered inputs (R n doubles).
+// R <= 16 vectors at once on the matrix cores: L (n x 16) = A^c (n x n) X (n x 16) in
+// 16 x 16 x 4 FP64 MFMA steps, the columns beyond R zero.  Each A^c element is read from
+// HBM once for all R vectors; X (R n doubles) sits in dynamic LDS.  Operand layout of
+// v_mfma_f64_16x16x4f64 (64 lanes, l = lane; checked on the device): A element
+// (l % 16, l / 16), B element (l / 16, l % 16), result item q = 0..3 at row l / 16 + 4 q,
+// column l % 16.
+typedef double mfs_double4_t __attribute__((ext_vector_type(4)));
+
 template <int R>
 __global__ __launch_bounds__(kPairThreads) void k_pair_A_rhs(int C, const int* __restrict__ pairs,
                                                              const int* __restrict__ src_off,
@@ -173,6 +179,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_A_rhs(int C, const int* _
                                                              const double* __restrict__ A,
                                                              const double* __restrict__ lam, int64_t lam_stride,
                                                              double* __restrict__ ltil, int64_t ltil_stride) {
+  static_assert(R >= 1 && R <= 16, "at most 16 stacked vectors");
   extern __shared__ double s_xr[];   // [r][n]
   const int c = blockIdx.x;
   if (c >= C) return;
@@ -186,17 +193,25 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_A_rhs(int C, const int* _
   }
   __syncthreads();
   const double* Ac = A + aoff[c];
-  for (int row = threadIdx.x; row < n; row += kPairThreads) {
-    double acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    for (int col = 0; col < n; ++col) {
-      const double a = Ac[(int64_t)col * n + row];
-#pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] = fma(a, s_xr[r * n + col], acc[r]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nrb = (n + 15) >> 4;
+  for (int rb = wave; rb < nrb; rb += kPairThreads / 64) {
+    const int row = rb * 16 + li;
+    mfs_double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += 4) {
+      const int kk = k0 + lk;
+      const double a = (row < n && kk < n) ? Ac[(int64_t)kk * n + row] : 0.0;
+      const double b = (li < R && kk < n) ? s_xr[li * n + kk] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
+    if (li < R) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) ltil[r * ltil_stride + xoff[c] + row] = acc[r];
+      for (int q = 0; q < 4; ++q) {
+        const int rr = rb * 16 + lk + 4 * q;
+        if (rr < n) ltil[li * ltil_stride + xoff[c] + rr] = acc[q];
+      }
+    }
   }
 }
 

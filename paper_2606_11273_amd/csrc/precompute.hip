@@ -465,9 +465,6 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     const char* env = std::getenv("MFS_PRECOMPUTE_BATCH");
     if (env) batch = std::max(1, std::atoi(env));
   }
-  // SVD algorithm: one-stage QR iteration (gesvd, default) or divide and conquer (gesdd)
-  const char* svd_env = std::getenv("MFS_SVD");
-  const bool svd_dc = svd_env && std::string(svd_env) == "gesdd";
   for (int b0 = 0; b0 < C; b0 += batch) {
     auto t0 = std::chrono::steady_clock::now();
     const int nb = std::min(batch, C - b0);
@@ -581,15 +578,10 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_HIP(hipMalloc(&dE.p, sizeof(double) * mn * nb));
     MFS_HIP(hipMalloc(&dinfo.p, sizeof(int) * nb));
     MFS_HIP(hipMalloc(&dinfoC.p, sizeof(int) * nb));
-    if (svd_dc)
-      MFS_RB(rocsolver_dgesdd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m,
-                                              (int)n, (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p,
-                                              (int)m, m * mn, (double*)dVT.p, (int)mn, mn * n, (int*)dinfo.p, nb));
-    else
-      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m,
-                                              (int)n, (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p,
-                                              (int)m, m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
-                                              rocblas_outofplace, (int*)dinfo.p, nb));
+    MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m, (int)n,
+                                            (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p, (int)m,
+                                            m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
+                                            rocblas_outofplace, (int*)dinfo.p, nb));
     tick(2, t0);
     // T1 = U^T X  (mn x nx)
     MFS_HIP(hipMalloc(&dT1.p, sizeof(double) * mn * nx * nb));
@@ -621,16 +613,10 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_HIP(hipMalloc(&dUC.p, sizeof(double) * mpp * mnc * nb));
     MFS_HIP(hipMalloc(&dVTC.p, sizeof(double) * mnc * nx * nb));
     MFS_HIP(hipMalloc(&dEC.p, sizeof(double) * mnc * nb));
-    if (svd_dc)
-      MFS_RB(rocsolver_dgesdd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
-                                              (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
-                                              (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
-                                              mnc * nx, (int*)dinfoC.p, nb));
-    else
-      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
-                                              (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
-                                              (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
-                                              mnc * nx, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nb));
+    MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
+                                            (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
+                                            (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
+                                            mnc * nx, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nb));
     tick(4, t0);
     MFS_HIP(hipMalloc(&dT2.p, sizeof(double) * mnc * nx * nb));
     MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnc,

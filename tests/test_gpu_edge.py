@@ -11,6 +11,8 @@ the largest disk discretisation the library accepts.
 * n_src = 511, n_col = 512 (the largest ring sizes): the kernel sum in both precisions
   against the oracle's direct sum, to the bounds of the kernel-sum tests (1e-13 and 2e-6
   of sum_s (|log r| + 1) |sigma_s| / (4 pi mu)).
+* An iteration limit below what the tolerance needs: MFS_ERR_NOCONV with the iterate's
+  outputs written (finite, and within O(1) of the converged answer).
 """
 
 import math
@@ -96,5 +98,27 @@ def test_kernel_sum_largest_rings():
                 err = (np.abs(u.cpu().numpy().reshape(-1, 2) - ref).max(1) / mag).max()
                 say(f"largest rings skip {skip} {prec}: max err / m_t {err:.1e}")
                 assert err <= tol
+    finally:
+        nv.mfs_destroy(ctx)
+
+
+def test_iteration_limit_returns_best_iterate():
+    # MFS_ERR_NOCONV: GMRES stops at max_iter above the tolerance, outputs hold the iterate
+    from workloads import jittered_grid, mobility_rhs
+    c, a = jittered_grid(260611273 + 1000)
+    nv, ctx = _ctx(c, a, delta_c=0.5)
+    try:
+        nv.mfs_precompute_pairs(ctx, "mobility")
+        given = mobility_rhs(3, 16)
+        full, _ = nv.mfs_gmres_solve(ctx, "mobility", "fp64", given, 1e-10, 300)
+        for prec in ("fp64", "mixed"):
+            out, info = nv.mfs_gmres_solve(ctx, "mobility", prec, given, 1e-10, 3, allow_noconv=True)
+            say(f"iteration limit {prec}: status {info['status']}, iters {info['iters']}, resid {info['rel_resid']:.2e}")
+            assert info["status"] == "MFS_ERR_NOCONV" and info["iters"] <= 3 and info["rel_resid"] > 1e-10
+            assert np.all(np.isfinite(out)) and np.abs(out).max() > 0
+            assert rel_rigid_error(out, full).max() < 1.0
+            with pytest.raises(nv.MFSError) as e:
+                nv.mfs_gmres_solve(ctx, "mobility", prec, given, 1e-10, 3)
+            assert e.value.code == nv.MFS_ERR_NOCONV
     finally:
         nv.mfs_destroy(ctx)
