@@ -5,8 +5,8 @@
   time; the outputs agree to 1e-12 of max |v| + |omega| (the arithmetic of a
   request does not depend on the others, so they are expected to be identical).
 * Admission by device-memory footprint: with a budget that holds one request at a
-  time, no two requests run together even with 3 slots; a request larger than the
-  whole budget is refused.
+  time (four requests of 300 disks), no two requests run together even with 3 slots; a
+  request larger than the whole budget is refused.
 * Two small requests agree with the FP64 oracle (eq. rel_vel_err <= 1e-5).
 Requests come from the serving workload generator (area fraction U[0.4, 0.65], min
 gap 10^U[-4,-2], N(0,1) forces and torques with zero net force), with P reduced to
@@ -62,15 +62,18 @@ def test_server_same_result_alone_and_in_mix():
 
 def test_server_admits_by_footprint():
     from paper_2606_11273_amd import native as nv
-    reqs = [serving_request(k, P_lo=50, P_hi=100) for k in range(10, 14)]
+    # equal sizes, so that every footprint is close to the others and a budget between the
+    # largest footprint and the sum of the two smallest holds exactly one request at a time
+    reqs = [serving_request(k, P_lo=300, P_hi=300) for k in range(10, 14)]
     probe = nv.mfs_server_create(1 << 40, 1)
     try:
         fp = [nv.mfs_server_footprint(probe, r["centers"], r["radii"], r["n_src"], r["n_col"], r["r_src"],
                                       "mobility", "mixed", r["given"], TOL, 300) for r in reqs]
     finally:
         nv.mfs_server_destroy(probe)
-    budget = int(1.5 * max(fp))
-    assert 2 * min(fp) > budget, "budget must hold one request at a time"
+    two_smallest = sum(sorted(fp)[:2])
+    assert two_smallest > max(fp), "footprints too different for a one-at-a-time budget"
+    budget = (max(fp) + two_smallest) // 2
     say("server footprints (MB)", [round(f / 2**20) for f in fp], "budget", budget >> 20)
     srv = nv.mfs_server_create(budget, 3)
     try:
@@ -80,13 +83,6 @@ def test_server_admits_by_footprint():
             t_sub.append(time.perf_counter())
             tickets.append(_submit(nv, srv, r))
         res = [nv.mfs_server_wait(srv, t, r["P"])[1] for t, r in zip(tickets, reqs)]
-        big = serving_request(20, P_lo=2500, P_hi=3000)
-        assert nv.mfs_server_footprint(srv, big["centers"], big["radii"], big["n_src"], big["n_col"], big["r_src"],
-                                       "mobility", "mixed", big["given"], TOL, 1000) > budget
-        with pytest.raises(nv.MFSError) as e:
-            nv.mfs_server_submit(srv, big["centers"], big["radii"], big["n_src"], big["n_col"], big["r_src"],
-                                 "mobility", "mixed", big["given"], TOL, 1000)
-        assert e.value.code == nv.MFS_ERR_ARG and "budget" in str(e.value)
         bad = np.array([[0.0, 0.0], [1.5, 0.0]])
         with pytest.raises(nv.MFSError) as e:
             nv.mfs_server_submit(srv, bad, 1.0, 36, 72, 0.7, "mobility", "mixed", np.zeros((2, 3)), TOL)
@@ -96,6 +92,14 @@ def test_server_admits_by_footprint():
         assert e.value.code == nv.MFS_ERR_ARG
     finally:
         nv.mfs_server_destroy(srv)
+    # a request larger than the whole budget is refused at submission
+    tiny = nv.mfs_server_create(min(fp) // 2, 1)
+    try:
+        with pytest.raises(nv.MFSError) as e:
+            _submit(nv, tiny, reqs[0])
+        assert e.value.code == nv.MFS_ERR_ARG and "budget" in str(e.value)
+    finally:
+        nv.mfs_server_destroy(tiny)
     spans = sorted((t0 + i["ms_queue"] / 1e3, t0 + i["ms_total"] / 1e3) for t0, i in zip(t_sub, res))
     for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
         assert b0 >= a1 - 2e-3, "two requests ran together beyond the budget"
