@@ -57,8 +57,9 @@ typedef enum { MFS_RESISTANCE = 0, MFS_MOBILITY = 1 } mfs_problem;
 
 /* Arithmetic of the all-pairs Stokeslet sum (step 2a of Alg. 3).  Every other step
  * is FP64 in both modes.  MFS_MIXED evaluates the kernel in FP32 on body-relative
- * coordinates with FP64 accumulation; mfs_gmres_solve then refines in FP64
- * (GMRES-IR: FP64 true residual, inner GMRES on the mixed operator). */
+ * coordinates with FP64 accumulation; mfs_gmres_solve then runs GMRES with the
+ * operator relaxed from FP64 to mixed as the residual falls, inside an FP64
+ * refinement on the true residual. */
 typedef enum { MFS_FP64 = 0, MFS_MIXED = 1 } mfs_precision;
 
 /* Method parameters; mfs_default_params fills the paper's values (Sec. 5, Sec. 6). */
@@ -162,8 +163,13 @@ mfs_status mfs_post(mfs_ctx* ctx, mfs_problem prob, const double* mu, double* ou
 /* Full solve (Alg. 2; Sec. 4.4).  rhs: host, n_rhs x P x 3; out: host, n_rhs x P x 3.
  * x0: device, n_rhs x n initial mu, or NULL for zero.  tol: relative residual of
  * the square system; max_iter: cap on GMRES iterations per solve (unrestarted).
- * MFS_FP64 runs GMRES on the FP64 operator; MFS_MIXED runs GMRES-IR (outer FP64
- * residuals, inner GMRES on the mixed operator).  info: host or NULL. */
+ * MFS_FP64 runs GMRES on the FP64 operator.  MFS_MIXED refines in FP64 on the true
+ * residual around a GMRES whose operator applications switch to the mixed kernel sum
+ * once its residual estimate is below tol_inner / delta (relaxed inexact Krylov;
+ * delta = 1e-4, environment MFS_MIXED_DELTA).  Right-hand sides run in lockstep
+ * groups of up to 8 (stacked products, one Krylov basis each).  Each stops on its own
+ * tolerance.  info: host or NULL; with several right-hand sides iters_total sums their
+ * inner iterations, rel_resid is the largest, and matvecs count vectors. */
 mfs_status mfs_gmres_solve(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t n_rhs,
                            const double* rhs, double* out, const double* x0, double tol,
                            int32_t max_iter, mfs_solve_info* info);

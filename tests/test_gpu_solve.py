@@ -1,4 +1,4 @@
-"""End-to-end parity on the GPU: device precompute + GMRES (FP64 and GMRES-IR mixed) + post
+"""End-to-end parity on the GPU: device precompute + GMRES (FP64 and relaxed mixed) + post
 against the FP64 oracle run independently (its own SVDs), on the 4x4 jittered grid
 with min gap 1e-3 (contact threshold 0.5).
 
