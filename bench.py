@@ -99,7 +99,8 @@ def main():
                          "velocities (at the paper's 1e-7 they differ by ~2e-4)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-targets", type=int, default=3000)
+    ap.add_argument("--cpu-targets", type=int, default=8000,
+                    help="targets of the CPU oracle sample (all sources; about 60 CPU-seconds)")
     ap.add_argument("--ksum-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB-in, 1 GiB-out elementwise kernel (reference for HBM counters)")

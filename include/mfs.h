@@ -253,7 +253,8 @@ mfs_status mfs_server_wait(mfs_server* srv, int64_t ticket, double* out, mfs_tic
 const char* mfs_server_last_error(const mfs_server* srv);
 
 /* Stop admitting, finish the running requests, drop the queued ones and release
- * every resource.  srv may be NULL. */
+ * every resource.  srv may be NULL.  No other call on srv may be in progress or made
+ * afterwards (a ticket still queued is dropped, not completed). */
 mfs_status mfs_server_destroy(mfs_server* srv);
 
 #ifdef __cplusplus
