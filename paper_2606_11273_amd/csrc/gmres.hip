@@ -280,13 +280,13 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* swi
 // delta.  In the inexact-Krylov bound (Simoncini & Szyld 2003) delta stands for the
 // mixed operator's relative error over the smallest singular value of the Hessenberg
 // matrix.  The FP32 sum with FP64 disk moments is accurate to a few 1e-6 on smooth
-// data; at P = 10^4 (area fraction 0.65) delta = 1e-4 reached tol 5e-9 in 3
-// refinement steps with 17 of 325 applications in FP64 (1e-3: 32 FP64, 1e-2: 203).
+// data.  At P = 10^4 (area fraction 0.65, tol 5e-9) delta = 1e-6 needed 5 FP64
+// applications of 323 and 2 refinement steps; 1e-4 needed 17, 1e-2 needed 203.
 // MFS_MIXED_DELTA overrides it.
 double mixed_delta() {
   const char* e = std::getenv("MFS_MIXED_DELTA");
-  const double d = e ? std::atof(e) : 1e-4;
-  return d > 0 ? d : 1e-4;
+  const double d = e ? std::atof(e) : 1e-6;
+  return d > 0 ? d : 1e-6;
 }
 
 }  // namespace

@@ -35,7 +35,7 @@ using clk = std::chrono::steady_clock;
 
 // pairs per precompute batch in the server: fixed, so that the batching (and with it
 // every library call's shapes) depends on the request alone
-constexpr int kServerPrecomputeBatch = 64;
+constexpr int kServerPrecomputeBatch = 256;
 
 struct Request {
   int64_t ticket = 0;

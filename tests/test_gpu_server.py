@@ -4,9 +4,9 @@
   different sizes runs through a 3-slot server concurrently and then one at a
   time; the outputs agree to 1e-12 of max |v| + |omega| (the arithmetic of a
   request does not depend on the others, so they are expected to be identical).
-* Admission by device-memory footprint: with a budget that holds one request at a
-  time (four requests of 300 disks), no two requests run together even with 3 slots; a
-  request larger than the whole budget is refused.
+* Admission by device-memory footprint: with a budget of 1.5 footprints (one request
+  submitted four times), no two requests run together even with 3 slots; a request
+  larger than the whole budget is refused.
 * Two small requests agree with the FP64 oracle (eq. rel_vel_err <= 1e-5).
 Requests come from the serving workload generator (area fraction U[0.4, 0.65], min
 gap 10^U[-4,-2], N(0,1) forces and torques with zero net force), with P reduced to
@@ -62,18 +62,16 @@ def test_server_same_result_alone_and_in_mix():
 
 def test_server_admits_by_footprint():
     from paper_2606_11273_amd import native as nv
-    # equal sizes, so that every footprint is close to the others and a budget between the
-    # largest footprint and the sum of the two smallest holds exactly one request at a time
-    reqs = [serving_request(k, P_lo=300, P_hi=300) for k in range(10, 14)]
+    # one request submitted four times: a budget of 1.5 footprints holds exactly one at a time
+    r0 = serving_request(10, P_lo=100, P_hi=100)
+    reqs = [r0] * 4
     probe = nv.mfs_server_create(1 << 40, 1)
     try:
-        fp = [nv.mfs_server_footprint(probe, r["centers"], r["radii"], r["n_src"], r["n_col"], r["r_src"],
-                                      "mobility", "mixed", r["given"], TOL, 300) for r in reqs]
+        fp = [nv.mfs_server_footprint(probe, r0["centers"], r0["radii"], r0["n_src"], r0["n_col"], r0["r_src"],
+                                      "mobility", "mixed", r0["given"], TOL, 300)] * 4
     finally:
         nv.mfs_server_destroy(probe)
-    two_smallest = sum(sorted(fp)[:2])
-    assert two_smallest > max(fp), "footprints too different for a one-at-a-time budget"
-    budget = (max(fp) + two_smallest) // 2
+    budget = fp[0] + fp[0] // 2
     say("server footprints (MB)", [round(f / 2**20) for f in fp], "budget", budget >> 20)
     srv = nv.mfs_server_create(budget, 3)
     try:
