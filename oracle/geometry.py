@@ -93,91 +93,114 @@ def _pair_frame(ci, ck):
     return ci, ck, d, dv / d
 
 
-def ellipse_points(delta, prm):
+def limit_point(a1, a2, d):
+    """Limit point x_1 (distance from the centre of disk 1 toward disk 2) of the coaxal system of
+    two circles of radii a1, a2 at centre distance d: the common fixed point, inside disk 1, of
+    the inversions in both circles, where the images of a source accumulate (Sec. 5; unequal
+    radii by the survey's reading Q23).  For a1 = a2 = 1 it is R_acc(d - 2)."""
+    b = d * d + a1 * a1 - a2 * a2
+    return (b - math.sqrt(b * b - 4.0 * d * d * a1 * a1)) / (2.0 * d)
+
+
+def fine_count(radius, prm):
+    """Fine proxy count of a disk: N_fp scales with the radius (150 at radius 1; reading Q23)."""
+    return int(round(prm.n_fp * radius))
+
+
+def ellipse_points(delta, prm, a1=1.0, a2=1.0):
     """Shielding ellipse nodes z(theta_j) in the body-local frame (pair axis = +x), Sec. 5.
 
-    z(theta) = (a/2)[1 + cos(theta + i alpha)], alpha = arcosh(1 + 2 gamma (1-a)/a),
-    theta_j = (j + 1/2) pi / N_ell, j = 0 .. 2 N_ell - 1; keep |z| > R_f.  Empty
-    when R_acc(delta) <= R_f.  Returned as complex numbers.
+    With x1 the limit point of the disk (radius a1) toward its neighbour (radius a2) at gap
+    delta: z(theta) = (x1/2)[1 + cos(theta + i alpha)], alpha = arcosh(1 + 2 gamma (a1 - x1)/x1),
+    the ellipse with foci 0 and x1 and tip x1 + gamma (a1 - x1); theta_j = (j + 1/2) pi / N_ell,
+    j = 0 .. 2 N_ell - 1; keep |z| > R_f (the disk's proxy radius).  Empty when x1 <= R_f.
+    For unit disks x1 = R_acc(delta).  Returned as complex numbers.
     """
-    Rf = ring_radius(prm.n_fp, prm.eps_ring)
-    a = r_acc(delta)
-    if a <= Rf:
+    Rf = a1 * ring_radius(fine_count(a1, prm), prm.eps_ring)
+    x1 = limit_point(a1, a2, a1 + a2 + delta) if (a1, a2) != (1.0, 1.0) else r_acc(delta)
+    if x1 <= Rf:
         return np.zeros(0, dtype=np.complex128)
-    alpha = math.acosh(1.0 + 2.0 * prm.gamma * (1.0 - a) / a)
+    alpha = math.acosh(1.0 + 2.0 * prm.gamma * (a1 - x1) / x1)
     th = (np.arange(2 * prm.n_ell) + 0.5) * math.pi / prm.n_ell
-    z = 0.5 * a * (1.0 + np.cos(th + 1j * alpha))
+    z = 0.5 * x1 * (1.0 + np.cos(th + 1j * alpha))
     return z[np.abs(z) > Rf]
 
 
-def fine_sources(ci, ck, prm):
-    """Fine source set of the pair (Sec. 5): [proxies_i, ellipse_i, proxies_k, ellipse_k].
+def fine_sources(ci, ck, prm, ai=1.0, ak=1.0):
+    """Fine source set of the pair (Sec. 5): [proxies_i, ellipse_i], [proxies_k, ellipse_k].
 
-    Proxies: N_fp points on the circle of radius R_f about each centre (global
-    angles).  Ellipse sources: c_i + e^{i phi} z_j and c_k - e^{i phi} z_j with
-    e^{i phi} the unit direction from c_i to c_k.  Returns (Y_i (n_i,2), Y_k (n_k,2)).
+    Proxies: N_fp(a) points on the circle of radius a R_f(N_fp(a)) about each centre (global
+    angles).  Ellipse sources: c_i + e^{i phi} z_j (disk i's ellipse) and c_k - e^{i phi} z'_j
+    (disk k's, toward i), with e^{i phi} the unit direction from c_i to c_k.  Returns
+    (Y_i (n_i,2), Y_k (n_k,2)); for equal radii both have the same length.
     """
     ci, ck, d, e = _pair_frame(ci, ck)
-    Rf = ring_radius(prm.n_fp, prm.eps_ring)
-    z = ellipse_points(d - 2.0, prm)
-    ez = (e[0] + 1j * e[1]) * z
-    enh = np.stack([ez.real, ez.imag], axis=1)
-    Yi = np.concatenate([ring(ci, Rf, prm.n_fp), ci[None, :] + enh], axis=0)
-    Yk = np.concatenate([ring(ck, Rf, prm.n_fp), ck[None, :] - enh], axis=0)
-    return Yi, Yk
+    eu = e[0] + 1j * e[1]
+    out = []
+    for c0, a0, a1, sgn in ((ci, ai, ak, 1.0), (ck, ak, ai, -1.0)):
+        nf = fine_count(a0, prm)
+        Rf = a0 * ring_radius(nf, prm.eps_ring)
+        ez = sgn * eu * ellipse_points(d - ai - ak, prm, a0, a1)
+        out.append(np.concatenate([ring(c0, Rf, nf), c0[None, :] + np.stack([ez.real, ez.imag], axis=1)], axis=0))
+    return out[0], out[1]
 
 
-def fine_nodes(ci, ck, prm):
-    """Fine collocation nodes of the pair (Sec. 5): per disk ceil(a_f N_fp) equispaced
+def fine_nodes(ci, ck, prm, ai=1.0, ak=1.0):
+    """Fine collocation nodes of the pair (Sec. 5): per disk ceil(a_f N_fp(a)) equispaced
     nodes plus a_ell N_ell Moebius-mapped nodes theta~ = pi + arg((e^{it} + r)/(1 + r e^{it})),
-    t = 2 pi j / M_ell, placed so that theta~ = pi faces the neighbour (Q15).
-    Returns (X_i, X_k), each (M_f, 2)."""
+    t = 2 pi j / M_ell, on the disk's boundary, placed so that theta~ = pi faces the
+    neighbour (Q15).  Returns (X_i, X_k)."""
     ci, ck, d, e = _pair_frame(ci, ck)
     phi = math.atan2(e[1], e[0])
-    m_eq = int(math.ceil(prm.a_f * prm.n_fp - 1e-12))
     m_ell = int(prm.a_ell * prm.n_ell)
     t = 2.0 * math.pi * np.arange(m_ell) / m_ell
     w = np.exp(1j * t)
     tt = math.pi + np.angle((w + prm.mobius_r) / (1.0 + prm.mobius_r * w))
-    ang_i = phi + tt - math.pi
-    ang_k = phi + tt
-    Xi = np.concatenate([ring(ci, 1.0, m_eq), ci[None, :] + np.stack([np.cos(ang_i), np.sin(ang_i)], axis=1)], axis=0)
-    Xk = np.concatenate([ring(ck, 1.0, m_eq), ck[None, :] + np.stack([np.cos(ang_k), np.sin(ang_k)], axis=1)], axis=0)
-    return Xi, Xk
+    out = []
+    for c0, a0, ang in ((ci, ai, phi + tt - math.pi), (ck, ak, phi + tt)):
+        m_eq = int(math.ceil(prm.a_f * fine_count(a0, prm) - 1e-12))
+        out.append(np.concatenate([ring(c0, a0, m_eq),
+                                   c0[None, :] + a0 * np.stack([np.cos(ang), np.sin(ang)], axis=1)], axis=0))
+    return out[0], out[1]
 
 
-def peanut_nodes(ci, ck, m_p):
-    """M_p nodes uniform in arc length on the peanut of two unit disks (Sec. 3.3, Q16).
+def peanut_nodes(ci, ck, m_p, ai=1.0, ak=1.0, rho=1.0):
+    """M_p nodes uniform in arc length on the peanut of the pair (Sec. 3.3, Q16; unequal radii Q23).
 
-    With e the unit axis from c_i to c_k, n = e^perp, d = |c_k - c_i| and
-    h = sqrt(4 - (d/2)^2), the rolling unit circle touching both disks is centred
-    at m +/- h n (m the midpoint).  psi = atan2(h, d/2).  Going counter-clockwise
-    from the far point of disk i: disk-i arc (angles pi .. 2 pi - psi about c_i),
-    lower concave arc (angles pi - psi down to psi about m - h n), disk-k arc
-    (angles pi + psi .. 3 pi - psi about c_k), upper concave arc (angles -psi down
-    to psi - pi about m + h n), and disk-i arc (psi .. pi).  Angles are measured in
-    the (e, n) frame.  Perimeter 6 pi - 8 psi.
+    The peanut is the outline of the two disks with the concave gaps filled by a circle of
+    radius rho rolled around the pair (rho = 1, the smallest disk).  With e the unit axis
+    from c_i to c_k, n = e^perp and d = |c_k - c_i|, the rolling circle touching both disks
+    is centred at c_i + s e +/- h n, s = ((a_i + rho)^2 - (a_k + rho)^2 + d^2) / (2 d),
+    h = sqrt((a_i + rho)^2 - s^2); it touches disk i at angle psi_i = atan2(h, s) and disk k
+    at pi - psi_k, psi_k = atan2(h, d - s).  Going counter-clockwise from the far point of
+    disk i: disk-i arc (pi .. 2 pi - psi_i about c_i), lower concave arc (pi - psi_i down to
+    psi_k about the lower rolling centre), disk-k arc (pi + psi_k .. 3 pi - psi_k about c_k),
+    upper concave arc (-psi_k down to psi_i - pi about the upper centre), disk-i arc
+    (psi_i .. pi).  Angles in the (e, n) frame.  Unit disks: perimeter 6 pi - 8 psi.
     """
     ci, ck, d, e = _pair_frame(ci, ck)
     n = perp(e)
-    h = math.sqrt(4.0 - 0.25 * d * d)
-    psi = math.atan2(h, 0.5 * d)
-    m = 0.5 * (ci + ck)
-    segs = [  # (centre, start angle, signed sweep)
-        (ci, math.pi, math.pi - psi),
-        (m - h * n, math.pi - psi, -(math.pi - 2.0 * psi)),
-        (ck, math.pi + psi, 2.0 * math.pi - 2.0 * psi),
-        (m + h * n, -psi, -(math.pi - 2.0 * psi)),
-        (ci, psi, math.pi - psi),
+    s = ((ai + rho) ** 2 - (ak + rho) ** 2 + d * d) / (2.0 * d)
+    h = math.sqrt((ai + rho) ** 2 - s * s)
+    psi_i = math.atan2(h, s)
+    psi_k = math.atan2(h, d - s)
+    m_lo = ci + s * e - h * n
+    m_hi = ci + s * e + h * n
+    segs = [  # (centre, radius, start angle, signed sweep)
+        (ci, ai, math.pi, math.pi - psi_i),
+        (m_lo, rho, math.pi - psi_i, -(math.pi - psi_i - psi_k)),
+        (ck, ak, math.pi + psi_k, 2.0 * math.pi - 2.0 * psi_k),
+        (m_hi, rho, -psi_k, -(math.pi - psi_i - psi_k)),
+        (ci, ai, psi_i, math.pi - psi_i),
     ]
-    lengths = np.array([abs(s[2]) for s in segs])
+    lengths = np.array([r * abs(sw) for _, r, _, sw in segs])
     total = lengths.sum()
-    s = np.arange(m_p) * total / m_p
+    t = np.arange(m_p) * total / m_p
     out = np.empty((m_p, 2))
     start = np.concatenate([[0.0], np.cumsum(lengths)[:-1]])
     for p in range(m_p):
-        j = int(np.searchsorted(start, s[p], side="right") - 1)
-        cen, a0, sw = segs[j]
-        ang = a0 + math.copysign(s[p] - start[j], sw)
-        out[p] = cen + math.cos(ang) * e + math.sin(ang) * n
+        j = int(np.searchsorted(start, t[p], side="right") - 1)
+        cen, r, a0, sw = segs[j]
+        ang = a0 + math.copysign((t[p] - start[j]) / r, sw)
+        out[p] = cen + r * (math.cos(ang) * e + math.sin(ang) * n)
     return out

@@ -1,8 +1,8 @@
 """Per-pair precompute of the two-body correction (oracle).
 
-For a near-contact pair (i, k) with coarse one-body data ``ob`` (both disks of the
-same class, unit radius), following Sec. 3.2-3.4 (resistance) and Sec. 4.3-4.4
-(mobility):
+For a near-contact pair (i, k) with coarse one-body data of each disk (unit disks as
+in the paper; radius 1.4 disks by reading Q23), following Sec. 3.2-3.4 (resistance)
+and Sec. 4.3-4.4 (mobility):
 
 * X = [[0, Q^(k,i)], [Q^(i,k), 0]]: rows are the fine nodes of body i then body k,
   columns are lambda_bar^(i) then lambda_bar^(k) (Remark "Symmetrizing pairs").
@@ -38,34 +38,39 @@ from .kernel import stokeslet_matrix
 from .onebody import apply_pinv, truncated_svd
 
 
-def pair_matrices(ci, ck, ob, prm, keep=False):
-    """Precompute A (4N_c x 4N_c), E (6 x 4N_c) and W (4M_c x 4N_c) for the pair (i, k)."""
-    if abs(ob.radius - 1.0) > 1e-14:
-        raise NotImplementedError("the fine pair discretisation of Sec. 5 is for unit disks")
+def pair_matrices(ci, ck, ob, prm, keep=False, ob_k=None):
+    """Precompute A, E and W for the pair (i, k): A (2N_i + 2N_k square), E (6 x (2N_i + 2N_k)),
+    W ((2M_i + 2M_k) x (2N_i + 2N_k)).  ob is disk i's one-body data, ob_k disk k's (default: the
+    same class).  Unequal radii follow reading Q23 (limit points, fine counts scaled with the
+    radius, a rolling unit circle for the peanut)."""
+    ob_i = ob
+    ob_k = ob if ob_k is None else ob_k
+    ai, ak = float(ob_i.radius), float(ob_k.radius)
     ci = np.asarray(ci, dtype=np.float64)
     ck = np.asarray(ck, dtype=np.float64)
     mu = prm.mu
-    mob = ob.problem == "mobility"
-    Yi = ci + ob.Yr
-    Yk = ck + ob.Yr
-    Xi = ci + ob.Xr
-    Xk = ck + ob.Xr
-    Yfi, Yfk = fine_sources(ci, ck, prm)
-    Xfi, Xfk = fine_nodes(ci, ck, prm)
-    z = peanut_nodes(ci, ck, prm.m_p)
+    mob = ob_i.problem == "mobility"
+    Yi = ci + ob_i.Yr
+    Yk = ck + ob_k.Yr
+    Xi = ci + ob_i.Xr
+    Xk = ck + ob_k.Xr
+    Yfi, Yfk = fine_sources(ci, ck, prm, ai, ak)
+    Xfi, Xfk = fine_nodes(ci, ck, prm, ai, ak)
+    z = peanut_nodes(ci, ck, prm.m_p, ai, ak, rho=1.0)
     Yf = np.concatenate([Yfi, Yfk])
     Xf = np.concatenate([Xfi, Xfk])
     Kfi = rigid_map(Yfi, ci)
     Kfk = rigid_map(Yfk, ck)
-    nc2 = 2 * ob.n_src
-    Pi = ob.IL if mob else np.eye(nc2)
+    nci, nck = 2 * ob_i.n_src, 2 * ob_k.n_src
+    Pi_i = ob_i.IL if mob else np.eye(nci)
+    Pi_k = ob_k.IL if mob else np.eye(nck)
 
-    Q_ik = stokeslet_matrix(Xfk, Yi, mu) @ Pi        # body i's basis on body k's fine nodes
-    Q_ki = stokeslet_matrix(Xfi, Yk, mu) @ Pi        # body k's basis on body i's fine nodes
-    mf2 = Q_ik.shape[0]
-    Xmat = np.zeros((2 * mf2, 2 * nc2))
-    Xmat[:mf2, nc2:] = Q_ki
-    Xmat[mf2:, :nc2] = Q_ik
+    Q_ik = stokeslet_matrix(Xfk, Yi, mu) @ Pi_i      # body i's basis on body k's fine nodes
+    Q_ki = stokeslet_matrix(Xfi, Yk, mu) @ Pi_k      # body k's basis on body i's fine nodes
+    mfi, mfk = 2 * Xfi.shape[0], 2 * Xfk.shape[0]
+    Xmat = np.zeros((mfi + mfk, nci + nck))
+    Xmat[:mfi, nci:] = Q_ki
+    Xmat[mfi:, :nci] = Q_ik
 
     Sff = stokeslet_matrix(Xf, Yf, mu)
     Szf = stokeslet_matrix(z, Yf, mu)
@@ -75,7 +80,7 @@ def pair_matrices(ci, ck, ob, prm, keep=False):
         Bfi = rigid_map(Xfi, ci)
         Bfk = rigid_map(Xfk, ck)
         F = Sff @ ILf + block_diag(Bfi @ Kfi.T, Bfk @ Kfk.T)
-        C = Szc @ block_diag(Pi, Pi)
+        C = Szc @ block_diag(Pi_i, Pi_k)
         D = Szf @ ILf
     else:
         F = Sff
@@ -89,11 +94,10 @@ def pair_matrices(ci, ck, ob, prm, keep=False):
     KfT = block_diag(Kfi.T, Kfk.T)
     E = KfT @ G if mob else -(KfT @ G)
 
-    P = ob.P
     Sik = stokeslet_matrix(Xi, Yk, mu)
     Ski = stokeslet_matrix(Xk, Yi, mu)
-    near = np.block([[P @ Pi, Sik @ Pi], [Ski @ Pi, P @ Pi]])
-    cross = np.block([[np.zeros_like(P), Sik @ Pi], [Ski @ Pi, np.zeros_like(P)]])
+    near = np.block([[ob_i.P @ Pi_i, Sik @ Pi_k], [Ski @ Pi_i, ob_k.P @ Pi_k]])
+    cross = np.block([[np.zeros((ob_i.P.shape[0], nci)), Sik @ Pi_k], [Ski @ Pi_i, np.zeros((ob_k.P.shape[0], nck))]])
     W = -(near @ A + cross)
 
     out = dict(A=A, E=E, W=W, n_fine=(Yfi.shape[0], Yfk.shape[0]))

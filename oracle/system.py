@@ -81,9 +81,7 @@ class System:
         if pair_data is None:
             pair_data = []
             for idx, (i, k) in enumerate(self.pairs):
-                if self.cls[i] is not self.cls[k]:
-                    raise NotImplementedError("pairs of different disk classes")
-                pair_data.append(pair_matrices(self.c[i], self.c[k], self.cls[i], prm))
+                pair_data.append(pair_matrices(self.c[i], self.c[k], self.cls[i], prm, ob_k=self.cls[k]))
                 if progress and idx % 50 == 0:
                     print(f"  pair {idx}/{len(self.pairs)}  {time.time() - t0:.1f}s", flush=True)
         self.pd = pair_data

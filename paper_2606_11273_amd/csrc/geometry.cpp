@@ -93,93 +93,109 @@ bool find_contacts(int P, const double* c, const double* a, double delta_c, std:
   return ok;
 }
 
-static void ellipse_nodes(double delta, const FineParams& fp, std::vector<std::complex<double>>& z) {
+double limit_point(double a1, double a2, double d) {
+  const double b = d * d + a1 * a1 - a2 * a2;
+  return (b - std::sqrt(b * b - 4.0 * d * d * a1 * a1)) / (2.0 * d);
+}
+
+int fine_count(double radius, const FineParams& fp) { return (int)std::lround(fp.n_fp * radius); }
+
+// Ellipse nodes of the disk of radius a1 toward its neighbour (radius a2) at gap delta, in the
+// disk's frame with the pair axis along +x: foci 0 and the limit point x1, tip x1 + gamma (a1 - x1).
+static void ellipse_nodes(double delta, double a1, double a2, const FineParams& fp,
+                          std::vector<std::complex<double>>& z) {
   z.clear();
-  const double Rf = ring_rule(fp.n_fp, fp.eps_ring);
-  const double a = accumulation_radius(delta);
-  if (!(a > Rf)) return;
-  const double alpha = std::acosh(1.0 + 2.0 * fp.gamma * (1.0 - a) / a);
+  const double Rf = a1 * ring_rule(fine_count(a1, fp), fp.eps_ring);
+  const double x1 = (a1 == 1.0 && a2 == 1.0) ? accumulation_radius(delta) : limit_point(a1, a2, a1 + a2 + delta);
+  if (!(x1 > Rf)) return;
+  const double alpha = std::acosh(1.0 + 2.0 * fp.gamma * (a1 - x1) / x1);
   const double ch = std::cosh(alpha), sh = std::sinh(alpha);
   for (int j = 0; j < 2 * fp.n_ell; ++j) {
     double th = (j + 0.5) * kPi / fp.n_ell;
     // cos(th + i alpha) = cos th cosh alpha - i sin th sinh alpha
-    std::complex<double> w(0.5 * a * (1.0 + std::cos(th) * ch), -0.5 * a * std::sin(th) * sh);
+    std::complex<double> w(0.5 * x1 * (1.0 + std::cos(th) * ch), -0.5 * x1 * std::sin(th) * sh);
     if (std::abs(w) > Rf) z.push_back(w);
   }
 }
 
-int ellipse_count(double delta, const FineParams& fp) {
+int ellipse_count(double delta, const FineParams& fp, double a1, double a2) {
   std::vector<std::complex<double>> z;
-  ellipse_nodes(delta, fp, z);
+  ellipse_nodes(delta, a1, a2, fp, z);
   return (int)z.size();
 }
 
-void pair_fine_sources(Pt ci, Pt ck, const FineParams& fp, std::vector<Pt>& yi, std::vector<Pt>& yk) {
+void pair_fine_sources(Pt ci, Pt ck, const FineParams& fp, std::vector<Pt>& yi, std::vector<Pt>& yk, double ai,
+                       double ak) {
   double ex = ck.x - ci.x, ey = ck.y - ci.y;
   double d = std::sqrt(ex * ex + ey * ey);
   ex /= d;
   ey /= d;
-  const double Rf = ring_rule(fp.n_fp, fp.eps_ring);
   std::vector<std::complex<double>> z;
-  ellipse_nodes(d - 2.0, fp, z);
-  ring_points(ci, Rf, fp.n_fp, yi);
-  ring_points(ck, Rf, fp.n_fp, yk);
-  for (auto& w : z) {
-    double rx = ex * w.real() - ey * w.imag();
-    double ry = ey * w.real() + ex * w.imag();
-    yi.push_back({ci.x + rx, ci.y + ry});
-    yk.push_back({ck.x - rx, ck.y - ry});
+  for (int side = 0; side < 2; ++side) {
+    const double a0 = side ? ak : ai, a1 = side ? ai : ak, sgn = side ? -1.0 : 1.0;
+    const Pt c0 = side ? ck : ci;
+    std::vector<Pt>& y = side ? yk : yi;
+    const int nf = fine_count(a0, fp);
+    ring_points(c0, a0 * ring_rule(nf, fp.eps_ring), nf, y);
+    ellipse_nodes(d - ai - ak, a0, a1, fp, z);
+    for (auto& w : z) {
+      const double rx = ex * w.real() - ey * w.imag();
+      const double ry = ey * w.real() + ex * w.imag();
+      y.push_back({c0.x + sgn * rx, c0.y + sgn * ry});
+    }
   }
 }
 
-void pair_fine_nodes(Pt ci, Pt ck, const FineParams& fp, std::vector<Pt>& xi, std::vector<Pt>& xk) {
+void pair_fine_nodes(Pt ci, Pt ck, const FineParams& fp, std::vector<Pt>& xi, std::vector<Pt>& xk, double ai,
+                     double ak) {
   const double phi = std::atan2(ck.y - ci.y, ck.x - ci.x);
-  const int m_eq = (int)std::ceil(fp.a_f * fp.n_fp - 1e-12);
   const int m_ell = fp.a_ell * fp.n_ell;
-  ring_points(ci, 1.0, m_eq, xi);
-  ring_points(ck, 1.0, m_eq, xk);
+  ring_points(ci, ai, (int)std::ceil(fp.a_f * fine_count(ai, fp) - 1e-12), xi);
+  ring_points(ck, ak, (int)std::ceil(fp.a_f * fine_count(ak, fp) - 1e-12), xk);
   const double r = fp.mobius_r;
   for (int j = 0; j < m_ell; ++j) {
     double t = 2.0 * kPi * j / m_ell;
     std::complex<double> w(std::cos(t), std::sin(t));
     double tt = kPi + std::arg((w + r) / (1.0 + r * w));
-    double ai = phi + tt - kPi, ak = phi + tt;
-    xi.push_back({ci.x + std::cos(ai), ci.y + std::sin(ai)});
-    xk.push_back({ck.x + std::cos(ak), ck.y + std::sin(ak)});
+    double angi = phi + tt - kPi, angk = phi + tt;
+    xi.push_back({ci.x + ai * std::cos(angi), ci.y + ai * std::sin(angi)});
+    xk.push_back({ck.x + ak * std::cos(angk), ck.y + ak * std::sin(angk)});
   }
 }
 
-void peanut(Pt ci, Pt ck, int m_p, std::vector<Pt>& z) {
+void peanut(Pt ci, Pt ck, int m_p, std::vector<Pt>& z, double ai, double ak, double rho) {
   double ex = ck.x - ci.x, ey = ck.y - ci.y;
   const double d = std::sqrt(ex * ex + ey * ey);
   ex /= d;
   ey /= d;
   const double nx = -ey, ny = ex;  // n = e^perp
-  const double h = std::sqrt(4.0 - 0.25 * d * d);
-  const double psi = std::atan2(h, 0.5 * d);
-  const Pt m{0.5 * (ci.x + ck.x), 0.5 * (ci.y + ck.y)};
-  struct Arc { Pt c; double a0, sweep; };
+  // centre of the rolling circle: distance ai + rho from c_i and ak + rho from c_k
+  const double s = ((ai + rho) * (ai + rho) - (ak + rho) * (ak + rho) + d * d) / (2.0 * d);
+  const double h = std::sqrt((ai + rho) * (ai + rho) - s * s);
+  const double psi_i = std::atan2(h, s), psi_k = std::atan2(h, d - s);
+  const Pt m{ci.x + s * ex, ci.y + s * ey};
+  struct Arc { Pt c; double r, a0, sweep; };
   const Arc arcs[5] = {
-      {ci, kPi, kPi - psi},                                   // disk i, far point -> lower tangency
-      {{m.x - h * nx, m.y - h * ny}, kPi - psi, -(kPi - 2 * psi)},  // lower concave arc
-      {ck, kPi + psi, 2 * kPi - 2 * psi},                     // disk k, lower -> upper tangency
-      {{m.x + h * nx, m.y + h * ny}, -psi, -(kPi - 2 * psi)},       // upper concave arc
-      {ci, psi, kPi - psi},                                   // disk i, upper tangency -> far point
+      {ci, ai, kPi, kPi - psi_i},                                                 // disk i, far point -> lower tangency
+      {{m.x - h * nx, m.y - h * ny}, rho, kPi - psi_i, -(kPi - psi_i - psi_k)},   // lower concave arc
+      {ck, ak, kPi + psi_k, 2 * kPi - 2 * psi_k},                                 // disk k, lower -> upper tangency
+      {{m.x + h * nx, m.y + h * ny}, rho, -psi_k, -(kPi - psi_i - psi_k)},        // upper concave arc
+      {ci, ai, psi_i, kPi - psi_i},                                               // disk i, upper tangency -> far point
   };
   double start[5], total = 0;
-  for (int s = 0; s < 5; ++s) {
-    start[s] = total;
-    total += std::fabs(arcs[s].sweep);
+  for (int q = 0; q < 5; ++q) {
+    start[q] = total;
+    total += arcs[q].r * std::fabs(arcs[q].sweep);
   }
   z.resize(m_p);
   for (int p = 0; p < m_p; ++p) {
     double sp = p * total / m_p;
-    int s = 4;
-    while (s > 0 && sp < start[s]) --s;
-    const Arc& A = arcs[s];
-    double ang = A.a0 + std::copysign(sp - start[s], A.sweep);
+    int q = 4;
+    while (q > 0 && sp < start[q]) --q;
+    const Arc& A = arcs[q];
+    double ang = A.a0 + std::copysign((sp - start[q]) / A.r, A.sweep);
     double ca = std::cos(ang), sa = std::sin(ang);
-    z[p] = {A.c.x + ca * ex + sa * nx, A.c.y + ca * ey + sa * ny};
+    z[p] = {A.c.x + A.r * (ca * ex + sa * nx), A.c.y + A.r * (ca * ey + sa * ny)};
   }
 }
 

@@ -29,20 +29,30 @@ struct FineParams {
   double gamma, a_f, mobius_r, eps_ring;
 };
 
-// Fine source set of a unit-disk pair: proxies on radius R_f about each centre
-// (global angles) and, when R_acc(delta) > R_f, shielding-ellipse sources
-// c_i + e z_j and c_k - e z_j with |z_j| > R_f.  Order: [proxies_i, ellipse_i],
-// [proxies_k, ellipse_k]; both lists have the same length.
-void pair_fine_sources(Pt ci, Pt ck, const FineParams& fp, std::vector<Pt>& yi, std::vector<Pt>& yk);
+// Limit point x_1 (distance from the centre of disk 1 toward disk 2) of two circles of radii
+// a1, a2 at centre distance d: the common fixed point of the inversions in both circles
+// (Sec. 5; unequal radii by reading Q23).  R_acc(d - 2) for unit disks.
+double limit_point(double a1, double a2, double d);
 
-// Number of kept ellipse nodes at gap delta (0 when R_acc(delta) <= R_f).
-int ellipse_count(double delta, const FineParams& fp);
+// Fine proxy count of a disk: n_fp scaled with the radius (reading Q23).
+int fine_count(double radius, const FineParams& fp);
 
-// Fine collocation nodes: ceil(a_f n_fp) equispaced (global angles) and
-// a_ell n_ell Moebius-mapped nodes densest toward the neighbour, per disk.
-void pair_fine_nodes(Pt ci, Pt ck, const FineParams& fp, std::vector<Pt>& xi, std::vector<Pt>& xk);
+// Fine source set of a pair (radii ai, ak): proxies on radius a R_f(N_fp(a)) about each
+// centre (global angles) and, when the limit point lies beyond R_f, shielding-ellipse sources
+// c_i + e z_j and c_k - e z'_j.  Order: [proxies_i, ellipse_i], [proxies_k, ellipse_k].
+void pair_fine_sources(Pt ci, Pt ck, const FineParams& fp, std::vector<Pt>& yi, std::vector<Pt>& yk,
+                       double ai = 1.0, double ak = 1.0);
 
-// m_p peanut nodes, uniform in arc length, counter-clockwise from the far point of disk i.
-void peanut(Pt ci, Pt ck, int m_p, std::vector<Pt>& z);
+// Number of kept ellipse nodes of a disk of radius a1 facing radius a2 at gap delta.
+int ellipse_count(double delta, const FineParams& fp, double a1 = 1.0, double a2 = 1.0);
+
+// Fine collocation nodes: ceil(a_f N_fp(a)) equispaced (global angles) and a_ell n_ell
+// Moebius-mapped nodes densest toward the neighbour, per disk, on its boundary.
+void pair_fine_nodes(Pt ci, Pt ck, const FineParams& fp, std::vector<Pt>& xi, std::vector<Pt>& xk,
+                     double ai = 1.0, double ak = 1.0);
+
+// m_p peanut nodes, uniform in arc length, counter-clockwise from the far point of disk i;
+// the concave arcs belong to a circle of radius rho rolled around the pair.
+void peanut(Pt ci, Pt ck, int m_p, std::vector<Pt>& z, double ai = 1.0, double ak = 1.0, double rho = 1.0);
 
 }  // namespace mfs

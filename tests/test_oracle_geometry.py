@@ -6,8 +6,8 @@ import os
 
 import numpy as np
 
-from oracle.geometry import (contacts, ellipse_points, fine_nodes, fine_sources, peanut_nodes, r_acc,
-                             rigid_map, rigid_projector, ring_radius)
+from oracle.geometry import (contacts, ellipse_points, fine_count, fine_nodes, fine_sources, limit_point,
+                             peanut_nodes, r_acc, rigid_map, rigid_projector, ring_radius)
 from oracle.params import MFSParams
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_parameters.json")
@@ -130,3 +130,87 @@ def test_contacts_brute_force():
     pr = contacts(c, a, 0.2)
     ref = [(i, k) for i in range(300) for k in range(i + 1, 300) if np.linalg.norm(c[i] - c[k]) <= 2.2]
     assert [tuple(p) for p in pr] == ref
+
+
+# -- unequal radii (the bidisperse workload; reading Q23) ---------------------------------------
+
+def _invert_r(p, c, r):
+    v = p - c
+    return c + r * r * v / (v @ v)
+
+
+def test_limit_point_is_fixed_by_both_inversions():
+    # x1 inside disk 1 (radius a1 at the origin) is the common fixed point of the inversions
+    # in both circles: inverting in circle 1 and then in circle 2 returns it.
+    for a1, a2 in ((1.0, 1.4), (1.4, 1.0), (1.0, 1.0), (1.4, 1.4)):
+        for delta in (1e-4, 1e-2, 0.15):
+            d = a1 + a2 + delta
+            p = np.array([limit_point(a1, a2, d), 0.0])
+            q = _invert_r(_invert_r(p, np.zeros(2), a1), np.array([d, 0.0]), a2)
+            assert abs(q[0] - p[0]) < 1e-12 * max(1.0, d) and 0 < p[0] < a1
+            if a1 == a2 == 1.0:
+                assert abs(p[0] - r_acc(delta)) < 1e-14
+
+
+def test_unequal_ellipse_and_fine_sets():
+    prm = MFSParams()
+    assert fine_count(1.0, prm) == 150 and fine_count(1.4, prm) == 210
+    ci = np.array([0.2, -1.0])
+    ang = -0.7
+    e = np.array([math.cos(ang), math.sin(ang)])
+    for ai, ak in ((1.0, 1.4), (1.4, 1.0)):
+        delta = 2e-3
+        ck = ci + (ai + ak + delta) * e
+        for a1, a2, c0, sgn in ((ai, ak, ci, 1), (ak, ai, ck, -1)):
+            z = ellipse_points(delta, prm, a1, a2)
+            x1 = limit_point(a1, a2, ai + ak + delta)
+            major = x1 + 2 * prm.gamma * (a1 - x1)
+            assert z.size > 0
+            assert np.allclose(np.abs(z) + np.abs(z - x1), major, rtol=0, atol=1e-13)
+            assert np.all(np.abs(z) > a1 * ring_radius(fine_count(a1, prm), prm.eps_ring))
+        Yi, Yk = fine_sources(ci, ck, prm, ai, ak)
+        ni, nk = fine_count(ai, prm), fine_count(ak, prm)
+        assert Yi.shape[0] == ni + ellipse_points(delta, prm, ai, ak).size
+        assert Yk.shape[0] == nk + ellipse_points(delta, prm, ak, ai).size
+        assert np.all(np.linalg.norm(Yi - ci, axis=1) < ai) and np.all(np.linalg.norm(Yk - ck, axis=1) < ak)
+        # ellipse sources lie on the centre line, toward the neighbour
+        assert np.all((Yi[ni:] - ci) @ e > 0) and np.all((Yk[nk:] - ck) @ e < 0)
+        Xi, Xk = fine_nodes(ci, ck, prm, ai, ak)
+        assert Xi.shape[0] == math.ceil(1.2 * ni) + 400 and Xk.shape[0] == math.ceil(1.2 * nk) + 400
+        assert np.allclose(np.linalg.norm(Xi - ci, axis=1), ai, atol=1e-13)
+        assert np.allclose(np.linalg.norm(Xk - ck, axis=1), ak, atol=1e-13)
+
+
+def test_unequal_peanut_is_the_rolling_disk_clearance():
+    # The rolling unit circle touching both disks touches the peanut from outside: every
+    # unit disk tangent to one body and not overlapping the other keeps distance >= 1 from
+    # the peanut nodes; no node is inside a body; nodes are uniform in arc length.
+    for ai, ak in ((1.0, 1.4), (1.4, 1.0), (1.4, 1.4)):
+        for delta in (1e-3, 0.05):
+            ci = np.array([0.3, 0.1])
+            ck = ci + (ai + ak + delta) * np.array([math.cos(1.0), math.sin(1.0)])
+            z = peanut_nodes(ci, ck, 400, ai, ak)
+            # perimeter: two disk arcs and two arcs of the rolling unit circle, whose centre
+            # is at distances ai + 1 and ak + 1 from the centres (law of cosines for the angles)
+            d = ai + ak + delta
+            psi_i = math.acos(((ai + 1) ** 2 + d * d - (ak + 1) ** 2) / (2 * (ai + 1) * d))
+            psi_k = math.acos(((ak + 1) ** 2 + d * d - (ai + 1) ** 2) / (2 * (ak + 1) * d))
+            L = 2 * ai * (math.pi - psi_i) + 2 * ak * (math.pi - psi_k) + 2 * (math.pi - psi_i - psi_k)
+            steps = np.linalg.norm(np.diff(np.vstack([z, z[:1]]), axis=0), axis=1)
+            assert np.all(steps <= L / 400 + 1e-12) and np.all(steps > 0.8 * L / 400)
+            assert abs(steps.sum() - L) < 1e-3 * L
+            assert np.all(np.linalg.norm(z - ci, axis=1) > ai - 1e-12)
+            assert np.all(np.linalg.norm(z - ck, axis=1) > ak - 1e-12)
+            for t in np.linspace(0, 2 * math.pi, 97):
+                for c0, r0, c1, r1 in ((ci, ai, ck, ak), (ck, ak, ci, ai)):
+                    p = c0 + (r0 + 1) * np.array([math.cos(t), math.sin(t)])
+                    if np.linalg.norm(p - c1) < r1 + 1 - 1e-12:
+                        continue
+                    dmin = np.min(np.linalg.norm(z - p, axis=1))
+                    assert dmin > 1 - 1e-12 and dmin < 1 + (L / 400) ** 2
+    # equal unit radii: the unit-disk peanut (perimeter 6 pi - 8 psi)
+    ci, ck = np.zeros(2), np.array([2.01, 0.0])
+    z = peanut_nodes(ci, ck, 400)
+    psi = math.atan2(math.sqrt(4 - 2.01 ** 2 / 4), 2.01 / 2)
+    steps = np.linalg.norm(np.diff(np.vstack([z, z[:1]]), axis=0), axis=1)
+    assert abs(steps.sum() - (6 * math.pi - 8 * psi)) < 1e-3

@@ -174,3 +174,47 @@ def test_peanut_compression_reproduces_far_field():
         uf = direct_sum(pts, d["Yf"], beta.reshape(-1, 2))
         uc = direct_sum(pts, Yc, lt.reshape(-1, 2))
         assert np.max(np.abs(uf - uc)) < 1e-7 * np.max(np.abs(uf))
+
+
+# -- unequal radii (the bidisperse workload; reading Q23) ---------------------------------------
+
+def _unequal_pair(delta, a=(1.0, 1.4), ang=0.7, c0=(0.1, 0.2)):
+    c0 = np.array(c0)
+    return np.array([c0, c0 + (a[0] + a[1] + delta) * np.array([math.cos(ang), math.sin(ang)])]), np.array(a)
+
+
+@pytest.mark.parametrize("problem", ["mobility", "resistance"])
+def test_isolated_unequal_pair_is_identity(problem):
+    # P4 for radii 1 and 1.4 (36/72 and 50/100 coarse points): T = I whatever A is.  The
+    # closed masked form gives I exactly; the literal Alg. 3 adds and cancels terms carrying
+    # lambda_bar, which the one-body pseudoinverse of the 50-source disk amplifies ~100x more
+    # than the 36-source one's (1e-10 for unit pairs), so it is held to 1e-8.
+    for delta in (1e-3, 0.05):
+        c, a = _unequal_pair(delta)
+        S = System(c, a, [36, 50], [72, 100], 0.7, problem, SMALL)
+        assert S.pd[0]["A"].shape == (2 * (36 + 50), 2 * (36 + 50))
+        v = np.random.default_rng(1).standard_normal(S.n)
+        assert np.max(np.abs(S.matvec(v) - v)) < 1e-8 * np.max(np.abs(v))
+        assert np.max(np.abs(S.matvec_masked(v) - v)) == 0.0
+
+
+@pytest.mark.parametrize("problem", ["mobility", "resistance"])
+def test_brute_force_unequal_pair(problem):
+    # P5 for radii 1 and 1.4 at gap 1e-3: the compressed method against a direct fine-grid
+    # solve on the pair's own fine sets.  Coarse sizes scale with the radius (paper's 60/72
+    # at radius 1, 84/100 at 1.4, ring rule for the source radius).
+    prm = MFSParams()
+    c, a = _unequal_pair(1e-3)
+    ns = [60, 84]
+    nc = [72, 100]
+    rs = [1 - 12 * math.log(10) / n for n in ns]
+    g = np.random.default_rng(6).standard_normal((2, 3))
+    if problem == "mobility":
+        g[:, :2] -= g[:, :2].mean(0)
+    S = System(c, a, ns, nc, rs, problem, prm)
+    out, _, _ = solve(S, g, 1e-13)
+    Yi, Yk = fine_sources(c[0], c[1], prm, a[0], a[1])
+    Xi, Xk = fine_nodes(c[0], c[1], prm, a[0], a[1])
+    ref = direct_solve([(c[0], Yi, Xi), (c[1], Yk, Xk)], g, problem)
+    err = rel_rigid_error(out, ref).max()
+    assert err < 2e-6, (problem, err)
