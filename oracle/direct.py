@@ -25,8 +25,10 @@ from .kernel import stokeslet_matrix
 from .onebody import apply_pinv, truncated_svd
 
 
-def direct_solve(bodies, given, problem, mu=1.0, eps=1e-11):
-    """bodies: list of (centre, sources (n,2), nodes (m,2)); given: (nb, 3).  Returns (nb, 3)."""
+def direct_solve(bodies, given, problem, mu=1.0, eps=1e-11, strengths=False):
+    """bodies: list of (centre, sources (n,2), nodes (m,2)); given: (nb, 3).  Returns (nb, 3), and
+    with strengths=True also (Y, sigma): the flow is u(x) = S(x, Y) sigma everywhere outside
+    the bodies (mobility: sigma = (I - L) beta + beta_0; resistance: sigma = beta)."""
     Y = np.concatenate([b[1] for b in bodies])
     X = np.concatenate([b[2] for b in bodies])
     K = [rigid_map(b[1], b[0]) for b in bodies]
@@ -50,4 +52,7 @@ def direct_solve(bodies, given, problem, mu=1.0, eps=1e-11):
         r = k.T @ beta[off:off + n]
         out.append(-r if problem == "mobility" else r)
         off += n
+    if strengths:
+        sigma = IL @ beta + beta0 if problem == "mobility" else beta
+        return np.array(out), Y, sigma
     return np.array(out)
