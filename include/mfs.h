@@ -166,8 +166,9 @@ mfs_status mfs_post(mfs_ctx* ctx, mfs_problem prob, const double* mu, double* ou
  * MFS_FP64 runs GMRES on the FP64 operator.  MFS_MIXED refines in FP64 on the true
  * residual around a GMRES whose operator applications switch to the mixed kernel sum
  * once its residual estimate is below tol_inner / delta (relaxed inexact Krylov;
- * delta = 1e-6, environment MFS_MIXED_DELTA).  Right-hand sides run in lockstep
- * groups of up to 8 (stacked products, one Krylov basis each).  Each stops on its own
+ * delta = 1e-6 for mobility, 1e-3 for resistance; environment MFS_MIXED_DELTA).
+ * Right-hand sides run in lockstep groups of up to 8 (stacked products, one Krylov
+ * basis each).  Each stops on its own
  * tolerance.  info: host or NULL; with several right-hand sides iters_total sums their
  * inner iterations, rel_resid is the largest, and matvecs count vectors. */
 mfs_status mfs_gmres_solve(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t n_rhs,

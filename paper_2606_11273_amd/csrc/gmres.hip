@@ -279,14 +279,19 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* swi
 // the FP64 to the mixed kernel sum once the residual estimate is below tol_inner /
 // delta.  In the inexact-Krylov bound (Simoncini & Szyld 2003) delta stands for the
 // mixed operator's relative error over the smallest singular value of the Hessenberg
-// matrix.  The FP32 sum with FP64 disk moments is accurate to a few 1e-6 on smooth
-// data.  At P = 10^4 (area fraction 0.65, tol 5e-9) delta = 1e-6 needed 5 FP64
-// applications of 323 and 2 refinement steps; 1e-4 needed 17, 1e-2 needed 203.
-// MFS_MIXED_DELTA overrides it.
-double mixed_delta() {
+// matrix, so it depends on the problem.  Mobility: the FP32 sum with FP64 disk
+// moments is accurate to a few 1e-6 on smooth data; at P = 10^4 (area fraction 0.65,
+// tol 5e-9) delta = 1e-6 needed 5 FP64 applications of 323 and 2 refinement steps;
+// 1e-4 needed 17, 1e-2 needed 203.  Resistance: the compressed strengths of
+// lubricated pairs are up to ~10^3 times the density, and the FP32 operator error
+// reaches 5e-3 relative at gap 1e-3; delta = 1e-6 (mixed from the first step) left a
+// 3-vector lockstep solve at 7e-6 after 300 iterations where 1e-4 converges, so
+// resistance uses 1e-3.  MFS_MIXED_DELTA overrides both.
+double mixed_delta(int prob) {
+  const double dflt = prob == MFS_MOBILITY ? 1e-6 : 1e-3;
   const char* e = std::getenv("MFS_MIXED_DELTA");
-  const double d = e ? std::atof(e) : 1e-6;
-  return d > 0 ? d : 1e-6;
+  const double d = e ? std::atof(e) : dflt;
+  return d > 0 ? d : dflt;
 }
 
 }  // namespace
@@ -337,7 +342,7 @@ Status solve_one(mfs_ctx* c, int prob, bool mixed, const double* given, double* 
     tot.outer = std::max(tot.outer, o + 1);
     // reach the target in one pass if the operator allows it
     const double tin = tol * bn / rn;
-    const double switch_below = mixed ? std::min(1.0, tin / mixed_delta()) : 0.0;
+    const double switch_below = mixed ? std::min(1.0, tin / mixed_delta(prob)) : 0.0;
     if (std::getenv("MFS_PROFILE"))
       std::fprintf(stderr, "[mfs gmres] refinement %d: |r|/|b| = %.3e, inner tol %.3e, mixed below %.3e\n", o, rel,
                    tin, switch_below);
@@ -404,7 +409,7 @@ Status solve_stacked(mfs_ctx* c, int prob, bool mixed, int R, const double* give
       if (act[q]) {
         any = true;
         tin[q] = tol * bn[q] / rn;
-        sw[q] = mixed ? std::min(1.0, tin[q] / mixed_delta()) : 0.0;
+        sw[q] = mixed ? std::min(1.0, tin[q] / mixed_delta(prob)) : 0.0;
       } else {
         tin[q] = 1.0;
         sw[q] = 1.0;
