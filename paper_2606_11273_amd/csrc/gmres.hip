@@ -10,7 +10,10 @@
 // MFS_MIXED: FP64 iterative refinement around a GMRES whose operator applications
 // switch from FP64 to the mixed operator (FP32 all-pairs sum, FP64 accumulation)
 // once the Arnoldi residual estimate has dropped below tol_inner / delta, delta an
-// upper estimate of the mixed operator's relative error.  This is the relaxation
+// upper estimate of the mixed operator's relative error: a per-problem floor, raised
+// to the error measured on the basis vector at the first switch (one extra mixed
+// application per solve), and raised again by f when a refinement step misses its
+// target by a factor f > 10.  This is the relaxation
 // of inexact Krylov methods (Simoncini & Szyld 2003; Bouras & Fraysse 2005): the
 // operator error tolerated at step k grows like tol / |r_k|, so only the first
 // iterations need FP64, and one Krylov space serves the whole solve instead of
@@ -80,12 +83,29 @@ double dnorm(mfs_ctx* c, const double* v, Status* st) {
 
 // Solve T d = r (starting from d = 0) to |r - T d| <= tol |r| (Givens estimate); d returned in k.d.
 // Operator applications use the mixed kernel sum once the estimate is below switch_below.
-Status gmres_core(mfs_ctx* c, int prob, bool mixed, double switch_below, const double* r, double tol, int maxit,
-                  int* iters, std::vector<double>& hist) {
+// |a - b| / |b| for device vectors of length n; a is overwritten with a - b.
+double rel_diff(mfs_ctx* c, int64_t n, double* a, const double* b, Status* st) {
+  launch_axpby(c->stream, n, -1.0, b, 1.0, a);
+  const double dn = dnorm(c, a, st);
+  if (st->code) return 0.0;
+  const double bn = dnorm(c, b, st);
+  return bn > 0.0 ? dn / bn : 0.0;
+}
+
+// Switch point of the relaxed inner GMRES: the mixed operator is used once the residual
+// estimate is below tol / max(delta, op_err), op_err the measured relative error of the
+// mixed operator (negative while unknown).
+double switch_point(bool mixed, double tol, double delta, double op_err) {
+  return mixed ? std::min(1.0, tol / std::max(delta, op_err)) : 0.0;
+}
+
+Status gmres_core(mfs_ctx* c, int prob, bool mixed, double delta, double& op_err, const double* r, double tol,
+                  int maxit, int* iters, std::vector<double>& hist) {
   Krylov& k = c->kr;
   const int64_t n = k.n;
   const int nblk = mdot_blocks(n);
   Status st;
+  double switch_below = switch_point(mixed, tol, delta, op_err);
   const double beta = dnorm(c, r, &st);
   if (st.code) return st;
   MFS_HIP(hipMemsetAsync(k.d, 0, sizeof(double) * n, c->stream));
@@ -103,8 +123,22 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, double switch_below, const d
   double rel_est = 1.0;
   for (int j = 0; j < maxit; ++j) {
     double* vj = k.V + (int64_t)j * n;
-    const bool use32 = mixed && rel_est <= switch_below;
-    if ((st = apply_T(c, prob, use32, vj, k.w)).code) return st;
+    bool use32 = mixed && rel_est <= switch_below;
+    if (use32 && op_err < 0.0) {
+      // first switch: measure the mixed operator on this basis vector against the FP64
+      // one (which this iteration keeps), then move the switch point if it is worse
+      if ((st = apply_T(c, prob, false, vj, k.w)).code) return st;
+      if ((st = apply_T(c, prob, true, vj, k.tmp)).code) return st;
+      op_err = rel_diff(c, n, k.tmp, k.w, &st);
+      if (st.code) return st;
+      switch_below = switch_point(mixed, tol, delta, op_err);
+      if (prof)
+        std::fprintf(stderr, "[mfs gmres] mixed operator relative error %.2e: switch below %.2e\n", op_err,
+                     switch_below);
+      use32 = false;
+    } else if ((st = apply_T(c, prob, use32, vj, k.w)).code) {
+      return st;
+    }
     // CGS2
     launch_mdot(c->stream, n, j + 1, k.V, n, k.w, k.part, k.hdev, nblk);
     launch_maxpy(c->stream, n, j + 1, k.V, n, k.hdev, k.w);
@@ -159,7 +193,7 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, double switch_below, const d
 // whose estimate reaches its tolerance is frozen (its slot is fed zeros).  The mixed
 // kernel sum is used once every active right-hand side is below its switch point.
 // r, d: R x n; tol, switch_below: R; iters: R.
-Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* switch_below, const double* r,
+Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, double& op_err, const double* r,
                       const double* tol, const bool* active_in, int maxit, int* iters,
                       std::vector<std::vector<double>>& hist) {
   Krylov& k = c->kr;
@@ -169,7 +203,8 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* swi
   const int cap = k.cap;
   const int64_t hstride = 3 * (int64_t)(cap + 2);
   Status st;
-  std::vector<double> beta(R, 0.0), rel(R, 1.0);
+  std::vector<double> beta(R, 0.0), rel(R, 1.0), switch_below(R);
+  for (int q = 0; q < R; ++q) switch_below[q] = switch_point(mixed, tol[q], delta, op_err);
   std::vector<char> active(R, 0);
   std::vector<int> kdone(R, 0);
   std::vector<std::vector<double>> H(R), cs(R), sn(R), g(R);
@@ -200,9 +235,25 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* swi
         if (rel[q] > switch_below[q]) all_low = false;
       }
     if (!any) break;
-    const bool use32 = mixed && all_low;
+    bool use32 = mixed && all_low;
     double* vj = k.V + (int64_t)j * ldv;
-    if ((st = apply_T_rhs(c, prob, use32, R, vj, k.w)).code) return st;
+    if (use32 && op_err < 0.0) {
+      // first switch: measure the mixed operator on the active basis vectors (see gmres_core)
+      if ((st = apply_T_rhs(c, prob, false, R, vj, k.w)).code) return st;
+      if ((st = apply_T_rhs(c, prob, true, R, vj, k.tmp)).code) return st;
+      double e = 0.0;
+      for (int q = 0; q < R; ++q) {
+        if (!active[q]) continue;
+        e = std::max(e, rel_diff(c, n, k.tmp + q * n, k.w + q * n, &st));
+        if (st.code) return st;
+      }
+      op_err = e;
+      for (int q = 0; q < R; ++q) switch_below[q] = switch_point(mixed, tol[q], delta, op_err);
+      if (prof) std::fprintf(stderr, "[mfs gmres x%d] mixed operator relative error %.2e\n", R, op_err);
+      use32 = false;
+    } else if ((st = apply_T_rhs(c, prob, use32, R, vj, k.w)).code) {
+      return st;
+    }
     for (int q = 0; q < R; ++q) {
       if (!active[q]) continue;
       const double* Vq = k.V + q * n;
@@ -286,7 +337,21 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* swi
 // lubricated pairs are up to ~10^3 times the density, and the FP32 operator error
 // reaches 5e-3 relative at gap 1e-3; delta = 1e-6 (mixed from the first step) left a
 // 3-vector lockstep solve at 7e-6 after 300 iterations where 1e-4 converges, so
-// resistance uses 1e-3.  MFS_MIXED_DELTA overrides both.
+// resistance uses 1e-3.  MFS_MIXED_DELTA overrides both.  These are floors: the
+// operator error measured at the first switch raises delta where the geometry makes
+// the FP32 sum less accurate (closer gaps, larger compressed strengths), and a refinement
+// step that misses its target raises it further (escalate).
+// After a refinement step whose true residual missed the target by a factor f, the
+// mixed operator's errors were amplified that much more than delta allowed for (the
+// smallest singular values of the packed system); later steps switch that much later.
+// delta reaches 1 at most (then the mixed operator serves only below the inner target).
+double escalate(double delta, double op_err, double f) {
+  if (!(f > 10.0)) return delta;
+  const double d = std::min(1.0, std::max(delta, op_err) * f);
+  if (std::getenv("MFS_PROFILE")) std::fprintf(stderr, "[mfs gmres] missed by %.2e: delta -> %.2e\n", f, d);
+  return d;
+}
+
 double mixed_delta(int prob) {
   const double dflt = prob == MFS_MOBILITY ? 1e-6 : 1e-3;
   const char* e = std::getenv("MFS_MIXED_DELTA");
@@ -325,6 +390,8 @@ Status solve_one(mfs_ctx* c, int prob, bool mixed, const double* given, double* 
   const int max_outer = mixed ? 10 : 3;
   int used = 0;
   double rel = 1.0;
+  double delta = mixed_delta(prob);
+  double op_err = -1.0;   // measured at the first switch to the mixed operator
   for (int o = 0; o < max_outer; ++o) {
     // r = b - T64 x
     if (o == 0 && !x0) {
@@ -339,15 +406,15 @@ Status solve_one(mfs_ctx* c, int prob, bool mixed, const double* given, double* 
     if (!std::isfinite(rn)) return Status{MFS_ERR_NUMERIC, "non-finite residual"};
     rel = bn > 0 ? rn / bn : 0.0;
     if (rel <= tol || used >= max_iter) break;
+    if (mixed && o > 0) delta = escalate(delta, op_err, rel / tol);
     tot.outer = std::max(tot.outer, o + 1);
     // reach the target in one pass if the operator allows it
     const double tin = tol * bn / rn;
-    const double switch_below = mixed ? std::min(1.0, tin / mixed_delta(prob)) : 0.0;
     if (std::getenv("MFS_PROFILE"))
       std::fprintf(stderr, "[mfs gmres] refinement %d: |r|/|b| = %.3e, inner tol %.3e, mixed below %.3e\n", o, rel,
-                   tin, switch_below);
+                   tin, switch_point(mixed, tin, delta, op_err));
     int it = 0;
-    if ((st = gmres_core(c, prob, mixed, switch_below, k.r, tin, max_iter - used, &it, hist)).code) return st;
+    if ((st = gmres_core(c, prob, mixed, delta, op_err, k.r, tin, max_iter - used, &it, hist)).code) return st;
     used += it;
     launch_axpby(c->stream, n, 1.0, k.d, 1.0, k.x);
     if (it == 0) break;
@@ -378,7 +445,9 @@ Status solve_stacked(mfs_ctx* c, int prob, bool mixed, int R, const double* give
     if (mfs_rhs(c, (mfs_problem)prob, given + 3 * (size_t)c->P * q, k.b + q * n) != MFS_OK) return c->last;
   tot.t_rhs += ms_since(t0);
   t0 = clk::now();
-  std::vector<double> bn(R), rel(R, 1.0), tin(R), sw(R);
+  std::vector<double> bn(R), rel(R, 1.0), tin(R);
+  double delta = mixed_delta(prob);
+  double op_err = -1.0;   // measured at the first switch to the mixed operator
   for (int q = 0; q < R; ++q) {
     bn[q] = dnorm(c, k.b + q * n, &st);
     if (st.code) return st;
@@ -409,13 +478,17 @@ Status solve_stacked(mfs_ctx* c, int prob, bool mixed, int R, const double* give
       if (act[q]) {
         any = true;
         tin[q] = tol * bn[q] / rn;
-        sw[q] = mixed ? std::min(1.0, tin[q] / mixed_delta(prob)) : 0.0;
       } else {
         tin[q] = 1.0;
-        sw[q] = 1.0;
       }
     }
     if (!any) break;
+    if (mixed && o > 0) {
+      double f = 0.0;
+      for (int q = 0; q < R; ++q)
+        if (act[q]) f = std::max(f, rel[q] / tol);
+      delta = escalate(delta, op_err, f);
+    }
     tot.outer = std::max(tot.outer, o + 1);
     if (std::getenv("MFS_PROFILE")) {
       double worst = 0;
@@ -425,7 +498,8 @@ Status solve_stacked(mfs_ctx* c, int prob, bool mixed, int R, const double* give
     int room = max_iter;
     for (int q = 0; q < R; ++q)
       if (act[q]) room = std::min(room, max_iter - used[q]);
-    if ((st = gmres_core_rhs(c, prob, mixed, R, sw.data(), k.r, tin.data(), act.get(), room, it.data(), hist)).code)
+    if ((st = gmres_core_rhs(c, prob, mixed, R, delta, op_err, k.r, tin.data(), act.get(), room, it.data(), hist))
+            .code)
       return st;
     int most = 0;
     for (int q = 0; q < R; ++q) {
@@ -476,6 +550,18 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
   c->cnt_pair_evals = 0;
   c->cnt_mv64 = c->cnt_mv32 = 0;
   SolveTotals tot;
+  // the densities are kept for mfs_get_density / flow evaluation
+  c->mu_count = 0;
+  if (c->mu_cap < n * n_rhs) {
+    if (c->d_mu_last) (void)hipFree(c->d_mu_last);
+    c->d_mu_last = nullptr;
+    c->mu_cap = 0;
+    if (hipMalloc(&c->d_mu_last, sizeof(double) * n * n_rhs) != hipSuccess) {
+      (void)hipGetLastError();
+      return failc(Status{MFS_ERR_OOM, "device allocation of the solution densities failed"});
+    }
+    c->mu_cap = n * n_rhs;
+  }
   for (int r0 = 0; r0 < n_rhs; r0 += R) {
     const int Rc = std::min(R, n_rhs - r0);
     const double* g = rhs + 3 * (size_t)c->P * r0;
@@ -484,7 +570,12 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
     st = Rc == 1 ? solve_one(c, prob, mixed, g, o, x, tol, max_iter, info, tot)
                  : solve_stacked(c, prob, mixed, Rc, g, o, x, tol, max_iter, info, tot);
     if (st.code) return failc(st);
+    if (hipMemcpyAsync(c->d_mu_last + n * r0, c->kr.x, sizeof(double) * n * Rc, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return failc(Status{MFS_ERR_DEVICE, "copy of the solution densities failed"});
   }
+  c->mu_count = n_rhs;
+  c->mu_prob = prob;
   if (info) {
     info->iters_total = tot.iters;
     info->outer_steps = tot.outer;
