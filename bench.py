@@ -13,6 +13,11 @@ is run once beside it for the mixed-vs-FP64 comparison.
 
 Prints one JSON line.  --gpus N > 1 exits: the benchmark runs on one GPU.
 
+--workload bidisperse replaces the packing by disks of radii 1 and 1.4 (assigned 50/50,
+area fraction 0.62, min gap 1e-4; 36/72 and 50/100 coarse points on radius 0.7 a),
+default P = 2000, usually with --rhs 8 (unit torques plus seven N(0,1) right-hand sides
+with zero net force, solved in lockstep).
+
 --serve runs the serving workload instead: a stream of independent mobility solves
 (P ~ U{50..3000}, area fraction U[0.4, 0.65], min gap 10^U[-4,-2], N(0,1) forces and
 torques) through the continuous-batching server; first a saturated pass (all requests
@@ -93,7 +98,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--P", type=int, default=10000)
+    ap.add_argument("--workload", choices=("packed", "bidisperse"), default="packed",
+                    help="packed: unit disks at area fraction 0.65, min gap 1e-3 (default P 10000); "
+                         "bidisperse: radii 1 and 1.4 (50/50) at area fraction 0.62, min gap 1e-4, 36/50 "
+                         "coarse sources (default P 2000)")
+    ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--tol", type=float, default=5e-9,
                     help="relative residual; 5e-9 brings both forms within 1e-5 of each other in the "
                          "velocities (at the paper's 1e-7 they differ by ~2e-4)")
@@ -134,7 +143,8 @@ def main():
         print(*a, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    g = config_geometry(3, P=args.P)
+    bidisperse = args.workload == "bidisperse"
+    g = config_geometry(5 if bidisperse else 3, P=args.P or (2000 if bidisperse else 10000))
     c, a, ns, nc, rs = g["centers"], g["radii"], g["n_src"], g["n_col"], g["r_src"]
     P = c.shape[0]
     given = unit_torques(P)
@@ -154,9 +164,8 @@ def main():
             nv.mfs_kernel_sum(ctx, "mixed", sig, u, 2)
         # two whole matvecs (mixed, then FP64) so that counters also cover the pair-correction
         # kernels; the pair matrices are zeros of the right shapes (same memory traffic)
-        n_pairs = len(nv.mfs_get_pairs(ctx))
-        m = 4 * int(ns[0])
-        nv.mfs_set_pair_matrices(ctx, "mobility", [np.zeros((m, m))] * n_pairs, [np.zeros((6, m))] * n_pairs)
+        sizes = [2 * int(ns[i] + ns[k]) for i, k in nv.mfs_get_pairs(ctx)]
+        nv.mfs_set_pair_matrices(ctx, "mobility", [np.zeros((m, m)) for m in sizes], [np.zeros((6, m)) for m in sizes])
         mu = torch.randn(2 * Nt, dtype=torch.float64, device="cuda")
         w = torch.zeros_like(mu)
         for prec in ("mixed", "fp64"):
@@ -292,8 +301,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"mobility solve, P={P} unit disks, area fraction 0.65, min gap 1e-3, "
-                               f"{n_pairs} close pairs, N_c=36 M_c=72 R_c=0.7, "
+        "config": {"workload": f"mobility solve, P={P} "
+                               + ("disks of radii 1 and 1.4 (50/50), area fraction 0.62, min gap 1e-4, "
+                                  f"{n_pairs} close pairs, N_c/M_c 36/72 and 50/100, R_c=0.7a, "
+                                  if bidisperse else
+                                  f"unit disks, area fraction 0.65, min gap 1e-3, {n_pairs} close pairs, "
+                                  "N_c=36 M_c=72 R_c=0.7, ")
                                + ("unit torques" if args.rhs == 1 else
                                   f"{args.rhs} right-hand sides in lockstep (unit torques + N(0,1))")
                                + f", GMRES tol {args.tol:g}",

@@ -175,6 +175,48 @@ mfs_status mfs_gmres_solve(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, i
                            const double* rhs, double* out, const double* x0, double tol,
                            int32_t max_iter, mfs_solve_info* info);
 
+/* ---------------------------------------------------------------------------------
+ * Flow evaluation after a solve (Sec. 3.3, eq. chi: the source triplet lambda,
+ * lambda_bar, beta that Alg. 2 returns when flowEval is set) and the relative boundary
+ * residual (Sec. 6.1, eqs. residual_x and residual).
+ *
+ * The flow at a point is the sum of every disk's coarse strengths, Pi (lambda_bar +
+ * the compressed pair corrections lambda_tilde), plus for mobility the force/torque
+ * sources lambda_0 = K (K^T K)^{-1} [f; t]; at a point near a close pair (on one of its
+ * two disks, or in the fluid inside its peanut) that pair's compressed strengths are
+ * replaced by its fine sources, -S(x, Yf) Pi_f G [lambda_bar_i; lambda_bar_k] (eq. bfm
+ * in the symmetric form, Pi_f the fine rigid projection for mobility).  All FP64. */
+
+/* Keep (keep != 0) or drop each pair's fine map G (2 (nf_i + nf_k) x 2 (N_i + N_k)
+ * doubles, about 0.9 MB per unit-disk pair), fine source points and peanut geometry in
+ * the next mfs_precompute_pairs calls, for mfs_flow_eval.  Default: not kept.  Matrices
+ * imported with mfs_set_pair_matrices carry no fine factors. */
+mfs_status mfs_keep_fine_factors(mfs_ctx* ctx, int32_t keep);
+
+/* Density mu (device, n = 2 N_t doubles, layout of mfs_apply) of right-hand side rhs
+ * (0-based) of the latest mfs_gmres_solve on ctx (also after MFS_ERR_NOCONV: the
+ * iterate).  MFS_ERR_STATE before any solve, MFS_ERR_ARG for rhs out of range. */
+mfs_status mfs_get_density(const mfs_ctx* ctx, int32_t rhs, double* mu);
+
+/* Velocity u (device, 2 n_pts: (u_x, u_y) per point) at points pts (device, 2 n_pts,
+ * absolute (x, y)) from the density mu (device, n) of problem prob.  body (device,
+ * n_pts): the disk whose boundary holds the point, or -1 for a point in the fluid;
+ * fluid points must lie outside every disk.  given (host, 3P): the forces and torques
+ * of a mobility solve (the lambda_0 sources); ignored for resistance (may be NULL).
+ * Needs the pair precompute of prob with fine factors kept when there are pairs
+ * (MFS_ERR_STATE otherwise).  Synchronous on the context's stream. */
+mfs_status mfs_flow_eval(mfs_ctx* ctx, mfs_problem prob, const double* mu, const double* given,
+                         int64_t n_pts, const double* pts, const int32_t* body, double* u);
+
+/* Relative boundary residual of a solution: n_per_body points per disk at angles
+ * 2 pi (j + 1/2) / n_per_body, eps(x) = |u(x) - (v_i + omega_i (x - c_i)^perp)| with u
+ * from mfs_flow_eval, and *eps_max (host) = max eps / max |v_i + omega_i (x - c_i)^perp|.
+ * rigid (host, 3P): the rigid motions (mobility: the solve's velocities; resistance:
+ * the prescribed velocities); given as for mfs_flow_eval.  eps (device, P n_per_body,
+ * disk-major) receives the pointwise residuals, or NULL.  1 <= n_per_body <= 2^20. */
+mfs_status mfs_boundary_residual(mfs_ctx* ctx, mfs_problem prob, const double* mu, const double* given,
+                                 const double* rigid, int32_t n_per_body, double* eps, double* eps_max);
+
 /* Sizes: P, total sources N_s, total nodes N_t (n = 2 N_t), pairs.  Any pointer may be NULL. */
 mfs_status mfs_get_sizes(const mfs_ctx* ctx, int32_t* P, int64_t* n_sources, int64_t* n_nodes,
                          int64_t* n_pairs);

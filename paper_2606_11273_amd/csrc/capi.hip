@@ -55,9 +55,13 @@ void free_all(mfs_ctx* c) {
                   c->d_out3,    c->d_given,   c->d_sig32, c->d_src64,    c->ps[0].A,  c->ps[0].E,  c->ps[1].A,
                   c->ps[1].E,   c->kr.V,      c->kr.w,    c->kr.part,    c->kr.hdev,  c->kr.x,     c->kr.r,
                   c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
-                  c->d_sig32m,  c->d_bdatm,   c->d_src64m};
+                  c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (const PairSet& ps : c->ps)
+    for (void* p : {(void*)ps.G, (void*)ps.Yf, (void*)ps.KKf, (void*)ps.pgeo, (void*)ps.nf, (void*)ps.d_goff,
+                    (void*)ps.d_yoff})
+      if (p) (void)hipFree(p);
   if (c->kr.hhost) (void)hipHostFree(c->kr.hhost);
   for (void* p : c->class_bufs)
     if (p) (void)hipFree(p);
@@ -406,6 +410,7 @@ mfs_status mfs_set_pair_matrices(mfs_ctx* c, mfs_problem prob, const double* A, 
       hipMemcpy(ps.E, Ec.data(), sizeof(double) * Ec.size(), hipMemcpyHostToDevice) != hipSuccess)
     return fail(c, Status{MFS_ERR_DEVICE, "hipMemcpy of pair matrices failed"});
   ps.ready = true;
+  ps.fine = false;   // imported matrices come without fine factors
   return ok(c);
 }
 

@@ -39,6 +39,15 @@ struct PairSet {
   bool ready = false;
   double* A = nullptr;   // per pair column-major (n x n), n = n_i + n_k, offset aoff[c]
   double* E = nullptr;   // per pair column-major (6 x n), offset 6 * xoff[c]
+  // fine factors for flow evaluation (kept by the precompute on request)
+  bool fine = false;
+  double* G = nullptr;        // per pair column-major (nf x n) fine map, nf = 2 (nf_i + nf_k), offset goff[c]
+  double* Yf = nullptr;       // per pair nf_i + nf_k fine source points (x, y), offset yoff[c]
+  double* KKf = nullptr;      // per pair 2 x 9: (K_f^T K_f)^{-1} of disk i's and disk k's fine sources
+  double* pgeo = nullptr;     // per pair 12: c_i, c_k, a_i, a_k, lower and upper rolling-circle centres
+  int32_t* nf = nullptr;      // per pair 2: fine source counts of disk i and disk k
+  int64_t *d_goff = nullptr, *d_yoff = nullptr;
+  std::vector<int64_t> goff, yoff;   // C + 1 (yoff counts doubles: 2 per fine point)
 };
 
 // GMRES work space, sized on first use, for up to rcap right-hand sides in lockstep.
@@ -68,6 +77,7 @@ struct mfs_ctx {
   rocblas_handle blas = nullptr;
   mfs::Status last;
   int pre_batch = 0;   // pairs per precompute batch; 0: sized from free device memory
+  bool keep_fine = false;  // the precompute keeps each pair's fine map and points (flow evaluation)
 
   // host geometry
   std::vector<double> centers, radii, r_src;
@@ -111,6 +121,14 @@ struct mfs_ctx {
   mfs::PairSet ps[2];
   mfs::Krylov kr;
 
+  // densities of the latest mfs_gmres_solve (n x mu_count) and flow-evaluation work space
+  double* d_mu_last = nullptr;
+  int64_t mu_cap = 0;
+  int mu_count = 0, mu_prob = -1;
+  double4* d_fsrc = nullptr;           // Ns records: sources with the total strengths
+  double *d_ptil = nullptr, *d_sigf = nullptr;   // projected lambda_tilde (xoff[C]); fine strengths (max yoff)
+  int64_t sigf_cap = 0;
+
   // work counters (host side, reset by mfs_gmres_solve)
   int64_t evals_all = 0, evals_skip = 0;     // pair evaluations of one kernel sum per skip mode
   int64_t cnt_pair_evals = 0;
@@ -138,6 +156,17 @@ void launch_finish(mfs_ctx* c, const double* u_sum, const double* mu, const doub
 void launch_rhs_mobility_sources(mfs_ctx* c, const double* given);
 void launch_rhs_resistance(mfs_ctx* c, const double* given, double* b);
 void launch_post(mfs_ctx* c, int prob, const double* lam_bar, double* out3);
+// flow evaluation (kernels.hip)
+void launch_add_rhs_sources(mfs_ctx* c, const double* given, double4* src64);
+bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, int64_t n_pts, const double* pts,
+                              const int32_t* body, double* u);
+void launch_fine_strengths(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, double* ptil,
+                           double* sigf);
+void launch_flow_near(mfs_ctx* c, int prob, int64_t n_pts, const double* pts, const int32_t* body,
+                      const double* ptil, const double* sigf, double* u);
+void launch_boundary_nodes(mfs_ctx* c, int n_per_body, double* pts, int32_t* body);
+void launch_boundary_residual(mfs_ctx* c, int64_t n_pts, const double* pts, const int32_t* body, const double* u,
+                              const double* rigid, double* eps, double* maxima);
 // GMRES helpers
 void launch_mdot(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* part,
                  double* out, int nblk);

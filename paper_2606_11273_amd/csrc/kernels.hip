@@ -849,7 +849,7 @@ __global__ __launch_bounds__(kBodyThreads) void k_rhs_sources(int P, const int* 
                                                              const int* __restrict__ src_off, ClassTab ct,
                                                              const double* __restrict__ centers,
                                                              const double* __restrict__ given,
-                                                             double4* __restrict__ src64) {
+                                                             double4* __restrict__ src64, int accumulate) {
   const int b = blockIdx.x;
   if (b >= P) return;
   const int k = cls[b];
@@ -862,7 +862,13 @@ __global__ __launch_bounds__(kBodyThreads) void k_rhs_sources(int P, const int* 
   const double* Yr = ct.Yr[k];
   for (int j = threadIdx.x; j < ct.nc[k]; j += kBodyThreads) {
     const double yx = Yr[2 * j], yy = Yr[2 * j + 1];
-    src64[src_off[b] + j] = make_double4(cx + yx, cy + yy, a0 - a2 * yy, a1 + a2 * yx);
+    const int64_t o = src_off[b] + j;
+    if (accumulate) {   // add lambda_0 to strengths already packed with their positions
+      src64[o].z += a0 - a2 * yy;
+      src64[o].w += a1 + a2 * yx;
+    } else {
+      src64[o] = make_double4(cx + yx, cy + yy, a0 - a2 * yy, a1 + a2 * yx);
+    }
   }
 }
 
@@ -1001,6 +1007,233 @@ __global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = fma(a, x[i], b * y[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Flow evaluation (Sec. 3.3, eq. chi; the source triplet Alg. 2 returns for flowEval).
+// The far field is the FP64 all-pairs sum of the total coarse strengths Pi (lambda_bar +
+// sum lambda_tilde) (plus lambda_0 for mobility) at the evaluation points; at a point
+// near pair c (on one of its disks, or in the fluid inside its peanut) the pair's
+// compressed strengths Pi lambda_tilde^c are taken out again and its fine correction
+// -S(x, Yf^c) sigma_f^c put in, sigma_f^c = Pi_f G^c [lambda_bar_i; lambda_bar_k].
+
+// Per pair: sigma_f (rows of the compact G times the pair's lambda_bar, then the
+// per-disk rigid projection of the fine sources for mobility) and Pi lambda_tilde.
+__global__ __launch_bounds__(kPairThreads) void k_fine_strengths(
+    int C, int mobility, const int* __restrict__ pairs, const int* __restrict__ cls,
+    const int* __restrict__ src_off, ClassTab ct, const double* __restrict__ centers,
+    const int64_t* __restrict__ xoff, const double* __restrict__ lam_bar, const double* __restrict__ ltil,
+    const double* __restrict__ G, const int64_t* __restrict__ goff, const double* __restrict__ Yf,
+    const int64_t* __restrict__ yoff, const int32_t* __restrict__ nf, const double* __restrict__ KKf,
+    double* __restrict__ ptil, double* __restrict__ sigf) {
+  const int c = blockIdx.x;
+  if (c >= C) return;
+  __shared__ double s_x[4 * kMaxCol];
+  __shared__ double red[48];
+  const int i = pairs[2 * c], k = pairs[2 * c + 1];
+  const int ni = 2 * (src_off[i + 1] - src_off[i]);
+  const int n = (int)(xoff[c + 1] - xoff[c]);
+  for (int q = threadIdx.x; q < n; q += kPairThreads)
+    s_x[q] = q < ni ? lam_bar[2 * (int64_t)src_off[i] + q] : lam_bar[2 * (int64_t)src_off[k] + (q - ni)];
+  __syncthreads();
+  const int nf0 = nf[2 * c], nf1 = nf[2 * c + 1];
+  const int nfr = 2 * (nf0 + nf1);
+  const double* Gc = G + goff[c];
+  double* sc = sigf + yoff[c];
+  for (int r = threadIdx.x; r < nfr; r += kPairThreads) {
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc = fma(Gc[(int64_t)q * nfr + r], s_x[q], acc);
+    sc[r] = acc;
+  }
+  __syncthreads();
+  if (mobility) {
+    const double* yf = Yf + yoff[c];
+    for (int b = 0; b < 2; ++b) {
+      const int s0 = b ? nf0 : 0, s1 = b ? nf0 + nf1 : nf0;
+      const double cx = centers[2 * (b ? k : i)], cy = centers[2 * (b ? k : i) + 1];
+      double f0 = 0, f1 = 0, f2 = 0;
+      for (int q = s0 + threadIdx.x; q < s1; q += kPairThreads) {
+        const double bx = sc[2 * q], by = sc[2 * q + 1];
+        f0 += bx;
+        f1 += by;
+        f2 += -(yf[2 * q + 1] - cy) * bx + (yf[2 * q] - cx) * by;
+      }
+      f0 = block_sum<kPairThreads>(f0, red);
+      f1 = block_sum<kPairThreads>(f1, red + 16);
+      f2 = block_sum<kPairThreads>(f2, red + 32);
+      const double* Q = KKf + 18 * (int64_t)c + 9 * b;
+      const double a0 = Q[0] * f0 + Q[1] * f1 + Q[2] * f2;
+      const double a1 = Q[3] * f0 + Q[4] * f1 + Q[5] * f2;
+      const double a2 = Q[6] * f0 + Q[7] * f1 + Q[8] * f2;
+      __syncthreads();
+      for (int q = s0 + threadIdx.x; q < s1; q += kPairThreads) {
+        sc[2 * q] -= a0 - a2 * (yf[2 * q + 1] - cy);
+        sc[2 * q + 1] -= a1 + a2 * (yf[2 * q] - cx);
+      }
+      __syncthreads();
+    }
+  }
+  // Pi lambda_tilde, disk by disk
+  for (int b = 0; b < 2; ++b) {
+    const int body = b ? k : i;
+    const int kc = cls[body];
+    const int nc = ct.nc[kc];
+    const int64_t off = xoff[c] + (b ? ni : 0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * nc; q += kPairThreads) s_x[q] = ltil[off + q];
+    __syncthreads();
+    if (mobility) project_rigid<kPairThreads>(s_x, nc, ct.Yr[kc], ct.KtKi[kc], red);
+    for (int q = threadIdx.x; q < 2 * nc; q += kPairThreads) ptil[off + q] = s_x[q];
+  }
+}
+
+// Point in the peanut of a pair: pg = c_i, c_k, a_i, a_k, lower and upper centres of the
+// rolling unit circle.  Inside a disk, or in the waist: inside the quadrilateral
+// c_i, m_lo, c_k, m_hi (the rolling circle touches the disks on its edges) and outside
+// both rolling circles.
+__device__ __forceinline__ bool in_peanut(const double* __restrict__ pg, double x, double y) {
+  const double cix = pg[0], ciy = pg[1], ckx = pg[2], cky = pg[3], ai = pg[4], ak = pg[5];
+  const double mx = 0.5 * (cix + ckx), my = 0.5 * (ciy + cky);
+  const double hd = 0.5 * sqrt((ckx - cix) * (ckx - cix) + (cky - ciy) * (cky - ciy));
+  const double rb = hd + fmax(ai, ak);
+  if ((x - mx) * (x - mx) + (y - my) * (y - my) > rb * rb) return false;
+  if ((x - cix) * (x - cix) + (y - ciy) * (y - ciy) <= ai * ai) return true;
+  if ((x - ckx) * (x - ckx) + (y - cky) * (y - cky) <= ak * ak) return true;
+  const double qx[4] = {cix, pg[6], ckx, pg[8]}, qy[4] = {ciy, pg[7], cky, pg[9]};
+  for (int e = 0; e < 4; ++e) {
+    const double ax = qx[e], ay = qy[e], bx = qx[(e + 1) & 3], by = qy[(e + 1) & 3];
+    if ((bx - ax) * (y - ay) - (by - ay) * (x - ax) < 0.0) return false;
+  }
+  const double dlx = x - pg[6], dly = y - pg[7], dhx = x - pg[8], dhy = y - pg[9];
+  return dlx * dlx + dly * dly >= 1.0 && dhx * dhx + dhy * dhy >= 1.0;
+}
+
+__device__ __forceinline__ void stokes_acc(double x, double y, double sx, double sy, double gx, double gy, double& lx,
+                                           double& ly, double& tx, double& ty) {
+  const double dx = x - sx, dy = y - sy;
+  const double r2 = fma(dx, dx, dy * dy);
+  const double lg = ln_f64(r2);
+  const double dot = fma(dx, gx, dy * gy) * rcp_f64(r2);
+  lx = fma(lg, gx, lx);
+  ly = fma(lg, gy, ly);
+  tx = fma(dot, dx, tx);
+  ty = fma(dot, dy, ty);
+}
+
+// One thread per evaluation point: subtract the compressed field and the fine correction
+// of every pair the point is near to.  Boundary points (body >= 0) take the pairs of their
+// disk; fluid points (body < 0) test every pair's peanut.
+__global__ __launch_bounds__(256) void k_flow_near(
+    int64_t n_pts, const double* __restrict__ pts, const int32_t* __restrict__ body, int C,
+    const int* __restrict__ pairs, const int* __restrict__ src_off, const double* __restrict__ Y,
+    const int64_t* __restrict__ xoff, const double* __restrict__ ptil, const double* __restrict__ Yf,
+    const int64_t* __restrict__ yoff, const int32_t* __restrict__ nf, const double* __restrict__ sigf,
+    const double* __restrict__ pgeo, const int* __restrict__ bp_off, const int* __restrict__ bp_list,
+    double scale, double* __restrict__ u) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_pts) return;
+  const double x = pts[2 * t], y = pts[2 * t + 1];
+  const int b = body[t];
+  double lx = 0, ly = 0, tx = 0, ty = 0;
+  auto apply = [&](int c) {
+    const int i = pairs[2 * c], k = pairs[2 * c + 1];
+    const int ni = 2 * (src_off[i + 1] - src_off[i]);
+    for (int s = src_off[i]; s < src_off[i + 1]; ++s) {
+      const int64_t o = xoff[c] + 2 * (s - src_off[i]);
+      stokes_acc(x, y, Y[2 * (int64_t)s], Y[2 * (int64_t)s + 1], ptil[o], ptil[o + 1], lx, ly, tx, ty);
+    }
+    for (int s = src_off[k]; s < src_off[k + 1]; ++s) {
+      const int64_t o = xoff[c] + ni + 2 * (s - src_off[k]);
+      stokes_acc(x, y, Y[2 * (int64_t)s], Y[2 * (int64_t)s + 1], ptil[o], ptil[o + 1], lx, ly, tx, ty);
+    }
+    const int nfp = nf[2 * c] + nf[2 * c + 1];
+    const double* yf = Yf + yoff[c];
+    const double* sf = sigf + yoff[c];
+    for (int q = 0; q < nfp; ++q) stokes_acc(x, y, yf[2 * q], yf[2 * q + 1], sf[2 * q], sf[2 * q + 1], lx, ly, tx, ty);
+  };
+  if (b >= 0) {
+    for (int e = bp_off[b]; e < bp_off[b + 1]; ++e) apply(bp_list[e] >> 1);
+  } else {
+    for (int c = 0; c < C; ++c)
+      if (in_peanut(pgeo + 12 * (int64_t)c, x, y)) apply(c);
+  }
+  u[2 * t] -= scale * fma(-0.5, lx, tx);
+  u[2 * t + 1] -= scale * fma(-0.5, ly, ty);
+}
+
+// n points per disk on its boundary at angles 2 pi (j + 1/2) / n.
+__global__ void k_boundary_nodes(int P, int n, const int* __restrict__ cls, ClassTab ct,
+                                 const double* __restrict__ centers, double* __restrict__ pts,
+                                 int32_t* __restrict__ body) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)P * n) return;
+  const int b = (int)(t / n), j = (int)(t - (int64_t)b * n);
+  const double th = (j + 0.5) * (2.0 * 3.14159265358979323846 / n);
+  const double a = ct.radius[cls[b]];
+  pts[2 * t] = centers[2 * b] + a * cos(th);
+  pts[2 * t + 1] = centers[2 * b + 1] + a * sin(th);
+  body[t] = b;
+}
+
+// eps_t = |u_t - g(x_t)|, g = v + omega (x - c)^perp of the point's body (eq. residual_x);
+// per block the largest eps and |g| go to maxima[2 blk], maxima[2 blk + 1].
+__global__ __launch_bounds__(256) void k_boundary_residual(int64_t n_pts, const double* __restrict__ pts,
+                                                           const int32_t* __restrict__ body,
+                                                           const double* __restrict__ centers,
+                                                           const double* __restrict__ u,
+                                                           const double* __restrict__ rigid,
+                                                           double* __restrict__ eps, double* __restrict__ maxima) {
+  __shared__ double s_e[256], s_g[256];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0, gn = 0.0;
+  if (t < n_pts) {
+    const int b = body[t];
+    const double rx = pts[2 * t] - centers[2 * b], ry = pts[2 * t + 1] - centers[2 * b + 1];
+    const double gx = rigid[3 * b] - rigid[3 * b + 2] * ry, gy = rigid[3 * b + 1] + rigid[3 * b + 2] * rx;
+    const double dx = u[2 * t] - gx, dy = u[2 * t + 1] - gy;
+    e = sqrt(dx * dx + dy * dy);
+    gn = sqrt(gx * gx + gy * gy);
+    if (eps) eps[t] = e;
+  }
+  s_e[threadIdx.x] = e;
+  s_g[threadIdx.x] = gn;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s_e[threadIdx.x] = fmax(s_e[threadIdx.x], s_e[threadIdx.x + h]);
+      s_g[threadIdx.x] = fmax(s_g[threadIdx.x], s_g[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    maxima[2 * blockIdx.x] = s_e[0];
+    maxima[2 * blockIdx.x + 1] = s_g[0];
+  }
+}
+
+// One block folds the per-block maxima: out[0] = max eps, out[1] = max |g|.
+__global__ __launch_bounds__(256) void k_max_pairs(int nblk, const double* __restrict__ maxima,
+                                                   double* __restrict__ out) {
+  __shared__ double s_e[256], s_g[256];
+  double e = 0.0, g = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += 256) {
+    e = fmax(e, maxima[2 * q]);
+    g = fmax(g, maxima[2 * q + 1]);
+  }
+  s_e[threadIdx.x] = e;
+  s_g[threadIdx.x] = g;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s_e[threadIdx.x] = fmax(s_e[threadIdx.x], s_e[threadIdx.x + h]);
+      s_g[threadIdx.x] = fmax(s_g[threadIdx.x], s_g[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s_e[0];
+    out[1] = s_g[0];
+  }
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -1180,7 +1413,12 @@ void launch_finish(mfs_ctx* c, const double* u_sum, const double* mu, const doub
 
 void launch_rhs_mobility_sources(mfs_ctx* c, const double* given) {
   hipLaunchKernelGGL(k_rhs_sources, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
-                     c->ct[MFS_MOBILITY], c->d_centers, given, c->d_src64);
+                     c->ct[MFS_MOBILITY], c->d_centers, given, c->d_src64, 0);
+}
+
+void launch_add_rhs_sources(mfs_ctx* c, const double* given, double4* src64) {
+  hipLaunchKernelGGL(k_rhs_sources, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
+                     c->ct[MFS_MOBILITY], c->d_centers, given, src64, 1);
 }
 
 void launch_rhs_resistance(mfs_ctx* c, const double* given, double* b) {
@@ -1223,6 +1461,80 @@ void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, doub
 
 void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, double* y) {
   hipLaunchKernelGGL(k_axpby, dim3(nblocks(n, 256)), dim3(256), 0, s, n, a, x, b, y);
+}
+
+
+// ---------------------------------------------------------------------------
+// flow evaluation launchers
+
+bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, int64_t n_pts, const double* pts,
+                              const int32_t* body, double* u) {
+  if (n_pts == 0) return true;
+  const int T = ksum_targets_per_thread(false);
+  const int64_t tblocks = (n_pts + KS_THREADS * T - 1) / (KS_THREADS * T);
+  const int ns = ksum_splits(tblocks, c->P);
+  const int bps = (c->P + ns - 1) / ns;
+  double* out = u;
+  if (ns > 1) {
+    const int64_t need = (int64_t)ns * n_pts * 2;
+    if (c->upart_cap < need) {
+      if (c->d_upart) (void)hipFree(c->d_upart);
+      c->d_upart = nullptr;
+      if (hipMalloc(&c->d_upart, need * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->d_upart = nullptr;
+        c->upart_cap = 0;
+        return false;
+      }
+      c->upart_cap = need;
+    }
+    out = c->d_upart;
+  }
+  const double scale = 1.0 / (4.0 * kPiD * c->prm.mu);
+  dim3 grid((unsigned)tblocks, (unsigned)ns);
+#define MFS_KP(TT)                                                                                          \
+  hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, src, n_pts, \
+                     body, pts, bps, 0, c->d_nbr_off, c->d_nbr_list, scale, out)
+  if (T == 4) MFS_KP(4); else if (T == 1) MFS_KP(1); else MFS_KP(2);
+#undef MFS_KP
+  if (ns > 1)
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * n_pts, 256)), dim3(256), 0, c->stream, 2 * n_pts, ns,
+                       c->d_upart, u);
+  return true;
+}
+
+void launch_fine_strengths(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, double* ptil,
+                           double* sigf) {
+  const int C = (int)(c->pairs.size() / 2);
+  if (C == 0) return;
+  const PairSet& ps = c->ps[prob];
+  hipLaunchKernelGGL(k_fine_strengths, dim3(C), dim3(kPairThreads), 0, c->stream, C, prob == MFS_MOBILITY ? 1 : 0,
+                     c->d_pairs, c->d_cls, c->d_src_off, c->ct[prob], c->d_centers, c->d_xoff, lam_bar, ltil, ps.G,
+                     ps.d_goff, ps.Yf, ps.d_yoff, ps.nf, ps.KKf, ptil, sigf);
+}
+
+void launch_flow_near(mfs_ctx* c, int prob, int64_t n_pts, const double* pts, const int32_t* body,
+                      const double* ptil, const double* sigf, double* u) {
+  const int C = (int)(c->pairs.size() / 2);
+  if (C == 0 || n_pts == 0) return;
+  const PairSet& ps = c->ps[prob];
+  hipLaunchKernelGGL(k_flow_near, dim3(nblocks(n_pts, 256)), dim3(256), 0, c->stream, n_pts, pts, body, C,
+                     c->d_pairs, c->d_src_off, c->d_Y, c->d_xoff, ptil, ps.Yf, ps.d_yoff, ps.nf, sigf, ps.pgeo,
+                     c->d_bp_off, c->d_bp_list, 1.0 / (4.0 * kPiD * c->prm.mu), u);
+}
+
+void launch_boundary_nodes(mfs_ctx* c, int n_per_body, double* pts, int32_t* body) {
+  const int64_t n = (int64_t)c->P * n_per_body;
+  hipLaunchKernelGGL(k_boundary_nodes, dim3(nblocks(n, 256)), dim3(256), 0, c->stream, c->P, n_per_body, c->d_cls,
+                     c->ct[0], c->d_centers, pts, body);
+}
+
+void launch_boundary_residual(mfs_ctx* c, int64_t n_pts, const double* pts, const int32_t* body, const double* u,
+                              const double* rigid, double* eps, double* maxima) {
+  const unsigned nb = nblocks(n_pts, 256);
+  hipLaunchKernelGGL(k_boundary_residual, dim3(nb), dim3(256), 0, c->stream, n_pts, pts, body, c->d_centers, u,
+                     rigid, eps, maxima + 2);
+  hipLaunchKernelGGL(k_max_pairs, dim3(1), dim3(256), 0, c->stream, (int)nb, maxima + 2, maxima);
 }
 
 }  // namespace mfs

@@ -10,9 +10,11 @@
 //   A  = -C^+ (D G)  (truncated SVD, 1e-14 relative)
 //   E  = +-blockdiag(Kf_i^T, Kf_k^T) G   (+ mobility velocities, - resistance forces)
 // Matrices are filled by a kernel of this file, factorised by rocSOLVER's batched
-// SVD and multiplied with rocBLAS GEMMs; pairs are processed in batches whose fine
-// source lists are zero-padded to a common length (zero columns do not change the
-// truncated pseudoinverse).
+// SVD and multiplied with rocBLAS GEMMs; pairs are processed in batches of one class
+// combination (class of disk i, class of disk k) whose fine source lists are zero-padded
+// per disk to a common length (zero columns do not change the truncated pseudoinverse).
+// The paper's fine sets are for unit disks; a disk of radius a gets fine counts scaled by a,
+// the limit point of its two circles and a rolling unit circle for the peanut.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -126,43 +128,44 @@ struct PairGeo {
   int nf[2];
   double c[2][2];
   double KKf[2][9];      // fine (K^T K)^{-1} per body
+  double KKc[2][9];      // coarse (K^T K)^{-1} per body (its class)
 };
 
+// Sizes of one batch (all its pairs have the same disk classes on each side).
 struct BatchDims {
-  int mf;      // fine nodes per disk
-  int nfpad;   // padded fine sources per disk
-  int nc;      // coarse sources per disk
-  int mp;      // peanut nodes
-  int64_t ldF, ldD;  // = 4 mf, 2 mp
+  int mf[2];     // fine nodes of disk i, disk k
+  int nfpad[2];  // padded fine sources of disk i, disk k
+  int nc[2];     // coarse sources of disk i, disk k
+  int mp;        // peanut nodes
+  int64_t ldF, ldD;  // = 2 (mf0 + mf1), 2 mp
   int64_t sF, sX, sD, sC;  // batch strides
 };
 
 // One thread per target point of one matrix; blockIdx.y = pair in batch, blockIdx.z = matrix (0 F, 1 X, 2 D, 3 C).
 __global__ __launch_bounds__(64) void k_fill(const PairGeo* __restrict__ geo, BatchDims d, int mobility, double kscale,
-                                             const double* __restrict__ KKc, double* F, double* X, double* D,
-                                             double* Cm) {
+                                             double* F, double* X, double* D, double* Cm) {
   const int p = blockIdx.y;
   const int which = blockIdx.z;
   const PairGeo& g = geo[p];
-  const int npts = (which <= 1) ? 2 * d.mf : d.mp;
+  const int npts = (which <= 1) ? d.mf[0] + d.mf[1] : d.mp;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= npts) return;
   SrcBlock blk[2];
   const bool fine_cols = (which == 0 || which == 2);
   for (int b = 0; b < 2; ++b) {
     blk[b].y = fine_cols ? g.yf[b] : g.yc[b];
-    blk[b].n = fine_cols ? g.nf[b] : d.nc;
-    blk[b].col0 = b * (fine_cols ? d.nfpad : d.nc);
+    blk[b].n = fine_cols ? g.nf[b] : d.nc[b];
+    blk[b].col0 = b == 0 ? 0 : (fine_cols ? d.nfpad[0] : d.nc[0]);
     blk[b].cx = g.c[b][0];
     blk[b].cy = g.c[b][1];
-    blk[b].KKi = fine_cols ? g.KKf[b] : KKc;
+    blk[b].KKi = fine_cols ? g.KKf[b] : g.KKc[b];
   }
   double x, y;
   int rb = -1;
   if (which <= 1) {
     x = g.xf[2 * t];
     y = g.xf[2 * t + 1];
-    rb = t < d.mf ? 0 : 1;
+    rb = t < d.mf[0] ? 0 : 1;
   } else {
     x = g.z[2 * t];
     y = g.z[2 * t + 1];
@@ -200,19 +203,34 @@ __global__ __launch_bounds__(256) void k_trunc_scale(int nsv, const double* __re
   T[p * sT + (int64_t)col * ld + j] *= f;
 }
 
-// E = sgn blockdiag(Kf_i^T, Kf_k^T) G for each pair; G column-major (2 * 2 nfpad) x ncols.
+// Keep G of each pair in compact form for flow evaluation: the rows of the padded
+// per-batch G (disk i's fine sources at 0, disk k's at 2 nfpad0) go to rows 0..2 nf_i and
+// 2 nf_i..2 (nf_i + nf_k) of a column-major (2 (nf_i + nf_k)) x ncols block at goff[q].
+__global__ __launch_bounds__(256) void k_store_fine(int ncols, int nfpad0, const int32_t* __restrict__ nfq,
+                                                    const double* __restrict__ G, int64_t sG, int64_t ldG,
+                                                    double* __restrict__ Gout, const int64_t* __restrict__ goff) {
+  const int col = blockIdx.x, q = blockIdx.y;
+  if (col >= ncols) return;
+  const int nf0 = nfq[2 * q], nf1 = nfq[2 * q + 1];
+  const int nfr = 2 * (nf0 + nf1);
+  const double* src = G + q * sG + (int64_t)col * ldG;
+  double* dst = Gout + goff[q] + (int64_t)col * nfr;
+  for (int rr = threadIdx.x; rr < nfr; rr += 256) dst[rr] = src[rr < 2 * nf0 ? rr : 2 * nfpad0 + (rr - 2 * nf0)];
+}
+
+// E = sgn blockdiag(Kf_i^T, Kf_k^T) G for each pair; G column-major (2 (nfpad0 + nfpad1)) x ncols.
 __global__ void k_extract(const PairGeo* __restrict__ geo, BatchDims d, const double* __restrict__ G, int64_t sG,
                           double sgn, double* __restrict__ E, const int64_t* __restrict__ eoff) {
   const int p = blockIdx.y;
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ncols = 4 * d.nc;
+  const int ncols = 2 * (d.nc[0] + d.nc[1]);
   if (col >= ncols) return;
   const PairGeo& g = geo[p];
-  const double* Gc = G + p * sG + (int64_t)col * (4 * d.nfpad);
+  const double* Gc = G + p * sG + (int64_t)col * (2 * (d.nfpad[0] + d.nfpad[1]));
   for (int b = 0; b < 2; ++b) {
     double f0 = 0, f1 = 0, f2 = 0;
     for (int s = 0; s < g.nf[b]; ++s) {
-      const int64_t r = 2 * (int64_t)(b * d.nfpad + s);
+      const int64_t r = 2 * (int64_t)((b == 0 ? 0 : d.nfpad[0]) + s);
       const double gx = Gc[r], gy = Gc[r + 1];
       const double rx = g.yf[b][2 * s] - g.c[b][0], ry = g.yf[b][2 * s + 1] - g.c[b][1];
       f0 += gx;
@@ -418,27 +436,57 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
   }
   FineParams fp{c->prm.n_fp, c->prm.n_ell, c->prm.m_p, c->prm.a_ell, c->prm.gamma, c->prm.a_f, c->prm.mobius_r,
                 c->prm.eps_ring};
-  for (int p = 0; p < C; ++p) {
-    const int i = c->pairs[2 * p], k = c->pairs[2 * p + 1];
-    if (c->cls[i] != c->cls[k]) return Status{MFS_ERR_ARG, "pair of disks of different classes is not supported"};
-    if (std::fabs(c->radii[i] - 1.0) > 1e-14)
-      return Status{MFS_ERR_ARG, "the fine pair discretisation is defined for unit disks"};
-  }
-  const int mf = (int)std::ceil(fp.a_f * fp.n_fp - 1e-12) + fp.a_ell * fp.n_ell;
   const int mp = fp.m_p;
   const double kscale = 1.0 / (4.0 * kPiD * c->prm.mu);
   const int mobility = prob == MFS_MOBILITY ? 1 : 0;
   const ClassTab& ct = c->ct[prob];
+  auto fine_nodes_of = [&](double a) { return (int)std::ceil(fp.a_f * fine_count(a, fp) - 1e-12) + fp.a_ell * fp.n_ell; };
 
-  // order pairs by fine-source count so each batch pads little
-  std::vector<int> order(C), nfe(C);
+  // Order pairs by (class of disk i, class of disk k, fine-source count): a batch holds one
+  // class combination (equal matrix shapes) and pads little.
+  std::vector<int> order(C), nfe0(C), nfe1(C);
   for (int p = 0; p < C; ++p) {
     const int i = c->pairs[2 * p], k = c->pairs[2 * p + 1];
     const double dx = c->centers[2 * k] - c->centers[2 * i], dy = c->centers[2 * k + 1] - c->centers[2 * i + 1];
-    nfe[p] = fp.n_fp + ellipse_count(std::sqrt(dx * dx + dy * dy) - 2.0, fp);
+    const double ai = c->radii[i], ak = c->radii[k], gap = std::sqrt(dx * dx + dy * dy) - ai - ak;
+    nfe0[p] = fine_count(ai, fp) + ellipse_count(gap, fp, ai, ak);
+    nfe1[p] = fine_count(ak, fp) + ellipse_count(gap, fp, ak, ai);
     order[p] = p;
   }
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nfe[a] < nfe[b]; });
+  auto type_of = [&](int p) { return c->cls[c->pairs[2 * p]] * kMaxClasses + c->cls[c->pairs[2 * p + 1]]; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (type_of(a) != type_of(b)) return type_of(a) < type_of(b);
+    return std::max(nfe0[a], nfe1[a]) < std::max(nfe0[b], nfe1[b]);
+  });
+  double rmax = 0.0;
+  for (int i = 0; i < c->P; ++i) rmax = std::max(rmax, c->radii[i]);
+  const int mf = fine_nodes_of(rmax);
+
+  // Fine factors for flow evaluation: each pair's G (compact rows), fine points, fine
+  // (K^T K)^{-1} and peanut geometry, kept when the context asks for them.
+  for (void** q : {(void**)&ps.G, (void**)&ps.Yf, (void**)&ps.KKf, (void**)&ps.pgeo, (void**)&ps.nf,
+                   (void**)&ps.d_goff, (void**)&ps.d_yoff}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  ps.fine = false;
+  const bool keep = c->keep_fine;
+  std::vector<double> h_Yf, h_KKf, h_pgeo;
+  std::vector<int32_t> h_nf;
+  if (keep) {
+    ps.goff.assign(C + 1, 0);
+    ps.yoff.assign(C + 1, 0);
+    for (int p = 0; p < C; ++p) {
+      const int64_t nfr = 2 * (int64_t)(nfe0[p] + nfe1[p]);
+      ps.goff[p + 1] = ps.goff[p] + nfr * (c->xoff[p + 1] - c->xoff[p]);
+      ps.yoff[p + 1] = ps.yoff[p] + nfr;
+    }
+    MFS_HIP(hipMalloc(&ps.G, sizeof(double) * std::max<int64_t>(1, ps.goff[C])));
+    h_Yf.assign(ps.yoff[C], 0.0);
+    h_KKf.assign(18 * (size_t)C, 0.0);
+    h_pgeo.assign(12 * (size_t)C, 0.0);
+    h_nf.assign(2 * (size_t)C, 0);
+  }
 
   const bool prof = std::getenv("MFS_PROFILE") != nullptr;
   double tstage[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -455,7 +503,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
   {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-      const int nfmax = fp.n_fp + 2 * fp.n_ell;
+      const int nfmax = fine_count(rmax, fp) + 2 * fp.n_ell;
       const double per_pair = 8.0 * (2.0 * (4.0 * mf) * (4.0 * nfmax) + 2.0 * (4.0 * nfmax) * (4.0 * nfmax) +
                                      6.0 * (4.0 * mf + 2.0 * mp) * 4.0 * kMaxCol / 4.0);
       const double cap = 0.5 * (double)free_b / per_pair;
@@ -465,26 +513,31 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     const char* env = std::getenv("MFS_PRECOMPUTE_BATCH");
     if (env) batch = std::max(1, std::atoi(env));
   }
-  for (int b0 = 0; b0 < C; b0 += batch) {
+  for (int b0 = 0; b0 < C;) {
     auto t0 = std::chrono::steady_clock::now();
-    const int nb = std::min(batch, C - b0);
-    int nfpad = 0;
-    for (int q = 0; q < nb; ++q) nfpad = std::max(nfpad, nfe[order[b0 + q]]);
-    const int nc = ct.nc[c->cls[c->pairs[2 * order[b0]]]];
+    int nb = 0;
+    while (nb < batch && b0 + nb < C && type_of(order[b0 + nb]) == type_of(order[b0])) ++nb;
+    const int ci0 = c->cls[c->pairs[2 * order[b0]]], ck0 = c->cls[c->pairs[2 * order[b0] + 1]];
     BatchDims d;
-    d.mf = mf;
-    d.nfpad = nfpad;
-    d.nc = nc;
+    d.nfpad[0] = d.nfpad[1] = 0;
+    for (int q = 0; q < nb; ++q) {
+      d.nfpad[0] = std::max(d.nfpad[0], nfe0[order[b0 + q]]);
+      d.nfpad[1] = std::max(d.nfpad[1], nfe1[order[b0 + q]]);
+    }
+    d.nc[0] = ct.nc[ci0];
+    d.nc[1] = ct.nc[ck0];
+    d.mf[0] = fine_nodes_of(ct.radius[ci0]);
+    d.mf[1] = fine_nodes_of(ct.radius[ck0]);
     d.mp = mp;
-    d.ldF = 4 * mf;
+    d.ldF = 2 * (d.mf[0] + d.mf[1]);
     d.ldD = 2 * mp;
-    const int64_t m = 4 * mf, n = 4 * nfpad, nx = 4 * nc, mpp = 2 * mp;
+    const int64_t m = d.ldF, n = 2 * (d.nfpad[0] + d.nfpad[1]), nx = 2 * (d.nc[0] + d.nc[1]), mpp = 2 * mp;
     d.sF = m * n;
     d.sX = m * nx;
     d.sD = mpp * n;
     d.sC = mpp * nx;
     // host staging: geometry
-    const int64_t per_pair = 2 * (2 * nfpad) + 2 * (2 * nc) + 2 * (2 * mf) + 2 * mp;
+    const int64_t per_pair = 2 * (d.nfpad[0] + d.nfpad[1]) + 2 * (d.nc[0] + d.nc[1]) + 2 * (d.mf[0] + d.mf[1]) + 2 * mp;
     std::vector<double> stage((size_t)per_pair * nb, 0.0);
     std::vector<PairGeo> geo(nb);
     DevMem dstage, dgeo;
@@ -496,31 +549,42 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       const int p = order[b0 + q];
       const int i = c->pairs[2 * p], k = c->pairs[2 * p + 1];
       const Pt ci{c->centers[2 * i], c->centers[2 * i + 1]}, ck{c->centers[2 * k], c->centers[2 * k + 1]};
+      const double ai = c->radii[i], ak = c->radii[k];
       std::vector<Pt> yi, yk, xi, xk, z;
-      pair_fine_sources(ci, ck, fp, yi, yk);
-      pair_fine_nodes(ci, ck, fp, xi, xk);
-      peanut(ci, ck, mp, z);
+      pair_fine_sources(ci, ck, fp, yi, yk, ai, ak);
+      pair_fine_nodes(ci, ck, fp, xi, xk, ai, ak);
+      peanut(ci, ck, mp, z, ai, ak);
+      if ((int)xi.size() != d.mf[0] || (int)xk.size() != d.mf[1] || (int)yi.size() > d.nfpad[0] ||
+          (int)yk.size() > d.nfpad[1])
+        return Status{MFS_ERR_ARG, "pair fine set sizes disagree with the batch dimensions"};
       double* base = stage.data() + (size_t)q * per_pair;
-      const int64_t o_yf0 = 0, o_yf1 = 2 * nfpad, o_yc0 = 4 * nfpad, o_yc1 = 4 * nfpad + 2 * nc,
-                    o_xf = 4 * nfpad + 4 * nc, o_z = o_xf + 4 * mf;
+      const int64_t o_yf0 = 0, o_yf1 = 2 * d.nfpad[0], o_yc0 = o_yf1 + 2 * d.nfpad[1], o_yc1 = o_yc0 + 2 * d.nc[0],
+                    o_xf = o_yc1 + 2 * d.nc[1], o_z = o_xf + 2 * (d.mf[0] + d.mf[1]);
       for (size_t s = 0; s < yi.size(); ++s) {
         base[o_yf0 + 2 * s] = yi[s].x;
         base[o_yf0 + 2 * s + 1] = yi[s].y;
+      }
+      for (size_t s = 0; s < yk.size(); ++s) {
         base[o_yf1 + 2 * s] = yk[s].x;
         base[o_yf1 + 2 * s + 1] = yk[s].y;
       }
-      const std::vector<double>& yr = c->h_Yr[c->cls[i]];
-      for (int s = 0; s < nc; ++s) {
-        base[o_yc0 + 2 * s] = ci.x + yr[2 * s];
-        base[o_yc0 + 2 * s + 1] = ci.y + yr[2 * s + 1];
-        base[o_yc1 + 2 * s] = ck.x + yr[2 * s];
-        base[o_yc1 + 2 * s + 1] = ck.y + yr[2 * s + 1];
+      const std::vector<double>& yri = c->h_Yr[c->cls[i]];
+      const std::vector<double>& yrk = c->h_Yr[c->cls[k]];
+      for (int s = 0; s < d.nc[0]; ++s) {
+        base[o_yc0 + 2 * s] = ci.x + yri[2 * s];
+        base[o_yc0 + 2 * s + 1] = ci.y + yri[2 * s + 1];
       }
-      for (int s = 0; s < mf; ++s) {
+      for (int s = 0; s < d.nc[1]; ++s) {
+        base[o_yc1 + 2 * s] = ck.x + yrk[2 * s];
+        base[o_yc1 + 2 * s + 1] = ck.y + yrk[2 * s + 1];
+      }
+      for (int s = 0; s < d.mf[0]; ++s) {
         base[o_xf + 2 * s] = xi[s].x;
         base[o_xf + 2 * s + 1] = xi[s].y;
-        base[o_xf + 2 * mf + 2 * s] = xk[s].x;
-        base[o_xf + 2 * mf + 2 * s + 1] = xk[s].y;
+      }
+      for (int s = 0; s < d.mf[1]; ++s) {
+        base[o_xf + 2 * d.mf[0] + 2 * s] = xk[s].x;
+        base[o_xf + 2 * d.mf[0] + 2 * s + 1] = xk[s].y;
       }
       for (int s = 0; s < mp; ++s) {
         base[o_z + 2 * s] = z[s].x;
@@ -542,15 +606,40 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       g.c[1][1] = ck.y;
       ktk_inv(yi, ci.x, ci.y, g.KKf[0]);
       ktk_inv(yk, ck.x, ck.y, g.KKf[1]);
+      std::memcpy(g.KKc[0], ct.KtKi[c->cls[i]], sizeof(g.KKc[0]));
+      std::memcpy(g.KKc[1], ct.KtKi[c->cls[k]], sizeof(g.KKc[1]));
       eoff[q] = 6 * c->xoff[p];
+      if (keep) {
+        if ((int)yi.size() != nfe0[p] || (int)yk.size() != nfe1[p])
+          return Status{MFS_ERR_ARG, "pair fine source counts disagree with the fine rules"};
+        double* yf = h_Yf.data() + ps.yoff[p];
+        for (size_t s2 = 0; s2 < yi.size(); ++s2) {
+          yf[2 * s2] = yi[s2].x;
+          yf[2 * s2 + 1] = yi[s2].y;
+        }
+        yf += 2 * yi.size();
+        for (size_t s2 = 0; s2 < yk.size(); ++s2) {
+          yf[2 * s2] = yk[s2].x;
+          yf[2 * s2 + 1] = yk[s2].y;
+        }
+        std::memcpy(h_KKf.data() + 18 * (size_t)p, g.KKf[0], 9 * sizeof(double));
+        std::memcpy(h_KKf.data() + 18 * (size_t)p + 9, g.KKf[1], 9 * sizeof(double));
+        // peanut: rolling unit circle centred s along the axis and h off it (both sides)
+        const double dx = ck.x - ci.x, dy = ck.y - ci.y, dd = std::sqrt(dx * dx + dy * dy);
+        const double ex = dx / dd, ey = dy / dd;
+        const double sh = ((ai + 1.0) * (ai + 1.0) - (ak + 1.0) * (ak + 1.0) + dd * dd) / (2.0 * dd);
+        const double hh = std::sqrt((ai + 1.0) * (ai + 1.0) - sh * sh);
+        double* pg = h_pgeo.data() + 12 * (size_t)p;
+        const double pv[12] = {ci.x, ci.y, ck.x, ck.y, ai, ak, ci.x + sh * ex + hh * ey, ci.y + sh * ey - hh * ex,
+                               ci.x + sh * ex - hh * ey, ci.y + sh * ey + hh * ex};
+        std::memcpy(pg, pv, sizeof(pv));
+        h_nf[2 * p] = nfe0[p];
+        h_nf[2 * p + 1] = nfe1[p];
+      }
     }
     MFS_HIP(hipMemcpyAsync(dstage.p, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice, c->stream));
     MFS_HIP(hipMemcpyAsync(dgeo.p, geo.data(), sizeof(PairGeo) * nb, hipMemcpyHostToDevice, c->stream));
-    // coarse (K^T K)^{-1}
-    DevMem dKKc, deoff;
-    MFS_HIP(hipMalloc(&dKKc.p, sizeof(double) * 9));
-    MFS_HIP(hipMemcpyAsync(dKKc.p, ct.KtKi[c->cls[c->pairs[2 * order[b0]]]], sizeof(double) * 9,
-                           hipMemcpyHostToDevice, c->stream));
+    DevMem deoff;
     MFS_HIP(hipMalloc(&deoff.p, sizeof(int64_t) * nb));
     MFS_HIP(hipMemcpyAsync(deoff.p, eoff.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, c->stream));
 
@@ -565,10 +654,10 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_HIP(hipMemsetAsync(dD.p, 0, sizeof(double) * d.sD * nb, c->stream));
     tick(0, t0);
     {
-      const int maxpts = std::max(2 * mf, mp);
+      const int maxpts = std::max(d.mf[0] + d.mf[1], mp);
       dim3 grid((maxpts + 63) / 64, nb, 4);
       hipLaunchKernelGGL(k_fill, grid, dim3(64), 0, c->stream, (const PairGeo*)dgeo.p, d, mobility, kscale,
-                         (const double*)dKKc.p, (double*)dF.p, (double*)dX.p, (double*)dD.p, (double*)dC.p);
+                         (double*)dF.p, (double*)dX.p, (double*)dD.p, (double*)dC.p);
       MFS_HIP(hipGetLastError());
     }
     tick(1, t0);
@@ -601,6 +690,24 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
                                          (int)nx, (int)mn, &one, (const double*)dVT.p, (int)mn, mn * n,
                                          (const double*)dT1.p, (int)mn, mn * nx, &zero, (double*)dG.p, (int)n, n * nx,
                                          nb));
+    if (keep) {
+      std::vector<int32_t> nfq(2 * nb);
+      std::vector<int64_t> gq(nb);
+      for (int q = 0; q < nb; ++q) {
+        nfq[2 * q] = nfe0[order[b0 + q]];
+        nfq[2 * q + 1] = nfe1[order[b0 + q]];
+        gq[q] = ps.goff[order[b0 + q]];
+      }
+      DevMem dnfq, dgq;
+      MFS_HIP(hipMalloc(&dnfq.p, sizeof(int32_t) * 2 * nb));
+      MFS_HIP(hipMalloc(&dgq.p, sizeof(int64_t) * nb));
+      MFS_HIP(hipMemcpyAsync(dnfq.p, nfq.data(), sizeof(int32_t) * 2 * nb, hipMemcpyHostToDevice, c->stream));
+      MFS_HIP(hipMemcpyAsync(dgq.p, gq.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_store_fine, dim3((unsigned)nx, nb), dim3(256), 0, c->stream, (int)nx, d.nfpad[0],
+                         (const int32_t*)dnfq.p, (const double*)dG.p, n * nx, n, ps.G, (const int64_t*)dgq.p);
+      MFS_HIP(hipGetLastError());
+      MFS_HIP(hipStreamSynchronize(c->stream));   // nfq, gq are released at the end of this scope
+    }
     // DG = D G  (2mp x nx)
     MFS_HIP(hipMalloc(&dDG.p, sizeof(double) * mpp * nx * nb));
     MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none, (int)mpp, (int)nx,
@@ -648,10 +755,26 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       if (info[q] != 0) return Status{MFS_ERR_NUMERIC, "pair SVD did not converge"};
     tick(5, t0);
     if (prof) std::fprintf(stderr, "[mfs precompute] %d / %d pairs (batch %d)\n", b0 + nb, C, batch);
+    b0 += nb;
   }
   if (prof)
     std::fprintf(stderr, "[mfs precompute] pairs %d: host+upload %.3fs fill %.3fs svdF %.3fs gemm %.3fs svdC %.3fs rest %.3fs\n",
                  C, tstage[0], tstage[1], tstage[2], tstage[3], tstage[4], tstage[5]);
+  if (keep) {
+    auto up = [&](void** dst, const void* src, size_t bytes) -> Status {
+      MFS_HIP(hipMalloc(dst, std::max<size_t>(bytes, 8)));
+      if (bytes) MFS_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+      return Status{};
+    };
+    Status st;
+    if ((st = up((void**)&ps.Yf, h_Yf.data(), sizeof(double) * h_Yf.size())).code) return st;
+    if ((st = up((void**)&ps.KKf, h_KKf.data(), sizeof(double) * h_KKf.size())).code) return st;
+    if ((st = up((void**)&ps.pgeo, h_pgeo.data(), sizeof(double) * h_pgeo.size())).code) return st;
+    if ((st = up((void**)&ps.nf, h_nf.data(), sizeof(int32_t) * h_nf.size())).code) return st;
+    if ((st = up((void**)&ps.d_goff, ps.goff.data(), sizeof(int64_t) * ps.goff.size())).code) return st;
+    if ((st = up((void**)&ps.d_yoff, ps.yoff.data(), sizeof(int64_t) * ps.yoff.size())).code) return st;
+    ps.fine = true;
+  }
   ps.ready = true;
   return Status{};
 }

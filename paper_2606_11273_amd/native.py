@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "MFS_OK", 1: "MFS_ERR_ARG", 2: "MFS_ERR_GEOMETRY", 3: "MFS_ER
 SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_pairs", "mfs_set_pair_matrices",
            "mfs_get_pair_matrices", "mfs_apply", "mfs_kernel_sum", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
            "mfs_get_sizes", "mfs_destroy", "mfs_last_error", "mfs_server_create", "mfs_server_footprint",
-           "mfs_server_submit", "mfs_server_wait", "mfs_server_last_error", "mfs_server_destroy"]
+           "mfs_server_submit", "mfs_server_wait", "mfs_server_last_error", "mfs_server_destroy",
+           "mfs_keep_fine_factors", "mfs_get_density", "mfs_flow_eval", "mfs_boundary_residual"]
 
 
 class MfsParams(C.Structure):
@@ -92,6 +93,10 @@ def lib():
     L.mfs_gmres_solve.argtypes = [vp, C.c_int, C.c_int, C.c_int32, dp, dp, vp, C.c_double, C.c_int32,
                                   C.POINTER(MfsSolveInfo)]
     L.mfs_get_sizes.argtypes = [vp, ip, i64p, i64p, i64p]
+    L.mfs_keep_fine_factors.argtypes = [vp, C.c_int32]
+    L.mfs_get_density.argtypes = [vp, C.c_int32, vp]
+    L.mfs_flow_eval.argtypes = [vp, C.c_int, vp, dp, C.c_int64, vp, vp, vp]
+    L.mfs_boundary_residual.argtypes = [vp, C.c_int, vp, dp, dp, C.c_int32, vp, dp]
     L.mfs_destroy.argtypes = [vp]
     L.mfs_last_error.argtypes = [vp]
     L.mfs_last_error.restype = C.c_char_p
@@ -215,6 +220,41 @@ def mfs_kernel_sum(ctx, precision, sigma, u, skip=1):
 def mfs_rhs(ctx, problem, given, b):
     given = np.ascontiguousarray(given, dtype=np.float64)
     _check(lib().mfs_rhs(ctx, PROBLEMS[problem], _dp(given), _dev(b)), ctx)
+
+
+def mfs_keep_fine_factors(ctx, keep=True):
+    _check(lib().mfs_keep_fine_factors(ctx, int(bool(keep))), ctx)
+
+
+def mfs_get_density(ctx, rhs, mu):
+    _check(lib().mfs_get_density(ctx, int(rhs), _dev(mu)), ctx)
+
+
+def _dev_i32(t):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+        raise TypeError("body indices must be a contiguous int32 torch tensor on the GPU")
+    return C.c_void_p(t.data_ptr())
+
+
+def mfs_flow_eval(ctx, problem, mu, given, pts, body, u):
+    """pts (device float64, 2 n), body (device int32, n; -1 fluid), u (device float64, 2 n)."""
+    n = body.numel()
+    g = None if given is None else np.ascontiguousarray(given, dtype=np.float64)
+    _check(lib().mfs_flow_eval(ctx, PROBLEMS[problem], _dev(mu), None if g is None else _dp(g), n,
+                               _dev(pts, 2 * n), _dev_i32(body), _dev(u, 2 * n)), ctx)
+
+
+def mfs_boundary_residual(ctx, problem, mu, given, rigid, n_per_body, eps=None):
+    """Returns eps_max; eps (device float64, P n_per_body) receives the pointwise residuals."""
+    g = None if given is None else np.ascontiguousarray(given, dtype=np.float64)
+    rig = np.ascontiguousarray(rigid, dtype=np.float64)
+    P = rig.size // 3
+    out = C.c_double(0.0)
+    if eps is not None:
+        _dev(eps, P * int(n_per_body))
+    _check(lib().mfs_boundary_residual(ctx, PROBLEMS[problem], _dev(mu), None if g is None else _dp(g), _dp(rig),
+                                       int(n_per_body), None if eps is None else _dev(eps), C.byref(out)), ctx)
+    return out.value
 
 
 def mfs_post(ctx, problem, mu, P):
