@@ -9,7 +9,9 @@ full mobility solve through the C ABI: right-hand side, GMRES on the Alg. 3 oper
 the kernel sum relaxed to FP32 (FP64 accumulation) as the residual falls, FP64 refinement
 on the true residual, and post-processing to velocities.  Setup and the pair precompute happen before the
 timed region and are reported separately; the plain-FP64 solve of the same input
-is run once beside it for the mixed-vs-FP64 comparison.
+is run once beside it for the mixed-vs-FP64 comparison.  After the timed region the
+relative boundary residual of the mixed solution (eqs. residual_x, residual: the flow
+evaluated with each pair's fine sources at 72 points per disk) is reported beside it.
 
 Prints one JSON line.  --gpus N > 1 exits: the benchmark runs on one GPU.
 
@@ -120,6 +122,10 @@ def main():
     ap.add_argument("--requests", type=int, default=12, help="requests in the Poisson stream (--serve)")
     ap.add_argument("--saturated", type=int, default=6, help="requests in the saturated pass (--serve)")
     ap.add_argument("--slots", type=int, default=4, help="server slots (--serve)")
+    ap.add_argument("--no-flow", action="store_true",
+                    help="skip the boundary residual of the solution (flow evaluation with the pairs' fine "
+                         "sources at --flow-nodes points per disk, after the timed region)")
+    ap.add_argument("--flow-nodes", type=int, default=72)
     ap.add_argument("--kernel-only", action="store_true",
                     help="set up the workload and run only the dominant kernel (5 launches), then one mixed "
                          "and one FP64 matvec with zero pair matrices (plus --copy-calibration): the short "
@@ -181,6 +187,8 @@ def main():
         print(json.dumps({"kernel_only": True, "launches": args.ksum_reps, "copy_bytes": (1 << 30) if
                           args.copy_calibration else 0}), flush=True)
         return
+    if not args.no_flow:
+        nv.mfs_keep_fine_factors(ctx, True)
     t0 = time.perf_counter()
     n_pairs = nv.mfs_precompute_pairs(ctx, "mobility")
     torch.cuda.synchronize()
@@ -213,12 +221,12 @@ def main():
     if not args.no_fp64:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out64, info64 = nv.mfs_gmres_solve(ctx, "mobility", "fp64", given, args.tol, 500)
+        out64, info64 = nv.mfs_gmres_solve(ctx, "mobility", "fp64", given, args.tol, 1000)
         t_fp64 = time.perf_counter() - t0
         log(f"fp64 solve {t_fp64:.2f}s iters {info64['iters']} resid {info64['rel_resid']:.2e}")
 
     for _ in range(args.warmup):
-        nv.mfs_gmres_solve(ctx, "mobility", "mixed", given, args.tol, 500)
+        nv.mfs_gmres_solve(ctx, "mobility", "mixed", given, args.tol, 1000)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -227,7 +235,7 @@ def main():
     e0.record(stream)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out32, info32 = nv.mfs_gmres_solve(ctx, "mobility", "mixed", given, args.tol, 500)
+        out32, info32 = nv.mfs_gmres_solve(ctx, "mobility", "mixed", given, args.tol, 1000)
         evals += info32["pair_evals"]
         infos.append(info32)
     e1.record(stream)
@@ -280,6 +288,22 @@ def main():
             torch.cuda.synchronize()
             stacked[f"{prec}_ms_per_vector"] = round(e0.elapsed_time(e1) / args.rhs, 2)
 
+    # accuracy of the mixed solution: relative boundary residual (eqs. residual_x, residual) of the
+    # first right-hand side, the flow evaluated with each pair's fine sources near contacts
+    flow = None
+    if not args.no_flow:
+        mu0 = torch.zeros(2 * Nt, dtype=torch.float64, device="cuda")
+        nv.mfs_get_density(ctx, 0, mu0)
+        out_first = out32.reshape(-1, P, 3)[0]
+        given_first = given.reshape(-1, P, 3)[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        em = nv.mfs_boundary_residual(ctx, "mobility", mu0, given_first, out_first, args.flow_nodes)
+        t_flow = time.perf_counter() - t0
+        flow = {"eps_max": em, "nodes_per_disk": args.flow_nodes, "points": P * args.flow_nodes,
+                "seconds": round(t_flow, 3)}
+        log(f"boundary residual {em:.3e} at {args.flow_nodes} nodes per disk, {t_flow:.2f}s")
+
     err = None
     if out64 is not None:
         err = max(rel_rigid_error(a32, a64) for a32, a64 in zip(out32.reshape(-1, P, 3), out64.reshape(-1, P, 3)))
@@ -321,6 +345,7 @@ def main():
         "setup_s": round(t_setup, 3),
         "precompute_s": round(t_pre, 2),
         "stacked_matvec": stacked,
+        "boundary_residual": flow,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -109,12 +109,37 @@ mfs_status mfs_setup(mfs_ctx** ctx, int32_t P, const double* centers, const doub
                      const int32_t* n_src, const int32_t* n_col, const double* r_src,
                      const mfs_params* prm, void* stream);
 
+/* Device-memory callbacks of a context.  alloc returns bytes (> 0) of device memory
+ * usable by work on the context's stream, or NULL when it cannot (the call that needed
+ * it then fails with MFS_ERR_OOM or MFS_ERR_DEVICE); free releases a pointer that alloc
+ * returned.  The library frees a buffer only after the work on the context's stream
+ * that uses it has completed.  user is passed through.  Both callbacks stay valid until
+ * mfs_destroy of the context returns, and are called from the thread that makes the
+ * library call. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} mfs_allocator;
+
+/* mfs_setup with every device buffer of the context (geometry, one-body factors, pair
+ * matrices, fine factors, Krylov basis, work space and per-call temporaries) taken
+ * from allocator, e.g. a framework's caching allocator; NULL behaves as mfs_setup
+ * (hipMalloc / hipFree).  rocBLAS and rocSOLVER keep their own internal work space.
+ * MFS_ERR_ARG if allocator is given with a NULL callback. */
+mfs_status mfs_setup_ex(mfs_ctx** ctx, int32_t P, const double* centers, const double* radii,
+                        const int32_t* n_src, const int32_t* n_col, const double* r_src,
+                        const mfs_params* prm, void* stream, const mfs_allocator* allocator);
+
 /* Precompute, on the device, the compressed correction A^c (eq. Amat) and the
  * extraction matrix E^c (velocities for mobility, eq. rbm2; forces/torques for
  * resistance, eq. force_ext read with a transpose and sign) of every close pair,
- * for problem prob.  n_pairs_out: host or NULL.  Pairs of disks with different
- * classes, or with radius != 1, give MFS_ERR_ARG.  Calling it again for the
- * other problem keeps both sets. */
+ * for problem prob.  n_pairs_out: host or NULL.  The fine pair discretisation of
+ * Sec. 5 is the paper's for unit disks; a disk of radius a gets fine counts scaled by
+ * a, the limit point of the pair's two circles for its shielding ellipse and a
+ * rolling unit circle for the peanut, so pairs of unequal radii and classes are
+ * accepted.  With mfs_keep_fine_factors set it also keeps the fine maps for
+ * mfs_flow_eval.  Calling it again for the other problem keeps both sets. */
 mfs_status mfs_precompute_pairs(mfs_ctx* ctx, mfs_problem prob, int64_t* n_pairs_out);
 
 /* Number of close pairs and the list itself.  pairs: host, n_pairs x 2 (i < k),

@@ -12,6 +12,32 @@
 
 using namespace mfs;
 
+namespace mfs {
+
+hipError_t dev_malloc(mfs_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (c && c->alloc.alloc) {
+    *p = c->alloc.alloc(bytes ? bytes : 1, c->alloc.user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  const hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+  }
+  return e;
+}
+
+void dev_free(mfs_ctx* c, void* p) {
+  if (!p) return;
+  if (c && c->alloc.alloc)
+    c->alloc.free(p, c->alloc.user);
+  else
+    (void)hipFree(p);
+}
+
+}  // namespace mfs
+
 namespace {
 
 thread_local std::string g_setup_err;
@@ -30,9 +56,9 @@ mfs_status ok(mfs_ctx* c) {
 }
 
 template <class T>
-Status dalloc(T** p, size_t n) {
+Status dalloc(mfs_ctx* c, T** p, size_t n) {
   *p = nullptr;
-  if (hipMalloc((void**)p, sizeof(T) * (n ? n : 1)) != hipSuccess) {
+  if (dev_malloc(c, (void**)p, sizeof(T) * (n ? n : 1)) != hipSuccess) {
     (void)hipGetLastError();
     return Status{MFS_ERR_OOM, "device allocation of " + std::to_string(sizeof(T) * n) + " bytes failed"};
   }
@@ -40,8 +66,8 @@ Status dalloc(T** p, size_t n) {
 }
 
 template <class T>
-Status upload(T** p, const std::vector<T>& h, hipStream_t s) {
-  Status st = dalloc(p, h.size());
+Status upload(mfs_ctx* c, T** p, const std::vector<T>& h, hipStream_t s) {
+  Status st = dalloc(c, p, h.size());
   if (st.code) return st;
   if (!h.empty()) MFS_HIP(hipMemcpyAsync(*p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s));
   return Status{};
@@ -57,14 +83,14 @@ void free_all(mfs_ctx* c) {
                   c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
                   c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf};
   for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+    if (p) dev_free(c, p);
   for (const PairSet& ps : c->ps)
     for (void* p : {(void*)ps.G, (void*)ps.Yf, (void*)ps.KKf, (void*)ps.pgeo, (void*)ps.nf, (void*)ps.d_goff,
                     (void*)ps.d_yoff})
-      if (p) (void)hipFree(p);
+      if (p) dev_free(c, p);
   if (c->kr.hhost) (void)hipHostFree(c->kr.hhost);
   for (void* p : c->class_bufs)
-    if (p) (void)hipFree(p);
+    if (p) dev_free(c, p);
   if (c->blas) rocblas_destroy_handle(c->blas);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
@@ -175,32 +201,32 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
     }
   }
   hipStream_t s = c->stream;
-  if ((st = upload(&c->d_src_off, c->src_off, s)).code) return st;
-  if ((st = upload(&c->d_col_off, c->col_off, s)).code) return st;
-  if ((st = upload(&c->d_cls, c->cls, s)).code) return st;
-  if ((st = upload(&c->d_tgt_body, tb, s)).code) return st;
-  if ((st = upload(&c->d_pairs, c->pairs, s)).code) return st;
-  if ((st = upload(&c->d_bp_off, c->bp_off, s)).code) return st;
-  if ((st = upload(&c->d_bp_list, c->bp_list, s)).code) return st;
-  if ((st = upload(&c->d_nbr_off, c->nbr_off, s)).code) return st;
-  if ((st = upload(&c->d_nbr_list, c->nbr_list, s)).code) return st;
-  if ((st = upload(&c->d_xoff, c->xoff, s)).code) return st;
-  if ((st = upload(&c->d_aoff, c->aoff, s)).code) return st;
-  if ((st = upload(&c->d_coff, c->coff, s)).code) return st;
-  if ((st = upload(&c->d_centers, c->centers, s)).code) return st;
-  if ((st = upload(&c->d_Y, Y, s)).code) return st;
-  if ((st = upload(&c->d_X, X, s)).code) return st;
-  if ((st = upload(&c->d_Xr32, Xr32, s)).code) return st;
-  if ((st = dalloc(&c->d_lam_bar, 2 * c->Ns)).code) return st;
-  if ((st = dalloc(&c->d_ltil, c->xoff[C])).code) return st;
-  if ((st = dalloc(&c->d_u, 2 * c->Nt)).code) return st;
-  if ((st = dalloc(&c->d_corr, c->coff[C])).code) return st;
-  if ((st = dalloc(&c->d_epair, 6 * (size_t)C)).code) return st;
-  if ((st = dalloc(&c->d_out3, 3 * (size_t)P)).code) return st;
-  if ((st = dalloc(&c->d_given, 3 * (size_t)P)).code) return st;
-  if ((st = dalloc(&c->d_sig32, c->Ns)).code) return st;
-  if ((st = dalloc(&c->d_bdat, (size_t)P)).code) return st;
-  if ((st = dalloc(&c->d_src64, c->Ns)).code) return st;
+  if ((st = upload(c, &c->d_src_off, c->src_off, s)).code) return st;
+  if ((st = upload(c, &c->d_col_off, c->col_off, s)).code) return st;
+  if ((st = upload(c, &c->d_cls, c->cls, s)).code) return st;
+  if ((st = upload(c, &c->d_tgt_body, tb, s)).code) return st;
+  if ((st = upload(c, &c->d_pairs, c->pairs, s)).code) return st;
+  if ((st = upload(c, &c->d_bp_off, c->bp_off, s)).code) return st;
+  if ((st = upload(c, &c->d_bp_list, c->bp_list, s)).code) return st;
+  if ((st = upload(c, &c->d_nbr_off, c->nbr_off, s)).code) return st;
+  if ((st = upload(c, &c->d_nbr_list, c->nbr_list, s)).code) return st;
+  if ((st = upload(c, &c->d_xoff, c->xoff, s)).code) return st;
+  if ((st = upload(c, &c->d_aoff, c->aoff, s)).code) return st;
+  if ((st = upload(c, &c->d_coff, c->coff, s)).code) return st;
+  if ((st = upload(c, &c->d_centers, c->centers, s)).code) return st;
+  if ((st = upload(c, &c->d_Y, Y, s)).code) return st;
+  if ((st = upload(c, &c->d_X, X, s)).code) return st;
+  if ((st = upload(c, &c->d_Xr32, Xr32, s)).code) return st;
+  if ((st = dalloc(c, &c->d_lam_bar, 2 * c->Ns)).code) return st;
+  if ((st = dalloc(c, &c->d_ltil, c->xoff[C])).code) return st;
+  if ((st = dalloc(c, &c->d_u, 2 * c->Nt)).code) return st;
+  if ((st = dalloc(c, &c->d_corr, c->coff[C])).code) return st;
+  if ((st = dalloc(c, &c->d_epair, 6 * (size_t)C)).code) return st;
+  if ((st = dalloc(c, &c->d_out3, 3 * (size_t)P)).code) return st;
+  if ((st = dalloc(c, &c->d_given, 3 * (size_t)P)).code) return st;
+  if ((st = dalloc(c, &c->d_sig32, c->Ns)).code) return st;
+  if ((st = dalloc(c, &c->d_bdat, (size_t)P)).code) return st;
+  if ((st = dalloc(c, &c->d_src64, c->Ns)).code) return st;
   MFS_HIP(hipStreamSynchronize(s));
   return Status{};
 }
@@ -236,20 +262,20 @@ Status ensure_stacked(mfs_ctx* c, int R) {
   if (c->rhs_cap >= R) return Status{};
   for (void* p : {(void*)c->d_lam_bar_m, (void*)c->d_ltil_m, (void*)c->d_u_m, (void*)c->d_corr_m,
                   (void*)c->d_sig32m, (void*)c->d_bdatm, (void*)c->d_src64m})
-    if (p) (void)hipFree(p);
+    if (p) dev_free(c, p);
   c->d_lam_bar_m = c->d_ltil_m = c->d_u_m = c->d_corr_m = nullptr;
   c->d_sig32m = c->d_bdatm = nullptr;
   c->d_src64m = nullptr;
   c->rhs_cap = 0;
   const int C = (int)(c->pairs.size() / 2);
   Status st;
-  if ((st = dalloc(&c->d_lam_bar_m, (size_t)R * 2 * c->Ns)).code) return st;
-  if ((st = dalloc(&c->d_ltil_m, (size_t)R * c->xoff[C])).code) return st;
-  if ((st = dalloc(&c->d_u_m, (size_t)R * 2 * c->Nt)).code) return st;
-  if ((st = dalloc(&c->d_corr_m, (size_t)R * c->coff[C])).code) return st;
-  if ((st = dalloc(&c->d_sig32m, (size_t)R * c->Ns)).code) return st;
-  if ((st = dalloc(&c->d_bdatm, (size_t)R * c->P)).code) return st;
-  if ((st = dalloc(&c->d_src64m, (size_t)R * c->Ns)).code) return st;
+  if ((st = dalloc(c, &c->d_lam_bar_m, (size_t)R * 2 * c->Ns)).code) return st;
+  if ((st = dalloc(c, &c->d_ltil_m, (size_t)R * c->xoff[C])).code) return st;
+  if ((st = dalloc(c, &c->d_u_m, (size_t)R * 2 * c->Nt)).code) return st;
+  if ((st = dalloc(c, &c->d_corr_m, (size_t)R * c->coff[C])).code) return st;
+  if ((st = dalloc(c, &c->d_sig32m, (size_t)R * c->Ns)).code) return st;
+  if ((st = dalloc(c, &c->d_bdatm, (size_t)R * c->P)).code) return st;
+  if ((st = dalloc(c, &c->d_src64m, (size_t)R * c->Ns)).code) return st;
   c->rhs_cap = R;
   return Status{};
 }
@@ -321,10 +347,18 @@ void mfs_default_params(mfs_params* p) {
 
 mfs_status mfs_setup(mfs_ctx** out, int32_t P, const double* centers, const double* radii, const int32_t* n_src,
                      const int32_t* n_col, const double* r_src, const mfs_params* prm, void* stream) {
+  return mfs_setup_ex(out, P, centers, radii, n_src, n_col, r_src, prm, stream, nullptr);
+}
+
+mfs_status mfs_setup_ex(mfs_ctx** out, int32_t P, const double* centers, const double* radii,
+                        const int32_t* n_src, const int32_t* n_col, const double* r_src, const mfs_params* prm,
+                        void* stream, const mfs_allocator* allocator) {
   if (!out) return fail(nullptr, Status{MFS_ERR_ARG, "ctx pointer is NULL"});
   *out = nullptr;
   if (P < 1 || !centers || !radii || !n_src || !n_col || !r_src)
     return fail(nullptr, Status{MFS_ERR_ARG, "P < 1 or NULL geometry array"});
+  if (allocator && (!allocator->alloc || !allocator->free))
+    return fail(nullptr, Status{MFS_ERR_ARG, "allocator without alloc or free callback"});
   mfs_params p;
   if (prm)
     p = *prm;
@@ -340,6 +374,7 @@ mfs_status mfs_setup(mfs_ctx** out, int32_t P, const double* centers, const doub
   if (!c) return fail(nullptr, Status{MFS_ERR_OOM, "host allocation failed"});
   c->P = P;
   c->prm = p;
+  if (allocator) c->alloc = *allocator;
   {
     Status st = validate_host(c, centers, radii, n_src, n_col, r_src);
     if (st.code) {
@@ -388,8 +423,8 @@ mfs_status mfs_set_pair_matrices(mfs_ctx* c, mfs_problem prob, const double* A, 
   const int C = (int)(c->pairs.size() / 2);
   PairSet& ps = c->ps[prob];
   if (!ps.A) {
-    Status st = dalloc(&ps.A, c->aoff[C]);
-    if (!st.code) st = dalloc(&ps.E, 6 * c->xoff[C]);
+    Status st = dalloc(c, &ps.A, c->aoff[C]);
+    if (!st.code) st = dalloc(c, &ps.E, 6 * c->xoff[C]);
     if (st.code) return fail(c, st);
   }
   std::vector<double> Ac(c->aoff[C]), Ec(6 * c->xoff[C]);

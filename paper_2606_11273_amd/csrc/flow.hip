@@ -24,16 +24,13 @@ mfs_status failc(mfs_ctx* c, Status st) {
 }
 
 template <class T>
-Status grow(T** p, int64_t* cap, int64_t need) {
+Status grow(mfs_ctx* c, T** p, int64_t* cap, int64_t need) {
   if (*cap >= need && *p) return Status{};
-  if (*p) (void)hipFree(*p);
+  dev_free(c, *p);
   *p = nullptr;
   *cap = 0;
-  if (hipMalloc((void**)p, sizeof(T) * std::max<int64_t>(need, 1)) != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
+  if (dev_malloc(c, p, sizeof(T) * std::max<int64_t>(need, 1)) != hipSuccess)
     return Status{MFS_ERR_OOM, "device allocation for flow evaluation failed"};
-  }
   *cap = need;
   return Status{};
 }
@@ -44,11 +41,12 @@ __global__ void k_check_body(int64_t n_pts, const int32_t* __restrict__ body, in
   if (t < n_pts && (body[t] < -1 || body[t] >= P)) flag[0] = 1;
 }
 
-struct Scratch {   // per-call device buffers, freed on every exit path
+struct Scratch {   // per-call device buffers of the context, freed on every exit path
+  mfs_ctx* c;
   void* p = nullptr;
-  ~Scratch() {
-    if (p) (void)hipFree(p);
-  }
+  explicit Scratch(mfs_ctx* ctx) : c(ctx) {}
+  hipError_t alloc(size_t bytes) { return dev_malloc(c, &p, bytes); }
+  ~Scratch() { dev_free(c, p); }
 };
 
 // u at n_pts points (device), see mfs_flow_eval.
@@ -61,9 +59,9 @@ Status flow_eval(mfs_ctx* c, int prob, const double* mu, const double* given, in
     return Status{MFS_ERR_STATE, "no fine factors: call mfs_keep_fine_factors before mfs_precompute_pairs"};
   if (n_pts == 0) return Status{};
   {
-    Scratch flag;
+    Scratch flag(c);
     int h = 0;
-    MFS_HIP(hipMalloc(&flag.p, sizeof(int)));
+    MFS_HIP(flag.alloc(sizeof(int)));
     MFS_HIP(hipMemcpyAsync(flag.p, &h, sizeof(int), hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_check_body, dim3((unsigned)((n_pts + 255) / 256)), dim3(256), 0, c->stream, n_pts, body,
                        c->P, (int*)flag.p);
@@ -73,11 +71,11 @@ Status flow_eval(mfs_ctx* c, int prob, const double* mu, const double* given, in
   }
   Status st;
   int64_t fsrc_cap = c->d_fsrc ? c->Ns : 0;
-  if ((st = grow(&c->d_fsrc, &fsrc_cap, c->Ns)).code) return st;
+  if ((st = grow(c, &c->d_fsrc, &fsrc_cap, c->Ns)).code) return st;
   if (C > 0) {
     int64_t ptil_cap = c->d_ptil ? c->xoff[C] : 0;
-    if ((st = grow(&c->d_ptil, &ptil_cap, c->xoff[C])).code) return st;
-    if ((st = grow(&c->d_sigf, &c->sigf_cap, ps.yoff[C])).code) return st;
+    if ((st = grow(c, &c->d_ptil, &ptil_cap, c->xoff[C])).code) return st;
+    if ((st = grow(c, &c->d_sigf, &c->sigf_cap, ps.yoff[C])).code) return st;
   }
   // step 1 of Alg. 3: lambda_bar and the pairs' lambda_tilde; total strengths with positions
   launch_onebody_apply(c, prob, mu, c->d_lam_bar);
@@ -152,15 +150,11 @@ mfs_status mfs_boundary_residual(mfs_ctx* c, mfs_problem prob, const double* mu,
     if (!std::isfinite(rigid[q])) return failc(c, Status{MFS_ERR_NUMERIC, "non-finite rigid motion"});
   const int64_t n_pts = (int64_t)c->P * n_per_body;
   const int64_t nblk = (n_pts + 255) / 256;
-  Scratch s_pts, s_body, s_u, s_rig, s_max;
-  if (hipMalloc(&s_pts.p, sizeof(double) * 2 * n_pts) != hipSuccess ||
-      hipMalloc(&s_body.p, sizeof(int32_t) * n_pts) != hipSuccess ||
-      hipMalloc(&s_u.p, sizeof(double) * 2 * n_pts) != hipSuccess ||
-      hipMalloc(&s_rig.p, sizeof(double) * 3 * c->P) != hipSuccess ||
-      hipMalloc(&s_max.p, sizeof(double) * 2 * (nblk + 1)) != hipSuccess) {
-    (void)hipGetLastError();
+  Scratch s_pts(c), s_body(c), s_u(c), s_rig(c), s_max(c);
+  if (s_pts.alloc(sizeof(double) * 2 * n_pts) != hipSuccess || s_body.alloc(sizeof(int32_t) * n_pts) != hipSuccess ||
+      s_u.alloc(sizeof(double) * 2 * n_pts) != hipSuccess || s_rig.alloc(sizeof(double) * 3 * c->P) != hipSuccess ||
+      s_max.alloc(sizeof(double) * 2 * (nblk + 1)) != hipSuccess)
     return failc(c, Status{MFS_ERR_OOM, "device allocation for the boundary residual failed"});
-  }
   double* pts = (double*)s_pts.p;
   int32_t* body = (int32_t*)s_body.p;
   double* u = (double*)s_u.p;

@@ -13,7 +13,8 @@
 // upper estimate of the mixed operator's relative error: a per-problem floor, raised
 // to the error measured on the basis vector at the first switch (one extra mixed
 // application per solve), and raised again by f when a refinement step misses its
-// target by a factor f > 10.  This is the relaxation
+// target by a factor f > 10.  A mixed phase whose residual estimate stalls (less than
+// 10% gained over 100 iterations) continues with the FP64 operator.  This is the relaxation
 // of inexact Krylov methods (Simoncini & Szyld 2003; Bouras & Fraysse 2005): the
 // operator error tolerated at step k grows like tol / |r_k|, so only the first
 // iterations need FP64, and one Krylov space serves the whole solve instead of
@@ -45,20 +46,20 @@ Status ensure_krylov(mfs_ctx* c, int cap, int R) {
   const int64_t n = 2 * c->Nt;
   if (k.V && k.cap >= cap && k.rcap >= R && k.n == n) return Status{};
   for (double** p : {&k.V, &k.part, &k.hdev, &k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp})
-    if (*p) (void)hipFree(*p);
+    if (*p) dev_free(c, *p);
   if (k.hhost) (void)hipHostFree(k.hhost);
   k.V = k.part = k.hdev = k.hhost = k.w = k.x = k.r = k.b = k.d = k.tmp = nullptr;
   k.cap = k.rcap = 0;
-  for (double** p : {&k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp}) MFS_HIP(hipMalloc((void**)p, sizeof(double) * n * R));
-  if (hipMalloc((void**)&k.V, sizeof(double) * n * R * (cap + 1)) != hipSuccess) {
+  for (double** p : {&k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp}) MFS_HIP(dev_malloc(c, (void**)p, sizeof(double) * n * R));
+  if (dev_malloc(c, (void**)&k.V, sizeof(double) * n * R * (cap + 1)) != hipSuccess) {
     (void)hipGetLastError();
     k.V = nullptr;
     return Status{MFS_ERR_OOM, "Krylov basis of " + std::to_string(cap + 1) + " x " + std::to_string(R) +
                                    " vectors does not fit"};
   }
   const int nblk = mdot_blocks(n);
-  MFS_HIP(hipMalloc((void**)&k.part, sizeof(double) * nblk * (cap + 2)));
-  MFS_HIP(hipMalloc((void**)&k.hdev, sizeof(double) * 3 * (cap + 2) * R));
+  MFS_HIP(dev_malloc(c, (void**)&k.part, sizeof(double) * nblk * (cap + 2)));
+  MFS_HIP(dev_malloc(c, (void**)&k.hdev, sizeof(double) * 3 * (cap + 2) * R));
   MFS_HIP(hipHostMalloc((void**)&k.hhost, sizeof(double) * 3 * (cap + 2) * R, hipHostMallocDefault));
   k.cap = cap;
   k.rcap = R;
@@ -99,6 +100,21 @@ double switch_point(bool mixed, double tol, double delta, double op_err) {
   return mixed ? std::min(1.0, tol / std::max(delta, op_err)) : 0.0;
 }
 
+// Stall test of the mixed phase: every kStallWindow / 2 mixed iterations, once there have
+// been kStallWindow of them, the residual estimate is compared with its value
+// kStallWindow iterations back; below a kStallDrop reduction the FP32 products have
+// stopped the Krylov process from progressing (the noise of the FP32 sum, not a
+// spectral plateau, which still gains ~40% per 100 iterations at P = 10^4), and the
+// rest of the inner solve applies the FP64 operator, keeping the Krylov space.
+constexpr int kStallWindow = 100;
+constexpr double kStallDrop = 0.9;
+
+bool stalled(const std::vector<double>& est, int first32, int j) {
+  const int done = j + 1;
+  return first32 >= 0 && done - first32 > kStallWindow && done % (kStallWindow / 2) == 0 &&
+         est[j] > kStallDrop * est[j - kStallWindow];   // j - kStallWindow >= first32 >= 0
+}
+
 Status gmres_core(mfs_ctx* c, int prob, bool mixed, double delta, double& op_err, const double* r, double tol,
                   int maxit, int* iters, std::vector<double>& hist) {
   Krylov& k = c->kr;
@@ -114,6 +130,9 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, double delta, double& op_err
   if (beta == 0.0) return Status{};
   launch_scale_copy(c->stream, n, 1.0 / beta, r, k.V);
   std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
+  std::vector<double> est(maxit, 1.0);
+  int first32 = -1;
+  bool force64 = false;
   auto Hc = [&](int row, int col) -> double& { return H[(size_t)col * (maxit + 1) + row]; };
   g[0] = beta;
   int kdone = 0;
@@ -123,7 +142,7 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, double delta, double& op_err
   double rel_est = 1.0;
   for (int j = 0; j < maxit; ++j) {
     double* vj = k.V + (int64_t)j * n;
-    bool use32 = mixed && rel_est <= switch_below;
+    bool use32 = mixed && !force64 && rel_est <= switch_below;
     if (use32 && op_err < 0.0) {
       // first switch: measure the mixed operator on this basis vector against the FP64
       // one (which this iteration keeps), then move the switch point if it is worse
@@ -139,6 +158,7 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, double delta, double& op_err
     } else if ((st = apply_T(c, prob, use32, vj, k.w)).code) {
       return st;
     }
+    if (use32 && first32 < 0) first32 = j;
     // CGS2
     launch_mdot(c->stream, n, j + 1, k.V, n, k.w, k.part, k.hdev, nblk);
     launch_maxpy(c->stream, n, j + 1, k.V, n, k.hdev, k.w);
@@ -172,6 +192,11 @@ Status gmres_core(mfs_ctx* c, int prob, bool mixed, double delta, double& op_err
       std::fprintf(stderr, "[mfs gmres] %s it %d resid %.3e  %.1f s\n", use32 ? "fp32-sum" : "fp64", kdone,
                    hist.back(), ms_since(t_start) * 1e-3);
     if (std::fabs(g[j + 1]) <= tol * beta || hn == 0.0) break;
+    est[j] = rel_est;
+    if (!force64 && stalled(est, first32, j)) {
+      force64 = true;
+      if (prof) std::fprintf(stderr, "[mfs gmres] mixed phase stalled at it %d: FP64 from here\n", kdone);
+    }
   }
   std::vector<double> y(kdone);
   for (int i = kdone - 1; i >= 0; --i) {
@@ -208,6 +233,9 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, dou
   std::vector<char> active(R, 0);
   std::vector<int> kdone(R, 0);
   std::vector<std::vector<double>> H(R), cs(R), sn(R), g(R);
+  std::vector<double> est(maxit, 1.0);   // worst active estimate
+  int first32 = -1;
+  bool force64 = false;
   MFS_HIP(hipMemsetAsync(k.d, 0, sizeof(double) * n * R, c->stream));
   MFS_HIP(hipMemsetAsync(k.V, 0, sizeof(double) * ldv, c->stream));
   for (int q = 0; q < R; ++q) {
@@ -235,7 +263,7 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, dou
         if (rel[q] > switch_below[q]) all_low = false;
       }
     if (!any) break;
-    bool use32 = mixed && all_low;
+    bool use32 = mixed && all_low && !force64;
     double* vj = k.V + (int64_t)j * ldv;
     if (use32 && op_err < 0.0) {
       // first switch: measure the mixed operator on the active basis vectors (see gmres_core)
@@ -254,6 +282,7 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, dou
     } else if ((st = apply_T_rhs(c, prob, use32, R, vj, k.w)).code) {
       return st;
     }
+    if (use32 && first32 < 0) first32 = j;
     for (int q = 0; q < R; ++q) {
       if (!active[q]) continue;
       const double* Vq = k.V + q * n;
@@ -300,6 +329,16 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, dou
       rel[q] = std::fabs(g[q][j + 1]) / beta[q];
       hist[q].push_back(rel[q]);
       if (std::fabs(g[q][j + 1]) <= tol[q] * beta[q] || hn == 0.0) active[q] = 0;
+    }
+    {
+      double worst = 0.0;
+      for (int q = 0; q < R; ++q)
+        if (active[q]) worst = std::max(worst, rel[q]);
+      est[j] = worst;
+      if (!force64 && worst > 0.0 && stalled(est, first32, j)) {
+        force64 = true;
+        if (prof) std::fprintf(stderr, "[mfs gmres x%d] mixed phase stalled at it %d: FP64 from here\n", R, j + 1);
+      }
     }
     if (prof && ((j + 1) % 10 == 0)) {
       double worst = 0;
@@ -553,10 +592,10 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
   // the densities are kept for mfs_get_density / flow evaluation
   c->mu_count = 0;
   if (c->mu_cap < n * n_rhs) {
-    if (c->d_mu_last) (void)hipFree(c->d_mu_last);
+    if (c->d_mu_last) dev_free(c, c->d_mu_last);
     c->d_mu_last = nullptr;
     c->mu_cap = 0;
-    if (hipMalloc(&c->d_mu_last, sizeof(double) * n * n_rhs) != hipSuccess) {
+    if (dev_malloc(c, &c->d_mu_last, sizeof(double) * n * n_rhs) != hipSuccess) {
       (void)hipGetLastError();
       return failc(Status{MFS_ERR_OOM, "device allocation of the solution densities failed"});
     }

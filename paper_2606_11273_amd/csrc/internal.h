@@ -78,6 +78,7 @@ struct mfs_ctx {
   mfs::Status last;
   int pre_batch = 0;   // pairs per precompute batch; 0: sized from free device memory
   bool keep_fine = false;  // the precompute keeps each pair's fine map and points (flow evaluation)
+  mfs_allocator alloc{nullptr, nullptr, nullptr};   // caller's device allocator (alloc NULL: hipMalloc)
 
   // host geometry
   std::vector<double> centers, radii, r_src;
@@ -136,6 +137,15 @@ struct mfs_ctx {
 };
 
 namespace mfs {
+
+// Device memory of a context: the caller's allocator when mfs_setup_ex gave one, else
+// hipMalloc / hipFree (capi.hip).
+hipError_t dev_malloc(mfs_ctx* c, void** p, size_t bytes);
+void dev_free(mfs_ctx* c, void* p);
+template <class T>
+hipError_t dev_malloc(mfs_ctx* c, T** p, size_t bytes) {
+  return dev_malloc(c, (void**)p, bytes);
+}
 
 // ---- kernel launchers (kernels.hip) ----
 void launch_onebody_apply(mfs_ctx* c, int prob, const double* mu, double* lam_bar);

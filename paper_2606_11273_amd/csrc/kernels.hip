@@ -1318,9 +1318,9 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
   if (ns > 1) {
     const int64_t need = (int64_t)ns * R * Nt * 2;
     if (c->upart_cap < need) {
-      if (c->d_upart) (void)hipFree(c->d_upart);
+      if (c->d_upart) dev_free(c, c->d_upart);
       c->d_upart = nullptr;
-      if (hipMalloc(&c->d_upart, need * sizeof(double)) != hipSuccess) {
+      if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         c->d_upart = nullptr;
         c->upart_cap = 0;
@@ -1363,9 +1363,9 @@ bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale
   if (ns > 1) {
     const int64_t need = (int64_t)ns * Nt * 2;
     if (c->upart_cap < need) {
-      if (c->d_upart) (void)hipFree(c->d_upart);
+      if (c->d_upart) dev_free(c, c->d_upart);
       c->d_upart = nullptr;
-      if (hipMalloc(&c->d_upart, need * sizeof(double)) != hipSuccess) {
+      if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         c->d_upart = nullptr;
         c->upart_cap = 0;
@@ -1478,9 +1478,9 @@ bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, int64_t n_pts, con
   if (ns > 1) {
     const int64_t need = (int64_t)ns * n_pts * 2;
     if (c->upart_cap < need) {
-      if (c->d_upart) (void)hipFree(c->d_upart);
+      if (c->d_upart) dev_free(c, c->d_upart);
       c->d_upart = nullptr;
-      if (hipMalloc(&c->d_upart, need * sizeof(double)) != hipSuccess) {
+      if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         c->d_upart = nullptr;
         c->upart_cap = 0;

@@ -275,11 +275,14 @@ void ktk_inv(const std::vector<Pt>& pts, double cx, double cy, double* out) {
   inv3(M, out);
 }
 
-struct DevMem {
+struct DevMem {   // a per-batch device buffer of the context, freed at the end of its scope
+  mfs_ctx* c = nullptr;
   void* p = nullptr;
-  ~DevMem() {
-    if (p) (void)hipFree(p);
+  hipError_t alloc(mfs_ctx* ctx, size_t bytes) {
+    c = ctx;
+    return dev_malloc(c, &p, bytes);
   }
+  ~DevMem() { dev_free(c, p); }
 };
 
 }  // namespace
@@ -358,12 +361,12 @@ Status onebody_factors(mfs_ctx* c) {
       // SVD on the device
       const int mn = std::min(m, n);
       DevMem dA, dS, dU, dV, dE, dInfo;
-      MFS_HIP(hipMalloc(&dA.p, sizeof(double) * m * n));
-      MFS_HIP(hipMalloc(&dS.p, sizeof(double) * mn));
-      MFS_HIP(hipMalloc(&dU.p, sizeof(double) * m * mn));
-      MFS_HIP(hipMalloc(&dV.p, sizeof(double) * mn * n));
-      MFS_HIP(hipMalloc(&dE.p, sizeof(double) * mn));
-      MFS_HIP(hipMalloc(&dInfo.p, sizeof(int)));
+      MFS_HIP(dA.alloc(c, sizeof(double) * m * n));
+      MFS_HIP(dS.alloc(c, sizeof(double) * mn));
+      MFS_HIP(dU.alloc(c, sizeof(double) * m * mn));
+      MFS_HIP(dV.alloc(c, sizeof(double) * mn * n));
+      MFS_HIP(dE.alloc(c, sizeof(double) * mn));
+      MFS_HIP(dInfo.alloc(c, sizeof(int)));
       MFS_HIP(hipMemcpyAsync(dA.p, M.data(), sizeof(double) * m * n, hipMemcpyHostToDevice, c->stream));
       MFS_RB(rocsolver_dgesvd(c->blas, rocblas_svect_singular, rocblas_svect_singular, m, n, (double*)dA.p, m,
                               (double*)dS.p, (double*)dU.p, m, (double*)dV.p, mn, (double*)dE.p,
@@ -399,7 +402,7 @@ Status onebody_factors(mfs_ctx* c) {
       }
       auto upload = [&](const std::vector<double>& h, const double** dst) -> Status {
         void* p = nullptr;
-        MFS_HIP(hipMalloc(&p, sizeof(double) * std::max<size_t>(1, h.size())));
+        MFS_HIP(dev_malloc(c, &p, sizeof(double) * std::max<size_t>(1, h.size())));
         c->class_bufs.push_back(p);
         MFS_HIP(hipMemcpy(p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
         *dst = (const double*)p;
@@ -427,8 +430,8 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
   PairSet& ps = c->ps[prob];
   const int64_t asz = c->aoff[C], esz = 6 * c->xoff[C];
   if (!ps.A) {
-    MFS_HIP(hipMalloc(&ps.A, sizeof(double) * std::max<int64_t>(1, asz)));
-    MFS_HIP(hipMalloc(&ps.E, sizeof(double) * std::max<int64_t>(1, esz)));
+    MFS_HIP(dev_malloc(c, &ps.A, sizeof(double) * std::max<int64_t>(1, asz)));
+    MFS_HIP(dev_malloc(c, &ps.E, sizeof(double) * std::max<int64_t>(1, esz)));
   }
   if (C == 0) {
     ps.ready = true;
@@ -466,7 +469,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
   // (K^T K)^{-1} and peanut geometry, kept when the context asks for them.
   for (void** q : {(void**)&ps.G, (void**)&ps.Yf, (void**)&ps.KKf, (void**)&ps.pgeo, (void**)&ps.nf,
                    (void**)&ps.d_goff, (void**)&ps.d_yoff}) {
-    if (*q) (void)hipFree(*q);
+    if (*q) dev_free(c, *q);
     *q = nullptr;
   }
   ps.fine = false;
@@ -481,7 +484,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       ps.goff[p + 1] = ps.goff[p] + nfr * (c->xoff[p + 1] - c->xoff[p]);
       ps.yoff[p + 1] = ps.yoff[p] + nfr;
     }
-    MFS_HIP(hipMalloc(&ps.G, sizeof(double) * std::max<int64_t>(1, ps.goff[C])));
+    MFS_HIP(dev_malloc(c, &ps.G, sizeof(double) * std::max<int64_t>(1, ps.goff[C])));
     h_Yf.assign(ps.yoff[C], 0.0);
     h_KKf.assign(18 * (size_t)C, 0.0);
     h_pgeo.assign(12 * (size_t)C, 0.0);
@@ -541,8 +544,8 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     std::vector<double> stage((size_t)per_pair * nb, 0.0);
     std::vector<PairGeo> geo(nb);
     DevMem dstage, dgeo;
-    MFS_HIP(hipMalloc(&dstage.p, sizeof(double) * stage.size()));
-    MFS_HIP(hipMalloc(&dgeo.p, sizeof(PairGeo) * nb));
+    MFS_HIP(dstage.alloc(c, sizeof(double) * stage.size()));
+    MFS_HIP(dgeo.alloc(c, sizeof(PairGeo) * nb));
     const double* dbase = (const double*)dstage.p;
     std::vector<int64_t> eoff(nb);
     for (int q = 0; q < nb; ++q) {
@@ -640,15 +643,15 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_HIP(hipMemcpyAsync(dstage.p, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice, c->stream));
     MFS_HIP(hipMemcpyAsync(dgeo.p, geo.data(), sizeof(PairGeo) * nb, hipMemcpyHostToDevice, c->stream));
     DevMem deoff;
-    MFS_HIP(hipMalloc(&deoff.p, sizeof(int64_t) * nb));
+    MFS_HIP(deoff.alloc(c, sizeof(int64_t) * nb));
     MFS_HIP(hipMemcpyAsync(deoff.p, eoff.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, c->stream));
 
     const int64_t mn = std::min(m, n);
     DevMem dF, dX, dD, dC, dSF, dU, dVT, dE, dT1, dG, dDG, dSC, dUC, dVTC, dEC, dT2, dinfo, dinfoC;
-    MFS_HIP(hipMalloc(&dF.p, sizeof(double) * d.sF * nb));
-    MFS_HIP(hipMalloc(&dX.p, sizeof(double) * d.sX * nb));
-    MFS_HIP(hipMalloc(&dD.p, sizeof(double) * d.sD * nb));
-    MFS_HIP(hipMalloc(&dC.p, sizeof(double) * d.sC * nb));
+    MFS_HIP(dF.alloc(c, sizeof(double) * d.sF * nb));
+    MFS_HIP(dX.alloc(c, sizeof(double) * d.sX * nb));
+    MFS_HIP(dD.alloc(c, sizeof(double) * d.sD * nb));
+    MFS_HIP(dC.alloc(c, sizeof(double) * d.sC * nb));
     MFS_HIP(hipMemsetAsync(dF.p, 0, sizeof(double) * d.sF * nb, c->stream));
     MFS_HIP(hipMemsetAsync(dX.p, 0, sizeof(double) * d.sX * nb, c->stream));
     MFS_HIP(hipMemsetAsync(dD.p, 0, sizeof(double) * d.sD * nb, c->stream));
@@ -661,20 +664,20 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       MFS_HIP(hipGetLastError());
     }
     tick(1, t0);
-    MFS_HIP(hipMalloc(&dSF.p, sizeof(double) * mn * nb));
-    MFS_HIP(hipMalloc(&dU.p, sizeof(double) * m * mn * nb));
-    MFS_HIP(hipMalloc(&dVT.p, sizeof(double) * mn * n * nb));
-    MFS_HIP(hipMalloc(&dE.p, sizeof(double) * mn * nb));
-    MFS_HIP(hipMalloc(&dinfo.p, sizeof(int) * nb));
-    MFS_HIP(hipMalloc(&dinfoC.p, sizeof(int) * nb));
+    MFS_HIP(dSF.alloc(c, sizeof(double) * mn * nb));
+    MFS_HIP(dU.alloc(c, sizeof(double) * m * mn * nb));
+    MFS_HIP(dVT.alloc(c, sizeof(double) * mn * n * nb));
+    MFS_HIP(dE.alloc(c, sizeof(double) * mn * nb));
+    MFS_HIP(dinfo.alloc(c, sizeof(int) * nb));
+    MFS_HIP(dinfoC.alloc(c, sizeof(int) * nb));
     MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m, (int)n,
                                             (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p, (int)m,
                                             m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
                                             rocblas_outofplace, (int*)dinfo.p, nb));
     tick(2, t0);
     // T1 = U^T X  (mn x nx)
-    MFS_HIP(hipMalloc(&dT1.p, sizeof(double) * mn * nx * nb));
-    MFS_HIP(hipMalloc(&dG.p, sizeof(double) * n * nx * nb));
+    MFS_HIP(dT1.alloc(c, sizeof(double) * mn * nx * nb));
+    MFS_HIP(dG.alloc(c, sizeof(double) * n * nx * nb));
     const double one = 1.0, zero = 0.0, mone = -1.0;
     MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mn,
                                          (int)nx, (int)m, &one, (const double*)dU.p, (int)m, m * mn,
@@ -699,8 +702,8 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
         gq[q] = ps.goff[order[b0 + q]];
       }
       DevMem dnfq, dgq;
-      MFS_HIP(hipMalloc(&dnfq.p, sizeof(int32_t) * 2 * nb));
-      MFS_HIP(hipMalloc(&dgq.p, sizeof(int64_t) * nb));
+      MFS_HIP(dnfq.alloc(c, sizeof(int32_t) * 2 * nb));
+      MFS_HIP(dgq.alloc(c, sizeof(int64_t) * nb));
       MFS_HIP(hipMemcpyAsync(dnfq.p, nfq.data(), sizeof(int32_t) * 2 * nb, hipMemcpyHostToDevice, c->stream));
       MFS_HIP(hipMemcpyAsync(dgq.p, gq.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, c->stream));
       hipLaunchKernelGGL(k_store_fine, dim3((unsigned)nx, nb), dim3(256), 0, c->stream, (int)nx, d.nfpad[0],
@@ -709,23 +712,23 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       MFS_HIP(hipStreamSynchronize(c->stream));   // nfq, gq are released at the end of this scope
     }
     // DG = D G  (2mp x nx)
-    MFS_HIP(hipMalloc(&dDG.p, sizeof(double) * mpp * nx * nb));
+    MFS_HIP(dDG.alloc(c, sizeof(double) * mpp * nx * nb));
     MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none, (int)mpp, (int)nx,
                                          (int)n, &one, (const double*)dD.p, (int)mpp, d.sD, (const double*)dG.p,
                                          (int)n, n * nx, &zero, (double*)dDG.p, (int)mpp, mpp * nx, nb));
     tick(3, t0);
     // SVD of C (2mp x nx), then A = -V_C Sigma_C^+ U_C^T (D G)
     const int64_t mnc = std::min(mpp, nx);
-    MFS_HIP(hipMalloc(&dSC.p, sizeof(double) * mnc * nb));
-    MFS_HIP(hipMalloc(&dUC.p, sizeof(double) * mpp * mnc * nb));
-    MFS_HIP(hipMalloc(&dVTC.p, sizeof(double) * mnc * nx * nb));
-    MFS_HIP(hipMalloc(&dEC.p, sizeof(double) * mnc * nb));
+    MFS_HIP(dSC.alloc(c, sizeof(double) * mnc * nb));
+    MFS_HIP(dUC.alloc(c, sizeof(double) * mpp * mnc * nb));
+    MFS_HIP(dVTC.alloc(c, sizeof(double) * mnc * nx * nb));
+    MFS_HIP(dEC.alloc(c, sizeof(double) * mnc * nb));
     MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
                                             (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
                                             (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
                                             mnc * nx, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nb));
     tick(4, t0);
-    MFS_HIP(hipMalloc(&dT2.p, sizeof(double) * mnc * nx * nb));
+    MFS_HIP(dT2.alloc(c, sizeof(double) * mnc * nx * nb));
     MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnc,
                                          (int)nx, (int)mpp, &one, (const double*)dUC.p, (int)mpp, mpp * mnc,
                                          (const double*)dDG.p, (int)mpp, mpp * nx, &zero, (double*)dT2.p, (int)mnc,
@@ -762,7 +765,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
                  C, tstage[0], tstage[1], tstage[2], tstage[3], tstage[4], tstage[5]);
   if (keep) {
     auto up = [&](void** dst, const void* src, size_t bytes) -> Status {
-      MFS_HIP(hipMalloc(dst, std::max<size_t>(bytes, 8)));
+      MFS_HIP(dev_malloc(c, dst, std::max<size_t>(bytes, 8)));
       if (bytes) MFS_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
       return Status{};
     };

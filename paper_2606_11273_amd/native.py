@@ -31,7 +31,8 @@ SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_p
            "mfs_get_pair_matrices", "mfs_apply", "mfs_kernel_sum", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
            "mfs_get_sizes", "mfs_destroy", "mfs_last_error", "mfs_server_create", "mfs_server_footprint",
            "mfs_server_submit", "mfs_server_wait", "mfs_server_last_error", "mfs_server_destroy",
-           "mfs_keep_fine_factors", "mfs_get_density", "mfs_flow_eval", "mfs_boundary_residual"]
+           "mfs_keep_fine_factors", "mfs_get_density", "mfs_flow_eval", "mfs_boundary_residual",
+           "mfs_setup_ex"]
 
 
 class MfsParams(C.Structure):
@@ -61,6 +62,52 @@ class MfsTicketInfo(C.Structure):
                 ("ms_precompute", C.c_double), ("footprint_bytes", C.c_int64), ("solve", MfsSolveInfo)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class MfsAllocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device memory of a context from PyTorch's caching allocator (mfs_setup_ex callbacks).
+
+    Counts calls and live bytes; keep the object alive while the context exists."""
+
+    def __init__(self, stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.cuda.current_device()
+        self.allocs = self.frees = 0
+        self.live = {}
+
+        def _alloc(nbytes, user):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:   # an exception must not cross the C frame: report failure as NULL
+                return None
+            self.allocs += 1
+            self.live[ptr] = int(nbytes)
+            return ptr
+
+        def _free(ptr, user):
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            finally:
+                self.frees += 1
+                self.live.pop(ptr, None)
+
+        self._cb = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+        self.struct = MfsAllocator(self._cb[0], self._cb[1], None)
+
+    @property
+    def live_bytes(self):
+        return sum(self.live.values())
+
+
+_ALLOCATORS = {}   # context handle -> allocator kept alive until mfs_destroy
+
+
 class MFSError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -82,6 +129,8 @@ def lib():
     L.mfs_default_params.argtypes = [C.POINTER(MfsParams)]
     L.mfs_default_params.restype = None
     L.mfs_setup.argtypes = [C.POINTER(vp), C.c_int32, dp, dp, ip, ip, dp, C.POINTER(MfsParams), vp]
+    L.mfs_setup_ex.argtypes = [C.POINTER(vp), C.c_int32, dp, dp, ip, ip, dp, C.POINTER(MfsParams), vp,
+                               C.POINTER(MfsAllocator)]
     L.mfs_precompute_pairs.argtypes = [vp, C.c_int, i64p]
     L.mfs_get_pairs.argtypes = [vp, i64p, ip]
     L.mfs_set_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
@@ -142,8 +191,9 @@ def mfs_default_params():
     return p
 
 
-def mfs_setup(centers, radii, n_src, n_col, r_src, params=None, stream=None):
-    """Returns an opaque context handle (c_void_p).  Host inputs: numpy arrays."""
+def mfs_setup(centers, radii, n_src, n_col, r_src, params=None, stream=None, allocator=None):
+    """Returns an opaque context handle (c_void_p).  Host inputs: numpy arrays.  allocator: a
+    TorchAllocator (or any object with a .struct MfsAllocator) for mfs_setup_ex, else hipMalloc."""
     centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 2)
     P = centers.shape[0]
     radii = np.ascontiguousarray(np.broadcast_to(radii, (P,)), dtype=np.float64)
@@ -153,10 +203,17 @@ def mfs_setup(centers, radii, n_src, n_col, r_src, params=None, stream=None):
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     ctx = C.c_void_p()
-    code = lib().mfs_setup(C.byref(ctx), P, _dp(centers), _dp(radii), _ip(n_src), _ip(n_col), _dp(r_src),
-                           C.byref(params) if params is not None else None, C.c_void_p(stream))
+    if allocator is None:
+        code = lib().mfs_setup(C.byref(ctx), P, _dp(centers), _dp(radii), _ip(n_src), _ip(n_col), _dp(r_src),
+                               C.byref(params) if params is not None else None, C.c_void_p(stream))
+    else:
+        code = lib().mfs_setup_ex(C.byref(ctx), P, _dp(centers), _dp(radii), _ip(n_src), _ip(n_col), _dp(r_src),
+                                  C.byref(params) if params is not None else None, C.c_void_p(stream),
+                                  C.byref(allocator.struct))
     if code != MFS_OK:
         raise MFSError(code, lib().mfs_last_error(None).decode())
+    if allocator is not None:
+        _ALLOCATORS[ctx.value] = allocator
     return ctx
 
 
@@ -286,6 +343,7 @@ def mfs_gmres_solve(ctx, problem, precision, rhs, tol, max_iter=500, x0=None, hi
 def mfs_destroy(ctx):
     if ctx:
         lib().mfs_destroy(ctx)
+        _ALLOCATORS.pop(ctx.value, None)
 
 
 # -- serving ----------------------------------------------------------------------------
