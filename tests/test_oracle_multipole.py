@@ -1,0 +1,83 @@
+"""Pins of the far-field expansion of a ring of Stokeslets (oracle/multipole.py).
+
+* against the direct Stokeslet sum (oracle/kernel.py, eq. stokeslet2d) for random
+  strengths on rings of several sizes and radii, at theta = rho/|Z| = 1/4 and 1/2:
+  the truncated expansion stays below sum |sigma| theta^(p+1) / (1 - theta) / (4 pi mu);
+* the error falls geometrically with the order p (ratio ~theta), and at high order the
+  expansion equals the direct sum to rounding;
+* the special strengths of the mobility problem (zero net force and torque after the
+  rigid projection): S0 = 0 and B_1 real, and the expansion still matches.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle.geometry import rigid_map, rigid_projector, ring
+from oracle.kernel import direct_sum
+from oracle.multipole import far_field, moments
+
+
+def _case(n, rho, seed, project=False):
+    rng = np.random.default_rng(seed)
+    c = np.array([0.3, -0.4])
+    y = ring(c, rho, n)
+    sig = rng.standard_normal((n, 2))
+    if project:
+        K = rigid_map(y, c)
+        sig = (sig.reshape(-1) - rigid_projector(K) @ sig.reshape(-1)).reshape(-1, 2)
+    w = (y[:, 0] - c[0]) + 1j * (y[:, 1] - c[1])
+    s = sig[:, 0] + 1j * sig[:, 1]
+    return c, y, sig, w, s
+
+
+def _points(c, R, m=11):
+    ang = np.linspace(0, 2 * math.pi, m, endpoint=False) + 0.3
+    return c + R * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+
+
+@pytest.mark.parametrize("n,rho", [(36, 0.7), (50, 0.98), (7, 0.5)])
+def test_truncated_expansion_within_bound(n, rho):
+    mu = 1.3
+    c, y, sig, w, s = _case(n, rho, 1)
+    for theta in (0.25, 0.5):
+        x = _points(c, rho / theta)
+        ref = direct_sum(x, y, sig, mu)
+        Z = (x[:, 0] - c[0]) + 1j * (x[:, 1] - c[1])
+        for p in (4, 8, 12):
+            A, B = moments(w, s, p)
+            u = far_field(Z, A, B, rho, mu)
+            err = np.abs(np.stack([u.real, u.imag], axis=1) - ref).max()
+            bound = np.abs(s).sum() * theta ** (p + 1) / (1 - theta) / (4 * math.pi * mu)
+            assert err <= bound, (n, rho, theta, p, err, bound)
+
+
+def test_error_falls_geometrically_and_high_order_is_exact():
+    c, y, sig, w, s = _case(36, 0.7, 2)
+    theta = 0.5
+    x = _points(c, 0.7 / theta)
+    ref = direct_sum(x, y, sig)
+    Z = (x[:, 0] - c[0]) + 1j * (x[:, 1] - c[1])
+    errs = []
+    for p in (6, 12, 18):
+        u = far_field(Z, *moments(w, s, p), 0.7)
+        errs.append(np.abs(np.stack([u.real, u.imag], axis=1) - ref).max())
+    assert errs[1] < 0.5 ** 5 * errs[0] and errs[2] < 0.5 ** 5 * errs[1]
+    x = _points(c, 0.7 / 0.25)                      # theta = 1/4, p = 30: truncation 1e-19
+    ref = direct_sum(x, y, sig)
+    Z = (x[:, 0] - c[0]) + 1j * (x[:, 1] - c[1])
+    u = far_field(Z, *moments(w, s, 30), 0.7)
+    assert np.abs(np.stack([u.real, u.imag], axis=1) - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_mobility_strengths_zero_force_and_torque():
+    c, y, sig, w, s = _case(36, 0.7, 3, project=True)
+    A, B = moments(w, s, 12)
+    assert abs(A[0]) < 1e-13 and abs(B[1].imag) < 1e-13   # net force, torque = Im(sum conj(w) sigma)
+    x = _points(c, 0.7 / 0.25)
+    ref = direct_sum(x, y, sig)
+    Z = (x[:, 0] - c[0]) + 1j * (x[:, 1] - c[1])
+    u = far_field(Z, A, B, 0.7)
+    bound = np.abs(s).sum() * 0.25 ** 13 / 0.75 / (4 * math.pi)
+    assert np.abs(np.stack([u.real, u.imag], axis=1) - ref).max() <= bound
