@@ -40,6 +40,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 20          # algorithmic flops of one Stokeslet evaluation applied to a 2-vector
+# One evaluation of a far disk's expansion in the FP32 kernel sum (order 12): three complex
+# Horner series, 24 flops per step over 11 steps, plus about 66 for the first terms, zeta,
+# the log term and the combination (two of them transcendental)
+MP_ORDER = 12
+FLOP_PER_EXPANSION = 24 * (MP_ORDER - 1) + 66
+MP_FAR2 = 16.0              # a disk is far for a target beyond 4 ring radii
+KSUM_T = 2                  # targets per thread of the FP32 kernel sum (its default)
+
+
+def ksum_work(centers, radii, n_src, r_src, X, threads_T=KSUM_T, block=256):
+    """Work of one FP32 kernel-sum launch: direct pair evaluations and far-disk expansions.
+
+    A thread holds T targets (block apart within a workgroup of block * T targets); a disk is
+    evaluated through its expansion when it is far from all of them (|x - c|^2 > 16 rho^2),
+    else directly over its sources for all of them (skipped disks included: their terms are
+    computed and not accumulated).  The last workgroup's missing targets are not counted."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    rho = np.asarray(r_src, dtype=np.float64) * np.asarray(radii, dtype=np.float64)
+    tree = cKDTree(centers)
+    lists = tree.query_ball_point(X, r=float(np.sqrt(MP_FAR2) * rho.max()))
+    cnt = np.array([len(l) for l in lists])
+    t_idx = np.repeat(np.arange(X.shape[0]), cnt)
+    k_idx = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists])
+    d = X[t_idx] - centers[k_idx]
+    keep = np.einsum("ij,ij->i", d, d) <= MP_FAR2 * rho[k_idx] ** 2
+    t_idx, k_idx = t_idx[keep], k_idx[keep]
+    per_blk = block * threads_T
+    thread = (t_idx // per_blk) * block + (t_idx % block)
+    n_threads = (X.shape[0] + per_blk - 1) // per_blk * block
+    P = centers.shape[0]
+    uniq = np.unique(thread.astype(np.int64) * P + k_idx)
+    near_k = uniq % P
+    pairs = threads_T * int(np.asarray(n_src, dtype=np.int64)[near_k].sum())
+    exps = threads_T * (n_threads * P - uniq.size)
+    return pairs, exps
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (dense, packed FP32)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6   # one FP32 FMA per lane per cycle: the ceiling without packed FP32
 PEAK_FP64_TFLOPS = 78.6
@@ -254,18 +290,30 @@ def main():
         torch.cuda.synchronize()
 
     # roofline of the dominant kernel (mixed kernel sum; one launch = one matvec's sum without
-    # each disk's own sources and its contact partners'): exact evaluations per launch
+    # each disk's own sources and its contact partners).  pair_evals_per_launch counts the
+    # Stokeslet pairs of the direct sum the launch stands for; the FP32 kernel evaluates far
+    # disks through their expansions, so its algorithmic flops are the direct pairs it does
+    # compute (near disks) times 20 plus its expansion evaluations times FLOP_PER_EXPANSION
     pr = nv.mfs_get_pairs(ctx)
     skipped = ns.astype(np.int64).copy()
     np.add.at(skipped, pr[:, 0], ns[pr[:, 1]])
     np.add.at(skipped, pr[:, 1], ns[pr[:, 0]])
     evals_launch = int(np.sum(nc.astype(np.int64) * (Ns - skipped)))
-    achieved = evals_launch * FLOP_PER_PAIR / (ks["mixed"] * 1e-3) / 1e12
+    Xt = np.concatenate([c[i] + a[i] * np.stack([np.cos(2 * np.pi * np.arange(nc[i]) / nc[i]),
+                                                 np.sin(2 * np.pi * np.arange(nc[i]) / nc[i])], axis=1)
+                         for i in range(P)])
+    t0 = time.perf_counter()
+    near_pairs, expansions = ksum_work(c, a, ns, rs, Xt)
+    log(f"kernel-sum work: {near_pairs} direct pairs, {expansions} expansions ({time.perf_counter() - t0:.1f}s)")
+    flops_launch = near_pairs * FLOP_PER_PAIR + expansions * FLOP_PER_EXPANSION
+    achieved = flops_launch / (ks["mixed"] * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=ksum_traffic_bytes(),
                     frac_of_nonpacked_peak=round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
-                    kernel="k_ksum_mixed (FP32 compensated Stokeslet sum)",
-                    ms_per_launch=round(ks["mixed"], 3), pair_evals_per_launch=evals_launch,
+                    kernel="k_ksum_mixed (FP32 Stokeslet sum; far disks by their order-12 expansions)",
+                    ms_per_launch=round(ks["mixed"], 3), flops_per_launch=flops_launch,
+                    direct_pairs_per_launch=near_pairs, expansions_per_launch=expansions,
+                    pair_evals_per_launch=evals_launch,
                     pair_evals_per_s=round(evals_launch / (ks["mixed"] * 1e-3), 1),
                     fp64_kernel_ms_per_launch=round(ks["fp64"], 2),
                     fp64_kernel_tflops=round(evals_launch * FLOP_PER_PAIR / (ks["fp64"] * 1e-3) / 1e12, 2),

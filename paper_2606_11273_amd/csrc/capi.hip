@@ -81,7 +81,7 @@ void free_all(mfs_ctx* c) {
                   c->d_out3,    c->d_given,   c->d_sig32, c->d_src64,    c->ps[0].A,  c->ps[0].E,  c->ps[1].A,
                   c->ps[1].E,   c->kr.V,      c->kr.w,    c->kr.part,    c->kr.hdev,  c->kr.x,     c->kr.r,
                   c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
-                  c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf};
+                  c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf, c->d_mp};
   for (void* p : ptrs)
     if (p) dev_free(c, p);
   for (const PairSet& ps : c->ps)
@@ -226,6 +226,7 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   if ((st = dalloc(c, &c->d_given, 3 * (size_t)P)).code) return st;
   if ((st = dalloc(c, &c->d_sig32, c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_bdat, (size_t)P)).code) return st;
+  if ((st = dalloc(c, &c->d_mp, (size_t)P * kMpCoefPerDisk)).code) return st;
   if ((st = dalloc(c, &c->d_src64, c->Ns)).code) return st;
   MFS_HIP(hipStreamSynchronize(s));
   return Status{};

@@ -15,6 +15,8 @@ namespace mfs {
 
 constexpr int kMaxClasses = 4;     // distinct (radius, n_src, n_col, r_src) disk classes
 constexpr int kMaxCol = 512;       // n_col limit per disk
+constexpr int kMpOrder = 12;       // order of the per-disk far-field expansion of the FP32 kernel sum
+constexpr int kMpCoefPerDisk = 3 * kMpOrder + 2;   // its FP32 complex coefficients per disk
 constexpr double kPiD = 3.14159265358979323846;
 
 struct Status {
@@ -108,7 +110,8 @@ struct mfs_ctx {
   double *d_lam_bar = nullptr, *d_ltil = nullptr, *d_sig64 = nullptr, *d_u = nullptr, *d_corr = nullptr;
   double *d_upart = nullptr, *d_epair = nullptr, *d_out3 = nullptr, *d_given = nullptr;
   float4* d_sig32 = nullptr;     // per source: (yr_x, yr_y, sigma_x, sigma_y)
-  float4* d_bdat = nullptr;      // per disk: (net strength x, y, ring radius^2, 0) for the FP32 sum
+  float4* d_bdat = nullptr;      // per disk: (net strength x, y, ring radius^2, W) for the FP32 sum
+  float2* d_mp = nullptr;        // per disk: far-field expansion coefficients for the FP32 sum
   double4* d_src64 = nullptr;    // per source: (y_x, y_y, sigma_x, sigma_y)
   int64_t upart_cap = 0;
 
@@ -153,7 +156,7 @@ void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil);
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                            bool pack32, bool pack64);
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                              float4* sig32, double4* src64, float4* bdat);
+                              float4* sig32, double4* src64, float4* bdat, float2* mp = nullptr);
 // stacked forms for R = 2, 4 or 8 vectors (false: unsupported size or out of memory)
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
                        int64_t ltil_stride);

@@ -218,12 +218,25 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_A_rhs(int C, const int* _
 // ---------------------------------------------------------------------------
 // eq. total_corr + projection: lambda^(b) = lambda_bar^(b) + sum_{c contains b} lambda_tilde^c_b,
 // sigma = (I - L) lambda (mobility) or lambda (resistance); packed for the kernel sum.
+// Far-field expansion of a disk for the FP32 kernel sum (Sec. 6 evaluates the far field
+// with a fast multipole method; here one level, per disk).  In complex notation, with
+// w_s = y_s - c on the ring |w| = rho, A_k = sum sigma w^k, B_k = sum sigma conj(w)^k and
+// zeta = 1/Z for a point x = c + Z, the disk's contribution to the sum below is
+//   -S0 ln|Z| + S0/2 + sum_k (A_k zeta^k + B_k conj(zeta)^k)/(2k)
+//   + conj(zeta)/2 [ (Z - rho^2 conj(zeta)) sum_{k>=0} conj(A_k) conj(zeta)^k - conj(B_1) ].
+// Order kMpOrder, used where |Z| > rho / kMpTheta: truncation below
+// sum |sigma| kMpTheta^(kMpOrder + 1) / (1 - kMpTheta) = 2e-8 sum |sigma|.  Coefficients per
+// disk (FP64 sums, stored FP32): A_k/(2k) (k = 1..p), B_k/(2k) (k = 1..p), conj(A_k)
+// (k = 0..p), conj(B_1).
+constexpr int kMpCoef = kMpCoefPerDisk;
+constexpr float kMpFar2 = 16.0f;   // (1 / kMpTheta)^2, kMpTheta = 1/4
+
 __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
     int P, int mobility, const int* __restrict__ cls, const int* __restrict__ src_off, ClassTab ct,
     const int* __restrict__ bp_off, const int* __restrict__ bp_list, const int* __restrict__ pairs,
     const int64_t* __restrict__ xoff, const double* __restrict__ ltil, const double* __restrict__ lam_bar,
     int with_pairs, const double* __restrict__ centers, double* __restrict__ sig64, float4* __restrict__ sig32,
-    double4* __restrict__ src64, float4* __restrict__ bdat) {
+    double4* __restrict__ src64, float4* __restrict__ bdat, float2* __restrict__ mp) {
   const int b = blockIdx.x;
   if (b >= P) return;
   const int k = cls[b];
@@ -262,6 +275,62 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
     if (threadIdx.x == 0) {
       const double q = Yr[0] * Yr[0] + Yr[1] * Yr[1];
       bdat[b] = make_float4((float)s0x, (float)s0y, (float)q, (float)w);
+    }
+  }
+  if (mp) {
+    // multipole moments A_1..A_p, B_1..B_p (FP64; A_0 = S0 and B_1 are the moments above)
+    double ar[kMpOrder], ai[kMpOrder], br[kMpOrder], bi[kMpOrder];
+#pragma unroll
+    for (int k = 0; k < kMpOrder; ++k) ar[k] = ai[k] = br[k] = bi[k] = 0.0;
+    double s0r = 0.0, s0i = 0.0;
+    for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
+      const double wx = Yr[2 * j], wy = Yr[2 * j + 1], sx = s_l[2 * j], sy = s_l[2 * j + 1];
+      s0r += sx;
+      s0i += sy;
+      double pr = sx, pi = sy, qr = sx, qi = sy;   // sigma w^k and sigma conj(w)^k
+#pragma unroll
+      for (int k = 0; k < kMpOrder; ++k) {
+        const double tr = pr * wx - pi * wy, ti = pr * wy + pi * wx;
+        const double ur = qr * wx + qi * wy, ui = qi * wx - qr * wy;
+        pr = tr;
+        pi = ti;
+        qr = ur;
+        qi = ui;
+        ar[k] += pr;
+        ai[k] += pi;
+        br[k] += qr;
+        bi[k] += qi;
+      }
+    }
+    __shared__ double mred[2][4 * kMpOrder + 2];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    auto put = [&](int slot, double v) {
+      v = wave_sum(v);
+      if (lane == 0) mred[wid][slot] = v;
+    };
+#pragma unroll
+    for (int k = 0; k < kMpOrder; ++k) {
+      put(4 * k, ar[k]);
+      put(4 * k + 1, ai[k]);
+      put(4 * k + 2, br[k]);
+      put(4 * k + 3, bi[k]);
+    }
+    put(4 * kMpOrder, s0r);
+    put(4 * kMpOrder + 1, s0i);
+    __syncthreads();
+    static_assert(kBodyThreads == 128, "two waves per body block");
+    for (int e = threadIdx.x; e < 4 * kMpOrder + 2; e += kBodyThreads) mred[0][e] += mred[1][e];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float2* o = mp + (int64_t)b * kMpCoef;
+      for (int k = 1; k <= kMpOrder; ++k) {
+        const double* m = &mred[0][4 * (k - 1)];
+        o[k - 1] = make_float2((float)(m[0] / (2 * k)), (float)(m[1] / (2 * k)));
+        o[kMpOrder + k - 1] = make_float2((float)(m[2] / (2 * k)), (float)(m[3] / (2 * k)));
+        o[2 * kMpOrder + k] = make_float2((float)m[0], (float)(-m[1]));
+      }
+      o[2 * kMpOrder] = make_float2((float)mred[0][4 * kMpOrder], (float)(-mred[0][4 * kMpOrder + 1]));
+      o[3 * kMpOrder + 1] = make_float2((float)mred[0][2], (float)(-mred[0][3]));
     }
   }
   for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
@@ -339,12 +408,14 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
                                                            const double* __restrict__ X, int bodies_per_split,
                                                            int mode, const int* __restrict__ nbr_off,
                                                            const int* __restrict__ nbr_list, double scale,
-                                                           double* __restrict__ out) {
+                                                           double* __restrict__ out,
+                                                           const float2* __restrict__ mp) {
   __shared__ float4 s_src[KS_TILE];    // (y_x, y_y, sigma_x, sigma_y), y relative to the disk centre
   __shared__ float s_w[KS_TILE];       // y . sigma
   __shared__ double s_c[2 * KS_MAXB];
   __shared__ float4 s_b[KS_MAXB];
   __shared__ int s_off[KS_MAXB + 1];
+  __shared__ float2 s_mp[KS_MAXB * kMpCoef];   // far-field coefficients of the tile's disks
   const int split = blockIdx.y;
   const int kb0 = split * bodies_per_split;
   const int kb1 = min(P, kb0 + bodies_per_split);
@@ -381,10 +452,85 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
       s_b[q] = bdat[kt + q];
     }
     for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
+    for (int q = threadIdx.x; q < nb * kMpCoef; q += KS_THREADS) s_mp[q] = mp[(int64_t)kt * kMpCoef + q];
     __syncthreads();
     for (int kk = 0; kk < nb; ++kk) {
       const int kbody = kt + kk;
       const float4 bd = s_b[kk];   // (S0x, S0y, q = |y|^2, W = sum y . sigma)
+      {
+        // far disk for every target of this thread: its multipole expansion (see k_gather_project)
+        float Zx[T], Zy[T], R2[T];
+        bool far = true;
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          Zx[j] = (float)(x[j] - s_c[2 * kk]);
+          Zy[j] = (float)(y[j] - s_c[2 * kk + 1]);
+          R2[j] = fmaf(Zx[j], Zx[j], Zy[j] * Zy[j]);
+          far = far && R2[j] > kMpFar2 * bd.z;
+        }
+        if (far) {
+          const float2* cf = s_mp + kk * kMpCoef;
+          float zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T];
+#pragma unroll
+          for (int j = 0; j < T; ++j) {
+            const float ir2 = __builtin_amdgcn_rcpf(R2[j]);
+            zr[j] = Zx[j] * ir2;    // zeta = conj(Z) / R^2 = (zr, -zi); conj(zeta) = (zr, zi)
+            zi[j] = Zy[j] * ir2;
+            h1r[j] = cf[kMpOrder - 1].x;
+            h1i[j] = cf[kMpOrder - 1].y;
+            h2r[j] = cf[2 * kMpOrder - 1].x;
+            h2i[j] = cf[2 * kMpOrder - 1].y;
+            h3r[j] = cf[3 * kMpOrder].x;
+            h3i[j] = cf[3 * kMpOrder].y;
+          }
+          // Horner: h1 over zeta (A_k/2k), h2 over conj(zeta) (B_k/2k), h3 over conj(zeta) (conj A_k)
+#pragma unroll
+          for (int k = kMpOrder - 1; k >= 1; --k) {
+            const float2 a = cf[k - 1], bq = cf[kMpOrder + k - 1], g = cf[2 * kMpOrder + k];
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+              const float t1r = fmaf(zr[j], h1r[j], fmaf(zi[j], h1i[j], a.x));
+              const float t1i = fmaf(zr[j], h1i[j], fmaf(-zi[j], h1r[j], a.y));
+              const float t2r = fmaf(zr[j], h2r[j], fmaf(-zi[j], h2i[j], bq.x));
+              const float t2i = fmaf(zr[j], h2i[j], fmaf(zi[j], h2r[j], bq.y));
+              const float t3r = fmaf(zr[j], h3r[j], fmaf(-zi[j], h3i[j], g.x));
+              const float t3i = fmaf(zr[j], h3i[j], fmaf(zi[j], h3r[j], g.y));
+              h1r[j] = t1r;
+              h1i[j] = t1i;
+              h2r[j] = t2r;
+              h2i[j] = t2i;
+              h3r[j] = t3r;
+              h3i[j] = t3i;
+            }
+          }
+          const float2 g0 = cf[2 * kMpOrder], dl = cf[3 * kMpOrder + 1];
+#pragma unroll
+          for (int j = 0; j < T; ++j) {
+            // P3 = conj(A_0) + conj(zeta) h3; P1 = zeta h1; P2 = conj(zeta) h2
+            const float p3r = fmaf(zr[j], h3r[j], fmaf(-zi[j], h3i[j], g0.x));
+            const float p3i = fmaf(zr[j], h3i[j], fmaf(zi[j], h3r[j], g0.y));
+            const float p1r = fmaf(zr[j], h1r[j], zi[j] * h1i[j]);
+            const float p1i = fmaf(zr[j], h1i[j], -zi[j] * h1r[j]);
+            const float p2r = fmaf(zr[j], h2r[j], -zi[j] * h2i[j]);
+            const float p2i = fmaf(zr[j], h2i[j], zi[j] * h2r[j]);
+            // conj(zeta)/2 [(Z - rho^2 conj(zeta)) P3 - conj(B_1)], Z - rho^2 conj(zeta) = Z (1 - q / R^2)
+            const float f = fmaf(-bd.z, zr[j] * zr[j] + zi[j] * zi[j], 1.0f);
+            const float mr = f * fmaf(Zx[j], p3r, -Zy[j] * p3i) - dl.x;
+            const float mi = f * fmaf(Zx[j], p3i, Zy[j] * p3r) - dl.y;
+            const float t3r = 0.5f * fmaf(zr[j], mr, -zi[j] * mi);
+            const float t3i = 0.5f * fmaf(zr[j], mi, zi[j] * mr);
+            // -S0 ln|Z| + S0 / 2
+            const float lZ = fmaf(-kHalfLn2, __builtin_amdgcn_logf(R2[j]), 0.5f);
+            const float fx = fmaf(bd.x, lZ, p1r + p2r + t3r);
+            const float fy = fmaf(bd.y, lZ, p1i + p2i + t3i);
+            if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
+              ax[j] += (double)fx;
+              ay[j] += (double)fy;
+            }
+          }
+          continue;
+        }
+      }
       // per (target, disk): D = x - c_k (FP64, rounded once), R^2 = |D|^2, and the
       // scaled offsets for w = r^2 / R^2 - 1 = (q - 2 D.y) / R^2
       float Dx[T], Dy[T], ir2[T], Dxs[T], Dys[T], qs[T], lx[T], ly[T], t0[T], tsx[T], tsy[T];
@@ -1258,15 +1404,15 @@ void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil) {
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                            bool pack32, bool pack64) {
   launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, pack32 ? c->d_sig32 : nullptr,
-                           pack64 ? c->d_src64 : nullptr, pack32 ? c->d_bdat : nullptr);
+                           pack64 ? c->d_src64 : nullptr, pack32 ? c->d_bdat : nullptr, pack32 ? c->d_mp : nullptr);
 }
 
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                              float4* sig32, double4* src64, float4* bdat) {
+                              float4* sig32, double4* src64, float4* bdat, float2* mp) {
   hipLaunchKernelGGL(k_gather_project, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P,
                      prob == MFS_MOBILITY ? 1 : 0, c->d_cls, c->d_src_off, c->ct[prob], c->d_bp_off, c->d_bp_list,
                      c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers, (double*)nullptr,
-                     sig32, src64, bdat);
+                     sig32, src64, bdat, mp);
 }
 
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
@@ -1379,7 +1525,7 @@ bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale
 #define MFS_KS_MIXED(TT)                                                                                          \
   hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_centers,   \
                      c->d_sig32, c->d_bdat, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, \
-                     scale, out)
+                     scale, out, (const float2*)c->d_mp)
 #define MFS_KS_FP64(TT)                                                                                       \
   hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_src64, Nt, \
                      c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out)
