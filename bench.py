@@ -77,14 +77,13 @@ def ksum_work(centers, radii, n_src, r_src, X, threads_T=KSUM_T, block=256):
     exps = threads_T * (n_threads * P - uniq.size)
     return pairs, exps
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (dense, packed FP32)
-PEAK_FP32_NONPACKED_TFLOPS = 78.6   # one FP32 FMA per lane per cycle: the ceiling without packed FP32
 PEAK_FP64_TFLOPS = 78.6
 
 # HBM traffic of one k_ksum_mixed launch on this workload: rocprofv3 --pmc FETCH_SIZE, then
 # WRITE_SIZE (KiB per dispatch, `bench.py --kernel-only --copy-calibration`), each scaled by what
 # the counter reads for an elementwise kernel that reads and writes 1 GiB (factors 2.0 and 1.0).
 # It holds for the kernel source it was measured on, identified by a hash of k_ksum_mixed's text.
-KSUM_TRAFFIC = {"src_sha256_16": "4b27b88e85ee1a8c", "fetch_kib": 138800.0, "write_kib": 180000.0,
+KSUM_TRAFFIC = {"src_sha256_16": "ffb4afe3b5c4eeb9", "fetch_kib": 151436.9, "write_kib": 180000.0,
                 "fetch_factor": 2.0, "write_factor": 1.0}
 
 
@@ -309,7 +308,6 @@ def main():
     achieved = flops_launch / (ks["mixed"] * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=ksum_traffic_bytes(),
-                    frac_of_nonpacked_peak=round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                     kernel="k_ksum_mixed (FP32 Stokeslet sum; far disks by their order-12 expansions)",
                     ms_per_launch=round(ks["mixed"], 3), flops_per_launch=flops_launch,
                     direct_pairs_per_launch=near_pairs, expansions_per_launch=expansions,

@@ -120,6 +120,7 @@ struct mfs_ctx {
   double *d_lam_bar_m = nullptr, *d_ltil_m = nullptr, *d_u_m = nullptr, *d_corr_m = nullptr;
   float4* d_sig32m = nullptr;    // rhs_cap arrays of Ns records
   float4* d_bdatm = nullptr;     // rhs_cap arrays of P records
+  float2* d_mpm = nullptr;       // rhs_cap arrays of P far-field coefficient records
   double4* d_src64m = nullptr;   // rhs_cap arrays of Ns records
 
   mfs::PairSet ps[2];

@@ -698,13 +698,14 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed_rhs(
     int P, const int* __restrict__ src_off, const double* __restrict__ centers, const float4* __restrict__ src,
     int64_t Ns, const float4* __restrict__ bdat, int64_t Nt, const int* __restrict__ tgt_body,
     const double* __restrict__ X, int bodies_per_split, int mode, const int* __restrict__ nbr_off,
-    const int* __restrict__ nbr_list, double scale, double* __restrict__ out) {
+    const int* __restrict__ nbr_list, double scale, double* __restrict__ out, const float2* __restrict__ mpm) {
   __shared__ float2 s_y[KR_TILE];
   __shared__ float2 s_s[KR_TILE * R];   // [q][r] strengths
   __shared__ float s_w[KR_TILE * R];    // [q][r] y . sigma_r
   __shared__ double s_c[2 * KR_MAXB];
   __shared__ float4 s_b[KR_MAXB * R];   // [kk][r] (S0x, S0y, q, W)
   __shared__ int s_off[KR_MAXB + 1];
+  __shared__ float2 s_mp[KR_MAXB * R * kMpCoef];   // [kk][r] far-field coefficients
   const int split = blockIdx.y;
   const int kb0 = split * bodies_per_split;
   const int kb1 = min(P, kb0 + bodies_per_split);
@@ -740,6 +741,11 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed_rhs(
       s_c[2 * q + 1] = centers[2 * (kt + q) + 1];
     }
     for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
+    for (int e = threadIdx.x; e < nb * R * kMpCoef; e += KS_THREADS) {
+      const int kk = e / (R * kMpCoef), rem = e - kk * (R * kMpCoef);
+      const int r = rem / kMpCoef, q = rem - r * kMpCoef;
+      s_mp[e] = mpm[((int64_t)r * P + kt + kk) * kMpCoef + q];
+    }
     __syncthreads();
     for (int kk = 0; kk < nb; ++kk) {
       const int kbody = kt + kk;
@@ -747,6 +753,47 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed_rhs(
       const float Dy = (float)(y - s_c[2 * kk + 1]);
       const float R2 = fmaf(Dx, Dx, Dy * Dy);
       const float ir2 = __builtin_amdgcn_rcpf(R2);
+      if (R2 > kMpFar2 * s_b[kk * R].z) {
+        // far disk: the expansion of each strength vector (k_ksum_mixed, k_gather_project)
+        const bool use = !skip_test(sk, mode, kbody, bt, nbr_list);
+        const float zr = Dx * ir2, zi = Dy * ir2;
+        const float f = fmaf(-s_b[kk * R].z, ir2, 1.0f);
+        const float lZ = fmaf(-kHalfLn2, __builtin_amdgcn_logf(R2), 0.5f);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float2* cf = s_mp + (kk * R + r) * kMpCoef;
+          float h1r = cf[kMpOrder - 1].x, h1i = cf[kMpOrder - 1].y;
+          float h2r = cf[2 * kMpOrder - 1].x, h2i = cf[2 * kMpOrder - 1].y;
+          float h3r = cf[3 * kMpOrder].x, h3i = cf[3 * kMpOrder].y;
+#pragma unroll
+          for (int k = kMpOrder - 1; k >= 1; --k) {
+            const float2 a = cf[k - 1], bq = cf[kMpOrder + k - 1], g = cf[2 * kMpOrder + k];
+            const float t1r = fmaf(zr, h1r, fmaf(zi, h1i, a.x)), t1i = fmaf(zr, h1i, fmaf(-zi, h1r, a.y));
+            const float t2r = fmaf(zr, h2r, fmaf(-zi, h2i, bq.x)), t2i = fmaf(zr, h2i, fmaf(zi, h2r, bq.y));
+            const float t3r = fmaf(zr, h3r, fmaf(-zi, h3i, g.x)), t3i = fmaf(zr, h3i, fmaf(zi, h3r, g.y));
+            h1r = t1r;
+            h1i = t1i;
+            h2r = t2r;
+            h2i = t2i;
+            h3r = t3r;
+            h3i = t3i;
+          }
+          const float2 g0 = cf[2 * kMpOrder], dl = cf[3 * kMpOrder + 1];
+          const float p3r = fmaf(zr, h3r, fmaf(-zi, h3i, g0.x)), p3i = fmaf(zr, h3i, fmaf(zi, h3r, g0.y));
+          const float p1r = fmaf(zr, h1r, zi * h1i), p1i = fmaf(zr, h1i, -zi * h1r);
+          const float p2r = fmaf(zr, h2r, -zi * h2i), p2i = fmaf(zr, h2i, zi * h2r);
+          const float mr = f * fmaf(Dx, p3r, -Dy * p3i) - dl.x;
+          const float mi = f * fmaf(Dx, p3i, Dy * p3r) - dl.y;
+          const float t3r = 0.5f * fmaf(zr, mr, -zi * mi);
+          const float t3i = 0.5f * fmaf(zr, mi, zi * mr);
+          const float4 bd = s_b[kk * R + r];
+          if (use) {
+            ax[r] += (double)fmaf(bd.x, lZ, p1r + p2r + t3r);
+            ay[r] += (double)fmaf(bd.y, lZ, p1i + p2i + t3i);
+          }
+        }
+        continue;
+      }
       const float Dxs = -2.0f * Dx * ir2, Dys = -2.0f * Dy * ir2;
       const float qs = s_b[kk * R].z * ir2;
       // With a_s = d_s . sigma_s and t_s = a_s / u_s, the dyadic sum of k_ksum_mixed is
@@ -1480,7 +1527,7 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
 #define MFS_KR_MIXED(RR)                                                                                     \
   hipLaunchKernelGGL(k_ksum_mixed_rhs<RR>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off,        \
                      c->d_centers, c->d_sig32m, c->Ns, c->d_bdatm, Nt, c->d_tgt_body, c->d_X, bps, mode,    \
-                     c->d_nbr_off, c->d_nbr_list, scale, out)
+                     c->d_nbr_off, c->d_nbr_list, scale, out, (const float2*)c->d_mpm)
 #define MFS_KR_FP64(RR)                                                                                    \
   hipLaunchKernelGGL(k_ksum_fp64_rhs<RR>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off,       \
                      c->d_src64m, c->Ns, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, \
