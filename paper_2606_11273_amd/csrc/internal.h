@@ -15,7 +15,7 @@ namespace mfs {
 
 constexpr int kMaxClasses = 4;     // distinct (radius, n_src, n_col, r_src) disk classes
 constexpr int kMaxCol = 512;       // n_col limit per disk
-constexpr int kMpOrder = 12;       // order of the per-disk far-field expansion of the FP32 kernel sum
+constexpr int kMpOrder = 8;        // order of the per-disk far-field expansion of the FP32 kernel sum
 constexpr int kMpCoefPerDisk = 3 * kMpOrder + 2;   // its FP32 complex coefficients per disk
 constexpr double kPiD = 3.14159265358979323846;
 

@@ -224,12 +224,12 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_A_rhs(int C, const int* _
 // zeta = 1/Z for a point x = c + Z, the disk's contribution to the sum below is
 //   -S0 ln|Z| + S0/2 + sum_k (A_k zeta^k + B_k conj(zeta)^k)/(2k)
 //   + conj(zeta)/2 [ (Z - rho^2 conj(zeta)) sum_{k>=0} conj(A_k) conj(zeta)^k - conj(B_1) ].
-// Order kMpOrder, used where |Z| > rho / kMpTheta: truncation below
-// sum |sigma| kMpTheta^(kMpOrder + 1) / (1 - kMpTheta) = 2e-8 sum |sigma|.  Coefficients per
+// Order kMpOrder = 8, used where |Z| > rho / kMpTheta, kMpTheta = 1/7: truncation below
+// sum |sigma| kMpTheta^(kMpOrder + 1) / (1 - kMpTheta) = 3e-8 sum |sigma|.  Coefficients per
 // disk (FP64 sums, stored FP32): A_k/(2k) (k = 1..p), B_k/(2k) (k = 1..p), conj(A_k)
 // (k = 0..p), conj(B_1).
 constexpr int kMpCoef = kMpCoefPerDisk;
-constexpr float kMpFar2 = 16.0f;   // (1 / kMpTheta)^2, kMpTheta = 1/4
+constexpr float kMpFar2 = 49.0f;   // (1 / kMpTheta)^2
 
 __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
     int P, int mobility, const int* __restrict__ cls, const int* __restrict__ src_off, ClassTab ct,
@@ -684,168 +684,15 @@ __global__ void k_reduce_splits(int64_t n2, int nsplit, const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Step 2a for R stacked strength vectors on the same sources and nodes (one thread per
-// target).  The geometry of each (target, source) pair is evaluated once and applied to
-// the R strengths: in the FP32 form w, log2(1 + w) and 1/(1 + w); in the FP64 form
-// ln r^2 and 1/r^2.  The per-pair arithmetic is otherwise that of k_ksum_mixed and
-// k_ksum_fp64, term for term.  src holds R packed arrays of Ns records, bdat R arrays
-// of P disk records; out is [split][R][Nt][2].  Disks must have at most KR_TILE sources.
+// Step 2a in FP64 for R stacked strength vectors on the same sources and nodes (one
+// thread per target).  The geometry of each (target, source) pair, ln r^2 and 1/r^2, is
+// evaluated once and applied to the R strengths; the per-pair arithmetic is otherwise
+// that of k_ksum_fp64, term for term.  src holds R packed arrays of Ns records; out is
+// [split][R][Nt][2].  Disks must have at most KR_TILE sources.  (The FP32 sum of stacked
+// vectors runs k_ksum_mixed once per vector: with far disks taken from their
+// expansions there is little per-pair geometry left to share.)
 constexpr int KR_TILE = 256;
 constexpr int KR_MAXB = 16;
-
-template <int R>
-__global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed_rhs(
-    int P, const int* __restrict__ src_off, const double* __restrict__ centers, const float4* __restrict__ src,
-    int64_t Ns, const float4* __restrict__ bdat, int64_t Nt, const int* __restrict__ tgt_body,
-    const double* __restrict__ X, int bodies_per_split, int mode, const int* __restrict__ nbr_off,
-    const int* __restrict__ nbr_list, double scale, double* __restrict__ out, const float2* __restrict__ mpm) {
-  __shared__ float2 s_y[KR_TILE];
-  __shared__ float2 s_s[KR_TILE * R];   // [q][r] strengths
-  __shared__ float s_w[KR_TILE * R];    // [q][r] y . sigma_r
-  __shared__ double s_c[2 * KR_MAXB];
-  __shared__ float4 s_b[KR_MAXB * R];   // [kk][r] (S0x, S0y, q, W)
-  __shared__ int s_off[KR_MAXB + 1];
-  __shared__ float2 s_mp[KR_MAXB * R * kMpCoef];   // [kk][r] far-field coefficients
-  const int split = blockIdx.y;
-  const int kb0 = split * bodies_per_split;
-  const int kb1 = min(P, kb0 + bodies_per_split);
-  const int64_t t = (int64_t)blockIdx.x * KS_THREADS + threadIdx.x;
-  const int64_t tc = t < Nt ? t : Nt - 1;
-  const int bt = tgt_body[tc];
-  const double x = X[2 * tc], y = X[2 * tc + 1];
-  double ax[R], ay[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) ax[r] = ay[r] = 0.0;
-  Skip sk;
-  skip_init(sk, mode, bt, kb0, nbr_off, nbr_list);
-  const float kHalfLn2 = 0.34657359027997264f;
-  for (int kt = kb0; kt < kb1;) {
-    const int s0 = src_off[kt];
-    int nb = 0;
-    while (kt + nb < kb1 && nb < KR_MAXB && src_off[kt + nb + 1] - s0 <= KR_TILE) ++nb;
-    const int ns = src_off[kt + nb] - s0;
-    __syncthreads();
-    for (int e = threadIdx.x; e < R * ns; e += KS_THREADS) {
-      const int r = e / ns, q = e - r * ns;
-      const float4 v = src[r * Ns + s0 + q];
-      if (r == 0) s_y[q] = make_float2(v.x, v.y);
-      s_s[q * R + r] = make_float2(v.z, v.w);
-      s_w[q * R + r] = fmaf(v.x, v.z, v.y * v.w);
-    }
-    for (int e = threadIdx.x; e < R * nb; e += KS_THREADS) {
-      const int kk = e / R, r = e - kk * R;
-      s_b[e] = bdat[(int64_t)r * P + kt + kk];
-    }
-    for (int q = threadIdx.x; q < nb; q += KS_THREADS) {
-      s_c[2 * q] = centers[2 * (kt + q)];
-      s_c[2 * q + 1] = centers[2 * (kt + q) + 1];
-    }
-    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
-    for (int e = threadIdx.x; e < nb * R * kMpCoef; e += KS_THREADS) {
-      const int kk = e / (R * kMpCoef), rem = e - kk * (R * kMpCoef);
-      const int r = rem / kMpCoef, q = rem - r * kMpCoef;
-      s_mp[e] = mpm[((int64_t)r * P + kt + kk) * kMpCoef + q];
-    }
-    __syncthreads();
-    for (int kk = 0; kk < nb; ++kk) {
-      const int kbody = kt + kk;
-      const float Dx = (float)(x - s_c[2 * kk]);
-      const float Dy = (float)(y - s_c[2 * kk + 1]);
-      const float R2 = fmaf(Dx, Dx, Dy * Dy);
-      const float ir2 = __builtin_amdgcn_rcpf(R2);
-      if (R2 > kMpFar2 * s_b[kk * R].z) {
-        // far disk: the expansion of each strength vector (k_ksum_mixed, k_gather_project)
-        const bool use = !skip_test(sk, mode, kbody, bt, nbr_list);
-        const float zr = Dx * ir2, zi = Dy * ir2;
-        const float f = fmaf(-s_b[kk * R].z, ir2, 1.0f);
-        const float lZ = fmaf(-kHalfLn2, __builtin_amdgcn_logf(R2), 0.5f);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float2* cf = s_mp + (kk * R + r) * kMpCoef;
-          float h1r = cf[kMpOrder - 1].x, h1i = cf[kMpOrder - 1].y;
-          float h2r = cf[2 * kMpOrder - 1].x, h2i = cf[2 * kMpOrder - 1].y;
-          float h3r = cf[3 * kMpOrder].x, h3i = cf[3 * kMpOrder].y;
-#pragma unroll
-          for (int k = kMpOrder - 1; k >= 1; --k) {
-            const float2 a = cf[k - 1], bq = cf[kMpOrder + k - 1], g = cf[2 * kMpOrder + k];
-            const float t1r = fmaf(zr, h1r, fmaf(zi, h1i, a.x)), t1i = fmaf(zr, h1i, fmaf(-zi, h1r, a.y));
-            const float t2r = fmaf(zr, h2r, fmaf(-zi, h2i, bq.x)), t2i = fmaf(zr, h2i, fmaf(zi, h2r, bq.y));
-            const float t3r = fmaf(zr, h3r, fmaf(-zi, h3i, g.x)), t3i = fmaf(zr, h3i, fmaf(zi, h3r, g.y));
-            h1r = t1r;
-            h1i = t1i;
-            h2r = t2r;
-            h2i = t2i;
-            h3r = t3r;
-            h3i = t3i;
-          }
-          const float2 g0 = cf[2 * kMpOrder], dl = cf[3 * kMpOrder + 1];
-          const float p3r = fmaf(zr, h3r, fmaf(-zi, h3i, g0.x)), p3i = fmaf(zr, h3i, fmaf(zi, h3r, g0.y));
-          const float p1r = fmaf(zr, h1r, zi * h1i), p1i = fmaf(zr, h1i, -zi * h1r);
-          const float p2r = fmaf(zr, h2r, -zi * h2i), p2i = fmaf(zr, h2i, zi * h2r);
-          const float mr = f * fmaf(Dx, p3r, -Dy * p3i) - dl.x;
-          const float mi = f * fmaf(Dx, p3i, Dy * p3r) - dl.y;
-          const float t3r = 0.5f * fmaf(zr, mr, -zi * mi);
-          const float t3i = 0.5f * fmaf(zr, mi, zi * mr);
-          const float4 bd = s_b[kk * R + r];
-          if (use) {
-            ax[r] += (double)fmaf(bd.x, lZ, p1r + p2r + t3r);
-            ay[r] += (double)fmaf(bd.y, lZ, p1i + p2i + t3i);
-          }
-        }
-        continue;
-      }
-      const float Dxs = -2.0f * Dx * ir2, Dys = -2.0f * Dy * ir2;
-      const float qs = s_b[kk * R].z * ir2;
-      // With a_s = d_s . sigma_s and t_s = a_s / u_s, the dyadic sum of k_ksum_mixed is
-      //   (D sum t - sum t y) R^-2 = (D (D.S0 - W) - sum_s t_s (D w_s + y_s)) R^-2,
-      // so one accumulator per component suffices: h = (D w + y) / u is shared by the R
-      // strength vectors and each of them costs 6 instructions per pair.
-      float lx[R], ly[R], hx[R], hy[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) lx[r] = ly[r] = hx[r] = hy[r] = 0.0f;
-      const int q1 = s_off[kk + 1];
-#pragma unroll 2
-      for (int q = s_off[kk]; q < q1; ++q) {
-        const float2 yq = s_y[q];
-        const float w = fmaf(Dxs, yq.x, fmaf(Dys, yq.y, qs));
-        const float u = 1.0f + w;
-        const float e = w - (u - 1.0f);
-        const float lg = fmaf(e, 1.44269504088896341f, __builtin_amdgcn_logf(u));
-        const float iu = __builtin_amdgcn_rcpf(u);
-        const float gx = iu * fmaf(Dx, w, yq.x), gy = iu * fmaf(Dy, w, yq.y);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float2 sg = s_s[q * R + r];
-          const float a = fmaf(Dx, sg.x, fmaf(Dy, sg.y, -s_w[q * R + r]));   // d . sigma, d = D - y
-          lx[r] = fmaf(lg, sg.x, lx[r]);
-          ly[r] = fmaf(lg, sg.y, ly[r]);
-          hx[r] = fmaf(a, gx, hx[r]);
-          hy[r] = fmaf(a, gy, hy[r]);
-        }
-      }
-      if (!skip_test(sk, mode, kbody, bt, nbr_list)) {
-        const float lR = __builtin_amdgcn_logf(R2);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float4 bd = s_b[kk * R + r];
-          const float M0 = fmaf(Dx, bd.x, fmaf(Dy, bd.y, -bd.w));   // D.S0 - W
-          const float tx = ir2 * fmaf(Dx, M0, -hx[r]);
-          const float ty = ir2 * fmaf(Dy, M0, -hy[r]);
-          ax[r] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.x, lx[r]), tx);
-          ay[r] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.y, ly[r]), ty);
-        }
-      }
-    }
-    kt += nb;
-  }
-  if (t < Nt) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      out[(((int64_t)split * R + r) * Nt + t) * 2] = ax[r] * scale;
-      out[(((int64_t)split * R + r) * Nt + t) * 2 + 1] = ay[r] * scale;
-    }
-  }
-}
 
 template <int R>
 __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64_rhs(
@@ -1499,10 +1346,20 @@ static int ksum_targets_per_thread(bool mixed) {
   return t == 1 || t == 2 || t == 4 ? t : 2;
 }
 
+static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
+                                     const float2* mp, double* u, double scale);
+
 // Stacked form of launch_kernel_sum: R strength vectors packed by launch_gather_project_to
 // into c->d_sig32m / c->d_bdatm (mixed) or c->d_src64m (FP64), R arrays each; u: R x 2 Nt.
 // false: out of memory for the split partials, or R unsupported.
 bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, double scale) {
+  if (mixed) {
+    for (int r = 0; r < R; ++r)
+      if (!launch_ksum_mixed_arrays(c, mode, c->d_sig32m + (int64_t)r * c->Ns, c->d_bdatm + (int64_t)r * c->P,
+                                    c->d_mpm + (int64_t)r * c->P * kMpCoef, u + (int64_t)r * 2 * c->Nt, scale))
+        return false;
+    return true;
+  }
   const int64_t Nt = c->Nt;
   const int64_t tblocks = (Nt + KS_THREADS - 1) / KS_THREADS;
   const int ns = ksum_splits(tblocks, c->P);
@@ -1524,21 +1381,16 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
     out = c->d_upart;
   }
   dim3 grid((unsigned)tblocks, (unsigned)ns);
-#define MFS_KR_MIXED(RR)                                                                                     \
-  hipLaunchKernelGGL(k_ksum_mixed_rhs<RR>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off,        \
-                     c->d_centers, c->d_sig32m, c->Ns, c->d_bdatm, Nt, c->d_tgt_body, c->d_X, bps, mode,    \
-                     c->d_nbr_off, c->d_nbr_list, scale, out, (const float2*)c->d_mpm)
 #define MFS_KR_FP64(RR)                                                                                    \
   hipLaunchKernelGGL(k_ksum_fp64_rhs<RR>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off,       \
                      c->d_src64m, c->Ns, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, \
                      scale, out)
   switch (R) {
-    case 2: if (mixed) MFS_KR_MIXED(2); else MFS_KR_FP64(2); break;
-    case 4: if (mixed) MFS_KR_MIXED(4); else MFS_KR_FP64(4); break;
-    case 8: if (mixed) MFS_KR_MIXED(8); else MFS_KR_FP64(8); break;
+    case 2: MFS_KR_FP64(2); break;
+    case 4: MFS_KR_FP64(4); break;
+    case 8: MFS_KR_FP64(8); break;
     default: return false;
   }
-#undef MFS_KR_MIXED
 #undef MFS_KR_FP64
   if (ns > 1)
     hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt * R, 256)), dim3(256), 0, c->stream, 2 * Nt * R, ns,
@@ -1546,7 +1398,45 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
   return true;
 }
 
+// One FP32 kernel sum on explicit packed arrays (sources, disk moments, expansion
+// coefficients); see launch_kernel_sum.
+static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
+                                     const float2* mp, double* u, double scale) {
+  const int T = ksum_targets_per_thread(true);
+  const int64_t Nt = c->Nt;
+  const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
+  const int ns = ksum_splits(tblocks, c->P);
+  const int bps = (c->P + ns - 1) / ns;
+  double* out = u;
+  if (ns > 1) {
+    const int64_t need = (int64_t)ns * Nt * 2;
+    if (c->upart_cap < need) {
+      if (c->d_upart) dev_free(c, c->d_upart);
+      c->d_upart = nullptr;
+      if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->d_upart = nullptr;
+        c->upart_cap = 0;
+        return false;
+      }
+      c->upart_cap = need;
+    }
+    out = c->d_upart;
+  }
+  dim3 grid((unsigned)tblocks, (unsigned)ns);
+#define MFS_KS_MIXED(TT)                                                                                         \
+  hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_centers, \
+                     sig32, bdat, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out, mp)
+  if (T == 4) MFS_KS_MIXED(4); else if (T == 1) MFS_KS_MIXED(1); else MFS_KS_MIXED(2);
+#undef MFS_KS_MIXED
+  if (ns > 1)
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns,
+                       c->d_upart, u);
+  return true;
+}
+
 bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale) {
+  if (mixed) return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, u, scale);
   const int T = ksum_targets_per_thread(mixed);
   const int64_t Nt = c->Nt;
   const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
@@ -1569,19 +1459,10 @@ bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale
     out = c->d_upart;
   }
   dim3 grid((unsigned)tblocks, (unsigned)ns);
-#define MFS_KS_MIXED(TT)                                                                                          \
-  hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_centers,   \
-                     c->d_sig32, c->d_bdat, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, \
-                     scale, out, (const float2*)c->d_mp)
 #define MFS_KS_FP64(TT)                                                                                       \
   hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_src64, Nt, \
                      c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out)
-  if (mixed) {
-    if (T == 4) MFS_KS_MIXED(4); else if (T == 1) MFS_KS_MIXED(1); else MFS_KS_MIXED(2);
-  } else {
-    if (T == 4) MFS_KS_FP64(4); else if (T == 1) MFS_KS_FP64(1); else MFS_KS_FP64(2);
-  }
-#undef MFS_KS_MIXED
+  if (T == 4) MFS_KS_FP64(4); else if (T == 1) MFS_KS_FP64(1); else MFS_KS_FP64(2);
 #undef MFS_KS_FP64
   if (ns > 1)
     hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns,
