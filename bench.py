@@ -45,15 +45,18 @@ FLOP_PER_PAIR = 20          # algorithmic flops of one Stokeslet evaluation appl
 # the log term and the combination (two of them transcendental)
 MP_ORDER = 8
 FLOP_PER_EXPANSION = 24 * (MP_ORDER - 1) + 66
+MP64_ORDER = 18             # the FP64 kernel sum's expansion order (same series and far test)
+FLOP_PER_EXPANSION64 = 24 * (MP64_ORDER - 1) + 66
 MP_FAR2 = 49.0              # a disk is far for a target beyond 7 ring radii
-KSUM_T = 2                  # targets per thread of the FP32 kernel sum (its default)
+KSUM_T = 2                  # targets per thread of both kernel sums (their default)
 
 
 def ksum_work(centers, radii, n_src, r_src, X, threads_T=KSUM_T, block=256):
-    """Work of one FP32 kernel-sum launch: direct pair evaluations and far-disk expansions.
+    """Work of one kernel-sum launch (FP32 or FP64: the same split): direct pair evaluations
+    and far-disk expansions.
 
     A thread holds T targets (block apart within a workgroup of block * T targets); a disk is
-    evaluated through its expansion when it is far from all of them (|x - c|^2 > 16 rho^2),
+    evaluated through its expansion when it is far from all of them (|x - c|^2 > 49 rho^2),
     else directly over its sources for all of them (skipped disks included: their terms are
     computed and not accumulated).  The last workgroup's missing targets are not counted."""
     import numpy as np
@@ -97,7 +100,7 @@ def ksum_traffic_bytes():
     body = src[i:src.index("\n}\n", i) + 3]
     # the expansion's order and radius live outside the kernel's text
     hdr = open(os.path.join(ROOT, "paper_2606_11273_amd", "csrc", "internal.h")).read()
-    body += "".join(l for l in (hdr + src).splitlines(True) if "constexpr" in l and "kMp" in l)
+    body += "".join(l for l in (hdr + src).splitlines(True) if "constexpr" in l and "kMp" in l and "kMp64" not in l)
     if hashlib.sha256(body.encode()).hexdigest()[:16] != KSUM_TRAFFIC["src_sha256_16"]:
         return None
     t = KSUM_TRAFFIC
@@ -295,7 +298,8 @@ def main():
     # each disk's own sources and its contact partners).  pair_evals_per_launch counts the
     # Stokeslet pairs of the direct sum the launch stands for; the FP32 kernel evaluates far
     # disks through their expansions, so its algorithmic flops are the direct pairs it does
-    # compute (near disks) times 20 plus its expansion evaluations times FLOP_PER_EXPANSION
+    # compute (near disks) times 20 plus its expansion evaluations times FLOP_PER_EXPANSION;
+    # the FP64 kernel splits near and far disks the same way, with order-18 expansions
     pr = nv.mfs_get_pairs(ctx)
     skipped = ns.astype(np.int64).copy()
     np.add.at(skipped, pr[:, 0], ns[pr[:, 1]])
@@ -317,7 +321,8 @@ def main():
                     pair_evals_per_launch=evals_launch,
                     pair_evals_per_s=round(evals_launch / (ks["mixed"] * 1e-3), 1),
                     fp64_kernel_ms_per_launch=round(ks["fp64"], 2),
-                    fp64_kernel_tflops=round(evals_launch * FLOP_PER_PAIR / (ks["fp64"] * 1e-3) / 1e12, 2),
+                    fp64_kernel_tflops=round((near_pairs * FLOP_PER_PAIR + expansions * FLOP_PER_EXPANSION64)
+                                             / (ks["fp64"] * 1e-3) / 1e12, 2),
                     fp64_peak=PEAK_FP64_TFLOPS)
 
     # stacked matvec: one T mu on args.rhs vectors at once, per vector (HIP events)

@@ -170,7 +170,11 @@ mfs_status mfs_apply(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t
  * of the disk's contact partners (the form step 2a of mfs_apply uses, with the
  * skipped blocks applied in FP64 by the pair step).  sigma: device,
  * 2 * sum(n_src); u: device, 2 * sum(n_col).  This is the kernel of step 2a,
- * exposed for tests and measurement. */
+ * exposed for tests and measurement.  A disk whose centre lies beyond 7 ring radii
+ * of the targets is summed through a multipole expansion of its FP64 moments
+ * (order 8 for MFS_MIXED, 18 for MFS_FP64: truncation below 3e-8 and 1e-16 of
+ * sum |sigma| / (4 pi mu), under each precision's rounding; the paper uses a fast
+ * multipole method for this sum, Sec. 6). */
 mfs_status mfs_kernel_sum(mfs_ctx* ctx, mfs_precision prec, const double* sigma, double* u,
                           int32_t skip);
 

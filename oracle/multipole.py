@@ -54,3 +54,42 @@ def far_field(Z, A, B, rho, mu=1.0):
     P = sum(np.conj(A[k]) * zb ** k for k in range(p + 1))
     u = u + zb / 2 * ((Z - rho * rho * zb) * P - np.conj(B[1]))
     return u / (4 * np.pi * mu)
+
+
+def cluster_moments(w, sigma, p):
+    """Moments of sources at arbitrary offsets w (n,) from an expansion centre (a cluster of
+    disks): A_k = sum sigma w^k, B_k = sum sigma conj(w)^k and D_k = sum sigma conj(w) w^k,
+    k = 0..p."""
+    w = np.asarray(w, dtype=np.complex128)
+    sigma = np.asarray(sigma, dtype=np.complex128)
+    A, B = moments(w, sigma, p)
+    k = np.arange(p + 1)
+    D = (sigma[None, :] * np.conj(w)[None, :] * w[None, :] ** k[:, None]).sum(axis=1)
+    return A, B, D
+
+
+def far_field_general(Z, A, B, D, mu=1.0):
+    """Velocity (complex) at offsets Z from the centre of sources that need not lie on a ring,
+    from cluster_moments, truncated after order p = len(A) - 1.
+
+    The third term of the Stokeslet sums conj(sigma) (Z - w) / (conj(Z) - conj(w)); with
+    1/(conj(Z) - conj(w)) = conj(zeta) sum_k (conj(w zeta))^k it is
+    conj(zeta) [Z sum_k conj(A_k) conj(zeta)^k - sum_k conj(D_k) conj(zeta)^k], so
+
+      4 pi mu u = -S0 log|Z| + S0/2 + sum_{k>=1} (A_k zeta^k + B_k conj(zeta)^k) / (2k)
+                  + conj(zeta)/2 [Z P - Q],  P = sum conj(A_k) conj(zeta)^k,
+                                             Q = sum conj(D_k) conj(zeta)^k.
+
+    On a ring |w| = rho, D_k = rho^2 A_{k-1} (k >= 1) and D_0 = B_1, which gives far_field.
+    Truncation: below about sum |sigma| theta^(p+1) / (1 - theta), theta = max|w| / |Z|."""
+    Z = np.asarray(Z, dtype=np.complex128)
+    p = len(A) - 1
+    zeta = 1.0 / Z
+    zb = np.conj(zeta)
+    u = -A[0] * np.log(np.abs(Z)) + A[0] / 2
+    for k in range(1, p + 1):
+        u = u + (A[k] * zeta ** k + B[k] * zb ** k) / (2 * k)
+    P = sum(np.conj(A[k]) * zb ** k for k in range(p + 1))
+    Q = sum(np.conj(D[k]) * zb ** k for k in range(p + 1))
+    u = u + zb / 2 * (Z * P - Q)
+    return u / (4 * np.pi * mu)

@@ -82,7 +82,7 @@ void free_all(mfs_ctx* c) {
                   c->ps[1].E,   c->kr.V,      c->kr.w,    c->kr.part,    c->kr.hdev,  c->kr.x,     c->kr.r,
                   c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
                   c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf, c->d_mp,
-                  c->d_mpm};
+                  c->d_mpm,     c->d_mp64,    c->d_mp64m,   c->d_fmp64};
   for (void* p : ptrs)
     if (p) dev_free(c, p);
   for (const PairSet& ps : c->ps)
@@ -229,6 +229,7 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   if ((st = dalloc(c, &c->d_bdat, (size_t)P)).code) return st;
   if ((st = dalloc(c, &c->d_mp, (size_t)P * kMpCoefPerDisk)).code) return st;
   if ((st = dalloc(c, &c->d_src64, c->Ns)).code) return st;
+  if ((st = dalloc(c, &c->d_mp64, (size_t)P * kMp64CoefPerDisk)).code) return st;
   MFS_HIP(hipStreamSynchronize(s));
   return Status{};
 }
@@ -263,11 +264,12 @@ Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u) {
 Status ensure_stacked(mfs_ctx* c, int R) {
   if (c->rhs_cap >= R) return Status{};
   for (void* p : {(void*)c->d_lam_bar_m, (void*)c->d_ltil_m, (void*)c->d_u_m, (void*)c->d_corr_m,
-                  (void*)c->d_sig32m, (void*)c->d_bdatm, (void*)c->d_src64m, (void*)c->d_mpm})
+                  (void*)c->d_sig32m, (void*)c->d_bdatm, (void*)c->d_src64m, (void*)c->d_mpm, (void*)c->d_mp64m})
     if (p) dev_free(c, p);
   c->d_lam_bar_m = c->d_ltil_m = c->d_u_m = c->d_corr_m = nullptr;
   c->d_sig32m = c->d_bdatm = nullptr;
   c->d_mpm = nullptr;
+  c->d_mp64m = nullptr;
   c->d_src64m = nullptr;
   c->rhs_cap = 0;
   const int C = (int)(c->pairs.size() / 2);
@@ -280,6 +282,7 @@ Status ensure_stacked(mfs_ctx* c, int R) {
   if ((st = dalloc(c, &c->d_bdatm, (size_t)R * c->P)).code) return st;
   if ((st = dalloc(c, &c->d_mpm, (size_t)R * c->P * kMpCoefPerDisk)).code) return st;
   if ((st = dalloc(c, &c->d_src64m, (size_t)R * c->Ns)).code) return st;
+  if ((st = dalloc(c, &c->d_mp64m, (size_t)R * c->P * kMp64CoefPerDisk)).code) return st;
   c->rhs_cap = R;
   return Status{};
 }
@@ -312,6 +315,9 @@ Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, do
                                mixed ? c->d_sig32m + r * c->Ns : nullptr, mixed ? nullptr : c->d_src64m + r * c->Ns,
                                mixed ? c->d_bdatm + (int64_t)r * c->P : nullptr,
                                mixed ? c->d_mpm + (int64_t)r * c->P * kMpCoefPerDisk : nullptr);
+    if (!mixed)
+      for (int r = 0; r < Rc; ++r)
+        launch_moments64(c, c->d_src64m + r * c->Ns, c->d_mp64m + (int64_t)r * c->P * kMp64CoefPerDisk);
     const bool ks = launch_kernel_sum_rhs(c, mixed, 2, Rc, c->d_u_m, 1.0 / (4.0 * kPiD * c->prm.mu));
     if ((st = check_kernel_sum(c, ks)).code) return st;
     c->cnt_pair_evals += (int64_t)Rc * c->evals_skip;

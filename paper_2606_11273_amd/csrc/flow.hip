@@ -72,6 +72,8 @@ Status flow_eval(mfs_ctx* c, int prob, const double* mu, const double* given, in
   Status st;
   int64_t fsrc_cap = c->d_fsrc ? c->Ns : 0;
   if ((st = grow(c, &c->d_fsrc, &fsrc_cap, c->Ns)).code) return st;
+  int64_t fmp_cap = c->d_fmp64 ? (int64_t)c->P * kMp64CoefPerDisk : 0;
+  if ((st = grow(c, &c->d_fmp64, &fmp_cap, (int64_t)c->P * kMp64CoefPerDisk)).code) return st;
   if (C > 0) {
     int64_t ptil_cap = c->d_ptil ? c->xoff[C] : 0;
     if ((st = grow(c, &c->d_ptil, &ptil_cap, c->xoff[C])).code) return st;
@@ -85,7 +87,8 @@ Status flow_eval(mfs_ctx* c, int prob, const double* mu, const double* given, in
     MFS_HIP(hipMemcpyAsync(c->d_given, given, sizeof(double) * 3 * c->P, hipMemcpyHostToDevice, c->stream));
     launch_add_rhs_sources(c, c->d_given, c->d_fsrc);
   }
-  if (!launch_kernel_sum_points(c, c->d_fsrc, n_pts, pts, body, u))
+  launch_moments64(c, c->d_fsrc, c->d_fmp64);
+  if (!launch_kernel_sum_points(c, c->d_fsrc, c->d_fmp64, n_pts, pts, body, u))
     return Status{MFS_ERR_OOM, "device allocation of the kernel-sum partials failed"};
   if (C > 0) {
     launch_fine_strengths(c, prob, c->d_lam_bar, c->d_ltil, c->d_ptil, c->d_sigf);

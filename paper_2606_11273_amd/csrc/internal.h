@@ -17,6 +17,8 @@ constexpr int kMaxClasses = 4;     // distinct (radius, n_src, n_col, r_src) dis
 constexpr int kMaxCol = 512;       // n_col limit per disk
 constexpr int kMpOrder = 8;        // order of the per-disk far-field expansion of the FP32 kernel sum
 constexpr int kMpCoefPerDisk = 3 * kMpOrder + 2;   // its FP32 complex coefficients per disk
+constexpr int kMp64Order = 18;     // order of the FP64 kernel sum's far-field expansion
+constexpr int kMp64CoefPerDisk = 3 * kMp64Order + 3;   // FP64 complex coefficients per disk (last: rho^2)
 constexpr double kPiD = 3.14159265358979323846;
 
 struct Status {
@@ -112,6 +114,7 @@ struct mfs_ctx {
   float4* d_sig32 = nullptr;     // per source: (yr_x, yr_y, sigma_x, sigma_y)
   float4* d_bdat = nullptr;      // per disk: (net strength x, y, ring radius^2, W) for the FP32 sum
   float2* d_mp = nullptr;        // per disk: far-field expansion coefficients for the FP32 sum
+  double2* d_mp64 = nullptr;     // per disk: far-field expansion coefficients of d_src64 for the FP64 sum
   double4* d_src64 = nullptr;    // per source: (y_x, y_y, sigma_x, sigma_y)
   int64_t upart_cap = 0;
 
@@ -121,6 +124,7 @@ struct mfs_ctx {
   float4* d_sig32m = nullptr;    // rhs_cap arrays of Ns records
   float4* d_bdatm = nullptr;     // rhs_cap arrays of P records
   float2* d_mpm = nullptr;       // rhs_cap arrays of P far-field coefficient records
+  double2* d_mp64m = nullptr;    // rhs_cap arrays of P FP64 far-field coefficient records
   double4* d_src64m = nullptr;   // rhs_cap arrays of Ns records
 
   mfs::PairSet ps[2];
@@ -132,6 +136,7 @@ struct mfs_ctx {
   int mu_count = 0, mu_prob = -1;
   double4* d_fsrc = nullptr;           // Ns records: sources with the total strengths
   double *d_ptil = nullptr, *d_sigf = nullptr;   // projected lambda_tilde (xoff[C]); fine strengths (max yoff)
+  double2* d_fmp64 = nullptr;          // far-field coefficients of d_fsrc
   int64_t sigf_cap = 0;
 
   // work counters (host side, reset by mfs_gmres_solve)
@@ -172,8 +177,10 @@ void launch_rhs_resistance(mfs_ctx* c, const double* given, double* b);
 void launch_post(mfs_ctx* c, int prob, const double* lam_bar, double* out3);
 // flow evaluation (kernels.hip)
 void launch_add_rhs_sources(mfs_ctx* c, const double* given, double4* src64);
-bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, int64_t n_pts, const double* pts,
-                              const int32_t* body, double* u);
+bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, const double2* mp64, int64_t n_pts,
+                              const double* pts, const int32_t* body, double* u);
+// FP64 far-field coefficients (kMp64CoefPerDisk per disk) of a packed FP64 source array
+void launch_moments64(mfs_ctx* c, const double4* src64, double2* mp64);
 void launch_fine_strengths(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, double* ptil,
                            double* sigf);
 void launch_flow_near(mfs_ctx* c, int prob, int64_t n_pts, const double* pts, const int32_t* body,

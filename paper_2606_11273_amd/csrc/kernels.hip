@@ -597,6 +597,81 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
   }
 }
 
+// FP64 far-field coefficients of a packed FP64 source array (the expansion of
+// k_gather_project to order kMp64Order): per disk A_k/(2k) (k = 1..p), B_k/(2k) (k = 1..p),
+// conj(A_k) (k = 0..p), conj(B_1) and (rho^2, 0).  The offsets w are the class ring Yr
+// (the packed positions are c + Yr); the strengths are the packed ones.  Truncation of the
+// FP64 sum's expansion beyond kMp64Far2: below sum |sigma| (1/7)^19 / (6/7) = 1e-16 sum |sigma|.
+constexpr int kMp64Coef = kMp64CoefPerDisk;
+constexpr double kMp64Far2 = 49.0;
+
+__global__ __launch_bounds__(kBodyThreads) void k_moments64(int P, const int* __restrict__ cls,
+                                                            const int* __restrict__ src_off, ClassTab ct,
+                                                            const double4* __restrict__ src,
+                                                            double2* __restrict__ mp64) {
+  const int b = blockIdx.x;
+  if (b >= P) return;
+  const int k = cls[b];
+  const double* Yr = ct.Yr[k];
+  const int nc = ct.nc[k];
+  const int64_t so = src_off[b];
+  double ar[kMp64Order], ai[kMp64Order], br[kMp64Order], bi[kMp64Order];
+#pragma unroll
+  for (int m = 0; m < kMp64Order; ++m) ar[m] = ai[m] = br[m] = bi[m] = 0.0;
+  double s0r = 0.0, s0i = 0.0;
+  for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
+    const double4 v = src[so + j];
+    const double wx = Yr[2 * j], wy = Yr[2 * j + 1];
+    s0r += v.z;
+    s0i += v.w;
+    double pr = v.z, pi = v.w, qr = v.z, qi = v.w;   // sigma w^m and sigma conj(w)^m
+#pragma unroll
+    for (int m = 0; m < kMp64Order; ++m) {
+      const double tr = pr * wx - pi * wy, ti = pr * wy + pi * wx;
+      const double ur = qr * wx + qi * wy, ui = qi * wx - qr * wy;
+      pr = tr;
+      pi = ti;
+      qr = ur;
+      qi = ui;
+      ar[m] += pr;
+      ai[m] += pi;
+      br[m] += qr;
+      bi[m] += qi;
+    }
+  }
+  __shared__ double mred[2][4 * kMp64Order + 2];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  auto put = [&](int slot, double v) {
+    v = wave_sum(v);
+    if (lane == 0) mred[wid][slot] = v;
+  };
+#pragma unroll
+  for (int m = 0; m < kMp64Order; ++m) {
+    put(4 * m, ar[m]);
+    put(4 * m + 1, ai[m]);
+    put(4 * m + 2, br[m]);
+    put(4 * m + 3, bi[m]);
+  }
+  put(4 * kMp64Order, s0r);
+  put(4 * kMp64Order + 1, s0i);
+  __syncthreads();
+  static_assert(kBodyThreads == 128, "two waves per body block");
+  for (int e = threadIdx.x; e < 4 * kMp64Order + 2; e += kBodyThreads) mred[0][e] += mred[1][e];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2* o = mp64 + (int64_t)b * kMp64Coef;
+    for (int m = 1; m <= kMp64Order; ++m) {
+      const double* r = &mred[0][4 * (m - 1)];
+      o[m - 1] = make_double2(r[0] / (2 * m), r[1] / (2 * m));
+      o[kMp64Order + m - 1] = make_double2(r[2] / (2 * m), r[3] / (2 * m));
+      o[2 * kMp64Order + m] = make_double2(r[0], -r[1]);
+    }
+    o[2 * kMp64Order] = make_double2(mred[0][4 * kMp64Order], -mred[0][4 * kMp64Order + 1]);
+    o[3 * kMp64Order + 1] = make_double2(mred[0][2], -mred[0][3]);
+    o[3 * kMp64Order + 2] = make_double2(Yr[0] * Yr[0] + Yr[1] * Yr[1], 0.0);
+  }
+}
+
 // FP64 form of the same sum, absolute coordinates (ln_f64, rcp_f64 above).
 template <int T>
 __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __restrict__ src_off,
@@ -605,7 +680,9 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
                                                           const double* __restrict__ X, int bodies_per_split,
                                                           int mode, const int* __restrict__ nbr_off,
                                                           const int* __restrict__ nbr_list, double scale,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ out,
+                                                          const double* __restrict__ centers,
+                                                          const double2* __restrict__ mp64) {
   __shared__ double4 s_src[KS_TILE / 2];
   __shared__ int s_off[KS_MAXB + 1];
   const int split = blockIdx.y;
@@ -637,6 +714,77 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
     __syncthreads();
     for (int kk = 0; kk < nb; ++kk) {
       const int kbody = kt + kk;
+      if (mp64) {
+        // far disk for every target of this thread: its FP64 expansion (k_moments64; the
+        // same series as the FP32 sum, to order kMp64Order)
+        const double2* cf = mp64 + (int64_t)kbody * kMp64Coef;
+        const double q = cf[3 * kMp64Order + 2].x;
+        const double cx = centers[2 * kbody], cy = centers[2 * kbody + 1];
+        double Zx[T], Zy[T], R2[T];
+        bool far = true;
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          Zx[j] = x[j] - cx;
+          Zy[j] = y[j] - cy;
+          R2[j] = fma(Zx[j], Zx[j], Zy[j] * Zy[j]);
+          far = far && R2[j] > kMp64Far2 * q;
+        }
+        if (far) {
+          double zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T];
+#pragma unroll
+          for (int j = 0; j < T; ++j) {
+            const double ir2 = rcp_f64(R2[j]);
+            zr[j] = Zx[j] * ir2;
+            zi[j] = Zy[j] * ir2;
+            h1r[j] = cf[kMp64Order - 1].x;
+            h1i[j] = cf[kMp64Order - 1].y;
+            h2r[j] = cf[2 * kMp64Order - 1].x;
+            h2i[j] = cf[2 * kMp64Order - 1].y;
+            h3r[j] = cf[3 * kMp64Order].x;
+            h3i[j] = cf[3 * kMp64Order].y;
+          }
+#pragma unroll 2
+          for (int m = kMp64Order - 1; m >= 1; --m) {   // coefficients loaded per step (uniform)
+            const double2 a = cf[m - 1], bq = cf[kMp64Order + m - 1], g = cf[2 * kMp64Order + m];
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+              const double t1r = fma(zr[j], h1r[j], fma(zi[j], h1i[j], a.x));
+              const double t1i = fma(zr[j], h1i[j], fma(-zi[j], h1r[j], a.y));
+              const double t2r = fma(zr[j], h2r[j], fma(-zi[j], h2i[j], bq.x));
+              const double t2i = fma(zr[j], h2i[j], fma(zi[j], h2r[j], bq.y));
+              const double t3r = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g.x));
+              const double t3i = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g.y));
+              h1r[j] = t1r;
+              h1i[j] = t1i;
+              h2r[j] = t2r;
+              h2i[j] = t2i;
+              h3r[j] = t3r;
+              h3i[j] = t3i;
+            }
+          }
+          const double2 g0 = cf[2 * kMp64Order], dl = cf[3 * kMp64Order + 1];
+#pragma unroll
+          for (int j = 0; j < T; ++j) {
+            const double p3r = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g0.x));
+            const double p3i = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g0.y));
+            const double p1r = fma(zr[j], h1r[j], zi[j] * h1i[j]);
+            const double p1i = fma(zr[j], h1i[j], -zi[j] * h1r[j]);
+            const double p2r = fma(zr[j], h2r[j], -zi[j] * h2i[j]);
+            const double p2i = fma(zr[j], h2i[j], zi[j] * h2r[j]);
+            const double f = fma(-q, zr[j] * zr[j] + zi[j] * zi[j], 1.0);
+            const double mr = f * fma(Zx[j], p3r, -Zy[j] * p3i) - dl.x;
+            const double mi = f * fma(Zx[j], p3i, Zy[j] * p3r) - dl.y;
+            const double t3r = 0.5 * fma(zr[j], mr, -zi[j] * mi);
+            const double t3i = 0.5 * fma(zr[j], mi, zi[j] * mr);
+            const double lZ = fma(-0.5, ln_f64(R2[j]), 0.5);   // -ln|Z| + 1/2
+            if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
+              ax[j] += fma(g0.x, lZ, p1r + p2r + t3r);          // S0 = conj(g0)
+              ay[j] += fma(-g0.y, lZ, p1i + p2i + t3i);
+            }
+          }
+          continue;
+        }
+      }
       double lx[T], ly[T], tx[T], ty[T];
 #pragma unroll
       for (int j = 0; j < T; ++j) lx[j] = ly[j] = tx[j] = ty[j] = 0.0;
@@ -683,92 +831,7 @@ __global__ void k_reduce_splits(int64_t n2, int nsplit, const double* __restrict
   u[i] = s;
 }
 
-// ---------------------------------------------------------------------------
-// Step 2a in FP64 for R stacked strength vectors on the same sources and nodes (one
-// thread per target).  The geometry of each (target, source) pair, ln r^2 and 1/r^2, is
-// evaluated once and applied to the R strengths; the per-pair arithmetic is otherwise
-// that of k_ksum_fp64, term for term.  src holds R packed arrays of Ns records; out is
-// [split][R][Nt][2].  Disks must have at most KR_TILE sources.  (The FP32 sum of stacked
-// vectors runs k_ksum_mixed once per vector: with far disks taken from their
-// expansions there is little per-pair geometry left to share.)
-constexpr int KR_TILE = 256;
-constexpr int KR_MAXB = 16;
 
-template <int R>
-__global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64_rhs(
-    int P, const int* __restrict__ src_off, const double4* __restrict__ src, int64_t Ns, int64_t Nt,
-    const int* __restrict__ tgt_body, const double* __restrict__ X, int bodies_per_split, int mode,
-    const int* __restrict__ nbr_off, const int* __restrict__ nbr_list, double scale, double* __restrict__ out) {
-  __shared__ double2 s_y[KR_TILE];
-  __shared__ double2 s_s[KR_TILE * R];
-  __shared__ int s_off[KR_MAXB + 1];
-  const int split = blockIdx.y;
-  const int kb0 = split * bodies_per_split;
-  const int kb1 = min(P, kb0 + bodies_per_split);
-  const int64_t t = (int64_t)blockIdx.x * KS_THREADS + threadIdx.x;
-  const int64_t tc = t < Nt ? t : Nt - 1;
-  const int bt = tgt_body[tc];
-  const double x = X[2 * tc], y = X[2 * tc + 1];
-  double ax[R], ay[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) ax[r] = ay[r] = 0.0;
-  Skip sk;
-  skip_init(sk, mode, bt, kb0, nbr_off, nbr_list);
-  for (int kt = kb0; kt < kb1;) {
-    const int s0 = src_off[kt];
-    int nb = 0;
-    while (kt + nb < kb1 && nb < KR_MAXB && src_off[kt + nb + 1] - s0 <= KR_TILE) ++nb;
-    const int ns = src_off[kt + nb] - s0;
-    __syncthreads();
-    for (int e = threadIdx.x; e < R * ns; e += KS_THREADS) {
-      const int r = e / ns, q = e - r * ns;
-      const double4 v = src[r * Ns + s0 + q];
-      if (r == 0) s_y[q] = make_double2(v.x, v.y);
-      s_s[q * R + r] = make_double2(v.z, v.w);
-    }
-    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
-    __syncthreads();
-    for (int kk = 0; kk < nb; ++kk) {
-      const int kbody = kt + kk;
-      double lx[R], ly[R], tx[R], ty[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) lx[r] = ly[r] = tx[r] = ty[r] = 0.0;
-      const int q1 = s_off[kk + 1];
-      for (int q = s_off[kk]; q < q1; ++q) {
-        const double2 yq = s_y[q];
-        const double dx = x - yq.x;
-        const double dy = y - yq.y;
-        const double r2 = fma(dx, dx, dy * dy);
-        const double lg = ln_f64(r2);
-        const double ir = rcp_f64(r2);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double2 sg = s_s[q * R + r];
-          const double dot = fma(dx, sg.x, dy * sg.y) * ir;
-          lx[r] = fma(lg, sg.x, lx[r]);
-          ly[r] = fma(lg, sg.y, ly[r]);
-          tx[r] = fma(dot, dx, tx[r]);
-          ty[r] = fma(dot, dy, ty[r]);
-        }
-      }
-      if (!skip_test(sk, mode, kbody, bt, nbr_list)) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          ax[r] += fma(-0.5, lx[r], tx[r]);
-          ay[r] += fma(-0.5, ly[r], ty[r]);
-        }
-      }
-    }
-    kt += nb;
-  }
-  if (t < Nt) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      out[(((int64_t)split * R + r) * Nt + t) * 2] = ax[r] * scale;
-      out[(((int64_t)split * R + r) * Nt + t) * 2 + 1] = ay[r] * scale;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Step 2b, per pair, in source form.  The kernel sum skipped each disk's own
@@ -1299,6 +1362,7 @@ void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const do
                            bool pack32, bool pack64) {
   launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, pack32 ? c->d_sig32 : nullptr,
                            pack64 ? c->d_src64 : nullptr, pack32 ? c->d_bdat : nullptr, pack32 ? c->d_mp : nullptr);
+  if (pack64) launch_moments64(c, c->d_src64, c->d_mp64);
 }
 
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
@@ -1348,53 +1412,23 @@ static int ksum_targets_per_thread(bool mixed) {
 
 static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
                                      const float2* mp, double* u, double scale);
+static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, const double2* mp64, int64_t Nt,
+                                    const double* X, const int32_t* tgt_body, double* u, double scale);
 
 // Stacked form of launch_kernel_sum: R strength vectors packed by launch_gather_project_to
 // into c->d_sig32m / c->d_bdatm (mixed) or c->d_src64m (FP64), R arrays each; u: R x 2 Nt.
 // false: out of memory for the split partials, or R unsupported.
 bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, double scale) {
-  if (mixed) {
-    for (int r = 0; r < R; ++r)
-      if (!launch_ksum_mixed_arrays(c, mode, c->d_sig32m + (int64_t)r * c->Ns, c->d_bdatm + (int64_t)r * c->P,
-                                    c->d_mpm + (int64_t)r * c->P * kMpCoef, u + (int64_t)r * 2 * c->Nt, scale))
-        return false;
-    return true;
+  for (int r = 0; r < R; ++r) {
+    double* ur = u + (int64_t)r * 2 * c->Nt;
+    const bool ok =
+        mixed ? launch_ksum_mixed_arrays(c, mode, c->d_sig32m + (int64_t)r * c->Ns, c->d_bdatm + (int64_t)r * c->P,
+                                         c->d_mpm + (int64_t)r * c->P * kMpCoef, ur, scale)
+              : launch_ksum_fp64_arrays(c, mode, c->d_src64m + (int64_t)r * c->Ns,
+                                        c->d_mp64m + (int64_t)r * c->P * kMp64Coef, c->Nt, c->d_X, c->d_tgt_body,
+                                        ur, scale);
+    if (!ok) return false;
   }
-  const int64_t Nt = c->Nt;
-  const int64_t tblocks = (Nt + KS_THREADS - 1) / KS_THREADS;
-  const int ns = ksum_splits(tblocks, c->P);
-  const int bps = (c->P + ns - 1) / ns;
-  double* out = u;
-  if (ns > 1) {
-    const int64_t need = (int64_t)ns * R * Nt * 2;
-    if (c->upart_cap < need) {
-      if (c->d_upart) dev_free(c, c->d_upart);
-      c->d_upart = nullptr;
-      if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        c->d_upart = nullptr;
-        c->upart_cap = 0;
-        return false;
-      }
-      c->upart_cap = need;
-    }
-    out = c->d_upart;
-  }
-  dim3 grid((unsigned)tblocks, (unsigned)ns);
-#define MFS_KR_FP64(RR)                                                                                    \
-  hipLaunchKernelGGL(k_ksum_fp64_rhs<RR>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off,       \
-                     c->d_src64m, c->Ns, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, \
-                     scale, out)
-  switch (R) {
-    case 2: MFS_KR_FP64(2); break;
-    case 4: MFS_KR_FP64(4); break;
-    case 8: MFS_KR_FP64(8); break;
-    default: return false;
-  }
-#undef MFS_KR_FP64
-  if (ns > 1)
-    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt * R, 256)), dim3(256), 0, c->stream, 2 * Nt * R, ns,
-                       c->d_upart, u);
   return true;
 }
 
@@ -1435,10 +1469,12 @@ static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, 
   return true;
 }
 
-bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale) {
-  if (mixed) return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, u, scale);
-  const int T = ksum_targets_per_thread(mixed);
-  const int64_t Nt = c->Nt;
+// FP64 kernel sum of a packed source array at Nt points X (mode as in k_ksum_fp64); mp64: the
+// far-field coefficients of src (k_moments64), or NULL for the direct sum over every disk.
+static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, const double2* mp64, int64_t Nt,
+                                    const double* X, const int32_t* tgt_body, double* u, double scale) {
+  if (Nt == 0) return true;
+  const int T = ksum_targets_per_thread(false);
   const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
   const int ns = ksum_splits(tblocks, c->P);
   const int bps = (c->P + ns - 1) / ns;
@@ -1459,15 +1495,20 @@ bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale
     out = c->d_upart;
   }
   dim3 grid((unsigned)tblocks, (unsigned)ns);
-#define MFS_KS_FP64(TT)                                                                                       \
-  hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_src64, Nt, \
-                     c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out)
+#define MFS_KS_FP64(TT)                                                                                     \
+  hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, src, Nt,    \
+                     tgt_body, X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out, c->d_centers, mp64)
   if (T == 4) MFS_KS_FP64(4); else if (T == 1) MFS_KS_FP64(1); else MFS_KS_FP64(2);
 #undef MFS_KS_FP64
   if (ns > 1)
     hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns,
                        c->d_upart, u);
   return true;
+}
+
+bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale) {
+  if (mixed) return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, u, scale);
+  return launch_ksum_fp64_arrays(c, mode, c->d_src64, c->d_mp64, c->Nt, c->d_X, c->d_tgt_body, u, scale);
 }
 
 void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr) {
@@ -1488,6 +1529,7 @@ void launch_finish(mfs_ctx* c, const double* u_sum, const double* mu, const doub
 void launch_rhs_mobility_sources(mfs_ctx* c, const double* given) {
   hipLaunchKernelGGL(k_rhs_sources, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
                      c->ct[MFS_MOBILITY], c->d_centers, given, c->d_src64, 0);
+  launch_moments64(c, c->d_src64, c->d_mp64);
 }
 
 void launch_add_rhs_sources(mfs_ctx* c, const double* given, double4* src64) {
@@ -1541,40 +1583,14 @@ void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b,
 // ---------------------------------------------------------------------------
 // flow evaluation launchers
 
-bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, int64_t n_pts, const double* pts,
-                              const int32_t* body, double* u) {
-  if (n_pts == 0) return true;
-  const int T = ksum_targets_per_thread(false);
-  const int64_t tblocks = (n_pts + KS_THREADS * T - 1) / (KS_THREADS * T);
-  const int ns = ksum_splits(tblocks, c->P);
-  const int bps = (c->P + ns - 1) / ns;
-  double* out = u;
-  if (ns > 1) {
-    const int64_t need = (int64_t)ns * n_pts * 2;
-    if (c->upart_cap < need) {
-      if (c->d_upart) dev_free(c, c->d_upart);
-      c->d_upart = nullptr;
-      if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        c->d_upart = nullptr;
-        c->upart_cap = 0;
-        return false;
-      }
-      c->upart_cap = need;
-    }
-    out = c->d_upart;
-  }
-  const double scale = 1.0 / (4.0 * kPiD * c->prm.mu);
-  dim3 grid((unsigned)tblocks, (unsigned)ns);
-#define MFS_KP(TT)                                                                                          \
-  hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, src, n_pts, \
-                     body, pts, bps, 0, c->d_nbr_off, c->d_nbr_list, scale, out)
-  if (T == 4) MFS_KP(4); else if (T == 1) MFS_KP(1); else MFS_KP(2);
-#undef MFS_KP
-  if (ns > 1)
-    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * n_pts, 256)), dim3(256), 0, c->stream, 2 * n_pts, ns,
-                       c->d_upart, u);
-  return true;
+bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, const double2* mp64, int64_t n_pts,
+                              const double* pts, const int32_t* body, double* u) {
+  return launch_ksum_fp64_arrays(c, 0, src, mp64, n_pts, pts, body, u, 1.0 / (4.0 * kPiD * c->prm.mu));
+}
+
+void launch_moments64(mfs_ctx* c, const double4* src64, double2* mp64) {
+  hipLaunchKernelGGL(k_moments64, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
+                     c->ct[0], src64, mp64);
 }
 
 void launch_fine_strengths(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, double* ptil,

@@ -16,7 +16,7 @@ import pytest
 
 from oracle.geometry import rigid_map, rigid_projector, ring
 from oracle.kernel import direct_sum
-from oracle.multipole import far_field, moments
+from oracle.multipole import cluster_moments, far_field, far_field_general, moments
 
 
 def _case(n, rho, seed, project=False):
@@ -81,3 +81,48 @@ def test_mobility_strengths_zero_force_and_torque():
     u = far_field(Z, A, B, 0.7)
     bound = np.abs(s).sum() * 0.25 ** 13 / 0.75 / (4 * math.pi)
     assert np.abs(np.stack([u.real, u.imag], axis=1) - ref).max() <= bound
+
+
+def _cluster(seed, n_disks=9, spread=2.5):
+    # sources of several rings scattered around the origin: a cluster of disks
+    rng = np.random.default_rng(seed)
+    cs = rng.uniform(-spread, spread, (n_disks, 2))
+    y = np.concatenate([ring(cc, 0.7, 36) for cc in cs])
+    sig = rng.standard_normal(y.shape)
+    return y, sig
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_cluster_expansion_within_bound(seed):
+    mu = 0.8
+    y, sig = _cluster(seed)
+    C = np.array([0.2, -0.1])
+    w = (y[:, 0] - C[0]) + 1j * (y[:, 1] - C[1])
+    s = sig[:, 0] + 1j * sig[:, 1]
+    Rc = np.abs(w).max()
+    for theta in (0.25, 0.5):
+        x = _points(C, Rc / theta, 13)
+        ref = direct_sum(x, y, sig, mu)
+        Z = (x[:, 0] - C[0]) + 1j * (x[:, 1] - C[1])
+        for p in (6, 12):
+            u = far_field_general(Z, *cluster_moments(w, s, p), mu)
+            err = np.abs(np.stack([u.real, u.imag], axis=1) - ref).max()
+            bound = np.abs(s).sum() * theta ** (p + 1) / (1 - theta) / (4 * math.pi * mu)
+            assert err <= bound, (theta, p, err, bound)
+    x = _points(C, Rc / 0.25, 7)                     # p = 30: the direct sum to rounding
+    ref = direct_sum(x, y, sig)
+    Z = (x[:, 0] - C[0]) + 1j * (x[:, 1] - C[1])
+    u = far_field_general(Z, *cluster_moments(w, s, 30))
+    assert np.abs(np.stack([u.real, u.imag], axis=1) - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_cluster_moments_of_a_ring_reduce_to_the_ring_form():
+    c, y, sig, w, s = _case(36, 0.7, 6)
+    A, B, D = cluster_moments(w, s, 10)
+    assert abs(D[0] - B[1]) < 1e-13 * np.abs(s).sum()
+    assert np.allclose(D[1:], 0.49 * A[:-1], rtol=0, atol=1e-13 * np.abs(s).sum())
+    # the two truncations differ by one term of Q; at order 30 both are the full series
+    A, B, D = cluster_moments(w, s, 30)
+    x = _points(c, 0.7 / 0.3)
+    Z = (x[:, 0] - c[0]) + 1j * (x[:, 1] - c[1])
+    assert np.allclose(far_field_general(Z, A, B, D), far_field(Z, A, B, 0.7), rtol=0, atol=1e-15)
