@@ -79,6 +79,61 @@ def ksum_work(centers, radii, n_src, r_src, X, threads_T=KSUM_T, block=256):
     pairs = threads_T * int(np.asarray(n_src, dtype=np.int64)[near_k].sum())
     exps = threads_T * (n_threads * P - uniq.size)
     return pairs, exps
+# One evaluation of a far cluster's expansion in the FP32 kernel sum (order 12 about the
+# cluster's centre): four complex Horner series, 32 flops per step over 11 steps, plus about
+# 64 for zeta, the first terms, the log term and the combination
+CL_ORDER = 12
+FLOP_PER_CLUSTER_EXPANSION = 32 * (CL_ORDER - 1) + 64
+CL_FAR2 = 16.0              # a cluster is far for a target beyond 4 cluster radii
+
+
+def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, threads_T=KSUM_T, block=256):
+    """Work of one FP32 kernel-sum launch with the two-level far field: cluster expansions,
+    disk expansions and direct pair evaluations.
+
+    Per thread (T targets, block apart) and cluster: the cluster is taken from its expansion
+    when every target is beyond 4 cluster radii (the kernel's other conditions, a target's
+    own disk or a skipped partner inside the cluster, only hold for clusters that are near
+    anyway); otherwise each of its disks is an expansion when every target is beyond 7 ring
+    radii, else direct over its sources.  cl: mfs_get_clusters of the context."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    P = centers.shape[0]
+    n_src = np.asarray(n_src, dtype=np.int64)
+    rho = np.asarray(r_src, dtype=np.float64) * np.asarray(radii, dtype=np.float64)
+    ncl = cl["radius"].size
+    size = np.diff(cl["cl_start"]).astype(np.int64)
+    body_cl = np.empty(P, dtype=np.int64)
+    body_cl[cl["slot_body"]] = np.repeat(np.arange(ncl), size)
+    per_blk = block * threads_T
+    n_thr = (X.shape[0] + per_blk - 1) // per_blk * block
+    tid = np.arange(X.shape[0])
+    thread = (tid // per_blk) * block + (tid % block)
+    # (thread, cluster) pairs that are near for some target of the thread
+    lists = cKDTree(X).query_ball_point(cl["centre"], r=np.sqrt(CL_FAR2) * cl["radius"])
+    cnt = np.array([len(l) for l in lists])
+    q_idx = np.repeat(np.arange(ncl), cnt)
+    t_idx = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists])
+    near_tq = np.unique(thread[t_idx].astype(np.int64) * ncl + q_idx)
+    near_bodies = int(size[near_tq % ncl].sum())
+    cl_exps = threads_T * (n_thr * ncl - near_tq.size)
+    # (thread, disk) pairs with a target within 7 ring radii, inside a near cluster
+    tree = cKDTree(centers)
+    lists = tree.query_ball_point(X, r=float(np.sqrt(MP_FAR2) * rho.max()))
+    cnt = np.array([len(l) for l in lists])
+    t_idx = np.repeat(tid, cnt)
+    k_idx = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists])
+    d = X[t_idx] - centers[k_idx]
+    keep = np.einsum("ij,ij->i", d, d) <= MP_FAR2 * rho[k_idx] ** 2
+    tk = np.unique(thread[t_idx[keep]].astype(np.int64) * P + k_idx[keep])
+    th, kb = tk // P, tk % P
+    inside = np.isin(th * ncl + body_cl[kb], near_tq)
+    direct_k = kb[inside]
+    pairs = threads_T * int(n_src[direct_k].sum())
+    disk_exps = threads_T * (near_bodies - direct_k.size)
+    return pairs, disk_exps, cl_exps
+
+
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (dense, packed FP32)
 PEAK_FP64_TFLOPS = 78.6
 
@@ -98,9 +153,9 @@ def ksum_traffic_bytes():
     if i < 0:
         return None
     body = src[i:src.index("\n}\n", i) + 3]
-    # the expansion's order and radius live outside the kernel's text
+    # the expansions' orders and radii live outside the kernel's text
     hdr = open(os.path.join(ROOT, "paper_2606_11273_amd", "csrc", "internal.h")).read()
-    body += "".join(l for l in (hdr + src).splitlines(True) if "constexpr" in l and "kMp" in l and "kMp64" not in l)
+    body += "".join(l for l in (hdr + src).splitlines(True) if "constexpr" in l and ("kMp" in l or "kCl" in l) and "kMp64" not in l)
     if hashlib.sha256(body.encode()).hexdigest()[:16] != KSUM_TRAFFIC["src_sha256_16"]:
         return None
     t = KSUM_TRAFFIC
@@ -297,9 +352,9 @@ def main():
     # roofline of the dominant kernel (mixed kernel sum; one launch = one matvec's sum without
     # each disk's own sources and its contact partners).  pair_evals_per_launch counts the
     # Stokeslet pairs of the direct sum the launch stands for; the FP32 kernel evaluates far
-    # disks through their expansions, so its algorithmic flops are the direct pairs it does
-    # compute (near disks) times 20 plus its expansion evaluations times FLOP_PER_EXPANSION;
-    # the FP64 kernel splits near and far disks the same way, with order-18 expansions
+    # clusters and far disks through their expansions, so its algorithmic flops are the direct
+    # pairs it does compute (near disks) times 20 plus its expansion evaluations times their
+    # flops; the FP64 kernel splits near and far disks (no clusters), with order-18 expansions
     pr = nv.mfs_get_pairs(ctx)
     skipped = ns.astype(np.int64).copy()
     np.add.at(skipped, pr[:, 0], ns[pr[:, 1]])
@@ -310,14 +365,19 @@ def main():
                          for i in range(P)])
     t0 = time.perf_counter()
     near_pairs, expansions = ksum_work(c, a, ns, rs, Xt)
-    log(f"kernel-sum work: {near_pairs} direct pairs, {expansions} expansions ({time.perf_counter() - t0:.1f}s)")
-    flops_launch = near_pairs * FLOP_PER_PAIR + expansions * FLOP_PER_EXPANSION
+    pairs32, disk_exps, cl_exps = ksum_work_clusters(c, a, ns, rs, Xt, nv.mfs_get_clusters(ctx))
+    log(f"kernel-sum work: FP32 {pairs32} direct pairs, {disk_exps} disk and {cl_exps} cluster expansions; "
+        f"FP64 {near_pairs} direct pairs, {expansions} expansions ({time.perf_counter() - t0:.1f}s)")
+    flops_launch = (pairs32 * FLOP_PER_PAIR + disk_exps * FLOP_PER_EXPANSION
+                    + cl_exps * FLOP_PER_CLUSTER_EXPANSION)
     achieved = flops_launch / (ks["mixed"] * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=ksum_traffic_bytes(),
-                    kernel="k_ksum_mixed (FP32 Stokeslet sum; far disks by their order-8 expansions)",
+                    kernel="k_ksum_mixed (FP32 Stokeslet sum; far clusters and disks by their order-12 "
+                           "and order-8 expansions)",
                     ms_per_launch=round(ks["mixed"], 3), flops_per_launch=flops_launch,
-                    direct_pairs_per_launch=near_pairs, expansions_per_launch=expansions,
+                    direct_pairs_per_launch=pairs32, expansions_per_launch=disk_exps,
+                    cluster_expansions_per_launch=cl_exps,
                     pair_evals_per_launch=evals_launch,
                     pair_evals_per_s=round(evals_launch / (ks["mixed"] * 1e-3), 1),
                     fp64_kernel_ms_per_launch=round(ks["fp64"], 2),

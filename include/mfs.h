@@ -146,6 +146,19 @@ mfs_status mfs_precompute_pairs(mfs_ctx* ctx, mfs_problem prob, int64_t* n_pairs
  * lexicographic order, or NULL to query only the count. */
 mfs_status mfs_get_pairs(const mfs_ctx* ctx, int64_t* n_pairs, int32_t* pairs);
 
+/* The disk order and clusters of the FP32 kernel sum (its two-level far field; for work
+ * accounting and tests).  Disks are sorted along a Morton curve over their centres and cut
+ * into clusters of consecutive disks (at most 16 disks and 1024 sources each, within one
+ * quadtree cell).  A cluster farther than 4 radii from a target is summed through one
+ * expansion of order 12 about its centre (moments A_k, B_k and D_k = sum sigma conj(w) w^k
+ * of its sources; the paper's fast multipole method plays this part, Sec. 6).
+ * n_clusters: host, written.  Each of the others is host memory or NULL: slot_body (P):
+ * the disk at each position of the order; cl_start (n_clusters + 1): first position of
+ * each cluster; centre (2 n_clusters): mean of its disks' centres; radius (n_clusters):
+ * the largest |c_b - centre| + rho_b over its disks (rho_b: source ring radius). */
+mfs_status mfs_get_clusters(const mfs_ctx* ctx, int32_t* n_clusters, int32_t* slot_body, int32_t* cl_start,
+                            double* centre, double* radius);
+
 /* Import (set) or export (get) the pair matrices of problem prob in the pair
  * order of mfs_get_pairs.  A: host, sum over pairs of (2 n_src_i + 2 n_src_k)^2,
  * each pair's matrix row-major; E: host, sum of 6 x (2 n_src_i + 2 n_src_k),

@@ -82,7 +82,8 @@ void free_all(mfs_ctx* c) {
                   c->ps[1].E,   c->kr.V,      c->kr.w,    c->kr.part,    c->kr.hdev,  c->kr.x,     c->kr.r,
                   c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
                   c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf, c->d_mp,
-                  c->d_mpm,     c->d_mp64,    c->d_mp64m,   c->d_fmp64};
+                  c->d_mpm,     c->d_mp64,    c->d_mp64m,   c->d_fmp64, c->d_slot_of, c->d_slot_body, c->d_ssrc_off, c->d_nbr_slot,
+                  c->d_cl_start, c->d_scent,  c->d_ccent,   c->d_crad2, c->d_cmp,  c->d_cmpm};
   for (void* p : ptrs)
     if (p) dev_free(c, p);
   for (const PairSet& ps : c->ps)
@@ -130,6 +131,82 @@ Status validate_host(mfs_ctx* c, const double* centers, const double* radii, con
   return Status{};
 }
 
+// Order of the disks for the FP32 kernel sum and its clusters.  Disks are sorted along a
+// Morton curve over their centres (16 bits per axis, ties by index); the curve is cut into
+// quadtree cells holding about 16..64 disks, and each cell into runs of at most
+// kClMaxBodies disks and kClMaxSources sources: these runs are the clusters.  A cluster's
+// centre is the mean of its disks' centres and its radius the largest distance from there to
+// a source ring (|c_b - C| + rho_b).
+void build_clusters(mfs_ctx* c) {
+  const int P = c->P;
+  double x0 = c->centers[0], x1 = x0, y0 = c->centers[1], y1 = y0;
+  for (int i = 1; i < P; ++i) {
+    x0 = std::min(x0, c->centers[2 * i]);
+    x1 = std::max(x1, c->centers[2 * i]);
+    y0 = std::min(y0, c->centers[2 * i + 1]);
+    y1 = std::max(y1, c->centers[2 * i + 1]);
+  }
+  const double span = std::max(std::max(x1 - x0, y1 - y0), 1e-300);
+  auto spread = [](uint32_t v) {   // bit k of v -> bit 2k
+    uint64_t x = v & 0xffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+  };
+  std::vector<uint64_t> code(P);
+  for (int i = 0; i < P; ++i) {
+    const uint32_t qx = (uint32_t)std::min(65535.0, std::floor((c->centers[2 * i] - x0) / span * 65535.0));
+    const uint32_t qy = (uint32_t)std::min(65535.0, std::floor((c->centers[2 * i + 1] - y0) / span * 65535.0));
+    code[i] = spread(qx) | (spread(qy) << 1);
+  }
+  c->slot_body.resize(P);
+  for (int i = 0; i < P; ++i) c->slot_body[i] = i;
+  std::stable_sort(c->slot_body.begin(), c->slot_body.end(), [&](int a, int b) { return code[a] < code[b]; });
+  c->slot_of.assign(P, 0);
+  for (int s = 0; s < P; ++s) c->slot_of[c->slot_body[s]] = s;
+  // quadtree level whose cells hold at least 16 disks on average: 4^(16 - L) cells <= P / 16
+  int depth = 0;
+  while (depth < 16 && (int64_t)1 << (2 * (depth + 1)) <= std::max(1, P / 16)) ++depth;
+  const int shift = 2 * (16 - depth);
+  c->cl_start.assign(1, 0);
+  int nb = 0, ns = 0;
+  for (int s = 0; s < P; ++s) {
+    const int b = c->slot_body[s];
+    const bool new_cell = s > 0 && (code[b] >> shift) != (code[c->slot_body[s - 1]] >> shift);
+    if (s > 0 && (new_cell || nb == kClMaxBodies || ns + c->n_src[b] > kClMaxSources)) {
+      c->cl_start.push_back(s);
+      nb = ns = 0;
+    }
+    ++nb;
+    ns += c->n_src[b];
+  }
+  c->cl_start.push_back(P);
+  c->ncl = (int)c->cl_start.size() - 1;
+  c->cl_centre.assign(2 * c->ncl, 0.0);
+  c->cl_radius.assign(c->ncl, 0.0);
+  for (int q = 0; q < c->ncl; ++q) {
+    double cx = 0, cy = 0;
+    for (int s = c->cl_start[q]; s < c->cl_start[q + 1]; ++s) {
+      cx += c->centers[2 * c->slot_body[s]];
+      cy += c->centers[2 * c->slot_body[s] + 1];
+    }
+    const int m = c->cl_start[q + 1] - c->cl_start[q];
+    cx /= m;
+    cy /= m;
+    double r = 0;
+    for (int s = c->cl_start[q]; s < c->cl_start[q + 1]; ++s) {
+      const int b = c->slot_body[s];
+      const double* yr = c->h_Yr[c->cls[b]].data();
+      r = std::max(r, std::hypot(c->centers[2 * b] - cx, c->centers[2 * b + 1] - cy) + std::hypot(yr[0], yr[1]));
+    }
+    c->cl_centre[2 * q] = cx;
+    c->cl_centre[2 * q + 1] = cy;
+    c->cl_radius[q] = r;
+  }
+}
+
 Status build(mfs_ctx* c, const double* centers, const double* radii, const int32_t* n_src, const int32_t* n_col,
              const double* r_src) {
   (void)radii;
@@ -172,6 +249,27 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   }
   Status st = onebody_factors(c);
   if (st.code) return st;
+  build_clusters(c);
+  // slot-ordered copies for the FP32 kernel sum
+  std::vector<int32_t> ssrc_off(P + 1, 0), nbr_slot(c->nbr_list.size());
+  std::vector<double> scent(2 * (size_t)P);
+  std::vector<float> crad2(c->ncl);
+  for (int s = 0; s < P; ++s) {
+    const int b = c->slot_body[s];
+    ssrc_off[s + 1] = ssrc_off[s] + n_src[b];
+    scent[2 * s] = c->centers[2 * b];
+    scent[2 * s + 1] = c->centers[2 * b + 1];
+  }
+  for (int i = 0; i < P; ++i) {
+    for (int e = c->nbr_off[i]; e < c->nbr_off[i + 1]; ++e) nbr_slot[e] = c->slot_of[c->nbr_list[e]];
+    std::sort(nbr_slot.begin() + c->nbr_off[i], nbr_slot.begin() + c->nbr_off[i + 1]);
+  }
+  // radius rounded up to FP32, so the kernel's far test never admits a nearer point
+  for (int q = 0; q < c->ncl; ++q) {
+    float r = (float)c->cl_radius[q];
+    if ((double)r < c->cl_radius[q]) r = std::nextafter(r, INFINITY);
+    crad2[q] = r * r;
+  }
   // exact evaluation counts of one kernel sum: all sources, and without own disk and partners
   c->evals_all = c->Ns * c->Nt;
   c->evals_skip = 0;
@@ -218,6 +316,14 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   if ((st = upload(c, &c->d_Y, Y, s)).code) return st;
   if ((st = upload(c, &c->d_X, X, s)).code) return st;
   if ((st = upload(c, &c->d_Xr32, Xr32, s)).code) return st;
+  if ((st = upload(c, &c->d_slot_of, c->slot_of, s)).code) return st;
+  if ((st = upload(c, &c->d_slot_body, c->slot_body, s)).code) return st;
+  if ((st = upload(c, &c->d_ssrc_off, ssrc_off, s)).code) return st;
+  if ((st = upload(c, &c->d_nbr_slot, nbr_slot, s)).code) return st;
+  if ((st = upload(c, &c->d_cl_start, c->cl_start, s)).code) return st;
+  if ((st = upload(c, &c->d_scent, scent, s)).code) return st;
+  if ((st = upload(c, &c->d_ccent, c->cl_centre, s)).code) return st;
+  if ((st = upload(c, &c->d_crad2, crad2, s)).code) return st;
   if ((st = dalloc(c, &c->d_lam_bar, 2 * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_ltil, c->xoff[C])).code) return st;
   if ((st = dalloc(c, &c->d_u, 2 * c->Nt)).code) return st;
@@ -228,6 +334,8 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   if ((st = dalloc(c, &c->d_sig32, c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_bdat, (size_t)P)).code) return st;
   if ((st = dalloc(c, &c->d_mp, (size_t)P * kMpCoefPerDisk)).code) return st;
+  if ((st = dalloc(c, &c->d_cmp, (size_t)c->ncl * kClCoefPerCluster)).code) return st;
+  if ((st = dalloc(c, &c->d_sig64, 2 * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_src64, c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_mp64, (size_t)P * kMp64CoefPerDisk)).code) return st;
   MFS_HIP(hipStreamSynchronize(s));
@@ -264,8 +372,10 @@ Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u) {
 Status ensure_stacked(mfs_ctx* c, int R) {
   if (c->rhs_cap >= R) return Status{};
   for (void* p : {(void*)c->d_lam_bar_m, (void*)c->d_ltil_m, (void*)c->d_u_m, (void*)c->d_corr_m,
-                  (void*)c->d_sig32m, (void*)c->d_bdatm, (void*)c->d_src64m, (void*)c->d_mpm, (void*)c->d_mp64m})
+                  (void*)c->d_sig32m, (void*)c->d_bdatm, (void*)c->d_src64m, (void*)c->d_mpm, (void*)c->d_mp64m,
+                  (void*)c->d_cmpm})
     if (p) dev_free(c, p);
+  c->d_cmpm = nullptr;
   c->d_lam_bar_m = c->d_ltil_m = c->d_u_m = c->d_corr_m = nullptr;
   c->d_sig32m = c->d_bdatm = nullptr;
   c->d_mpm = nullptr;
@@ -281,6 +391,7 @@ Status ensure_stacked(mfs_ctx* c, int R) {
   if ((st = dalloc(c, &c->d_sig32m, (size_t)R * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_bdatm, (size_t)R * c->P)).code) return st;
   if ((st = dalloc(c, &c->d_mpm, (size_t)R * c->P * kMpCoefPerDisk)).code) return st;
+  if ((st = dalloc(c, &c->d_cmpm, (size_t)R * c->ncl * kClCoefPerCluster)).code) return st;
   if ((st = dalloc(c, &c->d_src64m, (size_t)R * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_mp64m, (size_t)R * c->P * kMp64CoefPerDisk)).code) return st;
   c->rhs_cap = R;
@@ -314,7 +425,8 @@ Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, do
       launch_gather_project_to(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx, wp,
                                mixed ? c->d_sig32m + r * c->Ns : nullptr, mixed ? nullptr : c->d_src64m + r * c->Ns,
                                mixed ? c->d_bdatm + (int64_t)r * c->P : nullptr,
-                               mixed ? c->d_mpm + (int64_t)r * c->P * kMpCoefPerDisk : nullptr);
+                               mixed ? c->d_mpm + (int64_t)r * c->P * kMpCoefPerDisk : nullptr,
+                               mixed ? c->d_cmpm + (int64_t)r * c->ncl * kClCoefPerCluster : nullptr);
     if (!mixed)
       for (int r = 0; r < Rc; ++r)
         launch_moments64(c, c->d_src64m + r * c->Ns, c->d_mp64m + (int64_t)r * c->P * kMp64CoefPerDisk);
@@ -424,6 +536,17 @@ mfs_status mfs_get_pairs(const mfs_ctx* c, int64_t* n_pairs, int32_t* pairs) {
   if (!c || !n_pairs) return MFS_ERR_ARG;
   *n_pairs = (int64_t)(c->pairs.size() / 2);
   if (pairs) std::memcpy(pairs, c->pairs.data(), sizeof(int32_t) * c->pairs.size());
+  return MFS_OK;
+}
+
+mfs_status mfs_get_clusters(const mfs_ctx* c, int32_t* n_clusters, int32_t* slot_body, int32_t* cl_start,
+                            double* centre, double* radius) {
+  if (!c || !n_clusters) return MFS_ERR_ARG;
+  *n_clusters = c->ncl;
+  if (slot_body) std::memcpy(slot_body, c->slot_body.data(), sizeof(int32_t) * c->slot_body.size());
+  if (cl_start) std::memcpy(cl_start, c->cl_start.data(), sizeof(int32_t) * c->cl_start.size());
+  if (centre) std::memcpy(centre, c->cl_centre.data(), sizeof(double) * c->cl_centre.size());
+  if (radius) std::memcpy(radius, c->cl_radius.data(), sizeof(double) * c->cl_radius.size());
   return MFS_OK;
 }
 

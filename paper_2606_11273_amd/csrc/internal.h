@@ -19,6 +19,13 @@ constexpr int kMpOrder = 8;        // order of the per-disk far-field expansion 
 constexpr int kMpCoefPerDisk = 3 * kMpOrder + 2;   // its FP32 complex coefficients per disk
 constexpr int kMp64Order = 18;     // order of the FP64 kernel sum's far-field expansion
 constexpr int kMp64CoefPerDisk = 3 * kMp64Order + 3;   // FP64 complex coefficients per disk (last: rho^2)
+// Two-level FP32 kernel sum: disks in a space-filling-curve order ("slots"), grouped into
+// clusters of at most kClMaxBodies consecutive slots; a cluster far from a target is summed
+// through one expansion of order kClOrder about its centre.
+constexpr int kClOrder = 12;
+constexpr int kClCoefPerCluster = 4 * kClOrder + 2;   // FP32 complex coefficients per cluster
+constexpr int kClMaxBodies = 16;
+constexpr int kClMaxSources = 1024;                   // sources per cluster (one LDS tile)
 constexpr double kPiD = 3.14159265358979323846;
 
 struct Status {
@@ -92,6 +99,11 @@ struct mfs_ctx {
   std::vector<int64_t> xoff, aoff, coff;   // C + 1: pair source-vector, matrix and node-vector offsets
   std::vector<int32_t> bp_off, bp_list;    // body -> (pair, side) CSR
   std::vector<int32_t> nbr_off, nbr_list;  // body -> sorted contact partners
+  // FP32 kernel-sum order: slot_body[s] = body in slot s, slot_of[b] = its inverse;
+  // cluster q holds slots cl_start[q] .. cl_start[q + 1] - 1
+  std::vector<int32_t> slot_body, slot_of, cl_start;
+  std::vector<double> cl_centre, cl_radius;   // 2 ncl, ncl: centre and the radius holding its sources
+  int ncl = 0;
   int64_t Ns = 0, Nt = 0;
 
   // class data
@@ -107,6 +119,12 @@ struct mfs_ctx {
   double* d_Y = nullptr;         // Ns x 2 absolute sources
   double* d_X = nullptr;         // Nt x 2 absolute nodes
   float* d_Xr32 = nullptr;       // Nt x 2 nodes relative to their centre
+  // the same in slot order, for the FP32 kernel sum
+  int32_t *d_slot_of = nullptr, *d_slot_body = nullptr, *d_ssrc_off = nullptr, *d_nbr_slot = nullptr;
+  int32_t* d_cl_start = nullptr;
+  double* d_scent = nullptr;     // P x 2 centres in slot order
+  double* d_ccent = nullptr;     // ncl x 2 cluster centres
+  float* d_crad2 = nullptr;      // ncl squared cluster radii
 
   // work vectors
   double *d_lam_bar = nullptr, *d_ltil = nullptr, *d_sig64 = nullptr, *d_u = nullptr, *d_corr = nullptr;
@@ -114,6 +132,7 @@ struct mfs_ctx {
   float4* d_sig32 = nullptr;     // per source: (yr_x, yr_y, sigma_x, sigma_y)
   float4* d_bdat = nullptr;      // per disk: (net strength x, y, ring radius^2, W) for the FP32 sum
   float2* d_mp = nullptr;        // per disk: far-field expansion coefficients for the FP32 sum
+  float2* d_cmp = nullptr;       // per cluster: its expansion coefficients for the FP32 sum
   double2* d_mp64 = nullptr;     // per disk: far-field expansion coefficients of d_src64 for the FP64 sum
   double4* d_src64 = nullptr;    // per source: (y_x, y_y, sigma_x, sigma_y)
   int64_t upart_cap = 0;
@@ -124,6 +143,7 @@ struct mfs_ctx {
   float4* d_sig32m = nullptr;    // rhs_cap arrays of Ns records
   float4* d_bdatm = nullptr;     // rhs_cap arrays of P records
   float2* d_mpm = nullptr;       // rhs_cap arrays of P far-field coefficient records
+  float2* d_cmpm = nullptr;      // rhs_cap arrays of ncl cluster coefficient records
   double2* d_mp64m = nullptr;    // rhs_cap arrays of P FP64 far-field coefficient records
   double4* d_src64m = nullptr;   // rhs_cap arrays of Ns records
 
@@ -161,8 +181,10 @@ void launch_onebody_apply(mfs_ctx* c, int prob, const double* mu, double* lam_ba
 void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil);
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                            bool pack32, bool pack64);
+// sig32, bdat, mp (FP32 sum: slot order) and cmp (its cluster coefficients) go together
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                              float4* sig32, double4* src64, float4* bdat, float2* mp = nullptr);
+                              float4* sig32, double4* src64, float4* bdat, float2* mp = nullptr,
+                              float2* cmp = nullptr);
 // stacked forms for R = 2, 4 or 8 vectors (false: unsupported size or out of memory)
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
                        int64_t ltil_stride);

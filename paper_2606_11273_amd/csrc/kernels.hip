@@ -236,9 +236,13 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
     const int* __restrict__ bp_off, const int* __restrict__ bp_list, const int* __restrict__ pairs,
     const int64_t* __restrict__ xoff, const double* __restrict__ ltil, const double* __restrict__ lam_bar,
     int with_pairs, const double* __restrict__ centers, double* __restrict__ sig64, float4* __restrict__ sig32,
-    double4* __restrict__ src64, float4* __restrict__ bdat, float2* __restrict__ mp) {
+    double4* __restrict__ src64, float4* __restrict__ bdat, float2* __restrict__ mp, const int* __restrict__ slot_of,
+    const int* __restrict__ ssrc_off) {
   const int b = blockIdx.x;
   if (b >= P) return;
+  // the FP32 sum's records (sig32, bdat, mp) are stored in its slot order
+  const int sl = slot_of[b];
+  const int64_t sso = ssrc_off[sl];
   const int k = cls[b];
   const int nc = ct.nc[k];
   const int64_t so = src_off[b];
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
     w = block_sum<kBodyThreads>(w, red + 32);
     if (threadIdx.x == 0) {
       const double q = Yr[0] * Yr[0] + Yr[1] * Yr[1];
-      bdat[b] = make_float4((float)s0x, (float)s0y, (float)q, (float)w);
+      bdat[sl] = make_float4((float)s0x, (float)s0y, (float)q, (float)w);
     }
   }
   if (mp) {
@@ -322,7 +326,7 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
     for (int e = threadIdx.x; e < 4 * kMpOrder + 2; e += kBodyThreads) mred[0][e] += mred[1][e];
     __syncthreads();
     if (threadIdx.x == 0) {
-      float2* o = mp + (int64_t)b * kMpCoef;
+      float2* o = mp + (int64_t)sl * kMpCoef;
       for (int k = 1; k <= kMpOrder; ++k) {
         const double* m = &mred[0][4 * (k - 1)];
         o[k - 1] = make_float2((float)(m[0] / (2 * k)), (float)(m[1] / (2 * k)));
@@ -339,8 +343,87 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
       sig64[2 * (so + j)] = sx;
       sig64[2 * (so + j) + 1] = sy;
     }
-    if (sig32) sig32[so + j] = make_float4((float)Yr[2 * j], (float)Yr[2 * j + 1], (float)sx, (float)sy);
+    if (sig32) sig32[sso + j] = make_float4((float)Yr[2 * j], (float)Yr[2 * j + 1], (float)sx, (float)sy);
     if (src64) src64[so + j] = make_double4(cx + Yr[2 * j], cy + Yr[2 * j + 1], sx, sy);
+  }
+}
+
+// Expansion of a cluster of disks about its centre C for the FP32 kernel sum (the
+// two-level far field).  With w = y - C over the cluster's sources (not on one ring),
+//   4 pi mu u(C + Z) = -S0 ln|Z| + S0/2 + sum_k (A_k zeta^k + B_k conj(zeta)^k) / (2k)
+//                      + conj(zeta)/2 [Z P - Q],
+// zeta = 1/Z, A_k = sum sigma w^k, B_k = sum sigma conj(w)^k, D_k = sum sigma conj(w) w^k,
+// P = sum_k conj(A_k) conj(zeta)^k, Q = sum_k conj(D_k) conj(zeta)^k (k = 0..p).  The moments
+// are FP64 sums over the FP64 strengths (sig64, body order); record per cluster, FP32:
+// A_k/(2k), B_k/(2k) (k = 1..p), conj(A_k), conj(D_k) (k = 0..p).  Truncation: below
+// sum |sigma| theta^(p+1) / (1 - theta), theta = cluster radius / |Z| <= 1/4 where used.
+constexpr int kClCoef = kClCoefPerCluster;
+constexpr float kClFar2 = 16.0f;   // a cluster is far beyond 4 cluster radii
+constexpr int kClM = 6 * (kClOrder + 1);   // real moment components per cluster
+
+__global__ __launch_bounds__(kBodyThreads) void k_cluster_moments(int ncl, const int* __restrict__ cl_start,
+                                                                  const int* __restrict__ slot_body,
+                                                                  const int* __restrict__ cls,
+                                                                  const int* __restrict__ src_off, ClassTab ct,
+                                                                  const double* __restrict__ centers,
+                                                                  const double* __restrict__ ccent,
+                                                                  const double* __restrict__ sig64,
+                                                                  float2* __restrict__ cmp) {
+  const int q = blockIdx.x;
+  if (q >= ncl) return;
+  const double Cx = ccent[2 * q], Cy = ccent[2 * q + 1];
+  double m[kClM];   // per k: A (re, im), B (re, im), D (re, im)
+#pragma unroll
+  for (int e = 0; e < kClM; ++e) m[e] = 0.0;
+  for (int sl = cl_start[q]; sl < cl_start[q + 1]; ++sl) {
+    const int b = slot_body[sl];
+    const int k = cls[b];
+    const int nc = ct.nc[k];
+    const double* Yr = ct.Yr[k];
+    const int64_t so = src_off[b];
+    const double ox = centers[2 * b] - Cx, oy = centers[2 * b + 1] - Cy;
+    for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
+      const double wx = ox + Yr[2 * j], wy = oy + Yr[2 * j + 1];
+      double pr = sig64[2 * (so + j)], pi = sig64[2 * (so + j) + 1];   // sigma w^k
+      double qr = pr, qi = pi;                                           // sigma conj(w)^k
+#pragma unroll
+      for (int e = 0; e <= kClOrder; ++e) {
+        m[6 * e] += pr;
+        m[6 * e + 1] += pi;
+        m[6 * e + 2] += qr;
+        m[6 * e + 3] += qi;
+        m[6 * e + 4] += wx * pr + wy * pi;   // conj(w) sigma w^k
+        m[6 * e + 5] += wx * pi - wy * pr;
+        const double tr = pr * wx - pi * wy, ti = pr * wy + pi * wx;
+        const double ur = qr * wx + qi * wy, ui = qi * wx - qr * wy;
+        pr = tr;
+        pi = ti;
+        qr = ur;
+        qi = ui;
+      }
+    }
+  }
+  __shared__ double mred[2][kClM];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int e = 0; e < kClM; ++e) {
+    const double v = wave_sum(m[e]);
+    if (lane == 0) mred[wid][e] = v;
+  }
+  __syncthreads();
+  static_assert(kBodyThreads == 128, "two waves per cluster block");
+  float2* o = cmp + (int64_t)q * kClCoef;
+  for (int e = threadIdx.x; e <= kClOrder; e += kBodyThreads) {
+    const double* a = &mred[0][6 * e];
+    const double* a1 = &mred[1][6 * e];
+    const double Ar = a[0] + a1[0], Ai = a[1] + a1[1], Br = a[2] + a1[2], Bi = a[3] + a1[3];
+    const double Dr = a[4] + a1[4], Di = a[5] + a1[5];
+    if (e >= 1) {
+      o[e - 1] = make_float2((float)(Ar / (2 * e)), (float)(Ai / (2 * e)));
+      o[kClOrder + e - 1] = make_float2((float)(Br / (2 * e)), (float)(Bi / (2 * e)));
+    }
+    o[2 * kClOrder + e] = make_float2((float)Ar, (float)(-Ai));
+    o[3 * kClOrder + 1 + e] = make_float2((float)Dr, (float)(-Di));
   }
 }
 
@@ -399,17 +482,27 @@ __device__ __forceinline__ bool skip_test(Skip& sk, int mode, int kb, int body, 
   return false;
 }
 
+// Disks are visited in slot order (src_off, centers, src, bdat, mp and the partner lists
+// nbr_list are in slots), one cluster of consecutive slots per LDS tile.  A cluster that is
+// far (beyond 4 cluster radii) from every target of a thread and holds neither a target's
+// own disk nor a partner to be skipped is summed through its expansion (k_cluster_moments;
+// cmp = NULL: never); otherwise its disks are taken one by one as below.
 template <int T>
-__global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __restrict__ src_off,
+__global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* __restrict__ cl_start,
+                                                           const int* __restrict__ src_off,
                                                            const double* __restrict__ centers,
                                                            const float4* __restrict__ src,
                                                            const float4* __restrict__ bdat, int64_t Nt,
                                                            const int* __restrict__ tgt_body,
-                                                           const double* __restrict__ X, int bodies_per_split,
+                                                           const int* __restrict__ slot_of,
+                                                           const double* __restrict__ X, int clusters_per_split,
                                                            int mode, const int* __restrict__ nbr_off,
                                                            const int* __restrict__ nbr_list, double scale,
                                                            double* __restrict__ out,
-                                                           const float2* __restrict__ mp) {
+                                                           const float2* __restrict__ mp,
+                                                           const double* __restrict__ ccent,
+                                                           const float* __restrict__ crad2,
+                                                           const float2* __restrict__ cmp) {
   __shared__ float4 s_src[KS_TILE];    // (y_x, y_y, sigma_x, sigma_y), y relative to the disk centre
   __shared__ float s_w[KS_TILE];       // y . sigma
   __shared__ double s_c[2 * KS_MAXB];
@@ -417,30 +510,111 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
   __shared__ int s_off[KS_MAXB + 1];
   __shared__ float2 s_mp[KS_MAXB * kMpCoef];   // far-field coefficients of the tile's disks
   const int split = blockIdx.y;
-  const int kb0 = split * bodies_per_split;
-  const int kb1 = min(P, kb0 + bodies_per_split);
+  const int q0 = min(ncl, split * clusters_per_split);
+  const int q1 = min(ncl, q0 + clusters_per_split);
   int64_t t[T];
-  int bt[T];
+  int bt[T];   // the target's disk, in slot order
   double x[T], y[T], ax[T], ay[T];
   Skip sk[T];
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + j * KS_THREADS + threadIdx.x;
     const int64_t tc = t[j] < Nt ? t[j] : Nt - 1;
-    bt[j] = tgt_body[tc];
+    const int body = tgt_body[tc];
+    bt[j] = slot_of[body];
     x[j] = X[2 * tc];
     y[j] = X[2 * tc + 1];
     ax[j] = 0.0;
     ay[j] = 0.0;
-    skip_init(sk[j], mode, bt[j], kb0, nbr_off, nbr_list);
+    skip_init(sk[j], mode, body, cl_start[q0], nbr_off, nbr_list);
   }
   const float kHalfLn2 = 0.34657359027997264f;
-  for (int kt = kb0; kt < kb1;) {
+  for (int cq = q0; cq < q1; ++cq) {
+    const int kt = cl_start[cq], ke = cl_start[cq + 1];
+    const int nb = ke - kt;
+    bool cfar = cmp != nullptr;
+    if (cfar) {
+      const double cx = ccent[2 * cq], cy = ccent[2 * cq + 1];
+      const float rf = kClFar2 * crad2[cq];
+      float Zx[T], Zy[T], R2[T];
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        Zx[j] = (float)(x[j] - cx);
+        Zy[j] = (float)(y[j] - cy);
+        R2[j] = fmaf(Zx[j], Zx[j], Zy[j] * Zy[j]);
+        cfar = cfar && R2[j] > rf && (mode == 0 || bt[j] < kt || bt[j] >= ke) && (mode != 2 || sk[j].next >= ke);
+      }
+      if (cfar) {
+        // Horner over the cluster's series: h1 over zeta (A_k/2k), h2 over conj(zeta) (B_k/2k),
+        // h3 over conj(zeta) (conj A_k), h4 over conj(zeta) (conj D_k)
+        const float2* cf = cmp + (int64_t)cq * kClCoef;
+        float zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T], h4r[T], h4i[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const float ir2 = __builtin_amdgcn_rcpf(R2[j]);
+          zr[j] = Zx[j] * ir2;
+          zi[j] = Zy[j] * ir2;
+          h1r[j] = cf[kClOrder - 1].x;
+          h1i[j] = cf[kClOrder - 1].y;
+          h2r[j] = cf[2 * kClOrder - 1].x;
+          h2i[j] = cf[2 * kClOrder - 1].y;
+          h3r[j] = cf[3 * kClOrder].x;
+          h3i[j] = cf[3 * kClOrder].y;
+          h4r[j] = cf[4 * kClOrder + 1].x;
+          h4i[j] = cf[4 * kClOrder + 1].y;
+        }
+#pragma unroll
+        for (int k = kClOrder - 1; k >= 1; --k) {
+          const float2 a = cf[k - 1], bq = cf[kClOrder + k - 1], g = cf[2 * kClOrder + k], e = cf[3 * kClOrder + 1 + k];
+#pragma unroll
+          for (int j = 0; j < T; ++j) {
+            const float t1r = fmaf(zr[j], h1r[j], fmaf(zi[j], h1i[j], a.x));
+            const float t1i = fmaf(zr[j], h1i[j], fmaf(-zi[j], h1r[j], a.y));
+            const float t2r = fmaf(zr[j], h2r[j], fmaf(-zi[j], h2i[j], bq.x));
+            const float t2i = fmaf(zr[j], h2i[j], fmaf(zi[j], h2r[j], bq.y));
+            const float t3r = fmaf(zr[j], h3r[j], fmaf(-zi[j], h3i[j], g.x));
+            const float t3i = fmaf(zr[j], h3i[j], fmaf(zi[j], h3r[j], g.y));
+            const float t4r = fmaf(zr[j], h4r[j], fmaf(-zi[j], h4i[j], e.x));
+            const float t4i = fmaf(zr[j], h4i[j], fmaf(zi[j], h4r[j], e.y));
+            h1r[j] = t1r;
+            h1i[j] = t1i;
+            h2r[j] = t2r;
+            h2i[j] = t2i;
+            h3r[j] = t3r;
+            h3i[j] = t3i;
+            h4r[j] = t4r;
+            h4i[j] = t4i;
+          }
+        }
+        const float2 g0 = cf[2 * kClOrder], e0 = cf[3 * kClOrder + 1];
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          // P = conj(A_0) + conj(zeta) h3, Q = conj(D_0) + conj(zeta) h4, zeta h1, conj(zeta) h2
+          const float pr = fmaf(zr[j], h3r[j], fmaf(-zi[j], h3i[j], g0.x));
+          const float pi = fmaf(zr[j], h3i[j], fmaf(zi[j], h3r[j], g0.y));
+          const float qr = fmaf(zr[j], h4r[j], fmaf(-zi[j], h4i[j], e0.x));
+          const float qi = fmaf(zr[j], h4i[j], fmaf(zi[j], h4r[j], e0.y));
+          const float p1r = fmaf(zr[j], h1r[j], zi[j] * h1i[j]);
+          const float p1i = fmaf(zr[j], h1i[j], -zi[j] * h1r[j]);
+          const float p2r = fmaf(zr[j], h2r[j], -zi[j] * h2i[j]);
+          const float p2i = fmaf(zr[j], h2i[j], zi[j] * h2r[j]);
+          // conj(zeta)/2 (Z P - Q)
+          const float mr = fmaf(Zx[j], pr, fmaf(-Zy[j], pi, -qr));
+          const float mi = fmaf(Zx[j], pi, fmaf(Zy[j], pr, -qi));
+          const float t3r = 0.5f * fmaf(zr[j], mr, -zi[j] * mi);
+          const float t3i = 0.5f * fmaf(zr[j], mi, zi[j] * mr);
+          // -S0 ln|Z| + S0 / 2, S0 = conj(g0)
+          const float lZ = fmaf(-kHalfLn2, __builtin_amdgcn_logf(R2[j]), 0.5f);
+          ax[j] += (double)fmaf(g0.x, lZ, p1r + p2r + t3r);
+          ay[j] += (double)fmaf(-g0.y, lZ, p1i + p2i + t3i);
+        }
+      }
+    }
+    // every thread far: the tile is not needed.  The barrier also ends the reads of the
+    // previous tile before this one is staged.
+    if (__syncthreads_and(cfar ? 1 : 0)) continue;
     const int s0 = src_off[kt];
-    int nb = 0;
-    while (kt + nb < kb1 && nb < KS_MAXB && src_off[kt + nb + 1] - s0 <= KS_TILE) ++nb;
-    const int ns = src_off[kt + nb] - s0;
-    __syncthreads();
+    const int ns = src_off[ke] - s0;
     for (int q = threadIdx.x; q < ns; q += KS_THREADS) {
       const float4 v = src[s0 + q];
       s_src[q] = v;
@@ -454,6 +628,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
     for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
     for (int q = threadIdx.x; q < nb * kMpCoef; q += KS_THREADS) s_mp[q] = mp[(int64_t)kt * kMpCoef + q];
     __syncthreads();
+    if (cfar) continue;
     for (int kk = 0; kk < nb; ++kk) {
       const int kbody = kt + kk;
       const float4 bd = s_b[kk];   // (S0x, S0y, q = |y|^2, W = sum y . sigma)
@@ -586,7 +761,6 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int P, const int* __r
         }
       }
     }
-    kt += nb;
   }
 #pragma unroll
   for (int j = 0; j < T; ++j) {
@@ -1361,16 +1535,22 @@ void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil) {
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                            bool pack32, bool pack64) {
   launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, pack32 ? c->d_sig32 : nullptr,
-                           pack64 ? c->d_src64 : nullptr, pack32 ? c->d_bdat : nullptr, pack32 ? c->d_mp : nullptr);
+                           pack64 ? c->d_src64 : nullptr, pack32 ? c->d_bdat : nullptr, pack32 ? c->d_mp : nullptr,
+                           pack32 ? c->d_cmp : nullptr);
   if (pack64) launch_moments64(c, c->d_src64, c->d_mp64);
 }
 
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                              float4* sig32, double4* src64, float4* bdat, float2* mp) {
+                              float4* sig32, double4* src64, float4* bdat, float2* mp, float2* cmp) {
+  // the cluster moments read the FP64 strengths from d_sig64
   hipLaunchKernelGGL(k_gather_project, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P,
                      prob == MFS_MOBILITY ? 1 : 0, c->d_cls, c->d_src_off, c->ct[prob], c->d_bp_off, c->d_bp_list,
-                     c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers, (double*)nullptr,
-                     sig32, src64, bdat, mp);
+                     c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers,
+                     cmp ? c->d_sig64 : (double*)nullptr, sig32, src64, bdat, mp, c->d_slot_of, c->d_ssrc_off);
+  if (cmp)
+    hipLaunchKernelGGL(k_cluster_moments, dim3(c->ncl), dim3(kBodyThreads), 0, c->stream, c->ncl, c->d_cl_start,
+                       c->d_slot_body, c->d_cls, c->d_src_off, c->ct[prob], c->d_centers, c->d_ccent, c->d_sig64,
+                       cmp);
 }
 
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
@@ -1411,7 +1591,7 @@ static int ksum_targets_per_thread(bool mixed) {
 }
 
 static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
-                                     const float2* mp, double* u, double scale);
+                                     const float2* mp, const float2* cmp, double* u, double scale);
 static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, const double2* mp64, int64_t Nt,
                                     const double* X, const int32_t* tgt_body, double* u, double scale);
 
@@ -1423,7 +1603,8 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
     double* ur = u + (int64_t)r * 2 * c->Nt;
     const bool ok =
         mixed ? launch_ksum_mixed_arrays(c, mode, c->d_sig32m + (int64_t)r * c->Ns, c->d_bdatm + (int64_t)r * c->P,
-                                         c->d_mpm + (int64_t)r * c->P * kMpCoef, ur, scale)
+                                         c->d_mpm + (int64_t)r * c->P * kMpCoef,
+                                         c->d_cmpm + (int64_t)r * c->ncl * kClCoef, ur, scale)
               : launch_ksum_fp64_arrays(c, mode, c->d_src64m + (int64_t)r * c->Ns,
                                         c->d_mp64m + (int64_t)r * c->P * kMp64Coef, c->Nt, c->d_X, c->d_tgt_body,
                                         ur, scale);
@@ -1435,12 +1616,14 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
 // One FP32 kernel sum on explicit packed arrays (sources, disk moments, expansion
 // coefficients); see launch_kernel_sum.
 static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
-                                     const float2* mp, double* u, double scale) {
+                                     const float2* mp, const float2* cmp, double* u, double scale) {
   const int T = ksum_targets_per_thread(true);
   const int64_t Nt = c->Nt;
   const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
-  const int ns = ksum_splits(tblocks, c->P);
-  const int bps = (c->P + ns - 1) / ns;
+  const int ns = std::min(ksum_splits(tblocks, c->P), c->ncl);
+  const int cps = (c->ncl + ns - 1) / ns;
+  const char* ev = std::getenv("MFS_KSUM_CLUSTERS");
+  if (ev && std::atoi(ev) == 0) cmp = nullptr;
   double* out = u;
   if (ns > 1) {
     const int64_t need = (int64_t)ns * Nt * 2;
@@ -1459,8 +1642,9 @@ static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, 
   }
   dim3 grid((unsigned)tblocks, (unsigned)ns);
 #define MFS_KS_MIXED(TT)                                                                                         \
-  hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, c->d_centers, \
-                     sig32, bdat, Nt, c->d_tgt_body, c->d_X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out, mp)
+  hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->ncl, c->d_cl_start,          \
+                     c->d_ssrc_off, c->d_scent, sig32, bdat, Nt, c->d_tgt_body, c->d_slot_of, c->d_X, cps, mode,  \
+                     c->d_nbr_off, c->d_nbr_slot, scale, out, mp, c->d_ccent, c->d_crad2, cmp)
   if (T == 4) MFS_KS_MIXED(4); else if (T == 1) MFS_KS_MIXED(1); else MFS_KS_MIXED(2);
 #undef MFS_KS_MIXED
   if (ns > 1)
@@ -1507,7 +1691,7 @@ static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, co
 }
 
 bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale) {
-  if (mixed) return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, u, scale);
+  if (mixed) return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, c->d_cmp, u, scale);
   return launch_ksum_fp64_arrays(c, mode, c->d_src64, c->d_mp64, c->Nt, c->d_X, c->d_tgt_body, u, scale);
 }
 

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "MFS_OK", 1: "MFS_ERR_ARG", 2: "MFS_ERR_GEOMETRY", 3: "MFS_ER
                 5: "MFS_ERR_STATE", 6: "MFS_ERR_NOCONV", 7: "MFS_ERR_NUMERIC"}
 
 # Exported symbols, in the order of include/mfs.h.
-SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_pairs", "mfs_set_pair_matrices",
+SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_pairs", "mfs_get_clusters", "mfs_set_pair_matrices",
            "mfs_get_pair_matrices", "mfs_apply", "mfs_kernel_sum", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
            "mfs_get_sizes", "mfs_destroy", "mfs_last_error", "mfs_server_create", "mfs_server_footprint",
            "mfs_server_submit", "mfs_server_wait", "mfs_server_last_error", "mfs_server_destroy",
@@ -133,6 +133,7 @@ def lib():
                                C.POINTER(MfsAllocator)]
     L.mfs_precompute_pairs.argtypes = [vp, C.c_int, i64p]
     L.mfs_get_pairs.argtypes = [vp, i64p, ip]
+    L.mfs_get_clusters.argtypes = [vp, ip, ip, ip, dp, dp]
     L.mfs_set_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
     L.mfs_get_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
     L.mfs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int32, vp, vp]
@@ -235,6 +236,20 @@ def mfs_get_pairs(ctx):
     out = np.zeros((n.value, 2), dtype=np.int32)
     _check(lib().mfs_get_pairs(ctx, C.byref(n), _ip(out)), ctx)
     return out
+
+
+def mfs_get_clusters(ctx):
+    """The FP32 kernel sum's disk order and clusters: dict of slot_body (P), cl_start
+    (n_clusters + 1), centre (n_clusters x 2) and radius (n_clusters)."""
+    n = C.c_int32()
+    _check(lib().mfs_get_clusters(ctx, C.byref(n), None, None, None, None), ctx)
+    P = mfs_get_sizes(ctx)[0]
+    slot_body = np.zeros(P, dtype=np.int32)
+    cl_start = np.zeros(n.value + 1, dtype=np.int32)
+    centre = np.zeros((n.value, 2))
+    radius = np.zeros(n.value)
+    _check(lib().mfs_get_clusters(ctx, C.byref(n), _ip(slot_body), _ip(cl_start), _dp(centre), _dp(radius)), ctx)
+    return dict(slot_body=slot_body, cl_start=cl_start, centre=centre, radius=radius)
 
 
 def _pair_sizes(ctx, n_src):

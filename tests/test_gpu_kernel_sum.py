@@ -95,3 +95,46 @@ def test_kernel_sum_full_size_sampled():
     ref, mag = oracle_sum_excluding_self(X, Y, sig, so, co, targets=tsel, partners=_partners(c, a, 0.2))
     assert np.all(np.abs(g["fp64"][tsel] - ref).max(1) <= 1e-13 * mag)
     assert np.all(np.abs(g["mixed"][tsel] - ref).max(1) <= 2e-6 * mag)
+
+
+def test_kernel_sum_clusters_mid_size():
+    # P = 600 packing at area fraction 0.5 (about 55 x 55): the FP32 sum takes the clusters
+    # far from a target (beyond 4 cluster radii) from their expansions; 1500 sampled targets
+    # against the oracle, and the clusters are a valid partition of the disks
+    from paper_2606_11273_amd import native as nv
+    g0 = config_geometry(2, P=600)
+    c, a = g0["centers"], g0["radii"]
+    P = c.shape[0]
+    ns, nc, rs = g0["n_src"], g0["n_col"], g0["r_src"]
+    prm = nv.mfs_default_params()
+    prm.delta_c = g0["delta_c"]
+    ctx = nv.mfs_setup(c, a, ns, nc, rs, prm)
+    try:
+        cl = nv.mfs_get_clusters(ctx)
+    finally:
+        nv.mfs_destroy(ctx)
+    order, st = cl["slot_body"], cl["cl_start"]
+    assert np.array_equal(np.sort(order), np.arange(P)) and st[0] == 0 and st[-1] == P
+    sizes = np.diff(st)
+    assert sizes.min() >= 1 and sizes.max() <= 16
+    for q in range(sizes.size):
+        mem = order[st[q]:st[q + 1]]
+        assert ns[mem].sum() <= 1024
+        assert np.allclose(cl["centre"][q], c[mem].mean(0), rtol=0, atol=1e-12)
+        assert np.all(np.linalg.norm(c[mem] - cl["centre"][q], axis=1) + rs[mem] * a[mem] <= cl["radius"][q] * (1 + 1e-15))
+    X, Y, so, co = coarse_points(c, a, ns, nc, rs)
+    d = np.linalg.norm(X[:, None, :] - cl["centre"][None, :, :], axis=2)
+    far = d > 4 * cl["radius"][None, :]
+    say(f"P=600: {sizes.size} clusters, mean radius {cl['radius'].mean():.2f}; "
+        f"{far.mean():.2f} of the (target, cluster) pairs are far")
+    assert far.mean() > 0.3
+    rng = np.random.default_rng(3)
+    sig = rng.standard_normal((Y.shape[0], 2))
+    for skip in (0, 2):
+        g = _run(c, a, ns, nc, rs, sig, skip, delta_c=g0["delta_c"])
+        tsel = np.sort(rng.choice(X.shape[0], 1500, replace=False))
+        ref, mag = oracle_sum_excluding_self(X, Y, sig, so, co, targets=tsel, include_self=(skip == 0),
+                                             partners=_partners(c, a, g0["delta_c"]) if skip == 2 else None)
+        say(f"  skip {skip}: mixed max err / m_t {(np.abs(g['mixed'][tsel] - ref).max(1) / mag).max():.1e}")
+        assert np.all(np.abs(g["fp64"][tsel] - ref).max(1) <= 1e-13 * mag)
+        assert np.all(np.abs(g["mixed"][tsel] - ref).max(1) <= 2e-6 * mag)
