@@ -1240,16 +1240,21 @@ __global__ __launch_bounds__(kDotThreads) void k_mdot(int64_t n, int k, const do
     double acc = 0.0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kDotThreads) acc = fma(v[i], w[i], acc);
     acc = block_sum<kDotThreads>(acc, red);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + j] = acc;
+    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = acc;
   }
 }
 
-__global__ void k_mdot_reduce(int k, int nblk, const double* __restrict__ part, double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// out[j] = sum over the nblk block partials of product j (part: k rows of nblk), one
+// workgroup per product in a fixed order (strided per-thread sums, then the block tree)
+__global__ __launch_bounds__(kDotThreads) void k_mdot_reduce(int k, int nblk, const double* __restrict__ part,
+                                                             double* __restrict__ out) {
+  __shared__ double red[16];
+  const int j = blockIdx.x;
   if (j >= k) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * k + j];
-  out[j] = s;
+  for (int b = threadIdx.x; b < nblk; b += kDotThreads) s += part[(int64_t)j * nblk + b];
+  s = block_sum<kDotThreads>(s, red);
+  if (threadIdx.x == 0) out[j] = s;
 }
 
 __global__ void k_maxpy(int64_t n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
@@ -1744,7 +1749,7 @@ int mdot_blocks(int64_t n) {
 void launch_mdot(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* part,
                  double* out, int nblk) {
   hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(kDotThreads), 0, s, n, k, V, ldv, w, part);
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(nblocks(k, 64)), dim3(64), 0, s, k, nblk, part, out);
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(k), dim3(kDotThreads), 0, s, k, nblk, part, out);
 }
 
 void launch_maxpy(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w) {
