@@ -141,7 +141,7 @@ PEAK_FP64_TFLOPS = 78.6
 # WRITE_SIZE (KiB per dispatch, `bench.py --kernel-only --copy-calibration`), each scaled by what
 # the counter reads for an elementwise kernel that reads and writes 1 GiB (factors 2.0 and 1.0).
 # It holds for the kernel source it was measured on, identified by a hash of k_ksum_mixed's text.
-KSUM_TRAFFIC = {"src_sha256_16": "2824035918c698cf", "fetch_kib": 151667.8, "write_kib": 180000.0,
+KSUM_TRAFFIC = {"src_sha256_16": "ccfaa84067a6b8e9", "fetch_kib": 152367.9, "write_kib": 180000.0,
                 "fetch_factor": 2.0, "write_factor": 1.0}
 
 

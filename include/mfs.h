@@ -155,7 +155,9 @@ mfs_status mfs_get_pairs(const mfs_ctx* ctx, int64_t* n_pairs, int32_t* pairs);
  * n_clusters: host, written.  Each of the others is host memory or NULL: slot_body (P):
  * the disk at each position of the order; cl_start (n_clusters + 1): first position of
  * each cluster; centre (2 n_clusters): mean of its disks' centres; radius (n_clusters):
- * the largest |c_b - centre| + rho_b over its disks (rho_b: source ring radius). */
+ * the radius of the far test, at least the largest |c_b - centre| + rho_b over its disks
+ * (rho_b: source ring radius) and at least (3 max a + delta_c + that) / 4, so that a far
+ * cluster never holds a target's disk or one of its contact partners. */
 mfs_status mfs_get_clusters(const mfs_ctx* ctx, int32_t* n_clusters, int32_t* slot_body, int32_t* cl_start,
                             double* centre, double* radius);
 

@@ -135,8 +135,11 @@ Status validate_host(mfs_ctx* c, const double* centers, const double* radii, con
 // Morton curve over their centres (16 bits per axis, ties by index); the curve is cut into
 // quadtree cells holding about 16..64 disks, and each cell into runs of at most
 // kClMaxBodies disks and kClMaxSources sources: these runs are the clusters.  A cluster's
-// centre is the mean of its disks' centres and its radius the largest distance from there to
-// a source ring (|c_b - C| + rho_b).
+// centre is the mean of its disks' centres.  Its radius R, the one the far test uses (far:
+// beyond 4 R), is the largest distance from there to a source ring (|c_b - C| + rho_b), raised
+// where needed to (D + R) / 4 with D = 3 max(a) + delta_c: a node x of disk i lies within D of
+// every contact partner k of i (|x - c_k| <= a_i + a_i + a_k + delta_c), so a cluster holding
+// i or one of its partners is never far from x, whatever the cluster's size.
 void build_clusters(mfs_ctx* c) {
   const int P = c->P;
   double x0 = c->centers[0], x1 = x0, y0 = c->centers[1], y1 = y0;
@@ -184,6 +187,9 @@ void build_clusters(mfs_ctx* c) {
   }
   c->cl_start.push_back(P);
   c->ncl = (int)c->cl_start.size() - 1;
+  double amax = 0;
+  for (int i = 0; i < P; ++i) amax = std::max(amax, c->radii[i]);
+  const double reach = 3.0 * amax + c->prm.delta_c;
   c->cl_centre.assign(2 * c->ncl, 0.0);
   c->cl_radius.assign(c->ncl, 0.0);
   for (int q = 0; q < c->ncl; ++q) {
@@ -203,7 +209,7 @@ void build_clusters(mfs_ctx* c) {
     }
     c->cl_centre[2 * q] = cx;
     c->cl_centre[2 * q + 1] = cy;
-    c->cl_radius[q] = r;
+    c->cl_radius[q] = std::max(r, (reach + r) / 4.0);
   }
 }
 

@@ -528,14 +528,60 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
     ay[j] = 0.0;
     skip_init(sk[j], mode, body, cl_start[q0], nbr_off, nbr_list);
   }
+  // The workgroup's targets lie within rb of (bx, by) (their bounding box).  A cluster whose
+  // centre is beyond 4 R + rb from there is far for every thread: all take its expansion, with
+  // no per-thread test and no barrier.  The cluster radii are large enough that such a cluster
+  // holds no target's disk and no contact partner (cluster construction).
+  double bx, by, rb;
+  {
+    __shared__ double s_bb[4][KS_THREADS / 64];
+    double xl = x[0], xh = x[0], yl = y[0], yh = y[0];
+#pragma unroll
+    for (int j = 1; j < T; ++j) {
+      xl = fmin(xl, x[j]);
+      xh = fmax(xh, x[j]);
+      yl = fmin(yl, y[j]);
+      yh = fmax(yh, y[j]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      xl = fmin(xl, __shfl_xor(xl, off, 64));
+      xh = fmax(xh, __shfl_xor(xh, off, 64));
+      yl = fmin(yl, __shfl_xor(yl, off, 64));
+      yh = fmax(yh, __shfl_xor(yh, off, 64));
+    }
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      s_bb[0][wid] = xl;
+      s_bb[1][wid] = xh;
+      s_bb[2][wid] = yl;
+      s_bb[3][wid] = yh;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < KS_THREADS / 64; ++w) {
+      xl = fmin(xl, s_bb[0][w]);
+      xh = fmax(xh, s_bb[1][w]);
+      yl = fmin(yl, s_bb[2][w]);
+      yh = fmax(yh, s_bb[3][w]);
+    }
+    bx = 0.5 * (xl + xh);
+    by = 0.5 * (yl + yh);
+    rb = 0.5 * sqrt((xh - xl) * (xh - xl) + (yh - yl) * (yh - yl)) * (1.0 + 1e-9) + 1e-9;
+  }
   const float kHalfLn2 = 0.34657359027997264f;
   for (int cq = q0; cq < q1; ++cq) {
     const int kt = cl_start[cq], ke = cl_start[cq + 1];
     const int nb = ke - kt;
     bool cfar = cmp != nullptr;
+    bool bfar = false;
     if (cfar) {
       const double cx = ccent[2 * cq], cy = ccent[2 * cq + 1];
       const float rf = kClFar2 * crad2[cq];
+      {
+        const double dx = cx - bx, dy = cy - by;
+        const double thr = 4.0 * (1.0 + 1e-6) * sqrt((double)crad2[cq]) + rb;
+        bfar = dx * dx + dy * dy > thr * thr;
+      }
       float Zx[T], Zy[T], R2[T];
 #pragma unroll
       for (int j = 0; j < T; ++j) {
@@ -544,6 +590,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
         R2[j] = fmaf(Zx[j], Zx[j], Zy[j] * Zy[j]);
         cfar = cfar && R2[j] > rf && (mode == 0 || bt[j] < kt || bt[j] >= ke) && (mode != 2 || sk[j].next >= ke);
       }
+      cfar = cfar || bfar;
       if (cfar) {
         // Horner over the cluster's series: h1 over zeta (A_k/2k), h2 over conj(zeta) (B_k/2k),
         // h3 over conj(zeta) (conj A_k), h4 over conj(zeta) (conj D_k)
@@ -611,7 +658,8 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
       }
     }
     // every thread far: the tile is not needed.  The barrier also ends the reads of the
-    // previous tile before this one is staged.
+    // previous tile before this one is staged (bfar is uniform over the workgroup).
+    if (bfar) continue;
     if (__syncthreads_and(cfar ? 1 : 0)) continue;
     const int s0 = src_off[kt];
     const int ns = src_off[ke] - s0;
