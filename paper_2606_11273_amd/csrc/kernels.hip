@@ -430,9 +430,13 @@ __global__ __launch_bounds__(kBodyThreads) void k_cluster_moments(int ncl, const
 // ---------------------------------------------------------------------------
 // Step 2a: all-pairs Stokeslet sum u_t = sum_s S(x_t, y_s) sigma_s (eq. getall, eq. stokeslet2d).
 //
-// A workgroup owns KS_T * 256 consecutive targets and streams the sources of a
-// range of bodies (one split of blockIdx.y) through LDS in tiles of whole bodies.
+// A workgroup owns T * 256 consecutive targets.  The FP64 sum streams the sources of a
+// range of bodies (one split of blockIdx.y) through LDS in tiles of whole bodies; the FP32
+// sum walks a range of clusters of its disk order, one cluster per tile, and skips the
+// tile of a cluster that is far from all its targets (two-level far field, below).
 //   u = 1/(4 pi mu) [ sum (d.sigma / r^2) d  -  (ln 2 / 2) sum log2(r^2) sigma ].
+// A disk far from every target of a thread (beyond 7 ring radii) is summed from its
+// multipole expansion (k_gather_project, k_moments64).
 // Mixed form: per (target, source disk) the offset D of the target from the disk
 // centre is formed in FP64 and rounded once; the pair terms are evaluated in FP32
 // on body-relative coordinates (v_rcp_f32 for 1/r^2, v_log_f32 for the log) and
@@ -448,7 +452,8 @@ __global__ __launch_bounds__(kBodyThreads) void k_cluster_moments(int ncl, const
 // and those errors add up over all disks.
 constexpr int KS_THREADS = 256;
 constexpr int KS_TILE = 1024;   // sources per LDS tile (16 KB of float4)
-constexpr int KS_MAXB = 64;     // bodies per LDS tile
+constexpr int KS_MAXB = 64;     // bodies per LDS tile (a cluster is one tile)
+static_assert(kClMaxBodies <= KS_MAXB && kClMaxSources <= KS_TILE, "a cluster must fit one LDS tile");
 
 // Skip modes: 0 = every source, 1 = skip the target's own disk, 2 = skip the own disk
 // and its contact partners (nbr_off/nbr_list: sorted partner list per disk).  A
