@@ -9,7 +9,11 @@
  *   mfs_precompute_pairs  per-close-pair compressed corrections A, E (Sec. 3.2-3.4, 4.3-4.4, 5;
  *                         Alg. 2 precompute loop);
  *   mfs_apply             the preconditioned matrix-vector product T mu (Alg. 3);
- *   mfs_gmres_solve       RHS -> GMRES -> post-processing (Alg. 2; Sec. 4.4 for mobility).
+ *   mfs_gmres_solve       RHS -> GMRES -> post-processing (Alg. 2; Sec. 4.4 for mobility);
+ *   mfs_flow_eval         the flow at any points from a solve's density (Alg. 2 flowEval,
+ *                         Sec. 3.3), mfs_boundary_residual its relative boundary error
+ *                         (Sec. 6.1);
+ *   mfs_server_*          many independent solves sharing one device.
  *
  * Conventions shared by every call:
  *  - Every call returns mfs_status.  On error nothing is written to the outputs,
