@@ -2,16 +2,16 @@
 
 Readings taken here (the paper is silent or ambiguous):
 
-* Q3  every equispaced grid (coarse sources, coarse nodes, fine proxies, fine
-      equispaced nodes) starts at angle 0 in the global frame; grids do not
-      rotate with the pair (Sec. 5, remark on combining fine sources).
-* Q13 the ellipse focus a is the image accumulation radius R_acc(delta), so the
-      segment [0, R_acc] between the foci is shielded (Sec. 5).
-* Q15 a_ell * N_ell Moebius nodes are added for every contact pair, densest
-      toward the neighbour; per disk M_f = ceil(a_f N_fp) + a_ell N_ell.
-* Q16 the peanut is two convex arcs of the disk boundaries (far sides) and two
-      concave arcs of the unit circle rolled around the pair; M_p nodes uniform
-      in arc length starting at the far point of body i, counter-clockwise.
+* every equispaced grid (coarse sources, coarse nodes, fine proxies, fine
+  equispaced nodes) starts at angle 0 in the global frame; grids do not
+  rotate with the pair (Sec. 5, remark on combining fine sources).
+* the ellipse focus a is the image accumulation radius R_acc(delta), so the
+  segment [0, R_acc] between the foci is shielded (Sec. 5).
+* a_ell * N_ell Moebius nodes are added for every contact pair, densest
+  toward the neighbour; per disk M_f = ceil(a_f N_fp) + a_ell N_ell.
+* the peanut is two convex arcs of the disk boundaries (far sides) and two
+  concave arcs of the unit circle rolled around the pair; M_p nodes uniform
+  in arc length starting at the far point of body i, counter-clockwise.
 """
 
 from __future__ import annotations
@@ -96,14 +96,15 @@ def _pair_frame(ci, ck):
 def limit_point(a1, a2, d):
     """Limit point x_1 (distance from the centre of disk 1 toward disk 2) of the coaxal system of
     two circles of radii a1, a2 at centre distance d: the common fixed point, inside disk 1, of
-    the inversions in both circles, where the images of a source accumulate (Sec. 5; unequal
-    radii by the survey's reading Q23).  For a1 = a2 = 1 it is R_acc(d - 2)."""
+    the inversions in both circles, where the images of a source accumulate (Sec. 5; the paper
+    treats unit disks only, and this point is the reading taken for unequal radii).  For
+    a1 = a2 = 1 it is R_acc(d - 2)."""
     b = d * d + a1 * a1 - a2 * a2
     return (b - math.sqrt(b * b - 4.0 * d * d * a1 * a1)) / (2.0 * d)
 
 
 def fine_count(radius, prm):
-    """Fine proxy count of a disk: N_fp scales with the radius (150 at radius 1; reading Q23)."""
+    """Fine proxy count of a disk: N_fp scales with the radius (150 at radius 1; a reading of the paper)."""
     return int(round(prm.n_fp * radius))
 
 
@@ -149,7 +150,7 @@ def fine_nodes(ci, ck, prm, ai=1.0, ak=1.0):
     """Fine collocation nodes of the pair (Sec. 5): per disk ceil(a_f N_fp(a)) equispaced
     nodes plus a_ell N_ell Moebius-mapped nodes theta~ = pi + arg((e^{it} + r)/(1 + r e^{it})),
     t = 2 pi j / M_ell, on the disk's boundary, placed so that theta~ = pi faces the
-    neighbour (Q15).  Returns (X_i, X_k)."""
+    neighbour (a reading of the paper).  Returns (X_i, X_k)."""
     ci, ck, d, e = _pair_frame(ci, ck)
     phi = math.atan2(e[1], e[0])
     m_ell = int(prm.a_ell * prm.n_ell)
@@ -165,7 +166,7 @@ def fine_nodes(ci, ck, prm, ai=1.0, ak=1.0):
 
 
 def peanut_nodes(ci, ck, m_p, ai=1.0, ak=1.0, rho=1.0):
-    """M_p nodes uniform in arc length on the peanut of the pair (Sec. 3.3, Q16; unequal radii Q23).
+    """M_p nodes uniform in arc length on the peanut of the pair (Sec. 3.3; unequal radii: a rolling unit circle).
 
     The peanut is the outline of the two disks with the concave gaps filled by a circle of
     radius rho rolled around the pair (rho = 1, the smallest disk).  With e the unit axis

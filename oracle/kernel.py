@@ -3,7 +3,7 @@
 eq. stokeslet2d (Sec. 3): S(x, y) = 1/(4 pi mu) [ -log|x - y| I + (x - y)(x - y)^T / |x - y|^2 ].
 eq. stokes_sum / eq. stokes_operator: u(x) = sum over sources of S(x, y_j) lambda_j.
 
-2-vectors are stacked per point, (x, y) interleaved (reading Q4): row 2m + a of
+2-vectors are stacked per point, (x, y) interleaved (a reading of the paper): row 2m + a of
 S(X, Y) is component a at target m, column 2n + b is component b of source n.
 """
 

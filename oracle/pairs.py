@@ -1,7 +1,7 @@
 """Per-pair precompute of the two-body correction (oracle).
 
 For a near-contact pair (i, k) with coarse one-body data of each disk (unit disks as
-in the paper; radius 1.4 disks by reading Q23), following Sec. 3.2-3.4 (resistance)
+in the paper; radius 1.4 disks by the reading taken for unequal radii), following Sec. 3.2-3.4 (resistance)
 and Sec. 4.3-4.4 (mobility):
 
 * X = [[0, Q^(k,i)], [Q^(i,k), 0]]: rows are the fine nodes of body i then body k,
@@ -11,21 +11,21 @@ and Sec. 4.3-4.4 (mobility):
 * F = S(fine nodes, fine sources) (resistance), or, for mobility,
   S(fine nodes, fine sources)(I - calL) + blockdiag(calB_i calK_i^T, calB_k calK_k^T)
   with calL the blockwise rigid projector of the fine sources (eq. chi_mob) and
-  calB the fine-node rigid map (reading Q12: the text defines the fine counterpart).
+  calB the fine-node rigid map (a reading: the text defines the fine counterpart).
 * C = S(peanut, Y^(i) u Y^(k)) [(I - L^pair)],  D = S(peanut, fine sources) [(I - calL)]
   (eq. peanut / eq. peanut_mob).
-* G = F^+ X with truncation 1e-11 (reading Q17), applied as V Sigma^+ (U^T X).
-* A = -C^+ D G with truncation 1e-14 (eq. Amat), right to left (reading Q18).
+* G = F^+ X with truncation 1e-11 (a reading of the paper), applied as V Sigma^+ (U^T X).
+* A = -C^+ D G with truncation 1e-14 (eq. Amat), right to left (a reading of the paper).
 * E: force/torque extraction (resistance) E_ft = -blockdiag(calK_i^T, calK_k^T) G,
   since beta = -F^+ X lambda_bar and f = K^T lambda_bar + calK^T beta (eq. force_syst);
   velocity extraction (mobility) E_v = +blockdiag(calK^T) G, since
-  [v; omega] = -calK^T beta - K^T lambda_bar (eq. rbm2).  (Reading Q10: eq. force_ext
+  [v; omega] = -calK^T beta - K^T lambda_bar (eq. rbm2).  (A reading: eq. force_ext
   as printed lacks the transpose and the sign.)
 * W: the step-2b field correction of Alg. 3 for this pair, precombined,
   W = -([[P, S^(ik)], [S^(ki), P]] Pi A + [[0, S^(ik) Pi], [S^(ki) Pi, 0]]) with
-  Pi = I - L for mobility (reading Q9) and Pi = I for resistance, and with the
+  Pi = I - L for mobility (a reading of the paper) and Pi = I for resistance, and with the
   H blocks of step 2b read as the one-body basis of the neighbour evaluated at
-  the coarse nodes (reading Q8): H^(k,i) mu^(k) = S^(ik) Pi lambda_bar^(k).
+  the coarse nodes (a reading of the paper): H^(k,i) mu^(k) = S^(ik) Pi lambda_bar^(k).
 """
 
 from __future__ import annotations
@@ -41,7 +41,7 @@ from .onebody import apply_pinv, truncated_svd
 def pair_matrices(ci, ck, ob, prm, keep=False, ob_k=None):
     """Precompute A, E and W for the pair (i, k): A (2N_i + 2N_k square), E (6 x (2N_i + 2N_k)),
     W ((2M_i + 2M_k) x (2N_i + 2N_k)).  ob is disk i's one-body data, ob_k disk k's (default: the
-    same class).  Unequal radii follow reading Q23 (limit points, fine counts scaled with the
+    same class).  Unequal radii follow the reading taken for unequal radii (limit points, fine counts scaled with the
     radius, a rolling unit circle for the peanut)."""
     ob_i = ob
     ob_k = ob if ob_k is None else ob_k

@@ -1,7 +1,7 @@
 """The global preconditioned system, its matvec, RHS, post-processing and GMRES (oracle).
 
 The unknown is mu = {mu^(i)}: coarse collocation data, 2 M_c values per body,
-per node (x, y) interleaved, body-major (reading Q4).
+per node (x, y) interleaved, body-major (a reading of the paper).
 
 ``matvec`` is Alg. 3 step by step (with the mobility projections of Sec. 4.4):
  1a  lambda_bar^(i) = P^+ mu^(i)  (mobility: S_L^+ mu^(i)),  lambda = lambda_bar
@@ -11,8 +11,8 @@ per node (x, y) interleaved, body-major (reading Q4).
  2b  for each pair: u_pair -= [[P, S^(ik)], [S^(ki), P]] Pi lambda_tilde^c
                               + [[0, H^(k,i)], [H^(i,k), 0]] [mu^(i); mu^(k)]
      identity fix: u^(i) += mu^(i) - P Pi lambda_bar^(i)     (eq. onesub)
-where Pi = I - L for mobility (reading Q9) and Pi = I for resistance, and
-H^(k,i) mu^(k) = S^(ik) Pi lambda_bar^(k) (reading Q8).
+where Pi = I - L for mobility (a reading of the paper) and Pi = I for resistance, and
+H^(k,i) mu^(k) = S^(ik) Pi lambda_bar^(k) (a reading of the paper).
 
 ``matvec_masked`` is the closed form these steps collapse to in exact arithmetic:
   (T mu)^(i) = mu^(i) + sum_{k not i, k not a neighbour of i} S^(ik) Pi lambda_bar^(k)
@@ -21,14 +21,14 @@ an independent assembly used to pin the bookkeeping of step 2b.
 
 RHS (mobility, Sec. 4.1-4.2): lambda_0^(i) = K (K^T K)^{-1} [f; t]^(i) (so that
 K^T lambda_0 = [f; t]), u_0 = S lambda_0 summed over all bodies with self
-(eq. u0_def), b = -u_0 (reading Q20).  Resistance: b^(i) = B [v; omega]^(i)
+(eq. u0_def), b = -u_0 (a reading of the paper).  Resistance: b^(i) = B [v; omega]^(i)
 (eq. rigidbc at the coarse nodes).
 
 Post-processing: mobility [v; omega]^(i) = -K^T lambda_bar^(i) + sum_{c contains i}
-(E_v^c x_c)_i (eq. rbm_ansatz, eq. rbm2, reading Q21); resistance
+(E_v^c x_c)_i (eq. rbm_ansatz, eq. rbm2, a reading of the paper); resistance
 [f; t]^(i) = K^T lambda_bar^(i) + sum_c (E_ft^c x_c)_i (eq. two_force, Alg. 2).
 Forces are the sums of Stokeslet strengths, i.e. the force exerted on the fluid
-(reading Q1).
+(a reading of the paper).
 """
 
 from __future__ import annotations
@@ -216,7 +216,7 @@ class System:
 
 
 def gmres(matvec, b, tol, maxit=500, x0=None, callback=None):
-    """Unrestarted GMRES (modified Gram-Schmidt Arnoldi, Givens rotations), reading Q19.
+    """Unrestarted GMRES (modified Gram-Schmidt Arnoldi, Givens rotations; the paper does not fix the variant).
 
     Stops when the Givens residual estimate |g_{k+1}| <= tol * |b|.  Returns
     (x, info) with info = dict(iters, resid (estimates), true_resid).

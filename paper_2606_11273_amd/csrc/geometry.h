@@ -31,10 +31,10 @@ struct FineParams {
 
 // Limit point x_1 (distance from the centre of disk 1 toward disk 2) of two circles of radii
 // a1, a2 at centre distance d: the common fixed point of the inversions in both circles
-// (Sec. 5; unequal radii by reading Q23).  R_acc(d - 2) for unit disks.
+// (Sec. 5; unequal radii by the reading taken for unequal radii).  R_acc(d - 2) for unit disks.
 double limit_point(double a1, double a2, double d);
 
-// Fine proxy count of a disk: n_fp scaled with the radius (reading Q23).
+// Fine proxy count of a disk: n_fp scaled with the radius (a reading of the paper).
 int fine_count(double radius, const FineParams& fp);
 
 // Fine source set of a pair (radii ai, ak): proxies on radius a R_f(N_fp(a)) about each

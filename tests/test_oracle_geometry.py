@@ -132,7 +132,7 @@ def test_contacts_brute_force():
     assert [tuple(p) for p in pr] == ref
 
 
-# -- unequal radii (the bidisperse workload; reading Q23) ---------------------------------------
+# -- unequal radii (the bidisperse workload; a reading of the paper) ---------------------------------------
 
 def _invert_r(p, c, r):
     v = p - c

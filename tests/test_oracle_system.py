@@ -176,7 +176,7 @@ def test_peanut_compression_reproduces_far_field():
         assert np.max(np.abs(uf - uc)) < 1e-7 * np.max(np.abs(uf))
 
 
-# -- unequal radii (the bidisperse workload; reading Q23) ---------------------------------------
+# -- unequal radii (the bidisperse workload; a reading of the paper) ---------------------------------------
 
 def _unequal_pair(delta, a=(1.0, 1.4), ang=0.7, c0=(0.1, 0.2)):
     c0 = np.array(c0)
