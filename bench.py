@@ -51,40 +51,14 @@ MP_FAR2 = 49.0              # a disk is far for a target beyond 7 ring radii
 KSUM_T = 2                  # targets per thread of both kernel sums (their default)
 
 
-def ksum_work(centers, radii, n_src, r_src, X, threads_T=KSUM_T, block=256):
-    """Work of one kernel-sum launch (FP32 or FP64: the same split): direct pair evaluations
-    and far-disk expansions.
-
-    A thread holds T targets (block apart within a workgroup of block * T targets); a disk is
-    evaluated through its expansion when it is far from all of them (|x - c|^2 > 49 rho^2),
-    else directly over its sources for all of them (skipped disks included: their terms are
-    computed and not accumulated).  The last workgroup's missing targets are not counted."""
-    import numpy as np
-    from scipy.spatial import cKDTree
-    rho = np.asarray(r_src, dtype=np.float64) * np.asarray(radii, dtype=np.float64)
-    tree = cKDTree(centers)
-    lists = tree.query_ball_point(X, r=float(np.sqrt(MP_FAR2) * rho.max()))
-    cnt = np.array([len(l) for l in lists])
-    t_idx = np.repeat(np.arange(X.shape[0]), cnt)
-    k_idx = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists])
-    d = X[t_idx] - centers[k_idx]
-    keep = np.einsum("ij,ij->i", d, d) <= MP_FAR2 * rho[k_idx] ** 2
-    t_idx, k_idx = t_idx[keep], k_idx[keep]
-    per_blk = block * threads_T
-    thread = (t_idx // per_blk) * block + (t_idx % block)
-    n_threads = (X.shape[0] + per_blk - 1) // per_blk * block
-    P = centers.shape[0]
-    uniq = np.unique(thread.astype(np.int64) * P + k_idx)
-    near_k = uniq % P
-    pairs = threads_T * int(np.asarray(n_src, dtype=np.int64)[near_k].sum())
-    exps = threads_T * (n_threads * P - uniq.size)
-    return pairs, exps
 # One evaluation of a far cluster's expansion in the FP32 kernel sum (order 12 about the
 # cluster's centre): four complex Horner series, 32 flops per step over 11 steps, plus about
 # 64 for zeta, the first terms, the log term and the combination
 CL_ORDER = 12
 FLOP_PER_CLUSTER_EXPANSION = 32 * (CL_ORDER - 1) + 64
 CL_FAR2 = 16.0              # a cluster is far for a target beyond 4 cluster radii
+CL64_ORDER = 26             # the FP64 kernel sum's cluster expansions (same clusters and far test)
+FLOP_PER_CLUSTER_EXPANSION64 = 32 * (CL64_ORDER - 1) + 64
 
 
 def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, threads_T=KSUM_T, block=256):
@@ -155,7 +129,8 @@ def ksum_traffic_bytes():
     body = src[i:src.index("\n}\n", i) + 3]
     # the expansions' orders and radii live outside the kernel's text
     hdr = open(os.path.join(ROOT, "paper_2606_11273_amd", "csrc", "internal.h")).read()
-    body += "".join(l for l in (hdr + src).splitlines(True) if "constexpr" in l and ("kMp" in l or "kCl" in l) and "kMp64" not in l)
+    body += "".join(l for l in (hdr + src).splitlines(True) if "constexpr" in l and ("kMp" in l or "kCl" in l)
+                   and "kMp64" not in l and "kCl64" not in l)
     if hashlib.sha256(body.encode()).hexdigest()[:16] != KSUM_TRAFFIC["src_sha256_16"]:
         return None
     t = KSUM_TRAFFIC
@@ -354,7 +329,7 @@ def main():
     # Stokeslet pairs of the direct sum the launch stands for; the FP32 kernel evaluates far
     # clusters and far disks through their expansions, so its algorithmic flops are the direct
     # pairs it does compute (near disks) times 20 plus its expansion evaluations times their
-    # flops; the FP64 kernel splits near and far disks (no clusters), with order-18 expansions
+    # flops; the FP64 kernel takes the same clusters and disks, with order-26 and order-18 expansions
     pr = nv.mfs_get_pairs(ctx)
     skipped = ns.astype(np.int64).copy()
     np.add.at(skipped, pr[:, 0], ns[pr[:, 1]])
@@ -364,10 +339,9 @@ def main():
                                                  np.sin(2 * np.pi * np.arange(nc[i]) / nc[i])], axis=1)
                          for i in range(P)])
     t0 = time.perf_counter()
-    near_pairs, expansions = ksum_work(c, a, ns, rs, Xt)
     pairs32, disk_exps, cl_exps = ksum_work_clusters(c, a, ns, rs, Xt, nv.mfs_get_clusters(ctx))
-    log(f"kernel-sum work: FP32 {pairs32} direct pairs, {disk_exps} disk and {cl_exps} cluster expansions; "
-        f"FP64 {near_pairs} direct pairs, {expansions} expansions ({time.perf_counter() - t0:.1f}s)")
+    log(f"kernel-sum work (both precisions): {pairs32} direct pairs, {disk_exps} disk and {cl_exps} cluster "
+        f"expansions ({time.perf_counter() - t0:.1f}s)")
     flops_launch = (pairs32 * FLOP_PER_PAIR + disk_exps * FLOP_PER_EXPANSION
                     + cl_exps * FLOP_PER_CLUSTER_EXPANSION)
     achieved = flops_launch / (ks["mixed"] * 1e-3) / 1e12
@@ -381,7 +355,8 @@ def main():
                     pair_evals_per_launch=evals_launch,
                     pair_evals_per_s=round(evals_launch / (ks["mixed"] * 1e-3), 1),
                     fp64_kernel_ms_per_launch=round(ks["fp64"], 2),
-                    fp64_kernel_tflops=round((near_pairs * FLOP_PER_PAIR + expansions * FLOP_PER_EXPANSION64)
+                    fp64_kernel_tflops=round((pairs32 * FLOP_PER_PAIR + disk_exps * FLOP_PER_EXPANSION64
+                                              + cl_exps * FLOP_PER_CLUSTER_EXPANSION64)
                                              / (ks["fp64"] * 1e-3) / 1e12, 2),
                     fp64_peak=PEAK_FP64_TFLOPS)
 

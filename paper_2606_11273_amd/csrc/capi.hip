@@ -83,7 +83,7 @@ void free_all(mfs_ctx* c) {
                   c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
                   c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf, c->d_mp,
                   c->d_mpm,     c->d_mp64,    c->d_mp64m,   c->d_fmp64, c->d_slot_of, c->d_slot_body, c->d_ssrc_off, c->d_nbr_slot,
-                  c->d_cl_start, c->d_scent,  c->d_ccent,   c->d_crad2, c->d_cmp,  c->d_cmpm};
+                  c->d_cl_start, c->d_scent,  c->d_ccent,   c->d_crad2, c->d_cmp,  c->d_cmpm, c->d_crad64, c->d_body_cl};
   for (void* p : ptrs)
     if (p) dev_free(c, p);
   for (const PairSet& ps : c->ps)
@@ -330,6 +330,13 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   if ((st = upload(c, &c->d_scent, scent, s)).code) return st;
   if ((st = upload(c, &c->d_ccent, c->cl_centre, s)).code) return st;
   if ((st = upload(c, &c->d_crad2, crad2, s)).code) return st;
+  if ((st = upload(c, &c->d_crad64, c->cl_radius, s)).code) return st;
+  {
+    std::vector<int32_t> body_cl(P);
+    for (int q = 0; q < c->ncl; ++q)
+      for (int sl = c->cl_start[q]; sl < c->cl_start[q + 1]; ++sl) body_cl[c->slot_body[sl]] = q;
+    if ((st = upload(c, &c->d_body_cl, body_cl, s)).code) return st;
+  }
   if ((st = dalloc(c, &c->d_lam_bar, 2 * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_ltil, c->xoff[C])).code) return st;
   if ((st = dalloc(c, &c->d_u, 2 * c->Nt)).code) return st;
@@ -343,7 +350,7 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   if ((st = dalloc(c, &c->d_cmp, (size_t)c->ncl * kClCoefPerCluster)).code) return st;
   if ((st = dalloc(c, &c->d_sig64, 2 * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_src64, c->Ns)).code) return st;
-  if ((st = dalloc(c, &c->d_mp64, (size_t)P * kMp64CoefPerDisk)).code) return st;
+  if ((st = dalloc(c, &c->d_mp64, (size_t)mp64_record(c))).code) return st;
   MFS_HIP(hipStreamSynchronize(s));
   return Status{};
 }
@@ -399,7 +406,7 @@ Status ensure_stacked(mfs_ctx* c, int R) {
   if ((st = dalloc(c, &c->d_mpm, (size_t)R * c->P * kMpCoefPerDisk)).code) return st;
   if ((st = dalloc(c, &c->d_cmpm, (size_t)R * c->ncl * kClCoefPerCluster)).code) return st;
   if ((st = dalloc(c, &c->d_src64m, (size_t)R * c->Ns)).code) return st;
-  if ((st = dalloc(c, &c->d_mp64m, (size_t)R * c->P * kMp64CoefPerDisk)).code) return st;
+  if ((st = dalloc(c, &c->d_mp64m, (size_t)R * mp64_record(c))).code) return st;
   c->rhs_cap = R;
   return Status{};
 }
@@ -435,7 +442,7 @@ Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, do
                                mixed ? c->d_cmpm + (int64_t)r * c->ncl * kClCoefPerCluster : nullptr);
     if (!mixed)
       for (int r = 0; r < Rc; ++r)
-        launch_moments64(c, c->d_src64m + r * c->Ns, c->d_mp64m + (int64_t)r * c->P * kMp64CoefPerDisk);
+        launch_moments64(c, c->d_src64m + r * c->Ns, c->d_mp64m + (int64_t)r * mp64_record(c));
     const bool ks = launch_kernel_sum_rhs(c, mixed, 2, Rc, c->d_u_m, 1.0 / (4.0 * kPiD * c->prm.mu));
     if ((st = check_kernel_sum(c, ks)).code) return st;
     c->cnt_pair_evals += (int64_t)Rc * c->evals_skip;

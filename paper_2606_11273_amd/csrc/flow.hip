@@ -72,8 +72,8 @@ Status flow_eval(mfs_ctx* c, int prob, const double* mu, const double* given, in
   Status st;
   int64_t fsrc_cap = c->d_fsrc ? c->Ns : 0;
   if ((st = grow(c, &c->d_fsrc, &fsrc_cap, c->Ns)).code) return st;
-  int64_t fmp_cap = c->d_fmp64 ? (int64_t)c->P * kMp64CoefPerDisk : 0;
-  if ((st = grow(c, &c->d_fmp64, &fmp_cap, (int64_t)c->P * kMp64CoefPerDisk)).code) return st;
+  int64_t fmp_cap = c->d_fmp64 ? mp64_record(c) : 0;
+  if ((st = grow(c, &c->d_fmp64, &fmp_cap, mp64_record(c))).code) return st;
   if (C > 0) {
     int64_t ptil_cap = c->d_ptil ? c->xoff[C] : 0;
     if ((st = grow(c, &c->d_ptil, &ptil_cap, c->xoff[C])).code) return st;

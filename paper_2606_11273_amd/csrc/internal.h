@@ -26,6 +26,9 @@ constexpr int kClOrder = 12;
 constexpr int kClCoefPerCluster = 4 * kClOrder + 2;   // FP32 complex coefficients per cluster
 constexpr int kClMaxBodies = 16;
 constexpr int kClMaxSources = 1024;                   // sources per cluster (one LDS tile)
+// The FP64 kernel sum's cluster expansions (same clusters and far test, order for FP64 rounding)
+constexpr int kCl64Order = 26;
+constexpr int kCl64CoefPerCluster = 4 * kCl64Order + 2;   // FP64 complex coefficients per cluster
 constexpr double kPiD = 3.14159265358979323846;
 
 struct Status {
@@ -125,6 +128,8 @@ struct mfs_ctx {
   double* d_scent = nullptr;     // P x 2 centres in slot order
   double* d_ccent = nullptr;     // ncl x 2 cluster centres
   float* d_crad2 = nullptr;      // ncl squared cluster radii
+  double* d_crad64 = nullptr;    // ncl cluster radii (FP64 sum)
+  int32_t* d_body_cl = nullptr;  // P: cluster of each disk
 
   // work vectors
   double *d_lam_bar = nullptr, *d_ltil = nullptr, *d_sig64 = nullptr, *d_u = nullptr, *d_corr = nullptr;
@@ -133,7 +138,7 @@ struct mfs_ctx {
   float4* d_bdat = nullptr;      // per disk: (net strength x, y, ring radius^2, W) for the FP32 sum
   float2* d_mp = nullptr;        // per disk: far-field expansion coefficients for the FP32 sum
   float2* d_cmp = nullptr;       // per cluster: its expansion coefficients for the FP32 sum
-  double2* d_mp64 = nullptr;     // per disk: far-field expansion coefficients of d_src64 for the FP64 sum
+  double2* d_mp64 = nullptr;     // far-field coefficients of d_src64 for the FP64 sum (mp64_record)
   double4* d_src64 = nullptr;    // per source: (y_x, y_y, sigma_x, sigma_y)
   int64_t upart_cap = 0;
 
@@ -166,6 +171,12 @@ struct mfs_ctx {
 };
 
 namespace mfs {
+
+// Length (double2) of one FP64 far-field record: kMp64CoefPerDisk per disk, then
+// kCl64CoefPerCluster per cluster
+inline int64_t mp64_record(const mfs_ctx* c) {
+  return (int64_t)c->P * kMp64CoefPerDisk + (int64_t)c->ncl * kCl64CoefPerCluster;
+}
 
 // Device memory of a context: the caller's allocator when mfs_setup_ex gave one, else
 // hipMalloc / hipFree (capi.hip).
@@ -201,7 +212,8 @@ void launch_post(mfs_ctx* c, int prob, const double* lam_bar, double* out3);
 void launch_add_rhs_sources(mfs_ctx* c, const double* given, double4* src64);
 bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, const double2* mp64, int64_t n_pts,
                               const double* pts, const int32_t* body, double* u);
-// FP64 far-field coefficients (kMp64CoefPerDisk per disk) of a packed FP64 source array
+// FP64 far-field coefficients of a packed FP64 source array: per disk, then per cluster
+// (one mp64_record)
 void launch_moments64(mfs_ctx* c, const double4* src64, double2* mp64);
 void launch_fine_strengths(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, double* ptil,
                            double* sigf);

@@ -900,6 +900,74 @@ __global__ __launch_bounds__(kBodyThreads) void k_moments64(int P, const int* __
 }
 
 // FP64 form of the same sum, absolute coordinates (ln_f64, rcp_f64 above).
+// FP64 expansion of each cluster about its centre for the FP64 kernel sum: the moments of
+// k_cluster_moments (A_k, B_k, D_k of the sources' offsets w = y - C) from a packed FP64 source
+// array (absolute positions, body order), to order kCl64Order.  One workgroup per cluster,
+// thread e forms the order-e moments over the cluster's sources in slot order (w^e by binary
+// powering).  Record (after the per-disk records): A_k/(2k), B_k/(2k) (k = 1..p), conj(A_k),
+// conj(D_k) (k = 0..p).  Truncation at theta <= 1/4: below sum |sigma| 4^-27 / (3/4) = 7e-17
+// sum |sigma|.
+constexpr int kCl64Coef = kCl64CoefPerCluster;
+
+__global__ __launch_bounds__(64) void k_cluster_moments64(int ncl, const int* __restrict__ cl_start,
+                                                          const int* __restrict__ slot_body,
+                                                          const int* __restrict__ src_off,
+                                                          const double* __restrict__ ccent,
+                                                          const double4* __restrict__ src,
+                                                          double2* __restrict__ cmp) {
+  const int q = blockIdx.x;
+  const int e = threadIdx.x;
+  if (q >= ncl || e > kCl64Order) return;
+  const double Cx = ccent[2 * q], Cy = ccent[2 * q + 1];
+  double Ar = 0, Ai = 0, Br = 0, Bi = 0, Dr = 0, Di = 0;
+  for (int sl = cl_start[q]; sl < cl_start[q + 1]; ++sl) {
+    const int b = slot_body[sl];
+    for (int j = src_off[b]; j < src_off[b + 1]; ++j) {
+      const double4 v = src[j];
+      const double wx = v.x - Cx, wy = v.y - Cy;
+      double pr = 1.0, pi = 0.0, br = wx, bi = wy;   // w^e
+      for (int k = e; k; k >>= 1) {
+        if (k & 1) {
+          const double tr = pr * br - pi * bi;
+          pi = pr * bi + pi * br;
+          pr = tr;
+        }
+        const double ur = br * br - bi * bi;
+        bi = 2.0 * br * bi;
+        br = ur;
+      }
+      const double sr = v.z * pr - v.w * pi, si = v.z * pi + v.w * pr;   // sigma w^e
+      Ar += sr;
+      Ai += si;
+      Br += v.z * pr + v.w * pi;   // sigma conj(w^e)
+      Bi += v.w * pr - v.z * pi;
+      Dr += wx * sr + wy * si;     // conj(w) sigma w^e
+      Di += wx * si - wy * sr;
+    }
+  }
+  double2* o = cmp + (int64_t)q * kCl64Coef;
+  if (e >= 1) {
+    o[e - 1] = make_double2(Ar / (2 * e), Ai / (2 * e));
+    o[kCl64Order + e - 1] = make_double2(Br / (2 * e), Bi / (2 * e));
+  }
+  o[2 * kCl64Order + e] = make_double2(Ar, -Ai);
+  o[3 * kCl64Order + 1 + e] = make_double2(Dr, -Di);
+}
+
+// Far test of a cluster (centre cx, cy; lim = 16 R^2) for every target of a thread, without
+// contraction, so that the cluster pass and the disk pass of k_ksum_fp64 decide alike
+template <int T>
+__device__ __forceinline__ bool cl_far64(const double (&x)[T], const double (&y)[T], double cx, double cy,
+                                         double lim) {
+  bool far = true;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const double dx = __dsub_rn(x[j], cx), dy = __dsub_rn(y[j], cy);
+    far = far && __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) > lim;
+  }
+  return far;
+}
+
 template <int T>
 __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __restrict__ src_off,
                                                           const double4* __restrict__ src, int64_t Nt,
@@ -909,7 +977,11 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
                                                           const int* __restrict__ nbr_list, double scale,
                                                           double* __restrict__ out,
                                                           const double* __restrict__ centers,
-                                                          const double2* __restrict__ mp64) {
+                                                          const double2* __restrict__ mp64, int ncl,
+                                                          const int* __restrict__ body_cl,
+                                                          const double* __restrict__ ccent,
+                                                          const double* __restrict__ crad,
+                                                          const double2* __restrict__ cmp64) {
   __shared__ double4 s_src[KS_TILE / 2];
   __shared__ int s_off[KS_MAXB + 1];
   const int split = blockIdx.y;
@@ -930,6 +1002,79 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
     ay[j] = 0.0;
     skip_init(sk[j], mode, bt[j], kb0, nbr_off, nbr_list);
   }
+  if (cmp64) {
+    // clusters far from every target of this thread (this split's share of the clusters):
+    // their FP64 expansions; the disk pass below skips their disks.  A far cluster holds no
+    // target's disk or contact partner (cluster radii), so no skipped source is in it.
+    const int cps = (ncl + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int c0 = min(ncl, split * cps), c1 = min(ncl, c0 + cps);
+    for (int q = c0; q < c1; ++q) {
+      const double cx = ccent[2 * q], cy = ccent[2 * q + 1];
+      if (!cl_far64<T>(x, y, cx, cy, __dmul_rn(16.0, __dmul_rn(crad[q], crad[q])))) continue;
+      const double2* cf = cmp64 + (int64_t)q * kCl64Coef;
+      double Zx[T], Zy[T], R2[T], zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T], h4r[T], h4i[T];
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        Zx[j] = x[j] - cx;
+        Zy[j] = y[j] - cy;
+        R2[j] = fma(Zx[j], Zx[j], Zy[j] * Zy[j]);
+        const double ir2 = rcp_f64(R2[j]);
+        zr[j] = Zx[j] * ir2;
+        zi[j] = Zy[j] * ir2;
+        h1r[j] = cf[kCl64Order - 1].x;
+        h1i[j] = cf[kCl64Order - 1].y;
+        h2r[j] = cf[2 * kCl64Order - 1].x;
+        h2i[j] = cf[2 * kCl64Order - 1].y;
+        h3r[j] = cf[3 * kCl64Order].x;
+        h3i[j] = cf[3 * kCl64Order].y;
+        h4r[j] = cf[4 * kCl64Order + 1].x;
+        h4i[j] = cf[4 * kCl64Order + 1].y;
+      }
+#pragma unroll 2
+      for (int m = kCl64Order - 1; m >= 1; --m) {
+        const double2 a = cf[m - 1], bq = cf[kCl64Order + m - 1], g = cf[2 * kCl64Order + m],
+                      e = cf[3 * kCl64Order + 1 + m];
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const double t1r = fma(zr[j], h1r[j], fma(zi[j], h1i[j], a.x));
+          const double t1i = fma(zr[j], h1i[j], fma(-zi[j], h1r[j], a.y));
+          const double t2r = fma(zr[j], h2r[j], fma(-zi[j], h2i[j], bq.x));
+          const double t2i = fma(zr[j], h2i[j], fma(zi[j], h2r[j], bq.y));
+          const double t3r = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g.x));
+          const double t3i = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g.y));
+          const double t4r = fma(zr[j], h4r[j], fma(-zi[j], h4i[j], e.x));
+          const double t4i = fma(zr[j], h4i[j], fma(zi[j], h4r[j], e.y));
+          h1r[j] = t1r;
+          h1i[j] = t1i;
+          h2r[j] = t2r;
+          h2i[j] = t2i;
+          h3r[j] = t3r;
+          h3i[j] = t3i;
+          h4r[j] = t4r;
+          h4i[j] = t4i;
+        }
+      }
+      const double2 g0 = cf[2 * kCl64Order], e0 = cf[3 * kCl64Order + 1];
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        const double pr = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g0.x));
+        const double pi = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g0.y));
+        const double qr = fma(zr[j], h4r[j], fma(-zi[j], h4i[j], e0.x));
+        const double qi = fma(zr[j], h4i[j], fma(zi[j], h4r[j], e0.y));
+        const double p1r = fma(zr[j], h1r[j], zi[j] * h1i[j]);
+        const double p1i = fma(zr[j], h1i[j], -zi[j] * h1r[j]);
+        const double p2r = fma(zr[j], h2r[j], -zi[j] * h2i[j]);
+        const double p2i = fma(zr[j], h2i[j], zi[j] * h2r[j]);
+        const double mr = fma(Zx[j], pr, fma(-Zy[j], pi, -qr));   // Z P - Q
+        const double mi = fma(Zx[j], pi, fma(Zy[j], pr, -qi));
+        const double t3r = 0.5 * fma(zr[j], mr, -zi[j] * mi);
+        const double t3i = 0.5 * fma(zr[j], mi, zi[j] * mr);
+        const double lZ = fma(-0.5, ln_f64(R2[j]), 0.5);          // -ln|Z| + 1/2
+        ax[j] += fma(g0.x, lZ, p1r + p2r + t3r);                  // S0 = conj(g0)
+        ay[j] += fma(-g0.y, lZ, p1i + p2i + t3i);
+      }
+    }
+  }
   for (int kt = kb0; kt < kb1;) {
     const int s0 = src_off[kt];
     int nb = 0;
@@ -941,6 +1086,11 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
     __syncthreads();
     for (int kk = 0; kk < nb; ++kk) {
       const int kbody = kt + kk;
+      if (cmp64) {
+        const int q = body_cl[kbody];
+        if (cl_far64<T>(x, y, ccent[2 * q], ccent[2 * q + 1], __dmul_rn(16.0, __dmul_rn(crad[q], crad[q]))))
+          continue;   // summed with its cluster
+      }
       if (mp64) {
         // far disk for every target of this thread: its FP64 expansion (k_moments64; the
         // same series as the FP32 sum, to order kMp64Order)
@@ -1664,7 +1814,7 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
                                          c->d_mpm + (int64_t)r * c->P * kMpCoef,
                                          c->d_cmpm + (int64_t)r * c->ncl * kClCoef, ur, scale)
               : launch_ksum_fp64_arrays(c, mode, c->d_src64m + (int64_t)r * c->Ns,
-                                        c->d_mp64m + (int64_t)r * c->P * kMp64Coef, c->Nt, c->d_X, c->d_tgt_body,
+                                        c->d_mp64m + (int64_t)r * mp64_record(c), c->Nt, c->d_X, c->d_tgt_body,
                                         ur, scale);
     if (!ok) return false;
   }
@@ -1716,6 +1866,8 @@ static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, 
 static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, const double2* mp64, int64_t Nt,
                                     const double* X, const int32_t* tgt_body, double* u, double scale) {
   if (Nt == 0) return true;
+  const char* ev = std::getenv("MFS_KSUM_CLUSTERS");
+  const double2* cmp64 = mp64 && !(ev && std::atoi(ev) == 0) ? mp64 + (int64_t)c->P * kMp64Coef : nullptr;
   const int T = ksum_targets_per_thread(false);
   const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
   const int ns = ksum_splits(tblocks, c->P);
@@ -1739,7 +1891,8 @@ static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, co
   dim3 grid((unsigned)tblocks, (unsigned)ns);
 #define MFS_KS_FP64(TT)                                                                                     \
   hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, src, Nt,    \
-                     tgt_body, X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out, c->d_centers, mp64)
+                     tgt_body, X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out, c->d_centers, mp64,  \
+                     c->ncl, c->d_body_cl, c->d_ccent, c->d_crad64, cmp64)
   if (T == 4) MFS_KS_FP64(4); else if (T == 1) MFS_KS_FP64(1); else MFS_KS_FP64(2);
 #undef MFS_KS_FP64
   if (ns > 1)
@@ -1833,6 +1986,8 @@ bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, const double2* mp6
 void launch_moments64(mfs_ctx* c, const double4* src64, double2* mp64) {
   hipLaunchKernelGGL(k_moments64, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
                      c->ct[0], src64, mp64);
+  hipLaunchKernelGGL(k_cluster_moments64, dim3(c->ncl), dim3(64), 0, c->stream, c->ncl, c->d_cl_start,
+                     c->d_slot_body, c->d_src_off, c->d_ccent, src64, mp64 + (int64_t)c->P * kMp64Coef);
 }
 
 void launch_fine_strengths(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, double* ptil,

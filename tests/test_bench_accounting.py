@@ -1,10 +1,10 @@
-"""The benchmark's work accounting (bench.ksum_work, bench.ksum_work_clusters) against a
-brute-force count of the kernel sums' rules.
+"""The benchmark's work accounting (bench.ksum_work_clusters) against a brute-force count of
+the kernel sums' rules.
 
 The roofline's flops come from these counts.  A thread holds T = 2 targets, 256 apart in a
 workgroup of 512; per cluster it takes the cluster's expansion when every target is beyond
 4 cluster radii, else per disk of the cluster: the disk's expansion when every target is
-beyond 7 ring radii, else the direct sum over its sources (FP64 kernel: the disk rule alone).
+beyond 7 ring radii, else the direct sum over its sources (both kernel sums).
 16 x 16 disks on a jittered lattice of spacing 3 (18432 nodes, 36 workgroups), clusters of
 2 x 2 disks, so that all three cases occur.
 """
@@ -41,8 +41,6 @@ def _brute(c, ns, rs, X, cl):
     rho2 = (rs * 1.0) ** 2
     d2 = ((xt[:, :, None, :] - c[None, None, :, :]) ** 2).sum(-1)               # (threads, T, P)
     disk_far = (d2 > 49.0 * rho2[None, None, :]).all(1)                          # (threads, P)
-    pairs64 = T * int((~disk_far * ns[None, :]).sum())
-    exps64 = T * int(disk_far.sum())
     ncl = cl["radius"].size
     body_cl = np.empty(P, dtype=int)
     body_cl[cl["slot_body"]] = np.repeat(np.arange(ncl), np.diff(cl["cl_start"]))
@@ -52,12 +50,11 @@ def _brute(c, ns, rs, X, cl):
     pairs32 = T * int(((near_b & ~disk_far) * ns[None, :]).sum())
     dexp32 = T * int((near_b & disk_far).sum())
     cexp32 = T * int(cl_far.sum())
-    return pairs64, exps64, pairs32, dexp32, cexp32
+    return pairs32, dexp32, cexp32
 
 
 def test_work_counts_match_brute_force():
     c, a, ns, rs, X, cl = _setup()
-    p64, e64, p32, d32, c32 = _brute(c, ns, rs, X, cl)
+    p32, d32, c32 = _brute(c, ns, rs, X, cl)
     assert min(d32, c32, p32) > 0
-    assert bench.ksum_work(c, a, ns, rs, X) == (p64, e64)
     assert bench.ksum_work_clusters(c, a, ns, rs, X, cl) == (p32, d32, c32)
