@@ -62,7 +62,7 @@ FLOP_PER_CLUSTER_EXPANSION64 = 32 * (CL64_ORDER - 1) + 64
 
 
 def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, threads_T=KSUM_T, block=256):
-    """Work of one FP32 kernel-sum launch with the two-level far field: cluster expansions,
+    """Work of one kernel-sum launch (FP32 or FP64) with the two-level far field: cluster expansions,
     disk expansions and direct pair evaluations.
 
     Per thread (T targets, block apart) and cluster: the cluster is taken from its expansion
