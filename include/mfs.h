@@ -150,12 +150,13 @@ mfs_status mfs_precompute_pairs(mfs_ctx* ctx, mfs_problem prob, int64_t* n_pairs
  * lexicographic order, or NULL to query only the count. */
 mfs_status mfs_get_pairs(const mfs_ctx* ctx, int64_t* n_pairs, int32_t* pairs);
 
-/* The disk order and clusters of the FP32 kernel sum (its two-level far field; for work
- * accounting and tests).  Disks are sorted along a Morton curve over their centres and cut
+/* The disk order and clusters of the kernel sums' two-level far field (for work accounting
+ * and tests).  Disks are sorted along a Morton curve over their centres and cut
  * into clusters of consecutive disks (at most 16 disks and 1024 sources each, within one
  * quadtree cell).  A cluster farther than 4 radii from a target is summed through one
- * expansion of order 12 about its centre (moments A_k, B_k and D_k = sum sigma conj(w) w^k
- * of its sources; the paper's fast multipole method plays this part, Sec. 6).
+ * expansion about its centre, order 12 in FP32 and 26 in FP64 (moments A_k, B_k and
+ * D_k = sum sigma conj(w) w^k of its sources; the paper's fast multipole method plays this
+ * part, Sec. 6).
  * n_clusters: host, written.  Each of the others is host memory or NULL: slot_body (P):
  * the disk at each position of the order; cl_start (n_clusters + 1): first position of
  * each cluster; centre (2 n_clusters): mean of its disks' centres; radius (n_clusters):
@@ -192,8 +193,10 @@ mfs_status mfs_apply(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t
  * exposed for tests and measurement.  A disk whose centre lies beyond 7 ring radii
  * of the targets is summed through a multipole expansion of its FP64 moments
  * (order 8 for MFS_MIXED, 18 for MFS_FP64: truncation below 3e-8 and 1e-16 of
- * sum |sigma| / (4 pi mu), under each precision's rounding; the paper uses a fast
- * multipole method for this sum, Sec. 6). */
+ * sum |sigma| / (4 pi mu), under each precision's rounding), and a cluster of disks
+ * (mfs_get_clusters) beyond 4 cluster radii through one expansion about its centre
+ * (order 12 / 26: below 2e-8 and 7e-17).  The paper uses a fast multipole method for
+ * this sum (Sec. 6). */
 mfs_status mfs_kernel_sum(mfs_ctx* ctx, mfs_precision prec, const double* sigma, double* u,
                           int32_t skip);
 
