@@ -61,18 +61,22 @@ CL64_ORDER = 26             # the FP64 kernel sum's cluster expansions (same clu
 FLOP_PER_CLUSTER_EXPANSION64 = 32 * (CL64_ORDER - 1) + 64
 
 
-def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, threads_T=KSUM_T, block=256):
-    """Work of one kernel-sum launch (FP32 or FP64) with the two-level far field: cluster expansions,
-    disk expansions and direct pair evaluations.
+def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, tperm=None, threads_T=KSUM_T, block=256, wave=64):
+    """Work of one kernel-sum launch (FP32 or FP64) with the two-level far field: direct pair
+    evaluations, disk expansions and cluster expansions, each counted per target.
 
-    Per thread (T targets, block apart) and cluster: the cluster is taken from its expansion
-    when every target is beyond 4 cluster radii (the kernel's other conditions, a target's
-    own disk or a skipped partner inside the cluster, only hold for clusters that are near
-    anyway); otherwise each of its disks is an expansion when every target is beyond 7 ring
-    radii, else direct over its sources.  cl: mfs_get_clusters of the context."""
+    The kernels visit the targets in the order tperm (None: as given); position i of a grid of
+    blocks of block * T positions belongs to thread (i mod block T) // T of block i // (block T)
+    (a thread's T targets are consecutive), clamped to the last target in the ragged tail, so a
+    wave of `wave` consecutive threads holds wave * T consecutive positions and takes one path
+    for all its targets: a cluster's expansion when every
+    target is beyond 4 cluster radii; otherwise, per disk of the cluster, the disk's expansion
+    when every target is beyond 7 ring radii, else the direct sum over its sources.  Every lane
+    of a wave executes what the wave takes.  cl: mfs_get_clusters of the context."""
     import numpy as np
     from scipy.spatial import cKDTree
     P = centers.shape[0]
+    Nt = X.shape[0]
     n_src = np.asarray(n_src, dtype=np.int64)
     rho = np.asarray(r_src, dtype=np.float64) * np.asarray(radii, dtype=np.float64)
     ncl = cl["radius"].size
@@ -80,32 +84,48 @@ def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, threads_T=KSUM_T, bl
     body_cl = np.empty(P, dtype=np.int64)
     body_cl[cl["slot_body"]] = np.repeat(np.arange(ncl), size)
     per_blk = block * threads_T
-    n_thr = (X.shape[0] + per_blk - 1) // per_blk * block
-    tid = np.arange(X.shape[0])
-    thread = (tid // per_blk) * block + (tid % block)
-    # (thread, cluster) pairs that are near for some target of the thread
-    lists = cKDTree(X).query_ball_point(cl["centre"], r=np.sqrt(CL_FAR2) * cl["radius"])
-    cnt = np.array([len(l) for l in lists])
-    q_idx = np.repeat(np.arange(ncl), cnt)
-    t_idx = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists])
-    near_tq = np.unique(thread[t_idx].astype(np.int64) * ncl + q_idx)
-    near_bodies = int(size[near_tq % ncl].sum())
-    cl_exps = threads_T * (n_thr * ncl - near_tq.size)
-    # (thread, disk) pairs with a target within 7 ring radii, inside a near cluster
-    tree = cKDTree(centers)
-    lists = tree.query_ball_point(X, r=float(np.sqrt(MP_FAR2) * rho.max()))
-    cnt = np.array([len(l) for l in lists])
-    t_idx = np.repeat(tid, cnt)
-    k_idx = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists])
-    d = X[t_idx] - centers[k_idx]
-    keep = np.einsum("ij,ij->i", d, d) <= MP_FAR2 * rho[k_idx] ** 2
-    tk = np.unique(thread[t_idx[keep]].astype(np.int64) * P + k_idx[keep])
-    th, kb = tk // P, tk % P
-    inside = np.isin(th * ncl + body_cl[kb], near_tq)
-    direct_k = kb[inside]
-    pairs = threads_T * int(n_src[direct_k].sum())
-    disk_exps = threads_T * (near_bodies - direct_k.size)
+    nblk = (Nt + per_blk - 1) // per_blk
+    pos = np.arange(nblk * per_blk)
+    tgt = np.minimum(pos, Nt - 1)
+    if tperm is not None:
+        tgt = np.asarray(tperm, dtype=np.int64)[tgt]
+    wv = pos // (wave * threads_T)
+    n_waves = nblk * (block // wave)
+    lanes = wave * threads_T            # targets a wave handles, one path for all
+    # waves holding each target (one each, except the clamped tail)
+    order = np.argsort(tgt, kind="stable")
+    t_sorted, w_sorted = tgt[order], wv[order]
+
+    def waves_of(targets):
+        targets = np.asarray(targets, dtype=np.int64)
+        lo = np.searchsorted(t_sorted, targets, "left")
+        hi = np.searchsorted(t_sorted, targets, "right")
+        cnt = hi - lo
+        idx = np.repeat(lo - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt) + np.arange(cnt.sum())
+        return w_sorted[idx]
+
+    tree = cKDTree(X)
+    # (wave, cluster) pairs with some target within 4 cluster radii
+    lists = tree.query_ball_point(cl["centre"], r=4.0 * cl["radius"])
+    near_wq = np.unique(np.concatenate([waves_of(l) * ncl + q for q, l in enumerate(lists)]
+                                       + [np.zeros(0, dtype=np.int64)]))
+    cl_exps = lanes * (n_waves * ncl - near_wq.size)
+    # (wave, disk) pairs with some target within 7 ring radii
+    lists = tree.query_ball_point(centers, r=7.0 * rho)
+    near_wk = np.unique(np.concatenate([waves_of(l) * P + k for k, l in enumerate(lists)]
+                                       + [np.zeros(0, dtype=np.int64)]))
+    w_k, k_k = near_wk // P, near_wk % P
+    direct = np.isin(w_k * ncl + body_cl[k_k], near_wq)
+    pairs = lanes * int(n_src[k_k[direct]].sum())
+    disk_exps = lanes * (int(size[near_wq % ncl].sum()) - int(direct.sum()))
     return pairs, disk_exps, cl_exps
+
+
+def visiting_order(n_col, slot_body):
+    """The kernel sums' target order: the nodes of the disks in slot order (mfs_get_clusters)."""
+    import numpy as np
+    col_off = np.concatenate([[0], np.cumsum(np.asarray(n_col, dtype=np.int64))])
+    return np.concatenate([np.arange(col_off[b], col_off[b + 1]) for b in slot_body])
 
 
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (dense, packed FP32)
@@ -146,7 +166,9 @@ def rel_rigid_error(out, ref):
 
 
 def cpu_baseline(centers, radii, n_src, n_col, r_src, n_targets, sig_seed=1):
-    """The FP64 oracle's direct sum timed on the host cores on a sample of the workload's targets."""
+    """The FP64 oracle's direct sum timed on the host cores on a sample of the workload's targets.
+
+    It forks worker processes, so it runs before this process touches the GPU."""
     import numpy as np
     from oracle.geometry import ring
     from oracle.kernel import direct_sum
@@ -156,14 +178,16 @@ def cpu_baseline(centers, radii, n_src, n_col, r_src, n_targets, sig_seed=1):
     rng = np.random.default_rng(sig_seed)
     sig = rng.standard_normal((Y.shape[0], 2))
     tsel = np.sort(rng.choice(X.shape[0], n_targets, replace=False))
-    workers = min(16, os.cpu_count() or 1)
+    host = os.cpu_count() or 1
+    workers = min(16, host)
     t0 = time.perf_counter()
     direct_sum(X[tsel], Y, sig, workers=workers, chunk_elems=2_000_000)
     dt = time.perf_counter() - t0
     evals = n_targets * Y.shape[0]
-    return dict(value=evals / dt, unit="pair-evals/s", cores=workers, kind="oracle",
+    return dict(value=evals / dt, unit="pair-evals/s", cores=workers, host_cores=host, kind="oracle",
                 sample=f"{n_targets} of {X.shape[0]} targets x {Y.shape[0]} sources of the same packing, "
-                       f"FP64 NumPy direct sum, {dt:.1f} s")
+                       f"FP64 NumPy direct sum in {workers} single-threaded worker processes "
+                       f"({host} host cores), {dt:.1f} s")
 
 
 def main():
@@ -212,18 +236,25 @@ def main():
     # the library prints precompute progress and stage times to stderr with this set
     os.environ.setdefault("MFS_PROFILE", "1")
     import numpy as np
-    import torch
-    from paper_2606_11273_amd import native as nv
     from workloads import config_geometry, mobility_rhs, unit_torques
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
-    torch.cuda.set_device(0)
     bidisperse = args.workload == "bidisperse"
     g = config_geometry(5 if bidisperse else 3, P=args.P or (2000 if bidisperse else 10000))
     c, a, ns, nc, rs = g["centers"], g["radii"], g["n_src"], g["n_col"], g["r_src"]
     P = c.shape[0]
+    cpu = None
+    if not args.no_cpu and not args.kernel_only:
+        # the oracle's worker processes are forked before this process touches the GPU
+        cpu = cpu_baseline(c, a, ns, nc, rs, args.cpu_targets)
+        log(f"cpu baseline {cpu['value']:.3e} pair-evals/s in {cpu['cores']} processes "
+            f"({cpu['host_cores']} host cores)")
+
+    import torch
+    from paper_2606_11273_amd import native as nv
+    torch.cuda.set_device(0)
     given = unit_torques(P)
     if args.rhs > 1:
         given = np.stack([given] + [mobility_rhs(g["seed"] + r, P) for r in range(1, args.rhs)])
@@ -271,10 +302,11 @@ def main():
     sig = torch.randn(2 * Ns, dtype=torch.float64, device="cuda")
     u = torch.zeros(2 * Nt, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
-    ks = {}
+    ks, kwork = {}, {}
     for prec, reps in (("mixed", args.ksum_reps), ("fp64", 1)):
         nv.mfs_kernel_sum(ctx, prec, sig, u, 2)
         torch.cuda.synchronize()
+        nv.mfs_kernel_sum_work(ctx, reset=True)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -283,6 +315,8 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ks[prec] = e0.elapsed_time(e1) / reps
+        # work per launch as the kernel counted it
+        kwork[prec] = tuple(w // reps for w in nv.mfs_kernel_sum_work(ctx, reset=True))
     # the launch also packs the strengths (a few microseconds); the kernel-sum kernel itself dominates
 
     # plain FP64 solve of the same input (comparison)
@@ -301,22 +335,21 @@ def main():
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    evals = 0
     infos = []
     e0.record(stream)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out32, info32 = nv.mfs_gmres_solve(ctx, "mobility", "mixed", given, args.tol, 1000)
-        evals += info32["pair_evals"]
         infos.append(info32)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
-    log(f"mixed solve {ms:.1f} ms/solve iters {infos[-1]['iters']} outer {infos[-1]['outer']} "
-        f"resid {infos[-1]['rel_resid']:.2e}")
-    evals_skip = infos[-1]["pair_evals"]
-    value = evals / wall
+    log(f"mixed solve {ms:.1f} ms/solve (wall {wall / args.steps * 1e3:.1f}) iters {infos[-1]['iters']} "
+        f"outer {infos[-1]['outer']} resid {infos[-1]['rel_resid']:.2e}")
+    last = infos[-1]
+    solve_work = {k: last[k] for k in ("dense_pairs", "direct_pairs", "disk_expansions", "cluster_expansions")}
+    value = ms / 1e3
 
     if args.copy_calibration:
         buf = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -324,40 +357,40 @@ def main():
         torch.neg(buf, out=out)
         torch.cuda.synchronize()
 
-    # roofline of the dominant kernel (mixed kernel sum; one launch = one matvec's sum without
-    # each disk's own sources and its contact partners).  pair_evals_per_launch counts the
-    # Stokeslet pairs of the direct sum the launch stands for; the FP32 kernel evaluates far
-    # clusters and far disks through their expansions, so its algorithmic flops are the direct
-    # pairs it does compute (near disks) times 20 plus its expansion evaluations times their
-    # flops; the FP64 kernel takes the same clusters and disks, with order-26 and order-18 expansions
+    # roofline of the dominant kernel (the mixed kernel sum; one launch = one matvec's sum
+    # without each disk's own sources and its contact partners).  Its algorithmic flops are the
+    # work the kernel counted itself: direct pair evaluations x 20 plus disk and cluster
+    # expansion evaluations x their flops (order 8 and 12); the FP64 kernel takes the same
+    # decisions with order-18 and order-26 expansions.  dense_pairs_per_launch is the count of
+    # the plain direct sum the launch stands for, which the kernel does not evaluate.
     pr = nv.mfs_get_pairs(ctx)
     skipped = ns.astype(np.int64).copy()
     np.add.at(skipped, pr[:, 0], ns[pr[:, 1]])
     np.add.at(skipped, pr[:, 1], ns[pr[:, 0]])
-    evals_launch = int(np.sum(nc.astype(np.int64) * (Ns - skipped)))
-    Xt = np.concatenate([c[i] + a[i] * np.stack([np.cos(2 * np.pi * np.arange(nc[i]) / nc[i]),
-                                                 np.sin(2 * np.pi * np.arange(nc[i]) / nc[i])], axis=1)
-                         for i in range(P)])
-    t0 = time.perf_counter()
-    pairs32, disk_exps, cl_exps = ksum_work_clusters(c, a, ns, rs, Xt, nv.mfs_get_clusters(ctx))
-    log(f"kernel-sum work (both precisions): {pairs32} direct pairs, {disk_exps} disk and {cl_exps} cluster "
-        f"expansions ({time.perf_counter() - t0:.1f}s)")
+    dense_launch = int(np.sum(nc.astype(np.int64) * (Ns - skipped)))
+    pairs32, disk_exps, cl_exps = kwork["mixed"]
+    log(f"kernel-sum work per launch (device counters): {pairs32} direct pairs, {disk_exps} disk and "
+        f"{cl_exps} cluster expansions; FP64 sum {kwork['fp64']}")
     flops_launch = (pairs32 * FLOP_PER_PAIR + disk_exps * FLOP_PER_EXPANSION
                     + cl_exps * FLOP_PER_CLUSTER_EXPANSION)
+    p64, d64, c64 = kwork["fp64"]
+    flops64 = p64 * FLOP_PER_PAIR + d64 * FLOP_PER_EXPANSION64 + c64 * FLOP_PER_CLUSTER_EXPANSION64
     achieved = flops_launch / (ks["mixed"] * 1e-3) / 1e12
+    sec = ks["mixed"] * 1e-3
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=ksum_traffic_bytes(),
                     kernel="k_ksum_mixed (FP32 Stokeslet sum; far clusters and disks by their order-12 "
                            "and order-8 expansions)",
                     ms_per_launch=round(ks["mixed"], 3), flops_per_launch=flops_launch,
-                    direct_pairs_per_launch=pairs32, expansions_per_launch=disk_exps,
+                    direct_pairs_per_launch=pairs32, disk_expansions_per_launch=disk_exps,
                     cluster_expansions_per_launch=cl_exps,
-                    pair_evals_per_launch=evals_launch,
-                    pair_evals_per_s=round(evals_launch / (ks["mixed"] * 1e-3), 1),
+                    direct_pairs_per_s=round(pairs32 / sec, 1), disk_expansions_per_s=round(disk_exps / sec, 1),
+                    cluster_expansions_per_s=round(cl_exps / sec, 1),
+                    dense_pairs_per_launch=dense_launch,
+                    dense_equivalent_pairs_per_s=round(dense_launch / sec, 1),
                     fp64_kernel_ms_per_launch=round(ks["fp64"], 2),
-                    fp64_kernel_tflops=round((pairs32 * FLOP_PER_PAIR + disk_exps * FLOP_PER_EXPANSION64
-                                              + cl_exps * FLOP_PER_CLUSTER_EXPANSION64)
-                                             / (ks["fp64"] * 1e-3) / 1e12, 2),
+                    fp64_kernel_work_per_launch=list(kwork["fp64"]),
+                    fp64_kernel_tflops=round(flops64 / (ks["fp64"] * 1e-3) / 1e12, 2),
                     fp64_peak=PEAK_FP64_TFLOPS)
 
     # stacked matvec: one T mu on args.rhs vectors at once, per vector (HIP events)
@@ -396,20 +429,16 @@ def main():
     err = None
     if out64 is not None:
         err = max(rel_rigid_error(a32, a64) for a32, a64 in zip(out32.reshape(-1, P, 3), out64.reshape(-1, P, 3)))
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(c, a, ns, nc, rs, args.cpu_targets)
-        log(f"cpu baseline {cpu['value']:.3e} pair-evals/s on {cpu['cores']} processes")
 
     line = {
         "metric": "Stokeslet pair-evals/s + time-to-solve P=10k phi=0.65 at 1e-5 (mixed vs FP64)",
-        "value": round(value, 1),
-        "unit": "pair-evals/s",
+        "value": round(value, 4),
+        "unit": "s (time to solve, mixed form)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 2),
-        "higher_is_better": True,
+        "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
@@ -430,7 +459,7 @@ def main():
         "iterations": {"mixed_inner": infos[-1]["iters"], "mixed_outer": infos[-1]["outer"],
                        "fp64": info64.get("iters")},
         "rel_resid": {"mixed": infos[-1]["rel_resid"], "fp64": info64.get("rel_resid")},
-        "pair_evals_per_solve": evals_skip,
+        "kernel_sum_work_per_solve": solve_work,
         "setup_s": round(t_setup, 3),
         "precompute_s": round(t_pre, 2),
         "stacked_matvec": stacked,

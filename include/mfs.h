@@ -93,7 +93,14 @@ typedef struct {
   int64_t n_pairs;
   int32_t matvecs_fp64;   /* operator applications with the FP64 kernel sum (refinement residuals) */
   int32_t matvecs_mixed;  /* operator applications with the mixed kernel sum */
-  int64_t pair_evals;     /* Stokeslet (target, source) evaluations in all kernel sums of the solve */
+  /* Work of all kernel sums of the solve (eq. getall).  dense_pairs counts the (target, source)
+   * pairs of the plain direct sums they stand for; the kernels evaluate direct_pairs of them one
+   * by one and replace the rest by disk_expansions and cluster_expansions evaluations of a
+   * far-field expansion (each per target), as counted by the kernels themselves. */
+  int64_t dense_pairs;
+  int64_t direct_pairs;
+  int64_t disk_expansions;
+  int64_t cluster_expansions;
 } mfs_solve_info;
 
 /* Fill *prm with the paper's defaults.  prm: host, written. */
@@ -199,6 +206,15 @@ mfs_status mfs_apply(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t
  * this sum (Sec. 6). */
 mfs_status mfs_kernel_sum(mfs_ctx* ctx, mfs_precision prec, const double* sigma, double* u,
                           int32_t skip);
+
+/* Work counted by the context's kernel sums (eq. getall) since setup or the last reset:
+ * work[0] direct (target, source) pair evaluations, work[1] evaluations of a disk's far-field
+ * expansion, work[2] evaluations of a cluster's expansion (each per target; a wave of 64
+ * threads, 2 targets each, takes one path per disk or cluster for all its targets, and every
+ * thread counts what it executes).  Flow-evaluation points are not counted.  work: host, 3,
+ * written.  Synchronises the context's stream; reset != 0 then zeroes the counters.
+ * mfs_gmres_solve resets them at its start. */
+mfs_status mfs_kernel_sum_work(mfs_ctx* ctx, int64_t* work, int32_t reset);
 
 /* Right-hand side of the preconditioned system.  given: host, P x 3 (forces and
  * torques for mobility, velocities for resistance); b: device, n.  Mobility:

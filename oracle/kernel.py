@@ -12,6 +12,7 @@ from __future__ import annotations
 import math
 import multiprocessing as mp
 import os
+import sys
 
 import numpy as np
 from threadpoolctl import threadpool_limits
@@ -51,6 +52,21 @@ def _sum_chunk(x, y, sig, mu):
 _SHARED = {}
 
 
+def _gpu_initialised():
+    """True once this process has initialised a GPU through torch.
+
+    A process that has initialised the GPU runtime must not fork workers: the children
+    inherit device and profiler state they cannot use, and fail when the pool shuts down.
+    """
+    torch = sys.modules.get("torch")
+    if torch is None:
+        return False
+    try:
+        return bool(torch.cuda.is_initialized())
+    except Exception:
+        return False
+
+
 def _worker(bounds):
     lo, hi = bounds
     s = _SHARED
@@ -65,7 +81,8 @@ def direct_sum(x, y, sig, mu=1.0, workers=None, chunk_elems=4_000_000):
     x: (M, 2) targets, y: (N, 2) sources, sig: (N, 2) strengths -> (M, 2).
     Targets are split into blocks; large problems spread the blocks over
     forked worker processes (one block of targets each, no reordering of the sum
-    over sources within a target).
+    over sources within a target).  In a process that has initialised the GPU the sum
+    runs in this process only (workers=None), and workers > 1 is refused.
     """
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
     y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1, 2)
@@ -76,9 +93,13 @@ def direct_sum(x, y, sig, mu=1.0, workers=None, chunk_elems=4_000_000):
         return out
     step = max(1, chunk_elems // max(N, 1))
     bounds = [(lo, min(M, lo + step)) for lo in range(0, M, step)]
+    gpu = _gpu_initialised()
     if workers is None:
         # at most 16 processes: hosts that share their cores between jobs give each one that many
-        workers = min(len(bounds), os.cpu_count() or 1, 16) if M * N > 5e8 else 1
+        workers = min(len(bounds), os.cpu_count() or 1, 16) if M * N > 5e8 and not gpu else 1
+    elif workers > 1 and gpu:
+        raise RuntimeError("direct_sum: no worker processes are forked from a process that has "
+                           "initialised the GPU (pass workers=1 or None)")
     if workers <= 1 or len(bounds) == 1:
         for lo, hi in bounds:
             out[lo:hi] = _sum_chunk(x[lo:hi], y, sig, mu)

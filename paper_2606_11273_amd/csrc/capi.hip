@@ -83,7 +83,8 @@ void free_all(mfs_ctx* c) {
                   c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
                   c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf, c->d_mp,
                   c->d_mpm,     c->d_mp64,    c->d_mp64m,   c->d_fmp64, c->d_slot_of, c->d_slot_body, c->d_ssrc_off, c->d_nbr_slot,
-                  c->d_cl_start, c->d_scent,  c->d_ccent,   c->d_crad2, c->d_cmp,  c->d_cmpm, c->d_crad64, c->d_body_cl};
+                  c->d_cl_start, c->d_scent,  c->d_ccent,   c->d_crad2, c->d_cmp,  c->d_cmpm, c->d_crad64, c->d_body_cl,
+                  c->d_tperm,   c->d_work};
   for (void* p : ptrs)
     if (p) dev_free(c, p);
   for (const PairSet& ps : c->ps)
@@ -336,7 +337,18 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
     for (int q = 0; q < c->ncl; ++q)
       for (int sl = c->cl_start[q]; sl < c->cl_start[q + 1]; ++sl) body_cl[c->slot_body[sl]] = q;
     if ((st = upload(c, &c->d_body_cl, body_cl, s)).code) return st;
+    // the kernel sums visit the targets disk by disk in slot order, so that a workgroup's
+    // targets (and a wave's) lie close together and far clusters are far for all of them
+    std::vector<int32_t> tperm;
+    tperm.reserve(c->Nt);
+    for (int sl = 0; sl < P; ++sl) {
+      const int b = c->slot_body[sl];
+      for (int q = c->col_off[b]; q < c->col_off[b + 1]; ++q) tperm.push_back(q);
+    }
+    if ((st = upload(c, &c->d_tperm, tperm, s)).code) return st;
   }
+  if ((st = dalloc(c, &c->d_work, 4)).code) return st;
+  launch_zero_work(c);
   if ((st = dalloc(c, &c->d_lam_bar, 2 * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_ltil, c->xoff[C])).code) return st;
   if ((st = dalloc(c, &c->d_u, 2 * c->Nt)).code) return st;
@@ -365,12 +377,12 @@ Status check_kernel_sum(mfs_ctx* c, bool launched) {
 
 namespace mfs {
 
-Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u) {
+Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u, const SplitBuf* sb) {
   const bool wp = c->pairs.size() > 0;
   launch_onebody_apply(c, prob, mu, c->d_lam_bar);
   if (wp) launch_pair_A(c, prob, c->d_lam_bar, c->d_ltil);
   launch_gather_project(c, prob, c->d_lam_bar, c->d_ltil, wp, mixed, !mixed);
-  const bool ks = launch_kernel_sum(c, mixed, 2, c->d_u, 1.0 / (4.0 * kPiD * c->prm.mu));
+  const bool ks = launch_kernel_sum(c, mixed, 2, c->d_u, 1.0 / (4.0 * kPiD * c->prm.mu), sb);
   c->cnt_pair_evals += c->evals_skip;
   if (mixed)
     ++c->cnt_mv32;
@@ -632,6 +644,18 @@ mfs_status mfs_apply(mfs_ctx* c, mfs_problem prob, mfs_precision prec, int32_t n
     return fail(c, Status{MFS_ERR_STATE, "mfs_precompute_pairs has not run for this problem"});
   Status st = apply_T_rhs(c, prob, prec == MFS_MIXED, n_rhs, mu_in, u_out);
   if (st.code) return fail(c, st);
+  return ok(c);
+}
+
+mfs_status mfs_kernel_sum_work(mfs_ctx* c, int64_t* work, int32_t reset) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if (!work) return fail(c, Status{MFS_ERR_ARG, "work is NULL"});
+  unsigned long long h[3] = {0, 0, 0};
+  if (hipMemcpyAsync(h, c->d_work, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(c, Status{MFS_ERR_DEVICE, "reading the work counters failed"});
+  for (int e = 0; e < 3; ++e) work[e] = (int64_t)h[e];
+  if (reset) launch_zero_work(c);
   return ok(c);
 }
 

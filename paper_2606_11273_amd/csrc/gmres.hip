@@ -588,6 +588,7 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
   const bool mixed = prec == MFS_MIXED;
   c->cnt_pair_evals = 0;
   c->cnt_mv64 = c->cnt_mv32 = 0;
+  launch_zero_work(c);
   SolveTotals tot;
   // the densities are kept for mfs_get_density / flow evaluation
   c->mu_count = 0;
@@ -626,7 +627,12 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
     info->n_pairs = (int64_t)(c->pairs.size() / 2);
     info->matvecs_fp64 = c->cnt_mv64;
     info->matvecs_mixed = c->cnt_mv32;
-    info->pair_evals = c->cnt_pair_evals;
+    info->dense_pairs = c->cnt_pair_evals;
+    int64_t w[3] = {0, 0, 0};
+    if (mfs_kernel_sum_work(c, w, 0) != MFS_OK) return MFS_ERR_DEVICE;
+    info->direct_pairs = w[0];
+    info->disk_expansions = w[1];
+    info->cluster_expansions = w[2];
   }
   if (tot.noconv) {
     char buf[64];

@@ -36,6 +36,13 @@ struct Status {
   std::string msg;
 };
 
+// A caller-provided buffer for the kernel sum's split partials (cap doubles): the
+// kernel sum then allocates nothing.
+struct SplitBuf {
+  double* p = nullptr;
+  int64_t cap = 0;
+};
+
 // Shared one-body factors of a disk class, passed to kernels by value.
 struct ClassTab {
   int n = 0;
@@ -130,6 +137,8 @@ struct mfs_ctx {
   float* d_crad2 = nullptr;      // ncl squared cluster radii
   double* d_crad64 = nullptr;    // ncl cluster radii (FP64 sum)
   int32_t* d_body_cl = nullptr;  // P: cluster of each disk
+  int32_t* d_tperm = nullptr;    // Nt: the kernel sums visit targets in slot order (disk by disk)
+  unsigned long long* d_work = nullptr;   // kernel-sum work counters: direct pairs, disk and cluster expansions
 
   // work vectors
   double *d_lam_bar = nullptr, *d_ltil = nullptr, *d_sig64 = nullptr, *d_u = nullptr, *d_corr = nullptr;
@@ -201,7 +210,12 @@ bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64
                        int64_t ltil_stride);
 bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, double scale);
 // mode 0: all sources; 1: skip the target's own disk; 2: also skip its contact partners.  false: out of memory
-bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale);
+bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale, const SplitBuf* sb = nullptr);
+// doubles of split partials one kernel sum of this context needs (0: none)
+int64_t ksum_split_doubles(const mfs_ctx* c, bool mixed);
+// zero the kernel-sum work counters (a kernel, so that the call may sit in a captured graph)
+void launch_zero_work(mfs_ctx* c);
+
 void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr);
 void launch_finish(mfs_ctx* c, const double* u_sum, const double* mu, const double* corr, double* u_out,
                    bool with_pairs);
@@ -236,7 +250,7 @@ Status onebody_factors(mfs_ctx* c);
 Status precompute_pairs(mfs_ctx* c, int prob);
 
 // ---- matvec pieces (capi.hip) ----
-Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u);
+Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u, const SplitBuf* sb = nullptr);
 // T applied to R vectors (mu, u: R x n, vector r at offset r n); stacked kernels for R in {2, 4, 8}
 Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, double* u);
 

@@ -23,6 +23,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Work counters of a kernel-sum launch: each wave adds its lanes' counts (direct pair
+// evaluations, disk expansions, cluster expansions) to work[0..2] with one atomic each.
+__device__ __forceinline__ void add_work(unsigned long long* work, unsigned d, unsigned e, unsigned c) {
+  if (!work) return;
+  for (int off = 32; off > 0; off >>= 1) {
+    d += __shfl_down(d, off, 64);
+    e += __shfl_down(e, off, 64);
+    c += __shfl_down(c, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(work, (unsigned long long)d);
+    atomicAdd(work + 1, (unsigned long long)e);
+    atomicAdd(work + 2, (unsigned long long)c);
+  }
+}
+
 // Sum over a block of up to 1024 threads; every thread gets the result.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -430,7 +446,10 @@ __global__ __launch_bounds__(kBodyThreads) void k_cluster_moments(int ncl, const
 // ---------------------------------------------------------------------------
 // Step 2a: all-pairs Stokeslet sum u_t = sum_s S(x_t, y_s) sigma_s (eq. getall, eq. stokeslet2d).
 //
-// A workgroup owns T * 256 consecutive targets.  The FP64 sum streams the sources of a
+// A workgroup owns T * 256 consecutive targets of the visiting order (the nodes of the disks
+// in slot order, so nearby targets share a workgroup), thread i the T targets from T i on,
+// so a wave holds 64 T consecutive targets.  A wave takes one path per cluster and per disk
+// (expansion or direct) for all its targets.  The FP64 sum streams the sources of a
 // range of bodies (one split of blockIdx.y) through LDS in tiles of whole bodies; the FP32
 // sum walks a range of clusters of its disk order, one cluster per tile, and skips the
 // tile of a cluster that is far from all its targets (two-level far field, below).
@@ -507,7 +526,9 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
                                                            const float2* __restrict__ mp,
                                                            const double* __restrict__ ccent,
                                                            const float* __restrict__ crad2,
-                                                           const float2* __restrict__ cmp) {
+                                                           const float2* __restrict__ cmp,
+                                                           const int* __restrict__ tperm,
+                                                           unsigned long long* __restrict__ work) {
   __shared__ float4 s_src[KS_TILE];    // (y_x, y_y, sigma_x, sigma_y), y relative to the disk centre
   __shared__ float s_w[KS_TILE];       // y . sigma
   __shared__ double s_c[2 * KS_MAXB];
@@ -517,18 +538,21 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
   const int split = blockIdx.y;
   const int q0 = min(ncl, split * clusters_per_split);
   const int q1 = min(ncl, q0 + clusters_per_split);
-  int64_t t[T];
+  int64_t t[T];    // position in the visiting order
+  int64_t tt[T];   // the target there
   int bt[T];   // the target's disk, in slot order
   double x[T], y[T], ax[T], ay[T];
   Skip sk[T];
+  unsigned n_dir = 0, n_dexp = 0, n_cexp = 0;   // this lane's work (per target)
 #pragma unroll
   for (int j = 0; j < T; ++j) {
-    t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + j * KS_THREADS + threadIdx.x;
+    t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + threadIdx.x * T + j;   // a wave: 64 T consecutive targets
     const int64_t tc = t[j] < Nt ? t[j] : Nt - 1;
-    const int body = tgt_body[tc];
+    tt[j] = tperm ? tperm[tc] : tc;
+    const int body = tgt_body[tt[j]];
     bt[j] = slot_of[body];
-    x[j] = X[2 * tc];
-    y[j] = X[2 * tc + 1];
+    x[j] = X[2 * tt[j]];
+    y[j] = X[2 * tt[j] + 1];
     ax[j] = 0.0;
     ay[j] = 0.0;
     skip_init(sk[j], mode, body, cl_start[q0], nbr_off, nbr_list);
@@ -595,8 +619,11 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
         R2[j] = fmaf(Zx[j], Zx[j], Zy[j] * Zy[j]);
         cfar = cfar && R2[j] > rf && (mode == 0 || bt[j] < kt || bt[j] >= ke) && (mode != 2 || sk[j].next >= ke);
       }
-      cfar = cfar || bfar;
+      // one decision per wave: a wave whose lanes disagree takes the disks (near path) on
+      // every lane rather than executing both paths
+      cfar = bfar || __all(cfar);
       if (cfar) {
+        ++n_cexp;
         // Horner over the cluster's series: h1 over zeta (A_k/2k), h2 over conj(zeta) (B_k/2k),
         // h3 over conj(zeta) (conj A_k), h4 over conj(zeta) (conj D_k)
         const float2* cf = cmp + (int64_t)cq * kClCoef;
@@ -696,7 +723,8 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
           R2[j] = fmaf(Zx[j], Zx[j], Zy[j] * Zy[j]);
           far = far && R2[j] > kMpFar2 * bd.z;
         }
-        if (far) {
+        if (__all(far)) {   // one decision per wave, as for the clusters
+          ++n_dexp;
           const float2* cf = s_mp + kk * kMpCoef;
           float zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T];
 #pragma unroll
@@ -773,6 +801,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
         lx[j] = ly[j] = t0[j] = tsx[j] = tsy[j] = 0.0f;
       }
       const int q1 = s_off[kk + 1];
+      n_dir += q1 - s_off[kk];
 #pragma unroll 4
       for (int q = s_off[kk]; q < q1; ++q) {
         const float4 s = s_src[q];
@@ -815,11 +844,12 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
       }
     }
   }
+  add_work(work, T * n_dir, T * n_dexp, T * n_cexp);
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     if (t[j] < Nt) {
-      out[((int64_t)split * Nt + t[j]) * 2] = ax[j] * scale;
-      out[((int64_t)split * Nt + t[j]) * 2 + 1] = ay[j] * scale;
+      out[((int64_t)split * Nt + tt[j]) * 2] = ax[j] * scale;
+      out[((int64_t)split * Nt + tt[j]) * 2 + 1] = ay[j] * scale;
     }
   }
 }
@@ -981,23 +1011,28 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
                                                           const int* __restrict__ body_cl,
                                                           const double* __restrict__ ccent,
                                                           const double* __restrict__ crad,
-                                                          const double2* __restrict__ cmp64) {
+                                                          const double2* __restrict__ cmp64,
+                                                          const int* __restrict__ tperm,
+                                                          unsigned long long* __restrict__ work) {
   __shared__ double4 s_src[KS_TILE / 2];
   __shared__ int s_off[KS_MAXB + 1];
   const int split = blockIdx.y;
   const int kb0 = split * bodies_per_split;
   const int kb1 = min(P, kb0 + bodies_per_split);
-  int64_t t[T];
+  int64_t t[T];    // position in the visiting order
+  int64_t tt[T];   // the target there
   int bt[T];
   double x[T], y[T], ax[T], ay[T];
   Skip sk[T];
+  unsigned n_dir = 0, n_dexp = 0, n_cexp = 0;   // this lane's work (per target)
 #pragma unroll
   for (int j = 0; j < T; ++j) {
-    t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + j * KS_THREADS + threadIdx.x;
+    t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + threadIdx.x * T + j;   // a wave: 64 T consecutive targets
     const int64_t tc = t[j] < Nt ? t[j] : Nt - 1;
-    bt[j] = tgt_body[tc];
-    x[j] = X[2 * tc];
-    y[j] = X[2 * tc + 1];
+    tt[j] = tperm ? tperm[tc] : tc;
+    bt[j] = tgt_body[tt[j]];
+    x[j] = X[2 * tt[j]];
+    y[j] = X[2 * tt[j] + 1];
     ax[j] = 0.0;
     ay[j] = 0.0;
     skip_init(sk[j], mode, bt[j], kb0, nbr_off, nbr_list);
@@ -1010,7 +1045,9 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
     const int c0 = min(ncl, split * cps), c1 = min(ncl, c0 + cps);
     for (int q = c0; q < c1; ++q) {
       const double cx = ccent[2 * q], cy = ccent[2 * q + 1];
-      if (!cl_far64<T>(x, y, cx, cy, __dmul_rn(16.0, __dmul_rn(crad[q], crad[q])))) continue;
+      // one decision per wave (the disk pass below repeats the same vote)
+      if (!__all(cl_far64<T>(x, y, cx, cy, __dmul_rn(16.0, __dmul_rn(crad[q], crad[q]))))) continue;
+      ++n_cexp;
       const double2* cf = cmp64 + (int64_t)q * kCl64Coef;
       double Zx[T], Zy[T], R2[T], zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T], h4r[T], h4i[T];
 #pragma unroll
@@ -1088,7 +1125,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
       const int kbody = kt + kk;
       if (cmp64) {
         const int q = body_cl[kbody];
-        if (cl_far64<T>(x, y, ccent[2 * q], ccent[2 * q + 1], __dmul_rn(16.0, __dmul_rn(crad[q], crad[q]))))
+        if (__all(cl_far64<T>(x, y, ccent[2 * q], ccent[2 * q + 1], __dmul_rn(16.0, __dmul_rn(crad[q], crad[q])))))
           continue;   // summed with its cluster
       }
       if (mp64) {
@@ -1106,7 +1143,8 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
           R2[j] = fma(Zx[j], Zx[j], Zy[j] * Zy[j]);
           far = far && R2[j] > kMp64Far2 * q;
         }
-        if (far) {
+        if (__all(far)) {   // one decision per wave
+          ++n_dexp;
           double zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T];
 #pragma unroll
           for (int j = 0; j < T; ++j) {
@@ -1166,6 +1204,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
 #pragma unroll
       for (int j = 0; j < T; ++j) lx[j] = ly[j] = tx[j] = ty[j] = 0.0;
       const int q1 = s_off[kk + 1];
+      n_dir += q1 - s_off[kk];
       for (int q = s_off[kk]; q < q1; ++q) {
         const double4 s = s_src[q];
 #pragma unroll
@@ -1191,13 +1230,18 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
     }
     kt += nb;
   }
+  add_work(work, T * n_dir, T * n_dexp, T * n_cexp);
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     if (t[j] < Nt) {
-      out[((int64_t)split * Nt + t[j]) * 2] = ax[j] * scale;
-      out[((int64_t)split * Nt + t[j]) * 2 + 1] = ay[j] * scale;
+      out[((int64_t)split * Nt + tt[j]) * 2] = ax[j] * scale;
+      out[((int64_t)split * Nt + tt[j]) * 2 + 1] = ay[j] * scale;
     }
   }
+}
+
+__global__ void k_zero_work(unsigned long long* work) {
+  if (threadIdx.x < 3) work[threadIdx.x] = 0ull;
 }
 
 __global__ void k_reduce_splits(int64_t n2, int nsplit, const double* __restrict__ part, double* __restrict__ u) {
@@ -1728,6 +1772,10 @@ inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); 
 // ---------------------------------------------------------------------------
 // launchers
 
+void launch_zero_work(mfs_ctx* c) {
+  hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(64), 0, c->stream, c->d_work);
+}
+
 void launch_onebody_apply(mfs_ctx* c, int prob, const double* mu, double* lam_bar) {
   hipLaunchKernelGGL(k_onebody, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
                      c->d_col_off, c->ct[prob], mu, lam_bar);
@@ -1783,12 +1831,13 @@ bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64
 }
 
 // Choose the source split so that the grid holds enough workgroups to fill the chip
-// (256 CUs, several resident workgroups each).  MFS_KSUM_SPLITS overrides it.
+// (256 CUs, 32 workgroups each).  The split partials (splits x N_t x 16 bytes) then stay
+// below 16384 x 512 targets x 16 bytes = 128 MiB.  MFS_KSUM_SPLITS overrides it.
 static int ksum_splits(int64_t tblocks, int P) {
   const char* e = std::getenv("MFS_KSUM_SPLITS");
   if (e) return std::max(1, std::min(P, std::atoi(e)));
   int s = 1;
-  while (tblocks * s < 16384 && s * 2 <= std::max(1, P / 8) && s < 64) s *= 2;
+  while (tblocks * s < 8192 && s * 2 <= std::max(1, P / 8) && s < 64) s *= 2;
   return s;
 }
 
@@ -1799,9 +1848,36 @@ static int ksum_targets_per_thread(bool mixed) {
 }
 
 static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
-                                     const float2* mp, const float2* cmp, double* u, double scale);
+                                     const float2* mp, const float2* cmp, double* u, double scale,
+                                     const SplitBuf* sb = nullptr);
 static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, const double2* mp64, int64_t Nt,
-                                    const double* X, const int32_t* tgt_body, double* u, double scale);
+                                    const double* X, const int32_t* tgt_body, const int32_t* tperm, double* u,
+                                    double scale, const SplitBuf* sb = nullptr);
+
+// Split partials of one kernel sum: the caller's buffer (sb), else the context's own, grown
+// on demand.  NULL when it does not fit.
+static double* split_buffer(mfs_ctx* c, int64_t need, const SplitBuf* sb) {
+  if (sb) return need <= sb->cap ? sb->p : nullptr;
+  if (c->upart_cap < need) {
+    if (c->d_upart) dev_free(c, c->d_upart);
+    c->d_upart = nullptr;
+    if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      c->d_upart = nullptr;
+      c->upart_cap = 0;
+      return nullptr;
+    }
+    c->upart_cap = need;
+  }
+  return c->d_upart;
+}
+
+int64_t ksum_split_doubles(const mfs_ctx* c, bool mixed) {
+  const int64_t T = ksum_targets_per_thread(mixed);
+  int ns = ksum_splits((c->Nt + KS_THREADS * T - 1) / (KS_THREADS * T), c->P);
+  if (mixed) ns = std::min(ns, c->ncl);
+  return ns > 1 ? (int64_t)ns * c->Nt * 2 : 0;
+}
 
 // Stacked form of launch_kernel_sum: R strength vectors packed by launch_gather_project_to
 // into c->d_sig32m / c->d_bdatm (mixed) or c->d_src64m (FP64), R arrays each; u: R x 2 Nt.
@@ -1815,7 +1891,7 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
                                          c->d_cmpm + (int64_t)r * c->ncl * kClCoef, ur, scale)
               : launch_ksum_fp64_arrays(c, mode, c->d_src64m + (int64_t)r * c->Ns,
                                         c->d_mp64m + (int64_t)r * mp64_record(c), c->Nt, c->d_X, c->d_tgt_body,
-                                        ur, scale);
+                                        c->d_tperm, ur, scale);
     if (!ok) return false;
   }
   return true;
@@ -1824,7 +1900,8 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
 // One FP32 kernel sum on explicit packed arrays (sources, disk moments, expansion
 // coefficients); see launch_kernel_sum.
 static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
-                                     const float2* mp, const float2* cmp, double* u, double scale) {
+                                     const float2* mp, const float2* cmp, double* u, double scale,
+                                     const SplitBuf* sb) {
   const int T = ksum_targets_per_thread(true);
   const int64_t Nt = c->Nt;
   const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
@@ -1833,38 +1910,25 @@ static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, 
   const char* ev = std::getenv("MFS_KSUM_CLUSTERS");
   if (ev && std::atoi(ev) == 0) cmp = nullptr;
   double* out = u;
-  if (ns > 1) {
-    const int64_t need = (int64_t)ns * Nt * 2;
-    if (c->upart_cap < need) {
-      if (c->d_upart) dev_free(c, c->d_upart);
-      c->d_upart = nullptr;
-      if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        c->d_upart = nullptr;
-        c->upart_cap = 0;
-        return false;
-      }
-      c->upart_cap = need;
-    }
-    out = c->d_upart;
-  }
+  if (ns > 1 && !(out = split_buffer(c, (int64_t)ns * Nt * 2, sb))) return false;
   dim3 grid((unsigned)tblocks, (unsigned)ns);
 #define MFS_KS_MIXED(TT)                                                                                         \
   hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->ncl, c->d_cl_start,          \
                      c->d_ssrc_off, c->d_scent, sig32, bdat, Nt, c->d_tgt_body, c->d_slot_of, c->d_X, cps, mode,  \
-                     c->d_nbr_off, c->d_nbr_slot, scale, out, mp, c->d_ccent, c->d_crad2, cmp)
+                     c->d_nbr_off, c->d_nbr_slot, scale, out, mp, c->d_ccent, c->d_crad2, cmp, c->d_tperm,        \
+                     c->d_work)
   if (T == 4) MFS_KS_MIXED(4); else if (T == 1) MFS_KS_MIXED(1); else MFS_KS_MIXED(2);
 #undef MFS_KS_MIXED
   if (ns > 1)
-    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns,
-                       c->d_upart, u);
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns, out, u);
   return true;
 }
 
 // FP64 kernel sum of a packed source array at Nt points X (mode as in k_ksum_fp64); mp64: the
 // far-field coefficients of src (k_moments64), or NULL for the direct sum over every disk.
 static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, const double2* mp64, int64_t Nt,
-                                    const double* X, const int32_t* tgt_body, double* u, double scale) {
+                                    const double* X, const int32_t* tgt_body, const int32_t* tperm, double* u,
+                                    double scale, const SplitBuf* sb) {
   if (Nt == 0) return true;
   const char* ev = std::getenv("MFS_KSUM_CLUSTERS");
   const double2* cmp64 = mp64 && !(ev && std::atoi(ev) == 0) ? mp64 + (int64_t)c->P * kMp64Coef : nullptr;
@@ -1873,37 +1937,25 @@ static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, co
   const int ns = ksum_splits(tblocks, c->P);
   const int bps = (c->P + ns - 1) / ns;
   double* out = u;
-  if (ns > 1) {
-    const int64_t need = (int64_t)ns * Nt * 2;
-    if (c->upart_cap < need) {
-      if (c->d_upart) dev_free(c, c->d_upart);
-      c->d_upart = nullptr;
-      if (dev_malloc(c, &c->d_upart, need * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        c->d_upart = nullptr;
-        c->upart_cap = 0;
-        return false;
-      }
-      c->upart_cap = need;
-    }
-    out = c->d_upart;
-  }
+  if (ns > 1 && !(out = split_buffer(c, (int64_t)ns * Nt * 2, sb))) return false;
+  // the work counters count the context's own targets only (not flow-evaluation points)
+  unsigned long long* work = X == c->d_X ? c->d_work : nullptr;
   dim3 grid((unsigned)tblocks, (unsigned)ns);
 #define MFS_KS_FP64(TT)                                                                                     \
   hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, src, Nt,    \
                      tgt_body, X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out, c->d_centers, mp64,  \
-                     c->ncl, c->d_body_cl, c->d_ccent, c->d_crad64, cmp64)
+                     c->ncl, c->d_body_cl, c->d_ccent, c->d_crad64, cmp64, tperm, work)
   if (T == 4) MFS_KS_FP64(4); else if (T == 1) MFS_KS_FP64(1); else MFS_KS_FP64(2);
 #undef MFS_KS_FP64
   if (ns > 1)
-    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns,
-                       c->d_upart, u);
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns, out, u);
   return true;
 }
 
-bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale) {
-  if (mixed) return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, c->d_cmp, u, scale);
-  return launch_ksum_fp64_arrays(c, mode, c->d_src64, c->d_mp64, c->Nt, c->d_X, c->d_tgt_body, u, scale);
+bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale, const SplitBuf* sb) {
+  if (mixed) return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, c->d_cmp, u, scale, sb);
+  return launch_ksum_fp64_arrays(c, mode, c->d_src64, c->d_mp64, c->Nt, c->d_X, c->d_tgt_body, c->d_tperm, u, scale,
+                                 sb);
 }
 
 void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr) {
@@ -1980,7 +2032,7 @@ void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b,
 
 bool launch_kernel_sum_points(mfs_ctx* c, const double4* src, const double2* mp64, int64_t n_pts,
                               const double* pts, const int32_t* body, double* u) {
-  return launch_ksum_fp64_arrays(c, 0, src, mp64, n_pts, pts, body, u, 1.0 / (4.0 * kPiD * c->prm.mu));
+  return launch_ksum_fp64_arrays(c, 0, src, mp64, n_pts, pts, body, nullptr, u, 1.0 / (4.0 * kPiD * c->prm.mu));
 }
 
 void launch_moments64(mfs_ctx* c, const double4* src64, double2* mp64) {

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "MFS_OK", 1: "MFS_ERR_ARG", 2: "MFS_ERR_GEOMETRY", 3: "MFS_ER
 
 # Exported symbols, in the order of include/mfs.h.
 SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_pairs", "mfs_get_clusters", "mfs_set_pair_matrices",
-           "mfs_get_pair_matrices", "mfs_apply", "mfs_kernel_sum", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
+           "mfs_get_pair_matrices", "mfs_apply", "mfs_kernel_sum", "mfs_kernel_sum_work", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
            "mfs_get_sizes", "mfs_destroy", "mfs_last_error", "mfs_server_create", "mfs_server_footprint",
            "mfs_server_submit", "mfs_server_wait", "mfs_server_last_error", "mfs_server_destroy",
            "mfs_keep_fine_factors", "mfs_get_density", "mfs_flow_eval", "mfs_boundary_residual",
@@ -47,7 +47,8 @@ class MfsSolveInfo(C.Structure):
                 ("resid_hist", C.POINTER(C.c_double)), ("hist_cap", C.c_int32), ("hist_len", C.c_int32),
                 ("ms_rhs", C.c_double), ("ms_iterate", C.c_double), ("ms_post", C.c_double),
                 ("n_pairs", C.c_int64), ("matvecs_fp64", C.c_int32), ("matvecs_mixed", C.c_int32),
-                ("pair_evals", C.c_int64)]
+                ("dense_pairs", C.c_int64), ("direct_pairs", C.c_int64), ("disk_expansions", C.c_int64),
+                ("cluster_expansions", C.c_int64)]
 
 
 class MfsRequest(C.Structure):
@@ -138,6 +139,7 @@ def lib():
     L.mfs_get_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
     L.mfs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int32, vp, vp]
     L.mfs_kernel_sum.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
+    L.mfs_kernel_sum_work.argtypes = [vp, i64p, C.c_int32]
     L.mfs_rhs.argtypes = [vp, C.c_int, dp, vp]
     L.mfs_post.argtypes = [vp, C.c_int, vp, dp]
     L.mfs_gmres_solve.argtypes = [vp, C.c_int, C.c_int, C.c_int32, dp, dp, vp, C.c_double, C.c_int32,
@@ -284,6 +286,14 @@ def mfs_apply(ctx, problem, precision, mu, u, n_rhs=1):
     _check(lib().mfs_apply(ctx, PROBLEMS[problem], PRECISIONS[precision], n_rhs, _dev(mu), _dev(u)), ctx)
 
 
+def mfs_kernel_sum_work(ctx, reset=False):
+    """(direct pairs, disk expansions, cluster expansions) counted by the kernel sums since setup
+    or the last reset."""
+    w = np.zeros(3, dtype=np.int64)
+    _check(lib().mfs_kernel_sum_work(ctx, w.ctypes.data_as(C.POINTER(C.c_int64)), int(bool(reset))), ctx)
+    return tuple(int(v) for v in w)
+
+
 def mfs_kernel_sum(ctx, precision, sigma, u, skip=1):
     """skip: 0 all sources, 1 skip the target's own disk, 2 also skip its contact partners."""
     _check(lib().mfs_kernel_sum(ctx, PRECISIONS[precision], _dev(sigma), _dev(u), int(skip)), ctx)
@@ -351,7 +361,8 @@ def mfs_gmres_solve(ctx, problem, precision, rhs, tol, max_iter=500, x0=None, hi
     d = dict(iters=info.iters_total, outer=info.outer_steps, rel_resid=info.rel_resid,
              hist=hist[:info.hist_len].copy(), ms_rhs=info.ms_rhs, ms_iterate=info.ms_iterate, ms_post=info.ms_post,
              n_pairs=info.n_pairs, matvecs_fp64=info.matvecs_fp64, matvecs_mixed=info.matvecs_mixed,
-             pair_evals=info.pair_evals, status=STATUS_NAMES[code])
+             dense_pairs=info.dense_pairs, direct_pairs=info.direct_pairs, disk_expansions=info.disk_expansions,
+             cluster_expansions=info.cluster_expansions, status=STATUS_NAMES[code])
     return out, d
 
 
@@ -418,7 +429,8 @@ def mfs_server_wait(srv, ticket, P, timeout_ms=-1, allow_noconv=False):
     s = info.solve
     return out, dict(ms_queue=info.ms_queue, ms_service=info.ms_service, ms_total=info.ms_total,
                      ms_precompute=info.ms_precompute, footprint=info.footprint_bytes, iters=s.iters_total,
-                     outer=s.outer_steps, rel_resid=s.rel_resid, n_pairs=s.n_pairs, pair_evals=s.pair_evals,
+                     outer=s.outer_steps, rel_resid=s.rel_resid, n_pairs=s.n_pairs, dense_pairs=s.dense_pairs,
+                     direct_pairs=s.direct_pairs,
                      status=code)
 
 

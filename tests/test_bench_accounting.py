@@ -1,10 +1,12 @@
 """The benchmark's work accounting (bench.ksum_work_clusters) against a brute-force count of
 the kernel sums' rules.
 
-The roofline's flops come from these counts.  A thread holds T = 2 targets, 256 apart in a
-workgroup of 512; per cluster it takes the cluster's expansion when every target is beyond
-4 cluster radii, else per disk of the cluster: the disk's expansion when every target is
-beyond 7 ring radii, else the direct sum over its sources (both kernel sums).
+The kernels count their own work on the device (mfs_kernel_sum_work); these host counts pin
+their rules.  A thread holds T = 2 consecutive targets of a workgroup's 512, and a wave of 64
+threads takes one path for all of its 128 targets: per cluster the cluster's expansion when
+every target is beyond 4 cluster radii, else per disk of the cluster the disk's expansion
+when every target is beyond 7 ring radii, else the direct sum over its sources (both kernel
+sums).
 16 x 16 disks on a jittered lattice of spacing 3 (18432 nodes, 36 workgroups), clusters of
 2 x 2 disks, so that all three cases occur.
 """
@@ -32,24 +34,37 @@ def _setup():
     return c, a, ns, rs, X, cl
 
 
-def _brute(c, ns, rs, X, cl):
-    P, T, B = c.shape[0], 2, 256
-    nthr = X.shape[0] // (B * T) * B
-    th = np.arange(nthr)
-    tgt = np.stack([(th // B) * B * T + j * B + th % B for j in range(T)], 1)   # (threads, T)
-    xt = X[tgt]                                                                   # (threads, T, 2)
+def _brute(c, ns, rs, X, cl, tperm=None):
+    """Per wave (64 threads of T = 2 targets; thread tid of block b holds the targets at
+    positions b 512 + 2 tid + j of the visiting order), the kernels' decisions taken for all
+    its targets at once."""
+    P, T, B, W = c.shape[0], 2, 256, 64
+    Nt = X.shape[0]
+    nblk = -(-Nt // (B * T))
+    pos = np.arange(nblk * B * T)
+    tgt = np.minimum(pos, Nt - 1)
+    if tperm is not None:
+        tgt = tperm[tgt]
+    b, r = pos // (B * T), pos % (B * T)
+    tid, j = r // T, r % T
+    assert np.array_equal(b * B * T + tid * T + j, pos)
+    wave = b * (B // W) + tid // W
+    order = np.argsort(wave, kind="stable")
+    wt = tgt[order].reshape(-1, W * T)                                            # (waves, 128)
+    xt = X[wt]
     rho2 = (rs * 1.0) ** 2
-    d2 = ((xt[:, :, None, :] - c[None, None, :, :]) ** 2).sum(-1)               # (threads, T, P)
-    disk_far = (d2 > 49.0 * rho2[None, None, :]).all(1)                          # (threads, P)
+    d2 = ((xt[:, :, None, :] - c[None, None, :, :]) ** 2).sum(-1)               # (waves, 128, P)
+    disk_far = (d2 > 49.0 * rho2[None, None, :]).all(1)                          # (waves, P)
     ncl = cl["radius"].size
     body_cl = np.empty(P, dtype=int)
     body_cl[cl["slot_body"]] = np.repeat(np.arange(ncl), np.diff(cl["cl_start"]))
     dc2 = ((xt[:, :, None, :] - cl["centre"][None, None, :, :]) ** 2).sum(-1)
-    cl_far = (dc2 > 16.0 * cl["radius"][None, None, :] ** 2).all(1)              # (threads, ncl)
-    near_b = ~cl_far[:, body_cl]                                                  # (threads, P)
-    pairs32 = T * int(((near_b & ~disk_far) * ns[None, :]).sum())
-    dexp32 = T * int((near_b & disk_far).sum())
-    cexp32 = T * int(cl_far.sum())
+    cl_far = (dc2 > 16.0 * cl["radius"][None, None, :] ** 2).all(1)              # (waves, ncl)
+    near_b = ~cl_far[:, body_cl]                                                  # (waves, P)
+    lanes = W * T
+    pairs32 = lanes * int(((near_b & ~disk_far) * ns[None, :]).sum())
+    dexp32 = lanes * int((near_b & disk_far).sum())
+    cexp32 = lanes * int(cl_far.sum())
     return pairs32, dexp32, cexp32
 
 
@@ -58,3 +73,17 @@ def test_work_counts_match_brute_force():
     p32, d32, c32 = _brute(c, ns, rs, X, cl)
     assert min(d32, c32, p32) > 0
     assert bench.ksum_work_clusters(c, a, ns, rs, X, cl) == (p32, d32, c32)
+
+
+def test_work_counts_in_visiting_order_with_ragged_tail():
+    # the targets visited disk by disk in the clusters' slot order, and a node count that
+    # leaves a partly filled last workgroup (clamped positions)
+    c, a, ns, rs, X, cl = _setup()
+    X = X[:-100]
+    nc = np.full(256, 72)
+    tperm = bench.visiting_order(nc, cl["slot_body"])
+    tperm = tperm[tperm < X.shape[0]]
+    ref = _brute(c, ns, rs, X, cl, tperm)
+    assert min(ref) > 0
+    assert bench.ksum_work_clusters(c, a, ns, rs, X, cl, tperm=tperm) == ref
+    assert ref != _brute(c, ns, rs, X, cl)

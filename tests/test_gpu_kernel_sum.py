@@ -2,9 +2,10 @@
 
 Tolerances are stated per target relative to the magnitude
 m_t = sum_s (|log r_ts| + 1) |sigma_s| / (4 pi mu), which bounds how rounding in the
-terms can show in u_t: FP64 <= 1e-13 m_t; mixed (FP32 terms on body-relative
-coordinates, FP64 accumulation over bodies) <= 2e-6 m_t, i.e. about 30 units in
-the last place of FP32 per term.
+terms can show in u_t: FP64 <= 1e-13 m_t everywhere; mixed (FP32 terms on body-relative
+coordinates, FP64 accumulation over bodies, far disks and clusters from FP64 moments) per
+case at about ten times the error measured on the MI355X (stated beside each bound), so
+that a regression of an order of magnitude fails.
 """
 
 import numpy as np
@@ -36,6 +37,14 @@ def _run(centers, radii, n_src, n_col, r_src, sig, skip, delta_c=0.2):
         nv.mfs_destroy(ctx)
 
 
+def _check(g, ref, mag, what, bound32, rows=slice(None)):
+    e64 = (np.abs(g["fp64"][rows] - ref).max(1) / mag).max()
+    e32 = (np.abs(g["mixed"][rows] - ref).max(1) / mag).max()
+    say(f"  {what}: max err / m_t fp64 {e64:.2e} mixed {e32:.2e} (bound {bound32:.0e})")
+    assert e64 <= 1e-13
+    assert e32 <= bound32
+
+
 def _partners(c, a, delta_c):
     from oracle.geometry import contacts
     nb = [set() for _ in range(len(c))]
@@ -56,8 +65,7 @@ def test_kernel_sum_jittered_grid(skip):
     g = _run(c, a, ns, nc, rs, sig, skip, delta_c=0.5)
     ref, mag = oracle_sum_excluding_self(X, Y, sig, so, co, include_self=(skip == 0),
                                          partners=_partners(c, a, 0.5) if skip == 2 else None)
-    assert np.all(np.abs(g["fp64"] - ref).max(1) <= 1e-13 * mag)
-    assert np.all(np.abs(g["mixed"] - ref).max(1) <= 2e-6 * mag)
+    _check(g, ref, mag, f"4x4 grid skip {skip}", 6e-8)   # measured 5.5e-9 .. 6.3e-9
 
 
 def test_kernel_sum_ragged_mixed_classes():
@@ -74,8 +82,7 @@ def test_kernel_sum_ragged_mixed_classes():
     say("kernel sum ragged two classes")
     g = _run(c, a, ns, nc, rs, sig, 2, delta_c=1.0)
     ref, mag = oracle_sum_excluding_self(X, Y, sig, so, co, partners=_partners(c, a, 1.0))
-    assert np.all(np.abs(g["fp64"] - ref).max(1) <= 1e-13 * mag)
-    assert np.all(np.abs(g["mixed"] - ref).max(1) <= 2e-6 * mag)
+    _check(g, ref, mag, "ragged two classes", 2e-8)   # measured 2.2e-9
 
 
 def test_kernel_sum_full_size_sampled():
@@ -93,8 +100,7 @@ def test_kernel_sum_full_size_sampled():
     tsel = np.sort(rng.choice(X.shape[0], 300, replace=False))
     tsel[0], tsel[-1] = 0, X.shape[0] - 1
     ref, mag = oracle_sum_excluding_self(X, Y, sig, so, co, targets=tsel, partners=_partners(c, a, 0.2))
-    assert np.all(np.abs(g["fp64"][tsel] - ref).max(1) <= 1e-13 * mag)
-    assert np.all(np.abs(g["mixed"][tsel] - ref).max(1) <= 2e-6 * mag)
+    _check(g, ref, mag, "P=10000 sampled", 2e-9, tsel)   # measured 1.4e-10
 
 
 def test_kernel_sum_clusters_mid_size():
@@ -135,6 +141,60 @@ def test_kernel_sum_clusters_mid_size():
         tsel = np.sort(rng.choice(X.shape[0], 1500, replace=False))
         ref, mag = oracle_sum_excluding_self(X, Y, sig, so, co, targets=tsel, include_self=(skip == 0),
                                              partners=_partners(c, a, g0["delta_c"]) if skip == 2 else None)
-        say(f"  skip {skip}: mixed max err / m_t {(np.abs(g['mixed'][tsel] - ref).max(1) / mag).max():.1e}")
-        assert np.all(np.abs(g["fp64"][tsel] - ref).max(1) <= 1e-13 * mag)
-        assert np.all(np.abs(g["mixed"][tsel] - ref).max(1) <= 2e-6 * mag)
+        _check(g, ref, mag, f"P=600 skip {skip}", 7e-9, tsel)   # measured 6.5e-10 .. 6.9e-10
+
+
+def test_kernel_sum_projected_strengths():
+    # the strengths the mobility matvec sums: N(0,1) per source, projected by (I - L) per disk
+    # so that every disk carries zero net force and torque (Sec. 4.4).  Their fields cancel to
+    # leading order at a distance; the FP32 sum takes each disk's leading parts from FP64
+    # moments, so its error stays relative to the field itself.  Dense-packing generator
+    # (area fraction 0.65, min gap 1e-3) at P = 1000, 1500 sampled targets, skip mode 2.
+    from oracle.onebody import one_body
+    g0 = config_geometry(3, P=1000)
+    c, a = g0["centers"], g0["radii"]
+    ns, nc, rs = g0["n_src"], g0["n_col"], g0["r_src"]
+    X, Y, so, co = coarse_points(c, a, ns, nc, rs)
+    ob = one_body(1.0, 36, 72, 0.7, 1.0, "mobility", 1e-14, 1e-12)
+    rng = np.random.default_rng(4)
+    sig = np.concatenate([ob.project(rng.standard_normal(72)) for _ in range(c.shape[0])]).reshape(-1, 2)
+    say("kernel sum projected strengths, dense packing P=1000")
+    g = _run(c, a, ns, nc, rs, sig, 2)
+    tsel = np.sort(rng.choice(X.shape[0], 1500, replace=False))
+    ref, mag = oracle_sum_excluding_self(X, Y, sig, so, co, targets=tsel, partners=_partners(c, a, 0.2))
+    field = np.abs(ref).max()
+    e32 = np.abs(g["mixed"][tsel] - ref).max() / field
+    say(f"  mixed: max err / max |u| {e32:.2e}; max |u| / max m_t {field / mag.max():.2e}")
+    _check(g, ref, mag, "projected strengths", 3e-10, tsel)   # measured 2.2e-11
+    assert e32 <= 3e-6   # measured 2.3e-7 of max |u|
+
+
+def test_kernel_sum_work_counters():
+    # the kernels' own work counters (mfs_kernel_sum_work) against the host count of their
+    # rules (bench.ksum_work_clusters), per launch, at P = 600 (area fraction 0.5), skip mode 2
+    import bench
+    from paper_2606_11273_amd import native as nv
+    g0 = config_geometry(2, P=600)
+    c, a = g0["centers"], g0["radii"]
+    ns, nc, rs = g0["n_src"], g0["n_col"], g0["r_src"]
+    prm = nv.mfs_default_params()
+    prm.delta_c = g0["delta_c"]
+    X, Y, so, co = coarse_points(c, a, ns, nc, rs)
+    ctx = nv.mfs_setup(c, a, ns, nc, rs, prm)
+    try:
+        cl = nv.mfs_get_clusters(ctx)
+        s = torch.tensor(np.random.default_rng(5).standard_normal(2 * Y.shape[0]), device="cuda")
+        u = torch.zeros(2 * X.shape[0], dtype=torch.float64, device="cuda")
+        nv.mfs_kernel_sum_work(ctx, reset=True)
+        counts = {}
+        for prec in ("mixed", "fp64"):
+            nv.mfs_kernel_sum(ctx, prec, s, u, 2)
+            counts[prec] = nv.mfs_kernel_sum_work(ctx, reset=True)
+    finally:
+        nv.mfs_destroy(ctx)
+    ref = bench.ksum_work_clusters(c, a, ns, rs, X, cl, tperm=bench.visiting_order(nc, cl["slot_body"]))
+    say(f"work per launch: host {ref}, mixed {counts['mixed']}, fp64 {counts['fp64']}")
+    assert min(ref) > 0
+    for prec in ("mixed", "fp64"):
+        for k in range(3):
+            assert abs(counts[prec][k] - ref[k]) <= 1e-4 * ref[k], (prec, k)

@@ -15,8 +15,9 @@ is checked.  Both sides use the oracle's A^c (mfs_set_pair_matrices), as in the
 small-size matvec tests; the GPU's own precompute is checked against the oracle
 elsewhere.
 
-Tolerances.  FP64: 2e-11 of max |T mu|, as in the small-size smooth case.  Mixed: the
-FP32 sum differs from the FP64 one by at most 2e-6 m_t at each target t, with
+Tolerances.  FP64: 2e-11 of max |T mu|, as in the small-size smooth case.  Mixed, against
+the oracle: the FP32 sum's error is at most 2e-8 m_t at each target t (about ten times the
+measured error; plus the FP64 steps' 2e-11 of max |T mu|), with
 m_t = sum_s (|log r_ts| + 1) |sigma_s| / (4 pi mu) over the sources the step sums (the
 bound of the kernel-sum tests; every other step is FP64 in both forms).  Relative to
 max |T mu| that is not small here: the support holds the closest pair (gap 1e-3),
@@ -101,12 +102,18 @@ def test_matvec_full_size_localised_input(problem):
     finally:
         nv.mfs_destroy(ctx)
     e64 = np.abs(out["fp64"] - ref).max() / scale
-    d32 = np.abs(out["mixed"] - out["fp64"]).reshape(-1, 2).max(1)
+    e32 = np.abs(out["mixed"] - ref).max() / scale
+    d32 = np.abs(out["mixed"] - ref).reshape(-1, 2).max(1)
     mag = _magnitude(S, mu)
-    say(f"  fp64: max |T mu - ref| / max |ref| = {e64:.2e}; mixed: {np.abs(out['mixed'] - ref).max() / scale:.2e} "
-        f"of max |ref|, max_t |mixed - fp64| / m_t = {(d32 / mag).max():.2e}")
+    say(f"  fp64: max |T mu - ref| / max |ref| = {e64:.2e}; mixed: {e32:.2e} of max |ref|, "
+        f"max_t |mixed - ref| / m_t = {(d32 / mag).max():.2e}")
     assert e64 <= 2e-11
-    assert np.all(d32 <= 2e-6 * mag)
+    # the mixed product against the oracle: per target about ten times the measured error of the
+    # FP32 sum (1.9e-9 m_t mobility, 1.2e-9 resistance) plus the FP64 steps' bound; overall 6e-5
+    # of max |T mu| (measured 2.7e-5 mobility, 3.9e-6 resistance: the closest pair's compressed
+    # strengths are much larger than mu, and their FP32 near field reaches non-partner neighbours)
+    assert np.all(d32 <= 2e-8 * mag + 2e-11 * scale)
+    assert e32 <= 6e-5
 
 
 def _magnitude(S, mu):
