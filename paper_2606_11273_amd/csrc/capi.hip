@@ -91,7 +91,13 @@ void free_all(mfs_ctx* c) {
     for (void* p : {(void*)ps.G, (void*)ps.Yf, (void*)ps.KKf, (void*)ps.pgeo, (void*)ps.nf, (void*)ps.d_goff,
                     (void*)ps.d_yoff})
       if (p) dev_free(c, p);
+  for (void* p : {(void*)c->kr.H, (void*)c->kr.cs, (void*)c->kr.sn, (void*)c->kr.g, (void*)c->kr.y, (void*)c->kr.ctl,
+                  (void*)c->kr.rec})
+    if (p) dev_free(c, p);
   if (c->kr.hhost) (void)hipHostFree(c->kr.hhost);
+  if (c->kr.hrec) (void)hipHostFree(c->kr.hrec);
+  for (hipEvent_t e : c->kr.ev)
+    if (e) (void)hipEventDestroy(e);
   for (void* p : c->class_bufs)
     if (p) dev_free(c, p);
   if (c->blas) rocblas_destroy_handle(c->blas);

@@ -4,8 +4,12 @@
 // device memory.  Orthogonalisation is classical Gram-Schmidt applied twice
 // (CGS2): two passes of h = V^T w, w -= V h per iteration, all FP64, with the dot
 // products reduced in a fixed order.  The (k+1) x k Hessenberg least-squares
-// problem is updated by Givens rotations on the host (a few doubles per
-// iteration cross the bus).
+// problem stays on the device: one wave per right-hand side applies the Givens
+// rotations in FP64 (k_givens), scales the next basis vector and records the
+// residual estimate.  The host does not wait for an iteration before launching the
+// next one: it reads iteration j's estimate while iteration j + 1 runs, so it
+// learns of convergence one iteration late and one extra iteration is launched
+// and discarded (the device leaves a finished right-hand side's state alone).
 //
 // MFS_MIXED: FP64 iterative refinement around a GMRES whose operator applications
 // switch from FP64 to the mixed operator (FP32 all-pairs sum, FP64 accumulation)
@@ -45,11 +49,16 @@ Status ensure_krylov(mfs_ctx* c, int cap, int R) {
   Krylov& k = c->kr;
   const int64_t n = 2 * c->Nt;
   if (k.V && k.cap >= cap && k.rcap >= R && k.n == n) return Status{};
-  for (double** p : {&k.V, &k.part, &k.hdev, &k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp})
+  for (double** p : {&k.V, &k.part, &k.hdev, &k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp, &k.H, &k.cs, &k.sn, &k.g, &k.y,
+                     &k.ctl, &k.rec})
     if (*p) dev_free(c, *p);
   if (k.hhost) (void)hipHostFree(k.hhost);
+  if (k.hrec) (void)hipHostFree(k.hrec);
   k.V = k.part = k.hdev = k.hhost = k.w = k.x = k.r = k.b = k.d = k.tmp = nullptr;
+  k.H = k.cs = k.sn = k.g = k.y = k.ctl = k.rec = k.hrec = nullptr;
   k.cap = k.rcap = 0;
+  for (hipEvent_t& e : k.ev)
+    if (!e) MFS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (double** p : {&k.w, &k.x, &k.r, &k.b, &k.d, &k.tmp}) MFS_HIP(dev_malloc(c, (void**)p, sizeof(double) * n * R));
   if (dev_malloc(c, (void**)&k.V, sizeof(double) * n * R * (cap + 1)) != hipSuccess) {
     (void)hipGetLastError();
@@ -61,6 +70,15 @@ Status ensure_krylov(mfs_ctx* c, int cap, int R) {
   MFS_HIP(dev_malloc(c, (void**)&k.part, sizeof(double) * nblk * (cap + 2)));
   MFS_HIP(dev_malloc(c, (void**)&k.hdev, sizeof(double) * 3 * (cap + 2) * R));
   MFS_HIP(hipHostMalloc((void**)&k.hhost, sizeof(double) * 3 * (cap + 2) * R, hipHostMallocDefault));
+  const size_t cR = (size_t)R;
+  MFS_HIP(dev_malloc(c, (void**)&k.H, sizeof(double) * cR * (cap + 1) * cap));
+  MFS_HIP(dev_malloc(c, (void**)&k.cs, sizeof(double) * cR * cap));
+  MFS_HIP(dev_malloc(c, (void**)&k.sn, sizeof(double) * cR * cap));
+  MFS_HIP(dev_malloc(c, (void**)&k.g, sizeof(double) * cR * (cap + 1)));
+  MFS_HIP(dev_malloc(c, (void**)&k.y, sizeof(double) * cR * (cap + 1)));
+  MFS_HIP(dev_malloc(c, (void**)&k.ctl, sizeof(double) * cR * kGmCtl));
+  MFS_HIP(dev_malloc(c, (void**)&k.rec, sizeof(double) * cR * 4 * (cap + 1)));
+  MFS_HIP(hipHostMalloc((void**)&k.hrec, sizeof(double) * cR * 4 * (cap + 1), hipHostMallocDefault));
   k.cap = cap;
   k.rcap = R;
   k.n = n;
@@ -95,9 +113,18 @@ double rel_diff(mfs_ctx* c, int64_t n, double* a, const double* b, Status* st) {
 
 // Switch point of the relaxed inner GMRES: the mixed operator is used once the residual
 // estimate is below tol / max(delta, op_err), op_err the measured relative error of the
-// mixed operator (negative while unknown).
-double switch_point(bool mixed, double tol, double delta, double op_err) {
-  return mixed ? std::min(1.0, tol / std::max(delta, op_err)) : 0.0;
+// mixed operator (negative while unknown).  A mixed operator whose measured error exceeds
+// kMixedMaxErr is not used at all: its FP32 errors, amplified by the small singular values
+// of the packed system, stall the Krylov process (measured: 1e-4 plateaus with 60-source
+// rings on the ring-rule radius and on the bidisperse packing, where the FP64 solve needs a
+// fraction of the iterations), so the solve stays FP64 after the one measurement.  This
+// holds for mobility; resistance, whose compressed lubrication strengths make its mixed
+// operator error 1e-4 .. 5e-3 even on small grids, relies on its larger delta instead.
+constexpr double kMixedMaxErr = 1e-5;
+
+double switch_point(bool mixed, double tol, double delta, double op_err, double max_err) {
+  if (!mixed || op_err > max_err) return 0.0;
+  return std::min(1.0, tol / std::max(delta, op_err));
 }
 
 // Stall test of the mixed phase: every kStallWindow / 2 mixed iterations, once there have
@@ -115,109 +142,14 @@ bool stalled(const std::vector<double>& est, int first32, int j) {
          est[j] > kStallDrop * est[j - kStallWindow];   // j - kStallWindow >= first32 >= 0
 }
 
-Status gmres_core(mfs_ctx* c, int prob, bool mixed, double delta, double& op_err, const double* r, double tol,
-                  int maxit, int* iters, std::vector<double>& hist) {
-  Krylov& k = c->kr;
-  const int64_t n = k.n;
-  const int nblk = mdot_blocks(n);
-  Status st;
-  double switch_below = switch_point(mixed, tol, delta, op_err);
-  const double beta = dnorm(c, r, &st);
-  if (st.code) return st;
-  MFS_HIP(hipMemsetAsync(k.d, 0, sizeof(double) * n, c->stream));
-  *iters = 0;
-  if (!std::isfinite(beta)) return Status{MFS_ERR_NUMERIC, "non-finite residual"};
-  if (beta == 0.0) return Status{};
-  launch_scale_copy(c->stream, n, 1.0 / beta, r, k.V);
-  std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
-  std::vector<double> est(maxit, 1.0);
-  int first32 = -1;
-  bool force64 = false;
-  auto Hc = [&](int row, int col) -> double& { return H[(size_t)col * (maxit + 1) + row]; };
-  g[0] = beta;
-  int kdone = 0;
-  const int cap = k.cap;
-  const bool prof = std::getenv("MFS_PROFILE") != nullptr;
-  auto t_start = clk::now();
-  double rel_est = 1.0;
-  for (int j = 0; j < maxit; ++j) {
-    double* vj = k.V + (int64_t)j * n;
-    bool use32 = mixed && !force64 && rel_est <= switch_below;
-    if (use32 && op_err < 0.0) {
-      // first switch: measure the mixed operator on this basis vector against the FP64
-      // one (which this iteration keeps), then move the switch point if it is worse
-      if ((st = apply_T(c, prob, false, vj, k.w)).code) return st;
-      if ((st = apply_T(c, prob, true, vj, k.tmp)).code) return st;
-      op_err = rel_diff(c, n, k.tmp, k.w, &st);
-      if (st.code) return st;
-      switch_below = switch_point(mixed, tol, delta, op_err);
-      if (prof)
-        std::fprintf(stderr, "[mfs gmres] mixed operator relative error %.2e: switch below %.2e\n", op_err,
-                     switch_below);
-      use32 = false;
-    } else if ((st = apply_T(c, prob, use32, vj, k.w)).code) {
-      return st;
-    }
-    if (use32 && first32 < 0) first32 = j;
-    // CGS2
-    launch_mdot(c->stream, n, j + 1, k.V, n, k.w, k.part, k.hdev, nblk);
-    launch_maxpy(c->stream, n, j + 1, k.V, n, k.hdev, k.w);
-    launch_mdot(c->stream, n, j + 1, k.V, n, k.w, k.part, k.hdev + (cap + 2), nblk);
-    launch_maxpy(c->stream, n, j + 1, k.V, n, k.hdev + (cap + 2), k.w);
-    launch_mdot(c->stream, n, 1, k.w, n, k.w, k.part, k.hdev + 2 * (cap + 2), nblk);
-    MFS_HIP(hipMemcpyAsync(k.hhost, k.hdev, sizeof(double) * 3 * (cap + 2), hipMemcpyDeviceToHost, c->stream));
-    MFS_HIP(hipStreamSynchronize(c->stream));
-    for (int i = 0; i <= j; ++i) Hc(i, j) = k.hhost[i] + k.hhost[(cap + 2) + i];
-    const double hn = std::sqrt(std::max(0.0, k.hhost[2 * (cap + 2)]));
-    Hc(j + 1, j) = hn;
-    for (int i = 0; i <= j + 1; ++i)
-      if (!std::isfinite(Hc(i, j))) return Status{MFS_ERR_NUMERIC, "non-finite value in the Arnoldi process"};
-    if (hn > 0.0) launch_scale_copy(c->stream, n, 1.0 / hn, k.w, k.V + (int64_t)(j + 1) * n);
-    for (int i = 0; i < j; ++i) {
-      const double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
-      Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
-      Hc(i, j) = t;
-    }
-    const double den = std::hypot(Hc(j, j), Hc(j + 1, j));
-    cs[j] = Hc(j, j) / den;
-    sn[j] = Hc(j + 1, j) / den;
-    Hc(j, j) = den;
-    Hc(j + 1, j) = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    kdone = j + 1;
-    hist.push_back(std::fabs(g[j + 1]) / beta);
-    rel_est = hist.back();
-    if (prof && (kdone % 10 == 0))
-      std::fprintf(stderr, "[mfs gmres] %s it %d resid %.3e  %.1f s\n", use32 ? "fp32-sum" : "fp64", kdone,
-                   hist.back(), ms_since(t_start) * 1e-3);
-    if (std::fabs(g[j + 1]) <= tol * beta || hn == 0.0) break;
-    est[j] = rel_est;
-    if (!force64 && stalled(est, first32, j)) {
-      force64 = true;
-      if (prof) std::fprintf(stderr, "[mfs gmres] mixed phase stalled at it %d: FP64 from here\n", kdone);
-    }
-  }
-  std::vector<double> y(kdone);
-  for (int i = kdone - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int q = i + 1; q < kdone; ++q) s -= Hc(i, q) * y[q];
-    y[i] = s / Hc(i, i);
-  }
-  MFS_HIP(hipMemcpyAsync(k.hdev, y.data(), sizeof(double) * kdone, hipMemcpyHostToDevice, c->stream));
-  launch_gemv_n(c->stream, n, kdone, k.V, n, k.hdev, k.d);
-  MFS_HIP(hipStreamSynchronize(c->stream));
-  *iters = kdone;
-  return Status{};
-}
-
-// Lockstep GMRES for R right-hand sides (the stacked form of gmres_core): every right-hand
-// side keeps its own Krylov basis, Hessenberg matrix and Givens rotations; each step
-// applies the operator to the R newest basis vectors at once (apply_T_rhs), so the
+// GMRES for R right-hand sides in lockstep (R = 1: a single solve): every right-hand side
+// keeps its own Krylov basis, Hessenberg matrix and Givens rotations (on the device); each
+// step applies the operator to the R newest basis vectors at once (apply_T_rhs), so the
 // all-pairs sum and the pair matrices are read once for all of them.  A right-hand side
-// whose estimate reaches its tolerance is frozen (its slot is fed zeros).  The mixed
-// kernel sum is used once every active right-hand side is below its switch point.
-// r, d: R x n; tol, switch_below: R; iters: R.
+// whose estimate reaches its tolerance is frozen (the device feeds it zeros from then on).
+// The mixed kernel sum is used once every active right-hand side is below its switch
+// point.  Decisions (operator precision, stall, stop) use the estimates the host has read,
+// which lag one iteration.  r, d: R x n; tol: R; iters: R.
 Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, double& op_err, const double* r,
                       const double* tol, const bool* active_in, int maxit, int* iters,
                       std::vector<std::vector<double>>& hist) {
@@ -227,34 +159,66 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, dou
   const int nblk = mdot_blocks(n);
   const int cap = k.cap;
   const int64_t hstride = 3 * (int64_t)(cap + 2);
+  hipStream_t s = c->stream;
   Status st;
+  const double max_err = prob == MFS_MOBILITY ? kMixedMaxErr : INFINITY;
   std::vector<double> beta(R, 0.0), rel(R, 1.0), switch_below(R);
-  for (int q = 0; q < R; ++q) switch_below[q] = switch_point(mixed, tol[q], delta, op_err);
-  std::vector<char> active(R, 0);
-  std::vector<int> kdone(R, 0);
-  std::vector<std::vector<double>> H(R), cs(R), sn(R), g(R);
-  std::vector<double> est(maxit, 1.0);   // worst active estimate
+  for (int q = 0; q < R; ++q) switch_below[q] = switch_point(mixed, tol[q], delta, op_err, max_err);
+  std::vector<char> active(R, 0);   // as far as the host knows
+  std::vector<double> est(maxit, 1.0);   // worst active estimate per iteration
   int first32 = -1;
   bool force64 = false;
-  MFS_HIP(hipMemsetAsync(k.d, 0, sizeof(double) * n * R, c->stream));
-  MFS_HIP(hipMemsetAsync(k.V, 0, sizeof(double) * ldv, c->stream));
+  MFS_HIP(hipMemsetAsync(k.d, 0, sizeof(double) * n * R, s));
+  MFS_HIP(hipMemsetAsync(k.V, 0, sizeof(double) * ldv, s));
+  std::vector<double> ctl((size_t)R * kGmCtl, 0.0), g0((size_t)R * (cap + 1), 0.0);
   for (int q = 0; q < R; ++q) {
     iters[q] = 0;
+    double* cq = ctl.data() + (size_t)q * kGmCtl;
+    cq[kGmDone] = 1.0;
+    cq[kGmEst] = 1.0;
     if (!active_in[q]) continue;
     beta[q] = dnorm(c, r + q * n, &st);
     if (st.code) return st;
     if (!std::isfinite(beta[q])) return Status{MFS_ERR_NUMERIC, "non-finite residual"};
     if (beta[q] == 0.0) continue;
     active[q] = 1;
-    launch_scale_copy(c->stream, n, 1.0 / beta[q], r + q * n, k.V + q * n);
-    H[q].assign((size_t)(maxit + 1) * maxit, 0.0);
-    cs[q].assign(maxit, 0.0);
-    sn[q].assign(maxit, 0.0);
-    g[q].assign(maxit + 1, 0.0);
-    g[q][0] = beta[q];
+    cq[kGmBeta] = beta[q];
+    cq[kGmTol] = tol[q] * beta[q];
+    cq[kGmDone] = 0.0;
+    g0[(size_t)q * (cap + 1)] = beta[q];
+    launch_scale_copy(s, n, 1.0 / beta[q], r + q * n, k.V + q * n);
   }
+  MFS_HIP(hipMemcpyAsync(k.ctl, ctl.data(), sizeof(double) * ctl.size(), hipMemcpyHostToDevice, s));
+  MFS_HIP(hipMemcpyAsync(k.g, g0.data(), sizeof(double) * g0.size(), hipMemcpyHostToDevice, s));
   const bool prof = std::getenv("MFS_PROFILE") != nullptr;
   auto t_start = clk::now();
+  bool use32_last = false;
+  // read iteration jj's records (the host waits for that iteration's event first)
+  auto absorb = [&](int jj) -> Status {
+    MFS_HIP(hipEventSynchronize(k.ev[jj & 1]));
+    double worst = 0.0;
+    for (int q = 0; q < R; ++q) {
+      const double* o = k.hrec + ((int64_t)jj * R + q) * 4;
+      if (o[3] != 0.0) return Status{MFS_ERR_NUMERIC, "non-finite value in the Arnoldi process"};
+      if (!active[q]) continue;
+      if ((int)o[2] == jj + 1) {   // this iteration advanced right-hand side q
+        rel[q] = o[0];
+        hist[q].push_back(o[0]);
+      }
+      if (o[1] != 0.0) active[q] = 0;
+      else worst = std::max(worst, rel[q]);
+    }
+    est[jj] = worst;
+    if (!force64 && worst > 0.0 && stalled(est, first32, jj)) {
+      force64 = true;
+      if (prof) std::fprintf(stderr, "[mfs gmres x%d] mixed phase stalled at it %d: FP64 from here\n", R, jj + 1);
+    }
+    if (prof && ((jj + 1) % 10 == 0))
+      std::fprintf(stderr, "[mfs gmres x%d] %s it %d worst active resid %.3e  %.1f s\n", R,
+                   use32_last ? "fp32-sum" : "fp64", jj + 1, worst, ms_since(t_start) * 1e-3);
+    return Status{};
+  };
+  int launched = 0, absorbed = 0;
   for (int j = 0; j < maxit; ++j) {
     bool any = false, all_low = true;
     for (int q = 0; q < R; ++q)
@@ -266,7 +230,8 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, dou
     bool use32 = mixed && all_low && !force64;
     double* vj = k.V + (int64_t)j * ldv;
     if (use32 && op_err < 0.0) {
-      // first switch: measure the mixed operator on the active basis vectors (see gmres_core)
+      // first switch: measure the mixed operator on the active basis vectors against the FP64
+      // one (which this iteration keeps), then move the switch points
       if ((st = apply_T_rhs(c, prob, false, R, vj, k.w)).code) return st;
       if ((st = apply_T_rhs(c, prob, true, R, vj, k.tmp)).code) return st;
       double e = 0.0;
@@ -276,92 +241,50 @@ Status gmres_core_rhs(mfs_ctx* c, int prob, bool mixed, int R, double delta, dou
         if (st.code) return st;
       }
       op_err = e;
-      for (int q = 0; q < R; ++q) switch_below[q] = switch_point(mixed, tol[q], delta, op_err);
+      for (int q = 0; q < R; ++q) switch_below[q] = switch_point(mixed, tol[q], delta, op_err, max_err);
       if (prof) std::fprintf(stderr, "[mfs gmres x%d] mixed operator relative error %.2e\n", R, op_err);
       use32 = false;
     } else if ((st = apply_T_rhs(c, prob, use32, R, vj, k.w)).code) {
       return st;
     }
     if (use32 && first32 < 0) first32 = j;
+    use32_last = use32;
     for (int q = 0; q < R; ++q) {
-      if (!active[q]) continue;
+      if (!active[q]) continue;   // the device zero-feeds it
       const double* Vq = k.V + q * n;
       double* wq = k.w + q * n;
       double* hq = k.hdev + q * hstride;
-      launch_mdot(c->stream, n, j + 1, Vq, ldv, wq, k.part, hq, nblk);
-      launch_maxpy(c->stream, n, j + 1, Vq, ldv, hq, wq);
-      launch_mdot(c->stream, n, j + 1, Vq, ldv, wq, k.part, hq + (cap + 2), nblk);
-      launch_maxpy(c->stream, n, j + 1, Vq, ldv, hq + (cap + 2), wq);
-      launch_mdot(c->stream, n, 1, wq, n, wq, k.part, hq + 2 * (cap + 2), nblk);
+      launch_mdot(s, n, j + 1, Vq, ldv, wq, k.part, hq, nblk);
+      launch_maxpy(s, n, j + 1, Vq, ldv, hq, wq);
+      launch_mdot(s, n, j + 1, Vq, ldv, wq, k.part, hq + (cap + 2), nblk);
+      launch_maxpy(s, n, j + 1, Vq, ldv, hq + (cap + 2), wq);
+      launch_mdot(s, n, 1, wq, n, wq, k.part, hq + 2 * (cap + 2), nblk);
     }
-    MFS_HIP(hipMemcpyAsync(k.hhost, k.hdev, sizeof(double) * hstride * R, hipMemcpyDeviceToHost, c->stream));
-    MFS_HIP(hipStreamSynchronize(c->stream));
-    double* vn = k.V + (int64_t)(j + 1) * ldv;
-    for (int q = 0; q < R; ++q) {
-      if (!active[q]) {
-        MFS_HIP(hipMemsetAsync(vn + q * n, 0, sizeof(double) * n, c->stream));
-        continue;
-      }
-      const double* hh = k.hhost + q * hstride;
-      auto Hc = [&](int row, int col) -> double& { return H[q][(size_t)col * (maxit + 1) + row]; };
-      for (int i = 0; i <= j; ++i) Hc(i, j) = hh[i] + hh[(cap + 2) + i];
-      const double hn = std::sqrt(std::max(0.0, hh[2 * (cap + 2)]));
-      Hc(j + 1, j) = hn;
-      for (int i = 0; i <= j + 1; ++i)
-        if (!std::isfinite(Hc(i, j))) return Status{MFS_ERR_NUMERIC, "non-finite value in the Arnoldi process"};
-      if (hn > 0.0)
-        launch_scale_copy(c->stream, n, 1.0 / hn, k.w + q * n, vn + q * n);
-      else
-        MFS_HIP(hipMemsetAsync(vn + q * n, 0, sizeof(double) * n, c->stream));
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[q][i] * Hc(i, j) + sn[q][i] * Hc(i + 1, j);
-        Hc(i + 1, j) = -sn[q][i] * Hc(i, j) + cs[q][i] * Hc(i + 1, j);
-        Hc(i, j) = t;
-      }
-      const double den = std::hypot(Hc(j, j), Hc(j + 1, j));
-      cs[q][j] = Hc(j, j) / den;
-      sn[q][j] = Hc(j + 1, j) / den;
-      Hc(j, j) = den;
-      Hc(j + 1, j) = 0.0;
-      g[q][j + 1] = -sn[q][j] * g[q][j];
-      g[q][j] = cs[q][j] * g[q][j];
-      kdone[q] = j + 1;
-      rel[q] = std::fabs(g[q][j + 1]) / beta[q];
-      hist[q].push_back(rel[q]);
-      if (std::fabs(g[q][j + 1]) <= tol[q] * beta[q] || hn == 0.0) active[q] = 0;
-    }
-    {
-      double worst = 0.0;
-      for (int q = 0; q < R; ++q)
-        if (active[q]) worst = std::max(worst, rel[q]);
-      est[j] = worst;
-      if (!force64 && worst > 0.0 && stalled(est, first32, j)) {
-        force64 = true;
-        if (prof) std::fprintf(stderr, "[mfs gmres x%d] mixed phase stalled at it %d: FP64 from here\n", R, j + 1);
-      }
-    }
-    if (prof && ((j + 1) % 10 == 0)) {
-      double worst = 0;
-      for (int q = 0; q < R; ++q) worst = std::max(worst, active[q] ? rel[q] : 0.0);
-      std::fprintf(stderr, "[mfs gmres x%d] %s it %d worst active resid %.3e  %.1f s\n", R,
-                   use32 ? "fp32-sum" : "fp64", j + 1, worst, ms_since(t_start) * 1e-3);
+    launch_givens(s, j, cap, R, k.hdev, hstride, k.H, k.cs, k.sn, k.g, k.ctl, k.rec);
+    launch_scale_ctl(s, n, R, k.ctl, k.w, k.V + (int64_t)(j + 1) * ldv);
+    MFS_HIP(hipMemcpyAsync(k.hrec + (int64_t)j * R * 4, k.rec + (int64_t)j * R * 4, sizeof(double) * 4 * R,
+                           hipMemcpyDeviceToHost, s));
+    MFS_HIP(hipGetLastError());
+    MFS_HIP(hipEventRecord(k.ev[j & 1], s));
+    launched = j + 1;
+    // iteration j runs while the host reads iteration j - 1
+    if (j >= 1) {
+      if ((st = absorb(j - 1)).code) return st;
+      absorbed = j;
     }
   }
+  MFS_HIP(hipStreamSynchronize(s));
+  for (int jj = absorbed; jj < launched; ++jj)
+    if ((st = absorb(jj)).code) return st;
+  MFS_HIP(hipMemcpyAsync(ctl.data(), k.ctl, sizeof(double) * ctl.size(), hipMemcpyDeviceToHost, s));
+  MFS_HIP(hipStreamSynchronize(s));
+  launch_backsolve(s, cap, R, k.H, k.g, k.ctl, k.y);
   for (int q = 0; q < R; ++q) {
-    iters[q] = kdone[q];
-    if (kdone[q] == 0) continue;
-    auto Hc = [&](int row, int col) -> double& { return H[q][(size_t)col * (maxit + 1) + row]; };
-    std::vector<double> y(kdone[q]);
-    for (int i = kdone[q] - 1; i >= 0; --i) {
-      double sum = g[q][i];
-      for (int p = i + 1; p < kdone[q]; ++p) sum -= Hc(i, p) * y[p];
-      y[i] = sum / Hc(i, i);
-    }
-    double* hq = k.hdev + q * hstride;
-    MFS_HIP(hipMemcpyAsync(hq, y.data(), sizeof(double) * kdone[q], hipMemcpyHostToDevice, c->stream));
-    launch_gemv_n(c->stream, n, kdone[q], k.V + q * n, ldv, hq, k.d + q * n);
-    MFS_HIP(hipStreamSynchronize(c->stream));   // y is released at the end of this scope
+    iters[q] = (int)ctl[(size_t)q * kGmCtl + kGmK];
+    if (iters[q] > 0) launch_gemv_n(s, n, iters[q], k.V + q * n, ldv, k.y + (int64_t)q * (cap + 1), k.d + q * n);
   }
+  MFS_HIP(hipGetLastError());
+  MFS_HIP(hipStreamSynchronize(s));
   return Status{};
 }
 
@@ -408,72 +331,8 @@ struct SolveTotals {
   bool noconv = false;
 };
 
-// One right-hand side: FP64 refinement around gmres_core (see the file comment).
-Status solve_one(mfs_ctx* c, int prob, bool mixed, const double* given, double* out, const double* x0, double tol,
-                 int max_iter, mfs_solve_info* info, SolveTotals& tot) {
-  Krylov& k = c->kr;
-  const int64_t n = k.n;
-  Status st;
-  auto t0 = clk::now();
-  mfs_status s = mfs_rhs(c, (mfs_problem)prob, given, k.b);
-  if (s != MFS_OK) return c->last;
-  tot.t_rhs += ms_since(t0);
-  t0 = clk::now();
-  const double bn = dnorm(c, k.b, &st);
-  if (st.code) return st;
-  if (x0)
-    MFS_HIP(hipMemcpyAsync(k.x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-  else
-    MFS_HIP(hipMemsetAsync(k.x, 0, sizeof(double) * n, c->stream));
-  std::vector<double> hist;
-  const int max_outer = mixed ? 10 : 3;
-  int used = 0;
-  double rel = 1.0;
-  double delta = mixed_delta(prob);
-  double op_err = -1.0;   // measured at the first switch to the mixed operator
-  for (int o = 0; o < max_outer; ++o) {
-    // r = b - T64 x
-    if (o == 0 && !x0) {
-      MFS_HIP(hipMemcpyAsync(k.r, k.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-    } else {
-      if ((st = apply_T(c, prob, false, k.x, k.tmp)).code) return st;
-      MFS_HIP(hipMemcpyAsync(k.r, k.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-      launch_axpby(c->stream, n, -1.0, k.tmp, 1.0, k.r);
-    }
-    const double rn = dnorm(c, k.r, &st);
-    if (st.code) return st;
-    if (!std::isfinite(rn)) return Status{MFS_ERR_NUMERIC, "non-finite residual"};
-    rel = bn > 0 ? rn / bn : 0.0;
-    if (rel <= tol || used >= max_iter) break;
-    if (mixed && o > 0) delta = escalate(delta, op_err, rel / tol);
-    tot.outer = std::max(tot.outer, o + 1);
-    // reach the target in one pass if the operator allows it
-    const double tin = tol * bn / rn;
-    if (std::getenv("MFS_PROFILE"))
-      std::fprintf(stderr, "[mfs gmres] refinement %d: |r|/|b| = %.3e, inner tol %.3e, mixed below %.3e\n", o, rel,
-                   tin, switch_point(mixed, tin, delta, op_err));
-    int it = 0;
-    if ((st = gmres_core(c, prob, mixed, delta, op_err, k.r, tin, max_iter - used, &it, hist)).code) return st;
-    used += it;
-    launch_axpby(c->stream, n, 1.0, k.d, 1.0, k.x);
-    if (it == 0) break;
-  }
-  tot.iters += used;
-  tot.t_it += ms_since(t0);
-  t0 = clk::now();
-  s = mfs_post(c, (mfs_problem)prob, k.x, out);
-  if (s != MFS_OK) return c->last;
-  tot.t_post += ms_since(t0);
-  if (info && info->resid_hist && info->hist_cap > 0)
-    for (double h : hist)
-      if (tot.hist_len < info->hist_cap) info->resid_hist[tot.hist_len++] = h;
-  tot.rel = std::max(tot.rel, rel);
-  if (rel > tol) tot.noconv = true;
-  return Status{};
-}
-
-// R right-hand sides in lockstep (2 <= R <= Krylov rcap): the refinement of solve_one
-// with stacked residuals and gmres_core_rhs; each right-hand side stops on its own.
+// R right-hand sides in lockstep (1 <= R <= Krylov rcap): FP64 refinement on the true
+// residual around gmres_core_rhs (see the file comment); each right-hand side stops on its own.
 Status solve_stacked(mfs_ctx* c, int prob, bool mixed, int R, const double* given, double* out, const double* x0,
                      double tol, int max_iter, mfs_solve_info* info, SolveTotals& tot) {
   Krylov& k = c->kr;
@@ -607,8 +466,7 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
     const double* g = rhs + 3 * (size_t)c->P * r0;
     double* o = out + 3 * (size_t)c->P * r0;
     const double* x = x0 ? x0 + n * r0 : nullptr;
-    st = Rc == 1 ? solve_one(c, prob, mixed, g, o, x, tol, max_iter, info, tot)
-                 : solve_stacked(c, prob, mixed, Rc, g, o, x, tol, max_iter, info, tot);
+    st = solve_stacked(c, prob, mixed, Rc, g, o, x, tol, max_iter, info, tot);
     if (st.code) return failc(st);
     if (hipMemcpyAsync(c->d_mu_last + n * r0, c->kr.x, sizeof(double) * n * Rc, hipMemcpyDeviceToDevice,
                        c->stream) != hipSuccess)

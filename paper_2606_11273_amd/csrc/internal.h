@@ -86,6 +86,12 @@ struct Krylov {
   double* b = nullptr;
   double* d = nullptr;
   double* tmp = nullptr;
+  // device least squares (k_givens): per right-hand side H ((cap + 1) x cap), cs, sn (cap),
+  // g (cap + 1), y (cap + 1), ctl (kGmCtl); per iteration and right-hand side 4 record values,
+  // mirrored in pinned host memory
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *ctl = nullptr, *rec = nullptr;
+  double* hrec = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
 }  // namespace mfs
@@ -243,6 +249,12 @@ void launch_maxpy(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv,
 void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y);
 void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, double* y);
 void launch_gemv_n(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* y, double* x);
+// GMRES least squares on the device: control record per right-hand side
+constexpr int kGmBeta = 0, kGmTol = 1, kGmInv = 2, kGmK = 3, kGmDone = 4, kGmBad = 5, kGmEst = 6, kGmCtl = 8;
+void launch_givens(hipStream_t s, int j, int cap, int R, const double* hdev, int64_t hstride, double* H, double* cs,
+                   double* sn, double* g, double* ctl, double* rec);
+void launch_scale_ctl(hipStream_t s, int64_t n, int R, const double* ctl, const double* x, double* y);
+void launch_backsolve(hipStream_t s, int cap, int R, const double* H, const double* g, const double* ctl, double* y);
 int mdot_blocks(int64_t n);
 
 // ---- precompute (precompute.hip) ----

@@ -1528,6 +1528,122 @@ __global__ void k_gemv_n(int64_t n, int k, const double* __restrict__ V, int64_t
   x[i] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// GMRES least squares on the device (Alg. 2, GMRES).  One wave per right-hand side r adds
+// column j to the Hessenberg matrix (the two CGS2 coefficient sets plus the norm of the
+// orthogonalised vector), applies the previous Givens rotations and a new one, updates the
+// rotated right-hand side g and records the residual estimate |g_{j+1}| / beta.  Once the
+// estimate reaches tol beta (or h_{j+1,j} = 0) the right-hand side is done: later calls leave
+// its state alone and set its scale to 0, so its next basis vectors are zero.  Per right-hand
+// side: H column-major (cap + 1) x cap, cs and sn (cap), g (cap + 1), ctl (kGmCtl values) and,
+// per iteration, rec[(j R + r) 4 ..] = estimate, done, iterations, non-finite flag (for the host).
+__global__ __launch_bounds__(64) void k_givens(int j, int cap, int R, const double* __restrict__ hdev,
+                                               int64_t hstride, double* __restrict__ H, double* __restrict__ cs,
+                                               double* __restrict__ sn, double* __restrict__ g,
+                                               double* __restrict__ ctl, double* __restrict__ rec) {
+  __shared__ double col[1026];
+  __shared__ double s_cs[1024], s_sn[1024];
+  const int r = blockIdx.x;
+  if (r >= R || j >= cap) return;
+  double* c = ctl + (int64_t)r * kGmCtl;
+  const bool done = c[kGmDone] != 0.0;
+  const double* hq = hdev + (int64_t)r * hstride;
+  double* csr = cs + (int64_t)r * cap;
+  double* snr = sn + (int64_t)r * cap;
+  if (!done) {
+    for (int i = threadIdx.x; i <= j; i += 64) col[i] = hq[i] + hq[(cap + 2) + i];
+    for (int i = threadIdx.x; i < j; i += 64) {
+      s_cs[i] = csr[i];
+      s_sn[i] = snr[i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double* o = rec + ((int64_t)j * R + r) * 4;
+  if (done) {
+    c[kGmInv] = 0.0;
+    o[0] = c[kGmEst];
+    o[1] = 1.0;
+    o[2] = c[kGmK];
+    o[3] = c[kGmBad];
+    return;
+  }
+  const double hn = sqrt(fmax(0.0, hq[2 * (cap + 2)]));
+  bool bad = !isfinite(hn);
+  for (int i = 0; i <= j; ++i) bad = bad || !isfinite(col[i]);
+  if (bad) {
+    c[kGmBad] = 1.0;
+    c[kGmDone] = 1.0;
+    c[kGmInv] = 0.0;
+    o[0] = c[kGmEst];
+    o[1] = 1.0;
+    o[2] = c[kGmK];
+    o[3] = 1.0;
+    return;
+  }
+  // previous rotations, the running entry kept in a register
+  double a = col[0];
+  for (int i = 0; i < j; ++i) {
+    const double b = col[i + 1];
+    col[i] = s_cs[i] * a + s_sn[i] * b;
+    a = -s_sn[i] * a + s_cs[i] * b;
+  }
+  const double den = hypot(a, hn);
+  const double cj = a / den, sj = hn / den;
+  col[j] = den;
+  double* Hc = H + (int64_t)r * (cap + 1) * cap + (int64_t)j * (cap + 1);
+  for (int i = 0; i <= j; ++i) Hc[i] = col[i];
+  Hc[j + 1] = 0.0;
+  csr[j] = cj;
+  snr[j] = sj;
+  double* gr = g + (int64_t)r * (cap + 1);
+  const double gj = gr[j];
+  gr[j + 1] = -sj * gj;
+  gr[j] = cj * gj;
+  const double est = fabs(gr[j + 1]) / c[kGmBeta];
+  const bool conv = fabs(gr[j + 1]) <= c[kGmTol] || hn == 0.0;
+  c[kGmK] = (double)(j + 1);
+  c[kGmEst] = est;
+  c[kGmInv] = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (conv) c[kGmDone] = 1.0;
+  o[0] = est;
+  o[1] = conv ? 1.0 : 0.0;
+  o[2] = (double)(j + 1);
+  o[3] = 0.0;
+}
+
+// y = x * ctl[kGmInv] for each right-hand side (blockIdx.y): the next basis vector
+__global__ void k_scale_ctl(int64_t n, const double* __restrict__ ctl, const double* __restrict__ x,
+                            double* __restrict__ y) {
+  const int r = blockIdx.y;
+  const double a = ctl[(int64_t)r * kGmCtl + kGmInv];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[(int64_t)r * n + i] = x[(int64_t)r * n + i] * a;
+}
+
+// y = H(0:k, 0:k)^{-1} g(0:k) by back substitution, k = ctl[kGmK] (one workgroup per
+// right-hand side, the solution held in LDS, a column of H per step)
+__global__ __launch_bounds__(256) void k_backsolve(int cap, const double* __restrict__ H,
+                                                   const double* __restrict__ g, const double* __restrict__ ctl,
+                                                   double* __restrict__ y) {
+  __shared__ double s_y[1024];
+  const int r = blockIdx.x;
+  const int k = (int)ctl[(int64_t)r * kGmCtl + kGmK];
+  const double* Hr = H + (int64_t)r * (cap + 1) * cap;
+  const double* gr = g + (int64_t)r * (cap + 1);
+  for (int i = threadIdx.x; i < k; i += 256) s_y[i] = gr[i];
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    const double* Hi = Hr + (int64_t)i * (cap + 1);
+    const double yi = s_y[i] / Hi[i];
+    __syncthreads();
+    for (int q = threadIdx.x; q < i; q += 256) s_y[q] -= Hi[q] * yi;
+    if (threadIdx.x == 0) s_y[i] = yi;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < k; i += 256) y[(int64_t)r * (cap + 1) + i] = s_y[i];
+}
+
 __global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = a * x[i];
@@ -2016,6 +2132,19 @@ void launch_maxpy(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv,
 
 void launch_gemv_n(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* y, double* x) {
   hipLaunchKernelGGL(k_gemv_n, dim3(nblocks(n, 256)), dim3(256), 0, s, n, k, V, ldv, y, x);
+}
+
+void launch_givens(hipStream_t s, int j, int cap, int R, const double* hdev, int64_t hstride, double* H, double* cs,
+                   double* sn, double* g, double* ctl, double* rec) {
+  hipLaunchKernelGGL(k_givens, dim3(R), dim3(64), 0, s, j, cap, R, hdev, hstride, H, cs, sn, g, ctl, rec);
+}
+
+void launch_scale_ctl(hipStream_t s, int64_t n, int R, const double* ctl, const double* x, double* y) {
+  hipLaunchKernelGGL(k_scale_ctl, dim3(nblocks(n, 256), R), dim3(256), 0, s, n, ctl, x, y);
+}
+
+void launch_backsolve(hipStream_t s, int cap, int R, const double* H, const double* g, const double* ctl, double* y) {
+  hipLaunchKernelGGL(k_backsolve, dim3(R), dim3(256), 0, s, cap, H, g, ctl, y);
 }
 
 void launch_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
