@@ -191,6 +191,18 @@ mfs_status mfs_get_pair_matrices(const mfs_ctx* ctx, mfs_problem prob, double* A
 mfs_status mfs_apply(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t n_rhs,
                      const double* mu_in, double* u_out);
 
+/* mfs_apply for one vector (n_rhs = 1) that allocates no device memory, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The kernel sum's split partials, which mfs_apply keeps in a buffer of the
+ * context grown on first use, go to a static scratch array of 128 MiB that every context
+ * on the device shares (each device holds its own copy until the process ends).  Calls that
+ * overlap in time on one device race on that array: run them on one stream, or order them.
+ * The result equals mfs_apply's (same kernels, same split count).  mu_in, u_out: device, n
+ * doubles, not overlapping.  Errors: as mfs_apply; MFS_ERR_ARG when the split partials of
+ * this context (split count x 2 N_t doubles, e.g. 4 x 1.44e6 at P = 10^4) exceed the array. */
+mfs_status mfs_apply_noalloc(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, const double* mu_in,
+                             double* u_out);
+
 /* Plain all-pairs Stokeslet sum over the context's coarse sources and nodes
  * (eq. getall): u[t] = sum_s S(x_t, y_s) sigma[s].  skip = 0: every source;
  * skip = 1: sources of the target's own disk are left out; skip = 2: also those

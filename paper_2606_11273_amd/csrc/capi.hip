@@ -545,6 +545,7 @@ mfs_status mfs_setup_ex(mfs_ctx** out, int32_t P, const double* centers, const d
     return fail(nullptr, Status{MFS_ERR_DEVICE, "rocBLAS handle creation failed"});
   }
   Status st = build(c, centers, radii, n_src, n_col, r_src);
+  if (!st.code) st = scratch_for_current_device(&c->scratch);
   if (st.code) {
     free_all(c);
     delete c;
@@ -649,6 +650,27 @@ mfs_status mfs_apply(mfs_ctx* c, mfs_problem prob, mfs_precision prec, int32_t n
   if (!c->ps[prob].ready && !c->pairs.empty())
     return fail(c, Status{MFS_ERR_STATE, "mfs_precompute_pairs has not run for this problem"});
   Status st = apply_T_rhs(c, prob, prec == MFS_MIXED, n_rhs, mu_in, u_out);
+  if (st.code) return fail(c, st);
+  return ok(c);
+}
+
+mfs_status mfs_apply_noalloc(mfs_ctx* c, mfs_problem prob, mfs_precision prec, const double* mu_in,
+                             double* u_out) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if ((prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || (prec != MFS_FP64 && prec != MFS_MIXED) || !mu_in ||
+      !u_out)
+    return fail(c, Status{MFS_ERR_ARG, "bad argument"});
+  if (!c->ps[prob].ready && !c->pairs.empty())
+    return fail(c, Status{MFS_ERR_STATE, "mfs_precompute_pairs has not run for this problem"});
+  if (!c->scratch) return fail(c, Status{MFS_ERR_STATE, "no scratch array resolved for this context's device"});
+  const bool mixed = prec == MFS_MIXED;
+  const int64_t need = ksum_split_doubles(c, mixed);
+  if (need > kScratchDoubles)
+    return fail(c, Status{MFS_ERR_ARG, "the kernel sum's split partials (" + std::to_string(need * 8) +
+                                           " bytes) exceed the no-allocation scratch array (" +
+                                           std::to_string(kScratchDoubles * 8) + " bytes)"});
+  const SplitBuf sb{c->scratch, kScratchDoubles};
+  Status st = apply_T(c, prob, mixed, mu_in, u_out, &sb);
   if (st.code) return fail(c, st);
   return ok(c);
 }

@@ -145,6 +145,7 @@ struct mfs_ctx {
   int32_t* d_body_cl = nullptr;  // P: cluster of each disk
   int32_t* d_tperm = nullptr;    // Nt: the kernel sums visit targets in slot order (disk by disk)
   unsigned long long* d_work = nullptr;   // kernel-sum work counters: direct pairs, disk and cluster expansions
+  double* scratch = nullptr;     // the device's static scratch array (mfs_apply_noalloc), resolved at setup
 
   // work vectors
   double *d_lam_bar = nullptr, *d_ltil = nullptr, *d_sig64 = nullptr, *d_u = nullptr, *d_corr = nullptr;
@@ -221,7 +222,9 @@ bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale
 int64_t ksum_split_doubles(const mfs_ctx* c, bool mixed);
 // zero the kernel-sum work counters (a kernel, so that the call may sit in a captured graph)
 void launch_zero_work(mfs_ctx* c);
-
+// the device's static scratch array for mfs_apply_noalloc (kernels.hip), resolved once per device
+constexpr int64_t kScratchDoubles = (int64_t)16 << 20;   // 128 MiB
+Status scratch_for_current_device(double** ptr);
 void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr);
 void launch_finish(mfs_ctx* c, const double* u_sum, const double* mu, const double* corr, double* u_out,
                    bool with_pairs);

@@ -9,8 +9,14 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 
 #include "internal.h"
+
+// Scratch of mfs_apply_noalloc: the kernel sum's split partials for callers that cannot
+// allocate device memory.  One copy per device, held until the process ends; host code
+// uses the address hipGetSymbolAddress returns for the current device, never this name.
+static __device__ __align__(256) double scratch[mfs::kScratchDoubles];
 
 namespace mfs {
 
@@ -1887,6 +1893,30 @@ inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); 
 
 // ---------------------------------------------------------------------------
 // launchers
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // per device: the address of its copy of scratch
+}  // namespace
+
+Status scratch_for_current_device(double** ptr) {
+  *ptr = nullptr;
+  int dev = 0;
+  MFS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return Status{MFS_ERR_DEVICE, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e)};
+    }
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return Status{};
+}
 
 void launch_zero_work(mfs_ctx* c) {
   hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(64), 0, c->stream, c->d_work);

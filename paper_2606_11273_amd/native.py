@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "MFS_OK", 1: "MFS_ERR_ARG", 2: "MFS_ERR_GEOMETRY", 3: "MFS_ER
 
 # Exported symbols, in the order of include/mfs.h.
 SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_pairs", "mfs_get_clusters", "mfs_set_pair_matrices",
-           "mfs_get_pair_matrices", "mfs_apply", "mfs_kernel_sum", "mfs_kernel_sum_work", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
+           "mfs_get_pair_matrices", "mfs_apply", "mfs_apply_noalloc", "mfs_kernel_sum", "mfs_kernel_sum_work", "mfs_rhs", "mfs_post", "mfs_gmres_solve",
            "mfs_get_sizes", "mfs_destroy", "mfs_last_error", "mfs_server_create", "mfs_server_footprint",
            "mfs_server_submit", "mfs_server_wait", "mfs_server_last_error", "mfs_server_destroy",
            "mfs_keep_fine_factors", "mfs_get_density", "mfs_flow_eval", "mfs_boundary_residual",
@@ -138,6 +138,7 @@ def lib():
     L.mfs_set_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
     L.mfs_get_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
     L.mfs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int32, vp, vp]
+    L.mfs_apply_noalloc.argtypes = [vp, C.c_int, C.c_int, vp, vp]
     L.mfs_kernel_sum.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
     L.mfs_kernel_sum_work.argtypes = [vp, i64p, C.c_int32]
     L.mfs_rhs.argtypes = [vp, C.c_int, dp, vp]
@@ -284,6 +285,11 @@ def mfs_get_pair_matrices(ctx, problem, n_src):
 
 def mfs_apply(ctx, problem, precision, mu, u, n_rhs=1):
     _check(lib().mfs_apply(ctx, PROBLEMS[problem], PRECISIONS[precision], n_rhs, _dev(mu), _dev(u)), ctx)
+
+
+def mfs_apply_noalloc(ctx, problem, precision, mu, u):
+    """mfs_apply for one vector with no device allocation (split partials in the static scratch)."""
+    _check(lib().mfs_apply_noalloc(ctx, PROBLEMS[problem], PRECISIONS[precision], _dev(mu), _dev(u)), ctx)
 
 
 def mfs_kernel_sum_work(ctx, reset=False):
