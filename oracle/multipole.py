@@ -28,6 +28,8 @@ error below about sum_s |sigma_s| theta^(p+1) / (1 - theta) (units of 4 pi mu), 
 
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -93,3 +95,59 @@ def far_field_general(Z, A, B, D, mu=1.0):
     Q = sum(np.conj(D[k]) * zb ** k for k in range(p + 1))
     u = u + zb / 2 * (Z * P - Q)
     return u / (4 * np.pi * mu)
+
+
+def local_expansion(A, B, D, Delta, q):
+    """Local (Taylor) expansion about a point T of the field of sources with cluster_moments
+    A, B, D about C, Delta = T - C (complex, |Delta| > the sources' radius), to order q.
+
+    far_field_general is, with Z = x - C and F(Z) = sum_{k>=0} A_k Z^-(k+1),
+      4 pi mu u = Phi1(Z) + conj(Phi2(Z)) - Z conj(Phi1'(Z)) + A_0 / 2,
+      Phi1 = -(A_0/2) log Z + sum_{k>=1} A_k Z^-k / (2k),           Phi1' = -F / 2,
+      Phi2 = -(conj(A_0)/2) log Z + sum_{k>=1} conj(B_k) Z^-k / (2k) - (1/2) sum_{k>=0} D_k Z^-(k+1),
+    (Goursat's form of a plane Stokes flow).  Writing Z = w + Delta with w = x - T moves the
+    non-analytic factor to the target side: -Z conj(Phi1') = -w conj(Phi1') + conj(-conj(Delta) Phi1'),
+    so with Psi = Phi2 - conj(Delta) Phi1' (analytic near T)
+      4 pi mu u = Phi1 + conj(Psi) - w conj(Phi1') + A_0 / 2.
+    Each of f = Phi1, Psi is a log term a log Z plus sum_k c_k Z^-k; about T
+      log(w + Delta) = log Delta - sum_{l>=1} (-w/Delta)^l / l,
+      (w + Delta)^-k = sum_{l>=0} (-1)^l binom(k + l - 1, l) Delta^-(k+l) w^l.
+    Only Re log enters u (the imaginary parts of Phi1's and conj(Psi)'s log terms cancel), so
+    log Delta is taken as log|Delta|.  Returns (L1, L2, const): the coefficients of w^0..w^q of
+    Phi1 and Psi and A_0 / 2."""
+    A = np.asarray(A, dtype=np.complex128)
+    B = np.asarray(B, dtype=np.complex128)
+    D = np.asarray(D, dtype=np.complex128)
+    p = len(A) - 1
+    Delta = complex(Delta)
+    a1 = -A[0] / 2
+    a2 = -np.conj(A[0]) / 2
+    c1 = np.zeros(p + 2, dtype=np.complex128)
+    c2 = np.zeros(p + 2, dtype=np.complex128)
+    for k in range(1, p + 2):
+        if k <= p:
+            c1[k] = A[k] / (2 * k)
+            c2[k] += np.conj(B[k]) / (2 * k)
+        c2[k] += -D[k - 1] / 2 + np.conj(Delta) * A[k - 1] / 2
+
+    def taylor(a, c):
+        L = np.zeros(q + 1, dtype=np.complex128)
+        L[0] = a * math.log(abs(Delta)) + sum(c[k] * Delta ** (-k) for k in range(1, p + 2))
+        for l in range(1, q + 1):
+            L[l] = -a * (-1) ** l / (l * Delta ** l) + sum(
+                c[k] * (-1) ** l * math.comb(k + l - 1, l) * Delta ** (-k - l) for k in range(1, p + 2))
+        return L
+
+    return taylor(a1, c1), taylor(a2, c2), A[0] / 2
+
+
+def eval_local(w, L1, L2, const, mu=1.0):
+    """Velocity (complex) at offsets w from the expansion point of a local expansion
+    (local_expansion, or a sum of several): u = L1(w) + conj(L2(w)) - w conj(L1'(w)) + const,
+    in units of 1 / (4 pi mu)."""
+    w = np.asarray(w, dtype=np.complex128)
+    q = len(L1) - 1
+    v1 = sum(L1[l] * w ** l for l in range(q + 1))
+    d1 = sum(l * L1[l] * w ** (l - 1) for l in range(1, q + 1))
+    v2 = sum(L2[l] * w ** l for l in range(q + 1))
+    return (v1 + np.conj(v2) - w * np.conj(d1) + const) / (4 * np.pi * mu)

@@ -16,7 +16,7 @@ import pytest
 
 from oracle.geometry import rigid_map, rigid_projector, ring
 from oracle.kernel import direct_sum
-from oracle.multipole import cluster_moments, far_field, far_field_general, moments
+from oracle.multipole import cluster_moments, eval_local, far_field, far_field_general, local_expansion, moments
 
 
 def _case(n, rho, seed, project=False):
@@ -126,3 +126,68 @@ def test_cluster_moments_of_a_ring_reduce_to_the_ring_form():
     x = _points(c, 0.7 / 0.3)
     Z = (x[:, 0] - c[0]) + 1j * (x[:, 1] - c[1])
     assert np.allclose(far_field_general(Z, A, B, D), far_field(Z, A, B, 0.7), rtol=0, atol=1e-15)
+
+
+def _local_sum(groups, T, q, p):
+    """Sum of the local expansions about T of several source groups (sources y, strengths sig,
+    expansion centre C): (L1, L2, const)."""
+    L1 = np.zeros(q + 1, complex)
+    L2 = np.zeros(q + 1, complex)
+    const = 0.0
+    for y, sig, C in groups:
+        w = (y[:, 0] - C[0]) + 1j * (y[:, 1] - C[1])
+        s = sig[:, 0] + 1j * sig[:, 1]
+        a, b, cst = local_expansion(*cluster_moments(w, s, p), complex(T[0] - C[0], T[1] - C[1]), q)
+        L1, L2, const = L1 + a, L2 + b, const + cst
+    return L1, L2, const
+
+
+@pytest.mark.parametrize("direction", [(1.0, 0.6), (-1.0, 1e-9), (-1.0, -1e-9), (-0.3, -1.0)])
+def test_local_expansion_matches_direct_sum(direction):
+    # two clusters of rings (radius Rc about their centres) and targets within rt of T; the
+    # directions include Delta = T - C just above and below the negative real axis, where a
+    # complex log would jump by 2 pi i
+    mu = 1.1
+    y1, s1 = _cluster(7)
+    y2, s2 = _cluster(8)
+    d = np.array(direction) / np.linalg.norm(direction)
+    C1, C2 = np.array([0.0, 0.0]), -9.0 * d + 3.0 * np.array([-d[1], d[0]])
+    y2 = y2 + C2
+    Rc = max(np.abs(y1 - C1).max(), np.abs(y2 - C2).max()) * math.sqrt(2)
+    rt = 2.0
+    T = C1 + d * 3.2 * (Rc + rt)
+    rng = np.random.default_rng(9)
+    x = T + rng.uniform(-1, 1, (40, 2)) * rt / math.sqrt(2)
+    ref = direct_sum(x, np.concatenate([y1, y2]), np.concatenate([s1, s2]), mu)
+    theta = max((Rc + rt) / np.linalg.norm(T - C) for C in (C1, C2))
+    assert theta < 0.35
+    sabs = np.abs(np.concatenate([s1, s2])).sum(1).sum()
+    wt = (x[:, 0] - T[0]) + 1j * (x[:, 1] - T[1])
+    errs = []
+    for p in (10, 20, 30):
+        u = eval_local(wt, *_local_sum([(y1, s1, C1), (y2, s2, C2)], T, p, p), mu)
+        err = np.abs(np.stack([u.real, u.imag], axis=1) - ref).max()
+        errs.append(err)
+        assert err <= 10 * sabs * theta ** (p + 1) / (1 - theta) / (4 * math.pi * mu), (p, err)
+    assert errs[2] < 1e-13 * np.abs(ref).max()
+
+
+def test_local_expansion_of_mobility_strengths():
+    # zero net force and torque per disk (the mobility matvec's strengths): the field decays
+    # faster, and the expansion keeps the error relative to it
+    rng = np.random.default_rng(10)
+    cs = rng.uniform(-2.5, 2.5, (9, 2))
+    ys, ss = [], []
+    for cc in cs:
+        y = ring(cc, 0.7, 36)
+        K = rigid_map(y, cc)
+        sg = rng.standard_normal(72)
+        ys.append(y)
+        ss.append((sg - rigid_projector(K) @ sg).reshape(-1, 2))
+    y, sig = np.concatenate(ys), np.concatenate(ss)
+    C = np.zeros(2)
+    T = np.array([-14.0, 10.0])
+    x = T + rng.uniform(-1, 1, (30, 2))
+    ref = direct_sum(x, y, sig)
+    u = eval_local((x[:, 0] - T[0]) + 1j * (x[:, 1] - T[1]), *_local_sum([(y, sig, C)], T, 26, 26))
+    assert np.abs(np.stack([u.real, u.imag], axis=1) - ref).max() < 1e-12 * np.abs(ref).max()
