@@ -64,18 +64,50 @@ CL64_ORDER = 26             # the FP64 kernel sum's cluster expansions (same clu
 FLOP_PER_CLUSTER_EXPANSION64 = 32 * (CL64_ORDER - 1) + 64
 
 
-def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, tperm=None, threads_T=KSUM_T, block=256, wave=64):
-    """Work of one kernel-sum launch (FP32 or FP64) with the two-level far field: direct pair
-    evaluations, disk expansions and cluster expansions, each counted per target.
+def flop_per_translation(order):
+    """A cluster's expansion translated into a local expansion (both of the given order), two
+    analytic functions: the moments scaled by Delta^-k (6 flops each), the binomial sums (a real
+    times a complex number, 4 flops per term) and the scaling of the results by Delta^-l."""
+    return 2 * (4 * order * (order + 1) + 6 * order + 6 * (order + 1))
+
+
+def flop_per_local_evaluation(order):
+    """A local expansion at a target: three complex Horner series (L1, L1', L2), 8 flops a step."""
+    return 24 * order + 8
+
+
+LOC32_ORDER, LOC64_ORDER = 20, 26   # local expansion orders of the FP32 and FP64 kernel sums
+LOC32_SEP, LOC64_SEP = 3.0, 4.0     # their separation factors (theta <= 1/3, 1/4)
+
+
+def ksum_splits(n_targets, P, ncl=None, T=KSUM_T, block=256):
+    """The kernel sums' source-split count (doubled while the grid holds fewer than 8192
+    workgroups, at most 64 and P / 8; the FP32 sum at most one split per cluster)."""
+    tblocks = -(-n_targets // (block * T))
+    s = 1
+    while tblocks * s < 8192 and s * 2 <= max(1, P // 8) and s < 64:
+        s *= 2
+    return min(s, ncl) if ncl is not None else s
+
+
+def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, tperm=None, threads_T=KSUM_T, block=256, wave=64,
+                       local=True, splits=1, sep=LOC32_SEP):
+    """Work of one kernel-sum launch (FP32 or FP64) with the two-level far field and the
+    workgroups' local expansions: direct pair evaluations, disk expansions, cluster expansions
+    (each per target), cluster-to-local translations and local-expansion evaluations (per target).
 
     The kernels visit the targets in the order tperm (None: as given); position i of a grid of
     blocks of block * T positions belongs to thread (i mod block T) // T of block i // (block T)
     (a thread's T targets are consecutive), clamped to the last target in the ragged tail, so a
-    wave of `wave` consecutive threads holds wave * T consecutive positions and takes one path
-    for all its targets: a cluster's expansion when every
-    target is beyond 4 cluster radii; otherwise, per disk of the cluster, the disk's expansion
-    when every target is beyond 7 ring radii, else the direct sum over its sources.  Every lane
-    of a wave executes what the wave takes.  cl: mfs_get_clusters of the context."""
+    wave of `wave` consecutive threads holds wave * T consecutive positions.  A block's targets
+    have a bounding circle (centre b, radius rb); a cluster of radius R beyond both 4 R + rb and
+    sep (R + rb) of b goes into the block's local expansion (one translation; with `local`).
+    Otherwise a wave takes one path for all its targets: the cluster's expansion when every
+    target is beyond 4 cluster radii; else, per disk of the cluster, the disk's expansion when
+    every target is beyond 7 ring radii, else the direct sum over its sources.  Every lane of a
+    wave executes what the wave takes.  The clusters are shared among `splits` workgroups per
+    block (ceil(ncl / splits) consecutive clusters each); every one of them with a cluster in its
+    local expansion evaluates that expansion at its block's targets.  cl: mfs_get_clusters."""
     import numpy as np
     from scipy.spatial import cKDTree
     P = centers.shape[0]
@@ -95,24 +127,38 @@ def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, tperm=None, threads_
     wv = pos // (wave * threads_T)
     n_waves = nblk * (block // wave)
     lanes = wave * threads_T            # targets a wave handles, one path for all
+    # block bounding circles and the clusters each block takes into its local expansion
+    xb = X[tgt].reshape(nblk, per_blk, 2)
+    lo, hi = xb.min(axis=1), xb.max(axis=1)
+    bc = 0.5 * (lo + hi)
+    rb = 0.5 * np.sqrt(((hi - lo) ** 2).sum(axis=1)) * (1.0 + 1e-9) + 1e-9
+    R = cl["radius"]
+    d2 = ((bc[:, None, :] - cl["centre"][None, :, :]) ** 2).sum(axis=2)
+    thr = np.maximum(4.0 * (1.0 + 1e-6) * R[None, :] + rb[:, None], sep * (R[None, :] + rb[:, None]))
+    le = (d2 > thr * thr) if local else np.zeros((nblk, ncl), dtype=bool)   # (blocks, clusters)
+    translations = int(le.sum())
+    cps = -(-ncl // splits)
+    used = np.add.reduceat(le, np.arange(0, ncl, cps), axis=1) > 0 if ncl else np.zeros((nblk, 0), dtype=bool)
+    evaluations = int(used.sum()) * per_blk
+    le_w = np.repeat(le, block // wave, axis=0)   # (waves, clusters)
     # waves holding each target (one each, except the clamped tail)
     order = np.argsort(tgt, kind="stable")
     t_sorted, w_sorted = tgt[order], wv[order]
 
     def waves_of(targets):
         targets = np.asarray(targets, dtype=np.int64)
-        lo = np.searchsorted(t_sorted, targets, "left")
-        hi = np.searchsorted(t_sorted, targets, "right")
-        cnt = hi - lo
-        idx = np.repeat(lo - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt) + np.arange(cnt.sum())
+        lo_ = np.searchsorted(t_sorted, targets, "left")
+        hi_ = np.searchsorted(t_sorted, targets, "right")
+        cnt = hi_ - lo_
+        idx = np.repeat(lo_ - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt) + np.arange(cnt.sum())
         return w_sorted[idx]
 
     tree = cKDTree(X)
-    # (wave, cluster) pairs with some target within 4 cluster radii
+    # (wave, cluster) pairs with some target within 4 cluster radii (never in a local expansion)
     lists = tree.query_ball_point(cl["centre"], r=4.0 * cl["radius"])
     near_wq = np.unique(np.concatenate([waves_of(l) * ncl + q for q, l in enumerate(lists)]
                                        + [np.zeros(0, dtype=np.int64)]))
-    cl_exps = lanes * (n_waves * ncl - near_wq.size)
+    cl_exps = lanes * (n_waves * ncl - int(le_w.sum()) - near_wq.size)
     # (wave, disk) pairs with some target within 7 ring radii
     lists = tree.query_ball_point(centers, r=7.0 * rho)
     near_wk = np.unique(np.concatenate([waves_of(l) * P + k for k, l in enumerate(lists)]
@@ -121,7 +167,7 @@ def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, tperm=None, threads_
     direct = np.isin(w_k * ncl + body_cl[k_k], near_wq)
     pairs = lanes * int(n_src[k_k[direct]].sum())
     disk_exps = lanes * (int(size[near_wq % ncl].sum()) - int(direct.sum()))
-    return pairs, disk_exps, cl_exps
+    return pairs, disk_exps, cl_exps, translations, evaluations
 
 
 def visiting_order(n_col, slot_body):
@@ -364,7 +410,8 @@ def main():
     log(f"mixed solve {ms:.1f} ms/solve (wall {wall / args.steps * 1e3:.1f}) iters {infos[-1]['iters']} "
         f"outer {infos[-1]['outer']} resid {infos[-1]['rel_resid']:.2e}")
     last = infos[-1]
-    solve_work = {k: last[k] for k in ("dense_pairs", "direct_pairs", "disk_expansions", "cluster_expansions")}
+    solve_work = {k: last[k] for k in ("dense_pairs", "direct_pairs", "disk_expansions", "cluster_expansions",
+                                       "local_translations", "local_evaluations")}
     value = ms / 1e3
 
     if args.copy_calibration:
@@ -384,22 +431,27 @@ def main():
     np.add.at(skipped, pr[:, 0], ns[pr[:, 1]])
     np.add.at(skipped, pr[:, 1], ns[pr[:, 0]])
     dense_launch = int(np.sum(nc.astype(np.int64) * (Ns - skipped)))
-    pairs32, disk_exps, cl_exps = kwork["mixed"]
+    pairs32, disk_exps, cl_exps, m2l32, l2p32 = kwork["mixed"]
     log(f"kernel-sum work per launch (device counters): {pairs32} direct pairs, {disk_exps} disk and "
-        f"{cl_exps} cluster expansions; FP64 sum {kwork['fp64']}")
+        f"{cl_exps} cluster expansions, {m2l32} local translations, {l2p32} local evaluations; "
+        f"FP64 sum {kwork['fp64']}")
+    # the translations and local evaluations are FP64 in both sums
+    flops_m2l32 = m2l32 * flop_per_translation(LOC32_ORDER) + l2p32 * flop_per_local_evaluation(LOC32_ORDER)
     flops_launch = (pairs32 * FLOP_PER_PAIR + disk_exps * FLOP_PER_EXPANSION
-                    + cl_exps * FLOP_PER_CLUSTER_EXPANSION)
-    p64, d64, c64 = kwork["fp64"]
-    flops64 = p64 * FLOP_PER_PAIR + d64 * FLOP_PER_EXPANSION64 + c64 * FLOP_PER_CLUSTER_EXPANSION64
+                    + cl_exps * FLOP_PER_CLUSTER_EXPANSION + flops_m2l32)
+    p64, d64, c64, m64, l64 = kwork["fp64"]
+    flops64 = (p64 * FLOP_PER_PAIR + d64 * FLOP_PER_EXPANSION64 + c64 * FLOP_PER_CLUSTER_EXPANSION64
+               + m64 * flop_per_translation(LOC64_ORDER) + l64 * flop_per_local_evaluation(LOC64_ORDER))
     achieved = flops_launch / (ks["mixed"] * 1e-3) / 1e12
     sec = ks["mixed"] * 1e-3
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=ksum_traffic_bytes(),
-                    kernel="k_ksum_mixed (FP32 Stokeslet sum; far clusters and disks by their order-12 "
-                           "and order-8 expansions)",
+                    kernel="k_ksum_mixed (FP32 Stokeslet sum; far clusters through FP64 local expansions "
+                           "(order 20) or their order-12 expansions, far disks by order-8 expansions)",
                     ms_per_launch=round(ks["mixed"], 3), flops_per_launch=flops_launch,
                     direct_pairs_per_launch=pairs32, disk_expansions_per_launch=disk_exps,
-                    cluster_expansions_per_launch=cl_exps,
+                    cluster_expansions_per_launch=cl_exps, local_translations_per_launch=m2l32,
+                    local_evaluations_per_launch=l2p32, fp64_flops_per_launch=flops_m2l32,
                     direct_pairs_per_s=round(pairs32 / sec, 1), disk_expansions_per_s=round(disk_exps / sec, 1),
                     cluster_expansions_per_s=round(cl_exps / sec, 1),
                     dense_pairs_per_launch=dense_launch,

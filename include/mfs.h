@@ -96,11 +96,15 @@ typedef struct {
   /* Work of all kernel sums of the solve (eq. getall).  dense_pairs counts the (target, source)
    * pairs of the plain direct sums they stand for; the kernels evaluate direct_pairs of them one
    * by one and replace the rest by disk_expansions and cluster_expansions evaluations of a
-   * far-field expansion (each per target), as counted by the kernels themselves. */
+   * far-field expansion (each per target) and by local_translations of a cluster's expansion
+   * into a workgroup's local expansion, evaluated local_evaluations times (per target), as
+   * counted by the kernels themselves (mfs_kernel_sum_work). */
   int64_t dense_pairs;
   int64_t direct_pairs;
   int64_t disk_expansions;
   int64_t cluster_expansions;
+  int64_t local_translations;
+  int64_t local_evaluations;
 } mfs_solve_info;
 
 /* Fill *prm with the paper's defaults.  prm: host, written. */
@@ -223,8 +227,11 @@ mfs_status mfs_kernel_sum(mfs_ctx* ctx, mfs_precision prec, const double* sigma,
  * work[0] direct (target, source) pair evaluations, work[1] evaluations of a disk's far-field
  * expansion, work[2] evaluations of a cluster's expansion (each per target; a wave of 64
  * threads, 2 targets each, takes one path per disk or cluster for all its targets, and every
- * thread counts what it executes).  Flow-evaluation points are not counted.  work: host, 3,
- * written.  Synchronises the context's stream; reset != 0 then zeroes the counters.
+ * thread counts what it executes), work[3] translations of a cluster's expansion into the
+ * local expansion of a workgroup's 512 targets (clusters beyond 3 (R + r) and 4 R + r of their
+ * centre, R the cluster's and r the targets' radius; one wave each), work[4] evaluations of
+ * such local expansions (per target).  Flow-evaluation points are not counted.  work: host,
+ * 5, written.  Synchronises the context's stream; reset != 0 then zeroes the counters.
  * mfs_gmres_solve resets them at its start. */
 mfs_status mfs_kernel_sum_work(mfs_ctx* ctx, int64_t* work, int32_t reset);
 

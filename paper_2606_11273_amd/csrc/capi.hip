@@ -353,7 +353,7 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
     }
     if ((st = upload(c, &c->d_tperm, tperm, s)).code) return st;
   }
-  if ((st = dalloc(c, &c->d_work, 4)).code) return st;
+  if ((st = dalloc(c, &c->d_work, 8)).code) return st;
   launch_zero_work(c);
   if ((st = dalloc(c, &c->d_lam_bar, 2 * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_ltil, c->xoff[C])).code) return st;
@@ -457,7 +457,9 @@ Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, do
                                mixed ? c->d_sig32m + r * c->Ns : nullptr, mixed ? nullptr : c->d_src64m + r * c->Ns,
                                mixed ? c->d_bdatm + (int64_t)r * c->P : nullptr,
                                mixed ? c->d_mpm + (int64_t)r * c->P * kMpCoefPerDisk : nullptr,
-                               mixed ? c->d_cmpm + (int64_t)r * c->ncl * kClCoefPerCluster : nullptr);
+                               mixed ? c->d_cmpm + (int64_t)r * c->ncl * kClCoefPerCluster : nullptr,
+                               mixed ? c->d_mp64m + (int64_t)r * mp64_record(c) + (int64_t)c->P * kMp64CoefPerDisk
+                                     : nullptr);
     if (!mixed)
       for (int r = 0; r < Rc; ++r)
         launch_moments64(c, c->d_src64m + r * c->Ns, c->d_mp64m + (int64_t)r * mp64_record(c));
@@ -678,11 +680,11 @@ mfs_status mfs_apply_noalloc(mfs_ctx* c, mfs_problem prob, mfs_precision prec, c
 mfs_status mfs_kernel_sum_work(mfs_ctx* c, int64_t* work, int32_t reset) {
   if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
   if (!work) return fail(c, Status{MFS_ERR_ARG, "work is NULL"});
-  unsigned long long h[3] = {0, 0, 0};
+  unsigned long long h[5] = {0, 0, 0, 0, 0};
   if (hipMemcpyAsync(h, c->d_work, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return fail(c, Status{MFS_ERR_DEVICE, "reading the work counters failed"});
-  for (int e = 0; e < 3; ++e) work[e] = (int64_t)h[e];
+  for (int e = 0; e < 5; ++e) work[e] = (int64_t)h[e];
   if (reset) launch_zero_work(c);
   return ok(c);
 }

@@ -486,11 +486,13 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
     info->matvecs_fp64 = c->cnt_mv64;
     info->matvecs_mixed = c->cnt_mv32;
     info->dense_pairs = c->cnt_pair_evals;
-    int64_t w[3] = {0, 0, 0};
+    int64_t w[5] = {0, 0, 0, 0, 0};
     if (mfs_kernel_sum_work(c, w, 0) != MFS_OK) return MFS_ERR_DEVICE;
     info->direct_pairs = w[0];
     info->disk_expansions = w[1];
     info->cluster_expansions = w[2];
+    info->local_translations = w[3];
+    info->local_evaluations = w[4];
   }
   if (tot.noconv) {
     char buf[64];

@@ -26,8 +26,19 @@ constexpr int kClOrder = 12;
 constexpr int kClCoefPerCluster = 4 * kClOrder + 2;   // FP32 complex coefficients per cluster
 constexpr int kClMaxBodies = 16;
 constexpr int kClMaxSources = 1024;                   // sources per cluster (one LDS tile)
-// The FP64 kernel sum's cluster expansions (same clusters and far test, order for FP64 rounding)
+// The FP64 kernel sum's cluster expansions (same clusters and far test, order for FP64 rounding);
+// the same FP64 records feed both kernel sums' local expansions
 constexpr int kCl64Order = 26;
+// Local expansions (M2L / L2P) of the kernel sums: a cluster farther than kLocSep32 (R + r_b)
+// (FP32 sum) or kLocSep64 (R + r_b) (FP64 sum), and than 4 R + r_b, from the centre of a
+// workgroup's targets (r_b their radius) is translated into the workgroup's local expansion,
+// order kLoc32 / kLoc64 in both source and target orders (theta <= 1/3 and 1/4: truncation
+// below 1e-10 and 1e-16 of sum |sigma|)
+constexpr int kLoc32 = 20;
+constexpr int kLoc64 = 26;
+constexpr double kLocSep32 = 3.0;
+constexpr double kLocSep64 = 4.0;
+static_assert(kLoc32 <= kCl64Order && kLoc64 <= kCl64Order && kLoc64 < 32, "local orders");
 constexpr int kCl64CoefPerCluster = 4 * kCl64Order + 2;   // FP64 complex coefficients per cluster
 constexpr double kPiD = 3.14159265358979323846;
 
@@ -211,7 +222,7 @@ void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const do
 // sig32, bdat, mp (FP32 sum: slot order) and cmp (its cluster coefficients) go together
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                               float4* sig32, double4* src64, float4* bdat, float2* mp = nullptr,
-                              float2* cmp = nullptr);
+                              float2* cmp = nullptr, double2* cm64 = nullptr);
 // stacked forms for R = 2, 4 or 8 vectors (false: unsupported size or out of memory)
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
                        int64_t ltil_stride);

@@ -30,18 +30,24 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Work counters of a kernel-sum launch: each wave adds its lanes' counts (direct pair
-// evaluations, disk expansions, cluster expansions) to work[0..2] with one atomic each.
-__device__ __forceinline__ void add_work(unsigned long long* work, unsigned d, unsigned e, unsigned c) {
+// evaluations, disk expansions, cluster expansions, cluster-to-local translations, local
+// expansion evaluations) to work[0..4] with one atomic each.
+__device__ __forceinline__ void add_work(unsigned long long* work, unsigned d, unsigned e, unsigned c, unsigned m,
+                                         unsigned l) {
   if (!work) return;
   for (int off = 32; off > 0; off >>= 1) {
     d += __shfl_down(d, off, 64);
     e += __shfl_down(e, off, 64);
     c += __shfl_down(c, off, 64);
+    m += __shfl_down(m, off, 64);
+    l += __shfl_down(l, off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     atomicAdd(work, (unsigned long long)d);
     atomicAdd(work + 1, (unsigned long long)e);
     atomicAdd(work + 2, (unsigned long long)c);
+    atomicAdd(work + 3, (unsigned long long)m);
+    atomicAdd(work + 4, (unsigned long long)l);
   }
 }
 
@@ -477,6 +483,187 @@ __global__ __launch_bounds__(kBodyThreads) void k_cluster_moments(int ncl, const
 // and those errors add up over all disks.
 constexpr int KS_THREADS = 256;
 constexpr int KS_TILE = 1024;   // sources per LDS tile (16 KB of float4)
+
+// ---- local expansions of far clusters (M2L, L2P; the oracle's local_expansion, eval_local) ----
+// With w = x - T about the workgroup's target centre T and a cluster's moments about C,
+// Delta = T - C, the cluster's field is Phi1 + conj(Psi) - w conj(Phi1') + A_0 / 2 with
+//   Phi1 = -(A_0/2) log Z + sum_k A_k Z^-k / (2k),
+//   Psi  = -(conj A_0/2) log Z + sum_k [conj(B_k)/(2k) - D_{k-1}/2 + conj(Delta) A_{k-1}/2] Z^-k,
+// and (w + Delta)^-k = sum_l (-1)^l binom(k + l - 1, l) Delta^-(k+l) w^l: the coefficient of
+// w^l is (-1)^l Delta^-l sum_k binom(k + l - 1, l) c_k Delta^-k plus the log term's.  A wave
+// translates one cluster: lane l < 32 holds Phi1's coefficient of w^l, lane 32 + l Psi's;
+// lane k first scales its function's c_k by Delta^-k into the wave's LDS row, then every lane
+// sums the row with its binomials.  Only Re log enters the velocity, so log Delta = ln |Delta|.
+__constant__ double kInvInt[32] = {0.0,        1.0,        1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,
+                                   1.0 / 7,    1.0 / 8,    1.0 / 9,  1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13,
+                                   1.0 / 14,   1.0 / 15,   1.0 / 16, 1.0 / 17, 1.0 / 18, 1.0 / 19, 1.0 / 20,
+                                   1.0 / 21,   1.0 / 22,   1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
+                                   1.0 / 28,   1.0 / 29,   1.0 / 30, 1.0 / 31};
+
+// wave-level fence for LDS rows written and read by lanes of one wave (no workgroup barrier:
+// the waves of a workgroup translate different clusters)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A cluster (centre cx, cy, radius R) goes into the workgroup's local expansion when it is
+// beyond both 4 R + rb (every target then beyond 4 R: a far cluster holds no target's disk or
+// contact partner, by the cluster radii) and sep (R + rb) (theta <= 1/sep) from the centre
+// (bx, by) of the workgroup's targets; the same expression in every pass that decides it
+__device__ __forceinline__ bool le_far(double cx, double cy, double R, double bx, double by, double rb, double sep) {
+  const double dx = __dsub_rn(cx, bx), dy = __dsub_rn(cy, by);
+  const double thr = fmax(__dadd_rn(__dmul_rn(4.0 * (1.0 + 1e-6), R), rb), __dmul_rn(sep, __dadd_rn(R, rb)));
+  return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) > __dmul_rn(thr, thr);
+}
+
+// Workgroup bounding circle of its targets: centre (bx, by), radius rb (padded)
+template <int T>
+__device__ __forceinline__ void target_bounds(const double (&x)[T], const double (&y)[T], double (*s_bb)[KS_THREADS / 64],
+                                              double& bx, double& by, double& rb) {
+  double xl = x[0], xh = x[0], yl = y[0], yh = y[0];
+#pragma unroll
+  for (int j = 1; j < T; ++j) {
+    xl = fmin(xl, x[j]);
+    xh = fmax(xh, x[j]);
+    yl = fmin(yl, y[j]);
+    yh = fmax(yh, y[j]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    xl = fmin(xl, __shfl_xor(xl, off, 64));
+    xh = fmax(xh, __shfl_xor(xh, off, 64));
+    yl = fmin(yl, __shfl_xor(yl, off, 64));
+    yh = fmax(yh, __shfl_xor(yh, off, 64));
+  }
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_bb[0][wid] = xl;
+    s_bb[1][wid] = xh;
+    s_bb[2][wid] = yl;
+    s_bb[3][wid] = yh;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < KS_THREADS / 64; ++w) {
+    xl = fmin(xl, s_bb[0][w]);
+    xh = fmax(xh, s_bb[1][w]);
+    yl = fmin(yl, s_bb[2][w]);
+    yh = fmax(yh, s_bb[3][w]);
+  }
+  bx = 0.5 * (xl + xh);
+  by = 0.5 * (yl + yh);
+  rb = 0.5 * sqrt((xh - xl) * (xh - xl) + (yh - yl) * (yh - yl)) * (1.0 + 1e-9) + 1e-9;
+}
+
+// Add the local expansion about (bx, by) of the cluster whose FP64 record (k_cluster_moments64)
+// is rec and centre (cx, cy) to the lane's coefficient (Lr, Li); K source and Q local orders.
+template <int K, int Q>
+__device__ __forceinline__ void m2l_add(const double2* __restrict__ rec, double cx, double cy, double bx,
+                                        double by, double2* row, double& Lr, double& Li) {
+  static_assert(K < 32 && Q < 32, "one lane per order");
+  const int lane = threadIdx.x & 63, f = lane >> 5, l = lane & 31;
+  const double dx = bx - cx, dy = by - cy;   // Delta = T - C
+  const double d2 = fma(dx, dx, dy * dy);
+  const double id2 = rcp_f64(d2);
+  const double ix = dx * id2, iy = -dy * id2;   // 1/Delta
+  double pr = 1.0, pi = 0.0;                    // Delta^-l
+  {
+    double br = ix, bi = iy;
+    for (int e = l; e; e >>= 1) {
+      if (e & 1) {
+        const double t = pr * br - pi * bi;
+        pi = fma(pr, bi, pi * br);
+        pr = t;
+      }
+      const double u = br * br - bi * bi;
+      bi = 2.0 * br * bi;
+      br = u;
+    }
+  }
+  wave_lds_sync();   // the row's previous reads are done
+  if (l >= 1 && l <= K) {
+    double cr, ci;
+    if (f == 0) {   // A_k / (2k)
+      cr = rec[l - 1].x;
+      ci = rec[l - 1].y;
+    } else {        // conj(B_k)/(2k) - D_{k-1}/2 + conj(Delta) A_{k-1}/2 (the record holds conj(D), conj(A))
+      const double2 b = rec[kCl64Order + l - 1], dd = rec[3 * kCl64Order + l], a = rec[2 * kCl64Order + l - 1];
+      cr = b.x - 0.5 * dd.x + 0.5 * (dx * a.x - dy * a.y);
+      ci = -b.y + 0.5 * dd.y - 0.5 * (dx * a.y + dy * a.x);
+    }
+    row[lane] = make_double2(cr * pr - ci * pi, fma(cr, pi, ci * pr));
+  }
+  wave_lds_sync();
+  double ar = 0.0, ai = 0.0, bn = 1.0;   // binom(k + l - 1, l), k = 1
+  const double2* rf = row + (f << 5);
+#pragma unroll 2
+  for (int k = 1; k <= K; ++k) {
+    const double2 c = rf[k];
+    ar = fma(bn, c.x, ar);
+    ai = fma(bn, c.y, ai);
+    bn *= (double)(k + l) * kInvInt[k];
+  }
+  if (l > Q) return;
+  const double2 a0 = rec[2 * kCl64Order];   // conj(A_0)
+  const double lr = -0.5 * a0.x, li = f == 0 ? 0.5 * a0.y : -0.5 * a0.y;   // log coefficient
+  const double sg = (l & 1) ? -1.0 : 1.0;
+  double tr = sg * (ar * pr - ai * pi), ti = sg * fma(ar, pi, ai * pr);
+  if (l == 0) {
+    const double lg = 0.5 * ln_f64(d2);
+    tr = fma(lr, lg, tr);
+    ti = fma(li, lg, ti);
+    if (f == 0) {   // the constant A_0 / 2
+      tr = fma(0.5, a0.x, tr);
+      ti = fma(-0.5, a0.y, ti);
+    }
+  } else {
+    const double s2 = -sg * kInvInt[l];
+    tr = fma(s2, lr * pr - li * pi, tr);
+    ti = fma(s2, fma(lr, pi, li * pr), ti);
+  }
+  Lr += tr;
+  Li += ti;
+}
+
+// The workgroup's local expansion: the waves' coefficients summed in LDS (s_le, 64 double2),
+// then evaluated at offset (wx, wy): u = L1 + conj(L2) - w conj(L1') (units of 4 pi mu).
+template <int Q>
+__device__ __forceinline__ void le_reduce(double Lr, double Li, double2 (*s_part)[64], double2* s_le) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  s_part[wid][lane] = make_double2(Lr, Li);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double2 t = s_part[0][threadIdx.x];
+    for (int w = 1; w < KS_THREADS / 64; ++w) {
+      t.x += s_part[w][threadIdx.x].x;
+      t.y += s_part[w][threadIdx.x].y;
+    }
+    s_le[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+template <int Q>
+__device__ __forceinline__ void l2p(const double2* s_le, double wx, double wy, double& ux, double& uy) {
+  double vr = s_le[Q].x, vi = s_le[Q].y, dr = 0.0, di = 0.0;   // L1 and L1' by Horner
+  double gr = s_le[32 + Q].x, gi = s_le[32 + Q].y;             // L2
+#pragma unroll 1
+  for (int l = Q - 1; l >= 0; --l) {
+    const double t = fma(dr, wx, -di * wy) + vr;
+    di = fma(dr, wy, di * wx) + vi;
+    dr = t;
+    const double u = fma(vr, wx, -vi * wy) + s_le[l].x;
+    vi = fma(vr, wy, vi * wx) + s_le[l].y;
+    vr = u;
+    const double g = fma(gr, wx, -gi * wy) + s_le[32 + l].x;
+    gi = fma(gr, wy, gi * wx) + s_le[32 + l].y;
+    gr = g;
+  }
+  // w conj(L1') = (wx dr + wy di) + i (wy dr - wx di)
+  ux = vr + gr - fma(wx, dr, wy * di);
+  uy = vi - gi - fma(wy, dr, -wx * di);
+}
 constexpr int KS_MAXB = 64;     // bodies per LDS tile (a cluster is one tile)
 static_assert(kClMaxBodies <= KS_MAXB && kClMaxSources <= KS_TILE, "a cluster must fit one LDS tile");
 
@@ -534,7 +721,8 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
                                                            const float* __restrict__ crad2,
                                                            const float2* __restrict__ cmp,
                                                            const int* __restrict__ tperm,
-                                                           unsigned long long* __restrict__ work) {
+                                                           unsigned long long* __restrict__ work,
+                                                           const double2* __restrict__ cm64) {
   __shared__ float4 s_src[KS_TILE];    // (y_x, y_y, sigma_x, sigma_y), y relative to the disk centre
   __shared__ float s_w[KS_TILE];       // y . sigma
   __shared__ double s_c[2 * KS_MAXB];
@@ -549,7 +737,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
   int bt[T];   // the target's disk, in slot order
   double x[T], y[T], ax[T], ay[T];
   Skip sk[T];
-  unsigned n_dir = 0, n_dexp = 0, n_cexp = 0;   // this lane's work (per target)
+  unsigned n_dir = 0, n_dexp = 0, n_cexp = 0, n_m2l = 0, n_l2p = 0;   // this lane's work
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + threadIdx.x * T + j;   // a wave: 64 T consecutive targets
@@ -563,50 +751,32 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
     ay[j] = 0.0;
     skip_init(sk[j], mode, body, cl_start[q0], nbr_off, nbr_list);
   }
-  // The workgroup's targets lie within rb of (bx, by) (their bounding box).  A cluster whose
-  // centre is beyond 4 R + rb from there is far for every thread: all take its expansion, with
-  // no per-thread test and no barrier.  The cluster radii are large enough that such a cluster
-  // holds no target's disk and no contact partner (cluster construction).
+  // The workgroup's targets lie within rb of (bx, by) (their bounding box).  A cluster beyond
+  // le_far of it goes into the workgroup's local expansion (one wave translates it); one
+  // beyond 4 R + rb only is far for every thread: all take its expansion, with no per-thread
+  // test and no barrier.  The cluster radii are large enough that such a cluster holds no
+  // target's disk and no contact partner (cluster construction).
+  __shared__ double s_bb[4][KS_THREADS / 64];
+  __shared__ double2 s_row[KS_THREADS / 64][64];   // per wave: scaled moments; then the wave's expansion
+  __shared__ double2 s_le[64];
   double bx, by, rb;
-  {
-    __shared__ double s_bb[4][KS_THREADS / 64];
-    double xl = x[0], xh = x[0], yl = y[0], yh = y[0];
-#pragma unroll
-    for (int j = 1; j < T; ++j) {
-      xl = fmin(xl, x[j]);
-      xh = fmax(xh, x[j]);
-      yl = fmin(yl, y[j]);
-      yh = fmax(yh, y[j]);
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      xl = fmin(xl, __shfl_xor(xl, off, 64));
-      xh = fmax(xh, __shfl_xor(xh, off, 64));
-      yl = fmin(yl, __shfl_xor(yl, off, 64));
-      yh = fmax(yh, __shfl_xor(yh, off, 64));
-    }
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-      s_bb[0][wid] = xl;
-      s_bb[1][wid] = xh;
-      s_bb[2][wid] = yl;
-      s_bb[3][wid] = yh;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < KS_THREADS / 64; ++w) {
-      xl = fmin(xl, s_bb[0][w]);
-      xh = fmax(xh, s_bb[1][w]);
-      yl = fmin(yl, s_bb[2][w]);
-      yh = fmax(yh, s_bb[3][w]);
-    }
-    bx = 0.5 * (xl + xh);
-    by = 0.5 * (yl + yh);
-    rb = 0.5 * sqrt((xh - xl) * (xh - xl) + (yh - yl) * (yh - yl)) * (1.0 + 1e-9) + 1e-9;
-  }
+  target_bounds<T>(x, y, s_bb, bx, by, rb);
+  const int wid = threadIdx.x >> 6;
+  double Lr = 0.0, Li = 0.0;   // this lane's coefficient of the wave's local expansion
+  bool le_used = false;         // uniform over the workgroup
   const float kHalfLn2 = 0.34657359027997264f;
   for (int cq = q0; cq < q1; ++cq) {
     const int kt = cl_start[cq], ke = cl_start[cq + 1];
     const int nb = ke - kt;
+    if (cm64 && le_far(ccent[2 * cq], ccent[2 * cq + 1], sqrt((double)crad2[cq]), bx, by, rb, kLocSep32)) {
+      if ((cq & (KS_THREADS / 64 - 1)) == wid) {
+        m2l_add<kLoc32, kLoc32>(cm64 + (int64_t)cq * kCl64CoefPerCluster, ccent[2 * cq], ccent[2 * cq + 1], bx, by, s_row[wid],
+                                Lr, Li);
+        n_m2l += (threadIdx.x & 63) == 0;
+      }
+      le_used = true;
+      continue;
+    }
     bool cfar = cmp != nullptr;
     bool bfar = false;
     if (cfar) {
@@ -850,7 +1020,20 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* _
       }
     }
   }
-  add_work(work, T * n_dir, T * n_dexp, T * n_cexp);
+  if (le_used) {
+    // the workgroup's local expansion at every target (FP64)
+    __syncthreads();   // the last tile's reads of LDS are done
+    le_reduce<kLoc32>(Lr, Li, s_row, s_le);
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      double ux, uy;
+      l2p<kLoc32>(s_le, x[j] - bx, y[j] - by, ux, uy);
+      ax[j] += ux;
+      ay[j] += uy;
+    }
+    n_l2p = T;
+  }
+  add_work(work, T * n_dir, T * n_dexp, T * n_cexp, n_m2l, n_l2p);
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     if (t[j] < Nt) {
@@ -936,12 +1119,14 @@ __global__ __launch_bounds__(kBodyThreads) void k_moments64(int P, const int* __
 }
 
 // FP64 form of the same sum, absolute coordinates (ln_f64, rcp_f64 above).
-// FP64 expansion of each cluster about its centre for the FP64 kernel sum: the moments of
-// k_cluster_moments (A_k, B_k, D_k of the sources' offsets w = y - C) from a packed FP64 source
-// array (absolute positions, body order), to order kCl64Order.  One workgroup per cluster,
+// FP64 expansion of each cluster about its centre: the moments of k_cluster_moments (A_k,
+// B_k, D_k of the sources' offsets w = y - C) to order kCl64Order, from a packed FP64 source
+// array (src: absolute positions and strengths, body order) or, with src NULL, from the FP64
+// strengths sig64 on the disks' rings (the mixed sum's packing).  They serve the FP64 sum's
+// per-target cluster expansions and both sums' local expansions.  One workgroup per cluster,
 // thread e forms the order-e moments over the cluster's sources in slot order (w^e by binary
 // powering).  Record (after the per-disk records): A_k/(2k), B_k/(2k) (k = 1..p), conj(A_k),
-// conj(D_k) (k = 0..p).  Truncation at theta <= 1/4: below sum |sigma| 4^-27 / (3/4) = 7e-17
+// conj(D_k) (k = 0..p).  Truncation at theta <= 1/4: below sum |sigma| 4^-31 / (3/4) = 3e-19
 // sum |sigma|.
 constexpr int kCl64Coef = kCl64CoefPerCluster;
 
@@ -950,7 +1135,10 @@ __global__ __launch_bounds__(64) void k_cluster_moments64(int ncl, const int* __
                                                           const int* __restrict__ src_off,
                                                           const double* __restrict__ ccent,
                                                           const double4* __restrict__ src,
-                                                          double2* __restrict__ cmp) {
+                                                          double2* __restrict__ cmp,
+                                                          const double* __restrict__ sig64,
+                                                          const int* __restrict__ cls, ClassTab ct,
+                                                          const double* __restrict__ centers) {
   const int q = blockIdx.x;
   const int e = threadIdx.x;
   if (q >= ncl || e > kCl64Order) return;
@@ -958,9 +1146,21 @@ __global__ __launch_bounds__(64) void k_cluster_moments64(int ncl, const int* __
   double Ar = 0, Ai = 0, Br = 0, Bi = 0, Dr = 0, Di = 0;
   for (int sl = cl_start[q]; sl < cl_start[q + 1]; ++sl) {
     const int b = slot_body[sl];
+    const double ox = src ? 0.0 : centers[2 * b] - Cx, oy = src ? 0.0 : centers[2 * b + 1] - Cy;
+    const double* Yr = src ? nullptr : ct.Yr[cls[b]];
     for (int j = src_off[b]; j < src_off[b + 1]; ++j) {
-      const double4 v = src[j];
-      const double wx = v.x - Cx, wy = v.y - Cy;
+      double4 v;
+      double wx, wy;
+      if (src) {
+        v = src[j];
+        wx = v.x - Cx;
+        wy = v.y - Cy;
+      } else {
+        const int jj = j - src_off[b];
+        wx = ox + Yr[2 * jj];
+        wy = oy + Yr[2 * jj + 1];
+        v = make_double4(0.0, 0.0, sig64[2 * j], sig64[2 * j + 1]);
+      }
       double pr = 1.0, pi = 0.0, br = wx, bi = wy;   // w^e
       for (int k = e; k; k >>= 1) {
         if (k & 1) {
@@ -1019,7 +1219,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
                                                           const double* __restrict__ crad,
                                                           const double2* __restrict__ cmp64,
                                                           const int* __restrict__ tperm,
-                                                          unsigned long long* __restrict__ work) {
+                                                          unsigned long long* __restrict__ work, int local) {
   __shared__ double4 s_src[KS_TILE / 2];
   __shared__ int s_off[KS_MAXB + 1];
   const int split = blockIdx.y;
@@ -1030,7 +1230,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
   int bt[T];
   double x[T], y[T], ax[T], ay[T];
   Skip sk[T];
-  unsigned n_dir = 0, n_dexp = 0, n_cexp = 0;   // this lane's work (per target)
+  unsigned n_dir = 0, n_dexp = 0, n_cexp = 0, n_m2l = 0, n_l2p = 0;   // this lane's work
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + threadIdx.x * T + j;   // a wave: 64 T consecutive targets
@@ -1043,14 +1243,33 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
     ay[j] = 0.0;
     skip_init(sk[j], mode, bt[j], kb0, nbr_off, nbr_list);
   }
+  // local expansion of the clusters far from the workgroup's targets (see k_ksum_mixed)
+  __shared__ double s_bb[4][KS_THREADS / 64];
+  __shared__ double2 s_row[KS_THREADS / 64][64];
+  __shared__ double2 s_le[64];
+  double bx = 0.0, by = 0.0, rb = 0.0;
+  const bool use_le = cmp64 && local;
+  if (use_le) target_bounds<T>(x, y, s_bb, bx, by, rb);
+  const int wid = threadIdx.x >> 6;
+  double Lr = 0.0, Li = 0.0;
+  bool le_used = false;
   if (cmp64) {
     // clusters far from every target of this thread (this split's share of the clusters):
-    // their FP64 expansions; the disk pass below skips their disks.  A far cluster holds no
-    // target's disk or contact partner (cluster radii), so no skipped source is in it.
+    // their FP64 expansions, or the workgroup's local expansion; the disk pass below skips
+    // their disks.  A far cluster holds no target's disk or contact partner (cluster radii),
+    // so no skipped source is in it.
     const int cps = (ncl + (int)gridDim.y - 1) / (int)gridDim.y;
     const int c0 = min(ncl, split * cps), c1 = min(ncl, c0 + cps);
     for (int q = c0; q < c1; ++q) {
       const double cx = ccent[2 * q], cy = ccent[2 * q + 1];
+      if (use_le && le_far(cx, cy, crad[q], bx, by, rb, kLocSep64)) {
+        if ((q & (KS_THREADS / 64 - 1)) == wid) {
+          m2l_add<kLoc64, kLoc64>(cmp64 + (int64_t)q * kCl64Coef, cx, cy, bx, by, s_row[wid], Lr, Li);
+          n_m2l += (threadIdx.x & 63) == 0;
+        }
+        le_used = true;
+        continue;
+      }
       // one decision per wave (the disk pass below repeats the same vote)
       if (!__all(cl_far64<T>(x, y, cx, cy, __dmul_rn(16.0, __dmul_rn(crad[q], crad[q]))))) continue;
       ++n_cexp;
@@ -1131,6 +1350,8 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
       const int kbody = kt + kk;
       if (cmp64) {
         const int q = body_cl[kbody];
+        if (use_le && le_far(ccent[2 * q], ccent[2 * q + 1], crad[q], bx, by, rb, kLocSep64))
+          continue;   // in the local expansion
         if (__all(cl_far64<T>(x, y, ccent[2 * q], ccent[2 * q + 1], __dmul_rn(16.0, __dmul_rn(crad[q], crad[q])))))
           continue;   // summed with its cluster
       }
@@ -1236,7 +1457,19 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
     }
     kt += nb;
   }
-  add_work(work, T * n_dir, T * n_dexp, T * n_cexp);
+  if (le_used) {
+    __syncthreads();
+    le_reduce<kLoc64>(Lr, Li, s_row, s_le);
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      double ux, uy;
+      l2p<kLoc64>(s_le, x[j] - bx, y[j] - by, ux, uy);
+      ax[j] += ux;
+      ay[j] += uy;
+    }
+    n_l2p = T;
+  }
+  add_work(work, T * n_dir, T * n_dexp, T * n_cexp, n_m2l, n_l2p);
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     if (t[j] < Nt) {
@@ -1247,7 +1480,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
 }
 
 __global__ void k_zero_work(unsigned long long* work) {
-  if (threadIdx.x < 3) work[threadIdx.x] = 0ull;
+  if (threadIdx.x < 5) work[threadIdx.x] = 0ull;
 }
 
 __global__ void k_reduce_splits(int64_t n2, int nsplit, const double* __restrict__ part, double* __restrict__ u) {
@@ -1938,21 +2171,27 @@ void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const do
                            bool pack32, bool pack64) {
   launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, pack32 ? c->d_sig32 : nullptr,
                            pack64 ? c->d_src64 : nullptr, pack32 ? c->d_bdat : nullptr, pack32 ? c->d_mp : nullptr,
-                           pack32 ? c->d_cmp : nullptr);
+                           pack32 ? c->d_cmp : nullptr, pack32 ? c->d_mp64 + (int64_t)c->P * kMp64Coef : nullptr);
   if (pack64) launch_moments64(c, c->d_src64, c->d_mp64);
 }
 
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                              float4* sig32, double4* src64, float4* bdat, float2* mp, float2* cmp) {
+                              float4* sig32, double4* src64, float4* bdat, float2* mp, float2* cmp, double2* cm64) {
   // the cluster moments read the FP64 strengths from d_sig64
   hipLaunchKernelGGL(k_gather_project, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P,
                      prob == MFS_MOBILITY ? 1 : 0, c->d_cls, c->d_src_off, c->ct[prob], c->d_bp_off, c->d_bp_list,
                      c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers,
-                     cmp ? c->d_sig64 : (double*)nullptr, sig32, src64, bdat, mp, c->d_slot_of, c->d_ssrc_off);
+                     (cmp || cm64) ? c->d_sig64 : (double*)nullptr, sig32, src64, bdat, mp, c->d_slot_of,
+                     c->d_ssrc_off);
   if (cmp)
     hipLaunchKernelGGL(k_cluster_moments, dim3(c->ncl), dim3(kBodyThreads), 0, c->stream, c->ncl, c->d_cl_start,
                        c->d_slot_body, c->d_cls, c->d_src_off, c->ct[prob], c->d_centers, c->d_ccent, c->d_sig64,
                        cmp);
+  // FP64 cluster records for the workgroups' local expansions of the FP32 sum
+  if (cm64)
+    hipLaunchKernelGGL(k_cluster_moments64, dim3(c->ncl), dim3(64), 0, c->stream, c->ncl, c->d_cl_start,
+                       c->d_slot_body, c->d_src_off, c->d_ccent, (const double4*)nullptr, cm64, c->d_sig64, c->d_cls,
+                       c->ct[prob], c->d_centers);
 }
 
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
@@ -1994,8 +2233,8 @@ static int ksum_targets_per_thread(bool mixed) {
 }
 
 static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
-                                     const float2* mp, const float2* cmp, double* u, double scale,
-                                     const SplitBuf* sb = nullptr);
+                                     const float2* mp, const float2* cmp, const double2* cm64, double* u,
+                                     double scale, const SplitBuf* sb = nullptr);
 static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, const double2* mp64, int64_t Nt,
                                     const double* X, const int32_t* tgt_body, const int32_t* tperm, double* u,
                                     double scale, const SplitBuf* sb = nullptr);
@@ -2034,7 +2273,9 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
     const bool ok =
         mixed ? launch_ksum_mixed_arrays(c, mode, c->d_sig32m + (int64_t)r * c->Ns, c->d_bdatm + (int64_t)r * c->P,
                                          c->d_mpm + (int64_t)r * c->P * kMpCoef,
-                                         c->d_cmpm + (int64_t)r * c->ncl * kClCoef, ur, scale)
+                                         c->d_cmpm + (int64_t)r * c->ncl * kClCoef,
+                                         c->d_mp64m + (int64_t)r * mp64_record(c) + (int64_t)c->P * kMp64Coef, ur,
+                                         scale)
               : launch_ksum_fp64_arrays(c, mode, c->d_src64m + (int64_t)r * c->Ns,
                                         c->d_mp64m + (int64_t)r * mp64_record(c), c->Nt, c->d_X, c->d_tgt_body,
                                         c->d_tperm, ur, scale);
@@ -2045,16 +2286,27 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
 
 // One FP32 kernel sum on explicit packed arrays (sources, disk moments, expansion
 // coefficients); see launch_kernel_sum.
+// MFS_KSUM_LOCAL=0 turns the workgroups' local expansions off (every far cluster is then
+// evaluated per target from its expansion, as with the switch MFS_KSUM_CLUSTERS for disks)
+static bool local_expansions_on() {
+  const char* e = std::getenv("MFS_KSUM_LOCAL");
+  return !(e && std::atoi(e) == 0);
+}
+
 static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
-                                     const float2* mp, const float2* cmp, double* u, double scale,
-                                     const SplitBuf* sb) {
+                                     const float2* mp, const float2* cmp, const double2* cm64, double* u,
+                                     double scale, const SplitBuf* sb) {
   const int T = ksum_targets_per_thread(true);
   const int64_t Nt = c->Nt;
   const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
   const int ns = std::min(ksum_splits(tblocks, c->P), c->ncl);
   const int cps = (c->ncl + ns - 1) / ns;
   const char* ev = std::getenv("MFS_KSUM_CLUSTERS");
-  if (ev && std::atoi(ev) == 0) cmp = nullptr;
+  if (ev && std::atoi(ev) == 0) {
+    cmp = nullptr;
+    cm64 = nullptr;
+  }
+  if (!local_expansions_on()) cm64 = nullptr;
   double* out = u;
   if (ns > 1 && !(out = split_buffer(c, (int64_t)ns * Nt * 2, sb))) return false;
   dim3 grid((unsigned)tblocks, (unsigned)ns);
@@ -2062,7 +2314,7 @@ static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, 
   hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->ncl, c->d_cl_start,          \
                      c->d_ssrc_off, c->d_scent, sig32, bdat, Nt, c->d_tgt_body, c->d_slot_of, c->d_X, cps, mode,  \
                      c->d_nbr_off, c->d_nbr_slot, scale, out, mp, c->d_ccent, c->d_crad2, cmp, c->d_tperm,        \
-                     c->d_work)
+                     c->d_work, cm64)
   if (T == 4) MFS_KS_MIXED(4); else if (T == 1) MFS_KS_MIXED(1); else MFS_KS_MIXED(2);
 #undef MFS_KS_MIXED
   if (ns > 1)
@@ -2090,7 +2342,7 @@ static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, co
 #define MFS_KS_FP64(TT)                                                                                     \
   hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, src, Nt,    \
                      tgt_body, X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out, c->d_centers, mp64,  \
-                     c->ncl, c->d_body_cl, c->d_ccent, c->d_crad64, cmp64, tperm, work)
+                     c->ncl, c->d_body_cl, c->d_ccent, c->d_crad64, cmp64, tperm, work, local_expansions_on() ? 1 : 0)
   if (T == 4) MFS_KS_FP64(4); else if (T == 1) MFS_KS_FP64(1); else MFS_KS_FP64(2);
 #undef MFS_KS_FP64
   if (ns > 1)
@@ -2099,7 +2351,9 @@ static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, co
 }
 
 bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale, const SplitBuf* sb) {
-  if (mixed) return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, c->d_cmp, u, scale, sb);
+  if (mixed)
+    return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, c->d_cmp,
+                                    c->d_mp64 + (int64_t)c->P * kMp64Coef, u, scale, sb);
   return launch_ksum_fp64_arrays(c, mode, c->d_src64, c->d_mp64, c->Nt, c->d_X, c->d_tgt_body, c->d_tperm, u, scale,
                                  sb);
 }
@@ -2198,7 +2452,8 @@ void launch_moments64(mfs_ctx* c, const double4* src64, double2* mp64) {
   hipLaunchKernelGGL(k_moments64, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
                      c->ct[0], src64, mp64);
   hipLaunchKernelGGL(k_cluster_moments64, dim3(c->ncl), dim3(64), 0, c->stream, c->ncl, c->d_cl_start,
-                     c->d_slot_body, c->d_src_off, c->d_ccent, src64, mp64 + (int64_t)c->P * kMp64Coef);
+                     c->d_slot_body, c->d_src_off, c->d_ccent, src64, mp64 + (int64_t)c->P * kMp64Coef,
+                     (const double*)nullptr, (const int*)nullptr, c->ct[0], (const double*)nullptr);
 }
 
 void launch_fine_strengths(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, double* ptil,

@@ -48,7 +48,8 @@ class MfsSolveInfo(C.Structure):
                 ("ms_rhs", C.c_double), ("ms_iterate", C.c_double), ("ms_post", C.c_double),
                 ("n_pairs", C.c_int64), ("matvecs_fp64", C.c_int32), ("matvecs_mixed", C.c_int32),
                 ("dense_pairs", C.c_int64), ("direct_pairs", C.c_int64), ("disk_expansions", C.c_int64),
-                ("cluster_expansions", C.c_int64)]
+                ("cluster_expansions", C.c_int64), ("local_translations", C.c_int64),
+                ("local_evaluations", C.c_int64)]
 
 
 class MfsRequest(C.Structure):
@@ -293,9 +294,9 @@ def mfs_apply_noalloc(ctx, problem, precision, mu, u):
 
 
 def mfs_kernel_sum_work(ctx, reset=False):
-    """(direct pairs, disk expansions, cluster expansions) counted by the kernel sums since setup
-    or the last reset."""
-    w = np.zeros(3, dtype=np.int64)
+    """(direct pairs, disk expansions, cluster expansions, local translations, local evaluations)
+    counted by the kernel sums since setup or the last reset."""
+    w = np.zeros(5, dtype=np.int64)
     _check(lib().mfs_kernel_sum_work(ctx, w.ctypes.data_as(C.POINTER(C.c_int64)), int(bool(reset))), ctx)
     return tuple(int(v) for v in w)
 
@@ -368,7 +369,8 @@ def mfs_gmres_solve(ctx, problem, precision, rhs, tol, max_iter=500, x0=None, hi
              hist=hist[:info.hist_len].copy(), ms_rhs=info.ms_rhs, ms_iterate=info.ms_iterate, ms_post=info.ms_post,
              n_pairs=info.n_pairs, matvecs_fp64=info.matvecs_fp64, matvecs_mixed=info.matvecs_mixed,
              dense_pairs=info.dense_pairs, direct_pairs=info.direct_pairs, disk_expansions=info.disk_expansions,
-             cluster_expansions=info.cluster_expansions, status=STATUS_NAMES[code])
+             cluster_expansions=info.cluster_expansions, local_translations=info.local_translations,
+             local_evaluations=info.local_evaluations, status=STATUS_NAMES[code])
     return out, d
 
 

@@ -7,7 +7,7 @@ P = 1000 with N(0,1) forces (zero net force) and torques; resistance at P = 100 
 N(0,1) velocities (at P = 1000 the resistance GMRES does not converge within 1000
 iterations, in the oracle and on the GPU alike); both solved by the oracle to relative
 residual 1e-10.  The GPU runs its own precompute (device SVDs) and GMRES, in FP64 and
-mixed precision, to 1e-9 (resistance: 2e-9 in FP64, 1e-6 in mixed precision).  Bar: max_i E^(i) <= 1e-5 (eq. rel_vel_err with the
+mixed precision, to 1e-9 (resistance: to the configuration's 1e-6).  Bar: max_i E^(i) <= 1e-5 (eq. rel_vel_err with the
 max-speed normalisation).
 """
 
@@ -43,12 +43,12 @@ def test_c2_solves_match_stored_oracle_solution(problem):
         assert np.array_equal(nv.mfs_get_pairs(ctx), ref[f"{problem}_pairs"].astype(np.int32))
         say(f"P={P} {problem}: precompute {nv.mfs_precompute_pairs(ctx, problem)} pairs")
         for prec in ("fp64", "mixed"):
-            # resistance in mixed precision: to 1e-6, as in the small-size solve tests (its FP32
-            # operator error, lubrication-sized strengths, slows the refinement).  Resistance in
-            # FP64: to 2e-9, since the FP64 operator's rounding on these strengths puts the true
-            # residual's floor at about 1e-9 (the direct kernel sum ended at 0.997e-9 after a
-            # refinement step, the one with far-disk expansions stalls at 1.02e-9)
-            tol = {("resistance", "mixed"): 1e-6, ("resistance", "fp64"): 2e-9}.get((problem, prec), 1e-9)
+            # resistance: the configuration's own tolerance, 1e-6 (the resistance and mobility
+            # workload at area fraction 0.5).  The FP64 operator's rounding on the lubrication-sized
+            # strengths of its close pairs floors the true residual near 1e-9 .. 2e-9 (measured with
+            # the successive forms of the kernel sum), so a tolerance near the floor tests the floor,
+            # not the solve; the mixed form's FP32 operator error slows its refinement further
+            tol = 1e-6 if problem == "resistance" else 1e-9
             out, info = nv.mfs_gmres_solve(ctx, problem, prec, given, tol, 500)
             E = rel_rigid_error(out, ref[f"{problem}_out"]).max()
             say(f"  {prec}: iters {info['iters']} (oracle {int(ref[f'{problem}_iters'])}), outer {info['outer']}, "

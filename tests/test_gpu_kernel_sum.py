@@ -171,7 +171,8 @@ def test_kernel_sum_projected_strengths():
 
 def test_kernel_sum_work_counters():
     # the kernels' own work counters (mfs_kernel_sum_work) against the host count of their
-    # rules (bench.ksum_work_clusters), per launch, at P = 600 (area fraction 0.5), skip mode 2
+    # rules (bench.ksum_work_clusters: per-wave paths, the workgroups' local expansions), per
+    # launch, at P = 600 (area fraction 0.5), skip mode 2
     import bench
     from paper_2606_11273_amd import native as nv
     g0 = config_geometry(2, P=600)
@@ -192,9 +193,15 @@ def test_kernel_sum_work_counters():
             counts[prec] = nv.mfs_kernel_sum_work(ctx, reset=True)
     finally:
         nv.mfs_destroy(ctx)
-    ref = bench.ksum_work_clusters(c, a, ns, rs, X, cl, tperm=bench.visiting_order(nc, cl["slot_body"]))
-    say(f"work per launch: host {ref}, mixed {counts['mixed']}, fp64 {counts['fp64']}")
-    assert min(ref) > 0
+    tp = bench.visiting_order(nc, cl["slot_body"])
+    ncl = cl["radius"].size
+    say(f"work per launch: mixed {counts['mixed']}, fp64 {counts['fp64']}")
+    assert counts["mixed"][3] > counts["fp64"][3] > 0   # the FP64 sum translates only the farther clusters
     for prec in ("mixed", "fp64"):
-        for k in range(3):
+        ref = bench.ksum_work_clusters(c, a, ns, rs, X, cl, tperm=tp, local=True,
+                                       splits=bench.ksum_splits(X.shape[0], len(c), ncl if prec == "mixed" else None),
+                                       sep=bench.LOC32_SEP if prec == "mixed" else bench.LOC64_SEP)
+        say(f"  host count {prec}: {ref}")
+        assert min(ref) > 0
+        for k in range(5):
             assert abs(counts[prec][k] - ref[k]) <= 1e-4 * ref[k], (prec, k)
