@@ -82,7 +82,7 @@ LOC32_SEP, LOC64_SEP = 3.0, 4.0     # their separation factors (theta <= 1/3, 1/
 
 def ksum_splits(n_targets, P, ncl=None, T=KSUM_T, block=256):
     """The kernel sums' source-split count (doubled while the grid holds fewer than 8192
-    workgroups, at most 64 and P / 8; the FP32 sum at most one split per cluster)."""
+    workgroups, at most 64 and P / 8, and at most one split per cluster)."""
     tblocks = -(-n_targets // (block * T))
     s = 1
     while tblocks * s < 8192 and s * 2 <= max(1, P // 8) and s < 64:

@@ -1191,7 +1191,7 @@ __global__ __launch_bounds__(64) void k_cluster_moments64(int ncl, const int* __
 }
 
 // Far test of a cluster (centre cx, cy; lim = 16 R^2) for every target of a thread, without
-// contraction, so that the cluster pass and the disk pass of k_ksum_fp64 decide alike
+// contraction, so that every pass that decides it decides alike
 template <int T>
 __device__ __forceinline__ bool cl_far64(const double (&x)[T], const double (&y)[T], double cx, double cy,
                                          double lim) {
@@ -1204,30 +1204,111 @@ __device__ __forceinline__ bool cl_far64(const double (&x)[T], const double (&y)
   return far;
 }
 
+// A cluster's FP64 expansion (record cf, centre cx, cy; k_cluster_moments64) added at a thread's
+// targets: four complex Horner series of degree kCl64Order, as in the FP32 sum
 template <int T>
-__global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __restrict__ src_off,
+__device__ __forceinline__ void cluster_expansion64(const double2* __restrict__ cf, double cx, double cy,
+                                                    const double (&x)[T], const double (&y)[T], double (&ax)[T],
+                                                    double (&ay)[T]) {
+  double Zx[T], Zy[T], R2[T], zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T], h4r[T], h4i[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    Zx[j] = x[j] - cx;
+    Zy[j] = y[j] - cy;
+    R2[j] = fma(Zx[j], Zx[j], Zy[j] * Zy[j]);
+    const double ir2 = rcp_f64(R2[j]);
+    zr[j] = Zx[j] * ir2;
+    zi[j] = Zy[j] * ir2;
+    h1r[j] = cf[kCl64Order - 1].x;
+    h1i[j] = cf[kCl64Order - 1].y;
+    h2r[j] = cf[2 * kCl64Order - 1].x;
+    h2i[j] = cf[2 * kCl64Order - 1].y;
+    h3r[j] = cf[3 * kCl64Order].x;
+    h3i[j] = cf[3 * kCl64Order].y;
+    h4r[j] = cf[4 * kCl64Order + 1].x;
+    h4i[j] = cf[4 * kCl64Order + 1].y;
+  }
+#pragma unroll 2
+  for (int m = kCl64Order - 1; m >= 1; --m) {
+    const double2 a = cf[m - 1], bq = cf[kCl64Order + m - 1], g = cf[2 * kCl64Order + m], e = cf[3 * kCl64Order + 1 + m];
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      const double t1r = fma(zr[j], h1r[j], fma(zi[j], h1i[j], a.x));
+      const double t1i = fma(zr[j], h1i[j], fma(-zi[j], h1r[j], a.y));
+      const double t2r = fma(zr[j], h2r[j], fma(-zi[j], h2i[j], bq.x));
+      const double t2i = fma(zr[j], h2i[j], fma(zi[j], h2r[j], bq.y));
+      const double t3r = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g.x));
+      const double t3i = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g.y));
+      const double t4r = fma(zr[j], h4r[j], fma(-zi[j], h4i[j], e.x));
+      const double t4i = fma(zr[j], h4i[j], fma(zi[j], h4r[j], e.y));
+      h1r[j] = t1r;
+      h1i[j] = t1i;
+      h2r[j] = t2r;
+      h2i[j] = t2i;
+      h3r[j] = t3r;
+      h3i[j] = t3i;
+      h4r[j] = t4r;
+      h4i[j] = t4i;
+    }
+  }
+  const double2 g0 = cf[2 * kCl64Order], e0 = cf[3 * kCl64Order + 1];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const double pr = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g0.x));
+    const double pi = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g0.y));
+    const double qr = fma(zr[j], h4r[j], fma(-zi[j], h4i[j], e0.x));
+    const double qi = fma(zr[j], h4i[j], fma(zi[j], h4r[j], e0.y));
+    const double p1r = fma(zr[j], h1r[j], zi[j] * h1i[j]);
+    const double p1i = fma(zr[j], h1i[j], -zi[j] * h1r[j]);
+    const double p2r = fma(zr[j], h2r[j], -zi[j] * h2i[j]);
+    const double p2i = fma(zr[j], h2i[j], zi[j] * h2r[j]);
+    const double mr = fma(Zx[j], pr, fma(-Zy[j], pi, -qr));   // Z P - Q
+    const double mi = fma(Zx[j], pi, fma(Zy[j], pr, -qi));
+    const double t3r = 0.5 * fma(zr[j], mr, -zi[j] * mi);
+    const double t3i = 0.5 * fma(zr[j], mi, zi[j] * mr);
+    const double lZ = fma(-0.5, ln_f64(R2[j]), 0.5);          // -ln|Z| + 1/2
+    ax[j] += fma(g0.x, lZ, p1r + p2r + t3r);                  // S0 = conj(g0)
+    ay[j] += fma(-g0.y, lZ, p1i + p2i + t3i);
+  }
+}
+
+// FP64 form of the sum, absolute coordinates (ln_f64, rcp_f64 above), with the FP32 sum's
+// structure: the split's clusters one LDS tile each, in slot order.  A cluster far from the
+// workgroup (le_far) goes into its local expansion; one beyond 4 cluster radii from every
+// target of a wave is summed by that wave from its FP64 expansion (order kCl64Order); the
+// tile of a cluster that every wave takes that way is not staged.  Otherwise each disk of the
+// cluster is summed from its FP64 expansion (k_moments64, order kMp64Order) by a wave whose
+// targets are all beyond 7 ring radii, else directly over its sources.  src: FP64 packed
+// sources in body order (src_off); ssrc_off: the same counts in slot order.  Skip modes as in
+// k_ksum_mixed (partner lists in slots); mode 0 reads no body index (flow-evaluation points
+// may have body -1).  mp64 NULL: every disk direct; cmp64 NULL: no cluster expansions.
+template <int T>
+__global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int ncl, const int* __restrict__ cl_start,
+                                                          const int* __restrict__ slot_body,
+                                                          const int* __restrict__ ssrc_off,
+                                                          const int* __restrict__ src_off,
                                                           const double4* __restrict__ src, int64_t Nt,
                                                           const int* __restrict__ tgt_body,
-                                                          const double* __restrict__ X, int bodies_per_split,
+                                                          const int* __restrict__ slot_of,
+                                                          const double* __restrict__ X, int clusters_per_split,
                                                           int mode, const int* __restrict__ nbr_off,
-                                                          const int* __restrict__ nbr_list, double scale,
+                                                          const int* __restrict__ nbr_slot, double scale,
                                                           double* __restrict__ out,
                                                           const double* __restrict__ centers,
-                                                          const double2* __restrict__ mp64, int ncl,
-                                                          const int* __restrict__ body_cl,
+                                                          const double2* __restrict__ mp64,
                                                           const double* __restrict__ ccent,
                                                           const double* __restrict__ crad,
                                                           const double2* __restrict__ cmp64,
                                                           const int* __restrict__ tperm,
                                                           unsigned long long* __restrict__ work, int local) {
-  __shared__ double4 s_src[KS_TILE / 2];
+  __shared__ double4 s_src[kClMaxSources];
   __shared__ int s_off[KS_MAXB + 1];
   const int split = blockIdx.y;
-  const int kb0 = split * bodies_per_split;
-  const int kb1 = min(P, kb0 + bodies_per_split);
+  const int q0 = min(ncl, split * clusters_per_split);
+  const int q1 = min(ncl, q0 + clusters_per_split);
   int64_t t[T];    // position in the visiting order
   int64_t tt[T];   // the target there
-  int bt[T];
+  int bt[T];       // the target's disk, in slot order (skip modes 1, 2)
   double x[T], y[T], ax[T], ay[T];
   Skip sk[T];
   unsigned n_dir = 0, n_dexp = 0, n_cexp = 0, n_m2l = 0, n_l2p = 0;   // this lane's work
@@ -1236,128 +1317,68 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
     t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + threadIdx.x * T + j;   // a wave: 64 T consecutive targets
     const int64_t tc = t[j] < Nt ? t[j] : Nt - 1;
     tt[j] = tperm ? tperm[tc] : tc;
-    bt[j] = tgt_body[tt[j]];
+    const int body = mode != 0 ? tgt_body[tt[j]] : -1;
+    bt[j] = mode != 0 ? slot_of[body] : -1;
     x[j] = X[2 * tt[j]];
     y[j] = X[2 * tt[j] + 1];
     ax[j] = 0.0;
     ay[j] = 0.0;
-    skip_init(sk[j], mode, bt[j], kb0, nbr_off, nbr_list);
+    skip_init(sk[j], mode, body, cl_start[q0], nbr_off, nbr_slot);
   }
-  // local expansion of the clusters far from the workgroup's targets (see k_ksum_mixed)
   __shared__ double s_bb[4][KS_THREADS / 64];
   __shared__ double2 s_row[KS_THREADS / 64][64];
   __shared__ double2 s_le[64];
   double bx = 0.0, by = 0.0, rb = 0.0;
+  if (cmp64) target_bounds<T>(x, y, s_bb, bx, by, rb);
   const bool use_le = cmp64 && local;
-  if (use_le) target_bounds<T>(x, y, s_bb, bx, by, rb);
   const int wid = threadIdx.x >> 6;
   double Lr = 0.0, Li = 0.0;
-  bool le_used = false;
-  if (cmp64) {
-    // clusters far from every target of this thread (this split's share of the clusters):
-    // their FP64 expansions, or the workgroup's local expansion; the disk pass below skips
-    // their disks.  A far cluster holds no target's disk or contact partner (cluster radii),
-    // so no skipped source is in it.
-    const int cps = (ncl + (int)gridDim.y - 1) / (int)gridDim.y;
-    const int c0 = min(ncl, split * cps), c1 = min(ncl, c0 + cps);
-    for (int q = c0; q < c1; ++q) {
-      const double cx = ccent[2 * q], cy = ccent[2 * q + 1];
-      if (use_le && le_far(cx, cy, crad[q], bx, by, rb, kLocSep64)) {
-        if ((q & (KS_THREADS / 64 - 1)) == wid) {
-          m2l_add<kLoc64, kLoc64>(cmp64 + (int64_t)q * kCl64Coef, cx, cy, bx, by, s_row[wid], Lr, Li);
+  bool le_used = false;   // uniform over the workgroup
+  for (int cq = q0; cq < q1; ++cq) {
+    const int kt = cl_start[cq], ke = cl_start[cq + 1];
+    const int nb = ke - kt;
+    bool wfar = false;   // this wave sums the cluster from its expansion
+    if (cmp64) {
+      const double cx = ccent[2 * cq], cy = ccent[2 * cq + 1], R = crad[cq];
+      if (use_le && le_far(cx, cy, R, bx, by, rb, kLocSep64)) {
+        if ((cq & (KS_THREADS / 64 - 1)) == wid) {
+          m2l_add<kLoc64, kLoc64>(cmp64 + (int64_t)cq * kCl64Coef, cx, cy, bx, by, s_row[wid], Lr, Li);
           n_m2l += (threadIdx.x & 63) == 0;
         }
         le_used = true;
         continue;
       }
-      // one decision per wave (the disk pass below repeats the same vote)
-      if (!__all(cl_far64<T>(x, y, cx, cy, __dmul_rn(16.0, __dmul_rn(crad[q], crad[q]))))) continue;
-      ++n_cexp;
-      const double2* cf = cmp64 + (int64_t)q * kCl64Coef;
-      double Zx[T], Zy[T], R2[T], zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T], h4r[T], h4i[T];
-#pragma unroll
-      for (int j = 0; j < T; ++j) {
-        Zx[j] = x[j] - cx;
-        Zy[j] = y[j] - cy;
-        R2[j] = fma(Zx[j], Zx[j], Zy[j] * Zy[j]);
-        const double ir2 = rcp_f64(R2[j]);
-        zr[j] = Zx[j] * ir2;
-        zi[j] = Zy[j] * ir2;
-        h1r[j] = cf[kCl64Order - 1].x;
-        h1i[j] = cf[kCl64Order - 1].y;
-        h2r[j] = cf[2 * kCl64Order - 1].x;
-        h2i[j] = cf[2 * kCl64Order - 1].y;
-        h3r[j] = cf[3 * kCl64Order].x;
-        h3i[j] = cf[3 * kCl64Order].y;
-        h4r[j] = cf[4 * kCl64Order + 1].x;
-        h4i[j] = cf[4 * kCl64Order + 1].y;
+      // beyond 4 R + rb of the targets' centre: every target beyond 4 R (uniform, no barrier)
+      bool bfar;
+      {
+        const double dx = cx - bx, dy = cy - by;
+        const double thr = 4.0 * (1.0 + 1e-6) * R + rb;
+        bfar = dx * dx + dy * dy > thr * thr;
       }
-#pragma unroll 2
-      for (int m = kCl64Order - 1; m >= 1; --m) {
-        const double2 a = cf[m - 1], bq = cf[kCl64Order + m - 1], g = cf[2 * kCl64Order + m],
-                      e = cf[3 * kCl64Order + 1 + m];
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-          const double t1r = fma(zr[j], h1r[j], fma(zi[j], h1i[j], a.x));
-          const double t1i = fma(zr[j], h1i[j], fma(-zi[j], h1r[j], a.y));
-          const double t2r = fma(zr[j], h2r[j], fma(-zi[j], h2i[j], bq.x));
-          const double t2i = fma(zr[j], h2i[j], fma(zi[j], h2r[j], bq.y));
-          const double t3r = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g.x));
-          const double t3i = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g.y));
-          const double t4r = fma(zr[j], h4r[j], fma(-zi[j], h4i[j], e.x));
-          const double t4i = fma(zr[j], h4i[j], fma(zi[j], h4r[j], e.y));
-          h1r[j] = t1r;
-          h1i[j] = t1i;
-          h2r[j] = t2r;
-          h2i[j] = t2i;
-          h3r[j] = t3r;
-          h3i[j] = t3i;
-          h4r[j] = t4r;
-          h4i[j] = t4i;
-        }
+      wfar = bfar || __all(cl_far64<T>(x, y, cx, cy, __dmul_rn(16.0, __dmul_rn(R, R))));
+      if (wfar) {
+        ++n_cexp;
+        cluster_expansion64<T>(cmp64 + (int64_t)cq * kCl64Coef, cx, cy, x, y, ax, ay);
       }
-      const double2 g0 = cf[2 * kCl64Order], e0 = cf[3 * kCl64Order + 1];
-#pragma unroll
-      for (int j = 0; j < T; ++j) {
-        const double pr = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g0.x));
-        const double pi = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g0.y));
-        const double qr = fma(zr[j], h4r[j], fma(-zi[j], h4i[j], e0.x));
-        const double qi = fma(zr[j], h4i[j], fma(zi[j], h4r[j], e0.y));
-        const double p1r = fma(zr[j], h1r[j], zi[j] * h1i[j]);
-        const double p1i = fma(zr[j], h1i[j], -zi[j] * h1r[j]);
-        const double p2r = fma(zr[j], h2r[j], -zi[j] * h2i[j]);
-        const double p2i = fma(zr[j], h2i[j], zi[j] * h2r[j]);
-        const double mr = fma(Zx[j], pr, fma(-Zy[j], pi, -qr));   // Z P - Q
-        const double mi = fma(Zx[j], pi, fma(Zy[j], pr, -qi));
-        const double t3r = 0.5 * fma(zr[j], mr, -zi[j] * mi);
-        const double t3i = 0.5 * fma(zr[j], mi, zi[j] * mr);
-        const double lZ = fma(-0.5, ln_f64(R2[j]), 0.5);          // -ln|Z| + 1/2
-        ax[j] += fma(g0.x, lZ, p1r + p2r + t3r);                  // S0 = conj(g0)
-        ay[j] += fma(-g0.y, lZ, p1i + p2i + t3i);
-      }
+      if (bfar) continue;
     }
-  }
-  for (int kt = kb0; kt < kb1;) {
-    const int s0 = src_off[kt];
-    int nb = 0;
-    while (kt + nb < kb1 && nb < KS_MAXB && src_off[kt + nb + 1] - s0 <= KS_TILE / 2) ++nb;
-    const int ns = src_off[kt + nb] - s0;
-    __syncthreads();
-    for (int q = threadIdx.x; q < ns; q += KS_THREADS) s_src[q] = src[s0 + q];
-    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
-    __syncthreads();
+    // the barrier also ends the reads of the previous tile before this one is staged
+    if (__syncthreads_and(wfar ? 1 : 0)) continue;
+    const int s0 = ssrc_off[kt];
     for (int kk = 0; kk < nb; ++kk) {
-      const int kbody = kt + kk;
-      if (cmp64) {
-        const int q = body_cl[kbody];
-        if (use_le && le_far(ccent[2 * q], ccent[2 * q + 1], crad[q], bx, by, rb, kLocSep64))
-          continue;   // in the local expansion
-        if (__all(cl_far64<T>(x, y, ccent[2 * q], ccent[2 * q + 1], __dmul_rn(16.0, __dmul_rn(crad[q], crad[q])))))
-          continue;   // summed with its cluster
-      }
+      const int o = ssrc_off[kt + kk] - s0, n = ssrc_off[kt + kk + 1] - s0 - o;
+      const int64_t g = src_off[slot_body[kt + kk]];
+      for (int q = threadIdx.x; q < n; q += KS_THREADS) s_src[o + q] = src[g + q];
+    }
+    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = ssrc_off[kt + q] - s0;
+    __syncthreads();
+    if (wfar) continue;
+    for (int kk = 0; kk < nb; ++kk) {
+      const int kslot = kt + kk;
+      const int kbody = slot_body[kslot];
       if (mp64) {
-        // far disk for every target of this thread: its FP64 expansion (k_moments64; the
-        // same series as the FP32 sum, to order kMp64Order)
+        // far disk for every target of this wave: its FP64 expansion (the FP32 sum's series
+        // to order kMp64Order)
         const double2* cf = mp64 + (int64_t)kbody * kMp64Coef;
         const double q = cf[3 * kMp64Order + 2].x;
         const double cx = centers[2 * kbody], cy = centers[2 * kbody + 1];
@@ -1419,7 +1440,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
             const double t3r = 0.5 * fma(zr[j], mr, -zi[j] * mi);
             const double t3i = 0.5 * fma(zr[j], mi, zi[j] * mr);
             const double lZ = fma(-0.5, ln_f64(R2[j]), 0.5);   // -ln|Z| + 1/2
-            if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
+            if (!skip_test(sk[j], mode, kslot, bt[j], nbr_slot)) {
               ax[j] += fma(g0.x, lZ, p1r + p2r + t3r);          // S0 = conj(g0)
               ay[j] += fma(-g0.y, lZ, p1i + p2i + t3i);
             }
@@ -1430,9 +1451,9 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
       double lx[T], ly[T], tx[T], ty[T];
 #pragma unroll
       for (int j = 0; j < T; ++j) lx[j] = ly[j] = tx[j] = ty[j] = 0.0;
-      const int q1 = s_off[kk + 1];
-      n_dir += q1 - s_off[kk];
-      for (int q = s_off[kk]; q < q1; ++q) {
+      const int qe = s_off[kk + 1];
+      n_dir += qe - s_off[kk];
+      for (int q = s_off[kk]; q < qe; ++q) {
         const double4 s = s_src[q];
 #pragma unroll
         for (int j = 0; j < T; ++j) {
@@ -1449,16 +1470,15 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int P, const int* __re
       }
 #pragma unroll
       for (int j = 0; j < T; ++j) {
-        if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
+        if (!skip_test(sk[j], mode, kslot, bt[j], nbr_slot)) {
           ax[j] += fma(-0.5, lx[j], tx[j]);
           ay[j] += fma(-0.5, ly[j], ty[j]);
         }
       }
     }
-    kt += nb;
   }
   if (le_used) {
-    __syncthreads();
+    __syncthreads();   // the last tile's reads of LDS are done
     le_reduce<kLoc64>(Lr, Li, s_row, s_le);
 #pragma unroll
     for (int j = 0; j < T; ++j) {
@@ -2259,8 +2279,7 @@ static double* split_buffer(mfs_ctx* c, int64_t need, const SplitBuf* sb) {
 
 int64_t ksum_split_doubles(const mfs_ctx* c, bool mixed) {
   const int64_t T = ksum_targets_per_thread(mixed);
-  int ns = ksum_splits((c->Nt + KS_THREADS * T - 1) / (KS_THREADS * T), c->P);
-  if (mixed) ns = std::min(ns, c->ncl);
+  const int ns = std::min(ksum_splits((c->Nt + KS_THREADS * T - 1) / (KS_THREADS * T), c->P), c->ncl);
   return ns > 1 ? (int64_t)ns * c->Nt * 2 : 0;
 }
 
@@ -2332,17 +2351,18 @@ static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, co
   const double2* cmp64 = mp64 && !(ev && std::atoi(ev) == 0) ? mp64 + (int64_t)c->P * kMp64Coef : nullptr;
   const int T = ksum_targets_per_thread(false);
   const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
-  const int ns = ksum_splits(tblocks, c->P);
-  const int bps = (c->P + ns - 1) / ns;
+  const int ns = std::min(ksum_splits(tblocks, c->P), c->ncl);
+  const int cps = (c->ncl + ns - 1) / ns;
   double* out = u;
   if (ns > 1 && !(out = split_buffer(c, (int64_t)ns * Nt * 2, sb))) return false;
   // the work counters count the context's own targets only (not flow-evaluation points)
   unsigned long long* work = X == c->d_X ? c->d_work : nullptr;
   dim3 grid((unsigned)tblocks, (unsigned)ns);
-#define MFS_KS_FP64(TT)                                                                                     \
-  hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->P, c->d_src_off, src, Nt,    \
-                     tgt_body, X, bps, mode, c->d_nbr_off, c->d_nbr_list, scale, out, c->d_centers, mp64,  \
-                     c->ncl, c->d_body_cl, c->d_ccent, c->d_crad64, cmp64, tperm, work, local_expansions_on() ? 1 : 0)
+#define MFS_KS_FP64(TT)                                                                                      \
+  hipLaunchKernelGGL(k_ksum_fp64<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->ncl, c->d_cl_start,           \
+                     c->d_slot_body, c->d_ssrc_off, c->d_src_off, src, Nt, tgt_body, c->d_slot_of, X, cps, mode, \
+                     c->d_nbr_off, c->d_nbr_slot, scale, out, c->d_centers, mp64, c->d_ccent, c->d_crad64, cmp64,  \
+                     tperm, work, local_expansions_on() ? 1 : 0)
   if (T == 4) MFS_KS_FP64(4); else if (T == 1) MFS_KS_FP64(1); else MFS_KS_FP64(2);
 #undef MFS_KS_FP64
   if (ns > 1)

@@ -199,7 +199,7 @@ def test_kernel_sum_work_counters():
     assert counts["mixed"][3] > counts["fp64"][3] > 0   # the FP64 sum translates only the farther clusters
     for prec in ("mixed", "fp64"):
         ref = bench.ksum_work_clusters(c, a, ns, rs, X, cl, tperm=tp, local=True,
-                                       splits=bench.ksum_splits(X.shape[0], len(c), ncl if prec == "mixed" else None),
+                                       splits=bench.ksum_splits(X.shape[0], len(c), ncl),
                                        sep=bench.LOC32_SEP if prec == "mixed" else bench.LOC64_SEP)
         say(f"  host count {prec}: {ref}")
         assert min(ref) > 0
