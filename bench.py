@@ -43,131 +43,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 20          # algorithmic flops of one Stokeslet evaluation applied to a 2-vector
-# One evaluation of a far disk's expansion in the FP32 kernel sum (order 8): three complex
-# Horner series, 24 flops per step over 7 steps, plus about 66 for the first terms, zeta,
-# the log term and the combination (two of them transcendental)
-MP_ORDER = 8
-FLOP_PER_EXPANSION = 24 * (MP_ORDER - 1) + 66
-MP64_ORDER = 18             # the FP64 kernel sum's expansion order (same series and far test)
-FLOP_PER_EXPANSION64 = 24 * (MP64_ORDER - 1) + 66
-MP_FAR2 = 49.0              # a disk is far for a target beyond 7 ring radii
-KSUM_T = 2                  # targets per thread of both kernel sums (their default)
-
-
-# One evaluation of a far cluster's expansion in the FP32 kernel sum (order 12 about the
-# cluster's centre): four complex Horner series, 32 flops per step over 11 steps, plus about
-# 64 for zeta, the first terms, the log term and the combination
-CL_ORDER = 12
-FLOP_PER_CLUSTER_EXPANSION = 32 * (CL_ORDER - 1) + 64
-CL_FAR2 = 16.0              # a cluster is far for a target beyond 4 cluster radii
-CL64_ORDER = 26             # the FP64 kernel sum's cluster expansions (same clusters and far test)
-FLOP_PER_CLUSTER_EXPANSION64 = 32 * (CL64_ORDER - 1) + 64
-
-
-def flop_per_translation(order):
-    """A cluster's expansion translated into a local expansion (both of the given order), two
-    analytic functions: the moments scaled by Delta^-k (6 flops each), the binomial sums (a real
-    times a complex number, 4 flops per term) and the scaling of the results by Delta^-l."""
-    return 2 * (4 * order * (order + 1) + 6 * order + 6 * (order + 1))
-
-
-def flop_per_local_evaluation(order):
-    """A local expansion at a target: three complex Horner series (L1, L1', L2), 8 flops a step."""
-    return 24 * order + 8
-
-
-LOC32_ORDER, LOC64_ORDER = 20, 26   # local expansion orders of the FP32 and FP64 kernel sums
+KSUM_T = 2                  # targets per thread of both kernel sums
+CELL_ORDER = 26             # order of the cells' moments (the translations' source order)
+LOC32_ORDER, LOC64_ORDER = 20, 26   # local expansion orders of the mixed and FP64 kernel sums
 LOC32_SEP, LOC64_SEP = 3.0, 4.0     # their separation factors (theta <= 1/3, 1/4)
 
 
-def ksum_splits(n_targets, P, ncl=None, T=KSUM_T, block=256):
-    """The kernel sums' source-split count (doubled while the grid holds fewer than 8192
-    workgroups, at most 64 and P / 8, and at most one split per cluster)."""
-    tblocks = -(-n_targets // (block * T))
-    s = 1
-    while tblocks * s < 8192 and s * 2 <= max(1, P // 8) and s < 64:
-        s *= 2
-    return min(s, ncl) if ncl is not None else s
+def flop_ring_expansions(n, terms):
+    """n evaluations of a disk's ring expansion whose orders sum to terms: three complex Horner
+    series, 24 flops per step (p - 1 steps at order p), plus about 66 for zeta, the first terms,
+    the log term and the combination (two of them transcendental)."""
+    return 24 * (terms - n) + 66 * n
 
 
-def ksum_work_clusters(centers, radii, n_src, r_src, X, cl, tperm=None, threads_T=KSUM_T, block=256, wave=64,
-                       local=True, splits=1, sep=LOC32_SEP):
-    """Work of one kernel-sum launch (FP32 or FP64) with the two-level far field and the
-    workgroups' local expansions: direct pair evaluations, disk expansions, cluster expansions
-    (each per target), cluster-to-local translations and local-expansion evaluations (per target).
+def flop_per_translation(order, src_order=CELL_ORDER):
+    """A cell's moments (order src_order) translated into a local expansion of the given order,
+    two analytic functions: the moments scaled by Delta^-k (6 flops each), the binomial sums (a
+    real times a complex number added, 4 flops per term) and the scaling of the results by
+    Delta^-l (6 flops each)."""
+    return 2 * (4 * src_order * (order + 1) + 6 * src_order + 6 * (order + 1))
 
-    The kernels visit the targets in the order tperm (None: as given); position i of a grid of
-    blocks of block * T positions belongs to thread (i mod block T) // T of block i // (block T)
-    (a thread's T targets are consecutive), clamped to the last target in the ragged tail, so a
-    wave of `wave` consecutive threads holds wave * T consecutive positions.  A block's targets
-    have a bounding circle (centre b, radius rb); a cluster of radius R beyond both 4 R + rb and
-    sep (R + rb) of b goes into the block's local expansion (one translation; with `local`).
-    Otherwise a wave takes one path for all its targets: the cluster's expansion when every
-    target is beyond 4 cluster radii; else, per disk of the cluster, the disk's expansion when
-    every target is beyond 7 ring radii, else the direct sum over its sources.  Every lane of a
-    wave executes what the wave takes.  The clusters are shared among `splits` workgroups per
-    block (ceil(ncl / splits) consecutive clusters each); every one of them with a cluster in its
-    local expansion evaluates that expansion at its block's targets.  cl: mfs_get_clusters."""
-    import numpy as np
-    from scipy.spatial import cKDTree
-    P = centers.shape[0]
-    Nt = X.shape[0]
-    n_src = np.asarray(n_src, dtype=np.int64)
-    rho = np.asarray(r_src, dtype=np.float64) * np.asarray(radii, dtype=np.float64)
-    ncl = cl["radius"].size
-    size = np.diff(cl["cl_start"]).astype(np.int64)
-    body_cl = np.empty(P, dtype=np.int64)
-    body_cl[cl["slot_body"]] = np.repeat(np.arange(ncl), size)
-    per_blk = block * threads_T
-    nblk = (Nt + per_blk - 1) // per_blk
-    pos = np.arange(nblk * per_blk)
-    tgt = np.minimum(pos, Nt - 1)
-    if tperm is not None:
-        tgt = np.asarray(tperm, dtype=np.int64)[tgt]
-    wv = pos // (wave * threads_T)
-    n_waves = nblk * (block // wave)
-    lanes = wave * threads_T            # targets a wave handles, one path for all
-    # block bounding circles and the clusters each block takes into its local expansion
-    xb = X[tgt].reshape(nblk, per_blk, 2)
-    lo, hi = xb.min(axis=1), xb.max(axis=1)
-    bc = 0.5 * (lo + hi)
-    rb = 0.5 * np.sqrt(((hi - lo) ** 2).sum(axis=1)) * (1.0 + 1e-9) + 1e-9
-    R = cl["radius"]
-    d2 = ((bc[:, None, :] - cl["centre"][None, :, :]) ** 2).sum(axis=2)
-    thr = np.maximum(4.0 * (1.0 + 1e-6) * R[None, :] + rb[:, None], sep * (R[None, :] + rb[:, None]))
-    le = (d2 > thr * thr) if local else np.zeros((nblk, ncl), dtype=bool)   # (blocks, clusters)
-    translations = int(le.sum())
-    cps = -(-ncl // splits)
-    used = np.add.reduceat(le, np.arange(0, ncl, cps), axis=1) > 0 if ncl else np.zeros((nblk, 0), dtype=bool)
-    evaluations = int(used.sum()) * per_blk
-    le_w = np.repeat(le, block // wave, axis=0)   # (waves, clusters)
-    # waves holding each target (one each, except the clamped tail)
-    order = np.argsort(tgt, kind="stable")
-    t_sorted, w_sorted = tgt[order], wv[order]
 
-    def waves_of(targets):
-        targets = np.asarray(targets, dtype=np.int64)
-        lo_ = np.searchsorted(t_sorted, targets, "left")
-        hi_ = np.searchsorted(t_sorted, targets, "right")
-        cnt = hi_ - lo_
-        idx = np.repeat(lo_ - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt) + np.arange(cnt.sum())
-        return w_sorted[idx]
+def flop_per_local_evaluation(order):
+    """A local expansion at a node: three complex Horner series (L1, L1', L2), 8 flops a step."""
+    return 24 * order + 8
 
-    tree = cKDTree(X)
-    # (wave, cluster) pairs with some target within 4 cluster radii (never in a local expansion)
-    lists = tree.query_ball_point(cl["centre"], r=4.0 * cl["radius"])
-    near_wq = np.unique(np.concatenate([waves_of(l) * ncl + q for q, l in enumerate(lists)]
-                                       + [np.zeros(0, dtype=np.int64)]))
-    cl_exps = lanes * (n_waves * ncl - int(le_w.sum()) - near_wq.size)
-    # (wave, disk) pairs with some target within 7 ring radii
-    lists = tree.query_ball_point(centers, r=7.0 * rho)
-    near_wk = np.unique(np.concatenate([waves_of(l) * P + k for k, l in enumerate(lists)]
-                                       + [np.zeros(0, dtype=np.int64)]))
-    w_k, k_k = near_wk // P, near_wk % P
-    direct = np.isin(w_k * ncl + body_cl[k_k], near_wq)
-    pairs = lanes * int(n_src[k_k[direct]].sum())
-    disk_exps = lanes * (int(size[near_wq % ncl].sum()) - int(direct.sum()))
-    return pairs, disk_exps, cl_exps, translations, evaluations
+
+def ksum_flops(work, mixed):
+    """Algorithmic flops of the work a kernel sum counted (mfs_kernel_sum_work)."""
+    direct, n, terms, m2l, l2p = work
+    q = LOC32_ORDER if mixed else LOC64_ORDER
+    return (direct * FLOP_PER_PAIR + flop_ring_expansions(n, terms) + m2l * flop_per_translation(q)
+            + l2p * flop_per_local_evaluation(q))
 
 
 def visiting_order(n_col, slot_body):
@@ -177,32 +84,32 @@ def visiting_order(n_col, slot_body):
     return np.concatenate([np.arange(col_off[b], col_off[b + 1]) for b in slot_body])
 
 
-PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (dense, packed FP32)
+PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (dense, with packed FP32)
 PEAK_FP64_TFLOPS = 78.6
+# The kernel sums issue FP64 and unpacked FP32 VALU instructions (packed FP32 is disabled in the
+# build): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s for either.
+PEAK_VALU_TFLOPS = 78.6
 
-# HBM traffic of one k_ksum_mixed launch on this workload: rocprofv3 --pmc FETCH_SIZE, then
-# WRITE_SIZE (KiB per dispatch, `bench.py --kernel-only --copy-calibration`), each scaled by what
-# the counter reads for an elementwise kernel that reads and writes 1 GiB (factors 2.0 and 1.0).
-# It holds for the kernel source it was measured on, identified by a hash of k_ksum_mixed's text.
-KSUM_TRAFFIC = {"src_sha256_16": "ccfaa84067a6b8e9", "fetch_kib": 152367.9, "write_kib": 180000.0,
-                "fetch_factor": 2.0, "write_factor": 1.0}
+# HBM traffic of one k_ksum_fmm launch on this workload: rocprofv3 --pmc FETCH_SIZE, then
+# WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for an elementwise kernel
+# that reads and writes 1 GiB.  It holds for the kernel source it was measured on, identified by
+# a hash of k_ksum_fmm's text; None until measured.
+KSUM_TRAFFIC = None
 
 
-def ksum_traffic_bytes():
-    """HBM bytes per k_ksum_mixed launch, or None once the kernel differs from the measured one."""
+def ksum_traffic_bytes(mixed):
+    """HBM bytes per k_ksum_fmm launch, or None once the kernel differs from the measured one."""
     import hashlib
+    t = KSUM_TRAFFIC and KSUM_TRAFFIC.get("mixed" if mixed else "fp64")
+    if not t:
+        return None
     src = open(os.path.join(ROOT, "paper_2606_11273_amd", "csrc", "kernels.hip")).read()
-    i = src.find("void k_ksum_mixed(")
+    i = src.find("void k_ksum_fmm(")
     if i < 0:
         return None
     body = src[i:src.index("\n}\n", i) + 3]
-    # the expansions' orders and radii live outside the kernel's text
-    hdr = open(os.path.join(ROOT, "paper_2606_11273_amd", "csrc", "internal.h")).read()
-    body += "".join(l for l in (hdr + src).splitlines(True) if "constexpr" in l and ("kMp" in l or "kCl" in l)
-                   and "kMp64" not in l and "kCl64" not in l)
     if hashlib.sha256(body.encode()).hexdigest()[:16] != KSUM_TRAFFIC["src_sha256_16"]:
         return None
-    t = KSUM_TRAFFIC
     return int((t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024)
 
 
@@ -330,8 +237,8 @@ def main():
         _, Ns, Nt, _ = nv.mfs_get_sizes(ctx)
         sig = torch.randn(2 * Ns, dtype=torch.float64, device="cuda")
         u = torch.zeros(2 * Nt, dtype=torch.float64, device="cuda")
-        for _ in range(args.ksum_reps):
-            nv.mfs_kernel_sum(ctx, "mixed", sig, u, 2)
+        for prec in ("mixed", "fp64"):
+            nv.mfs_time_kernel_sum(ctx, prec, sig, u, 2, args.ksum_reps)
         # two whole matvecs (mixed, then FP64) so that counters also cover the pair-correction
         # kernels; the pair matrices are zeros of the right shapes (same memory traffic)
         sizes = [2 * int(ns[i] + ns[k]) for i, k in nv.mfs_get_pairs(ctx)]
@@ -360,26 +267,17 @@ def main():
     _, Ns, Nt, _ = nv.mfs_get_sizes(ctx)
     log(f"setup {t_setup:.2f}s  precompute {n_pairs} pairs {t_pre:.2f}s  Ns {Ns} Nt {Nt}")
 
-    # dominant kernel: the mixed all-pairs sum in the matvec's launch configuration (skip own disk and partners)
+    # the kernel sums in the matvec's launch configuration (skip own disk and partners): HIP events
+    # on the context's stream around the sum kernel alone (mfs_time_kernel_sum), work as counted
+    stream = torch.cuda.current_stream()
     sig = torch.randn(2 * Ns, dtype=torch.float64, device="cuda")
     u = torch.zeros(2 * Nt, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
-    ks, kwork = {}, {}
-    for prec, reps in (("mixed", args.ksum_reps), ("fp64", 1)):
-        nv.mfs_kernel_sum(ctx, prec, sig, u, 2)
-        torch.cuda.synchronize()
+    ks, krec, kwork = {}, {}, {}
+    for prec in ("mixed", "fp64"):
+        nv.mfs_time_kernel_sum(ctx, prec, sig, u, 2, 1)
         nv.mfs_kernel_sum_work(ctx, reset=True)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            nv.mfs_kernel_sum(ctx, prec, sig, u, 2)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ks[prec] = e0.elapsed_time(e1) / reps
-        # work per launch as the kernel counted it
-        kwork[prec] = tuple(w // reps for w in nv.mfs_kernel_sum_work(ctx, reset=True))
-    # the launch also packs the strengths (a few microseconds); the kernel-sum kernel itself dominates
+        krec[prec], ks[prec] = nv.mfs_time_kernel_sum(ctx, prec, sig, u, 2, args.ksum_reps)
+        kwork[prec] = tuple(w // args.ksum_reps for w in nv.mfs_kernel_sum_work(ctx, reset=True))
 
     # plain FP64 solve of the same input (comparison)
     out64 = None
@@ -410,7 +308,7 @@ def main():
     log(f"mixed solve {ms:.1f} ms/solve (wall {wall / args.steps * 1e3:.1f}) iters {infos[-1]['iters']} "
         f"outer {infos[-1]['outer']} resid {infos[-1]['rel_resid']:.2e}")
     last = infos[-1]
-    solve_work = {k: last[k] for k in ("dense_pairs", "direct_pairs", "disk_expansions", "cluster_expansions",
+    solve_work = {k: last[k] for k in ("dense_pairs", "direct_pairs", "ring_expansions", "expansion_terms",
                                        "local_translations", "local_evaluations")}
     value = ms / 1e3
 
@@ -420,46 +318,38 @@ def main():
         torch.neg(buf, out=out)
         torch.cuda.synchronize()
 
-    # roofline of the dominant kernel (the mixed kernel sum; one launch = one matvec's sum
-    # without each disk's own sources and its contact partners).  Its algorithmic flops are the
-    # work the kernel counted itself: direct pair evaluations x 20 plus disk and cluster
-    # expansion evaluations x their flops (order 8 and 12); the FP64 kernel takes the same
-    # decisions with order-18 and order-26 expansions.  dense_pairs_per_launch is the count of
-    # the plain direct sum the launch stands for, which the kernel does not evaluate.
+    # roofline of the dominant kernel: the kernel sum the timed solve applied most (mixed or FP64;
+    # one launch = one matvec's sum without each disk's own sources and its contact partners).
+    # Its algorithmic flops are the work the kernel counted itself (ksum_flops); dense_pairs is
+    # the count of the plain direct sum a launch stands for, which the kernel does not evaluate.
     pr = nv.mfs_get_pairs(ctx)
     skipped = ns.astype(np.int64).copy()
     np.add.at(skipped, pr[:, 0], ns[pr[:, 1]])
     np.add.at(skipped, pr[:, 1], ns[pr[:, 0]])
     dense_launch = int(np.sum(nc.astype(np.int64) * (Ns - skipped)))
-    pairs32, disk_exps, cl_exps, m2l32, l2p32 = kwork["mixed"]
-    log(f"kernel-sum work per launch (device counters): {pairs32} direct pairs, {disk_exps} disk and "
-        f"{cl_exps} cluster expansions, {m2l32} local translations, {l2p32} local evaluations; "
-        f"FP64 sum {kwork['fp64']}")
-    # the translations and local evaluations are FP64 in both sums
-    flops_m2l32 = m2l32 * flop_per_translation(LOC32_ORDER) + l2p32 * flop_per_local_evaluation(LOC32_ORDER)
-    flops_launch = (pairs32 * FLOP_PER_PAIR + disk_exps * FLOP_PER_EXPANSION
-                    + cl_exps * FLOP_PER_CLUSTER_EXPANSION + flops_m2l32)
-    p64, d64, c64, m64, l64 = kwork["fp64"]
-    flops64 = (p64 * FLOP_PER_PAIR + d64 * FLOP_PER_EXPANSION64 + c64 * FLOP_PER_CLUSTER_EXPANSION64
-               + m64 * flop_per_translation(LOC64_ORDER) + l64 * flop_per_local_evaluation(LOC64_ORDER))
-    achieved = flops_launch / (ks["mixed"] * 1e-3) / 1e12
-    sec = ks["mixed"] * 1e-3
-    roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=ksum_traffic_bytes(),
-                    kernel="k_ksum_mixed (FP32 Stokeslet sum; far clusters through FP64 local expansions "
-                           "(order 20) or their order-12 expansions, far disks by order-8 expansions)",
-                    ms_per_launch=round(ks["mixed"], 3), flops_per_launch=flops_launch,
-                    direct_pairs_per_launch=pairs32, disk_expansions_per_launch=disk_exps,
-                    cluster_expansions_per_launch=cl_exps, local_translations_per_launch=m2l32,
-                    local_evaluations_per_launch=l2p32, fp64_flops_per_launch=flops_m2l32,
-                    direct_pairs_per_s=round(pairs32 / sec, 1), disk_expansions_per_s=round(disk_exps / sec, 1),
-                    cluster_expansions_per_s=round(cl_exps / sec, 1),
-                    dense_pairs_per_launch=dense_launch,
-                    dense_equivalent_pairs_per_s=round(dense_launch / sec, 1),
-                    fp64_kernel_ms_per_launch=round(ks["fp64"], 2),
-                    fp64_kernel_work_per_launch=list(kwork["fp64"]),
-                    fp64_kernel_tflops=round(flops64 / (ks["fp64"] * 1e-3) / 1e12, 2),
-                    fp64_peak=PEAK_FP64_TFLOPS)
+    dom = "mixed" if last["matvecs_mixed"] >= last["matvecs_fp64"] else "fp64"
+    kern = {}
+    for prec in ("mixed", "fp64"):
+        fl = ksum_flops(kwork[prec], prec == "mixed")
+        sec = ks[prec] * 1e-3
+        d, n, terms, m2l, l2p = kwork[prec]
+        kern[prec] = dict(ms_per_launch=round(ks[prec], 4), ms_records=round(krec[prec], 4), flops_per_launch=fl,
+                          tflops=round(fl / sec / 1e12, 2), frac_valu=round(fl / sec / 1e12 / PEAK_VALU_TFLOPS, 4),
+                          direct_pairs=d, ring_expansions=n, mean_ring_order=round(terms / max(n, 1), 2),
+                          local_translations=m2l, local_evaluations=l2p,
+                          dense_equivalent_pairs_per_s=round(dense_launch / sec, 1))
+        log(f"kernel sum {prec}: {ks[prec]:.3f} ms per launch (+{krec[prec]:.3f} ms packing and records), "
+            f"{fl / sec / 1e12:.2f} TFLOP/s; work {kwork[prec]}")
+    kd = kern[dom]
+    roofline = dict(bound="alu", achieved=kd["tflops"], peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+                    frac=kd["frac_valu"], traffic=ksum_traffic_bytes(dom == "mixed"),
+                    kernel=f"k_ksum_fmm<{'true' if dom == 'mixed' else 'false'}, 2> ({dom} kernel sum: per wave of "
+                           "128 nodes, cell translations into an FP64 local expansion and near disks from their ring "
+                           f"expansions{' in FP32' if dom == 'mixed' else ''})",
+                    peak_note="FP64 and unpacked FP32 VALU FMA rate (256 CUs x 64 lanes x 2 flops x 2.4 GHz); the "
+                              "published FP32 vector peak 157.3 TFLOP/s needs packed FP32, which the build disables",
+                    frac_of_published_fp32_peak=round(kd["tflops"] / PEAK_FP32_TFLOPS, 4) if dom == "mixed" else None,
+                    dense_pairs_per_launch=dense_launch, kernels=kern)
 
     # stacked matvec: one T mu on args.rhs vectors at once, per vector (HIP events)
     stacked = None

@@ -93,16 +93,16 @@ typedef struct {
   int64_t n_pairs;
   int32_t matvecs_fp64;   /* operator applications with the FP64 kernel sum (refinement residuals) */
   int32_t matvecs_mixed;  /* operator applications with the mixed kernel sum */
-  /* Work of all kernel sums of the solve (eq. getall).  dense_pairs counts the (target, source)
+  /* Work of all kernel sums of the solve (eq. getall).  dense_pairs counts the (node, source)
    * pairs of the plain direct sums they stand for; the kernels evaluate direct_pairs of them one
-   * by one and replace the rest by disk_expansions and cluster_expansions evaluations of a
-   * far-field expansion (each per target) and by local_translations of a cluster's expansion
-   * into a workgroup's local expansion, evaluated local_evaluations times (per target), as
-   * counted by the kernels themselves (mfs_kernel_sum_work). */
+   * by one and replace the rest by ring_expansions evaluations of a disk's ring expansion (each
+   * per node, of orders summing to expansion_terms) and by local_translations of a cell's
+   * moments into a wave's local expansion, evaluated local_evaluations times (per node slot),
+   * as counted by the kernels themselves (mfs_kernel_sum_work). */
   int64_t dense_pairs;
   int64_t direct_pairs;
-  int64_t disk_expansions;
-  int64_t cluster_expansions;
+  int64_t ring_expansions;
+  int64_t expansion_terms;
   int64_t local_translations;
   int64_t local_evaluations;
 } mfs_solve_info;
@@ -177,6 +177,30 @@ mfs_status mfs_get_pairs(const mfs_ctx* ctx, int64_t* n_pairs, int32_t* pairs);
 mfs_status mfs_get_clusters(const mfs_ctx* ctx, int32_t* n_clusters, int32_t* slot_body, int32_t* cl_start,
                             double* centre, double* radius);
 
+/* The hierarchical far field of the kernel sum over the context's own nodes (inspection,
+ * for tests and measurement; the paper evaluates this sum with a fast multipole method,
+ * Sec. 6).  Cells: a quadtree over the disks in the order of mfs_get_clusters (slot_body),
+ * leaf s < P the disk in slot s, an internal cell the slots [cell_lo, cell_hi) of one curve
+ * prefix; centre the mean of its disks' centres, radius max |c_b - centre| + a_b (a_b the disk
+ * radius).  Waves: runs of at most 128 consecutive nodes of the visiting order (the nodes of
+ * the disks in slot order), cut where the next disk lies more than 3 radii from the run's
+ * first disk; wave w holds positions [wave_start[w], wave_start[w + 1]), centre wave_c (the
+ * midpoint of its nodes' bounding box).  A wave's m2l list holds the cells translated into its
+ * local expansion (|centre - wave_c| >= sep (radius + r), r the wave's largest node distance
+ * from wave_c, sep 4 for MFS_FP64 and 3 for MFS_MIXED, and no node's own disk or contact
+ * partner inside); its near list the other disks (slots, increasing), each summed from the
+ * disk's ring expansion at the lowest of the orders 27, 40, 56 (MFS_FP64) or 14, 24, 44
+ * (MFS_MIXED) whose squared distance tier_d2 every node of the wave exceeds (skipped nodes
+ * aside), else directly.  prob: the one-body map whose strengths set tier_d2.  sizes (host,
+ * 4, written): ncell, nwave, m2l and near list lengths.  Every other pointer is host memory of
+ * the size it implies or NULL (not written): cell_lo, cell_hi, cell_r (ncell), cell_c
+ * (2 ncell), wave_start, m2l_off, near_off (nwave + 1), wave_c (2 nwave), m2l, near, tier_d2
+ * (3 P, slot order). */
+mfs_status mfs_get_fmm(const mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int64_t* sizes,
+                       int32_t* cell_lo, int32_t* cell_hi, double* cell_c, double* cell_r, int32_t* wave_start,
+                       double* wave_c, int32_t* m2l_off, int32_t* m2l, int32_t* near_off, int32_t* near,
+                       double* tier_d2);
+
 /* Import (set) or export (get) the pair matrices of problem prob in the pair
  * order of mfs_get_pairs.  A: host, sum over pairs of (2 n_src_i + 2 n_src_k)^2,
  * each pair's matrix row-major; E: host, sum of 6 x (2 n_src_i + 2 n_src_k),
@@ -197,42 +221,50 @@ mfs_status mfs_apply(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t
 
 /* mfs_apply for one vector (n_rhs = 1) that allocates no device memory, for callers that
  * cannot allocate: code under HIP graph capture, tight serving loops, harnesses that forbid
- * hipMalloc.  The kernel sum's split partials, which mfs_apply keeps in a buffer of the
- * context grown on first use, go to a static scratch array of 128 MiB that every context
- * on the device shares (each device holds its own copy until the process ends).  Calls that
- * overlap in time on one device race on that array: run them on one stream, or order them.
- * The result equals mfs_apply's (same kernels, same split count).  mu_in, u_out: device, n
- * doubles, not overlapping.  Errors: as mfs_apply; MFS_ERR_ARG when the split partials of
- * this context (split count x 2 N_t doubles, e.g. 4 x 1.44e6 at P = 10^4) exceed the array. */
+ * hipMalloc.  The kernel sum's expansion records of the vector (the disks' ring expansions and
+ * the cells' moments and records, mfs_get_fmm), which mfs_apply keeps in buffers of the
+ * context, go to a static scratch array of 128 MiB that every context on the device shares
+ * (each device holds its own copy until the process ends).  Calls that overlap in time on one
+ * device race on that array: run them on one stream, or order them.  The result equals
+ * mfs_apply's (same kernels).  mu_in, u_out: device, n doubles, not overlapping.  Errors: as
+ * mfs_apply; MFS_ERR_ARG when this context's records (16 (ncell (81 + 108) + 174 P) + 8 x 140 P
+ * bytes, 78 MB at P = 10^4) exceed the array. */
 mfs_status mfs_apply_noalloc(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, const double* mu_in,
                              double* u_out);
 
-/* Plain all-pairs Stokeslet sum over the context's coarse sources and nodes
- * (eq. getall): u[t] = sum_s S(x_t, y_s) sigma[s].  skip = 0: every source;
- * skip = 1: sources of the target's own disk are left out; skip = 2: also those
- * of the disk's contact partners (the form step 2a of mfs_apply uses, with the
- * skipped blocks applied in FP64 by the pair step).  sigma: device,
- * 2 * sum(n_src); u: device, 2 * sum(n_col).  This is the kernel of step 2a,
- * exposed for tests and measurement.  A disk whose centre lies beyond 7 ring radii
- * of the targets is summed through a multipole expansion of its FP64 moments
- * (order 8 for MFS_MIXED, 18 for MFS_FP64: truncation below 3e-8 and 1e-16 of
- * sum |sigma| / (4 pi mu), under each precision's rounding), and a cluster of disks
- * (mfs_get_clusters) beyond 4 cluster radii through one expansion about its centre
- * (order 12 / 26: below 2e-8 and 7e-17).  The paper uses a fast multipole method for
- * this sum (Sec. 6). */
+/* All-pairs Stokeslet sum over the context's coarse sources and nodes (eq. getall):
+ * u[t] = sum_s S(x_t, y_s) sigma[s].  skip = 0: every source; skip = 1: sources of the
+ * target's own disk are left out; skip = 2: also those of the disk's contact partners (the
+ * form step 2a of mfs_apply uses, with the skipped blocks applied in FP64 by the pair step).
+ * sigma: device, 2 * sum(n_src); u: device, 2 * sum(n_col).  This is the kernel of step 2a,
+ * exposed for tests and measurement.  The far field is hierarchical (mfs_get_fmm; the paper
+ * uses a fast multipole method, Sec. 6): per wave of up to 128 nodes, cells far from the wave
+ * are translated into the wave's local expansion (FP64, order 26 with MFS_FP64, 20 with
+ * MFS_MIXED; truncation below 4^-27 and 3^-21 of the sources' strength sums), the other disks
+ * are summed from their ring expansions (FP64 moments; evaluated in FP64, or in FP32 with
+ * MFS_MIXED) at an order that keeps the truncation below 1e-15 (FP64) or 1e-9 (FP32) of the
+ * field of unit boundary data through the one-body map and below 1e-16 / 1e-9 of sum |sigma|
+ * for any strengths, or directly in FP64 when a node is too close for every order. */
 mfs_status mfs_kernel_sum(mfs_ctx* ctx, mfs_precision prec, const double* sigma, double* u,
                           int32_t skip);
 
+/* Measurement form of mfs_kernel_sum: packs sigma and forms its expansion records once, then
+ * launches the sum kernel reps times (each writes the same u), timed with HIP events on the
+ * context's stream.  ms_records (host, written): packing and records; ms_sum (host, written):
+ * the average duration of one sum launch.  Synchronises the stream.  Arguments as
+ * mfs_kernel_sum; reps >= 1. */
+mfs_status mfs_time_kernel_sum(mfs_ctx* ctx, mfs_precision prec, const double* sigma, double* u, int32_t skip,
+                               int32_t reps, double* ms_records, double* ms_sum);
+
 /* Work counted by the context's kernel sums (eq. getall) since setup or the last reset:
- * work[0] direct (target, source) pair evaluations, work[1] evaluations of a disk's far-field
- * expansion, work[2] evaluations of a cluster's expansion (each per target; a wave of 64
- * threads, 2 targets each, takes one path per disk or cluster for all its targets, and every
- * thread counts what it executes), work[3] translations of a cluster's expansion into the
- * local expansion of a workgroup's 512 targets (clusters beyond 3 (R + r) and 4 R + r of their
- * centre, R the cluster's and r the targets' radius; one wave each), work[4] evaluations of
- * such local expansions (per target).  Flow-evaluation points are not counted.  work: host,
- * 5, written.  Synchronises the context's stream; reset != 0 then zeroes the counters.
- * mfs_gmres_solve resets them at its start. */
+ * work[0] direct (node, source) pair evaluations, work[1] evaluations of a disk's ring
+ * expansion and work[2] their orders summed (each per node; a wave of 64 threads, 2 nodes
+ * each, takes one path per near disk for all its nodes, and every thread counts what it
+ * executes), work[3] translations of a cell's moments into a wave's local expansion (one wave
+ * each), work[4] evaluations of local expansions (per node slot of a wave with translations).
+ * Flow-evaluation points are not counted.  work: host, 5, written.  Synchronises the
+ * context's stream; reset != 0 then zeroes the counters.  mfs_gmres_solve resets them at its
+ * start. */
 mfs_status mfs_kernel_sum_work(mfs_ctx* ctx, int64_t* work, int32_t reset);
 
 /* Right-hand side of the preconditioned system.  given: host, P x 3 (forces and

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libmfs_hip.so")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["kernels.hip", "precompute.hip", "capi.hip", "gmres.hip", "flow.hip", "server.hip"]
+HIP_SOURCES = ["kernels.hip", "precompute.hip", "capi.hip", "gmres.hip", "flow.hip", "server.hip", "fmm_tree.hip"]
 CXX_SOURCES = ["geometry.cpp"]
 
 HIPCC_FLAGS = [

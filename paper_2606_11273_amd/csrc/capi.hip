@@ -87,6 +87,12 @@ void free_all(mfs_ctx* c) {
                   c->d_tperm,   c->d_work};
   for (void* p : ptrs)
     if (p) dev_free(c, p);
+  for (void* p : {(void*)c->d_cell_child_off, (void*)c->d_cell_child, (void*)c->d_cell_by_height, (void*)c->d_cell_c,
+                  (void*)c->d_wcent, (void*)c->d_wstart, (void*)c->d_cellraw, (void*)c->d_cellrec, (void*)c->d_ring64, (void*)c->d_ring32})
+    if (p) dev_free(c, p);
+  for (const FmmLists& L : c->fl)
+    for (void* p : {(void*)L.d_m2l_off, (void*)L.d_m2l, (void*)L.d_near_off, (void*)L.d_near})
+      if (p) dev_free(c, p);
   for (const PairSet& ps : c->ps)
     for (void* p : {(void*)ps.G, (void*)ps.Yf, (void*)ps.KKf, (void*)ps.pgeo, (void*)ps.nf, (void*)ps.d_goff,
                     (void*)ps.d_yoff})
@@ -353,6 +359,7 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
     }
     if ((st = upload(c, &c->d_tperm, tperm, s)).code) return st;
   }
+  if ((st = build_fmm(c)).code) return st;
   if ((st = dalloc(c, &c->d_work, 8)).code) return st;
   launch_zero_work(c);
   if ((st = dalloc(c, &c->d_lam_bar, 2 * c->Ns)).code) return st;
@@ -387,8 +394,10 @@ Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u, co
   const bool wp = c->pairs.size() > 0;
   launch_onebody_apply(c, prob, mu, c->d_lam_bar);
   if (wp) launch_pair_A(c, prob, c->d_lam_bar, c->d_ltil);
-  launch_gather_project(c, prob, c->d_lam_bar, c->d_ltil, wp, mixed, !mixed);
-  const bool ks = launch_kernel_sum(c, mixed, 2, c->d_u, 1.0 / (4.0 * kPiD * c->prm.mu), sb);
+  FmmRec fr = fmm_records(c, 0);
+  if (sb && !fmm_records_in(c, sb, &fr)) return Status{MFS_ERR_ARG, "the caller's buffer is too small"};
+  launch_gather_project(c, prob, c->d_lam_bar, c->d_ltil, wp, mixed, !mixed, &fr);
+  const bool ks = launch_kernel_sum(c, mixed, 2, c->d_u, 1.0 / (4.0 * kPiD * c->prm.mu), &fr);
   c->cnt_pair_evals += c->evals_skip;
   if (mixed)
     ++c->cnt_mv32;
@@ -446,6 +455,7 @@ Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, do
     }
     Status st = ensure_stacked(c, 8);
     if (st.code) return st;
+    if ((st = ensure_fmm_records(c, 8)).code) return st;
     const bool wp = c->pairs.size() > 0;
     const int C = (int)(c->pairs.size() / 2);
     const int64_t ns2 = 2 * c->Ns, nx = c->xoff[C], nc = c->coff[C];
@@ -453,16 +463,9 @@ Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, do
     if (wp && !launch_pair_A_rhs(c, prob, Rc, c->d_lam_bar_m, ns2, c->d_ltil_m, nx))
       for (int r = 0; r < Rc; ++r) launch_pair_A(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx);
     for (int r = 0; r < Rc; ++r)
-      launch_gather_project_to(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx, wp,
-                               mixed ? c->d_sig32m + r * c->Ns : nullptr, mixed ? nullptr : c->d_src64m + r * c->Ns,
-                               mixed ? c->d_bdatm + (int64_t)r * c->P : nullptr,
-                               mixed ? c->d_mpm + (int64_t)r * c->P * kMpCoefPerDisk : nullptr,
-                               mixed ? c->d_cmpm + (int64_t)r * c->ncl * kClCoefPerCluster : nullptr,
-                               mixed ? c->d_mp64m + (int64_t)r * mp64_record(c) + (int64_t)c->P * kMp64CoefPerDisk
-                                     : nullptr);
-    if (!mixed)
-      for (int r = 0; r < Rc; ++r)
-        launch_moments64(c, c->d_src64m + r * c->Ns, c->d_mp64m + (int64_t)r * mp64_record(c));
+      launch_gather_project_to(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx, wp, nullptr,
+                               c->d_src64m + r * c->Ns, nullptr);
+    for (int r = 0; r < Rc; ++r) launch_fmm_records(c, prob, c->d_src64m + r * c->Ns, fmm_records(c, r), mixed);
     const bool ks = launch_kernel_sum_rhs(c, mixed, 2, Rc, c->d_u_m, 1.0 / (4.0 * kPiD * c->prm.mu));
     if ((st = check_kernel_sum(c, ks)).code) return st;
     c->cnt_pair_evals += (int64_t)Rc * c->evals_skip;
@@ -584,6 +587,40 @@ mfs_status mfs_get_clusters(const mfs_ctx* c, int32_t* n_clusters, int32_t* slot
   return MFS_OK;
 }
 
+mfs_status mfs_get_fmm(const mfs_ctx* c, mfs_problem prob, mfs_precision prec, int64_t* sizes, int32_t* cell_lo,
+                       int32_t* cell_hi, double* cell_c, double* cell_r, int32_t* wave_start, double* wave_c,
+                       int32_t* m2l_off, int32_t* m2l, int32_t* near_off, int32_t* near, double* tier_d2) {
+  if (!c || !sizes || (prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || (prec != MFS_FP64 && prec != MFS_MIXED))
+    return MFS_ERR_ARG;
+  const FmmLists& L = c->fl[prec == MFS_MIXED ? 1 : 0];
+  sizes[0] = c->ncell;
+  sizes[1] = c->nwave;
+  sizes[2] = (int64_t)L.m2l.size();
+  sizes[3] = (int64_t)L.near.size();
+  auto cp = [](void* dst, const void* src, size_t bytes) {
+    if (dst && bytes) std::memcpy(dst, src, bytes);
+  };
+  cp(cell_lo, c->cell_lo.data(), sizeof(int32_t) * c->cell_lo.size());
+  cp(cell_hi, c->cell_hi.data(), sizeof(int32_t) * c->cell_hi.size());
+  cp(cell_c, c->cell_c.data(), sizeof(double) * c->cell_c.size());
+  cp(cell_r, c->cell_r.data(), sizeof(double) * c->cell_r.size());
+  cp(wave_start, c->h_wstart.data(), sizeof(int32_t) * c->h_wstart.size());
+  cp(wave_c, c->h_wcent.data(), sizeof(double) * c->h_wcent.size());
+  cp(m2l_off, L.m2l_off.data(), sizeof(int32_t) * L.m2l_off.size());
+  cp(m2l, L.m2l.data(), sizeof(int32_t) * L.m2l.size());
+  cp(near_off, L.near_off.data(), sizeof(int32_t) * L.near_off.size());
+  cp(near, L.near.data(), sizeof(int32_t) * L.near.size());
+  if (tier_d2) {
+    const ClassTab& ct = c->ct[prob];
+    for (int s = 0; s < c->P; ++s) {
+      const int k = c->cls[c->slot_body[s]];
+      for (int t = 0; t < kRingTiers; ++t)
+        tier_d2[kRingTiers * s + t] = prec == MFS_MIXED ? ct.tier32[k][t] : ct.tier64[k][t];
+    }
+  }
+  return MFS_OK;
+}
+
 mfs_status mfs_set_pair_matrices(mfs_ctx* c, mfs_problem prob, const double* A, const double* E) {
   if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
   if ((prob != MFS_RESISTANCE && prob != MFS_MOBILITY) || !A || !E)
@@ -666,9 +703,9 @@ mfs_status mfs_apply_noalloc(mfs_ctx* c, mfs_problem prob, mfs_precision prec, c
     return fail(c, Status{MFS_ERR_STATE, "mfs_precompute_pairs has not run for this problem"});
   if (!c->scratch) return fail(c, Status{MFS_ERR_STATE, "no scratch array resolved for this context's device"});
   const bool mixed = prec == MFS_MIXED;
-  const int64_t need = ksum_split_doubles(c, mixed);
+  const int64_t need = fmm_record_doubles(c);
   if (need > kScratchDoubles)
-    return fail(c, Status{MFS_ERR_ARG, "the kernel sum's split partials (" + std::to_string(need * 8) +
+    return fail(c, Status{MFS_ERR_ARG, "the kernel sum's expansion records (" + std::to_string(need * 8) +
                                            " bytes) exceed the no-allocation scratch array (" +
                                            std::to_string(kScratchDoubles * 8) + " bytes)"});
   const SplitBuf sb{c->scratch, kScratchDoubles};
@@ -698,6 +735,35 @@ mfs_status mfs_kernel_sum(mfs_ctx* c, mfs_precision prec, const double* sigma, d
   const bool ks = launch_kernel_sum(c, mixed, skip, u, 1.0 / (4.0 * kPiD * c->prm.mu));
   Status st = check_kernel_sum(c, ks);
   if (st.code) return fail(c, st);
+  return ok(c);
+}
+
+mfs_status mfs_time_kernel_sum(mfs_ctx* c, mfs_precision prec, const double* sigma, double* u, int32_t skip,
+                               int32_t reps, double* ms_records, double* ms_sum) {
+  if (!c) return fail(nullptr, Status{MFS_ERR_ARG, "ctx is NULL"});
+  if ((prec != MFS_FP64 && prec != MFS_MIXED) || !sigma || !u || skip < 0 || skip > 2 || reps < 1 || !ms_records ||
+      !ms_sum)
+    return fail(c, Status{MFS_ERR_ARG, "bad argument"});
+  const bool mixed = prec == MFS_MIXED;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(c, Status{MFS_ERR_DEVICE, "hipEventCreate"});
+  const FmmRec fr = fmm_records(c, 0);
+  (void)hipEventRecord(ev[0], c->stream);
+  launch_gather_project(c, MFS_RESISTANCE, sigma, nullptr, false, mixed, !mixed, &fr);
+  (void)hipEventRecord(ev[1], c->stream);
+  for (int r = 0; r < reps; ++r) launch_ksum_fmm(c, mixed, skip, c->d_src64, fr, u, 1.0 / (4.0 * kPiD * c->prm.mu));
+  (void)hipEventRecord(ev[2], c->stream);
+  Status st;
+  if (hipGetLastError() != hipSuccess || hipEventSynchronize(ev[2]) != hipSuccess)
+    st = Status{MFS_ERR_DEVICE, "kernel-sum launch failed"};
+  float a = 0.f, b = 0.f;
+  if (!st.code && (hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess || hipEventElapsedTime(&b, ev[1], ev[2]) != hipSuccess))
+    st = Status{MFS_ERR_DEVICE, "hipEventElapsedTime"};
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  if (st.code) return fail(c, st);
+  *ms_records = a;
+  *ms_sum = b / reps;
   return ok(c);
 }
 

@@ -489,8 +489,8 @@ extern "C" mfs_status mfs_gmres_solve(mfs_ctx* c, mfs_problem prob, mfs_precisio
     int64_t w[5] = {0, 0, 0, 0, 0};
     if (mfs_kernel_sum_work(c, w, 0) != MFS_OK) return MFS_ERR_DEVICE;
     info->direct_pairs = w[0];
-    info->disk_expansions = w[1];
-    info->cluster_expansions = w[2];
+    info->ring_expansions = w[1];
+    info->expansion_terms = w[2];
     info->local_translations = w[3];
     info->local_evaluations = w[4];
   }

@@ -40,6 +40,28 @@ constexpr double kLocSep32 = 3.0;
 constexpr double kLocSep64 = 4.0;
 static_assert(kLoc32 <= kCl64Order && kLoc64 <= kCl64Order && kLoc64 < 32, "local orders");
 constexpr int kCl64CoefPerCluster = 4 * kCl64Order + 2;   // FP64 complex coefficients per cluster
+// Hierarchical far field of the kernel sums over the context's own targets: a quadtree of
+// cells over the disks in slot order (leaf c < P = the disk in slot c); per wave of kFmmT x 64
+// consecutive targets of the visiting order, a list of cells translated into the wave's local
+// expansion (M2L, a cell beyond kFmmSep (R + r_w) of the wave's centre, r_w the wave's radius,
+// holding no target's disk or contact partner) and a list of near disks, each summed at the
+// wave's targets from the disk's own ring expansion, at the lowest order of kTierOrder whose
+// distance threshold every target meets, else directly.  Cell records: kCl64Order.
+constexpr int kFmmT = 2;
+constexpr int kRing64Order = 56;   // ring expansion orders of the near disks (FP64, FP32 sums)
+constexpr int kRing32Order = 44;
+constexpr int kRingTiers = 3;
+// per disk: A_k/(2k), B_k/(2k) (k = 1..p), conj(A_k) (k = 0..p), conj(B_1), (rho^2, d3^2), (d1^2, d2^2),
+// d_i the distances beyond which the tier-i order meets the truncation target, then the disk's
+// FP64 centre and body index: (c_x, c_y), (body, 0) in the FP64 record; c_x, c_y and body as
+// the bits of FP64 values in one float2 each in the FP32 record (padded to 16-byte units)
+constexpr int kRing64Coef = 3 * kRing64Order + 6;
+constexpr int kRing32Coef = 3 * kRing32Order + 8;
+static_assert(kRing32Coef % 2 == 0, "FP32 ring records are staged in 16-byte units");
+// raw moments of a cell about its centre for the upward pass: A_k, B_k, D_k (k = 0..kCl64Order)
+constexpr int kCellRaw = 3 * (kCl64Order + 1);
+// a cell's record for the translations: k_cluster_moments64's layout, then (c_x, c_y), pad
+constexpr int kCellRec = kCl64CoefPerCluster + 2;
 constexpr double kPiD = 3.14159265358979323846;
 
 struct Status {
@@ -65,6 +87,25 @@ struct ClassTab {
   const double* Xr[kMaxClasses];    // mc x 2: nodes relative to the centre
   double KtKi[kMaxClasses][9];      // (K^T K)^{-1}, row-major, of the coarse source ring
   double radius[kMaxClasses];
+  // squared distances from a disk's centre beyond which its ring expansion at the tier orders
+  // (FP64 sum: 27, 40, kRing64Order; FP32 sum: 14, 24, kRing32Order) meets the truncation target
+  double tier64[kMaxClasses][kRingTiers], tier32[kMaxClasses][kRingTiers];
+};
+
+// Where one vector's records of the hierarchical kernel sum go: the context's buffers (vector
+// r, fmm_records) or a caller's buffer
+struct FmmRec {
+  double2* raw = nullptr;   // ncell x kCellRaw
+  double2* rec = nullptr;   // ncell x kCellRec
+  double2* r64 = nullptr;   // P x kRing64Coef
+  float2* r32 = nullptr;    // P x kRing32Coef
+};
+
+// Per-wave interaction lists of the hierarchical kernel sum for one separation factor
+struct FmmLists {
+  double sep = 0.0;
+  std::vector<int32_t> m2l_off, m2l, near_off, near;   // CSR per wave; near: slots, increasing
+  int32_t *d_m2l_off = nullptr, *d_m2l = nullptr, *d_near_off = nullptr, *d_near = nullptr;
 };
 
 struct PairSet {
@@ -155,6 +196,21 @@ struct mfs_ctx {
   double* d_crad64 = nullptr;    // ncl cluster radii (FP64 sum)
   int32_t* d_body_cl = nullptr;  // P: cluster of each disk
   int32_t* d_tperm = nullptr;    // Nt: the kernel sums visit targets in slot order (disk by disk)
+  // hierarchical kernel sum: cells (leaves 0..P-1 = slots), children CSR, heights, wave centres
+  int ncell = 0, nwave = 0, cell_height = 0;
+  std::vector<int32_t> cell_lo, cell_hi, cell_child_off, cell_child, cell_by_height, height_off;
+  std::vector<double> cell_c, cell_r;   // 2 ncell centres, ncell source radii
+  int32_t *d_cell_child_off = nullptr, *d_cell_child = nullptr, *d_cell_by_height = nullptr;
+  double *d_cell_c = nullptr, *d_wcent = nullptr;
+  int32_t* d_wstart = nullptr;   // nwave + 1: each wave's first position in the visiting order
+  std::vector<int32_t> h_wstart;   // host copies of the wave starts and centres
+  std::vector<double> h_wcent;
+  mfs::FmmLists fl[2];           // [0] FP64 sum, [1] mixed sum
+  double2* d_cellraw = nullptr;  // ncell x kCellRaw (per stacked vector: rhs_cap of them)
+  double2* d_cellrec = nullptr;  // ncell x kCl64CoefPerCluster
+  double2* d_ring64 = nullptr;   // P x kRing64Coef (slot order)
+  float2* d_ring32 = nullptr;    // P x kRing32Coef (slot order)
+  int fmm_rcap = 0;              // vectors the record buffers above hold
   unsigned long long* d_work = nullptr;   // kernel-sum work counters: direct pairs, disk and cluster expansions
   double* scratch = nullptr;     // the device's static scratch array (mfs_apply_noalloc), resolved at setup
 
@@ -217,8 +273,10 @@ hipError_t dev_malloc(mfs_ctx* c, T** p, size_t bytes) {
 // ---- kernel launchers (kernels.hip) ----
 void launch_onebody_apply(mfs_ctx* c, int prob, const double* mu, double* lam_bar);
 void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil);
+// strengths packed into c->d_src64 and the hierarchical kernel sum's records of them (fr; NULL:
+// the context's), with the FP32 ring records when pack32
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                           bool pack32, bool pack64);
+                           bool pack32, bool pack64, const FmmRec* fr = nullptr);
 // sig32, bdat, mp (FP32 sum: slot order) and cmp (its cluster coefficients) go together
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                               float4* sig32, double4* src64, float4* bdat, float2* mp = nullptr,
@@ -227,10 +285,19 @@ void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
                        int64_t ltil_stride);
 bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, double scale);
-// mode 0: all sources; 1: skip the target's own disk; 2: also skip its contact partners.  false: out of memory
-bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale, const SplitBuf* sb = nullptr);
-// doubles of split partials one kernel sum of this context needs (0: none)
-int64_t ksum_split_doubles(const mfs_ctx* c, bool mixed);
+// mode 0: all sources; 1: skip the target's own disk; 2: also skip its contact partners.  Sums
+// c->d_src64 with the records fr (NULL: the context's).  false: out of memory
+bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale, const FmmRec* fr = nullptr);
+// hierarchical kernel sum (fmm.hip): host tree and lists at setup; records of packed FP64
+// sources (src64) for R stacked vectors; the sum itself at the context's targets
+Status build_fmm(mfs_ctx* c);
+Status ensure_fmm_records(mfs_ctx* c, int R);
+FmmRec fmm_records(mfs_ctx* c, int r);
+int64_t fmm_record_doubles(const mfs_ctx* c);
+bool fmm_records_in(const mfs_ctx* c, const SplitBuf* sb, FmmRec* out);   // false: sb too small
+void launch_fmm_records(mfs_ctx* c, int prob, const double4* src64, const FmmRec& fr, bool ring32);
+void launch_ksum_fmm(mfs_ctx* c, bool mixed, int mode, const double4* src64, const FmmRec& fr, double* u,
+                     double scale);
 // zero the kernel-sum work counters (a kernel, so that the call may sit in a captured graph)
 void launch_zero_work(mfs_ctx* c);
 // the device's static scratch array for mfs_apply_noalloc (kernels.hip), resolved once per device
@@ -276,6 +343,7 @@ Status onebody_factors(mfs_ctx* c);
 Status precompute_pairs(mfs_ctx* c, int prob);
 
 // ---- matvec pieces (capi.hip) ----
+// sb: a caller's buffer for the kernel sum's records (mfs_apply_noalloc); NULL: the context's
 Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u, const SplitBuf* sb = nullptr);
 // T applied to R vectors (mu, u: R x n, vector r at offset r n); stacked kernels for R in {2, 4, 8}
 Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, double* u);

@@ -2145,6 +2145,480 @@ inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); 
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Hierarchical kernel sum over the context's own targets (Alg. 3 step 2a, eq. getall; the
+// paper evaluates it with a fast multipole method, Sec. 6).  Tree and per-wave lists:
+// fmm_tree.hip.  Per matvec: the disks' ring expansions and the cells' moments (upward pass),
+// then one wave per 64 kFmmT targets: the M2L list into the wave's local expansion, its
+// evaluation at the targets (L2P), and the near list, disk by disk, from each disk's ring
+// expansion at the lowest tier order whose distance every target of the wave meets, else
+// directly over the disk's sources (FP64).  The mixed form evaluates the ring expansions in
+// FP32 (coefficients from FP64 moments, which keep the cancellation between the strengths);
+// translations, local expansions and direct sums are FP64 in both forms.
+
+// w^e for 0 <= e < 64 by binary powering
+__device__ __forceinline__ void cpow_int(double wx, double wy, int e, double& pr, double& pi) {
+  pr = 1.0;
+  pi = 0.0;
+  double br = wx, bi = wy;
+  for (; e; e >>= 1) {
+    if (e & 1) {
+      const double t = pr * br - pi * bi;
+      pi = fma(pr, bi, pi * br);
+      pr = t;
+    }
+    const double u = br * br - bi * bi;
+    bi = 2.0 * br * bi;
+    br = u;
+  }
+}
+
+// One disk per workgroup, lane e forms the order-e moments of its sources about its centre,
+// A_e = sum sigma w^e, B_e = sum sigma conj(w)^e, D_e = sum sigma conj(w) w^e (w = y - c from
+// the class ring, sigma from the packed src64), and writes the disk's ring records (FP64 order
+// kRing64Order, FP32 order kRing32Order, slot order, with the class's tier distances) and its
+// leaf cell (raw moments and the order-kCl64Order record of k_cluster_moments64's layout).
+// In the ring records the k = 1 term of the conj(zeta) series, B_1 conj(zeta) / 2, and the
+// term -conj(zeta) conj(B_1) / 2 of the third part are merged into i Im(B_1) conj(zeta), and
+// conj(B_1) is stored as 0: the dilation moment Re(B_1) = sum y . sigma has no field outside
+// the ring, and the one-body map makes it large (the near-null radial mode of the ring), so
+// the two terms would otherwise cancel in the evaluation's precision.
+__global__ __launch_bounds__(64) void k_ring_moments(int P, const int* __restrict__ cls,
+                                                     const int* __restrict__ src_off, ClassTab ct,
+                                                     const double4* __restrict__ src64,
+                                                     const int* __restrict__ slot_of, const double* __restrict__ centers,
+                                                     double2* __restrict__ ring64, float2* __restrict__ ring32,
+                                                     double2* __restrict__ cellraw, double2* __restrict__ cellrec) {
+  const int b = blockIdx.x;
+  if (b >= P) return;
+  const double cx = centers[2 * b], cy = centers[2 * b + 1];
+  const int e = threadIdx.x;
+  const int k = cls[b];
+  const int nc = ct.nc[k];
+  const double* Yr = ct.Yr[k];
+  const int64_t so = src_off[b];
+  const int sl = slot_of[b];
+  double Ar = 0, Ai = 0, Br = 0, Bi = 0, Dr = 0, Di = 0;
+  for (int j = 0; j < nc; ++j) {
+    const double4 v = src64[so + j];
+    const double wx = Yr[2 * j], wy = Yr[2 * j + 1];
+    double pr, pi;
+    cpow_int(wx, wy, e, pr, pi);
+    const double sr = v.z * pr - v.w * pi, si = v.z * pi + v.w * pr;   // sigma w^e
+    Ar += sr;
+    Ai += si;
+    Br += v.z * pr + v.w * pi;   // sigma conj(w)^e
+    Bi += v.w * pr - v.z * pi;
+    Dr += wx * sr + wy * si;     // conj(w) sigma w^e
+    Di += wx * si - wy * sr;
+  }
+  const double rho2 = Yr[0] * Yr[0] + Yr[1] * Yr[1];
+  {
+    constexpr int Pq = kRing64Order;
+    double2* o = ring64 + (int64_t)sl * kRing64Coef;
+    if (e >= 1 && e <= Pq) {
+      o[e - 1] = make_double2(Ar / (2 * e), Ai / (2 * e));
+      o[Pq + e - 1] = e == 1 ? make_double2(0.0, Bi) : make_double2(Br / (2 * e), Bi / (2 * e));
+    }
+    if (e <= Pq) o[2 * Pq + e] = make_double2(Ar, -Ai);
+    if (e == 1) o[3 * Pq + 1] = make_double2(0.0, 0.0);
+    if (e == 0) {
+      o[3 * Pq + 2] = make_double2(rho2, ct.tier64[k][2]);
+      o[3 * Pq + 3] = make_double2(ct.tier64[k][0], ct.tier64[k][1]);
+      o[3 * Pq + 4] = make_double2(cx, cy);
+      o[3 * Pq + 5] = make_double2((double)b, 0.0);
+    }
+  }
+  if (ring32) {
+    constexpr int Pq = kRing32Order;
+    float2* o = ring32 + (int64_t)sl * kRing32Coef;
+    if (e >= 1 && e <= Pq) {
+      o[e - 1] = make_float2((float)(Ar / (2 * e)), (float)(Ai / (2 * e)));
+      o[Pq + e - 1] = e == 1 ? make_float2(0.0f, (float)Bi) : make_float2((float)(Br / (2 * e)), (float)(Bi / (2 * e)));
+    }
+    if (e <= Pq) o[2 * Pq + e] = make_float2((float)Ar, (float)-Ai);
+    if (e == 1) o[3 * Pq + 1] = make_float2(0.0f, 0.0f);
+    if (e == 0) {
+      // distances rounded up in FP32, so that the FP32 comparison never admits a nearer target
+      auto up = [](double v) {   // v > 0
+        float f = (float)v;
+        if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
+        return f;
+      };
+      o[3 * Pq + 2] = make_float2((float)rho2, up(ct.tier32[k][2]));
+      o[3 * Pq + 3] = make_float2(up(ct.tier32[k][0]), up(ct.tier32[k][1]));
+      const double hv[3] = {cx, cy, (double)b};
+      for (int h = 0; h < 3; ++h) {
+        const unsigned long long u = (unsigned long long)__double_as_longlong(hv[h]);
+        o[3 * Pq + 4 + h] = make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
+      }
+      o[3 * Pq + 7] = make_float2(0.0f, 0.0f);
+    }
+  }
+  if (e <= kCl64Order) {
+    double2* r = cellraw + (int64_t)sl * kCellRaw;
+    r[e] = make_double2(Ar, Ai);
+    r[kCl64Order + 1 + e] = make_double2(Br, Bi);
+    r[2 * (kCl64Order + 1) + e] = make_double2(Dr, Di);
+    double2* o = cellrec + (int64_t)sl * kCellRec;
+    if (e >= 1) {
+      o[e - 1] = make_double2(Ar / (2 * e), Ai / (2 * e));
+      o[kCl64Order + e - 1] = make_double2(Br / (2 * e), Bi / (2 * e));
+    }
+    o[2 * kCl64Order + e] = make_double2(Ar, -Ai);
+    o[3 * kCl64Order + 1 + e] = make_double2(Dr, -Di);
+    if (e == 0) {
+      o[kCl64CoefPerCluster] = make_double2(cx, cy);
+      o[kCl64CoefPerCluster + 1] = make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// Upward pass, one wave per internal cell of one height: its children's moments moved to the
+// cell's centre C and summed.  With delta = C_child - C, w' = w + delta:
+//   A'_k = sum_j binom(k, j) delta^(k-j) A_j,   B'_k = sum_j binom(k, j) conj(delta)^(k-j) B_j,
+//   D'_k = sum_j binom(k, j) delta^(k-j) (D_j + conj(delta) A_j).
+// Lane k <= kCl64Order forms A'_k and D'_k, lane 32 + k forms B'_k; each child's raw moments and
+// the powers of its delta are staged in LDS first.
+__global__ __launch_bounds__(64) void k_cell_m2m(int n, const int* __restrict__ cells,
+                                                 const int* __restrict__ child_off, const int* __restrict__ child,
+                                                 const double* __restrict__ cell_c, double2* __restrict__ raw,
+                                                 double2* __restrict__ rec) {
+  static_assert(kCl64Order < 32 && kCellRaw <= 128, "one lane per order, two raw entries per lane");
+  if ((int)blockIdx.x >= n) return;
+  const int q = cells[blockIdx.x];
+  const int lane = threadIdx.x, f = lane >> 5, k = lane & 31;
+  const double cx = cell_c[2 * q], cy = cell_c[2 * q + 1];
+  __shared__ double2 s_pw[32];          // delta^m
+  __shared__ double2 s_raw[kCellRaw];   // the child's A, B, D
+  double ar = 0, ai = 0, dr = 0, di = 0;
+  for (int e = child_off[q]; e < child_off[q + 1]; ++e) {
+    const int ch = child[e];
+    const double dx = cell_c[2 * ch] - cx, dy = cell_c[2 * ch + 1] - cy;
+    const double2* cr = raw + (int64_t)ch * kCellRaw;
+    const double2 v0 = cr[lane];
+    const double2 v1 = lane + 64 < kCellRaw ? cr[lane + 64] : make_double2(0.0, 0.0);
+    double pr = 0.0, pi = 0.0;
+    if (lane < 32) cpow_int(dx, dy, lane, pr, pi);
+    wave_lds_sync();   // the previous child's reads are done
+    s_raw[lane] = v0;
+    if (lane + 64 < kCellRaw) s_raw[lane + 64] = v1;
+    if (lane < 32) s_pw[lane] = make_double2(pr, pi);
+    wave_lds_sync();
+    if (k <= kCl64Order) {
+      double bn = 1.0;   // binom(k, j)
+      for (int j = 0; j <= k; ++j) {
+        const double2 pw = s_pw[k - j];
+        const double pwr = pw.x, pwi = f == 0 ? pw.y : -pw.y;
+        const double cr2 = bn * pwr, ci2 = bn * pwi;
+        if (f == 0) {
+          const double2 a = s_raw[j], d = s_raw[2 * (kCl64Order + 1) + j];
+          ar = fma(cr2, a.x, fma(-ci2, a.y, ar));
+          ai = fma(cr2, a.y, fma(ci2, a.x, ai));
+          // D_j + conj(delta) A_j
+          const double gr = d.x + (dx * a.x + dy * a.y), gi = d.y + (dx * a.y - dy * a.x);
+          dr = fma(cr2, gr, fma(-ci2, gi, dr));
+          di = fma(cr2, gi, fma(ci2, gr, di));
+        } else {
+          const double2 bq = s_raw[kCl64Order + 1 + j];
+          ar = fma(cr2, bq.x, fma(-ci2, bq.y, ar));
+          ai = fma(cr2, bq.y, fma(ci2, bq.x, ai));
+        }
+        bn = bn * (double)(k - j) * kInvInt[j + 1];
+      }
+    }
+  }
+  if (lane == 0) {
+    double2* o = rec + (int64_t)q * kCellRec;
+    o[kCl64CoefPerCluster] = make_double2(cx, cy);
+    o[kCl64CoefPerCluster + 1] = make_double2(0.0, 0.0);
+  }
+  if (k > kCl64Order) return;
+  double2* r = raw + (int64_t)q * kCellRaw;
+  double2* o = rec + (int64_t)q * kCellRec;
+  if (f == 0) {
+    r[k] = make_double2(ar, ai);
+    r[2 * (kCl64Order + 1) + k] = make_double2(dr, di);
+    if (k >= 1) o[k - 1] = make_double2(ar / (2 * k), ai / (2 * k));
+    o[2 * kCl64Order + k] = make_double2(ar, -ai);
+    o[3 * kCl64Order + 1 + k] = make_double2(dr, -di);
+  } else {
+    r[kCl64Order + 1 + k] = make_double2(ar, ai);
+    if (k >= 1) o[kCl64Order + k - 1] = make_double2(ar / (2 * k), ai / (2 * k));
+  }
+}
+
+// Ring expansion of one disk (record cf of order Pq, evaluated to order p <= Pq) added at a
+// thread's targets (offsets Zx, Zy from the disk's centre, R2 = |Z|^2, q = rho^2) where not
+// skipped: the series of k_gather_project's far field in precision Real.
+template <typename Real, typename C2, int T>
+__device__ __forceinline__ void ring_m2p(const C2* __restrict__ cf, int Pq, int p, Real q, const Real (&Zx)[T],
+                                         const Real (&Zy)[T], const Real (&R2)[T], const bool (&skip)[T],
+                                         double (&ax)[T], double (&ay)[T]) {
+  Real zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T];
+  const C2 c1 = cf[p - 1], c2 = cf[Pq + p - 1], c3 = cf[2 * Pq + p];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    Real ir2;
+    if constexpr (sizeof(Real) == 4)
+      ir2 = __builtin_amdgcn_rcpf(R2[j]);
+    else
+      ir2 = rcp_f64(R2[j]);
+    zr[j] = Zx[j] * ir2;   // zeta = conj(Z) / R^2 = (zr, -zi); conj(zeta) = (zr, zi)
+    zi[j] = Zy[j] * ir2;
+    h1r[j] = c1.x;
+    h1i[j] = c1.y;
+    h2r[j] = c2.x;
+    h2i[j] = c2.y;
+    h3r[j] = c3.x;
+    h3i[j] = c3.y;
+  }
+  // Horner: h1 over zeta (A_k/2k), h2 over conj(zeta) (B_k/2k), h3 over conj(zeta) (conj A_k)
+#pragma unroll 2
+  for (int m = p - 1; m >= 1; --m) {
+    const C2 a = cf[m - 1], bq = cf[Pq + m - 1], g = cf[2 * Pq + m];
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      const Real t1r = fma(zr[j], h1r[j], fma(zi[j], h1i[j], a.x));
+      const Real t1i = fma(zr[j], h1i[j], fma(-zi[j], h1r[j], a.y));
+      const Real t2r = fma(zr[j], h2r[j], fma(-zi[j], h2i[j], bq.x));
+      const Real t2i = fma(zr[j], h2i[j], fma(zi[j], h2r[j], bq.y));
+      const Real t3r = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g.x));
+      const Real t3i = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g.y));
+      h1r[j] = t1r;
+      h1i[j] = t1i;
+      h2r[j] = t2r;
+      h2i[j] = t2i;
+      h3r[j] = t3r;
+      h3i[j] = t3i;
+    }
+  }
+  const C2 g0 = cf[2 * Pq], dl = cf[3 * Pq + 1];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    // P3 = conj(A_0) + conj(zeta) h3; P1 = zeta h1; P2 = conj(zeta) h2
+    const Real p3r = fma(zr[j], h3r[j], fma(-zi[j], h3i[j], g0.x));
+    const Real p3i = fma(zr[j], h3i[j], fma(zi[j], h3r[j], g0.y));
+    const Real p1r = fma(zr[j], h1r[j], zi[j] * h1i[j]);
+    const Real p1i = fma(zr[j], h1i[j], -zi[j] * h1r[j]);
+    const Real p2r = fma(zr[j], h2r[j], -zi[j] * h2i[j]);
+    const Real p2i = fma(zr[j], h2i[j], zi[j] * h2r[j]);
+    // conj(zeta)/2 [(Z - rho^2 conj(zeta)) P3 - conj(B_1)], Z - rho^2 conj(zeta) = Z (1 - q / R^2)
+    const Real fq = fma(-q, zr[j] * zr[j] + zi[j] * zi[j], Real(1));
+    const Real mr = fq * fma(Zx[j], p3r, -Zy[j] * p3i) - dl.x;
+    const Real mi = fq * fma(Zx[j], p3i, Zy[j] * p3r) - dl.y;
+    const Real t3r = Real(0.5) * fma(zr[j], mr, -zi[j] * mi);
+    const Real t3i = Real(0.5) * fma(zr[j], mi, zi[j] * mr);
+    // -S0 ln|Z| + S0 / 2
+    Real lZ;
+    if constexpr (sizeof(Real) == 4)
+      lZ = fmaf(-0.34657359027997264f, __builtin_amdgcn_logf(R2[j]), 0.5f);
+    else
+      lZ = fma(-0.5, ln_f64(R2[j]), 0.5);
+    const Real fx = fma(g0.x, lZ, p1r + p2r + t3r);   // S0 = conj(g0)
+    const Real fy = fma(-g0.y, lZ, p1i + p2i + t3i);
+    if (!skip[j]) {
+      ax[j] += (double)fx;
+      ay[j] += (double)fy;
+    }
+  }
+}
+
+__device__ __forceinline__ double bits_to_double(float2 v) {
+  return __longlong_as_double((long long)(((unsigned long long)__float_as_uint(v.y) << 32) | __float_as_uint(v.x)));
+}
+
+// One wave per 64 T targets.  The records a wave reads (a cell's for each translation, a disk's
+// ring record for each near disk) are staged in LDS, two buffers deep: the global loads of the
+// next record are in flight while the current one is used.
+template <bool MIXED, int T>
+__global__ __launch_bounds__(64) void k_ksum_fmm(
+    const int* __restrict__ wstart, const int* __restrict__ tperm, const int* __restrict__ tgt_body,
+    const int* __restrict__ slot_of, const double* __restrict__ X, const int* __restrict__ src_off,
+    const double4* __restrict__ src64,
+    const int* __restrict__ m2l_off, const int* __restrict__ m2l, const int* __restrict__ near_off,
+    const int* __restrict__ near, const double* __restrict__ wcent, const double2* __restrict__ cellrec,
+    const double2* __restrict__ rings, int mode, const int* __restrict__ nbr_off,
+    const int* __restrict__ nbr_slot, double scale, double* __restrict__ out, unsigned long long* __restrict__ work) {
+  constexpr int Q = MIXED ? kLoc32 : kLoc64;
+  // a ring record in 16-byte units (FP32 records: two float2 per unit)
+  constexpr int RU = MIXED ? kRing32Coef / 2 : kRing64Coef;
+  constexpr int SU = RU > kCellRec ? RU : kCellRec;
+  static_assert(SU <= 192, "three 16-byte units per lane");
+  __shared__ double2 s_buf[2][SU];
+  __shared__ double2 s_row[64];
+  const int w = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int p0 = wstart[w], p1 = wstart[w + 1];   // this wave's positions in the visiting order
+  int t[T];
+  int64_t tt[T];
+  int bt[T];
+  double x[T], y[T], ax[T], ay[T];
+  Skip sk[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    t[j] = p0 + lane * T + j;
+    const int tc = t[j] < p1 ? t[j] : p1 - 1;
+    tt[j] = tperm[tc];
+    const int body = tgt_body[tt[j]];
+    bt[j] = mode != 0 ? slot_of[body] : -1;
+    x[j] = X[2 * tt[j]];
+    y[j] = X[2 * tt[j] + 1];
+    ax[j] = 0.0;
+    ay[j] = 0.0;
+    skip_init(sk[j], mode, body, 0, nbr_off, nbr_slot);
+  }
+  unsigned n_dir = 0, n_exp = 0, n_terms = 0, n_m2l = 0, n_l2p = 0;
+  double2 pre[3];
+  auto fetch = [&](const double2* g, int units) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int i = lane + 64 * u;
+      pre[u] = i < units ? g[i] : make_double2(0.0, 0.0);
+    }
+  };
+  auto stage = [&](double2* buf, int units) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int i = lane + 64 * u;
+      if (i < units) buf[i] = pre[u];
+    }
+  };
+  // far field: the wave's local expansion about its centre B
+  const double bx = wcent[2 * w], by = wcent[2 * w + 1];
+  const int m0 = m2l_off[w], m1 = m2l_off[w + 1];
+  if (m1 > m0) {
+    double Lr = 0.0, Li = 0.0;
+    fetch(cellrec + (int64_t)m2l[m0] * kCellRec, kCellRec);
+    for (int e = m0; e < m1; ++e) {
+      double2* buf = s_buf[e & 1];
+      stage(buf, kCellRec);   // its previous reads (two translations back) are done
+      wave_lds_sync();
+      if (e + 1 < m1) fetch(cellrec + (int64_t)m2l[e + 1] * kCellRec, kCellRec);
+      const double2 cc = buf[kCl64CoefPerCluster];
+      m2l_add<kCl64Order, Q>(buf, cc.x, cc.y, bx, by, s_row, Lr, Li);
+    }
+    wave_lds_sync();   // the last translation's reads of the row are done
+    s_row[lane] = make_double2(Lr, Li);
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      double ux, uy;
+      l2p<Q>(s_row, x[j] - bx, y[j] - by, ux, uy);
+      ax[j] += ux;
+      ay[j] += uy;
+    }
+    n_m2l = lane == 0 ? (unsigned)(m1 - m0) : 0u;
+    n_l2p = T;
+  }
+  // near disks, in increasing slot order (the skip cursors rely on it)
+  const int n0 = near_off[w], n1 = near_off[w + 1];
+  if (n1 > n0) fetch(rings + (int64_t)near[n0] * RU, RU);
+  for (int e = n0; e < n1; ++e) {
+    const int s = near[e];
+    double2* buf = s_buf[e & 1];
+    stage(buf, RU);
+    wave_lds_sync();
+    if (e + 1 < n1) fetch(rings + (int64_t)near[e + 1] * RU, RU);
+    // header: tier distances (squared, d1 > d2 > d3), the disk's centre and body
+    double d1, d2, d3, cx, cy;
+    int b;
+    if (MIXED) {
+      const float2* o = (const float2*)buf;
+      d1 = o[3 * kRing32Order + 3].x;
+      d2 = o[3 * kRing32Order + 3].y;
+      d3 = o[3 * kRing32Order + 2].y;
+      cx = bits_to_double(o[3 * kRing32Order + 4]);
+      cy = bits_to_double(o[3 * kRing32Order + 5]);
+      b = (int)bits_to_double(o[3 * kRing32Order + 6]);
+    } else {
+      const double2* o = buf;
+      d1 = o[3 * kRing64Order + 3].x;
+      d2 = o[3 * kRing64Order + 3].y;
+      d3 = o[3 * kRing64Order + 2].y;
+      cx = o[3 * kRing64Order + 4].x;
+      cy = o[3 * kRing64Order + 4].y;
+      b = (int)o[3 * kRing64Order + 5].x;
+    }
+    double Zx[T], Zy[T], R2[T];
+    bool skip[T];
+    bool all_skip = true, ok1 = true, ok2 = true, ok3 = true;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      Zx[j] = x[j] - cx;
+      Zy[j] = y[j] - cy;
+      R2[j] = fma(Zx[j], Zx[j], Zy[j] * Zy[j]);
+      skip[j] = skip_test(sk[j], mode, s, bt[j], nbr_slot);
+      all_skip = all_skip && skip[j];
+      ok1 = ok1 && (skip[j] || R2[j] > d1);
+      ok2 = ok2 && (skip[j] || R2[j] > d2);
+      ok3 = ok3 && (skip[j] || R2[j] > d3);
+    }
+    if (__all(all_skip)) continue;
+    int p = 0;
+    if (__all(ok1))
+      p = MIXED ? 14 : 27;
+    else if (__all(ok2))
+      p = MIXED ? 24 : 40;
+    else if (__all(ok3))
+      p = MIXED ? kRing32Order : kRing64Order;
+    if (p > 0) {
+      ++n_exp;
+      n_terms += p;
+      if (MIXED) {
+        const float2* cf = (const float2*)buf;
+        float fZx[T], fZy[T], fR2[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          fZx[j] = (float)Zx[j];
+          fZy[j] = (float)Zy[j];
+          fR2[j] = fmaf(fZx[j], fZx[j], fZy[j] * fZy[j]);
+        }
+        ring_m2p<float, float2, T>(cf, kRing32Order, p, cf[3 * kRing32Order + 2].x, fZx, fZy, fR2, skip, ax, ay);
+      } else {
+        ring_m2p<double, double2, T>(buf, kRing64Order, p, buf[3 * kRing64Order + 2].x, Zx, Zy, R2, skip, ax, ay);
+      }
+      continue;
+    }
+    // direct FP64 sum over the disk's sources
+    double lx[T], ly[T], txx[T], tyy[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) lx[j] = ly[j] = txx[j] = tyy[j] = 0.0;
+    const int q0 = src_off[b], q1 = src_off[b + 1];
+    n_dir += q1 - q0;
+    for (int qq = q0; qq < q1; ++qq) {
+      const double4 sv = src64[qq];
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        const double dx = x[j] - sv.x;
+        const double dy = y[j] - sv.y;
+        const double r2 = fma(dx, dx, dy * dy);
+        const double lg = ln_f64(r2);
+        const double dot = fma(dx, sv.z, dy * sv.w) * rcp_f64(r2);
+        lx[j] = fma(lg, sv.z, lx[j]);
+        ly[j] = fma(lg, sv.w, ly[j]);
+        txx[j] = fma(dot, dx, txx[j]);
+        tyy[j] = fma(dot, dy, tyy[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      if (!skip[j]) {
+        ax[j] += fma(-0.5, lx[j], txx[j]);
+        ay[j] += fma(-0.5, ly[j], tyy[j]);
+      }
+    }
+  }
+  add_work(work, T * n_dir, T * n_exp, T * n_terms, n_m2l, n_l2p);
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    if (t[j] < p1) {
+      out[tt[j] * 2] = ax[j] * scale;
+      out[tt[j] * 2 + 1] = ay[j] * scale;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 
 namespace {
@@ -2188,11 +2662,10 @@ void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil) {
 }
 
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                           bool pack32, bool pack64) {
-  launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, pack32 ? c->d_sig32 : nullptr,
-                           pack64 ? c->d_src64 : nullptr, pack32 ? c->d_bdat : nullptr, pack32 ? c->d_mp : nullptr,
-                           pack32 ? c->d_cmp : nullptr, pack32 ? c->d_mp64 + (int64_t)c->P * kMp64Coef : nullptr);
-  if (pack64) launch_moments64(c, c->d_src64, c->d_mp64);
+                           bool pack32, bool pack64, const FmmRec* fr) {
+  (void)pack64;
+  launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, nullptr, c->d_src64, nullptr);
+  launch_fmm_records(c, prob, c->d_src64, fr ? *fr : fmm_records(c, 0), pack32);
 }
 
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
@@ -2277,29 +2750,13 @@ static double* split_buffer(mfs_ctx* c, int64_t need, const SplitBuf* sb) {
   return c->d_upart;
 }
 
-int64_t ksum_split_doubles(const mfs_ctx* c, bool mixed) {
-  const int64_t T = ksum_targets_per_thread(mixed);
-  const int ns = std::min(ksum_splits((c->Nt + KS_THREADS * T - 1) / (KS_THREADS * T), c->P), c->ncl);
-  return ns > 1 ? (int64_t)ns * c->Nt * 2 : 0;
-}
 
-// Stacked form of launch_kernel_sum: R strength vectors packed by launch_gather_project_to
-// into c->d_sig32m / c->d_bdatm (mixed) or c->d_src64m (FP64), R arrays each; u: R x 2 Nt.
-// false: out of memory for the split partials, or R unsupported.
+// Stacked form of launch_kernel_sum: R strength vectors packed into c->d_src64m (R arrays of Ns
+// records) and their records (launch_fmm_records); u: R x 2 Nt.
 bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, double scale) {
-  for (int r = 0; r < R; ++r) {
-    double* ur = u + (int64_t)r * 2 * c->Nt;
-    const bool ok =
-        mixed ? launch_ksum_mixed_arrays(c, mode, c->d_sig32m + (int64_t)r * c->Ns, c->d_bdatm + (int64_t)r * c->P,
-                                         c->d_mpm + (int64_t)r * c->P * kMpCoef,
-                                         c->d_cmpm + (int64_t)r * c->ncl * kClCoef,
-                                         c->d_mp64m + (int64_t)r * mp64_record(c) + (int64_t)c->P * kMp64Coef, ur,
-                                         scale)
-              : launch_ksum_fp64_arrays(c, mode, c->d_src64m + (int64_t)r * c->Ns,
-                                        c->d_mp64m + (int64_t)r * mp64_record(c), c->Nt, c->d_X, c->d_tgt_body,
-                                        c->d_tperm, ur, scale);
-    if (!ok) return false;
-  }
+  for (int r = 0; r < R; ++r)
+    launch_ksum_fmm(c, mixed, mode, c->d_src64m + (int64_t)r * c->Ns, fmm_records(c, r), u + (int64_t)r * 2 * c->Nt,
+                    scale);
   return true;
 }
 
@@ -2370,12 +2827,65 @@ static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, co
   return true;
 }
 
-bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale, const SplitBuf* sb) {
-  if (mixed)
-    return launch_ksum_mixed_arrays(c, mode, c->d_sig32, c->d_bdat, c->d_mp, c->d_cmp,
-                                    c->d_mp64 + (int64_t)c->P * kMp64Coef, u, scale, sb);
-  return launch_ksum_fp64_arrays(c, mode, c->d_src64, c->d_mp64, c->Nt, c->d_X, c->d_tgt_body, c->d_tperm, u, scale,
-                                 sb);
+bool launch_kernel_sum(mfs_ctx* c, bool mixed, int mode, double* u, double scale, const FmmRec* fr) {
+  const FmmRec f = fr ? *fr : fmm_records(c, 0);
+  launch_ksum_fmm(c, mixed, mode, c->d_src64, f, u, scale);
+  return true;
+}
+
+FmmRec fmm_records(mfs_ctx* c, int r) {
+  FmmRec f;
+  f.raw = c->d_cellraw + (int64_t)r * c->ncell * kCellRaw;
+  f.rec = c->d_cellrec + (int64_t)r * c->ncell * kCellRec;
+  f.r64 = c->d_ring64 + (int64_t)r * c->P * kRing64Coef;
+  f.r32 = c->d_ring32 + (int64_t)r * c->P * kRing32Coef;
+  return f;
+}
+
+// doubles of one vector's records (a float2 counts as one double)
+int64_t fmm_record_doubles(const mfs_ctx* c) {
+  return 2 * (int64_t)c->ncell * (kCellRaw + kCellRec) + 2 * (int64_t)c->P * kRing64Coef +
+         (int64_t)c->P * kRing32Coef;
+}
+
+bool fmm_records_in(const mfs_ctx* c, const SplitBuf* sb, FmmRec* out) {
+  if (!sb || sb->cap < fmm_record_doubles(c)) return false;
+  double* p = sb->p;   // 256-byte aligned; every part below is a multiple of 16 bytes
+  out->raw = (double2*)p;
+  p += 2 * (int64_t)c->ncell * kCellRaw;
+  out->rec = (double2*)p;
+  p += 2 * (int64_t)c->ncell * kCellRec;
+  out->r64 = (double2*)p;
+  p += 2 * (int64_t)c->P * kRing64Coef;
+  out->r32 = (float2*)p;
+  return true;
+}
+
+// Records of the hierarchical kernel sum for a packed source array: ring records and leaf
+// cells of every disk, then the internal cells by height.
+void launch_fmm_records(mfs_ctx* c, int prob, const double4* src64, const FmmRec& fr, bool ring32) {
+  hipLaunchKernelGGL(k_ring_moments, dim3(c->P), dim3(64), 0, c->stream, c->P, c->d_cls, c->d_src_off, c->ct[prob],
+                     src64, c->d_slot_of, c->d_centers, fr.r64, ring32 ? fr.r32 : (float2*)nullptr, fr.raw, fr.rec);
+  for (int h = 1; h <= c->cell_height; ++h) {
+    const int n = c->height_off[h + 1] - c->height_off[h];
+    if (n > 0)
+      hipLaunchKernelGGL(k_cell_m2m, dim3(n), dim3(64), 0, c->stream, n, c->d_cell_by_height + c->height_off[h],
+                         c->d_cell_child_off, c->d_cell_child, c->d_cell_c, fr.raw, fr.rec);
+  }
+}
+
+// The hierarchical kernel sum at the context's targets (records fr of launch_fmm_records,
+// direct sums from src64), written to u (2 Nt), scaled.
+void launch_ksum_fmm(mfs_ctx* c, bool mixed, int mode, const double4* src64, const FmmRec& fr, double* u,
+                     double scale) {
+  const FmmLists& L = c->fl[mixed ? 1 : 0];
+#define MFS_KS_FMM(MX, RINGS)                                                                                    \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ksum_fmm<MX, kFmmT>), dim3(c->nwave), dim3(64), 0, c->stream,             \
+                     c->d_wstart, c->d_tperm, c->d_tgt_body, c->d_slot_of, c->d_X, c->d_src_off, src64, L.d_m2l_off, L.d_m2l,  \
+                     L.d_near_off, L.d_near, c->d_wcent, fr.rec, RINGS, mode, c->d_nbr_off, c->d_nbr_slot, scale, \
+                     u, c->d_work)
+  if (mixed) MFS_KS_FMM(true, (const double2*)fr.r32); else MFS_KS_FMM(false, (const double2*)fr.r64);
+#undef MFS_KS_FMM
 }
 
 void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr) {
@@ -2396,7 +2906,7 @@ void launch_finish(mfs_ctx* c, const double* u_sum, const double* mu, const doub
 void launch_rhs_mobility_sources(mfs_ctx* c, const double* given) {
   hipLaunchKernelGGL(k_rhs_sources, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
                      c->ct[MFS_MOBILITY], c->d_centers, given, c->d_src64, 0);
-  launch_moments64(c, c->d_src64, c->d_mp64);
+  launch_fmm_records(c, MFS_MOBILITY, c->d_src64, fmm_records(c, 0), false);
 }
 
 void launch_add_rhs_sources(mfs_ctx* c, const double* given, double4* src64) {

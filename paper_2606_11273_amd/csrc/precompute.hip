@@ -287,6 +287,71 @@ struct DevMem {   // a per-batch device buffer of the context, freed at the end 
 
 }  // namespace
 
+// Tier distances of a class's ring expansion (hierarchical kernel sum).  For strengths
+// sigma = G mu of the one-body map (G = (I - L) S_L^+ for mobility, P^+ for resistance; n x m,
+// column-major) and |mu| = 1, the moments A_k = sum sigma w^k and B_k = sum sigma conj(w)^k
+// are bounded by the norms of their rows a_k, b_k, and truncating the ring expansion after
+// order p leaves at distance R at most
+//   tail(p, R) = sum_{k > p} (|a_k| / (2k) + |b_k| / (2k) + |a_k|) R^-k
+// (the three series of the ring expansion; k up to kmax, beyond which the ring's aliasing
+// repeats the moments scaled by rho^nc).  The ring rule's small singular values make the top
+// modes of sigma large, so this bound, not (rho / R)^p, sets the order near a disk.  For any
+// other strengths the bound is sum |sigma| (rho / R)^(p+1) / (1 - rho / R).  The tier distance
+// is the larger of the distances where the two meet tol and tol_theta; its square is stored.
+static void ring_tiers(int nc, int m, const std::vector<double>& Yr, const std::vector<double>& G, const int* orders,
+                       int ntier, double tol, double tol_theta, double* thr2) {
+  const int kmax = std::min(2 * nc + 8, 320);
+  std::vector<double> na(kmax + 1, 0.0), nb(kmax + 1, 0.0);
+  std::vector<double> ar((size_t)(kmax + 1) * m, 0.0), ai(ar.size(), 0.0), br(ar.size(), 0.0), bi(ar.size(), 0.0);
+  for (int s2 = 0; s2 < nc; ++s2) {
+    const double wx = Yr[2 * s2], wy = Yr[2 * s2 + 1];
+    double pr = 1.0, pi = 0.0;   // w^k
+    for (int k = 0; k <= kmax; ++k) {
+      for (int q = 0; q < m; ++q) {
+        const double gx = G[(size_t)q * 2 * nc + 2 * s2], gy = G[(size_t)q * 2 * nc + 2 * s2 + 1];
+        // sigma w^k and sigma conj(w)^k with sigma = gx + i gy
+        ar[(size_t)k * m + q] += gx * pr - gy * pi;
+        ai[(size_t)k * m + q] += gx * pi + gy * pr;
+        br[(size_t)k * m + q] += gx * pr + gy * pi;
+        bi[(size_t)k * m + q] += gy * pr - gx * pi;
+      }
+      const double t = pr * wx - pi * wy;
+      pi = pr * wy + pi * wx;
+      pr = t;
+    }
+  }
+  for (int k = 0; k <= kmax; ++k) {
+    double sa = 0.0, sb = 0.0;
+    for (int q = 0; q < m; ++q) {
+      sa += ar[(size_t)k * m + q] * ar[(size_t)k * m + q] + ai[(size_t)k * m + q] * ai[(size_t)k * m + q];
+      sb += br[(size_t)k * m + q] * br[(size_t)k * m + q] + bi[(size_t)k * m + q] * bi[(size_t)k * m + q];
+    }
+    na[k] = std::sqrt(sa);
+    nb[k] = std::sqrt(sb);
+  }
+  const double rho = std::sqrt(Yr[0] * Yr[0] + Yr[1] * Yr[1]);
+  for (int t = 0; t < ntier; ++t) {
+    const int p = orders[t];
+    auto tail = [&](double R) {
+      double e = 0.0;
+      for (int k = p + 1; k <= kmax; ++k) e += ((na[k] + nb[k]) / (2.0 * k) + na[k]) * std::pow(R, -(double)k);
+      return e;
+    };
+    double lo = rho * (1.0 + 1e-9), hi = 1e3 * std::max(rho, 1.0), R;
+    if (tail(hi) > tol) {
+      R = 1e150;   // never: the tier is not used
+    } else {
+      for (int it = 0; it < 100; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (tail(mid) > tol) lo = mid; else hi = mid;
+      }
+      R = std::max(hi, rho * std::pow(tol_theta, -1.0 / (p + 1)));
+    }
+    thr2[t] = R * R;
+  }
+  for (int t = 1; t < ntier; ++t) thr2[t] = std::min(thr2[t], thr2[t - 1]);
+}
+
 // ---------------------------------------------------------------------------
 Status onebody_factors(mfs_ctx* c) {
   // distinct classes
@@ -381,6 +446,39 @@ Status onebody_factors(mfs_ctx* c) {
       if (info != 0) return Status{MFS_ERR_NUMERIC, "one-body SVD did not converge"};
       int rank = 0;
       while (rank < mn && S[rank] > S[0] * c->prm.eps_trunc) ++rank;
+      {
+        // G = Pi S^+ (n x m, column-major): V Sigma^+ U^T, then (I - L) per column for mobility
+        std::vector<double> Gm((size_t)n * m, 0.0);
+        for (int q = 0; q < m; ++q)
+          for (int j = 0; j < rank; ++j) {
+            const double f = U[(size_t)j * m + q] / S[j];
+            for (int i = 0; i < n; ++i) Gm[(size_t)q * n + i] += VT[(size_t)i * mn + j] * f;
+          }
+        if (prob == MFS_MOBILITY)
+          for (int q = 0; q < m; ++q) {
+            double* col = Gm.data() + (size_t)q * n;
+            double kt[3] = {0, 0, 0};
+            for (int j = 0; j < nc; ++j) {
+              kt[0] += col[2 * j];
+              kt[1] += col[2 * j + 1];
+              kt[2] += -Y[j].y * col[2 * j] + Y[j].x * col[2 * j + 1];
+            }
+            double cf[3];
+            for (int r = 0; r < 3; ++r) cf[r] = KKi[3 * r] * kt[0] + KKi[3 * r + 1] * kt[1] + KKi[3 * r + 2] * kt[2];
+            for (int j = 0; j < nc; ++j) {
+              col[2 * j] -= cf[0] - cf[2] * Y[j].y;
+              col[2 * j + 1] -= cf[1] + cf[2] * Y[j].x;
+            }
+          }
+        std::vector<double> Yv(2 * nc);
+        for (int j = 0; j < nc; ++j) {
+          Yv[2 * j] = Y[j].x;
+          Yv[2 * j + 1] = Y[j].y;
+        }
+        const int o64[kRingTiers] = {27, 40, kRing64Order}, o32[kRingTiers] = {14, 24, kRing32Order};
+        ring_tiers(nc, m, Yv, Gm, o64, kRingTiers, 1e-15, 1e-16, ct.tier64[k]);
+        ring_tiers(nc, m, Yv, Gm, o32, kRingTiers, 1e-9, 1e-9, ct.tier32[k]);
+      }
       std::vector<double> Urm((size_t)m * rank), Vtrm((size_t)rank * n), sinv(rank);
       for (int q = 0; q < m; ++q)
         for (int j = 0; j < rank; ++j) Urm[(size_t)q * rank + j] = U[(size_t)j * m + q];

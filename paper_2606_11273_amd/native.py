@@ -32,7 +32,7 @@ SYMBOLS = ["mfs_default_params", "mfs_setup", "mfs_precompute_pairs", "mfs_get_p
            "mfs_get_sizes", "mfs_destroy", "mfs_last_error", "mfs_server_create", "mfs_server_footprint",
            "mfs_server_submit", "mfs_server_wait", "mfs_server_last_error", "mfs_server_destroy",
            "mfs_keep_fine_factors", "mfs_get_density", "mfs_flow_eval", "mfs_boundary_residual",
-           "mfs_setup_ex"]
+           "mfs_setup_ex", "mfs_get_fmm", "mfs_time_kernel_sum"]
 
 
 class MfsParams(C.Structure):
@@ -47,8 +47,8 @@ class MfsSolveInfo(C.Structure):
                 ("resid_hist", C.POINTER(C.c_double)), ("hist_cap", C.c_int32), ("hist_len", C.c_int32),
                 ("ms_rhs", C.c_double), ("ms_iterate", C.c_double), ("ms_post", C.c_double),
                 ("n_pairs", C.c_int64), ("matvecs_fp64", C.c_int32), ("matvecs_mixed", C.c_int32),
-                ("dense_pairs", C.c_int64), ("direct_pairs", C.c_int64), ("disk_expansions", C.c_int64),
-                ("cluster_expansions", C.c_int64), ("local_translations", C.c_int64),
+                ("dense_pairs", C.c_int64), ("direct_pairs", C.c_int64), ("ring_expansions", C.c_int64),
+                ("expansion_terms", C.c_int64), ("local_translations", C.c_int64),
                 ("local_evaluations", C.c_int64)]
 
 
@@ -136,11 +136,13 @@ def lib():
     L.mfs_precompute_pairs.argtypes = [vp, C.c_int, i64p]
     L.mfs_get_pairs.argtypes = [vp, i64p, ip]
     L.mfs_get_clusters.argtypes = [vp, ip, ip, ip, dp, dp]
+    L.mfs_get_fmm.argtypes = [vp, C.c_int, C.c_int, i64p, ip, ip, dp, dp, ip, dp, ip, ip, ip, ip, dp]
     L.mfs_set_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
     L.mfs_get_pair_matrices.argtypes = [vp, C.c_int, dp, dp]
     L.mfs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int32, vp, vp]
     L.mfs_apply_noalloc.argtypes = [vp, C.c_int, C.c_int, vp, vp]
     L.mfs_kernel_sum.argtypes = [vp, C.c_int, vp, vp, C.c_int32]
+    L.mfs_time_kernel_sum.argtypes = [vp, C.c_int, vp, vp, C.c_int32, C.c_int32, dp, dp]
     L.mfs_kernel_sum_work.argtypes = [vp, i64p, C.c_int32]
     L.mfs_rhs.argtypes = [vp, C.c_int, dp, vp]
     L.mfs_post.argtypes = [vp, C.c_int, vp, dp]
@@ -174,6 +176,10 @@ def _dp(a):
 
 def _ip(a):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _i64p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
 
 
 def _check(code, ctx):
@@ -256,6 +262,27 @@ def mfs_get_clusters(ctx):
     return dict(slot_body=slot_body, cl_start=cl_start, centre=centre, radius=radius)
 
 
+def mfs_get_fmm(ctx, problem, precision):
+    """The hierarchical kernel sum's cells, waves and per-wave lists (mfs_get_fmm): dict of
+    cell_lo, cell_hi, cell_c (ncell x 2), cell_r, wave_start (nwave + 1), wave_c (nwave x 2),
+    m2l_off, m2l, near_off, near, tier_d2 (P x 3, slot order)."""
+    sz = np.zeros(4, dtype=np.int64)
+    nul = [None] * 11
+    _check(lib().mfs_get_fmm(ctx, PROBLEMS[problem], PRECISIONS[precision], _i64p(sz), *nul), ctx)
+    ncell, nwave, nm, nn = (int(v) for v in sz)
+    P = mfs_get_sizes(ctx)[0]
+    d = dict(cell_lo=np.zeros(ncell, np.int32), cell_hi=np.zeros(ncell, np.int32), cell_c=np.zeros((ncell, 2)),
+             cell_r=np.zeros(ncell), wave_start=np.zeros(nwave + 1, np.int32), wave_c=np.zeros((nwave, 2)),
+             m2l_off=np.zeros(nwave + 1, np.int32), m2l=np.zeros(max(nm, 1), np.int32),
+             near_off=np.zeros(nwave + 1, np.int32), near=np.zeros(max(nn, 1), np.int32), tier_d2=np.zeros((P, 3)))
+    _check(lib().mfs_get_fmm(ctx, PROBLEMS[problem], PRECISIONS[precision], _i64p(sz), _ip(d["cell_lo"]),
+                             _ip(d["cell_hi"]), _dp(d["cell_c"]), _dp(d["cell_r"]), _ip(d["wave_start"]),
+                             _dp(d["wave_c"]), _ip(d["m2l_off"]), _ip(d["m2l"]), _ip(d["near_off"]), _ip(d["near"]),
+                             _dp(d["tier_d2"])), ctx)
+    d["m2l"], d["near"] = d["m2l"][:nm], d["near"][:nn]
+    return d
+
+
 def _pair_sizes(ctx, n_src):
     pr = mfs_get_pairs(ctx)
     n = 2 * (n_src[pr[:, 0]] + n_src[pr[:, 1]]) if len(pr) else np.zeros(0, dtype=np.int64)
@@ -304,6 +331,15 @@ def mfs_kernel_sum_work(ctx, reset=False):
 def mfs_kernel_sum(ctx, precision, sigma, u, skip=1):
     """skip: 0 all sources, 1 skip the target's own disk, 2 also skip its contact partners."""
     _check(lib().mfs_kernel_sum(ctx, PRECISIONS[precision], _dev(sigma), _dev(u), int(skip)), ctx)
+
+
+def mfs_time_kernel_sum(ctx, precision, sigma, u, skip=2, reps=5):
+    """(ms to pack and form the records, average ms of one sum launch), HIP events on the
+    context's stream."""
+    a, b = C.c_double(), C.c_double()
+    _check(lib().mfs_time_kernel_sum(ctx, PRECISIONS[precision], _dev(sigma), _dev(u), int(skip), int(reps),
+                                     C.byref(a), C.byref(b)), ctx)
+    return a.value, b.value
 
 
 def mfs_rhs(ctx, problem, given, b):
@@ -368,8 +404,8 @@ def mfs_gmres_solve(ctx, problem, precision, rhs, tol, max_iter=500, x0=None, hi
     d = dict(iters=info.iters_total, outer=info.outer_steps, rel_resid=info.rel_resid,
              hist=hist[:info.hist_len].copy(), ms_rhs=info.ms_rhs, ms_iterate=info.ms_iterate, ms_post=info.ms_post,
              n_pairs=info.n_pairs, matvecs_fp64=info.matvecs_fp64, matvecs_mixed=info.matvecs_mixed,
-             dense_pairs=info.dense_pairs, direct_pairs=info.direct_pairs, disk_expansions=info.disk_expansions,
-             cluster_expansions=info.cluster_expansions, local_translations=info.local_translations,
+             dense_pairs=info.dense_pairs, direct_pairs=info.direct_pairs, ring_expansions=info.ring_expansions,
+             expansion_terms=info.expansion_terms, local_translations=info.local_translations,
              local_evaluations=info.local_evaluations, status=STATUS_NAMES[code])
     return out, d
 

@@ -12,6 +12,8 @@ import numpy as np
 import pytest
 import torch
 
+import bench
+
 from workloads import config_geometry, jittered_grid
 from tests.gpu_helpers import coarse_points, oracle_sum_excluding_self, say
 
@@ -169,11 +171,10 @@ def test_kernel_sum_projected_strengths():
     assert e32 <= 3e-6   # measured 2.3e-7 of max |u|
 
 
-def test_kernel_sum_work_counters():
-    # the kernels' own work counters (mfs_kernel_sum_work) against the host count of their
-    # rules (bench.ksum_work_clusters: per-wave paths, the workgroups' local expansions), per
-    # launch, at P = 600 (area fraction 0.5), skip mode 2
-    import bench
+def test_fmm_lists_partition_the_disks():
+    # every wave's M2L cells and near disks cover each disk once; every M2L cell is separated
+    # from the wave (|C - B| >= sep (R + r)) and holds no node's own disk or contact partner;
+    # cells are quadtree ranges of the slot order with their centres and radii
     from paper_2606_11273_amd import native as nv
     g0 = config_geometry(2, P=600)
     c, a = g0["centers"], g0["radii"]
@@ -184,6 +185,107 @@ def test_kernel_sum_work_counters():
     ctx = nv.mfs_setup(c, a, ns, nc, rs, prm)
     try:
         cl = nv.mfs_get_clusters(ctx)
+        pr = nv.mfs_get_pairs(ctx)
+        f = {prec: nv.mfs_get_fmm(ctx, "mobility", prec) for prec in ("fp64", "mixed")}
+    finally:
+        nv.mfs_destroy(ctx)
+    P = c.shape[0]
+    sb = cl["slot_body"]
+    slot_of = np.empty(P, dtype=int)
+    slot_of[sb] = np.arange(P)
+    partners = [set() for _ in range(P)]
+    for i, k in pr:
+        partners[i].add(int(k))
+        partners[k].add(int(i))
+    tp = bench.visiting_order(nc, sb)
+    body_of_t = np.repeat(np.arange(P), nc)
+    for prec, sep in (("fp64", 4.0), ("mixed", 3.0)):
+        d = f[prec]
+        lo, hi = d["cell_lo"], d["cell_hi"]
+        assert np.array_equal(lo[:P], np.arange(P)) and np.array_equal(hi[:P], np.arange(1, P + 1))
+        for q in range(len(lo)):
+            mem = sb[lo[q]:hi[q]]
+            C = c[mem].mean(0)
+            assert np.allclose(d["cell_c"][q], C, atol=1e-12)
+            assert d["cell_r"][q] >= (np.linalg.norm(c[mem] - C, axis=1) + a[mem]).max()
+        ws = d["wave_start"]
+        assert ws[0] == 0 and ws[-1] == X.shape[0] and np.all(np.diff(ws) >= 1) and np.all(np.diff(ws) <= 128)
+        for w in range(len(ws) - 1):
+            t = tp[ws[w]:ws[w + 1]]
+            B = d["wave_c"][w]
+            r = np.linalg.norm(X[t] - B, axis=1).max()
+            excl = set()
+            for b in set(body_of_t[t]):
+                excl.add(slot_of[b])
+                excl.update(slot_of[k] for k in partners[b])
+            cover = np.zeros(P, dtype=int)
+            for q in d["m2l"][d["m2l_off"][w]:d["m2l_off"][w + 1]]:
+                assert np.linalg.norm(d["cell_c"][q] - B) >= sep * (d["cell_r"][q] + r) * (1 - 1e-12)
+                assert not any(lo[q] <= e < hi[q] for e in excl)
+                cover[lo[q]:hi[q]] += 1
+            near = d["near"][d["near_off"][w]:d["near_off"][w + 1]]
+            assert np.all(np.diff(near) > 0)
+            cover[near] += 1
+            assert np.all(cover == 1), (prec, w)
+
+
+def _fmm_work(c, X, ns, nc, d, tp, partners, slot_of, mixed):
+    """Host count of the kernel's rules per wave: the M2L list length (one translation, one
+    wave), the local evaluations (64 lanes x 2 node slots per wave with translations) and, per
+    near disk, the node slots of the 64 x 2 that take the lowest tier order whose squared
+    distance every node not skipped (own disk and partners, skip mode 2) exceeds, else the
+    direct sum over the disk's sources."""
+    P = c.shape[0]
+    sb = np.argsort(slot_of)
+    body_of_t = np.repeat(np.arange(P), nc)
+    orders = (14, 24, 44) if mixed else (27, 40, 56)
+    thr = d["tier_d2"].copy()
+    if mixed:   # the FP32 records hold the distances rounded up to FP32
+        t32 = thr.astype(np.float32)
+        t32 = np.where(t32.astype(np.float64) < thr, np.nextafter(t32, np.float32(np.inf)), t32)
+        thr = t32.astype(np.float64)
+    direct = exps = terms = m2l = l2p = 0
+    ws = d["wave_start"]
+    for w in range(len(ws) - 1):
+        t = tp[ws[w]:ws[w + 1]]
+        nm = d["m2l_off"][w + 1] - d["m2l_off"][w]
+        m2l += nm
+        l2p += 128 if nm > 0 else 0
+        tb = body_of_t[t]
+        for s in d["near"][d["near_off"][w]:d["near_off"][w + 1]]:
+            b = sb[s]
+            skip = np.array([b == bb or b in partners[bb] for bb in tb])
+            if skip.all():
+                continue
+            r2 = ((X[t] - c[b]) ** 2).sum(1)
+            p = 0
+            for tier in range(3):
+                if np.all(skip | (r2 > thr[s, tier])):
+                    p = orders[tier]
+                    break
+            if p:
+                exps += 128
+                terms += 128 * p
+            else:
+                direct += 128 * ns[b]
+    return direct, exps, terms, m2l, l2p
+
+
+def test_kernel_sum_work_counters():
+    # the kernels' own work counters (mfs_kernel_sum_work) against a host count of their rules
+    # on the lists mfs_get_fmm exports, per launch, at P = 600 (area fraction 0.5), skip mode 2
+    from paper_2606_11273_amd import native as nv
+    g0 = config_geometry(2, P=600)
+    c, a = g0["centers"], g0["radii"]
+    ns, nc, rs = g0["n_src"], g0["n_col"], g0["r_src"]
+    prm = nv.mfs_default_params()
+    prm.delta_c = g0["delta_c"]
+    X, Y, so, co = coarse_points(c, a, ns, nc, rs)
+    ctx = nv.mfs_setup(c, a, ns, nc, rs, prm)
+    try:
+        cl = nv.mfs_get_clusters(ctx)
+        pr = nv.mfs_get_pairs(ctx)
+        fm = {prec: nv.mfs_get_fmm(ctx, "resistance", prec) for prec in ("fp64", "mixed")}
         s = torch.tensor(np.random.default_rng(5).standard_normal(2 * Y.shape[0]), device="cuda")
         u = torch.zeros(2 * X.shape[0], dtype=torch.float64, device="cuda")
         nv.mfs_kernel_sum_work(ctx, reset=True)
@@ -193,15 +295,17 @@ def test_kernel_sum_work_counters():
             counts[prec] = nv.mfs_kernel_sum_work(ctx, reset=True)
     finally:
         nv.mfs_destroy(ctx)
+    P = c.shape[0]
+    slot_of = np.empty(P, dtype=int)
+    slot_of[cl["slot_body"]] = np.arange(P)
+    partners = [set() for _ in range(P)]
+    for i, k in pr:
+        partners[i].add(int(k))
+        partners[k].add(int(i))
     tp = bench.visiting_order(nc, cl["slot_body"])
-    ncl = cl["radius"].size
     say(f"work per launch: mixed {counts['mixed']}, fp64 {counts['fp64']}")
-    assert counts["mixed"][3] > counts["fp64"][3] > 0   # the FP64 sum translates only the farther clusters
     for prec in ("mixed", "fp64"):
-        ref = bench.ksum_work_clusters(c, a, ns, rs, X, cl, tperm=tp, local=True,
-                                       splits=bench.ksum_splits(X.shape[0], len(c), ncl),
-                                       sep=bench.LOC32_SEP if prec == "mixed" else bench.LOC64_SEP)
+        ref = _fmm_work(c, X, ns, nc, fm[prec], tp, partners, slot_of, prec == "mixed")
         say(f"  host count {prec}: {ref}")
-        assert min(ref) > 0
-        for k in range(5):
-            assert abs(counts[prec][k] - ref[k]) <= 1e-4 * ref[k], (prec, k)
+        assert ref[1] > 0 and ref[3] > 0
+        assert tuple(counts[prec]) == ref, prec

@@ -1,15 +1,14 @@
 """mfs_apply_noalloc (the matvec with no device allocation) against mfs_apply.
 
-The no-allocation entry point keeps the kernel sum's split partials in the library's static
-scratch array instead of the context's own buffer; everything else is the same launch
-sequence, so its output must equal mfs_apply's bit for bit.  Two calls in a row on the same
+The no-allocation entry point keeps the kernel sum's expansion records (the disks' ring
+expansions and the cells' moments) in the library's static scratch array instead of the
+context's own buffers; everything else is the same launch sequence, so its output must equal
+mfs_apply's bit for bit.  Two calls in a row on the same
 device, the second on a smaller context (the array keeps the first call's contents), in both
 precisions and both problems.  The pair matrices are seeded random ones of the right shapes
-(the comparison is between two entry points on one operator).  A split count whose partials
-exceed the array is refused with MFS_ERR_ARG.
+(the comparison is between two entry points on one operator).
+A context whose records exceed the array is refused with MFS_ERR_ARG.
 """
-
-import os
 
 import numpy as np
 import pytest
@@ -60,24 +59,24 @@ def test_noalloc_equals_apply_two_calls():
             nv.mfs_destroy(ctx)
 
 
-def test_noalloc_refuses_partials_beyond_scratch():
+def test_noalloc_refuses_records_beyond_scratch():
+    # 142 x 142 disks on a square lattice of spacing 3 (no close pairs, so no precompute): the
+    # kernel sum's records need 16 (ncell (81 + 108) + 174 P) + 1120 P bytes, about 170 MB,
+    # above the 128 MiB array
     from paper_2606_11273_amd import native as nv
-    g = config_geometry(3, P=2000)
-    ctx = _ctx(nv, g["centers"], g["radii"], g["n_src"], g["n_col"], g["r_src"], g["delta_c"], seed=3)
-    old = os.environ.get("MFS_KSUM_SPLITS")
+    n = 142
+    g = np.stack(np.meshgrid(np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 2) * 3.0
+    P = g.shape[0]
+    prm = nv.mfs_default_params()
+    ctx = nv.mfs_setup(g.astype(np.float64), np.ones(P), np.full(P, 36), np.full(P, 72), np.full(P, 0.7), prm)
     try:
+        assert nv.mfs_get_pairs(ctx).shape[0] == 0
         _, _, Nt, _ = nv.mfs_get_sizes(ctx)
         mu = torch.ones(2 * Nt, dtype=torch.float64, device="cuda")
         u = torch.zeros_like(mu)
-        # 64 splits x 2 N_t doubles = 147 MB of partials, above the 128 MiB array
-        os.environ["MFS_KSUM_SPLITS"] = "64"
         with pytest.raises(nv.MFSError) as e:
             nv.mfs_apply_noalloc(ctx, "mobility", "mixed", mu, u)
         assert e.value.code == nv.MFS_ERR_ARG
         say(f"refused: {e.value}")
     finally:
-        if old is None:
-            os.environ.pop("MFS_KSUM_SPLITS", None)
-        else:
-            os.environ["MFS_KSUM_SPLITS"] = old
         nv.mfs_destroy(ctx)
