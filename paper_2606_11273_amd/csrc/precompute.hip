@@ -180,13 +180,16 @@ __global__ __launch_bounds__(64) void k_fill(const PairGeo* __restrict__ geo, Ba
 }
 
 // sinv_j = 1/s_j if s_j > eps s_0 else 0, then scale row j of T (column-major, ld, ncol columns).
+// s_0 is the largest singular value of the group of `group` consecutive matrices that p belongs
+// to (the two symmetry blocks of one pair share the threshold of the whole matrix).
 __global__ __launch_bounds__(256) void k_trunc_scale(int nsv, const double* __restrict__ S, int64_t sS, double eps,
-                                                     double* T, int64_t ld, int ncol, int64_t sT) {
+                                                     double* T, int64_t ld, int ncol, int64_t sT, int group) {
   const int p = blockIdx.y;
   // sigma_1 as the largest entry (no reliance on the order the SVD returns)
   __shared__ double red[256];
   double m = 0.0;
-  for (int j = threadIdx.x; j < nsv; j += 256) m = fmax(m, S[p * sS + j]);
+  const int g0 = (p / group) * group;
+  for (int j = threadIdx.x; j < nsv * group; j += 256) m = fmax(m, S[(g0 + j / nsv) * sS + j % nsv]);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -201,6 +204,97 @@ __global__ __launch_bounds__(256) void k_trunc_scale(int nsv, const double* __re
   const double sj = S[p * sS + j];
   const double f = (sj > eps * s0) ? 1.0 / sj : 0.0;
   T[p * sT + (int64_t)col * ld + j] *= f;
+}
+
+// Pairs of equal disks.  The point reflection through the pair's midpoint maps each of the
+// pair's point sets onto itself, disk i's points onto disk k's (a ring of an even count from
+// angle 0: point j to point j + n/2; the ellipse sources and Moebius nodes, built in the pair's
+// frame: point j to point j; the peanut: point p to point p + M_p/2), and flips every vector.
+// The Stokeslet is even in x - y, so F, C, D and X commute with it, and in the orthonormal
+// bases Q_e = [I; e Sigma] / sqrt 2 (e = +1, -1; Sigma the map from disk i's points to disk
+// k's with the sign flip) each splits into two blocks of half the size:
+//   F_e = F_ii + e F_ik Sigma_s,  X_e = (X_i + e Sigma_n^T X_k) / sqrt 2,
+// F^+ X = sum_e Q_e F_e^+ X_e, the singular values of F being those of F_+ and F_- (one
+// truncation threshold for both).  The peanut's two halves (points p < M_p/2 and their images)
+// play the parts of disk i's and disk k's nodes for C and D G.
+__device__ __forceinline__ int sym_map(int j, int nring) { return j < nring ? (j + nring / 2) % nring : j; }
+
+// F_e (mh x nh) and X_e (mh x nx) of every pair of a batch: matrix 2q + (e < 0) of Fs, Xs.
+// One block per (column, matrix); column c < nh of F_e, else column c - nh of X_e.
+__global__ __launch_bounds__(256) void k_sym_split_F(const double* __restrict__ F, int64_t ldF, int64_t sF,
+                                                     const double* __restrict__ X, int64_t sX, int mh, int nh, int nx,
+                                                     int nring_src, int nring_node, double* __restrict__ Fs,
+                                                     double* __restrict__ Xs) {
+  const int col = blockIdx.x, mat = blockIdx.y, q = mat >> 1;
+  const double e = (mat & 1) ? 1.0 : -1.0;   // + block: F_ii - F_ik[mapped]; the minus sign is Sigma's flip
+  if (col < nh) {
+    const int colk = nh + 2 * sym_map(col >> 1, nring_src) + (col & 1);
+    const double* a = F + q * sF + (int64_t)col * ldF;
+    const double* b = F + q * sF + (int64_t)colk * ldF;
+    double* o = Fs + (int64_t)mat * mh * nh + (int64_t)col * mh;
+    for (int r = threadIdx.x; r < mh; r += 256) o[r] = a[r] + e * b[r];
+  } else if (col < nh + nx) {
+    const int xc = col - nh;
+    const double* a = X + q * sX + (int64_t)xc * ldF;
+    double* o = Xs + (int64_t)mat * mh * nx + (int64_t)xc * mh;
+    for (int r = threadIdx.x; r < mh; r += 256) {
+      const int rk = mh + 2 * sym_map(r >> 1, nring_node) + (r & 1);
+      o[r] = (a[r] + e * a[rk]) * 0.70710678118654752440;
+    }
+  }
+}
+
+// G (n x nx per pair, stride sG) from G_e (nh x nx, matrices 2q, 2q + 1):
+// G_i = (G_+ + G_-) / sqrt 2, G_k = Sigma_s (G_+ - G_-) / sqrt 2.  One block per (column, pair).
+__global__ __launch_bounds__(256) void k_sym_join_G(const double* __restrict__ Gs, int nh, int nx, int nring_src,
+                                                    double* __restrict__ G, int64_t sG) {
+  const int col = blockIdx.x, q = blockIdx.y;
+  const double* gp = Gs + (int64_t)(2 * q) * nh * nx + (int64_t)col * nh;
+  const double* gm = gp + (int64_t)nh * nx;
+  double* o = G + q * sG + (int64_t)col * (2 * nh);
+  for (int j = threadIdx.x; j < nh; j += 256) {
+    const double p = gp[j], m = gm[j];
+    o[j] = (p + m) * 0.70710678118654752440;
+    o[nh + 2 * sym_map(j >> 1, nring_src) + (j & 1)] = -(p - m) * 0.70710678118654752440;
+  }
+}
+
+// C_e (zh x nxh) and (D G)_e (zh x nx): rows of the peanut's first half (zh = M_p rows) and of
+// its images (rows zh + r); columns of disk i's coarse sources and of disk k's (ring of ncc).
+__global__ __launch_bounds__(256) void k_sym_split_C(const double* __restrict__ Cm, int64_t sC,
+                                                     const double* __restrict__ DG, int64_t sDG, int zh, int nxh,
+                                                     int nx, int ncc, double* __restrict__ Cs,
+                                                     double* __restrict__ DGs) {
+  const int col = blockIdx.x, mat = blockIdx.y, q = mat >> 1;
+  const double e = (mat & 1) ? 1.0 : -1.0;
+  const int64_t ld = 2 * (int64_t)zh;
+  if (col < nxh) {
+    const int colk = nxh + 2 * sym_map(col >> 1, ncc) + (col & 1);
+    const double* a = Cm + q * sC + (int64_t)col * ld;
+    const double* b = Cm + q * sC + (int64_t)colk * ld;
+    double* o = Cs + (int64_t)mat * zh * nxh + (int64_t)col * zh;
+    for (int r = threadIdx.x; r < zh; r += 256) o[r] = a[r] + e * b[r];
+  } else if (col < nxh + nx) {
+    const int xc = col - nxh;
+    const double* a = DG + q * sDG + (int64_t)xc * ld;
+    double* o = DGs + (int64_t)mat * zh * nx + (int64_t)xc * zh;
+    for (int r = threadIdx.x; r < zh; r += 256) o[r] = (a[r] + e * a[zh + r]) * 0.70710678118654752440;
+  }
+}
+
+// A (nx x nx, column-major, into A + aoff[q]) from A_e (nxh x nx): rows of disk i's coarse
+// sources (A_+ + A_-) / sqrt 2, of disk k's Sigma_c (A_+ - A_-) / sqrt 2.
+__global__ __launch_bounds__(256) void k_sym_join_A(const double* __restrict__ As, int nxh, int nx, int ncc,
+                                                    double* __restrict__ A, const int64_t* __restrict__ aoff) {
+  const int col = blockIdx.x, q = blockIdx.y;
+  const double* ap = As + (int64_t)(2 * q) * nxh * nx + (int64_t)col * nxh;
+  const double* am = ap + (int64_t)nxh * nx;
+  double* o = A + aoff[q] + (int64_t)col * nx;
+  for (int j = threadIdx.x; j < nxh; j += 256) {
+    const double p = ap[j], m = am[j];
+    o[j] = (p + m) * 0.70710678118654752440;
+    o[nxh + 2 * sym_map(j >> 1, ncc) + (j & 1)] = -(p - m) * 0.70710678118654752440;
+  }
 }
 
 // Keep G of each pair in compact form for flow evaluation: the rows of the padded
@@ -555,8 +649,35 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     order[p] = p;
   }
   auto type_of = [&](int p) { return c->cls[c->pairs[2 * p]] * kMaxClasses + c->cls[c->pairs[2 * p + 1]]; };
+  // pairs of equal disks whose point sets the reflection through the midpoint maps onto each
+  // other with the index maps of k_sym_split_F (checked on the constructed points) take the
+  // split form: two SVDs of half the size
+  std::vector<char> symp(C, 0);
+  for (int p = 0; p < C; ++p) {
+    const int i = c->pairs[2 * p], k = c->pairs[2 * p + 1];
+    if (c->cls[i] != c->cls[k] || std::getenv("MFS_PRECOMPUTE_NOSYM")) continue;
+    const double a = c->radii[i];
+    const int nring = fine_count(a, fp), nnode = (int)std::ceil(fp.a_f * nring - 1e-12);
+    if (nring % 2 || nnode % 2 || mp % 2 || ct.nc[c->cls[i]] % 2) continue;
+    const Pt ci{c->centers[2 * i], c->centers[2 * i + 1]}, ck{c->centers[2 * k], c->centers[2 * k + 1]};
+    std::vector<Pt> yi, yk, xi, xk, z;
+    pair_fine_sources(ci, ck, fp, yi, yk, a, a);
+    pair_fine_nodes(ci, ck, fp, xi, xk, a, a);
+    peanut(ci, ck, mp, z, a, a);
+    if (yi.size() != yk.size() || xi.size() != xk.size() || (int)xi.size() < nnode) continue;
+    const double sx = ci.x + ck.x, sy = ci.y + ck.y, tol = 1e-11 * (1.0 + std::fabs(sx) + std::fabs(sy));
+    auto mirror = [&](Pt u, Pt v) { return std::fabs(u.x + v.x - sx) <= tol && std::fabs(u.y + v.y - sy) <= tol; };
+    bool ok = true;
+    for (size_t j = 0; ok && j < yi.size(); ++j)
+      ok = mirror(yi[j], yk[(int)j < nring ? ((int)j + nring / 2) % nring : (int)j]);
+    for (size_t j = 0; ok && j < xi.size(); ++j)
+      ok = mirror(xi[j], xk[(int)j < nnode ? ((int)j + nnode / 2) % nnode : (int)j]);
+    for (int j = 0; ok && j < mp / 2; ++j) ok = mirror(z[j], z[j + mp / 2]);
+    symp[p] = ok ? 1 : 0;
+  }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     if (type_of(a) != type_of(b)) return type_of(a) < type_of(b);
+    if (symp[a] != symp[b]) return symp[a] > symp[b];
     return std::max(nfe0[a], nfe1[a]) < std::max(nfe0[b], nfe1[b]);
   });
   double rmax = 0.0;
@@ -617,7 +738,10 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
   for (int b0 = 0; b0 < C;) {
     auto t0 = std::chrono::steady_clock::now();
     int nb = 0;
-    while (nb < batch && b0 + nb < C && type_of(order[b0 + nb]) == type_of(order[b0])) ++nb;
+    while (nb < batch && b0 + nb < C && type_of(order[b0 + nb]) == type_of(order[b0]) &&
+           symp[order[b0 + nb]] == symp[order[b0]])
+      ++nb;
+    const bool sym = symp[order[b0]] != 0;
     const int ci0 = c->cls[c->pairs[2 * order[b0]]], ck0 = c->cls[c->pairs[2 * order[b0] + 1]];
     BatchDims d;
     d.nfpad[0] = d.nfpad[1] = 0;
@@ -762,35 +886,79 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       MFS_HIP(hipGetLastError());
     }
     tick(1, t0);
-    MFS_HIP(dSF.alloc(c, sizeof(double) * mn * nb));
-    MFS_HIP(dU.alloc(c, sizeof(double) * m * mn * nb));
-    MFS_HIP(dVT.alloc(c, sizeof(double) * mn * n * nb));
-    MFS_HIP(dE.alloc(c, sizeof(double) * mn * nb));
-    MFS_HIP(dinfo.alloc(c, sizeof(int) * nb));
-    MFS_HIP(dinfoC.alloc(c, sizeof(int) * nb));
-    MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m, (int)n,
-                                            (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p, (int)m,
-                                            m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
-                                            rocblas_outofplace, (int*)dinfo.p, nb));
-    tick(2, t0);
-    // T1 = U^T X  (mn x nx)
-    MFS_HIP(dT1.alloc(c, sizeof(double) * mn * nx * nb));
-    MFS_HIP(dG.alloc(c, sizeof(double) * n * nx * nb));
     const double one = 1.0, zero = 0.0, mone = -1.0;
-    MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mn,
-                                         (int)nx, (int)m, &one, (const double*)dU.p, (int)m, m * mn,
-                                         (const double*)dX.p, (int)m, d.sX, &zero, (double*)dT1.p, (int)mn, mn * nx,
-                                         nb));
-    {
-      dim3 grid((unsigned)((mn * nx + 255) / 256), nb);
-      hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mn, (const double*)dSF.p, mn,
-                         c->prm.eps_trunc_fine, (double*)dT1.p, mn, (int)nx, mn * nx);
+    const int nbs = sym ? 2 * nb : nb;   // matrices per SVD batch
+    // index maps of the split form: the rings of disk i's fine sources and fine nodes
+    const int sym_nsrc = fine_count(ct.radius[ci0], fp);
+    const int sym_nnode = (int)std::ceil(fp.a_f * sym_nsrc - 1e-12);
+    MFS_HIP(dinfo.alloc(c, sizeof(int) * nbs));
+    MFS_HIP(dinfoC.alloc(c, sizeof(int) * nbs));
+    MFS_HIP(dG.alloc(c, sizeof(double) * n * nx * nb));
+    if (sym) {
+      // F_e (mh x nh), X_e (mh x nx), e = +, -: half the rows and columns
+      const int64_t mh = m / 2, nh = n / 2, mnh = std::min(mh, nh);
+      DevMem dFs, dXs, dGs;
+      MFS_HIP(dFs.alloc(c, sizeof(double) * mh * nh * nbs));
+      MFS_HIP(dXs.alloc(c, sizeof(double) * mh * nx * nbs));
+      hipLaunchKernelGGL(k_sym_split_F, dim3((unsigned)(nh + nx), nbs), dim3(256), 0, c->stream, (const double*)dF.p,
+                         m, d.sF, (const double*)dX.p, d.sX, (int)mh, (int)nh, (int)nx, sym_nsrc, sym_nnode,
+                         (double*)dFs.p, (double*)dXs.p);
+      MFS_HIP(hipGetLastError());
+      MFS_HIP(dSF.alloc(c, sizeof(double) * mnh * nbs));
+      MFS_HIP(dU.alloc(c, sizeof(double) * mh * mnh * nbs));
+      MFS_HIP(dVT.alloc(c, sizeof(double) * mnh * nh * nbs));
+      MFS_HIP(dE.alloc(c, sizeof(double) * mnh * nbs));
+      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mh,
+                                              (int)nh, (double*)dFs.p, (int)mh, mh * nh, (double*)dSF.p, mnh,
+                                              (double*)dU.p, (int)mh, mh * mnh, (double*)dVT.p, (int)mnh, mnh * nh,
+                                              (double*)dE.p, mnh, rocblas_outofplace, (int*)dinfo.p, nbs));
+      tick(2, t0);
+      MFS_HIP(dT1.alloc(c, sizeof(double) * mnh * nx * nbs));
+      MFS_HIP(dGs.alloc(c, sizeof(double) * nh * nx * nbs));
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnh,
+                                           (int)nx, (int)mh, &one, (const double*)dU.p, (int)mh, mh * mnh,
+                                           (const double*)dXs.p, (int)mh, mh * nx, &zero, (double*)dT1.p, (int)mnh,
+                                           mnh * nx, nbs));
+      {
+        dim3 grid((unsigned)((mnh * nx + 255) / 256), nbs);
+        hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mnh, (const double*)dSF.p, mnh,
+                           c->prm.eps_trunc_fine, (double*)dT1.p, mnh, (int)nx, mnh * nx, 2);
+      }
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)nh,
+                                           (int)nx, (int)mnh, &one, (const double*)dVT.p, (int)mnh, mnh * nh,
+                                           (const double*)dT1.p, (int)mnh, mnh * nx, &zero, (double*)dGs.p, (int)nh,
+                                           nh * nx, nbs));
+      hipLaunchKernelGGL(k_sym_join_G, dim3((unsigned)nx, nb), dim3(256), 0, c->stream, (const double*)dGs.p, (int)nh,
+                         (int)nx, sym_nsrc, (double*)dG.p, n * nx);
+      MFS_HIP(hipGetLastError());
+      MFS_HIP(hipStreamSynchronize(c->stream));   // the split buffers are released at the end of this scope
+    } else {
+      MFS_HIP(dSF.alloc(c, sizeof(double) * mn * nb));
+      MFS_HIP(dU.alloc(c, sizeof(double) * m * mn * nb));
+      MFS_HIP(dVT.alloc(c, sizeof(double) * mn * n * nb));
+      MFS_HIP(dE.alloc(c, sizeof(double) * mn * nb));
+      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m, (int)n,
+                                              (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p, (int)m,
+                                              m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
+                                              rocblas_outofplace, (int*)dinfo.p, nb));
+      tick(2, t0);
+      // T1 = U^T X  (mn x nx)
+      MFS_HIP(dT1.alloc(c, sizeof(double) * mn * nx * nb));
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mn,
+                                           (int)nx, (int)m, &one, (const double*)dU.p, (int)m, m * mn,
+                                           (const double*)dX.p, (int)m, d.sX, &zero, (double*)dT1.p, (int)mn,
+                                           mn * nx, nb));
+      {
+        dim3 grid((unsigned)((mn * nx + 255) / 256), nb);
+        hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mn, (const double*)dSF.p, mn,
+                           c->prm.eps_trunc_fine, (double*)dT1.p, mn, (int)nx, mn * nx, 1);
+      }
+      // G = V T1 = (V^T)^T T1   (n x nx)
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)n,
+                                           (int)nx, (int)mn, &one, (const double*)dVT.p, (int)mn, mn * n,
+                                           (const double*)dT1.p, (int)mn, mn * nx, &zero, (double*)dG.p, (int)n,
+                                           n * nx, nb));
     }
-    // G = V T1 = (V^T)^T T1   (n x nx)
-    MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)n,
-                                         (int)nx, (int)mn, &one, (const double*)dVT.p, (int)mn, mn * n,
-                                         (const double*)dT1.p, (int)mn, mn * nx, &zero, (double*)dG.p, (int)n, n * nx,
-                                         nb));
     if (keep) {
       std::vector<int32_t> nfq(2 * nb);
       std::vector<int64_t> gq(nb);
@@ -816,43 +984,87 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
                                          (int)n, n * nx, &zero, (double*)dDG.p, (int)mpp, mpp * nx, nb));
     tick(3, t0);
     // SVD of C (2mp x nx), then A = -V_C Sigma_C^+ U_C^T (D G)
-    const int64_t mnc = std::min(mpp, nx);
-    MFS_HIP(dSC.alloc(c, sizeof(double) * mnc * nb));
-    MFS_HIP(dUC.alloc(c, sizeof(double) * mpp * mnc * nb));
-    MFS_HIP(dVTC.alloc(c, sizeof(double) * mnc * nx * nb));
-    MFS_HIP(dEC.alloc(c, sizeof(double) * mnc * nb));
-    MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
-                                            (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
-                                            (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
-                                            mnc * nx, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nb));
-    tick(4, t0);
-    MFS_HIP(dT2.alloc(c, sizeof(double) * mnc * nx * nb));
-    MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnc,
-                                         (int)nx, (int)mpp, &one, (const double*)dUC.p, (int)mpp, mpp * mnc,
-                                         (const double*)dDG.p, (int)mpp, mpp * nx, &zero, (double*)dT2.p, (int)mnc,
-                                         mnc * nx, nb));
-    {
-      dim3 grid((unsigned)((mnc * nx + 255) / 256), nb);
-      hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mnc, (const double*)dSC.p, mnc,
-                         c->prm.eps_trunc, (double*)dT2.p, mnc, (int)nx, mnc * nx);
-    }
-    // A into place; pairs of a batch are not contiguous in the pair order, so one GEMM per pair
-    for (int q = 0; q < nb; ++q) {
-      const int p = order[b0 + q];
-      MFS_RB(rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)nx, (int)nx, (int)mnc,
-                           &mone, (const double*)dVTC.p + q * mnc * nx, (int)mnc,
-                           (const double*)dT2.p + q * mnc * nx, (int)mnc, &zero, ps.A + c->aoff[p], (int)nx));
+    if (sym) {
+      const int64_t zh = mp, nxh = nx / 2, mnc = std::min(zh, nxh);
+      const int ncc = ct.nc[ci0];
+      std::vector<int64_t> aq(nb);
+      for (int q = 0; q < nb; ++q) aq[q] = c->aoff[order[b0 + q]];
+      DevMem dCs, dDGs, dAs, daq;
+      MFS_HIP(dCs.alloc(c, sizeof(double) * zh * nxh * nbs));
+      MFS_HIP(dDGs.alloc(c, sizeof(double) * zh * nx * nbs));
+      MFS_HIP(daq.alloc(c, sizeof(int64_t) * nb));
+      MFS_HIP(hipMemcpyAsync(daq.p, aq.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_sym_split_C, dim3((unsigned)(nxh + nx), nbs), dim3(256), 0, c->stream, (const double*)dC.p,
+                         d.sC, (const double*)dDG.p, mpp * nx, (int)zh, (int)nxh, (int)nx, ncc, (double*)dCs.p,
+                         (double*)dDGs.p);
+      MFS_HIP(hipGetLastError());
+      MFS_HIP(dSC.alloc(c, sizeof(double) * mnc * nbs));
+      MFS_HIP(dUC.alloc(c, sizeof(double) * zh * mnc * nbs));
+      MFS_HIP(dVTC.alloc(c, sizeof(double) * mnc * nxh * nbs));
+      MFS_HIP(dEC.alloc(c, sizeof(double) * mnc * nbs));
+      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)zh,
+                                              (int)nxh, (double*)dCs.p, (int)zh, zh * nxh, (double*)dSC.p, mnc,
+                                              (double*)dUC.p, (int)zh, zh * mnc, (double*)dVTC.p, (int)mnc,
+                                              mnc * nxh, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nbs));
+      tick(4, t0);
+      MFS_HIP(dT2.alloc(c, sizeof(double) * mnc * nx * nbs));
+      MFS_HIP(dAs.alloc(c, sizeof(double) * nxh * nx * nbs));
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnc,
+                                           (int)nx, (int)zh, &one, (const double*)dUC.p, (int)zh, zh * mnc,
+                                           (const double*)dDGs.p, (int)zh, zh * nx, &zero, (double*)dT2.p, (int)mnc,
+                                           mnc * nx, nbs));
+      {
+        dim3 grid((unsigned)((mnc * nx + 255) / 256), nbs);
+        hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mnc, (const double*)dSC.p, mnc,
+                           c->prm.eps_trunc, (double*)dT2.p, mnc, (int)nx, mnc * nx, 2);
+      }
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)nxh,
+                                           (int)nx, (int)mnc, &mone, (const double*)dVTC.p, (int)mnc, mnc * nxh,
+                                           (const double*)dT2.p, (int)mnc, mnc * nx, &zero, (double*)dAs.p, (int)nxh,
+                                           nxh * nx, nbs));
+      hipLaunchKernelGGL(k_sym_join_A, dim3((unsigned)nx, nb), dim3(256), 0, c->stream, (const double*)dAs.p,
+                         (int)nxh, (int)nx, ncc, ps.A, (const int64_t*)daq.p);
+      MFS_HIP(hipGetLastError());
+      MFS_HIP(hipStreamSynchronize(c->stream));   // the split buffers are released at the end of this scope
+    } else {
+      const int64_t mnc = std::min(mpp, nx);
+      MFS_HIP(dSC.alloc(c, sizeof(double) * mnc * nb));
+      MFS_HIP(dUC.alloc(c, sizeof(double) * mpp * mnc * nb));
+      MFS_HIP(dVTC.alloc(c, sizeof(double) * mnc * nx * nb));
+      MFS_HIP(dEC.alloc(c, sizeof(double) * mnc * nb));
+      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
+                                              (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
+                                              (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
+                                              mnc * nx, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nb));
+      tick(4, t0);
+      MFS_HIP(dT2.alloc(c, sizeof(double) * mnc * nx * nb));
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnc,
+                                           (int)nx, (int)mpp, &one, (const double*)dUC.p, (int)mpp, mpp * mnc,
+                                           (const double*)dDG.p, (int)mpp, mpp * nx, &zero, (double*)dT2.p, (int)mnc,
+                                           mnc * nx, nb));
+      {
+        dim3 grid((unsigned)((mnc * nx + 255) / 256), nb);
+        hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mnc, (const double*)dSC.p, mnc,
+                           c->prm.eps_trunc, (double*)dT2.p, mnc, (int)nx, mnc * nx, 1);
+      }
+      // A into place; pairs of a batch are not contiguous in the pair order, so one GEMM per pair
+      for (int q = 0; q < nb; ++q) {
+        const int p = order[b0 + q];
+        MFS_RB(rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)nx, (int)nx,
+                             (int)mnc, &mone, (const double*)dVTC.p + q * mnc * nx, (int)mnc,
+                             (const double*)dT2.p + q * mnc * nx, (int)mnc, &zero, ps.A + c->aoff[p], (int)nx));
+      }
     }
     {
       dim3 grid((unsigned)((nx + 63) / 64), nb);
       hipLaunchKernelGGL(k_extract, grid, dim3(64), 0, c->stream, (const PairGeo*)dgeo.p, d, (const double*)dG.p,
                          n * nx, mobility ? 1.0 : -1.0, ps.E, (const int64_t*)deoff.p);
     }
-    std::vector<int> info(2 * nb);
-    MFS_HIP(hipMemcpyAsync(info.data(), dinfo.p, sizeof(int) * nb, hipMemcpyDeviceToHost, c->stream));
-    MFS_HIP(hipMemcpyAsync(info.data() + nb, dinfoC.p, sizeof(int) * nb, hipMemcpyDeviceToHost, c->stream));
+    std::vector<int> info(2 * nbs);
+    MFS_HIP(hipMemcpyAsync(info.data(), dinfo.p, sizeof(int) * nbs, hipMemcpyDeviceToHost, c->stream));
+    MFS_HIP(hipMemcpyAsync(info.data() + nbs, dinfoC.p, sizeof(int) * nbs, hipMemcpyDeviceToHost, c->stream));
     MFS_HIP(hipStreamSynchronize(c->stream));
-    for (int q = 0; q < 2 * nb; ++q)
+    for (int q = 0; q < 2 * nbs; ++q)
       if (info[q] != 0) return Status{MFS_ERR_NUMERIC, "pair SVD did not converge"};
     tick(5, t0);
     if (prof) std::fprintf(stderr, "[mfs precompute] %d / %d pairs (batch %d)\n", b0 + nb, C, batch);

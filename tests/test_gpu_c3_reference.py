@@ -8,7 +8,7 @@ torques (Fig. 1) and with N(0,1) forces (zero net force) and torques (Sec. 6.1),
 by the oracle to relative residual 1e-10; and the same with the paper's coarse discretisation
 of its P = 10^4 run (tests/golden/c3p_reference.npz: N_c = 60 on the ring-rule radius
 1 - ln(10^12)/60).  The GPU runs its own precompute (device SVDs) and GMRES, plain FP64 and
-relaxed mixed, to 5e-9 (the mixed form with N(0,1) forces to 1e-9).  Bar: max_i E^(i) <= 1e-5
+relaxed mixed, to 5e-9 (the mixed form with N(0,1) forces to 1e-9; 1e-8 and 3e-8 with 60-source rings).  Bar: max_i E^(i) <= 1e-5
 (eq. rel_vel_err with the max-speed normalisation).
 """
 
@@ -52,10 +52,18 @@ def test_dense_packing_solves_match_stored_oracle_solutions(kind):
         say(f"dense packing P={P}, {kind} discretisation: precompute {nv.mfs_precompute_pairs(ctx, 'mobility')} pairs")
         for name, given in rhs.items():
             for prec in ("fp64", "mixed"):
-                # the benchmark's tolerance, except the mixed form with N(0,1) forces: at 5e-9 its
-                # true residual carries the FP32 noise into slowly converging directions and its
-                # velocities were 1.1e-5 from the oracle's (FP64 at the same residual: 3.8e-7)
-                tol = 1e-9 if (prec, name) == ("mixed", "random") else 5e-9
+                # the benchmark's tolerance for each discretisation (5e-9 and 1e-8), except the
+                # mixed form with N(0,1) forces on 36-source rings: at 5e-9 its true residual
+                # carried the FP32 noise into slowly converging directions and its velocities
+                # were 1.1e-5 from the oracle's (FP64 at the same residual: 3.8e-7).  With 60
+                # sources on the ring-rule radius FP64 rounding alone holds the true residual
+                # near 6e-9 with unit torques and 1.6e-8 with N(0,1) forces (the one-body map
+                # amplifies the ring's top modes 4e10-fold; the oracle's own true residual is
+                # about 2e-8)
+                if kind == "paper":
+                    tol = 1e-8 if name == "torque" else 3e-8
+                else:
+                    tol = 1e-9 if (prec, name) == ("mixed", "random") else 5e-9
                 out, info = nv.mfs_gmres_solve(ctx, "mobility", prec, given, tol, 1000)
                 E = rel_rigid_error(out, ref[f"{name}_out"]).max()
                 say(f"  {name} {prec} tol {tol:g}: iters {info['iters']} (oracle {int(ref[f'{name}_iters'])} to "
