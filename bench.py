@@ -69,12 +69,27 @@ def flop_per_local_evaluation(order):
     return 24 * order + 8
 
 
-def ksum_flops(work, mixed):
-    """Algorithmic flops of the work a kernel sum counted (mfs_kernel_sum_work)."""
+def ksum_flops_split(work, mixed):
+    """Algorithmic flops of the work a kernel sum counted (mfs_kernel_sum_work), as (FP64, FP32):
+    the mixed sum evaluates the near disks' ring expansions in FP32 and everything else (direct
+    pairs, translations, local expansions) in FP64."""
     direct, n, terms, m2l, l2p = work
     q = LOC32_ORDER if mixed else LOC64_ORDER
-    return (direct * FLOP_PER_PAIR + flop_ring_expansions(n, terms) + m2l * flop_per_translation(q)
-            + l2p * flop_per_local_evaluation(q))
+    ring = flop_ring_expansions(n, terms)
+    f64 = direct * FLOP_PER_PAIR + m2l * flop_per_translation(q) + l2p * flop_per_local_evaluation(q)
+    return (f64, ring) if mixed else (f64 + ring, 0)
+
+
+def ksum_flops(work, mixed):
+    """Algorithmic flops of the work a kernel sum counted."""
+    return sum(ksum_flops_split(work, mixed))
+
+
+def alu_peak_tflops(f64, f32):
+    """The VALU peak for a flop mix: the published rates (FP64 78.6, FP32 157.3 TFLOP/s) give
+    the shortest time f64 / 78.6 + f32 / 157.3, and the peak is the total over that time."""
+    t = f64 / PEAK_FP64_TFLOPS + f32 / PEAK_FP32_TFLOPS
+    return (f64 + f32) / t if t > 0 else PEAK_FP64_TFLOPS
 
 
 def visiting_order(n_col, slot_body):
@@ -84,17 +99,18 @@ def visiting_order(n_col, slot_body):
     return np.concatenate([np.arange(col_off[b], col_off[b + 1]) for b in slot_body])
 
 
-PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (dense, with packed FP32)
-PEAK_FP64_TFLOPS = 78.6
-# The kernel sums issue FP64 and unpacked FP32 VALU instructions (packed FP32 is disabled in the
-# build): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s for either.
-PEAK_VALU_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (256 CUs, 2.4 GHz)
+PEAK_FP64_TFLOPS = 78.6     # MI355X published FP64 vector peak
 
 # HBM traffic of one k_ksum_fmm launch on this workload: rocprofv3 --pmc FETCH_SIZE, then
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for an elementwise kernel
 # that reads and writes 1 GiB.  It holds for the kernel source it was measured on, identified by
 # a hash of k_ksum_fmm's text; None until measured.
-KSUM_TRAFFIC = None
+KSUM_TRAFFIC = {
+    "src_sha256_16": "50afe3b5d473746f",
+    "mixed": {"fetch_kib": 563222.75, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
+    "fp64": {"fetch_kib": 1322984.13, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
+}
 
 
 def ksum_traffic_bytes(mixed):
@@ -182,6 +198,8 @@ def main():
                     help="skip the boundary residual of the solution (flow evaluation with the pairs' fine "
                          "sources at --flow-nodes points per disk, after the timed region)")
     ap.add_argument("--flow-nodes", type=int, default=72)
+    ap.add_argument("--precompute-only", action="store_true",
+                    help="setup and the pair precompute only, then exit (a short program for profiling it)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="set up the workload and run only the dominant kernel (5 launches), then one mixed "
                          "and one FP64 matvec with zero pair matrices (plus --copy-calibration): the short "
@@ -215,7 +233,7 @@ def main():
     if args.tol is None:
         args.tol = 1e-8 if paper else 5e-9
     cpu = None
-    if not args.no_cpu and not args.kernel_only:
+    if not args.no_cpu and not args.kernel_only and not args.precompute_only:
         # the oracle's worker processes are forked before this process touches the GPU
         cpu = cpu_baseline(c, a, ns, nc, rs, args.cpu_targets)
         log(f"cpu baseline {cpu['value']:.3e} pair-evals/s in {cpu['cores']} processes "
@@ -258,7 +276,7 @@ def main():
         print(json.dumps({"kernel_only": True, "launches": args.ksum_reps, "copy_bytes": (1 << 30) if
                           args.copy_calibration else 0}), flush=True)
         return
-    if not args.no_flow:
+    if not args.no_flow and not args.precompute_only:
         nv.mfs_keep_fine_factors(ctx, True)
     t0 = time.perf_counter()
     n_pairs = nv.mfs_precompute_pairs(ctx, "mobility")
@@ -266,6 +284,11 @@ def main():
     t_pre = time.perf_counter() - t0
     _, Ns, Nt, _ = nv.mfs_get_sizes(ctx)
     log(f"setup {t_setup:.2f}s  precompute {n_pairs} pairs {t_pre:.2f}s  Ns {Ns} Nt {Nt}")
+    if args.precompute_only:
+        nv.mfs_destroy(ctx)
+        print(json.dumps({"precompute_only": True, "P": P, "pairs": n_pairs, "precompute_s": round(t_pre, 3),
+                          "setup_s": round(t_setup, 3)}), flush=True)
+        return
 
     # the kernel sums in the matvec's launch configuration (skip own disk and partners): HIP events
     # on the context's stream around the sum kernel alone (mfs_time_kernel_sum), work as counted
@@ -330,25 +353,28 @@ def main():
     dom = "mixed" if last["matvecs_mixed"] >= last["matvecs_fp64"] else "fp64"
     kern = {}
     for prec in ("mixed", "fp64"):
-        fl = ksum_flops(kwork[prec], prec == "mixed")
+        f64, f32 = ksum_flops_split(kwork[prec], prec == "mixed")
+        fl = f64 + f32
         sec = ks[prec] * 1e-3
         d, n, terms, m2l, l2p = kwork[prec]
+        peak = alu_peak_tflops(f64, f32)
         kern[prec] = dict(ms_per_launch=round(ks[prec], 4), ms_records=round(krec[prec], 4), flops_per_launch=fl,
-                          tflops=round(fl / sec / 1e12, 2), frac_valu=round(fl / sec / 1e12 / PEAK_VALU_TFLOPS, 4),
+                          flops_fp64=f64, flops_fp32=f32, peak_tflops=round(peak, 2),
+                          tflops=round(fl / sec / 1e12, 2), frac_valu=round(fl / sec / 1e12 / peak, 4),
                           direct_pairs=d, ring_expansions=n, mean_ring_order=round(terms / max(n, 1), 2),
                           local_translations=m2l, local_evaluations=l2p,
                           dense_equivalent_pairs_per_s=round(dense_launch / sec, 1))
         log(f"kernel sum {prec}: {ks[prec]:.3f} ms per launch (+{krec[prec]:.3f} ms packing and records), "
             f"{fl / sec / 1e12:.2f} TFLOP/s; work {kwork[prec]}")
     kd = kern[dom]
-    roofline = dict(bound="alu", achieved=kd["tflops"], peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+    roofline = dict(bound="alu", achieved=kd["tflops"], peak=kd["peak_tflops"], unit="TFLOP/s",
                     frac=kd["frac_valu"], traffic=ksum_traffic_bytes(dom == "mixed"),
                     kernel=f"k_ksum_fmm<{'true' if dom == 'mixed' else 'false'}, 2> ({dom} kernel sum: per wave of "
                            "128 nodes, cell translations into an FP64 local expansion and near disks from their ring "
                            f"expansions{' in FP32' if dom == 'mixed' else ''})",
-                    peak_note="FP64 and unpacked FP32 VALU FMA rate (256 CUs x 64 lanes x 2 flops x 2.4 GHz); the "
-                              "published FP32 vector peak 157.3 TFLOP/s needs packed FP32, which the build disables",
-                    frac_of_published_fp32_peak=round(kd["tflops"] / PEAK_FP32_TFLOPS, 4) if dom == "mixed" else None,
+                    peak_note="the kernel's own flop mix at the published vector peaks: (FP64 + FP32 flops) / "
+                              "(FP64 flops / 78.6 + FP32 flops / 157.3 TFLOP/s); the FP32 flops are the near disks' "
+                              "ring expansions",
                     dense_pairs_per_launch=dense_launch, kernels=kern)
 
     # stacked matvec: one T mu on args.rhs vectors at once, per vector (HIP events)

@@ -60,10 +60,11 @@ typedef enum {
 typedef enum { MFS_RESISTANCE = 0, MFS_MOBILITY = 1 } mfs_problem;
 
 /* Arithmetic of the all-pairs Stokeslet sum (step 2a of Alg. 3).  Every other step
- * is FP64 in both modes.  MFS_MIXED evaluates the kernel in FP32 on body-relative
- * coordinates with FP64 accumulation; mfs_gmres_solve then runs GMRES with the
- * operator relaxed from FP64 to mixed as the residual falls, inside an FP64
- * refinement on the true residual. */
+ * is FP64 in both modes.  MFS_MIXED evaluates the near disks' ring expansions (FP64
+ * moments, offsets rounded once) in FP32 with FP64 accumulation, and translates far cells
+ * into the local expansions in FP64 at a lower order; mfs_gmres_solve then runs GMRES with
+ * the operator relaxed from FP64 to mixed as the residual falls, inside an FP64 refinement
+ * on the true residual. */
 typedef enum { MFS_FP64 = 0, MFS_MIXED = 1 } mfs_precision;
 
 /* Method parameters; mfs_default_params fills the paper's values (Sec. 5, Sec. 6). */
@@ -161,13 +162,14 @@ mfs_status mfs_precompute_pairs(mfs_ctx* ctx, mfs_problem prob, int64_t* n_pairs
  * lexicographic order, or NULL to query only the count. */
 mfs_status mfs_get_pairs(const mfs_ctx* ctx, int64_t* n_pairs, int32_t* pairs);
 
-/* The disk order and clusters of the kernel sums' two-level far field (for work accounting
- * and tests).  Disks are sorted along a Morton curve over their centres and cut
+/* The disk order of the kernel sums and the clusters of the two-level FP64 sum (for tests
+ * and inspection).  Disks are sorted along a Morton curve over their centres and cut
  * into clusters of consecutive disks (at most 16 disks and 1024 sources each, within one
- * quadtree cell).  A cluster farther than 4 radii from a target is summed through one
- * expansion about its centre, order 12 in FP32 and 26 in FP64 (moments A_k, B_k and
- * D_k = sum sigma conj(w) w^k of its sources; the paper's fast multipole method plays this
- * part, Sec. 6).
+ * quadtree cell).  In the FP64 sum at arbitrary points (mfs_flow_eval), a cluster farther
+ * than 4 radii from a target is summed through one order-26 expansion about its centre
+ * (moments A_k, B_k and D_k = sum sigma conj(w) w^k of its sources; the paper's fast
+ * multipole method plays this part, Sec. 6).  The same disk order is the leaf order of the
+ * hierarchical sum's quadtree (mfs_get_fmm).
  * n_clusters: host, written.  Each of the others is host memory or NULL: slot_body (P):
  * the disk at each position of the order; cl_start (n_clusters + 1): first position of
  * each cluster; centre (2 n_clusters): mean of its disks' centres; radius (n_clusters):

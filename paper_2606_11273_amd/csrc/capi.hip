@@ -74,17 +74,16 @@ Status upload(mfs_ctx* c, T** p, const std::vector<T>& h, hipStream_t s) {
 }
 
 void free_all(mfs_ctx* c) {
-  void* ptrs[] = {c->d_nbr_off, c->d_nbr_list, c->d_bdat,
-                  c->d_src_off, c->d_col_off, c->d_cls,   c->d_tgt_body, c->d_pairs,  c->d_bp_off, c->d_bp_list,
-                  c->d_xoff,    c->d_aoff,    c->d_coff,  c->d_centers,  c->d_Y,      c->d_X,      c->d_Xr32,
-                  c->d_lam_bar, c->d_ltil,    c->d_sig64, c->d_u,        c->d_corr,   c->d_upart,  c->d_epair,
-                  c->d_out3,    c->d_given,   c->d_sig32, c->d_src64,    c->ps[0].A,  c->ps[0].E,  c->ps[1].A,
-                  c->ps[1].E,   c->kr.V,      c->kr.w,    c->kr.part,    c->kr.hdev,  c->kr.x,     c->kr.r,
-                  c->kr.b,      c->kr.d,      c->kr.tmp,  c->d_lam_bar_m, c->d_ltil_m, c->d_u_m,   c->d_corr_m,
-                  c->d_sig32m,  c->d_bdatm,   c->d_src64m,  c->d_mu_last, c->d_fsrc,  c->d_ptil,  c->d_sigf, c->d_mp,
-                  c->d_mpm,     c->d_mp64,    c->d_mp64m,   c->d_fmp64, c->d_slot_of, c->d_slot_body, c->d_ssrc_off, c->d_nbr_slot,
-                  c->d_cl_start, c->d_scent,  c->d_ccent,   c->d_crad2, c->d_cmp,  c->d_cmpm, c->d_crad64, c->d_body_cl,
-                  c->d_tperm,   c->d_work};
+  void* ptrs[] = {c->d_nbr_off,  c->d_nbr_list, c->d_src_off,  c->d_col_off,  c->d_cls,       c->d_tgt_body,
+                  c->d_pairs,    c->d_bp_off,   c->d_bp_list,  c->d_xoff,     c->d_aoff,      c->d_coff,
+                  c->d_centers,  c->d_Y,        c->d_X,        c->d_lam_bar,  c->d_ltil,      c->d_u,
+                  c->d_corr,     c->d_upart,    c->d_epair,    c->d_out3,     c->d_given,     c->d_src64,
+                  c->ps[0].A,    c->ps[0].E,    c->ps[1].A,    c->ps[1].E,    c->kr.V,        c->kr.w,
+                  c->kr.part,    c->kr.hdev,    c->kr.x,       c->kr.r,       c->kr.b,        c->kr.d,
+                  c->kr.tmp,     c->d_lam_bar_m, c->d_ltil_m,  c->d_u_m,      c->d_corr_m,    c->d_src64m,
+                  c->d_mu_last,  c->d_fsrc,     c->d_ptil,     c->d_sigf,     c->d_fmp64,     c->d_slot_of,
+                  c->d_slot_body, c->d_ssrc_off, c->d_nbr_slot, c->d_cl_start, c->d_ccent,    c->d_crad64,
+                  c->d_tperm,    c->d_work};
   for (void* p : ptrs)
     if (p) dev_free(c, p);
   for (void* p : {(void*)c->d_cell_child_off, (void*)c->d_cell_child, (void*)c->d_cell_by_height, (void*)c->d_cell_c,
@@ -144,7 +143,8 @@ Status validate_host(mfs_ctx* c, const double* centers, const double* radii, con
   return Status{};
 }
 
-// Order of the disks for the FP32 kernel sum and its clusters.  Disks are sorted along a
+// Order of the disks for the kernel sums ("slots") and the clusters of the two-level FP64 sum
+// at arbitrary points (flow evaluation).  Disks are sorted along a
 // Morton curve over their centres (16 bits per axis, ties by index); the curve is cut into
 // quadtree cells holding about 16..64 disks, and each cell into runs of at most
 // kClMaxBodies disks and kClMaxSources sources: these runs are the clusters.  A cluster's
@@ -269,25 +269,12 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   Status st = onebody_factors(c);
   if (st.code) return st;
   build_clusters(c);
-  // slot-ordered copies for the FP32 kernel sum
+  // slot-ordered source offsets and partner lists (kernel sums)
   std::vector<int32_t> ssrc_off(P + 1, 0), nbr_slot(c->nbr_list.size());
-  std::vector<double> scent(2 * (size_t)P);
-  std::vector<float> crad2(c->ncl);
-  for (int s = 0; s < P; ++s) {
-    const int b = c->slot_body[s];
-    ssrc_off[s + 1] = ssrc_off[s] + n_src[b];
-    scent[2 * s] = c->centers[2 * b];
-    scent[2 * s + 1] = c->centers[2 * b + 1];
-  }
+  for (int s = 0; s < P; ++s) ssrc_off[s + 1] = ssrc_off[s] + n_src[c->slot_body[s]];
   for (int i = 0; i < P; ++i) {
     for (int e = c->nbr_off[i]; e < c->nbr_off[i + 1]; ++e) nbr_slot[e] = c->slot_of[c->nbr_list[e]];
     std::sort(nbr_slot.begin() + c->nbr_off[i], nbr_slot.begin() + c->nbr_off[i + 1]);
-  }
-  // radius rounded up to FP32, so the kernel's far test never admits a nearer point
-  for (int q = 0; q < c->ncl; ++q) {
-    float r = (float)c->cl_radius[q];
-    if ((double)r < c->cl_radius[q]) r = std::nextafter(r, INFINITY);
-    crad2[q] = r * r;
   }
   // exact evaluation counts of one kernel sum: all sources, and without own disk and partners
   c->evals_all = c->Ns * c->Nt;
@@ -297,9 +284,8 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
     for (int e = c->nbr_off[i]; e < c->nbr_off[i + 1]; ++e) skipped += n_src[c->nbr_list[e]];
     c->evals_skip += (int64_t)n_col[i] * (c->Ns - skipped);
   }
-  // absolute and relative coordinates
+  // absolute coordinates
   std::vector<double> Y(2 * c->Ns), X(2 * c->Nt);
-  std::vector<float> Xr32(2 * c->Nt);
   std::vector<int32_t> tb(c->Nt);
   for (int i = 0; i < P; ++i) {
     const int k = c->cls[i];
@@ -313,8 +299,6 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
       const int64_t t = c->col_off[i] + q;
       X[2 * t] = centers[2 * i] + xr[2 * q];
       X[2 * t + 1] = centers[2 * i + 1] + xr[2 * q + 1];
-      Xr32[2 * t] = (float)xr[2 * q];
-      Xr32[2 * t + 1] = (float)xr[2 * q + 1];
       tb[t] = i;
     }
   }
@@ -334,21 +318,14 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   if ((st = upload(c, &c->d_centers, c->centers, s)).code) return st;
   if ((st = upload(c, &c->d_Y, Y, s)).code) return st;
   if ((st = upload(c, &c->d_X, X, s)).code) return st;
-  if ((st = upload(c, &c->d_Xr32, Xr32, s)).code) return st;
   if ((st = upload(c, &c->d_slot_of, c->slot_of, s)).code) return st;
   if ((st = upload(c, &c->d_slot_body, c->slot_body, s)).code) return st;
   if ((st = upload(c, &c->d_ssrc_off, ssrc_off, s)).code) return st;
   if ((st = upload(c, &c->d_nbr_slot, nbr_slot, s)).code) return st;
   if ((st = upload(c, &c->d_cl_start, c->cl_start, s)).code) return st;
-  if ((st = upload(c, &c->d_scent, scent, s)).code) return st;
   if ((st = upload(c, &c->d_ccent, c->cl_centre, s)).code) return st;
-  if ((st = upload(c, &c->d_crad2, crad2, s)).code) return st;
   if ((st = upload(c, &c->d_crad64, c->cl_radius, s)).code) return st;
   {
-    std::vector<int32_t> body_cl(P);
-    for (int q = 0; q < c->ncl; ++q)
-      for (int sl = c->cl_start[q]; sl < c->cl_start[q + 1]; ++sl) body_cl[c->slot_body[sl]] = q;
-    if ((st = upload(c, &c->d_body_cl, body_cl, s)).code) return st;
     // the kernel sums visit the targets disk by disk in slot order, so that a workgroup's
     // targets (and a wave's) lie close together and far clusters are far for all of them
     std::vector<int32_t> tperm;
@@ -369,13 +346,7 @@ Status build(mfs_ctx* c, const double* centers, const double* radii, const int32
   if ((st = dalloc(c, &c->d_epair, 6 * (size_t)C)).code) return st;
   if ((st = dalloc(c, &c->d_out3, 3 * (size_t)P)).code) return st;
   if ((st = dalloc(c, &c->d_given, 3 * (size_t)P)).code) return st;
-  if ((st = dalloc(c, &c->d_sig32, c->Ns)).code) return st;
-  if ((st = dalloc(c, &c->d_bdat, (size_t)P)).code) return st;
-  if ((st = dalloc(c, &c->d_mp, (size_t)P * kMpCoefPerDisk)).code) return st;
-  if ((st = dalloc(c, &c->d_cmp, (size_t)c->ncl * kClCoefPerCluster)).code) return st;
-  if ((st = dalloc(c, &c->d_sig64, 2 * c->Ns)).code) return st;
   if ((st = dalloc(c, &c->d_src64, c->Ns)).code) return st;
-  if ((st = dalloc(c, &c->d_mp64, (size_t)mp64_record(c))).code) return st;
   MFS_HIP(hipStreamSynchronize(s));
   return Status{};
 }
@@ -411,15 +382,9 @@ Status apply_T(mfs_ctx* c, int prob, bool mixed, const double* mu, double* u, co
 // Stacked buffers for R right-hand sides.
 Status ensure_stacked(mfs_ctx* c, int R) {
   if (c->rhs_cap >= R) return Status{};
-  for (void* p : {(void*)c->d_lam_bar_m, (void*)c->d_ltil_m, (void*)c->d_u_m, (void*)c->d_corr_m,
-                  (void*)c->d_sig32m, (void*)c->d_bdatm, (void*)c->d_src64m, (void*)c->d_mpm, (void*)c->d_mp64m,
-                  (void*)c->d_cmpm})
+  for (void* p : {(void*)c->d_lam_bar_m, (void*)c->d_ltil_m, (void*)c->d_u_m, (void*)c->d_corr_m, (void*)c->d_src64m})
     if (p) dev_free(c, p);
-  c->d_cmpm = nullptr;
   c->d_lam_bar_m = c->d_ltil_m = c->d_u_m = c->d_corr_m = nullptr;
-  c->d_sig32m = c->d_bdatm = nullptr;
-  c->d_mpm = nullptr;
-  c->d_mp64m = nullptr;
   c->d_src64m = nullptr;
   c->rhs_cap = 0;
   const int C = (int)(c->pairs.size() / 2);
@@ -428,12 +393,7 @@ Status ensure_stacked(mfs_ctx* c, int R) {
   if ((st = dalloc(c, &c->d_ltil_m, (size_t)R * c->xoff[C])).code) return st;
   if ((st = dalloc(c, &c->d_u_m, (size_t)R * 2 * c->Nt)).code) return st;
   if ((st = dalloc(c, &c->d_corr_m, (size_t)R * c->coff[C])).code) return st;
-  if ((st = dalloc(c, &c->d_sig32m, (size_t)R * c->Ns)).code) return st;
-  if ((st = dalloc(c, &c->d_bdatm, (size_t)R * c->P)).code) return st;
-  if ((st = dalloc(c, &c->d_mpm, (size_t)R * c->P * kMpCoefPerDisk)).code) return st;
-  if ((st = dalloc(c, &c->d_cmpm, (size_t)R * c->ncl * kClCoefPerCluster)).code) return st;
   if ((st = dalloc(c, &c->d_src64m, (size_t)R * c->Ns)).code) return st;
-  if ((st = dalloc(c, &c->d_mp64m, (size_t)R * mp64_record(c))).code) return st;
   c->rhs_cap = R;
   return Status{};
 }
@@ -463,8 +423,7 @@ Status apply_T_rhs(mfs_ctx* c, int prob, bool mixed, int R, const double* mu, do
     if (wp && !launch_pair_A_rhs(c, prob, Rc, c->d_lam_bar_m, ns2, c->d_ltil_m, nx))
       for (int r = 0; r < Rc; ++r) launch_pair_A(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx);
     for (int r = 0; r < Rc; ++r)
-      launch_gather_project_to(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx, wp, nullptr,
-                               c->d_src64m + r * c->Ns, nullptr);
+      launch_gather_project_to(c, prob, c->d_lam_bar_m + r * ns2, c->d_ltil_m + r * nx, wp, c->d_src64m + r * c->Ns);
     for (int r = 0; r < Rc; ++r) launch_fmm_records(c, prob, c->d_src64m + r * c->Ns, fmm_records(c, r), mixed);
     const bool ks = launch_kernel_sum_rhs(c, mixed, 2, Rc, c->d_u_m, 1.0 / (4.0 * kPiD * c->prm.mu));
     if ((st = check_kernel_sum(c, ks)).code) return st;

@@ -82,7 +82,7 @@ Status flow_eval(mfs_ctx* c, int prob, const double* mu, const double* given, in
   // step 1 of Alg. 3: lambda_bar and the pairs' lambda_tilde; total strengths with positions
   launch_onebody_apply(c, prob, mu, c->d_lam_bar);
   launch_pair_A(c, prob, c->d_lam_bar, c->d_ltil);
-  launch_gather_project_to(c, prob, c->d_lam_bar, c->d_ltil, true, nullptr, c->d_fsrc, nullptr);
+  launch_gather_project_to(c, prob, c->d_lam_bar, c->d_ltil, true, c->d_fsrc);
   if (prob == MFS_MOBILITY) {
     MFS_HIP(hipMemcpyAsync(c->d_given, given, sizeof(double) * 3 * c->P, hipMemcpyHostToDevice, c->stream));
     launch_add_rhs_sources(c, c->d_given, c->d_fsrc);

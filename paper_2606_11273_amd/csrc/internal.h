@@ -15,19 +15,14 @@ namespace mfs {
 
 constexpr int kMaxClasses = 4;     // distinct (radius, n_src, n_col, r_src) disk classes
 constexpr int kMaxCol = 512;       // n_col limit per disk
-constexpr int kMpOrder = 8;        // order of the per-disk far-field expansion of the FP32 kernel sum
-constexpr int kMpCoefPerDisk = 3 * kMpOrder + 2;   // its FP32 complex coefficients per disk
 constexpr int kMp64Order = 18;     // order of the FP64 kernel sum's far-field expansion
 constexpr int kMp64CoefPerDisk = 3 * kMp64Order + 3;   // FP64 complex coefficients per disk (last: rho^2)
-// Two-level FP32 kernel sum: disks in a space-filling-curve order ("slots"), grouped into
-// clusters of at most kClMaxBodies consecutive slots; a cluster far from a target is summed
-// through one expansion of order kClOrder about its centre.
-constexpr int kClOrder = 12;
-constexpr int kClCoefPerCluster = 4 * kClOrder + 2;   // FP32 complex coefficients per cluster
+// Two-level FP64 sum at arbitrary points (flow evaluation): disks in a space-filling-curve
+// order ("slots"), grouped into clusters of at most kClMaxBodies consecutive slots; a cluster
+// far from a target is summed through one expansion of order kCl64Order about its centre.  The
+// hierarchical kernel sum's cells carry records of the same layout.
 constexpr int kClMaxBodies = 16;
 constexpr int kClMaxSources = 1024;                   // sources per cluster (one LDS tile)
-// The FP64 kernel sum's cluster expansions (same clusters and far test, order for FP64 rounding);
-// the same FP64 records feed both kernel sums' local expansions
 constexpr int kCl64Order = 26;
 // Local expansions (M2L / L2P) of the kernel sums: a cluster farther than kLocSep32 (R + r_b)
 // (FP32 sum) or kLocSep64 (R + r_b) (FP64 sum), and than 4 R + r_b, from the centre of a
@@ -186,15 +181,11 @@ struct mfs_ctx {
   double* d_centers = nullptr;   // P x 2
   double* d_Y = nullptr;         // Ns x 2 absolute sources
   double* d_X = nullptr;         // Nt x 2 absolute nodes
-  float* d_Xr32 = nullptr;       // Nt x 2 nodes relative to their centre
-  // the same in slot order, for the FP32 kernel sum
+  // disks in slot order (a space-filling curve): the kernel sums' visiting order
   int32_t *d_slot_of = nullptr, *d_slot_body = nullptr, *d_ssrc_off = nullptr, *d_nbr_slot = nullptr;
   int32_t* d_cl_start = nullptr;
-  double* d_scent = nullptr;     // P x 2 centres in slot order
   double* d_ccent = nullptr;     // ncl x 2 cluster centres
-  float* d_crad2 = nullptr;      // ncl squared cluster radii
   double* d_crad64 = nullptr;    // ncl cluster radii (FP64 sum)
-  int32_t* d_body_cl = nullptr;  // P: cluster of each disk
   int32_t* d_tperm = nullptr;    // Nt: the kernel sums visit targets in slot order (disk by disk)
   // hierarchical kernel sum: cells (leaves 0..P-1 = slots), children CSR, heights, wave centres
   int ncell = 0, nwave = 0, cell_height = 0;
@@ -215,24 +206,14 @@ struct mfs_ctx {
   double* scratch = nullptr;     // the device's static scratch array (mfs_apply_noalloc), resolved at setup
 
   // work vectors
-  double *d_lam_bar = nullptr, *d_ltil = nullptr, *d_sig64 = nullptr, *d_u = nullptr, *d_corr = nullptr;
+  double *d_lam_bar = nullptr, *d_ltil = nullptr, *d_u = nullptr, *d_corr = nullptr;
   double *d_upart = nullptr, *d_epair = nullptr, *d_out3 = nullptr, *d_given = nullptr;
-  float4* d_sig32 = nullptr;     // per source: (yr_x, yr_y, sigma_x, sigma_y)
-  float4* d_bdat = nullptr;      // per disk: (net strength x, y, ring radius^2, W) for the FP32 sum
-  float2* d_mp = nullptr;        // per disk: far-field expansion coefficients for the FP32 sum
-  float2* d_cmp = nullptr;       // per cluster: its expansion coefficients for the FP32 sum
-  double2* d_mp64 = nullptr;     // far-field coefficients of d_src64 for the FP64 sum (mp64_record)
   double4* d_src64 = nullptr;    // per source: (y_x, y_y, sigma_x, sigma_y)
   int64_t upart_cap = 0;
 
   // stacked right-hand sides of the matvec (allocated on first use for rhs_cap vectors)
   int rhs_cap = 0;
   double *d_lam_bar_m = nullptr, *d_ltil_m = nullptr, *d_u_m = nullptr, *d_corr_m = nullptr;
-  float4* d_sig32m = nullptr;    // rhs_cap arrays of Ns records
-  float4* d_bdatm = nullptr;     // rhs_cap arrays of P records
-  float2* d_mpm = nullptr;       // rhs_cap arrays of P far-field coefficient records
-  float2* d_cmpm = nullptr;      // rhs_cap arrays of ncl cluster coefficient records
-  double2* d_mp64m = nullptr;    // rhs_cap arrays of P FP64 far-field coefficient records
   double4* d_src64m = nullptr;   // rhs_cap arrays of Ns records
 
   mfs::PairSet ps[2];
@@ -277,10 +258,9 @@ void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil);
 // the context's), with the FP32 ring records when pack32
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                            bool pack32, bool pack64, const FmmRec* fr = nullptr);
-// sig32, bdat, mp (FP32 sum: slot order) and cmp (its cluster coefficients) go together
+// the same into an explicit packed array (caller's disk order)
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                              float4* sig32, double4* src64, float4* bdat, float2* mp = nullptr,
-                              float2* cmp = nullptr, double2* cm64 = nullptr);
+                              double4* src64);
 // stacked forms for R = 2, 4 or 8 vectors (false: unsupported size or out of memory)
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
                        int64_t ltil_stride);

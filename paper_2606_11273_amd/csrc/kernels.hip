@@ -245,32 +245,15 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_A_rhs(int C, const int* _
 
 // ---------------------------------------------------------------------------
 // eq. total_corr + projection: lambda^(b) = lambda_bar^(b) + sum_{c contains b} lambda_tilde^c_b,
-// sigma = (I - L) lambda (mobility) or lambda (resistance); packed for the kernel sum.
-// Far-field expansion of a disk for the FP32 kernel sum (Sec. 6 evaluates the far field
-// with a fast multipole method; here one level, per disk).  In complex notation, with
-// w_s = y_s - c on the ring |w| = rho, A_k = sum sigma w^k, B_k = sum sigma conj(w)^k and
-// zeta = 1/Z for a point x = c + Z, the disk's contribution to the sum below is
-//   -S0 ln|Z| + S0/2 + sum_k (A_k zeta^k + B_k conj(zeta)^k)/(2k)
-//   + conj(zeta)/2 [ (Z - rho^2 conj(zeta)) sum_{k>=0} conj(A_k) conj(zeta)^k - conj(B_1) ].
-// Order kMpOrder = 8, used where |Z| > rho / kMpTheta, kMpTheta = 1/7: truncation below
-// sum |sigma| kMpTheta^(kMpOrder + 1) / (1 - kMpTheta) = 3e-8 sum |sigma|.  Coefficients per
-// disk (FP64 sums, stored FP32): A_k/(2k) (k = 1..p), B_k/(2k) (k = 1..p), conj(A_k)
-// (k = 0..p), conj(B_1).
-constexpr int kMpCoef = kMpCoefPerDisk;
-constexpr float kMpFar2 = 49.0f;   // (1 / kMpTheta)^2
-
+// sigma = (I - L) lambda (mobility) or lambda (resistance); packed for the kernel sum as
+// (y, sigma) per source, FP64, in the caller's disk order.
 __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
     int P, int mobility, const int* __restrict__ cls, const int* __restrict__ src_off, ClassTab ct,
     const int* __restrict__ bp_off, const int* __restrict__ bp_list, const int* __restrict__ pairs,
     const int64_t* __restrict__ xoff, const double* __restrict__ ltil, const double* __restrict__ lam_bar,
-    int with_pairs, const double* __restrict__ centers, double* __restrict__ sig64, float4* __restrict__ sig32,
-    double4* __restrict__ src64, float4* __restrict__ bdat, float2* __restrict__ mp, const int* __restrict__ slot_of,
-    const int* __restrict__ ssrc_off) {
+    int with_pairs, const double* __restrict__ centers, double4* __restrict__ src64) {
   const int b = blockIdx.x;
   if (b >= P) return;
-  // the FP32 sum's records (sig32, bdat, mp) are stored in its slot order
-  const int sl = slot_of[b];
-  const int64_t sso = ssrc_off[sl];
   const int k = cls[b];
   const int nc = ct.nc[k];
   const int64_t so = src_off[b];
@@ -291,196 +274,20 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
   if (mobility) project_rigid<kBodyThreads>(s_l, nc, ct.Yr[k], ct.KtKi[k], red);
   const double* Yr = ct.Yr[k];
   const double cx = centers[2 * b], cy = centers[2 * b + 1];
-  if (bdat) {
-    // moments of the disk's strengths in FP64 for the FP32 kernel sum: the net
-    // strength S0 = sum_j sigma_j, W = sum_j y_j . sigma_j (y relative to the
-    // centre), and the ring radius squared q = |y_j|^2
-    double s0x = 0, s0y = 0, w = 0;
-    for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
-      s0x += s_l[2 * j];
-      s0y += s_l[2 * j + 1];
-      w += Yr[2 * j] * s_l[2 * j] + Yr[2 * j + 1] * s_l[2 * j + 1];
-    }
-    s0x = block_sum<kBodyThreads>(s0x, red);
-    s0y = block_sum<kBodyThreads>(s0y, red + 16);
-    w = block_sum<kBodyThreads>(w, red + 32);
-    if (threadIdx.x == 0) {
-      const double q = Yr[0] * Yr[0] + Yr[1] * Yr[1];
-      bdat[sl] = make_float4((float)s0x, (float)s0y, (float)q, (float)w);
-    }
-  }
-  if (mp) {
-    // multipole moments A_1..A_p, B_1..B_p (FP64; A_0 = S0 and B_1 are the moments above)
-    double ar[kMpOrder], ai[kMpOrder], br[kMpOrder], bi[kMpOrder];
-#pragma unroll
-    for (int k = 0; k < kMpOrder; ++k) ar[k] = ai[k] = br[k] = bi[k] = 0.0;
-    double s0r = 0.0, s0i = 0.0;
-    for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
-      const double wx = Yr[2 * j], wy = Yr[2 * j + 1], sx = s_l[2 * j], sy = s_l[2 * j + 1];
-      s0r += sx;
-      s0i += sy;
-      double pr = sx, pi = sy, qr = sx, qi = sy;   // sigma w^k and sigma conj(w)^k
-#pragma unroll
-      for (int k = 0; k < kMpOrder; ++k) {
-        const double tr = pr * wx - pi * wy, ti = pr * wy + pi * wx;
-        const double ur = qr * wx + qi * wy, ui = qi * wx - qr * wy;
-        pr = tr;
-        pi = ti;
-        qr = ur;
-        qi = ui;
-        ar[k] += pr;
-        ai[k] += pi;
-        br[k] += qr;
-        bi[k] += qi;
-      }
-    }
-    __shared__ double mred[2][4 * kMpOrder + 2];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    auto put = [&](int slot, double v) {
-      v = wave_sum(v);
-      if (lane == 0) mred[wid][slot] = v;
-    };
-#pragma unroll
-    for (int k = 0; k < kMpOrder; ++k) {
-      put(4 * k, ar[k]);
-      put(4 * k + 1, ai[k]);
-      put(4 * k + 2, br[k]);
-      put(4 * k + 3, bi[k]);
-    }
-    put(4 * kMpOrder, s0r);
-    put(4 * kMpOrder + 1, s0i);
-    __syncthreads();
-    static_assert(kBodyThreads == 128, "two waves per body block");
-    for (int e = threadIdx.x; e < 4 * kMpOrder + 2; e += kBodyThreads) mred[0][e] += mred[1][e];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float2* o = mp + (int64_t)sl * kMpCoef;
-      for (int k = 1; k <= kMpOrder; ++k) {
-        const double* m = &mred[0][4 * (k - 1)];
-        o[k - 1] = make_float2((float)(m[0] / (2 * k)), (float)(m[1] / (2 * k)));
-        o[kMpOrder + k - 1] = make_float2((float)(m[2] / (2 * k)), (float)(m[3] / (2 * k)));
-        o[2 * kMpOrder + k] = make_float2((float)m[0], (float)(-m[1]));
-      }
-      o[2 * kMpOrder] = make_float2((float)mred[0][4 * kMpOrder], (float)(-mred[0][4 * kMpOrder + 1]));
-      o[3 * kMpOrder + 1] = make_float2((float)mred[0][2], (float)(-mred[0][3]));
-    }
-  }
-  for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
-    const double sx = s_l[2 * j], sy = s_l[2 * j + 1];
-    if (sig64) {
-      sig64[2 * (so + j)] = sx;
-      sig64[2 * (so + j) + 1] = sy;
-    }
-    if (sig32) sig32[sso + j] = make_float4((float)Yr[2 * j], (float)Yr[2 * j + 1], (float)sx, (float)sy);
-    if (src64) src64[so + j] = make_double4(cx + Yr[2 * j], cy + Yr[2 * j + 1], sx, sy);
-  }
-}
-
-// Expansion of a cluster of disks about its centre C for the FP32 kernel sum (the
-// two-level far field).  With w = y - C over the cluster's sources (not on one ring),
-//   4 pi mu u(C + Z) = -S0 ln|Z| + S0/2 + sum_k (A_k zeta^k + B_k conj(zeta)^k) / (2k)
-//                      + conj(zeta)/2 [Z P - Q],
-// zeta = 1/Z, A_k = sum sigma w^k, B_k = sum sigma conj(w)^k, D_k = sum sigma conj(w) w^k,
-// P = sum_k conj(A_k) conj(zeta)^k, Q = sum_k conj(D_k) conj(zeta)^k (k = 0..p).  The moments
-// are FP64 sums over the FP64 strengths (sig64, body order); record per cluster, FP32:
-// A_k/(2k), B_k/(2k) (k = 1..p), conj(A_k), conj(D_k) (k = 0..p).  Truncation: below
-// sum |sigma| theta^(p+1) / (1 - theta), theta = cluster radius / |Z| <= 1/4 where used.
-constexpr int kClCoef = kClCoefPerCluster;
-constexpr float kClFar2 = 16.0f;   // a cluster is far beyond 4 cluster radii
-constexpr int kClM = 6 * (kClOrder + 1);   // real moment components per cluster
-
-__global__ __launch_bounds__(kBodyThreads) void k_cluster_moments(int ncl, const int* __restrict__ cl_start,
-                                                                  const int* __restrict__ slot_body,
-                                                                  const int* __restrict__ cls,
-                                                                  const int* __restrict__ src_off, ClassTab ct,
-                                                                  const double* __restrict__ centers,
-                                                                  const double* __restrict__ ccent,
-                                                                  const double* __restrict__ sig64,
-                                                                  float2* __restrict__ cmp) {
-  const int q = blockIdx.x;
-  if (q >= ncl) return;
-  const double Cx = ccent[2 * q], Cy = ccent[2 * q + 1];
-  double m[kClM];   // per k: A (re, im), B (re, im), D (re, im)
-#pragma unroll
-  for (int e = 0; e < kClM; ++e) m[e] = 0.0;
-  for (int sl = cl_start[q]; sl < cl_start[q + 1]; ++sl) {
-    const int b = slot_body[sl];
-    const int k = cls[b];
-    const int nc = ct.nc[k];
-    const double* Yr = ct.Yr[k];
-    const int64_t so = src_off[b];
-    const double ox = centers[2 * b] - Cx, oy = centers[2 * b + 1] - Cy;
-    for (int j = threadIdx.x; j < nc; j += kBodyThreads) {
-      const double wx = ox + Yr[2 * j], wy = oy + Yr[2 * j + 1];
-      double pr = sig64[2 * (so + j)], pi = sig64[2 * (so + j) + 1];   // sigma w^k
-      double qr = pr, qi = pi;                                           // sigma conj(w)^k
-#pragma unroll
-      for (int e = 0; e <= kClOrder; ++e) {
-        m[6 * e] += pr;
-        m[6 * e + 1] += pi;
-        m[6 * e + 2] += qr;
-        m[6 * e + 3] += qi;
-        m[6 * e + 4] += wx * pr + wy * pi;   // conj(w) sigma w^k
-        m[6 * e + 5] += wx * pi - wy * pr;
-        const double tr = pr * wx - pi * wy, ti = pr * wy + pi * wx;
-        const double ur = qr * wx + qi * wy, ui = qi * wx - qr * wy;
-        pr = tr;
-        pi = ti;
-        qr = ur;
-        qi = ui;
-      }
-    }
-  }
-  __shared__ double mred[2][kClM];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int e = 0; e < kClM; ++e) {
-    const double v = wave_sum(m[e]);
-    if (lane == 0) mred[wid][e] = v;
-  }
-  __syncthreads();
-  static_assert(kBodyThreads == 128, "two waves per cluster block");
-  float2* o = cmp + (int64_t)q * kClCoef;
-  for (int e = threadIdx.x; e <= kClOrder; e += kBodyThreads) {
-    const double* a = &mred[0][6 * e];
-    const double* a1 = &mred[1][6 * e];
-    const double Ar = a[0] + a1[0], Ai = a[1] + a1[1], Br = a[2] + a1[2], Bi = a[3] + a1[3];
-    const double Dr = a[4] + a1[4], Di = a[5] + a1[5];
-    if (e >= 1) {
-      o[e - 1] = make_float2((float)(Ar / (2 * e)), (float)(Ai / (2 * e)));
-      o[kClOrder + e - 1] = make_float2((float)(Br / (2 * e)), (float)(Bi / (2 * e)));
-    }
-    o[2 * kClOrder + e] = make_float2((float)Ar, (float)(-Ai));
-    o[3 * kClOrder + 1 + e] = make_float2((float)Dr, (float)(-Di));
-  }
+  for (int j = threadIdx.x; j < nc; j += kBodyThreads)
+    src64[so + j] = make_double4(cx + Yr[2 * j], cy + Yr[2 * j + 1], s_l[2 * j], s_l[2 * j + 1]);
 }
 
 // ---------------------------------------------------------------------------
-// Step 2a: all-pairs Stokeslet sum u_t = sum_s S(x_t, y_s) sigma_s (eq. getall, eq. stokeslet2d).
-//
-// A workgroup owns T * 256 consecutive targets of the visiting order (the nodes of the disks
-// in slot order, so nearby targets share a workgroup), thread i the T targets from T i on,
-// so a wave holds 64 T consecutive targets.  A wave takes one path per cluster and per disk
-// (expansion or direct) for all its targets.  The FP64 sum streams the sources of a
-// range of bodies (one split of blockIdx.y) through LDS in tiles of whole bodies; the FP32
-// sum walks a range of clusters of its disk order, one cluster per tile, and skips the
-// tile of a cluster that is far from all its targets (two-level far field, below).
+// Step 2a: all-pairs Stokeslet sum u_t = sum_s S(x_t, y_s) sigma_s (eq. getall, eq. stokeslet2d),
 //   u = 1/(4 pi mu) [ sum (d.sigma / r^2) d  -  (ln 2 / 2) sum log2(r^2) sigma ].
-// A disk far from every target of a thread (beyond 7 ring radii) is summed from its
-// multipole expansion (k_gather_project, k_moments64).
-// Mixed form: per (target, source disk) the offset D of the target from the disk
-// centre is formed in FP64 and rounded once; the pair terms are evaluated in FP32
-// on body-relative coordinates (v_rcp_f32 for 1/r^2, v_log_f32 for the log) and
-// summed per source disk in FP32; each disk's partial is added to FP64
-// accumulators.  The disk's field is split so that the FP32 loop only sums parts
-// that shrink with the distance R = |D| as the field itself does, the leading parts
-// coming from FP64 moments of the disk's strengths (S0 = sum sigma, W = sum y.sigma):
-//   log2 r^2 = log2 R^2 + log2(1 + w),  w = (q - 2 D.y) / R^2,  |y|^2 = q,
-// with log2(1 + w) rounded relative to w (not to 1), and
-//   sum_s (d.sigma) / (r^2 / R^2) = D.S0 - W - sum_s w_s (d.sigma)_s / (r_s^2 / R^2).
-// Without this a disk whose strengths nearly cancel (zero net force and torque in
-// the mobility problem) leaves an FP32 error of ~eps_32 |sigma| at every distance,
-// and those errors add up over all disks.
+// Two kernels evaluate it.  The context's own sum (every matvec, the right-hand side) is the
+// hierarchical k_ksum_fmm at the end of this file.  Sums at arbitrary points (flow
+// evaluation) use the two-level FP64 k_ksum_fp64: a workgroup owns T * 256 consecutive
+// targets, thread i the T targets from T i on; it streams one split's clusters of disks
+// through LDS, one cluster per tile; a cluster far from every target of a wave is summed
+// from its expansion, a disk beyond 7 ring radii from its multipole expansion (k_moments64),
+// the rest directly.
 constexpr int KS_THREADS = 256;
 constexpr int KS_TILE = 1024;   // sources per LDS tile (16 KB of float4)
 
@@ -699,350 +506,6 @@ __device__ __forceinline__ bool skip_test(Skip& sk, int mode, int kb, int body, 
   return false;
 }
 
-// Disks are visited in slot order (src_off, centers, src, bdat, mp and the partner lists
-// nbr_list are in slots), one cluster of consecutive slots per LDS tile.  A cluster that is
-// far (beyond 4 cluster radii) from every target of a thread and holds neither a target's
-// own disk nor a partner to be skipped is summed through its expansion (k_cluster_moments;
-// cmp = NULL: never); otherwise its disks are taken one by one as below.
-template <int T>
-__global__ __launch_bounds__(KS_THREADS) void k_ksum_mixed(int ncl, const int* __restrict__ cl_start,
-                                                           const int* __restrict__ src_off,
-                                                           const double* __restrict__ centers,
-                                                           const float4* __restrict__ src,
-                                                           const float4* __restrict__ bdat, int64_t Nt,
-                                                           const int* __restrict__ tgt_body,
-                                                           const int* __restrict__ slot_of,
-                                                           const double* __restrict__ X, int clusters_per_split,
-                                                           int mode, const int* __restrict__ nbr_off,
-                                                           const int* __restrict__ nbr_list, double scale,
-                                                           double* __restrict__ out,
-                                                           const float2* __restrict__ mp,
-                                                           const double* __restrict__ ccent,
-                                                           const float* __restrict__ crad2,
-                                                           const float2* __restrict__ cmp,
-                                                           const int* __restrict__ tperm,
-                                                           unsigned long long* __restrict__ work,
-                                                           const double2* __restrict__ cm64) {
-  __shared__ float4 s_src[KS_TILE];    // (y_x, y_y, sigma_x, sigma_y), y relative to the disk centre
-  __shared__ float s_w[KS_TILE];       // y . sigma
-  __shared__ double s_c[2 * KS_MAXB];
-  __shared__ float4 s_b[KS_MAXB];
-  __shared__ int s_off[KS_MAXB + 1];
-  __shared__ float2 s_mp[KS_MAXB * kMpCoef];   // far-field coefficients of the tile's disks
-  const int split = blockIdx.y;
-  const int q0 = min(ncl, split * clusters_per_split);
-  const int q1 = min(ncl, q0 + clusters_per_split);
-  int64_t t[T];    // position in the visiting order
-  int64_t tt[T];   // the target there
-  int bt[T];   // the target's disk, in slot order
-  double x[T], y[T], ax[T], ay[T];
-  Skip sk[T];
-  unsigned n_dir = 0, n_dexp = 0, n_cexp = 0, n_m2l = 0, n_l2p = 0;   // this lane's work
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
-    t[j] = (int64_t)blockIdx.x * (KS_THREADS * T) + threadIdx.x * T + j;   // a wave: 64 T consecutive targets
-    const int64_t tc = t[j] < Nt ? t[j] : Nt - 1;
-    tt[j] = tperm ? tperm[tc] : tc;
-    const int body = tgt_body[tt[j]];
-    bt[j] = slot_of[body];
-    x[j] = X[2 * tt[j]];
-    y[j] = X[2 * tt[j] + 1];
-    ax[j] = 0.0;
-    ay[j] = 0.0;
-    skip_init(sk[j], mode, body, cl_start[q0], nbr_off, nbr_list);
-  }
-  // The workgroup's targets lie within rb of (bx, by) (their bounding box).  A cluster beyond
-  // le_far of it goes into the workgroup's local expansion (one wave translates it); one
-  // beyond 4 R + rb only is far for every thread: all take its expansion, with no per-thread
-  // test and no barrier.  The cluster radii are large enough that such a cluster holds no
-  // target's disk and no contact partner (cluster construction).
-  __shared__ double s_bb[4][KS_THREADS / 64];
-  __shared__ double2 s_row[KS_THREADS / 64][64];   // per wave: scaled moments; then the wave's expansion
-  __shared__ double2 s_le[64];
-  double bx, by, rb;
-  target_bounds<T>(x, y, s_bb, bx, by, rb);
-  const int wid = threadIdx.x >> 6;
-  double Lr = 0.0, Li = 0.0;   // this lane's coefficient of the wave's local expansion
-  bool le_used = false;         // uniform over the workgroup
-  const float kHalfLn2 = 0.34657359027997264f;
-  for (int cq = q0; cq < q1; ++cq) {
-    const int kt = cl_start[cq], ke = cl_start[cq + 1];
-    const int nb = ke - kt;
-    if (cm64 && le_far(ccent[2 * cq], ccent[2 * cq + 1], sqrt((double)crad2[cq]), bx, by, rb, kLocSep32)) {
-      if ((cq & (KS_THREADS / 64 - 1)) == wid) {
-        m2l_add<kLoc32, kLoc32>(cm64 + (int64_t)cq * kCl64CoefPerCluster, ccent[2 * cq], ccent[2 * cq + 1], bx, by, s_row[wid],
-                                Lr, Li);
-        n_m2l += (threadIdx.x & 63) == 0;
-      }
-      le_used = true;
-      continue;
-    }
-    bool cfar = cmp != nullptr;
-    bool bfar = false;
-    if (cfar) {
-      const double cx = ccent[2 * cq], cy = ccent[2 * cq + 1];
-      const float rf = kClFar2 * crad2[cq];
-      {
-        const double dx = cx - bx, dy = cy - by;
-        const double thr = 4.0 * (1.0 + 1e-6) * sqrt((double)crad2[cq]) + rb;
-        bfar = dx * dx + dy * dy > thr * thr;
-      }
-      float Zx[T], Zy[T], R2[T];
-#pragma unroll
-      for (int j = 0; j < T; ++j) {
-        Zx[j] = (float)(x[j] - cx);
-        Zy[j] = (float)(y[j] - cy);
-        R2[j] = fmaf(Zx[j], Zx[j], Zy[j] * Zy[j]);
-        cfar = cfar && R2[j] > rf && (mode == 0 || bt[j] < kt || bt[j] >= ke) && (mode != 2 || sk[j].next >= ke);
-      }
-      // one decision per wave: a wave whose lanes disagree takes the disks (near path) on
-      // every lane rather than executing both paths
-      cfar = bfar || __all(cfar);
-      if (cfar) {
-        ++n_cexp;
-        // Horner over the cluster's series: h1 over zeta (A_k/2k), h2 over conj(zeta) (B_k/2k),
-        // h3 over conj(zeta) (conj A_k), h4 over conj(zeta) (conj D_k)
-        const float2* cf = cmp + (int64_t)cq * kClCoef;
-        float zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T], h4r[T], h4i[T];
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-          const float ir2 = __builtin_amdgcn_rcpf(R2[j]);
-          zr[j] = Zx[j] * ir2;
-          zi[j] = Zy[j] * ir2;
-          h1r[j] = cf[kClOrder - 1].x;
-          h1i[j] = cf[kClOrder - 1].y;
-          h2r[j] = cf[2 * kClOrder - 1].x;
-          h2i[j] = cf[2 * kClOrder - 1].y;
-          h3r[j] = cf[3 * kClOrder].x;
-          h3i[j] = cf[3 * kClOrder].y;
-          h4r[j] = cf[4 * kClOrder + 1].x;
-          h4i[j] = cf[4 * kClOrder + 1].y;
-        }
-#pragma unroll
-        for (int k = kClOrder - 1; k >= 1; --k) {
-          const float2 a = cf[k - 1], bq = cf[kClOrder + k - 1], g = cf[2 * kClOrder + k], e = cf[3 * kClOrder + 1 + k];
-#pragma unroll
-          for (int j = 0; j < T; ++j) {
-            const float t1r = fmaf(zr[j], h1r[j], fmaf(zi[j], h1i[j], a.x));
-            const float t1i = fmaf(zr[j], h1i[j], fmaf(-zi[j], h1r[j], a.y));
-            const float t2r = fmaf(zr[j], h2r[j], fmaf(-zi[j], h2i[j], bq.x));
-            const float t2i = fmaf(zr[j], h2i[j], fmaf(zi[j], h2r[j], bq.y));
-            const float t3r = fmaf(zr[j], h3r[j], fmaf(-zi[j], h3i[j], g.x));
-            const float t3i = fmaf(zr[j], h3i[j], fmaf(zi[j], h3r[j], g.y));
-            const float t4r = fmaf(zr[j], h4r[j], fmaf(-zi[j], h4i[j], e.x));
-            const float t4i = fmaf(zr[j], h4i[j], fmaf(zi[j], h4r[j], e.y));
-            h1r[j] = t1r;
-            h1i[j] = t1i;
-            h2r[j] = t2r;
-            h2i[j] = t2i;
-            h3r[j] = t3r;
-            h3i[j] = t3i;
-            h4r[j] = t4r;
-            h4i[j] = t4i;
-          }
-        }
-        const float2 g0 = cf[2 * kClOrder], e0 = cf[3 * kClOrder + 1];
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-          // P = conj(A_0) + conj(zeta) h3, Q = conj(D_0) + conj(zeta) h4, zeta h1, conj(zeta) h2
-          const float pr = fmaf(zr[j], h3r[j], fmaf(-zi[j], h3i[j], g0.x));
-          const float pi = fmaf(zr[j], h3i[j], fmaf(zi[j], h3r[j], g0.y));
-          const float qr = fmaf(zr[j], h4r[j], fmaf(-zi[j], h4i[j], e0.x));
-          const float qi = fmaf(zr[j], h4i[j], fmaf(zi[j], h4r[j], e0.y));
-          const float p1r = fmaf(zr[j], h1r[j], zi[j] * h1i[j]);
-          const float p1i = fmaf(zr[j], h1i[j], -zi[j] * h1r[j]);
-          const float p2r = fmaf(zr[j], h2r[j], -zi[j] * h2i[j]);
-          const float p2i = fmaf(zr[j], h2i[j], zi[j] * h2r[j]);
-          // conj(zeta)/2 (Z P - Q)
-          const float mr = fmaf(Zx[j], pr, fmaf(-Zy[j], pi, -qr));
-          const float mi = fmaf(Zx[j], pi, fmaf(Zy[j], pr, -qi));
-          const float t3r = 0.5f * fmaf(zr[j], mr, -zi[j] * mi);
-          const float t3i = 0.5f * fmaf(zr[j], mi, zi[j] * mr);
-          // -S0 ln|Z| + S0 / 2, S0 = conj(g0)
-          const float lZ = fmaf(-kHalfLn2, __builtin_amdgcn_logf(R2[j]), 0.5f);
-          ax[j] += (double)fmaf(g0.x, lZ, p1r + p2r + t3r);
-          ay[j] += (double)fmaf(-g0.y, lZ, p1i + p2i + t3i);
-        }
-      }
-    }
-    // every thread far: the tile is not needed.  The barrier also ends the reads of the
-    // previous tile before this one is staged (bfar is uniform over the workgroup).
-    if (bfar) continue;
-    if (__syncthreads_and(cfar ? 1 : 0)) continue;
-    const int s0 = src_off[kt];
-    const int ns = src_off[ke] - s0;
-    for (int q = threadIdx.x; q < ns; q += KS_THREADS) {
-      const float4 v = src[s0 + q];
-      s_src[q] = v;
-      s_w[q] = fmaf(v.x, v.z, v.y * v.w);
-    }
-    for (int q = threadIdx.x; q < nb; q += KS_THREADS) {
-      s_c[2 * q] = centers[2 * (kt + q)];
-      s_c[2 * q + 1] = centers[2 * (kt + q) + 1];
-      s_b[q] = bdat[kt + q];
-    }
-    for (int q = threadIdx.x; q <= nb; q += KS_THREADS) s_off[q] = src_off[kt + q] - s0;
-    for (int q = threadIdx.x; q < nb * kMpCoef; q += KS_THREADS) s_mp[q] = mp[(int64_t)kt * kMpCoef + q];
-    __syncthreads();
-    if (cfar) continue;
-    for (int kk = 0; kk < nb; ++kk) {
-      const int kbody = kt + kk;
-      const float4 bd = s_b[kk];   // (S0x, S0y, q = |y|^2, W = sum y . sigma)
-      {
-        // far disk for every target of this thread: its multipole expansion (see k_gather_project)
-        float Zx[T], Zy[T], R2[T];
-        bool far = true;
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-          Zx[j] = (float)(x[j] - s_c[2 * kk]);
-          Zy[j] = (float)(y[j] - s_c[2 * kk + 1]);
-          R2[j] = fmaf(Zx[j], Zx[j], Zy[j] * Zy[j]);
-          far = far && R2[j] > kMpFar2 * bd.z;
-        }
-        if (__all(far)) {   // one decision per wave, as for the clusters
-          ++n_dexp;
-          const float2* cf = s_mp + kk * kMpCoef;
-          float zr[T], zi[T], h1r[T], h1i[T], h2r[T], h2i[T], h3r[T], h3i[T];
-#pragma unroll
-          for (int j = 0; j < T; ++j) {
-            const float ir2 = __builtin_amdgcn_rcpf(R2[j]);
-            zr[j] = Zx[j] * ir2;    // zeta = conj(Z) / R^2 = (zr, -zi); conj(zeta) = (zr, zi)
-            zi[j] = Zy[j] * ir2;
-            h1r[j] = cf[kMpOrder - 1].x;
-            h1i[j] = cf[kMpOrder - 1].y;
-            h2r[j] = cf[2 * kMpOrder - 1].x;
-            h2i[j] = cf[2 * kMpOrder - 1].y;
-            h3r[j] = cf[3 * kMpOrder].x;
-            h3i[j] = cf[3 * kMpOrder].y;
-          }
-          // Horner: h1 over zeta (A_k/2k), h2 over conj(zeta) (B_k/2k), h3 over conj(zeta) (conj A_k)
-#pragma unroll
-          for (int k = kMpOrder - 1; k >= 1; --k) {
-            const float2 a = cf[k - 1], bq = cf[kMpOrder + k - 1], g = cf[2 * kMpOrder + k];
-#pragma unroll
-            for (int j = 0; j < T; ++j) {
-              const float t1r = fmaf(zr[j], h1r[j], fmaf(zi[j], h1i[j], a.x));
-              const float t1i = fmaf(zr[j], h1i[j], fmaf(-zi[j], h1r[j], a.y));
-              const float t2r = fmaf(zr[j], h2r[j], fmaf(-zi[j], h2i[j], bq.x));
-              const float t2i = fmaf(zr[j], h2i[j], fmaf(zi[j], h2r[j], bq.y));
-              const float t3r = fmaf(zr[j], h3r[j], fmaf(-zi[j], h3i[j], g.x));
-              const float t3i = fmaf(zr[j], h3i[j], fmaf(zi[j], h3r[j], g.y));
-              h1r[j] = t1r;
-              h1i[j] = t1i;
-              h2r[j] = t2r;
-              h2i[j] = t2i;
-              h3r[j] = t3r;
-              h3i[j] = t3i;
-            }
-          }
-          const float2 g0 = cf[2 * kMpOrder], dl = cf[3 * kMpOrder + 1];
-#pragma unroll
-          for (int j = 0; j < T; ++j) {
-            // P3 = conj(A_0) + conj(zeta) h3; P1 = zeta h1; P2 = conj(zeta) h2
-            const float p3r = fmaf(zr[j], h3r[j], fmaf(-zi[j], h3i[j], g0.x));
-            const float p3i = fmaf(zr[j], h3i[j], fmaf(zi[j], h3r[j], g0.y));
-            const float p1r = fmaf(zr[j], h1r[j], zi[j] * h1i[j]);
-            const float p1i = fmaf(zr[j], h1i[j], -zi[j] * h1r[j]);
-            const float p2r = fmaf(zr[j], h2r[j], -zi[j] * h2i[j]);
-            const float p2i = fmaf(zr[j], h2i[j], zi[j] * h2r[j]);
-            // conj(zeta)/2 [(Z - rho^2 conj(zeta)) P3 - conj(B_1)], Z - rho^2 conj(zeta) = Z (1 - q / R^2)
-            const float f = fmaf(-bd.z, zr[j] * zr[j] + zi[j] * zi[j], 1.0f);
-            const float mr = f * fmaf(Zx[j], p3r, -Zy[j] * p3i) - dl.x;
-            const float mi = f * fmaf(Zx[j], p3i, Zy[j] * p3r) - dl.y;
-            const float t3r = 0.5f * fmaf(zr[j], mr, -zi[j] * mi);
-            const float t3i = 0.5f * fmaf(zr[j], mi, zi[j] * mr);
-            // -S0 ln|Z| + S0 / 2
-            const float lZ = fmaf(-kHalfLn2, __builtin_amdgcn_logf(R2[j]), 0.5f);
-            const float fx = fmaf(bd.x, lZ, p1r + p2r + t3r);
-            const float fy = fmaf(bd.y, lZ, p1i + p2i + t3i);
-            if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
-              ax[j] += (double)fx;
-              ay[j] += (double)fy;
-            }
-          }
-          continue;
-        }
-      }
-      // per (target, disk): D = x - c_k (FP64, rounded once), R^2 = |D|^2, and the
-      // scaled offsets for w = r^2 / R^2 - 1 = (q - 2 D.y) / R^2
-      float Dx[T], Dy[T], ir2[T], Dxs[T], Dys[T], qs[T], lx[T], ly[T], t0[T], tsx[T], tsy[T];
-#pragma unroll
-      for (int j = 0; j < T; ++j) {
-        Dx[j] = (float)(x[j] - s_c[2 * kk]);
-        Dy[j] = (float)(y[j] - s_c[2 * kk + 1]);
-        ir2[j] = __builtin_amdgcn_rcpf(fmaf(Dx[j], Dx[j], Dy[j] * Dy[j]));
-        Dxs[j] = -2.0f * Dx[j] * ir2[j];
-        Dys[j] = -2.0f * Dy[j] * ir2[j];
-        qs[j] = bd.z * ir2[j];
-        lx[j] = ly[j] = t0[j] = tsx[j] = tsy[j] = 0.0f;
-      }
-      const int q1 = s_off[kk + 1];
-      n_dir += q1 - s_off[kk];
-#pragma unroll 4
-      for (int q = s_off[kk]; q < q1; ++q) {
-        const float4 s = s_src[q];
-        const float wq = s_w[q];
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-          // u = 1 + w = r^2 / R^2.  For a far disk w is small and u = fl(1 + w) loses
-          // the low bits of w: e = w - (u - 1) is that rounding error (exact for
-          // |w| <= 1), and log2(1 + w) = log2(u) + e / (u ln 2) + O(e^2), with the
-          // factor 1/u ~ 1 dropped (an error of e w, below the rounding of log2(u))
-          const float w = fmaf(Dxs[j], s.x, fmaf(Dys[j], s.y, qs[j]));
-          const float u = 1.0f + w;
-          const float e = w - (u - 1.0f);
-          const float lg = fmaf(e, 1.44269504088896341f, __builtin_amdgcn_logf(u));
-          const float iu = __builtin_amdgcn_rcpf(u);
-          const float tt = fmaf(Dx[j], s.z, fmaf(Dy[j], s.w, -wq)) * iu;   // R^2 (d.sigma) / r^2
-          lx[j] = fmaf(lg, s.z, lx[j]);
-          ly[j] = fmaf(lg, s.w, ly[j]);
-          t0[j] = fmaf(tt, w, t0[j]);
-          tsx[j] = fmaf(tt, s.x, tsx[j]);
-          tsy[j] = fmaf(tt, s.y, tsy[j]);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < T; ++j) {
-        if (!skip_test(sk[j], mode, kbody, bt[j], nbr_list)) {
-          // sum_s (d.sigma) d / r^2 = (D sum_s t_s - sum_s t_s y_s) / R^2 with
-          // t_s = R^2 (d_s.sigma_s) / r_s^2 = a_s / u_s, a_s = D.sigma_s - y_s.sigma_s.
-          // sum_s a_s / u_s = sum_s a_s - sum_s a_s w_s / u_s = D.S0 - W - sum_s t_s w_s:
-          // the leading part comes from the disk's FP64 moments and the FP32 loop
-          // only sums the remainder, which shrinks with the distance like the field
-          const float T0 = fmaf(Dx[j], bd.x, fmaf(Dy[j], bd.y, -bd.w)) - t0[j];
-          const float tx = ir2[j] * fmaf(Dx[j], T0, -tsx[j]);
-          const float ty = ir2[j] * fmaf(Dy[j], T0, -tsy[j]);
-          // sum_s sigma_s ln r_s^2 = S0 ln R^2 + sum_s sigma_s ln u_s
-          const float lR = __builtin_amdgcn_logf(fmaf(Dx[j], Dx[j], Dy[j] * Dy[j]));
-          ax[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.x, lx[j]), tx);
-          ay[j] += (double)fmaf(-kHalfLn2, fmaf(lR, bd.y, ly[j]), ty);
-        }
-      }
-    }
-  }
-  if (le_used) {
-    // the workgroup's local expansion at every target (FP64)
-    __syncthreads();   // the last tile's reads of LDS are done
-    le_reduce<kLoc32>(Lr, Li, s_row, s_le);
-#pragma unroll
-    for (int j = 0; j < T; ++j) {
-      double ux, uy;
-      l2p<kLoc32>(s_le, x[j] - bx, y[j] - by, ux, uy);
-      ax[j] += ux;
-      ay[j] += uy;
-    }
-    n_l2p = T;
-  }
-  add_work(work, T * n_dir, T * n_dexp, T * n_cexp, n_m2l, n_l2p);
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
-    if (t[j] < Nt) {
-      out[((int64_t)split * Nt + tt[j]) * 2] = ax[j] * scale;
-      out[((int64_t)split * Nt + tt[j]) * 2 + 1] = ay[j] * scale;
-    }
-  }
-}
-
 // FP64 far-field coefficients of a packed FP64 source array (the expansion of
 // k_gather_project to order kMp64Order): per disk A_k/(2k) (k = 1..p), B_k/(2k) (k = 1..p),
 // conj(A_k) (k = 0..p), conj(B_1) and (rho^2, 0).  The offsets w are the class ring Yr
@@ -1118,16 +581,14 @@ __global__ __launch_bounds__(kBodyThreads) void k_moments64(int P, const int* __
   }
 }
 
-// FP64 form of the same sum, absolute coordinates (ln_f64, rcp_f64 above).
-// FP64 expansion of each cluster about its centre: the moments of k_cluster_moments (A_k,
-// B_k, D_k of the sources' offsets w = y - C) to order kCl64Order, from a packed FP64 source
-// array (src: absolute positions and strengths, body order) or, with src NULL, from the FP64
-// strengths sig64 on the disks' rings (the mixed sum's packing).  They serve the FP64 sum's
-// per-target cluster expansions and both sums' local expansions.  One workgroup per cluster,
-// thread e forms the order-e moments over the cluster's sources in slot order (w^e by binary
-// powering).  Record (after the per-disk records): A_k/(2k), B_k/(2k) (k = 1..p), conj(A_k),
-// conj(D_k) (k = 0..p).  Truncation at theta <= 1/4: below sum |sigma| 4^-31 / (3/4) = 3e-19
-// sum |sigma|.
+// FP64 expansion of each cluster about its centre C: the moments A_k = sum sigma w^k,
+// B_k = sum sigma conj(w)^k and D_k = sum sigma conj(w) w^k of the sources' offsets w = y - C,
+// to order kCl64Order, from a packed FP64 source array (src: absolute positions and strengths,
+// body order).  They serve the two-level sum's per-target cluster expansions and its local
+// expansions.  One workgroup per cluster, thread e forms the order-e moments over the
+// cluster's sources in slot order (w^e by binary powering).  Record: A_k/(2k), B_k/(2k)
+// (k = 1..p), conj(A_k), conj(D_k) (k = 0..p).  Truncation at theta <= 1/4: below
+// sum |sigma| 4^-27 / (3/4) = 7e-17 sum |sigma|.
 constexpr int kCl64Coef = kCl64CoefPerCluster;
 
 __global__ __launch_bounds__(64) void k_cluster_moments64(int ncl, const int* __restrict__ cl_start,
@@ -1135,10 +596,7 @@ __global__ __launch_bounds__(64) void k_cluster_moments64(int ncl, const int* __
                                                           const int* __restrict__ src_off,
                                                           const double* __restrict__ ccent,
                                                           const double4* __restrict__ src,
-                                                          double2* __restrict__ cmp,
-                                                          const double* __restrict__ sig64,
-                                                          const int* __restrict__ cls, ClassTab ct,
-                                                          const double* __restrict__ centers) {
+                                                          double2* __restrict__ cmp) {
   const int q = blockIdx.x;
   const int e = threadIdx.x;
   if (q >= ncl || e > kCl64Order) return;
@@ -1146,21 +604,9 @@ __global__ __launch_bounds__(64) void k_cluster_moments64(int ncl, const int* __
   double Ar = 0, Ai = 0, Br = 0, Bi = 0, Dr = 0, Di = 0;
   for (int sl = cl_start[q]; sl < cl_start[q + 1]; ++sl) {
     const int b = slot_body[sl];
-    const double ox = src ? 0.0 : centers[2 * b] - Cx, oy = src ? 0.0 : centers[2 * b + 1] - Cy;
-    const double* Yr = src ? nullptr : ct.Yr[cls[b]];
     for (int j = src_off[b]; j < src_off[b + 1]; ++j) {
-      double4 v;
-      double wx, wy;
-      if (src) {
-        v = src[j];
-        wx = v.x - Cx;
-        wy = v.y - Cy;
-      } else {
-        const int jj = j - src_off[b];
-        wx = ox + Yr[2 * jj];
-        wy = oy + Yr[2 * jj + 1];
-        v = make_double4(0.0, 0.0, sig64[2 * j], sig64[2 * j + 1]);
-      }
+      const double4 v = src[j];
+      const double wx = v.x - Cx, wy = v.y - Cy;
       double pr = 1.0, pi = 0.0, br = wx, bi = wy;   // w^e
       for (int k = e; k; k >>= 1) {
         if (k & 1) {
@@ -1205,7 +651,7 @@ __device__ __forceinline__ bool cl_far64(const double (&x)[T], const double (&y)
 }
 
 // A cluster's FP64 expansion (record cf, centre cx, cy; k_cluster_moments64) added at a thread's
-// targets: four complex Horner series of degree kCl64Order, as in the FP32 sum
+// targets: four complex Horner series of degree kCl64Order
 template <int T>
 __device__ __forceinline__ void cluster_expansion64(const double2* __restrict__ cf, double cx, double cy,
                                                     const double (&x)[T], const double (&y)[T], double (&ax)[T],
@@ -1272,15 +718,16 @@ __device__ __forceinline__ void cluster_expansion64(const double2* __restrict__ 
   }
 }
 
-// FP64 form of the sum, absolute coordinates (ln_f64, rcp_f64 above), with the FP32 sum's
-// structure: the split's clusters one LDS tile each, in slot order.  A cluster far from the
+// Two-level FP64 sum at arbitrary points (flow evaluation; the context's own kernel sum is the
+// hierarchical k_ksum_fmm below), absolute coordinates (ln_f64, rcp_f64 above): the split's
+// clusters one LDS tile each, in slot order.  A cluster far from the
 // workgroup (le_far) goes into its local expansion; one beyond 4 cluster radii from every
 // target of a wave is summed by that wave from its FP64 expansion (order kCl64Order); the
 // tile of a cluster that every wave takes that way is not staged.  Otherwise each disk of the
 // cluster is summed from its FP64 expansion (k_moments64, order kMp64Order) by a wave whose
 // targets are all beyond 7 ring radii, else directly over its sources.  src: FP64 packed
 // sources in body order (src_off); ssrc_off: the same counts in slot order.  Skip modes as in
-// k_ksum_mixed (partner lists in slots); mode 0 reads no body index (flow-evaluation points
+// k_ksum_fmm (partner lists in slots); mode 0 reads no body index (flow-evaluation points
 // may have body -1).  mp64 NULL: every disk direct; cmp64 NULL: no cluster expansions.
 template <int T>
 __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int ncl, const int* __restrict__ cl_start,
@@ -1377,7 +824,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int ncl, const int* __
       const int kslot = kt + kk;
       const int kbody = slot_body[kslot];
       if (mp64) {
-        // far disk for every target of this wave: its FP64 expansion (the FP32 sum's series
+        // far disk for every target of this wave: its FP64 expansion (three complex series
         // to order kMp64Order)
         const double2* cf = mp64 + (int64_t)kbody * kMp64Coef;
         const double q = cf[3 * kMp64Order + 2].x;
@@ -2664,27 +2111,15 @@ void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil) {
 void launch_gather_project(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
                            bool pack32, bool pack64, const FmmRec* fr) {
   (void)pack64;
-  launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, nullptr, c->d_src64, nullptr);
+  launch_gather_project_to(c, prob, lam_bar, ltil, with_pairs, c->d_src64);
   launch_fmm_records(c, prob, c->d_src64, fr ? *fr : fmm_records(c, 0), pack32);
 }
 
 void launch_gather_project_to(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, bool with_pairs,
-                              float4* sig32, double4* src64, float4* bdat, float2* mp, float2* cmp, double2* cm64) {
-  // the cluster moments read the FP64 strengths from d_sig64
+                              double4* src64) {
   hipLaunchKernelGGL(k_gather_project, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P,
                      prob == MFS_MOBILITY ? 1 : 0, c->d_cls, c->d_src_off, c->ct[prob], c->d_bp_off, c->d_bp_list,
-                     c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers,
-                     (cmp || cm64) ? c->d_sig64 : (double*)nullptr, sig32, src64, bdat, mp, c->d_slot_of,
-                     c->d_ssrc_off);
-  if (cmp)
-    hipLaunchKernelGGL(k_cluster_moments, dim3(c->ncl), dim3(kBodyThreads), 0, c->stream, c->ncl, c->d_cl_start,
-                       c->d_slot_body, c->d_cls, c->d_src_off, c->ct[prob], c->d_centers, c->d_ccent, c->d_sig64,
-                       cmp);
-  // FP64 cluster records for the workgroups' local expansions of the FP32 sum
-  if (cm64)
-    hipLaunchKernelGGL(k_cluster_moments64, dim3(c->ncl), dim3(64), 0, c->stream, c->ncl, c->d_cl_start,
-                       c->d_slot_body, c->d_src_off, c->d_ccent, (const double4*)nullptr, cm64, c->d_sig64, c->d_cls,
-                       c->ct[prob], c->d_centers);
+                     c->d_pairs, c->d_xoff, ltil, lam_bar, with_pairs ? 1 : 0, c->d_centers, src64);
 }
 
 bool launch_pair_A_rhs(mfs_ctx* c, int prob, int R, const double* lam_bar, int64_t lam_stride, double* ltil,
@@ -2725,9 +2160,6 @@ static int ksum_targets_per_thread(bool mixed) {
   return t == 1 || t == 2 || t == 4 ? t : 2;
 }
 
-static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
-                                     const float2* mp, const float2* cmp, const double2* cm64, double* u,
-                                     double scale, const SplitBuf* sb = nullptr);
 static bool launch_ksum_fp64_arrays(mfs_ctx* c, int mode, const double4* src, const double2* mp64, int64_t Nt,
                                     const double* X, const int32_t* tgt_body, const int32_t* tperm, double* u,
                                     double scale, const SplitBuf* sb = nullptr);
@@ -2760,42 +2192,11 @@ bool launch_kernel_sum_rhs(mfs_ctx* c, bool mixed, int mode, int R, double* u, d
   return true;
 }
 
-// One FP32 kernel sum on explicit packed arrays (sources, disk moments, expansion
-// coefficients); see launch_kernel_sum.
 // MFS_KSUM_LOCAL=0 turns the workgroups' local expansions off (every far cluster is then
-// evaluated per target from its expansion, as with the switch MFS_KSUM_CLUSTERS for disks)
+// evaluated per target from its expansion)
 static bool local_expansions_on() {
   const char* e = std::getenv("MFS_KSUM_LOCAL");
   return !(e && std::atoi(e) == 0);
-}
-
-static bool launch_ksum_mixed_arrays(mfs_ctx* c, int mode, const float4* sig32, const float4* bdat,
-                                     const float2* mp, const float2* cmp, const double2* cm64, double* u,
-                                     double scale, const SplitBuf* sb) {
-  const int T = ksum_targets_per_thread(true);
-  const int64_t Nt = c->Nt;
-  const int64_t tblocks = (Nt + KS_THREADS * T - 1) / (KS_THREADS * T);
-  const int ns = std::min(ksum_splits(tblocks, c->P), c->ncl);
-  const int cps = (c->ncl + ns - 1) / ns;
-  const char* ev = std::getenv("MFS_KSUM_CLUSTERS");
-  if (ev && std::atoi(ev) == 0) {
-    cmp = nullptr;
-    cm64 = nullptr;
-  }
-  if (!local_expansions_on()) cm64 = nullptr;
-  double* out = u;
-  if (ns > 1 && !(out = split_buffer(c, (int64_t)ns * Nt * 2, sb))) return false;
-  dim3 grid((unsigned)tblocks, (unsigned)ns);
-#define MFS_KS_MIXED(TT)                                                                                         \
-  hipLaunchKernelGGL(k_ksum_mixed<TT>, grid, dim3(KS_THREADS), 0, c->stream, c->ncl, c->d_cl_start,          \
-                     c->d_ssrc_off, c->d_scent, sig32, bdat, Nt, c->d_tgt_body, c->d_slot_of, c->d_X, cps, mode,  \
-                     c->d_nbr_off, c->d_nbr_slot, scale, out, mp, c->d_ccent, c->d_crad2, cmp, c->d_tperm,        \
-                     c->d_work, cm64)
-  if (T == 4) MFS_KS_MIXED(4); else if (T == 1) MFS_KS_MIXED(1); else MFS_KS_MIXED(2);
-#undef MFS_KS_MIXED
-  if (ns > 1)
-    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(2 * Nt, 256)), dim3(256), 0, c->stream, 2 * Nt, ns, out, u);
-  return true;
 }
 
 // FP64 kernel sum of a packed source array at Nt points X (mode as in k_ksum_fp64); mp64: the
@@ -2879,6 +2280,10 @@ void launch_fmm_records(mfs_ctx* c, int prob, const double4* src64, const FmmRec
 void launch_ksum_fmm(mfs_ctx* c, bool mixed, int mode, const double4* src64, const FmmRec& fr, double* u,
                      double scale) {
   const FmmLists& L = c->fl[mixed ? 1 : 0];
+  if (c->nwave == 0) return;
+  // one workgroup per wave, in curve order: the hardware deals consecutive workgroups to the 8
+  // XCDs in turn, which spreads the waves with long lists evenly (giving each XCD a contiguous
+  // run of the curve instead, so that neighbouring waves share an L2, was 5-7% slower)
 #define MFS_KS_FMM(MX, RINGS)                                                                                    \
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ksum_fmm<MX, kFmmT>), dim3(c->nwave), dim3(64), 0, c->stream,             \
                      c->d_wstart, c->d_tperm, c->d_tgt_body, c->d_slot_of, c->d_X, c->d_src_off, src64, L.d_m2l_off, L.d_m2l,  \
@@ -2982,8 +2387,7 @@ void launch_moments64(mfs_ctx* c, const double4* src64, double2* mp64) {
   hipLaunchKernelGGL(k_moments64, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
                      c->ct[0], src64, mp64);
   hipLaunchKernelGGL(k_cluster_moments64, dim3(c->ncl), dim3(64), 0, c->stream, c->ncl, c->d_cl_start,
-                     c->d_slot_body, c->d_src_off, c->d_ccent, src64, mp64 + (int64_t)c->P * kMp64Coef,
-                     (const double*)nullptr, (const int*)nullptr, c->ct[0], (const double*)nullptr);
+                     c->d_slot_body, c->d_src_off, c->d_ccent, src64, mp64 + (int64_t)c->P * kMp64Coef);
 }
 
 void launch_fine_strengths(mfs_ctx* c, int prob, const double* lam_bar, const double* ltil, double* ptil,

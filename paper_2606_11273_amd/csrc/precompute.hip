@@ -908,11 +908,17 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       MFS_HIP(dU.alloc(c, sizeof(double) * mh * mnh * nbs));
       MFS_HIP(dVT.alloc(c, sizeof(double) * mnh * nh * nbs));
       MFS_HIP(dE.alloc(c, sizeof(double) * mnh * nbs));
+      tick(7, t0);
       MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mh,
                                               (int)nh, (double*)dFs.p, (int)mh, mh * nh, (double*)dSF.p, mnh,
                                               (double*)dU.p, (int)mh, mh * mnh, (double*)dVT.p, (int)mnh, mnh * nh,
                                               (double*)dE.p, mnh, rocblas_outofplace, (int*)dinfo.p, nbs));
-      tick(2, t0);
+      if (prof) {
+        const double before = tstage[2];
+        tick(2, t0);
+        std::fprintf(stderr, "[mfs precompute] split gesvd %lld x %lld, %d matrices: %.3f s\n", (long long)mh,
+                     (long long)nh, nbs, tstage[2] - before);
+      }
       MFS_HIP(dT1.alloc(c, sizeof(double) * mnh * nx * nbs));
       MFS_HIP(dGs.alloc(c, sizeof(double) * nh * nx * nbs));
       MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnh,
@@ -1071,8 +1077,9 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     b0 += nb;
   }
   if (prof)
-    std::fprintf(stderr, "[mfs precompute] pairs %d: host+upload %.3fs fill %.3fs svdF %.3fs gemm %.3fs svdC %.3fs rest %.3fs\n",
-                 C, tstage[0], tstage[1], tstage[2], tstage[3], tstage[4], tstage[5]);
+    std::fprintf(stderr, "[mfs precompute] pairs %d: host+upload %.3fs fill %.3fs split %.3fs svdF %.3fs gemm %.3fs "
+                 "svdC %.3fs rest %.3fs\n",
+                 C, tstage[0], tstage[1], tstage[7], tstage[2], tstage[3], tstage[4], tstage[5]);
   if (keep) {
     auto up = [&](void** dst, const void* src, size_t bytes) -> Status {
       MFS_HIP(dev_malloc(c, dst, std::max<size_t>(bytes, 8)));

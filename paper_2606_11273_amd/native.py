@@ -249,7 +249,8 @@ def mfs_get_pairs(ctx):
 
 
 def mfs_get_clusters(ctx):
-    """The FP32 kernel sum's disk order and clusters: dict of slot_body (P), cl_start
+    """The kernel sums' disk order (slots) and the clusters of the two-level sum at arbitrary
+    points: dict of slot_body (P), cl_start
     (n_clusters + 1), centre (n_clusters x 2) and radius (n_clusters)."""
     n = C.c_int32()
     _check(lib().mfs_get_clusters(ctx, C.byref(n), None, None, None, None), ctx)

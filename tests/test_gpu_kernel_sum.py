@@ -2,10 +2,10 @@
 
 Tolerances are stated per target relative to the magnitude
 m_t = sum_s (|log r_ts| + 1) |sigma_s| / (4 pi mu), which bounds how rounding in the
-terms can show in u_t: FP64 <= 1e-13 m_t everywhere; mixed (FP32 terms on body-relative
-coordinates, FP64 accumulation over bodies, far disks and clusters from FP64 moments) per
-case at about ten times the error measured on the MI355X (stated beside each bound), so
-that a regression of an order of magnitude fails.
+terms can show in u_t: FP64 <= 1e-13 m_t everywhere; mixed (near disks' ring expansions in
+FP32 from FP64 moments, FP64 accumulation; cell translations, local expansions and direct sums
+in FP64) per case at about ten times the error measured on the MI355X (stated beside each
+bound), so that a regression of an order of magnitude fails.
 """
 
 import numpy as np
@@ -106,9 +106,11 @@ def test_kernel_sum_full_size_sampled():
 
 
 def test_kernel_sum_clusters_mid_size():
-    # P = 600 packing at area fraction 0.5 (about 55 x 55): the FP32 sum takes the clusters
-    # far from a target (beyond 4 cluster radii) from their expansions; 1500 sampled targets
-    # against the oracle, and the clusters are a valid partition of the disks
+    # P = 600 packing at area fraction 0.5 (about 55 x 55), where most of the (target, cell)
+    # pairs are far: the hierarchical sum translates far cells into local expansions and takes
+    # near disks from their ring expansions; 1500 sampled targets against the oracle.  The
+    # clusters of the two-level sum at arbitrary points (mfs_get_clusters) are checked as a
+    # partition of the disks
     from paper_2606_11273_amd import native as nv
     g0 = config_geometry(2, P=600)
     c, a = g0["centers"], g0["radii"]
@@ -149,8 +151,8 @@ def test_kernel_sum_clusters_mid_size():
 def test_kernel_sum_projected_strengths():
     # the strengths the mobility matvec sums: N(0,1) per source, projected by (I - L) per disk
     # so that every disk carries zero net force and torque (Sec. 4.4).  Their fields cancel to
-    # leading order at a distance; the FP32 sum takes each disk's leading parts from FP64
-    # moments, so its error stays relative to the field itself.  Dense-packing generator
+    # leading order at a distance; the mixed sum's ring expansions come from FP64 moments, so
+    # its error stays relative to the field itself.  Dense-packing generator
     # (area fraction 0.65, min gap 1e-3) at P = 1000, 1500 sampled targets, skip mode 2.
     from oracle.onebody import one_body
     g0 = config_geometry(3, P=1000)
