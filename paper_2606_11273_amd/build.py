@@ -27,6 +27,8 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     f"-I{ROCM}/include", f"-I{os.path.join(HERE, '..', 'include')}",
+    # the ROCm library directory the library is built against (its rocSOLVER is resolved there)
+    f"-DMFS_ROCM_LIB=\"{os.path.realpath(os.path.join(ROCM, 'lib'))}\"",
 ]
 
 
@@ -61,7 +63,7 @@ def build(verbose=False):
     objs = [j[-1] for j in jobs]
     tmp = OUT + ".tmp"
     _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, f"-L{ROCM}/lib",
-          "-lrocsolver", "-lrocblas", "-pthread", f"-Wl,-rpath,{ROCM}/lib"])
+          "-lrocsolver", "-lrocblas", "-ldl", "-pthread", f"-Wl,-rpath,{ROCM}/lib"])
     os.replace(tmp, OUT)
     return OUT
 

@@ -15,6 +15,7 @@
 // per disk to a common length (zero columns do not change the truncated pseudoinverse).
 // The paper's fine sets are for unit disks; a disk of radius a gets fine counts scaled by a,
 // the limit point of its two circles and a rolling unit circle for the peanut.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -31,6 +32,41 @@
 #include "internal.h"
 
 namespace mfs {
+
+// The SVD entry points.  A host process may already hold another rocSOLVER under the same soname
+// (PyTorch's wheel bundles its own ROCm libraries and loads them first; the library's
+// dependencies then bind to those, which keeps one HIP runtime per process).  The batched SVD of
+// the rocSOLVER in the ROCm installation this library is built against (MFS_ROCM_LIB) is several
+// times faster at these sizes than older ones, so its two entry points are taken from there,
+// loaded by path; it binds to the process's rocBLAS and HIP runtime like the library itself
+// (same soname majors).  If that file cannot be loaded, or MFS_ROCSOLVER_LINKED=1, the linked
+// rocSOLVER is used.
+#ifndef MFS_ROCM_LIB
+#define MFS_ROCM_LIB "/opt/rocm/lib"
+#endif
+struct SvdEntry {
+  decltype(&rocsolver_dgesvd) gesvd = &rocsolver_dgesvd;
+  decltype(&rocsolver_dgesvd_strided_batched) gesvd_sb = &rocsolver_dgesvd_strided_batched;
+  const char* origin = "linked";
+};
+static const SvdEntry& svd_entry() {
+  static const SvdEntry e = [] {
+    SvdEntry r;
+    const char* lk = std::getenv("MFS_ROCSOLVER_LINKED");
+    if (lk && std::atoi(lk) != 0) return r;
+    void* h = dlopen(MFS_ROCM_LIB "/librocsolver.so.0", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return r;
+    auto a = (decltype(&rocsolver_dgesvd))dlsym(h, "rocsolver_dgesvd");
+    auto b = (decltype(&rocsolver_dgesvd_strided_batched))dlsym(h, "rocsolver_dgesvd_strided_batched");
+    if (a && b) {
+      r.gesvd = a;
+      r.gesvd_sb = b;
+      r.origin = MFS_ROCM_LIB "/librocsolver.so.0";
+    }
+    return r;
+  }();
+  return e;
+}
 
 #define MFS_RB(call)                                                                          \
   do {                                                                                        \
@@ -527,7 +563,7 @@ Status onebody_factors(mfs_ctx* c) {
       MFS_HIP(dE.alloc(c, sizeof(double) * mn));
       MFS_HIP(dInfo.alloc(c, sizeof(int)));
       MFS_HIP(hipMemcpyAsync(dA.p, M.data(), sizeof(double) * m * n, hipMemcpyHostToDevice, c->stream));
-      MFS_RB(rocsolver_dgesvd(c->blas, rocblas_svect_singular, rocblas_svect_singular, m, n, (double*)dA.p, m,
+      MFS_RB(svd_entry().gesvd(c->blas, rocblas_svect_singular, rocblas_svect_singular, m, n, (double*)dA.p, m,
                               (double*)dS.p, (double*)dU.p, m, (double*)dV.p, mn, (double*)dE.p,
                               rocblas_outofplace, (int*)dInfo.p));
       std::vector<double> S(mn), U((size_t)m * mn), VT((size_t)mn * n);
@@ -909,7 +945,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       MFS_HIP(dVT.alloc(c, sizeof(double) * mnh * nh * nbs));
       MFS_HIP(dE.alloc(c, sizeof(double) * mnh * nbs));
       tick(7, t0);
-      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mh,
+      MFS_RB(svd_entry().gesvd_sb(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mh,
                                               (int)nh, (double*)dFs.p, (int)mh, mh * nh, (double*)dSF.p, mnh,
                                               (double*)dU.p, (int)mh, mh * mnh, (double*)dVT.p, (int)mnh, mnh * nh,
                                               (double*)dE.p, mnh, rocblas_outofplace, (int*)dinfo.p, nbs));
@@ -943,7 +979,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       MFS_HIP(dU.alloc(c, sizeof(double) * m * mn * nb));
       MFS_HIP(dVT.alloc(c, sizeof(double) * mn * n * nb));
       MFS_HIP(dE.alloc(c, sizeof(double) * mn * nb));
-      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m, (int)n,
+      MFS_RB(svd_entry().gesvd_sb(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m, (int)n,
                                               (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p, (int)m,
                                               m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
                                               rocblas_outofplace, (int*)dinfo.p, nb));
@@ -1008,7 +1044,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       MFS_HIP(dUC.alloc(c, sizeof(double) * zh * mnc * nbs));
       MFS_HIP(dVTC.alloc(c, sizeof(double) * mnc * nxh * nbs));
       MFS_HIP(dEC.alloc(c, sizeof(double) * mnc * nbs));
-      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)zh,
+      MFS_RB(svd_entry().gesvd_sb(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)zh,
                                               (int)nxh, (double*)dCs.p, (int)zh, zh * nxh, (double*)dSC.p, mnc,
                                               (double*)dUC.p, (int)zh, zh * mnc, (double*)dVTC.p, (int)mnc,
                                               mnc * nxh, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nbs));
@@ -1038,7 +1074,7 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
       MFS_HIP(dUC.alloc(c, sizeof(double) * mpp * mnc * nb));
       MFS_HIP(dVTC.alloc(c, sizeof(double) * mnc * nx * nb));
       MFS_HIP(dEC.alloc(c, sizeof(double) * mnc * nb));
-      MFS_RB(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
+      MFS_RB(svd_entry().gesvd_sb(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mpp,
                                               (int)nx, (double*)dC.p, (int)mpp, d.sC, (double*)dSC.p, mnc,
                                               (double*)dUC.p, (int)mpp, mpp * mnc, (double*)dVTC.p, (int)mnc,
                                               mnc * nx, (double*)dEC.p, mnc, rocblas_outofplace, (int*)dinfoC.p, nb));
@@ -1078,8 +1114,8 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
   }
   if (prof)
     std::fprintf(stderr, "[mfs precompute] pairs %d: host+upload %.3fs fill %.3fs split %.3fs svdF %.3fs gemm %.3fs "
-                 "svdC %.3fs rest %.3fs\n",
-                 C, tstage[0], tstage[1], tstage[7], tstage[2], tstage[3], tstage[4], tstage[5]);
+                 "svdC %.3fs rest %.3fs (rocSOLVER: %s)\n",
+                 C, tstage[0], tstage[1], tstage[7], tstage[2], tstage[3], tstage[4], tstage[5], svd_entry().origin);
   if (keep) {
     auto up = [&](void** dst, const void* src, size_t bytes) -> Status {
       MFS_HIP(dev_malloc(c, dst, std::max<size_t>(bytes, 8)));
