@@ -26,7 +26,7 @@ with zero net force, solved in lockstep).
 --serve runs the serving workload instead: a stream of independent mobility solves
 (P ~ U{50..3000}, area fraction U[0.4, 0.65], min gap 10^U[-4,-2], N(0,1) forces and
 torques) through the continuous-batching server; first a saturated pass (all requests
-queued at once) for solves/s, then a Poisson stream at 0.8 x that rate for the time to
+queued at once; 16 by default) for solves/s, then a Poisson stream (64 requests) at 0.8 x that rate for the time to
 solution (p50, p99).  It prints its own JSON line.
 """
 
@@ -156,7 +156,7 @@ def cpu_baseline(centers, radii, n_src, n_col, r_src, n_targets, sig_seed=1):
     direct_sum(X[tsel], Y, sig, workers=workers, chunk_elems=2_000_000)
     dt = time.perf_counter() - t0
     evals = n_targets * Y.shape[0]
-    return dict(value=evals / dt, unit="pair-evals/s", cores=workers, host_cores=host, kind="oracle",
+    return dict(rate=evals / dt, rate_unit="pair-evals/s", cores=workers, host_cores=host, kind="oracle",
                 sample=f"{n_targets} of {X.shape[0]} targets x {Y.shape[0]} sources of the same packing, "
                        f"FP64 NumPy direct sum in {workers} single-threaded worker processes "
                        f"({host} host cores), {dt:.1f} s")
@@ -182,8 +182,8 @@ def main():
                     help="skip the FP64 reference solve to relative residual 1e-10")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-targets", type=int, default=8000,
-                    help="targets of the CPU oracle sample (all sources; about 60 CPU-seconds)")
+    ap.add_argument("--cpu-targets", type=int, default=24000,
+                    help="targets of the CPU oracle sample (all sources; about 13 s on 16 cores)")
     ap.add_argument("--ksum-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB-in, 1 GiB-out elementwise kernel (reference for HBM counters)")
@@ -191,8 +191,8 @@ def main():
                     help="stacked right-hand sides solved in lockstep: #1 unit torques, the others N(0,1) "
                          "forces and torques with zero net force")
     ap.add_argument("--serve", action="store_true", help="run the serving workload (see the module doc)")
-    ap.add_argument("--requests", type=int, default=12, help="requests in the Poisson stream (--serve)")
-    ap.add_argument("--saturated", type=int, default=6, help="requests in the saturated pass (--serve)")
+    ap.add_argument("--requests", type=int, default=64, help="requests in the Poisson stream (--serve)")
+    ap.add_argument("--saturated", type=int, default=16, help="requests in the saturated pass (--serve)")
     ap.add_argument("--slots", type=int, default=4, help="server slots (--serve)")
     ap.add_argument("--no-flow", action="store_true",
                     help="skip the boundary residual of the solution (flow evaluation with the pairs' fine "
@@ -236,7 +236,7 @@ def main():
     if not args.no_cpu and not args.kernel_only and not args.precompute_only:
         # the oracle's worker processes are forked before this process touches the GPU
         cpu = cpu_baseline(c, a, ns, nc, rs, args.cpu_targets)
-        log(f"cpu baseline {cpu['value']:.3e} pair-evals/s in {cpu['cores']} processes "
+        log(f"cpu baseline {cpu['rate']:.3e} pair-evals/s in {cpu['cores']} processes "
             f"({cpu['host_cores']} host cores)")
 
     import torch
@@ -468,6 +468,16 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if cpu is not None:
+        # the oracle's time to solve in the metric's unit, extrapolated from its measured direct-sum
+        # rate: one kernel sum per GMRES iteration over the dense (target, source) pairs a launch
+        # stands for; its one-body, pair and orthogonalisation steps and its precompute are left
+        # out, so this is a lower bound
+        its = infos[-1]["iters"]
+        cpu = dict(value=round(its * dense_launch / cpu["rate"], 1),
+                   unit="s (oracle time to solve: iterations x dense pairs per kernel sum / oracle rate; lower bound)",
+                   iterations=its, dense_pairs_per_kernel_sum=dense_launch, **cpu)
+        line["cpu_baseline"] = cpu
     nv.mfs_destroy(ctx)
     print(json.dumps(line), flush=True)
 
