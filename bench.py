@@ -102,29 +102,25 @@ def visiting_order(n_col, slot_body):
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak (256 CUs, 2.4 GHz)
 PEAK_FP64_TFLOPS = 78.6     # MI355X published FP64 vector peak
 
-# HBM traffic of one k_ksum_fmm launch on this workload: rocprofv3 --pmc FETCH_SIZE, then
-# WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for an elementwise kernel
-# that reads and writes 1 GiB.  It holds for the kernel source it was measured on, identified by
-# a hash of k_ksum_fmm's text; None until measured.
+# HBM traffic of one kernel-sum launch (k_ksum_fmm_mixed, k_ksum_fmm_fp64) on this workload:
+# rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE (KiB per dispatch), each scaled by what the counter
+# reads for an elementwise kernel that reads and writes 1 GiB.  It holds for the kernel source it
+# was measured on, identified by a hash of kernels.hip; None until measured.
 KSUM_TRAFFIC = {
-    "src_sha256_16": "50afe3b5d473746f",
-    "mixed": {"fetch_kib": 563222.75, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
-    "fp64": {"fetch_kib": 1322984.13, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
+    "src_sha256_16": "94d053df63a4c6bd",
+    "mixed": {"fetch_kib": 161041.75, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
+    "fp64": {"fetch_kib": 527950.69, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
 }
 
 
 def ksum_traffic_bytes(mixed):
-    """HBM bytes per k_ksum_fmm launch, or None once the kernel differs from the measured one."""
+    """HBM bytes per kernel-sum launch, or None once the kernels differ from the measured ones."""
     import hashlib
     t = KSUM_TRAFFIC and KSUM_TRAFFIC.get("mixed" if mixed else "fp64")
     if not t:
         return None
-    src = open(os.path.join(ROOT, "paper_2606_11273_amd", "csrc", "kernels.hip")).read()
-    i = src.find("void k_ksum_fmm(")
-    if i < 0:
-        return None
-    body = src[i:src.index("\n}\n", i) + 3]
-    if hashlib.sha256(body.encode()).hexdigest()[:16] != KSUM_TRAFFIC["src_sha256_16"]:
+    src = open(os.path.join(ROOT, "paper_2606_11273_amd", "csrc", "kernels.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != KSUM_TRAFFIC["src_sha256_16"]:
         return None
     return int((t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024)
 
@@ -369,7 +365,7 @@ def main():
     kd = kern[dom]
     roofline = dict(bound="alu", achieved=kd["tflops"], peak=kd["peak_tflops"], unit="TFLOP/s",
                     frac=kd["frac_valu"], traffic=ksum_traffic_bytes(dom == "mixed"),
-                    kernel=f"k_ksum_fmm<{'true' if dom == 'mixed' else 'false'}, 2> ({dom} kernel sum: per wave of "
+                    kernel=f"k_ksum_fmm_{dom} ({dom} kernel sum: per wave of "
                            "128 nodes, cell translations into an FP64 local expansion and near disks from their ring "
                            f"expansions{' in FP32' if dom == 'mixed' else ''})",
                     peak_note="the kernel's own flop mix at the published vector peaks: (FP64 + FP32 flops) / "

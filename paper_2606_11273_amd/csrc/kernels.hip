@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kBodyThreads) void k_gather_project(
 // Step 2a: all-pairs Stokeslet sum u_t = sum_s S(x_t, y_s) sigma_s (eq. getall, eq. stokeslet2d),
 //   u = 1/(4 pi mu) [ sum (d.sigma / r^2) d  -  (ln 2 / 2) sum log2(r^2) sigma ].
 // Two kernels evaluate it.  The context's own sum (every matvec, the right-hand side) is the
-// hierarchical k_ksum_fmm at the end of this file.  Sums at arbitrary points (flow
+// hierarchical k_ksum_fmm_mixed / k_ksum_fmm_fp64 at the end of this file.  Sums at arbitrary points (flow
 // evaluation) use the two-level FP64 k_ksum_fp64: a workgroup owns T * 256 consecutive
 // targets, thread i the T targets from T i on; it streams one split's clusters of disks
 // through LDS, one cluster per tile; a cluster far from every target of a wave is summed
@@ -719,7 +719,7 @@ __device__ __forceinline__ void cluster_expansion64(const double2* __restrict__ 
 }
 
 // Two-level FP64 sum at arbitrary points (flow evaluation; the context's own kernel sum is the
-// hierarchical k_ksum_fmm below), absolute coordinates (ln_f64, rcp_f64 above): the split's
+// hierarchical k_ksum_fmm_* below), absolute coordinates (ln_f64, rcp_f64 above): the split's
 // clusters one LDS tile each, in slot order.  A cluster far from the
 // workgroup (le_far) goes into its local expansion; one beyond 4 cluster radii from every
 // target of a wave is summed by that wave from its FP64 expansion (order kCl64Order); the
@@ -727,7 +727,7 @@ __device__ __forceinline__ void cluster_expansion64(const double2* __restrict__ 
 // cluster is summed from its FP64 expansion (k_moments64, order kMp64Order) by a wave whose
 // targets are all beyond 7 ring radii, else directly over its sources.  src: FP64 packed
 // sources in body order (src_off); ssrc_off: the same counts in slot order.  Skip modes as in
-// k_ksum_fmm (partner lists in slots); mode 0 reads no body index (flow-evaluation points
+// ksum_fmm_body (partner lists in slots); mode 0 reads no body index (flow-evaluation points
 // may have body -1).  mp64 NULL: every disk direct; cmp64 NULL: no cluster expansions.
 template <int T>
 __global__ __launch_bounds__(KS_THREADS) void k_ksum_fp64(int ncl, const int* __restrict__ cl_start,
@@ -1878,14 +1878,15 @@ __device__ __forceinline__ double bits_to_double(float2 v) {
 // ring record for each near disk) are staged in LDS, two buffers deep: the global loads of the
 // next record are in flight while the current one is used.
 template <bool MIXED, int T>
-__global__ __launch_bounds__(64) void k_ksum_fmm(
+__device__ __forceinline__ void ksum_fmm_body(
     const int* __restrict__ wstart, const int* __restrict__ tperm, const int* __restrict__ tgt_body,
     const int* __restrict__ slot_of, const double* __restrict__ X, const int* __restrict__ src_off,
     const double4* __restrict__ src64,
     const int* __restrict__ m2l_off, const int* __restrict__ m2l, const int* __restrict__ near_off,
     const int* __restrict__ near, const double* __restrict__ wcent, const double2* __restrict__ cellrec,
     const double2* __restrict__ rings, int mode, const int* __restrict__ nbr_off,
-    const int* __restrict__ nbr_slot, double scale, double* __restrict__ out, unsigned long long* __restrict__ work) {
+    const int* __restrict__ nbr_slot, double scale, double* __restrict__ out, unsigned long long* __restrict__ work,
+    int nwave, int group) {
   constexpr int Q = MIXED ? kLoc32 : kLoc64;
   // a ring record in 16-byte units (FP32 records: two float2 per unit)
   constexpr int RU = MIXED ? kRing32Coef / 2 : kRing64Coef;
@@ -1893,7 +1894,13 @@ __global__ __launch_bounds__(64) void k_ksum_fmm(
   static_assert(SU <= 192, "three 16-byte units per lane");
   __shared__ double2 s_buf[2][SU];
   __shared__ double2 s_row[64];
-  const int w = blockIdx.x;
+  // Workgroups go to the 8 XCDs in turn (workgroup b to XCD b mod 8).  Runs of `group`
+  // consecutive waves along the curve, which read mostly the same cell and ring records, are
+  // kept on one XCD (its L2), and the runs are dealt to the XCDs in turn, so that every XCD
+  // gets waves from all over the domain (group 1: workgroup b runs wave b).
+  const int b = blockIdx.x, i = b >> 3;
+  const int w = ((i / group) * 8 + (b & 7)) * group + i % group;
+  if (w >= nwave) return;
   const int lane = threadIdx.x;
   const int p0 = wstart[w], p1 = wstart[w + 1];   // this wave's positions in the visiting order
   int t[T];
@@ -2064,6 +2071,38 @@ __global__ __launch_bounds__(64) void k_ksum_fmm(
     }
   }
 }
+
+// The two forms as kernels, each with its register budget (waves per SIMD): 104 VGPRs and 4 waves
+// for the mixed form, 138 and 3 for the FP64 form.  More waves were slower: the mixed form at 5
+// (88 VGPRs, no spills) and at 6 (14 spilled), the FP64 form at 4 (14 spilled).
+// MFS_KSUM_WAVES_MIXED / MFS_KSUM_WAVES_64 override the targets at build time.
+#ifndef MFS_KSUM_WAVES_MIXED
+#define MFS_KSUM_WAVES_MIXED 4
+#endif
+#ifndef MFS_KSUM_WAVES_64
+#define MFS_KSUM_WAVES_64 3
+#endif
+#define MFS_KSUM_FMM_PARAMS                                                                                     \
+  const int *__restrict__ wstart, const int *__restrict__ tperm, const int *__restrict__ tgt_body,             \
+      const int *__restrict__ slot_of, const double *__restrict__ X, const int *__restrict__ src_off,          \
+      const double4 *__restrict__ src64, const int *__restrict__ m2l_off, const int *__restrict__ m2l,        \
+      const int *__restrict__ near_off, const int *__restrict__ near, const double *__restrict__ wcent,       \
+      const double2 *__restrict__ cellrec, const double2 *__restrict__ rings, int mode,                       \
+      const int *__restrict__ nbr_off, const int *__restrict__ nbr_slot, double scale, double *__restrict__ out, \
+      unsigned long long *__restrict__ work, int nwave, int group
+#define MFS_KSUM_FMM_ARGS                                                                                       \
+  wstart, tperm, tgt_body, slot_of, X, src_off, src64, m2l_off, m2l, near_off, near, wcent, cellrec, rings,    \
+      mode, nbr_off, nbr_slot, scale, out, work, nwave, group
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MFS_KSUM_WAVES_MIXED, 8))) void
+k_ksum_fmm_mixed(MFS_KSUM_FMM_PARAMS) {
+  ksum_fmm_body<true, kFmmT>(MFS_KSUM_FMM_ARGS);
+}
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MFS_KSUM_WAVES_64, 8))) void
+k_ksum_fmm_fp64(MFS_KSUM_FMM_PARAMS) {
+  ksum_fmm_body<false, kFmmT>(MFS_KSUM_FMM_ARGS);
+}
+#undef MFS_KSUM_FMM_PARAMS
+#undef MFS_KSUM_FMM_ARGS
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -2277,19 +2316,23 @@ void launch_fmm_records(mfs_ctx* c, int prob, const double4* src64, const FmmRec
 
 // The hierarchical kernel sum at the context's targets (records fr of launch_fmm_records,
 // direct sums from src64), written to u (2 Nt), scaled.
+constexpr int kKsumXcdGroup = 64;
+
 void launch_ksum_fmm(mfs_ctx* c, bool mixed, int mode, const double4* src64, const FmmRec& fr, double* u,
                      double scale) {
   const FmmLists& L = c->fl[mixed ? 1 : 0];
   if (c->nwave == 0) return;
-  // one workgroup per wave, in curve order: the hardware deals consecutive workgroups to the 8
-  // XCDs in turn, which spreads the waves with long lists evenly (giving each XCD a contiguous
-  // run of the curve instead, so that neighbouring waves share an L2, was 5-7% slower)
-#define MFS_KS_FMM(MX, RINGS)                                                                                    \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ksum_fmm<MX, kFmmT>), dim3(c->nwave), dim3(64), 0, c->stream,             \
-                     c->d_wstart, c->d_tperm, c->d_tgt_body, c->d_slot_of, c->d_X, c->d_src_off, src64, L.d_m2l_off, L.d_m2l,  \
-                     L.d_near_off, L.d_near, c->d_wcent, fr.rec, RINGS, mode, c->d_nbr_off, c->d_nbr_slot, scale, \
-                     u, c->d_work)
-  if (mixed) MFS_KS_FMM(true, (const double2*)fr.r32); else MFS_KS_FMM(false, (const double2*)fr.r64);
+  // runs of `group` consecutive waves per XCD (see ksum_fmm_body; MFS_KSUM_XCD_GROUP overrides)
+  const char* ev = std::getenv("MFS_KSUM_XCD_GROUP");
+  const int group = std::max(1, ev ? std::atoi(ev) : kKsumXcdGroup);
+  const int64_t per = 8 * (int64_t)group;
+  const unsigned nwg = (unsigned)((c->nwave + per - 1) / per * per);
+#define MFS_KS_FMM(KERNEL, RINGS)                                                                                \
+  hipLaunchKernelGGL(KERNEL, dim3(nwg), dim3(64), 0, c->stream, c->d_wstart, c->d_tperm, c->d_tgt_body,          \
+                     c->d_slot_of, c->d_X, c->d_src_off, src64, L.d_m2l_off, L.d_m2l, L.d_near_off, L.d_near,     \
+                     c->d_wcent, fr.rec, RINGS, mode, c->d_nbr_off, c->d_nbr_slot, scale, u, c->d_work, c->nwave, \
+                     group)
+  if (mixed) MFS_KS_FMM(k_ksum_fmm_mixed, (const double2*)fr.r32); else MFS_KS_FMM(k_ksum_fmm_fp64, (const double2*)fr.r64);
 #undef MFS_KS_FMM
 }
 
