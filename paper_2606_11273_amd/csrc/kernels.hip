@@ -185,6 +185,9 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_A(int C, const int* __res
   const double* Ac = A + aoff[c];
   for (int row = threadIdx.x; row < n; row += kPairThreads) {
     double acc = 0.0;
+    // the loads of 16 columns in flight per thread (A^c streams from HBM); the sum keeps the
+    // column order of the stacked form k_pair_A_rhs, so both give the same bits
+#pragma unroll 16
     for (int col = 0; col < n; ++col) acc = fma(Ac[(int64_t)col * n + row], s_x[col], acc);
     ltil[xoff[c] + row] = acc;
   }
@@ -301,11 +304,45 @@ constexpr int KS_TILE = 1024;   // sources per LDS tile (16 KB of float4)
 // translates one cluster: lane l < 32 holds Phi1's coefficient of w^l, lane 32 + l Psi's;
 // lane k first scales its function's c_k by Delta^-k into the wave's LDS row, then every lane
 // sums the row with its binomials.  Only Re log enters the velocity, so log Delta = ln |Delta|.
+// The binomials: with a factorial table in LDS (fac), binom(k + l - 1, l) = (k + l - 1)! /
+// (l! (k - 1)!), the row scaled by 1/(k - 1)! and the sum by 1/l!, two FMAs per term; without
+// it, by the recurrence binom(k + l, l) = binom(k + l - 1, l) (k + l) / k.
 __constant__ double kInvInt[32] = {0.0,        1.0,        1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,
                                    1.0 / 7,    1.0 / 8,    1.0 / 9,  1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13,
                                    1.0 / 14,   1.0 / 15,   1.0 / 16, 1.0 / 17, 1.0 / 18, 1.0 / 19, 1.0 / 20,
                                    1.0 / 21,   1.0 / 22,   1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
                                    1.0 / 28,   1.0 / 29,   1.0 / 30, 1.0 / 31};
+
+constexpr int kFactN = 58;
+// j! and 1/j! for j = 0..57, correctly rounded: the translation's binomials
+// binom(k + l - 1, l) = (k + l - 1)! / (l! (k - 1)!) from three rounded factors
+__constant__ double kFact[2 * kFactN] = {
+    1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40320.0, 362880.0, 3628800.0, 39916800.0, 479001600.0,
+    6227020800.0, 87178291200.0, 1307674368000.0, 20922789888000.0, 355687428096000.0, 6402373705728000.0,
+    1.21645100408832e+17, 2.43290200817664e+18, 5.109094217170944e+19, 1.1240007277776077e+21,
+    2.585201673888498e+22, 6.204484017332394e+23, 1.5511210043330986e+25, 4.0329146112660565e+26,
+    1.0888869450418352e+28, 3.0488834461171387e+29, 8.841761993739702e+30, 2.6525285981219107e+32,
+    8.222838654177922e+33, 2.631308369336935e+35, 8.683317618811886e+36, 2.9523279903960416e+38,
+    1.0333147966386145e+40, 3.7199332678990125e+41, 1.3763753091226346e+43, 5.230226174666011e+44,
+    2.0397882081197444e+46, 8.159152832478977e+47, 3.345252661316381e+49, 1.40500611775288e+51,
+    6.041526306337383e+52, 2.658271574788449e+54, 1.1962222086548019e+56, 5.502622159812089e+57,
+    2.5862324151116818e+59, 1.2413915592536073e+61, 6.082818640342675e+62, 3.0414093201713376e+64,
+    1.5511187532873822e+66, 8.065817517094388e+67, 4.2748832840600255e+69, 2.308436973392414e+71,
+    1.2696403353658276e+73, 7.109985878048635e+74, 4.0526919504877214e+76,
+    1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333, 0.001388888888888889,
+    0.0001984126984126984, 2.48015873015873e-05, 2.7557319223985893e-06, 2.755731922398589e-07,
+    2.505210838544172e-08, 2.08767569878681e-09, 1.6059043836821613e-10, 1.1470745597729725e-11,
+    7.647163731819816e-13, 4.779477332387385e-14, 2.8114572543455206e-15, 1.5619206968586225e-16,
+    8.22063524662433e-18, 4.110317623312165e-19, 1.9572941063391263e-20, 8.896791392450574e-22,
+    3.868170170630684e-23, 1.6117375710961184e-24, 6.446950284384474e-26, 2.4795962632247976e-27,
+    9.183689863795546e-29, 3.279889237069838e-30, 1.1309962886447716e-31, 3.7699876288159054e-33,
+    1.216125041553518e-34, 3.8003907548547434e-36, 1.151633562077195e-37, 3.387157535521162e-39,
+    9.67759295863189e-41, 2.6882202662866363e-42, 7.265460179153071e-44, 1.911963205040282e-45,
+    4.902469756513544e-47, 1.2256174391283858e-48, 2.9893108271424046e-50, 7.117406731291439e-52,
+    1.6552108677421951e-53, 3.7618428812322616e-55, 8.359650847182804e-57, 1.817315401561479e-58,
+    3.866628513960594e-60, 8.055476070751236e-62, 1.643974708316579e-63, 3.287949416633158e-65,
+    6.446959640457172e-67, 1.2397999308571486e-68, 2.3392451525606576e-70, 4.331935467704922e-72,
+    7.876246304918039e-74, 1.4064725544496498e-75, 2.4674957095607893e-77};
 
 // wave-level fence for LDS rows written and read by lanes of one wave (no workgroup barrier:
 // the waves of a workgroup translate different clusters)
@@ -367,7 +404,8 @@ __device__ __forceinline__ void target_bounds(const double (&x)[T], const double
 // is rec and centre (cx, cy) to the lane's coefficient (Lr, Li); K source and Q local orders.
 template <int K, int Q>
 __device__ __forceinline__ void m2l_add(const double2* __restrict__ rec, double cx, double cy, double bx,
-                                        double by, double2* row, double& Lr, double& Li) {
+                                        double by, double2* row, double& Lr, double& Li,
+                                        const double* fac = nullptr) {
   static_assert(K < 32 && Q < 32, "one lane per order");
   const int lane = threadIdx.x & 63, f = lane >> 5, l = lane & 31;
   const double dx = bx - cx, dy = by - cy;   // Delta = T - C
@@ -399,17 +437,34 @@ __device__ __forceinline__ void m2l_add(const double2* __restrict__ rec, double 
       cr = b.x - 0.5 * dd.x + 0.5 * (dx * a.x - dy * a.y);
       ci = -b.y + 0.5 * dd.y - 0.5 * (dx * a.y + dy * a.x);
     }
-    row[lane] = make_double2(cr * pr - ci * pi, fma(cr, pi, ci * pr));
+    // with the factorial table the row holds c_l Delta^-l / (l - 1)!
+    const double sc = fac ? fac[kFactN + l - 1] : 1.0;
+    row[lane] = make_double2((cr * pr - ci * pi) * sc, fma(cr, pi, ci * pr) * sc);
   }
   wave_lds_sync();
-  double ar = 0.0, ai = 0.0, bn = 1.0;   // binom(k + l - 1, l), k = 1
+  double ar = 0.0, ai = 0.0;
   const double2* rf = row + (f << 5);
+  if (fac) {
+    // sum_k (k + l - 1)! [c_k Delta^-k / (k - 1)!], then / l!  (the factorials in LDS)
+    const double* fk = fac + l;
 #pragma unroll 2
-  for (int k = 1; k <= K; ++k) {
-    const double2 c = rf[k];
-    ar = fma(bn, c.x, ar);
-    ai = fma(bn, c.y, ai);
-    bn *= (double)(k + l) * kInvInt[k];
+    for (int k = 1; k <= K; ++k) {
+      const double2 c = rf[k];
+      const double g = fk[k - 1];
+      ar = fma(g, c.x, ar);
+      ai = fma(g, c.y, ai);
+    }
+    ar *= fac[kFactN + l];
+    ai *= fac[kFactN + l];
+  } else {
+    double bn = 1.0;   // binom(k + l - 1, l), k = 1
+#pragma unroll 2
+    for (int k = 1; k <= K; ++k) {
+      const double2 c = rf[k];
+      ar = fma(bn, c.x, ar);
+      ai = fma(bn, c.y, ai);
+      bn *= (double)(k + l) * kInvInt[k];
+    }
   }
   if (l > Q) return;
   const double2 a0 = rec[2 * kCl64Order];   // conj(A_0)
@@ -1188,7 +1243,30 @@ __global__ __launch_bounds__(kDotThreads) void k_mdot(int64_t n, int k, const do
   const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + kDotThreads - 1) / kDotThreads * kDotThreads;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = min(n, lo + chunk);
-  for (int j = 0; j < k; ++j) {
+  int j = 0;
+  // four products per pass over w (each summed in the same order as alone)
+  for (; j + 4 <= k; j += 4) {
+    const double* v = V + (int64_t)j * ldv;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kDotThreads) {
+      const double wi = w[i];
+      a0 = fma(v[i], wi, a0);
+      a1 = fma(v[ldv + i], wi, a1);
+      a2 = fma(v[2 * ldv + i], wi, a2);
+      a3 = fma(v[3 * ldv + i], wi, a3);
+    }
+    a0 = block_sum<kDotThreads>(a0, red);
+    a1 = block_sum<kDotThreads>(a1, red);
+    a2 = block_sum<kDotThreads>(a2, red);
+    a3 = block_sum<kDotThreads>(a3, red);
+    if (threadIdx.x == 0) {
+      part[(int64_t)j * gridDim.x + blockIdx.x] = a0;
+      part[(int64_t)(j + 1) * gridDim.x + blockIdx.x] = a1;
+      part[(int64_t)(j + 2) * gridDim.x + blockIdx.x] = a2;
+      part[(int64_t)(j + 3) * gridDim.x + blockIdx.x] = a3;
+    }
+  }
+  for (; j < k; ++j) {
     const double* v = V + (int64_t)j * ldv;
     double acc = 0.0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kDotThreads) acc = fma(v[i], w[i], acc);
@@ -1218,6 +1296,7 @@ __global__ void k_maxpy(int64_t n, int k, const double* __restrict__ V, int64_t 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double acc = w[i];
+#pragma unroll 8
   for (int j = 0; j < k; ++j) acc = fma(-s_h[j], V[(int64_t)j * ldv + i], acc);
   w[i] = acc;
 }
@@ -1894,6 +1973,7 @@ __device__ __forceinline__ void ksum_fmm_body(
   static_assert(SU <= 192, "three 16-byte units per lane");
   __shared__ double2 s_buf[2][SU];
   __shared__ double2 s_row[64];
+  __shared__ double s_fac[2 * kFactN];   // j!, then 1/j! (the translations' binomials)
   // Workgroups go to the 8 XCDs in turn (workgroup b to XCD b mod 8).  Runs of `group`
   // consecutive waves along the curve, which read mostly the same cell and ring records, are
   // kept on one XCD (its L2), and the runs are dealt to the XCDs in turn, so that every XCD
@@ -1902,6 +1982,7 @@ __device__ __forceinline__ void ksum_fmm_body(
   const int w = ((i / group) * 8 + (b & 7)) * group + i % group;
   if (w >= nwave) return;
   const int lane = threadIdx.x;
+  for (int e = lane; e < 2 * kFactN; e += 64) s_fac[e] = kFact[e];   // read after the fences of m2l_add
   const int p0 = wstart[w], p1 = wstart[w + 1];   // this wave's positions in the visiting order
   int t[T];
   int64_t tt[T];
@@ -1949,7 +2030,7 @@ __device__ __forceinline__ void ksum_fmm_body(
       wave_lds_sync();
       if (e + 1 < m1) fetch(cellrec + (int64_t)m2l[e + 1] * kCellRec, kCellRec);
       const double2 cc = buf[kCl64CoefPerCluster];
-      m2l_add<kCl64Order, Q>(buf, cc.x, cc.y, bx, by, s_row, Lr, Li);
+      m2l_add<kCl64Order, Q>(buf, cc.x, cc.y, bx, by, s_row, Lr, Li, s_fac);
     }
     wave_lds_sync();   // the last translation's reads of the row are done
     s_row[lane] = make_double2(Lr, Li);
