@@ -44,15 +44,19 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 20          # algorithmic flops of one Stokeslet evaluation applied to a 2-vector
 KSUM_T = 2                  # targets per thread of both kernel sums
-CELL_ORDER = 26             # order of the cells' moments (the translations' source order)
+CELL_ORDER = 26             # order of the cells' moments (the FP64 translations' source order)
 LOC32_ORDER, LOC64_ORDER = 20, 26   # local expansion orders of the mixed and FP64 kernel sums
 LOC32_SEP, LOC64_SEP = 3.0, 4.0     # their separation factors (theta <= 1/3, 1/4)
 
 
-def flop_ring_expansions(n, terms):
+def flop_ring_expansions(n, terms, merged=False):
     """n evaluations of a disk's ring expansion whose orders sum to terms: three complex Horner
     series, 24 flops per step (p - 1 steps at order p), plus about 66 for zeta, the first terms,
-    the log term and the combination (two of them transcendental)."""
+    the log term and the combination (two of them transcendental); merged (the FP32 form): two
+    series, one in zeta and one in conj(zeta) that carries the other two, 20 flops per step, plus
+    57."""
+    if merged:
+        return 20 * (terms - n) + 57 * n
     return 24 * (terms - n) + 66 * n
 
 
@@ -75,8 +79,9 @@ def ksum_flops_split(work, mixed):
     pairs, translations, local expansions) in FP64."""
     direct, n, terms, m2l, l2p = work
     q = LOC32_ORDER if mixed else LOC64_ORDER
-    ring = flop_ring_expansions(n, terms)
-    f64 = direct * FLOP_PER_PAIR + m2l * flop_per_translation(q) + l2p * flop_per_local_evaluation(q)
+    ring = flop_ring_expansions(n, terms, merged=mixed)
+    # the translations take the cells' moments up to the local order
+    f64 = direct * FLOP_PER_PAIR + m2l * flop_per_translation(q, q) + l2p * flop_per_local_evaluation(q)
     return (f64, ring) if mixed else (f64 + ring, 0)
 
 
