@@ -1027,7 +1027,10 @@ __global__ void k_reduce_splits(int64_t n2, int nsplit, const double* __restrict
 //   corr^c_i = S^(ik) Pi sum_{c' contains k, c' != c} lambda_tilde^{c'}_k
 // (the self blocks P Pi (.) of step 2b and the neighbour one-body terms H mu cancel
 // exactly against the skipped terms).  Evaluated directly in FP64, relative to c_k.
-__global__ __launch_bounds__(kPairThreads) void k_pair_field(
+// Five waves per pair: the 2 (M_i + M_k) (node, half of the partner's sources) items of a pair of
+// 72-node disks fill 288 of the 320 lanes in one pass.
+constexpr int kFieldThreads = 320;
+__global__ __launch_bounds__(kFieldThreads) void k_pair_field(
     int C, int mobility, const int* __restrict__ pairs, const int* __restrict__ cls,
     const int* __restrict__ src_off, const int* __restrict__ col_off, ClassTab ct,
     const double* __restrict__ centers, const int64_t* __restrict__ xoff, const int64_t* __restrict__ coff,
@@ -1044,14 +1047,14 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_field(
   // sums over the other pairs of i (for the field on k) and of k (for the field on i)
   const bool other_i = bp_off[i + 1] - bp_off[i] > 1, other_k = bp_off[k + 1] - bp_off[k] > 1;
   if (!other_i && !other_k) {
-    for (int q = threadIdx.x; q < 2 * (mci + mck); q += kPairThreads) corr[coff[c] + q] = 0.0;
+    for (int q = threadIdx.x; q < 2 * (mci + mck); q += kFieldThreads) corr[coff[c] + q] = 0.0;
     return;
   }
   for (int side = 0; side < 2; ++side) {
     const int b = side ? k : i;
     const int n2 = 2 * (side ? nck : nci);
     double* s_v = side ? s_vk : s_vi;
-    for (int q = threadIdx.x; q < n2; q += kPairThreads) {
+    for (int q = threadIdx.x; q < n2; q += kFieldThreads) {
       double v = 0.0;
       for (int e = bp_off[b]; e < bp_off[b + 1]; ++e) {
         const int cc = bp_list[e] >> 1, sd = bp_list[e] & 1;
@@ -1064,11 +1067,14 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_field(
   }
   __syncthreads();
   if (mobility) {
-    project_rigid<kPairThreads>(s_vi, nci, ct.Yr[ci], ct.KtKi[ci], red);
-    project_rigid<kPairThreads>(s_vk, nck, ct.Yr[ck], ct.KtKi[ck], red);
+    project_rigid<kFieldThreads>(s_vi, nci, ct.Yr[ci], ct.KtKi[ci], red);
+    project_rigid<kFieldThreads>(s_vk, nck, ct.Yr[ck], ct.KtKi[ck], red);
   }
   const double dcx = centers[2 * i] - centers[2 * k], dcy = centers[2 * i + 1] - centers[2 * k + 1];
-  for (int q = threadIdx.x; q < mci + mck; q += kPairThreads) {
+  // item it: node q = it / 2, half h = it % 2 of the partner's sources; the two halves sit in
+  // adjacent lanes (the item count is even) and are added with one shuffle
+  for (int it = threadIdx.x; it < 2 * (mci + mck); it += kFieldThreads) {
+    const int q = it >> 1, h = it & 1;
     double tx, ty;
     const double* Ys;
     const double* vs;
@@ -1088,19 +1094,25 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_field(
       ns = other_i ? nci : 0;
     }
     double lx = 0, ly = 0, px = 0, py = 0;
-    for (int s = 0; s < ns; ++s) {
+    const int s1 = h ? ns : ns / 2;
+    for (int s = h ? ns / 2 : 0; s < s1; ++s) {
       const double dx = tx - Ys[2 * s], dy = ty - Ys[2 * s + 1];
       const double r2 = fma(dx, dx, dy * dy);
-      const double lg = log(r2);
+      const double lg = ln_f64(r2);
       const double sx = vs[2 * s], sy = vs[2 * s + 1];
-      const double dot = fma(dx, sx, dy * sy) / r2;
+      const double dot = fma(dx, sx, dy * sy) * rcp_f64(r2);
       lx = fma(lg, sx, lx);
       ly = fma(lg, sy, ly);
       px = fma(dot, dx, px);
       py = fma(dot, dy, py);
     }
-    corr[coff[c] + 2 * q] = fma(-0.5, lx, px) * inv4pimu;
-    corr[coff[c] + 2 * q + 1] = fma(-0.5, ly, py) * inv4pimu;
+    double ox = fma(-0.5, lx, px), oy = fma(-0.5, ly, py);
+    ox += __shfl_xor(ox, 1, 64);
+    oy += __shfl_xor(oy, 1, 64);
+    if (h == 0) {
+      corr[coff[c] + 2 * q] = ox * inv4pimu;
+      corr[coff[c] + 2 * q + 1] = oy * inv4pimu;
+    }
   }
 }
 
@@ -1810,19 +1822,25 @@ __global__ __launch_bounds__(64) void k_ring_moments(int P, const int* __restric
 //   D'_k = sum_j binom(k, j) delta^(k-j) (D_j + conj(delta) A_j).
 // Lane k <= kCl64Order forms A'_k and D'_k, lane 32 + k forms B'_k; each child's raw moments and
 // the powers of its delta are staged in LDS first.
-__global__ __launch_bounds__(64) void k_cell_m2m(int n, const int* __restrict__ cells,
+// One workgroup per cell, one wave per child (children w, w + 4, ... to wave w); the waves' sums
+// are added in wave order.
+constexpr int kM2mWaves = 4;
+__global__ __launch_bounds__(64 * kM2mWaves) void k_cell_m2m(int n, const int* __restrict__ cells,
                                                  const int* __restrict__ child_off, const int* __restrict__ child,
                                                  const double* __restrict__ cell_c, double2* __restrict__ raw,
                                                  double2* __restrict__ rec) {
   static_assert(kCl64Order < 32 && kCellRaw <= 128, "one lane per order, two raw entries per lane");
   if ((int)blockIdx.x >= n) return;
   const int q = cells[blockIdx.x];
-  const int lane = threadIdx.x, f = lane >> 5, k = lane & 31;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, f = lane >> 5, k = lane & 31;
   const double cx = cell_c[2 * q], cy = cell_c[2 * q + 1];
-  __shared__ double2 s_pw[32];          // delta^m
-  __shared__ double2 s_raw[kCellRaw];   // the child's A, B, D
+  __shared__ double2 s_pw_all[kM2mWaves][32];          // delta^m
+  __shared__ double2 s_raw_all[kM2mWaves][kCellRaw];   // the child's A, B, D
+  __shared__ double4 s_acc[kM2mWaves - 1][64];         // the sums of waves 1, 2, 3
+  double2* s_pw = s_pw_all[wv];
+  double2* s_raw = s_raw_all[wv];
   double ar = 0, ai = 0, dr = 0, di = 0;
-  for (int e = child_off[q]; e < child_off[q + 1]; ++e) {
+  for (int e = child_off[q] + wv; e < child_off[q + 1]; e += kM2mWaves) {
     const int ch = child[e];
     const double dx = cell_c[2 * ch] - cx, dy = cell_c[2 * ch + 1] - cy;
     const double2* cr = raw + (int64_t)ch * kCellRaw;
@@ -1857,6 +1875,17 @@ __global__ __launch_bounds__(64) void k_cell_m2m(int n, const int* __restrict__ 
         bn = bn * (double)(k - j) * kInvInt[j + 1];
       }
     }
+  }
+  if (wv > 0) s_acc[wv - 1][lane] = make_double4(ar, ai, dr, di);
+  __syncthreads();
+  if (wv > 0) return;
+#pragma unroll
+  for (int w = 0; w < kM2mWaves - 1; ++w) {
+    const double4 t = s_acc[w][lane];
+    ar += t.x;
+    ai += t.y;
+    dr += t.z;
+    di += t.w;
   }
   if (lane == 0) {
     double2* o = rec + (int64_t)q * kCellRec;
@@ -2470,7 +2499,7 @@ void launch_fmm_records(mfs_ctx* c, int prob, const double4* src64, const FmmRec
   for (int h = 1; h <= c->cell_height; ++h) {
     const int n = c->height_off[h + 1] - c->height_off[h];
     if (n > 0)
-      hipLaunchKernelGGL(k_cell_m2m, dim3(n), dim3(64), 0, c->stream, n, c->d_cell_by_height + c->height_off[h],
+      hipLaunchKernelGGL(k_cell_m2m, dim3(n), dim3(64 * kM2mWaves), 0, c->stream, n, c->d_cell_by_height + c->height_off[h],
                          c->d_cell_child_off, c->d_cell_child, c->d_cell_c, fr.raw, fr.rec);
   }
 }
@@ -2500,7 +2529,7 @@ void launch_ksum_fmm(mfs_ctx* c, bool mixed, int mode, const double4* src64, con
 void launch_pair_field(mfs_ctx* c, int prob, const double* ltil, double* corr) {
   const int C = (int)(c->pairs.size() / 2);
   if (C == 0) return;
-  hipLaunchKernelGGL(k_pair_field, dim3(C), dim3(kPairThreads), 0, c->stream, C, prob == MFS_MOBILITY ? 1 : 0,
+  hipLaunchKernelGGL(k_pair_field, dim3(C), dim3(kFieldThreads), 0, c->stream, C, prob == MFS_MOBILITY ? 1 : 0,
                      c->d_pairs, c->d_cls, c->d_src_off, c->d_col_off, c->ct[prob], c->d_centers, c->d_xoff,
                      c->d_coff, c->d_bp_off, c->d_bp_list, ltil, 1.0 / (4.0 * kPiD * c->prm.mu), corr);
 }

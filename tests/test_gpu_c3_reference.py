@@ -57,11 +57,12 @@ def test_dense_packing_solves_match_stored_oracle_solutions(kind):
                 # carried the FP32 noise into slowly converging directions and its velocities
                 # were 1.1e-5 from the oracle's (FP64 at the same residual: 3.8e-7).  With 60
                 # sources on the ring-rule radius FP64 rounding alone holds the true residual
-                # near 6e-9 with unit torques and 1.6e-8 with N(0,1) forces (the one-body map
-                # amplifies the ring's top modes 4e10-fold; the oracle's own true residual is
-                # about 2e-8)
+                # between 6e-9 and 1.1e-8 with unit torques (it moves with the rounding order of
+                # equivalent forms of the operator) and near 1.6e-8 with N(0,1) forces (the
+                # one-body map amplifies the ring's top modes 4e10-fold; the oracle's own true
+                # residual is about 2e-8), so these solves stop at 2e-8 and 3e-8
                 if kind == "paper":
-                    tol = 1e-8 if name == "torque" else 3e-8
+                    tol = 2e-8 if name == "torque" else 3e-8
                 else:
                     tol = 1e-9 if (prec, name) == ("mixed", "random") else 5e-9
                 out, info = nv.mfs_gmres_solve(ctx, "mobility", prec, given, tol, 1000)
