@@ -44,9 +44,9 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 20          # algorithmic flops of one Stokeslet evaluation applied to a 2-vector
 KSUM_T = 2                  # targets per thread of both kernel sums
-CELL_ORDER = 26             # order of the cells' moments (the FP64 translations' source order)
-LOC32_ORDER, LOC64_ORDER = 26, 26   # local expansion orders of the mixed and FP64 kernel sums
-LOC32_SEP, LOC64_SEP = 2.25, 4.0    # their separation factors (theta <= 1/2.25, 1/4)
+CELL_ORDER = 31             # order of the cells' moments (the translations' source order)
+LOC32_ORDER, LOC64_ORDER = 31, 31   # local expansion orders of the mixed and FP64 kernel sums
+LOC32_SEP, LOC64_SEP = 2.0, 3.0     # their separation factors (theta <= 1/2, 1/3)
 
 
 def flop_ring_expansions(n, terms, merged=False):

@@ -23,16 +23,16 @@ constexpr int kMp64CoefPerDisk = 3 * kMp64Order + 3;   // FP64 complex coefficie
 // hierarchical kernel sum's cells carry records of the same layout.
 constexpr int kClMaxBodies = 16;
 constexpr int kClMaxSources = 1024;                   // sources per cluster (one LDS tile)
-constexpr int kCl64Order = 26;
+constexpr int kCl64Order = 31;
 // Local expansions (M2L / L2P) of the kernel sums: a cluster farther than kLocSep32 (R + r_b)
 // (FP32 sum) or kLocSep64 (R + r_b) (FP64 sum), and than 4 R + r_b, from the centre of a
 // workgroup's targets (r_b their radius) is translated into the workgroup's local expansion,
-// order kLoc32 / kLoc64 in both source and target orders (theta <= 1/2.25 and 1/4: truncation
-// below 6e-10 and 1e-16 of sum |sigma|)
-constexpr int kLoc32 = 26;
-constexpr int kLoc64 = 26;
-constexpr double kLocSep32 = 2.25;
-constexpr double kLocSep64 = 4.0;
+// order kLoc32 / kLoc64 in both source and target orders (theta <= 1/2 and 1/3: truncation
+// below 5e-10 and 1e-15 of sum |sigma|)
+constexpr int kLoc32 = 31;
+constexpr int kLoc64 = 31;
+constexpr double kLocSep32 = 2.0;
+constexpr double kLocSep64 = 3.0;
 static_assert(kLoc32 <= kCl64Order && kLoc64 <= kCl64Order && kLoc64 < 32, "local orders");
 constexpr int kCl64CoefPerCluster = 4 * kCl64Order + 2;   // FP64 complex coefficients per cluster
 // Hierarchical far field of the kernel sums over the context's own targets: a quadtree of

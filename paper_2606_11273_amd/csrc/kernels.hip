@@ -313,8 +313,8 @@ __constant__ double kInvInt[32] = {0.0,        1.0,        1.0 / 2,  1.0 / 3,  1
                                    1.0 / 21,   1.0 / 22,   1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
                                    1.0 / 28,   1.0 / 29,   1.0 / 30, 1.0 / 31};
 
-constexpr int kFactN = 58;
-// j! and 1/j! for j = 0..57, correctly rounded: the translation's binomials
+constexpr int kFactN = 64;
+// j! and 1/j! for j = 0..63, correctly rounded: the translation's binomials
 // binom(k + l - 1, l) = (k + l - 1)! / (l! (k - 1)!) from three rounded factors
 __constant__ double kFact[2 * kFactN] = {
     1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40320.0, 362880.0, 3628800.0, 39916800.0, 479001600.0,
@@ -328,21 +328,24 @@ __constant__ double kFact[2 * kFactN] = {
     6.041526306337383e+52, 2.658271574788449e+54, 1.1962222086548019e+56, 5.502622159812089e+57,
     2.5862324151116818e+59, 1.2413915592536073e+61, 6.082818640342675e+62, 3.0414093201713376e+64,
     1.5511187532873822e+66, 8.065817517094388e+67, 4.2748832840600255e+69, 2.308436973392414e+71,
-    1.2696403353658276e+73, 7.109985878048635e+74, 4.0526919504877214e+76,
-    1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333, 0.001388888888888889,
-    0.0001984126984126984, 2.48015873015873e-05, 2.7557319223985893e-06, 2.755731922398589e-07,
-    2.505210838544172e-08, 2.08767569878681e-09, 1.6059043836821613e-10, 1.1470745597729725e-11,
-    7.647163731819816e-13, 4.779477332387385e-14, 2.8114572543455206e-15, 1.5619206968586225e-16,
-    8.22063524662433e-18, 4.110317623312165e-19, 1.9572941063391263e-20, 8.896791392450574e-22,
-    3.868170170630684e-23, 1.6117375710961184e-24, 6.446950284384474e-26, 2.4795962632247976e-27,
-    9.183689863795546e-29, 3.279889237069838e-30, 1.1309962886447716e-31, 3.7699876288159054e-33,
-    1.216125041553518e-34, 3.8003907548547434e-36, 1.151633562077195e-37, 3.387157535521162e-39,
-    9.67759295863189e-41, 2.6882202662866363e-42, 7.265460179153071e-44, 1.911963205040282e-45,
-    4.902469756513544e-47, 1.2256174391283858e-48, 2.9893108271424046e-50, 7.117406731291439e-52,
-    1.6552108677421951e-53, 3.7618428812322616e-55, 8.359650847182804e-57, 1.817315401561479e-58,
-    3.866628513960594e-60, 8.055476070751236e-62, 1.643974708316579e-63, 3.287949416633158e-65,
-    6.446959640457172e-67, 1.2397999308571486e-68, 2.3392451525606576e-70, 4.331935467704922e-72,
-    7.876246304918039e-74, 1.4064725544496498e-75, 2.4674957095607893e-77};
+    1.2696403353658276e+73, 7.109985878048635e+74, 4.0526919504877214e+76, 2.3505613312828785e+78,
+    1.3868311854568984e+80, 8.32098711274139e+81, 5.075802138772248e+83, 3.146997326038794e+85,
+    1.98260831540444e+87, 1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333,
+    0.001388888888888889, 0.0001984126984126984, 2.48015873015873e-05, 2.7557319223985893e-06,
+    2.755731922398589e-07, 2.505210838544172e-08, 2.08767569878681e-09, 1.6059043836821613e-10,
+    1.1470745597729725e-11, 7.647163731819816e-13, 4.779477332387385e-14, 2.8114572543455206e-15,
+    1.5619206968586225e-16, 8.22063524662433e-18, 4.110317623312165e-19, 1.9572941063391263e-20,
+    8.896791392450574e-22, 3.868170170630684e-23, 1.6117375710961184e-24, 6.446950284384474e-26,
+    2.4795962632247976e-27, 9.183689863795546e-29, 3.279889237069838e-30, 1.1309962886447716e-31,
+    3.7699876288159054e-33, 1.216125041553518e-34, 3.8003907548547434e-36, 1.151633562077195e-37,
+    3.387157535521162e-39, 9.67759295863189e-41, 2.6882202662866363e-42, 7.265460179153071e-44,
+    1.911963205040282e-45, 4.902469756513544e-47, 1.2256174391283858e-48, 2.9893108271424046e-50,
+    7.117406731291439e-52, 1.6552108677421951e-53, 3.7618428812322616e-55, 8.359650847182804e-57,
+    1.817315401561479e-58, 3.866628513960594e-60, 8.055476070751236e-62, 1.643974708316579e-63,
+    3.287949416633158e-65, 6.446959640457172e-67, 1.2397999308571486e-68, 2.3392451525606576e-70,
+    4.331935467704922e-72, 7.876246304918039e-74, 1.4064725544496498e-75, 2.4674957095607893e-77,
+    4.254302947518602e-79, 7.2106829618959365e-81, 1.2017804936493226e-82, 1.9701319568021682e-84,
+    3.1776321883905942e-86, 5.043860616493007e-88};
 
 // wave-level fence for LDS rows written and read by lanes of one wave (no workgroup barrier:
 // the waves of a workgroup translate different clusters)

@@ -201,7 +201,7 @@ def test_fmm_lists_partition_the_disks():
         partners[k].add(int(i))
     tp = bench.visiting_order(nc, sb)
     body_of_t = np.repeat(np.arange(P), nc)
-    for prec, sep in (("fp64", 4.0), ("mixed", 2.25)):
+    for prec, sep in (("fp64", 3.0), ("mixed", 2.0)):
         d = f[prec]
         lo, hi = d["cell_lo"], d["cell_hi"]
         assert np.array_equal(lo[:P], np.arange(P)) and np.array_equal(hi[:P], np.arange(1, P + 1))
