@@ -147,8 +147,11 @@ __global__ __launch_bounds__(kBodyThreads) void k_onebody(int P, const int* __re
   __syncthreads();
   const double* U = ct.U[k];
   const double* si = ct.sinv[k];
+  // sixteen loads of the shared factors in flight per thread (they come from L2; four per round
+  // trip left the loops waiting on memory)
   for (int j = threadIdx.x; j < r; j += kBodyThreads) {
     double acc = 0.0;
+#pragma unroll 16
     for (int q = 0; q < m2; ++q) acc = fma(U[(int64_t)q * r + j], s_mu[q], acc);
     s_t[j] = acc * si[j];
   }
@@ -157,6 +160,7 @@ __global__ __launch_bounds__(kBodyThreads) void k_onebody(int P, const int* __re
   double* lb = lam + 2 * (int64_t)src_off[b];
   for (int i = threadIdx.x; i < n2; i += kBodyThreads) {
     double acc = 0.0;
+#pragma unroll 16
     for (int j = 0; j < r; ++j) acc = fma(Vt[(int64_t)j * n2 + i], s_t[j], acc);
     lb[i] = acc;
   }
@@ -1743,12 +1747,40 @@ __global__ __launch_bounds__(64) void k_ring_moments(int P, const int* __restric
   const double* Yr = ct.Yr[k];
   const int64_t so = src_off[b];
   const int sl = slot_of[b];
+  // the disk's strengths and ring offsets staged in LDS with one load per lane (a loop of
+  // dependent global loads would wait on memory once per source); the launch gives 2 x the
+  // largest class's source count double2 of dynamic LDS
+  extern __shared__ double2 s_dyn[];
+  double2* s_sig = s_dyn;
+  double2* s_w = s_dyn + nc;
+  for (int j = e; j < nc; j += 64) {
+    const double4 v = src64[so + j];
+    s_sig[j] = make_double2(v.z, v.w);
+    s_w[j] = make_double2(Yr[2 * j], Yr[2 * j + 1]);
+  }
+  __syncthreads();
+  // The sources are the class's ring w_j = rho exp(2 pi i j / nc) from angle 0 (Yr[0] = (rho, 0)),
+  // so w_j^e = rho^(e-1) w_m with m = j e mod nc: one lookup and a real scaling per source
+  // instead of a complex power (rho^(e-1) by binary powering once per lane).
+  const double rho = Yr[0];
+  double re = 1.0;
+  {
+    double bb = rho;
+    for (int t = e - 1; t > 0; t >>= 1) {
+      if (t & 1) re *= bb;
+      bb *= bb;
+    }
+  }
+  const int em = e % nc;
+  int m = 0;
   double Ar = 0, Ai = 0, Br = 0, Bi = 0, Dr = 0, Di = 0;
   for (int j = 0; j < nc; ++j) {
-    const double4 v = src64[so + j];
-    const double wx = Yr[2 * j], wy = Yr[2 * j + 1];
-    double pr, pi;
-    cpow_int(wx, wy, e, pr, pi);
+    const double2 sg = s_sig[j], wv = s_w[j], wm = s_w[m];
+    m += em;
+    if (m >= nc) m -= nc;
+    const double4 v = make_double4(0.0, 0.0, sg.x, sg.y);
+    const double wx = wv.x, wy = wv.y;
+    const double pr = e ? re * wm.x : 1.0, pi = e ? re * wm.y : 0.0;   // w_j^e
     const double sr = v.z * pr - v.w * pi, si = v.z * pi + v.w * pr;   // sigma w^e
     Ar += sr;
     Ai += si;
@@ -2497,7 +2529,10 @@ bool fmm_records_in(const mfs_ctx* c, const SplitBuf* sb, FmmRec* out) {
 // Records of the hierarchical kernel sum for a packed source array: ring records and leaf
 // cells of every disk, then the internal cells by height.
 void launch_fmm_records(mfs_ctx* c, int prob, const double4* src64, const FmmRec& fr, bool ring32) {
-  hipLaunchKernelGGL(k_ring_moments, dim3(c->P), dim3(64), 0, c->stream, c->P, c->d_cls, c->d_src_off, c->ct[prob],
+  int ncmax = 1;
+  for (int k = 0; k < c->ct[prob].n; ++k) ncmax = std::max(ncmax, c->ct[prob].nc[k]);
+  hipLaunchKernelGGL(k_ring_moments, dim3(c->P), dim3(64), sizeof(double2) * 2 * ncmax, c->stream, c->P, c->d_cls,
+                     c->d_src_off, c->ct[prob],
                      src64, c->d_slot_of, c->d_centers, fr.r64, ring32 ? fr.r32 : (float2*)nullptr, fr.raw, fr.rec);
   for (int h = 1; h <= c->cell_height; ++h) {
     const int n = c->height_off[h + 1] - c->height_off[h];
