@@ -131,38 +131,65 @@ __device__ void project_rigid(double* s_l, int nc, const double* Yr, const doubl
 
 // ---------------------------------------------------------------------------
 // Step 1a: lambda_bar = V Sigma^+ (U^T mu) per body, shared factors per class (eq. howG+, eq. SL).
+// ob <= kObBodies consecutive bodies per workgroup: when they share a class each factor element
+// read from L2 serves all of them (the factors, 2 x 144 x 120 doubles per class, are otherwise
+// read once per body); each body's sums keep the one-body order, so the result does not depend
+// on the grouping.  Dynamic LDS: ob x (m2max + rmax) doubles (2 max n_col, max rank).
+constexpr int kObBodies = 4;
 __global__ __launch_bounds__(kBodyThreads) void k_onebody(int P, const int* __restrict__ cls,
                                                           const int* __restrict__ src_off,
                                                           const int* __restrict__ col_off, ClassTab ct,
                                                           const double* __restrict__ mu,
-                                                          double* __restrict__ lam) {
-  const int b = blockIdx.x;
-  if (b >= P) return;
-  const int k = cls[b];
-  const int m2 = 2 * ct.mc[k], n2 = 2 * ct.nc[k], r = ct.rank[k];
-  __shared__ double s_mu[2 * kMaxCol];
-  __shared__ double s_t[2 * kMaxCol];
-  const double* mub = mu + 2 * (int64_t)col_off[b];
-  for (int q = threadIdx.x; q < m2; q += kBodyThreads) s_mu[q] = mub[q];
-  __syncthreads();
-  const double* U = ct.U[k];
-  const double* si = ct.sinv[k];
-  // sixteen loads of the shared factors in flight per thread (they come from L2; four per round
-  // trip left the loops waiting on memory)
-  for (int j = threadIdx.x; j < r; j += kBodyThreads) {
-    double acc = 0.0;
-#pragma unroll 16
-    for (int q = 0; q < m2; ++q) acc = fma(U[(int64_t)q * r + j], s_mu[q], acc);
-    s_t[j] = acc * si[j];
-  }
-  __syncthreads();
-  const double* Vt = ct.Vt[k];
-  double* lb = lam + 2 * (int64_t)src_off[b];
-  for (int i = threadIdx.x; i < n2; i += kBodyThreads) {
-    double acc = 0.0;
-#pragma unroll 16
-    for (int j = 0; j < r; ++j) acc = fma(Vt[(int64_t)j * n2 + i], s_t[j], acc);
-    lb[i] = acc;
+                                                          double* __restrict__ lam, int ob, int m2max, int rmax) {
+  const int b0 = blockIdx.x * ob;
+  if (b0 >= P) return;
+  const int nb = min(ob, P - b0);
+  extern __shared__ double s_ob[];
+  double* s_mu = s_ob;                  // [ob][m2max]
+  double* s_t = s_ob + ob * m2max;      // [ob][rmax]
+  const int k0 = cls[b0];
+  bool same = true;
+  for (int i = 1; i < nb; ++i) same = same && cls[b0 + i] == k0;
+  // bodies processed together: all nb of one class, else one at a time
+  for (int g0 = 0; g0 < nb; g0 += same ? nb : 1) {
+    const int gn = same ? nb : 1;
+    const int k = cls[b0 + g0];
+    const int m2 = 2 * ct.mc[k], n2 = 2 * ct.nc[k], r = ct.rank[k];
+    // LDS slots 0..ob-1; the accumulators beyond ob read slot 0 and are not stored
+    for (int i = 0; i < ob; ++i) {
+      const double* mub = mu + 2 * (int64_t)col_off[b0 + g0 + (i < gn ? i : 0)];
+      for (int q = threadIdx.x; q < m2; q += kBodyThreads) s_mu[i * m2max + q] = i < gn ? mub[q] : 0.0;
+    }
+    __syncthreads();
+    const double* U = ct.U[k];
+    const double* si = ct.sinv[k];
+    for (int j = threadIdx.x; j < r; j += kBodyThreads) {
+      double acc[kObBodies] = {};
+#pragma unroll 8
+      for (int q = 0; q < m2; ++q) {
+        const double u = U[(int64_t)q * r + j];
+#pragma unroll
+        for (int i = 0; i < kObBodies; ++i) acc[i] = fma(u, s_mu[(i < ob ? i : 0) * m2max + q], acc[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < kObBodies; ++i)
+        if (i < ob) s_t[i * rmax + j] = acc[i] * si[j];
+    }
+    __syncthreads();
+    const double* Vt = ct.Vt[k];
+    for (int o = threadIdx.x; o < n2; o += kBodyThreads) {
+      double acc[kObBodies] = {};
+#pragma unroll 8
+      for (int j = 0; j < r; ++j) {
+        const double v = Vt[(int64_t)j * n2 + o];
+#pragma unroll
+        for (int i = 0; i < kObBodies; ++i) acc[i] = fma(v, s_t[(i < ob ? i : 0) * rmax + j], acc[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < kObBodies; ++i)
+        if (i < gn) lam[2 * (int64_t)src_off[b0 + g0 + i] + o] = acc[i];
+    }
+    __syncthreads();   // s_mu and s_t are reused by the next group
   }
 }
 
@@ -2361,8 +2388,16 @@ void launch_zero_work(mfs_ctx* c) {
 }
 
 void launch_onebody_apply(mfs_ctx* c, int prob, const double* mu, double* lam_bar) {
-  hipLaunchKernelGGL(k_onebody, dim3(c->P), dim3(kBodyThreads), 0, c->stream, c->P, c->d_cls, c->d_src_off,
-                     c->d_col_off, c->ct[prob], mu, lam_bar);
+  int m2max = 1, rmax = 1;
+  for (int k = 0; k < c->ct[prob].n; ++k) {
+    m2max = std::max(m2max, 2 * c->ct[prob].mc[k]);
+    rmax = std::max(rmax, c->ct[prob].rank[k]);
+  }
+  // four bodies per workgroup while their staging fits 64 KB of LDS, else one
+  const int ob = sizeof(double) * kObBodies * (m2max + rmax) <= 65536 ? kObBodies : 1;
+  hipLaunchKernelGGL(k_onebody, dim3((c->P + ob - 1) / ob), dim3(kBodyThreads), sizeof(double) * ob * (m2max + rmax),
+                     c->stream, c->P, c->d_cls, c->d_src_off, c->d_col_off, c->ct[prob], mu, lam_bar, ob,
+                     m2max, rmax);
 }
 
 void launch_pair_A(mfs_ctx* c, int prob, const double* lam_bar, double* ltil) {
