@@ -112,9 +112,9 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X published FP64 vector peak
 # reads for an elementwise kernel that reads and writes 1 GiB.  It holds for the kernel source it
 # was measured on, identified by a hash of kernels.hip; None until measured.
 KSUM_TRAFFIC = {
-    "src_sha256_16": "00a2d501d435cd42",
-    "mixed": {"fetch_kib": 101339.94, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
-    "fp64": {"fetch_kib": 268774.44, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
+    "src_sha256_16": "8a8f34a265271f95",
+    "mixed": {"fetch_kib": 101368.0, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
+    "fp64": {"fetch_kib": 266924.56, "fetch_factor": 2.0, "write_kib": 12391.56, "write_factor": 1.0},
 }
 
 
