@@ -33,11 +33,11 @@
 
 namespace mfs {
 
-// The SVD entry points.  A host process may already hold another rocSOLVER under the same soname
+// The SVD and QR entry points.  A host process may already hold another rocSOLVER under the same soname
 // (PyTorch's wheel bundles its own ROCm libraries and loads them first; the library's
 // dependencies then bind to those, which keeps one HIP runtime per process).  The batched SVD of
 // the rocSOLVER in the ROCm installation this library is built against (MFS_ROCM_LIB) is several
-// times faster at these sizes than older ones, so its two entry points are taken from there,
+// times faster at these sizes than older ones, so its entry points are taken from there,
 // loaded by path; it binds to the process's rocBLAS and HIP runtime like the library itself
 // (same soname majors).  If that file cannot be loaded, or MFS_ROCSOLVER_LINKED=1, the linked
 // rocSOLVER is used.
@@ -47,6 +47,7 @@ namespace mfs {
 struct SvdEntry {
   decltype(&rocsolver_dgesvd) gesvd = &rocsolver_dgesvd;
   decltype(&rocsolver_dgesvd_strided_batched) gesvd_sb = &rocsolver_dgesvd_strided_batched;
+  decltype(&rocsolver_dgeqrf_strided_batched) geqrf_sb = &rocsolver_dgeqrf_strided_batched;
   const char* origin = "linked";
 };
 static const SvdEntry& svd_entry() {
@@ -58,9 +59,11 @@ static const SvdEntry& svd_entry() {
     if (!h) return r;
     auto a = (decltype(&rocsolver_dgesvd))dlsym(h, "rocsolver_dgesvd");
     auto b = (decltype(&rocsolver_dgesvd_strided_batched))dlsym(h, "rocsolver_dgesvd_strided_batched");
-    if (a && b) {
+    auto q = (decltype(&rocsolver_dgeqrf_strided_batched))dlsym(h, "rocsolver_dgeqrf_strided_batched");
+    if (a && b && q) {
       r.gesvd = a;
       r.gesvd_sb = b;
+      r.geqrf_sb = q;
       r.origin = MFS_ROCM_LIB "/librocsolver.so.0";
     }
     return r;
@@ -255,28 +258,42 @@ __global__ __launch_bounds__(256) void k_trunc_scale(int nsv, const double* __re
 // play the parts of disk i's and disk k's nodes for C and D G.
 __device__ __forceinline__ int sym_map(int j, int nring) { return j < nring ? (j + nring / 2) % nring : j; }
 
-// F_e (mh x nh) and X_e (mh x nx) of every pair of a batch: matrix 2q + (e < 0) of Fs, Xs.
-// One block per (column, matrix); column c < nh of F_e, else column c - nh of X_e.
+// [F_e X_e] (mh x (nh + nx), leading dimension mh) of every pair of a batch: matrix 2q + (e < 0)
+// of FXs.  One block per (column, matrix); column c < nh of F_e, else column c - nh of X_e.
 __global__ __launch_bounds__(256) void k_sym_split_F(const double* __restrict__ F, int64_t ldF, int64_t sF,
                                                      const double* __restrict__ X, int64_t sX, int mh, int nh, int nx,
-                                                     int nring_src, int nring_node, double* __restrict__ Fs,
-                                                     double* __restrict__ Xs) {
+                                                     int nring_src, int nring_node, double* __restrict__ FXs) {
   const int col = blockIdx.x, mat = blockIdx.y, q = mat >> 1;
   const double e = (mat & 1) ? 1.0 : -1.0;   // + block: F_ii - F_ik[mapped]; the minus sign is Sigma's flip
+  double* o = FXs + (int64_t)mat * mh * (nh + nx) + (int64_t)col * mh;
   if (col < nh) {
     const int colk = nh + 2 * sym_map(col >> 1, nring_src) + (col & 1);
     const double* a = F + q * sF + (int64_t)col * ldF;
     const double* b = F + q * sF + (int64_t)colk * ldF;
-    double* o = Fs + (int64_t)mat * mh * nh + (int64_t)col * mh;
     for (int r = threadIdx.x; r < mh; r += 256) o[r] = a[r] + e * b[r];
   } else if (col < nh + nx) {
     const int xc = col - nh;
     const double* a = X + q * sX + (int64_t)xc * ldF;
-    double* o = Xs + (int64_t)mat * mh * nx + (int64_t)xc * mh;
     for (int r = threadIdx.x; r < mh; r += 256) {
       const int rk = mh + 2 * sym_map(r >> 1, nring_node) + (r & 1);
       o[r] = (a[r] + e * a[rk]) * 0.70710678118654752440;
     }
+  }
+}
+
+// After the Householder QR of a tall [F X] (rows x (cols + nx), R in the upper triangle): the
+// cols x cols factor R11 (zeros below the diagonal) and R12 = Q1^T X (cols x nx), both with
+// leading dimension cols.  One block per (column, matrix).
+__global__ __launch_bounds__(256) void k_split_qr(const double* __restrict__ A, int64_t rows, int64_t sA, int cols,
+                                                  int nx, double* __restrict__ R, double* __restrict__ T0) {
+  const int col = blockIdx.x, mat = blockIdx.y;
+  const double* a = A + (int64_t)mat * sA + (int64_t)col * rows;
+  if (col < cols) {
+    double* o = R + (int64_t)mat * cols * cols + (int64_t)col * cols;
+    for (int r = threadIdx.x; r < cols; r += 256) o[r] = r <= col ? a[r] : 0.0;
+  } else if (col < cols + nx) {
+    double* o = T0 + (int64_t)mat * cols * nx + (int64_t)(col - cols) * cols;
+    for (int r = threadIdx.x; r < cols; r += 256) o[r] = a[r];
   }
 }
 
@@ -793,8 +810,8 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     d.ldF = 2 * (d.mf[0] + d.mf[1]);
     d.ldD = 2 * mp;
     const int64_t m = d.ldF, n = 2 * (d.nfpad[0] + d.nfpad[1]), nx = 2 * (d.nc[0] + d.nc[1]), mpp = 2 * mp;
-    d.sF = m * n;
-    d.sX = m * nx;
+    d.sF = m * (n + nx);   // [F X] of a pair side by side, leading dimension m (X at column n)
+    d.sX = d.sF;
     d.sD = mpp * n;
     d.sC = mpp * nx;
     // host staging: geometry
@@ -904,21 +921,20 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_HIP(deoff.alloc(c, sizeof(int64_t) * nb));
     MFS_HIP(hipMemcpyAsync(deoff.p, eoff.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, c->stream));
 
-    const int64_t mn = std::min(m, n);
-    DevMem dF, dX, dD, dC, dSF, dU, dVT, dE, dT1, dG, dDG, dSC, dUC, dVTC, dEC, dT2, dinfo, dinfoC;
-    MFS_HIP(dF.alloc(c, sizeof(double) * d.sF * nb));
-    MFS_HIP(dX.alloc(c, sizeof(double) * d.sX * nb));
+    DevMem dFX, dD, dC, dG, dDG, dSC, dUC, dVTC, dEC, dT2, dinfo, dinfoC;
+    MFS_HIP(dFX.alloc(c, sizeof(double) * d.sF * nb));
+    double* const pF = (double*)dFX.p;
+    double* const pX = pF + m * n;
     MFS_HIP(dD.alloc(c, sizeof(double) * d.sD * nb));
     MFS_HIP(dC.alloc(c, sizeof(double) * d.sC * nb));
-    MFS_HIP(hipMemsetAsync(dF.p, 0, sizeof(double) * d.sF * nb, c->stream));
-    MFS_HIP(hipMemsetAsync(dX.p, 0, sizeof(double) * d.sX * nb, c->stream));
+    MFS_HIP(hipMemsetAsync(dFX.p, 0, sizeof(double) * d.sF * nb, c->stream));
     MFS_HIP(hipMemsetAsync(dD.p, 0, sizeof(double) * d.sD * nb, c->stream));
     tick(0, t0);
     {
       const int maxpts = std::max(d.mf[0] + d.mf[1], mp);
       dim3 grid((maxpts + 63) / 64, nb, 4);
-      hipLaunchKernelGGL(k_fill, grid, dim3(64), 0, c->stream, (const PairGeo*)dgeo.p, d, mobility, kscale,
-                         (double*)dF.p, (double*)dX.p, (double*)dD.p, (double*)dC.p);
+      hipLaunchKernelGGL(k_fill, grid, dim3(64), 0, c->stream, (const PairGeo*)dgeo.p, d, mobility, kscale, pF, pX,
+                         (double*)dD.p, (double*)dC.p);
       MFS_HIP(hipGetLastError());
     }
     tick(1, t0);
@@ -930,77 +946,89 @@ Status precompute_pairs(mfs_ctx* c, int prob) {
     MFS_HIP(dinfo.alloc(c, sizeof(int) * nbs));
     MFS_HIP(dinfoC.alloc(c, sizeof(int) * nbs));
     MFS_HIP(dG.alloc(c, sizeof(double) * n * nx * nb));
-    if (sym) {
-      // F_e (mh x nh), X_e (mh x nx), e = +, -: half the rows and columns
-      const int64_t mh = m / 2, nh = n / 2, mnh = std::min(mh, nh);
-      DevMem dFs, dXs, dGs;
-      MFS_HIP(dFs.alloc(c, sizeof(double) * mh * nh * nbs));
-      MFS_HIP(dXs.alloc(c, sizeof(double) * mh * nx * nbs));
-      hipLaunchKernelGGL(k_sym_split_F, dim3((unsigned)(nh + nx), nbs), dim3(256), 0, c->stream, (const double*)dF.p,
-                         m, d.sF, (const double*)dX.p, d.sX, (int)mh, (int)nh, (int)nx, sym_nsrc, sym_nnode,
-                         (double*)dFs.p, (double*)dXs.p);
-      MFS_HIP(hipGetLastError());
-      MFS_HIP(dSF.alloc(c, sizeof(double) * mnh * nbs));
-      MFS_HIP(dU.alloc(c, sizeof(double) * mh * mnh * nbs));
-      MFS_HIP(dVT.alloc(c, sizeof(double) * mnh * nh * nbs));
-      MFS_HIP(dE.alloc(c, sizeof(double) * mnh * nbs));
-      tick(7, t0);
-      MFS_RB(svd_entry().gesvd_sb(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)mh,
-                                              (int)nh, (double*)dFs.p, (int)mh, mh * nh, (double*)dSF.p, mnh,
-                                              (double*)dU.p, (int)mh, mh * mnh, (double*)dVT.p, (int)mnh, mnh * nh,
-                                              (double*)dE.p, mnh, rocblas_outofplace, (int*)dinfo.p, nbs));
+    // G = F^+ X with the truncated pseudoinverse (singular values below eps_trunc_fine times the
+    // largest of the group's matrices dropped) for nmat matrices A = [F X] (rows x (cols + nx),
+    // leading dimension rows, stride sA; A is overwritten).  A tall F first goes through a
+    // Householder QR of the whole of A, F = Q1 R, whose last nx columns become Q1^T X: F and R
+    // share their singular values and right vectors, and U_F = Q1 U_R, so
+    // G = V Sigma^+ U_R^T (Q1^T X) and the SVD is of the cols x cols factor R alone.
+    auto pinv_apply = [&](double* A, int64_t rows, int64_t cols, int64_t sA, int nmat, int group,
+                          double* G) -> Status {
+      DevMem dTau, dR, dT0, dS, dU, dVT, dE, dT1;
+      double *svA = A, *Xp = A + rows * cols;
+      int64_t sr = rows, ssv = sA, ldx = rows, sx = sA;
+      if (rows >= cols) {
+        const int64_t kq = std::min(rows, cols + nx);
+        MFS_HIP(dTau.alloc(c, sizeof(double) * kq * nmat));
+        MFS_HIP(dR.alloc(c, sizeof(double) * cols * cols * nmat));
+        MFS_HIP(dT0.alloc(c, sizeof(double) * cols * nx * nmat));
+        MFS_RB(svd_entry().geqrf_sb(c->blas, (int)rows, (int)(cols + nx), A, (int)rows, sA, (double*)dTau.p, kq,
+                                    nmat));
+        hipLaunchKernelGGL(k_split_qr, dim3((unsigned)(cols + nx), nmat), dim3(256), 0, c->stream, A, rows, sA,
+                           (int)cols, (int)nx, (double*)dR.p, (double*)dT0.p);
+        MFS_HIP(hipGetLastError());
+        svA = (double*)dR.p;
+        Xp = (double*)dT0.p;
+        sr = cols;
+        ssv = cols * cols;
+        ldx = cols;
+        sx = cols * nx;
+      }
+      const int64_t k = std::min(sr, cols);
+      MFS_HIP(dS.alloc(c, sizeof(double) * k * nmat));
+      MFS_HIP(dU.alloc(c, sizeof(double) * sr * k * nmat));
+      MFS_HIP(dVT.alloc(c, sizeof(double) * k * cols * nmat));
+      MFS_HIP(dE.alloc(c, sizeof(double) * k * nmat));
+      MFS_HIP(dT1.alloc(c, sizeof(double) * k * nx * nmat));
+      MFS_RB(svd_entry().gesvd_sb(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)sr, (int)cols, svA,
+                                  (int)sr, ssv, (double*)dS.p, k, (double*)dU.p, (int)sr, sr * k, (double*)dVT.p,
+                                  (int)k, k * cols, (double*)dE.p, k, rocblas_outofplace, (int*)dinfo.p, nmat));
       if (prof) {
         const double before = tstage[2];
         tick(2, t0);
-        std::fprintf(stderr, "[mfs precompute] split gesvd %lld x %lld, %d matrices: %.3f s\n", (long long)mh,
-                     (long long)nh, nbs, tstage[2] - before);
+        std::fprintf(stderr, "[mfs precompute] F %lld x %lld -> SVD %lld x %lld, %d matrices: %.3f s\n",
+                     (long long)rows, (long long)cols, (long long)sr, (long long)cols, nmat, tstage[2] - before);
       }
-      MFS_HIP(dT1.alloc(c, sizeof(double) * mnh * nx * nbs));
-      MFS_HIP(dGs.alloc(c, sizeof(double) * nh * nx * nbs));
-      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mnh,
-                                           (int)nx, (int)mh, &one, (const double*)dU.p, (int)mh, mh * mnh,
-                                           (const double*)dXs.p, (int)mh, mh * nx, &zero, (double*)dT1.p, (int)mnh,
-                                           mnh * nx, nbs));
+      // T1 = U^T (Q1^T X), scaled by the kept 1 / sigma_j; G = V T1
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)k,
+                                           (int)nx, (int)sr, &one, (const double*)dU.p, (int)sr, sr * k,
+                                           (const double*)Xp, (int)ldx, sx, &zero, (double*)dT1.p, (int)k, k * nx,
+                                           nmat));
       {
-        dim3 grid((unsigned)((mnh * nx + 255) / 256), nbs);
-        hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mnh, (const double*)dSF.p, mnh,
-                           c->prm.eps_trunc_fine, (double*)dT1.p, mnh, (int)nx, mnh * nx, 2);
+        dim3 grid((unsigned)((k * nx + 255) / 256), nmat);
+        hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)k, (const double*)dS.p, k,
+                           c->prm.eps_trunc_fine, (double*)dT1.p, k, (int)nx, k * nx, group);
+        MFS_HIP(hipGetLastError());
       }
-      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)nh,
-                                           (int)nx, (int)mnh, &one, (const double*)dVT.p, (int)mnh, mnh * nh,
-                                           (const double*)dT1.p, (int)mnh, mnh * nx, &zero, (double*)dGs.p, (int)nh,
-                                           nh * nx, nbs));
+      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)cols,
+                                           (int)nx, (int)k, &one, (const double*)dVT.p, (int)k, k * cols,
+                                           (const double*)dT1.p, (int)k, k * nx, &zero, G, (int)cols, cols * nx,
+                                           nmat));
+      MFS_HIP(hipStreamSynchronize(c->stream));   // the work buffers are released at the end of this scope
+      return Status{};
+    };
+    if (sym) {
+      // [F_e X_e] (mh x (nh + nx)), e = +, -: half the rows and columns
+      const int64_t mh = m / 2, nh = n / 2;
+      DevMem dFXs, dGs;
+      MFS_HIP(dFXs.alloc(c, sizeof(double) * mh * (nh + nx) * nbs));
+      hipLaunchKernelGGL(k_sym_split_F, dim3((unsigned)(nh + nx), nbs), dim3(256), 0, c->stream, (const double*)pF,
+                         m, d.sF, (const double*)pX, d.sX, (int)mh, (int)nh, (int)nx, sym_nsrc, sym_nnode,
+                         (double*)dFXs.p);
+      MFS_HIP(hipGetLastError());
+      MFS_HIP(dGs.alloc(c, sizeof(double) * nh * nx * nbs));
+      tick(7, t0);
+      Status st = pinv_apply((double*)dFXs.p, mh, nh, mh * (nh + nx), nbs, 2, (double*)dGs.p);
+      if (st.code != MFS_OK) return st;
       hipLaunchKernelGGL(k_sym_join_G, dim3((unsigned)nx, nb), dim3(256), 0, c->stream, (const double*)dGs.p, (int)nh,
                          (int)nx, sym_nsrc, (double*)dG.p, n * nx);
       MFS_HIP(hipGetLastError());
       MFS_HIP(hipStreamSynchronize(c->stream));   // the split buffers are released at the end of this scope
     } else {
-      MFS_HIP(dSF.alloc(c, sizeof(double) * mn * nb));
-      MFS_HIP(dU.alloc(c, sizeof(double) * m * mn * nb));
-      MFS_HIP(dVT.alloc(c, sizeof(double) * mn * n * nb));
-      MFS_HIP(dE.alloc(c, sizeof(double) * mn * nb));
-      MFS_RB(svd_entry().gesvd_sb(c->blas, rocblas_svect_singular, rocblas_svect_singular, (int)m, (int)n,
-                                              (double*)dF.p, (int)m, d.sF, (double*)dSF.p, mn, (double*)dU.p, (int)m,
-                                              m * mn, (double*)dVT.p, (int)mn, mn * n, (double*)dE.p, mn,
-                                              rocblas_outofplace, (int*)dinfo.p, nb));
-      tick(2, t0);
-      // T1 = U^T X  (mn x nx)
-      MFS_HIP(dT1.alloc(c, sizeof(double) * mn * nx * nb));
-      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)mn,
-                                           (int)nx, (int)m, &one, (const double*)dU.p, (int)m, m * mn,
-                                           (const double*)dX.p, (int)m, d.sX, &zero, (double*)dT1.p, (int)mn,
-                                           mn * nx, nb));
-      {
-        dim3 grid((unsigned)((mn * nx + 255) / 256), nb);
-        hipLaunchKernelGGL(k_trunc_scale, grid, dim3(256), 0, c->stream, (int)mn, (const double*)dSF.p, mn,
-                           c->prm.eps_trunc_fine, (double*)dT1.p, mn, (int)nx, mn * nx, 1);
-      }
-      // G = V T1 = (V^T)^T T1   (n x nx)
-      MFS_RB(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)n,
-                                           (int)nx, (int)mn, &one, (const double*)dVT.p, (int)mn, mn * n,
-                                           (const double*)dT1.p, (int)mn, mn * nx, &zero, (double*)dG.p, (int)n,
-                                           n * nx, nb));
+      Status st = pinv_apply(pF, m, n, d.sF, nb, 1, (double*)dG.p);
+      if (st.code != MFS_OK) return st;
     }
+    tick(3, t0);
     if (keep) {
       std::vector<int32_t> nfq(2 * nb);
       std::vector<int64_t> gq(nb);
