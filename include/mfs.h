@@ -228,7 +228,10 @@ mfs_status mfs_apply(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, int32_t
  * context, go to a static scratch array of 128 MiB that every context on the device shares
  * (each device holds its own copy until the process ends).  Calls that overlap in time on one
  * device race on that array: run them on one stream, or order them.  The result equals
- * mfs_apply's (same kernels).  mu_in, u_out: device, n doubles, not overlapping.  Errors: as
+ * mfs_apply's (same kernels).  It launches kernels only (no allocation, copy, fill or
+ * synchronisation), so on a context whose stream is capturing it records into a HIP graph,
+ * and each replay reads mu_in and writes u_out at the captured addresses.  mu_in, u_out:
+ * device, n doubles, not overlapping.  Errors: as
  * mfs_apply; MFS_ERR_ARG when this context's records (16 (ncell (81 + 108) + 174 P) + 8 x 140 P
  * bytes, 78 MB at P = 10^4) exceed the array. */
 mfs_status mfs_apply_noalloc(mfs_ctx* ctx, mfs_problem prob, mfs_precision prec, const double* mu_in,
